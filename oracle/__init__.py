@@ -1,0 +1,10 @@
+"""CPU oracle for the one-site TDVP sweep (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP library.
+"""
+from .ttn_oracle import (Oracle, clamp_bonds, dense_sop, full_state, expm_krylov,
+                         householder_qr_lapack)
+
+__all__ = ["Oracle", "clamp_bonds", "dense_sop", "full_state", "expm_krylov",
+           "householder_qr_lapack"]
