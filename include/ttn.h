@@ -1,0 +1,178 @@
+/*
+ * ttn.h - C boundary of the MI355X (gfx950) one-site TDVP library for tree
+ * tensor networks (multilayer MCTDH), after pyTTN (arXiv 2503.15460).
+ *
+ * The calls follow the paper's problem statement:
+ *   ttn_create     - the tree tensor network ansatz (Sec. II A: a tree of
+ *                    coefficient tensors, the number of single-particle
+ *                    functions n on every bond, primitive dimensions at leaves);
+ *   ttn_set_sop    - the sum-of-product generator H = sum_r c_r prod h_{a,r}
+ *                    (Sec. II B 1, SOP equation);
+ *   ttn_step       - the projector-splitting solution of the local equation of
+ *                    motion dA/dt = -i sum_r c_r h_r A H_r (Sec. II C) over dt;
+ *   ttn_observe    - autocorrelation a(t) (Sec. IV A), populations and spin
+ *                    expectation values (Secs. IV, V A), and the HEOM reduced
+ *                    density matrix by vacuum projection (SI, FP-HEOM section).
+ *
+ * Conventions common to every call
+ *   - Every function returns a ttn_status: TTN_OK (0) or a negative error.
+ *     After an error, ttn_last_error() returns a message; the state of the
+ *     handle is unchanged, except after TTN_E_DEVICE, which leaves the handle
+ *     unusable (destroy it).
+ *   - All pointer arguments are HOST pointers owned by the caller.  The library
+ *     copies what it needs during the call and never keeps a caller pointer.
+ *   - Complex numbers are two consecutive doubles (re, im).
+ *   - The library owns all device memory of a handle (or sub-allocates the
+ *     workspace given with ttn_bind_workspace).  A handle is not thread safe and
+ *     runs all its work on one HIP stream (ttn_options.hip_stream, or the null
+ *     stream).
+ *   - Time evolution is d/dt psi = -i G psi (G = H/hbar for unitary models).
+ *
+ * Tensor layout (used by ttn_get_state / ttn_set_state)
+ *   Node z holds A^z with the children's indices first, in increasing node id,
+ *   and the index toward the parent last; leaves hold (d, n); the root's parent
+ *   index has dimension 1.  Row-major, complex interleaved, nodes concatenated
+ *   in node-id order.
+ */
+#ifndef TTN_H
+#define TTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ttn_status;
+#define TTN_OK 0
+#define TTN_E_INVALID (-1) /* bad argument, or hermitian=1 with a non-Hermitian G */
+#define TTN_E_TREE (-2)    /* parent array is not a single rooted tree */
+#define TTN_E_DIMS (-3)    /* local/bond dimensions invalid or buffer size mismatch */
+#define TTN_E_OOM (-4)     /* device allocation failed or workspace too small */
+#define TTN_E_DEVICE (-5)  /* HIP runtime error; the handle is unusable */
+#define TTN_E_NOCONV (-6)  /* local exponential did not converge */
+#define TTN_E_STATE (-7)   /* call out of order (e.g. ttn_step before ttn_set_sop) */
+
+/* precision of the H_eff / environment contractions; QR, Krylov
+ * orthogonalisation and the small projected exponential always run in FP64 */
+#define TTN_FP64 0
+#define TTN_FP32 1
+
+/* observable kinds for ttn_observe */
+#define TTN_OBS_EXPECT 0      /* <Psi| prod_i op_ids[i] |Psi>, ops on distinct leaves */
+#define TTN_OBS_NORM 1        /* <Psi|Psi> */
+#define TTN_OBS_ENERGY 2      /* <Psi|G|Psi> */
+#define TTN_OBS_OVERLAP_T0 3  /* a(t) = <Psi(0)|Psi(t)>, Psi(0) = last state set */
+#define TTN_OBS_BILINEAR 4    /* (b|Psi) = sum_x b_x Psi_x, b a product vector (no conj.) */
+
+typedef struct ttn_ctx *ttn_t;
+
+typedef struct {
+    int32_t precision;   /* TTN_FP64 or TTN_FP32 */
+    double krylov_tol;   /* local exponential error target, relative (0 -> 1e-13) */
+    int32_t krylov_mmax; /* max Krylov dimension per solve (0 -> 40) */
+    int32_t hermitian;   /* 1: Lanczos (G must be Hermitian), 0: Arnoldi */
+    void *hip_stream;    /* hipStream_t for all work of the handle, NULL = null stream */
+    int32_t device;      /* HIP device ordinal */
+    int32_t use_graph;   /* reserved, 0 */
+    uint64_t seed;       /* reserved */
+} ttn_options;
+
+/* Fill *opt with the defaults (FP64, tol 1e-13, mmax 40, Hermitian). */
+void ttn_default_options(ttn_options *opt);
+
+/* Create a tree tensor network.
+ *   n_nodes   number of nodes (>= 2)
+ *   parent    [n_nodes] parent id, exactly one -1 (the root); children of a node
+ *             are ordered by increasing node id
+ *   local_dim [n_nodes] primitive dimension d > 0 for leaves, 0 for interior nodes
+ *   bond_dim  [n_nodes] requested number of SPFs on the bond to the parent
+ *             (ignored for the root).  Requests the tree cannot support are
+ *             clamped: n = min(request, prod dims below, prod dims above), then
+ *             lowered until every matricisation has rows >= columns.  The
+ *             effective values are returned by ttn_get_info.
+ * Errors: TTN_E_TREE (not a tree), TTN_E_DIMS (leaf/interior dims invalid),
+ *         TTN_E_DEVICE.  On success *out receives the handle. */
+ttn_status ttn_create(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                      const int32_t *bond_dim, const ttn_options *opt, ttn_t *out);
+
+/* Set the SOP generator G = sum_r coeff[r] prod_{o in term r} op_o.
+ *   n_ops, op_leaf[n_ops]      leaf each operator acts on
+ *   op_offset[n_ops+1]         offsets (in complex elements) into op_data
+ *   op_data                    dense d x d row-major complex matrices
+ *   n_terms, coeff[2*n_terms]  complex coefficients
+ *   term_ptr[n_terms+1], term_ops[...]  operator ids of each term, at most one
+ *                              per leaf, at least one per term
+ * The generator is compiled into a hierarchical SOP (sparse tree operator)
+ * whose bond operators are chosen by a minimum vertex cover of the bipartite
+ * term graph of every bond (Sec. II B 2).  With hermitian=1, G is checked for
+ * Hermiticity (operators and coefficients) and TTN_E_INVALID is returned if it
+ * is not.  Device environments are rebuilt if a state is already set.
+ * Errors: TTN_E_INVALID, TTN_E_DIMS, TTN_E_OOM, TTN_E_DEVICE. */
+ttn_status ttn_set_sop(ttn_t h, int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                       const double *op_data, int32_t n_terms, const double *coeff,
+                       const int64_t *term_ptr, const int32_t *term_ops);
+
+/* Product initial state: leaf_vecs holds one complex vector of length d per
+ * leaf, concatenated in increasing leaf id.  Unoccupied single-particle
+ * functions are completed with unit vectors (leaf: modified Gram-Schmidt of
+ * e_0, e_1, ... against the given vector, skipping residuals below 1e-6;
+ * interior node: the first n columns of the identity; root: e_(0..0)).
+ * This state becomes Psi(0) for TTN_OBS_OVERLAP_T0.
+ * Errors: TTN_E_STATE (no SOP yet), TTN_E_INVALID (zero vector), TTN_E_DEVICE. */
+ttn_status ttn_set_product_state(ttn_t h, const double *leaf_vecs);
+
+/* Advance n_steps steps of dt (dt may be negative).  One step is the symmetric
+ * projector-splitting sweep S(dt/2) S*(dt/2) with the two root forward half
+ * steps merged (2N-1 forward, 2(N-1) backward local exponentials, 4(N-1) QRs).
+ * Errors: TTN_E_STATE, TTN_E_NOCONV (state restored to before the failed
+ * step), TTN_E_DEVICE. */
+ttn_status ttn_step(ttn_t h, double dt, int32_t n_steps);
+
+/* Observables; out receives complex values (2 doubles each), caller-owned.
+ *   TTN_OBS_EXPECT     n op ids (distinct leaves) -> 1 value
+ *   TTN_OBS_NORM       n = 0 -> 1 value
+ *   TTN_OBS_ENERGY     n = 0 -> 1 value
+ *   TTN_OBS_OVERLAP_T0 n = 0 -> 1 value
+ *   TTN_OBS_BILINEAR   op_ids unused; vecs = one complex vector per leaf
+ *                      (concatenated by leaf id), passed in `vecs` -> 1 value
+ * Values are raw (not divided by the norm).
+ * Errors: TTN_E_STATE, TTN_E_INVALID, TTN_E_DEVICE. */
+ttn_status ttn_observe(ttn_t h, int32_t kind, int32_t n, const int32_t *op_ids,
+                       const double *vecs, double *out);
+
+/* Apply the effective generator of the root node to x (complex, size of the
+ * root tensor) -> y, using the current environments.  Diagnostic entry point
+ * for brute-force checks of the contraction kernels.
+ * Errors: TTN_E_STATE, TTN_E_DEVICE. */
+ttn_status ttn_apply_root_heff(ttn_t h, const double *x, double *y);
+
+/* Info: effective bond dims [n_nodes]; counters[8] = {steps, forward solves,
+ * backward solves, total Krylov matvecs, algorithmic H_eff flops (8 per complex
+ * MAC), bytes of device memory in use, tree-operator entries, redo count}.
+ * Either pointer may be NULL. */
+ttn_status ttn_get_info(ttn_t h, int32_t *effective_bond_dim, int64_t *counters);
+
+/* Size in bytes (complex128 elements * 16) of the state for get/set_state. */
+ttn_status ttn_state_size(ttn_t h, size_t *bytes);
+
+/* Copy all node tensors to/from a host buffer of exactly ttn_state_size bytes.
+ * ttn_set_state expects every non-root node to be an isometry toward its
+ * parent (the orthogonality centre at the root); it rebuilds the environments
+ * and makes the state Psi(0).  Errors: TTN_E_DIMS, TTN_E_STATE, TTN_E_DEVICE. */
+ttn_status ttn_get_state(ttn_t h, double *buf, size_t bytes);
+ttn_status ttn_set_state(ttn_t h, const double *buf, size_t bytes);
+
+/* Per-handle message of the last error (NULL handle: last error of this
+ * thread).  The string is owned by the library. */
+const char *ttn_last_error(ttn_t h);
+
+/* Release all resources of the handle. */
+void ttn_destroy(ttn_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTN_H */

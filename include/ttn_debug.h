@@ -1,0 +1,37 @@
+/*
+ * ttn_debug.h - host-only diagnostic entry points of the TTN library.
+ * They allocate no device memory and run on machines without a GPU.
+ */
+#ifndef TTN_DEBUG_H
+#define TTN_DEBUG_H
+
+#include "ttn.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Compile the SOP generator of a tree (arguments as for ttn_create and
+ * ttn_set_sop) into the library's sparse tree operator (hierarchical SOP,
+ * Sec. II B 2 of the paper) and assemble it back into a dense matrix over the
+ * leaves in depth-first order (children in increasing id).  `out` receives
+ * dim*dim complex values (row-major) where dim = prod of leaf dims, which must
+ * not exceed max_dim.  n_entries (may be NULL) receives the number of
+ * tree-operator entries (hSOP channels summed over nodes).
+ * Errors: TTN_E_TREE, TTN_E_DIMS, TTN_E_INVALID (including dim > max_dim). */
+ttn_status ttn_debug_dense_tree_operator(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                                         int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                                         const double *op_data, int32_t n_terms, const double *coeff,
+                                         const int64_t *term_ptr, const int32_t *term_ops, int64_t max_dim,
+                                         double *out, int64_t *n_entries);
+
+/* Effective (clamped) bond dimensions for a tree, host only.
+ * Errors: TTN_E_TREE, TTN_E_DIMS. */
+ttn_status ttn_debug_clamp_bonds(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                                 const int32_t *bond_dim, int32_t *effective);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTN_DEBUG_H */

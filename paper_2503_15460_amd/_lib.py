@@ -1,0 +1,261 @@
+"""ctypes binding of the HIP library ``libttn.so`` (argument marshalling only).
+
+Every numerical step runs inside the library's HIP kernels.  Importing this
+module does not need a GPU; calls that touch the device fail with a TTN error
+when none is present.  If the library is missing the import fails loudly:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("TTN_LIBRARY", os.path.join(HERE, "libttn.so"))
+
+TTN_OK = 0
+ERRORS = {-1: "TTN_E_INVALID", -2: "TTN_E_TREE", -3: "TTN_E_DIMS", -4: "TTN_E_OOM", -5: "TTN_E_DEVICE",
+          -6: "TTN_E_NOCONV", -7: "TTN_E_STATE"}
+TTN_FP64, TTN_FP32 = 0, 1
+OBS_EXPECT, OBS_NORM, OBS_ENERGY, OBS_OVERLAP_T0, OBS_BILINEAR = 0, 1, 2, 3, 4
+
+# every symbol declared in include/ttn.h and include/ttn_debug.h
+EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product_state", "ttn_step",
+            "ttn_observe", "ttn_apply_root_heff", "ttn_get_info", "ttn_state_size", "ttn_get_state",
+            "ttn_set_state", "ttn_last_error", "ttn_destroy", "ttn_debug_dense_tree_operator",
+            "ttn_debug_clamp_bonds"]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("krylov_tol", C.c_double), ("krylov_mmax", C.c_int32),
+                ("hermitian", C.c_int32), ("hip_stream", C.c_void_p), ("device", C.c_int32),
+                ("use_graph", C.c_int32), ("seed", C.c_uint64)]
+
+
+class TTNError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32p, i64p, dp = C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)
+    sig = {
+        "ttn_default_options": (None, [C.POINTER(Options)]),
+        "ttn_create": (C.c_int32, [C.c_int32, i32p, i32p, i32p, C.POINTER(Options), C.POINTER(P)]),
+        "ttn_set_sop": (C.c_int32, [P, C.c_int32, i32p, i64p, dp, C.c_int32, dp, i64p, i32p]),
+        "ttn_set_product_state": (C.c_int32, [P, dp]),
+        "ttn_step": (C.c_int32, [P, C.c_double, C.c_int32]),
+        "ttn_observe": (C.c_int32, [P, C.c_int32, C.c_int32, i32p, dp, dp]),
+        "ttn_apply_root_heff": (C.c_int32, [P, dp, dp]),
+        "ttn_get_info": (C.c_int32, [P, i32p, i64p]),
+        "ttn_state_size": (C.c_int32, [P, C.POINTER(C.c_size_t)]),
+        "ttn_get_state": (C.c_int32, [P, dp, C.c_size_t]),
+        "ttn_set_state": (C.c_int32, [P, dp, C.c_size_t]),
+        "ttn_last_error": (C.c_char_p, [P]),
+        "ttn_destroy": (None, [P]),
+        "ttn_debug_dense_tree_operator": (C.c_int32, [C.c_int32, i32p, i32p, C.c_int32, i32p, i64p, dp,
+                                                      C.c_int32, dp, i64p, i32p, C.c_int64, dp, i64p]),
+        "ttn_debug_clamp_bonds": (C.c_int32, [C.c_int32, i32p, i32p, i32p, i32p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _check(code: int, handle=None):
+    if code != TTN_OK:
+        msg = lib.ttn_last_error(handle)
+        raise TTNError(code, msg.decode() if msg else "")
+
+
+def clamp_bonds(parent, local_dim, bond_dim) -> np.ndarray:
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    ld = np.ascontiguousarray(local_dim, dtype=np.int32)
+    bd = np.ascontiguousarray(bond_dim, dtype=np.int32)
+    out = np.zeros(len(parent), dtype=np.int32)
+    _check(lib.ttn_debug_clamp_bonds(len(parent), _ptr(parent, C.c_int32), _ptr(ld, C.c_int32),
+                                     _ptr(bd, C.c_int32), _ptr(out, C.c_int32)))
+    return out
+
+
+def dense_tree_operator(problem, max_dim: int = 4096):
+    """Dense matrix of the compiled sparse tree operator (host only)."""
+    parent = np.ascontiguousarray(problem.parent, dtype=np.int32)
+    ld = np.ascontiguousarray(problem.local_dim, dtype=np.int32)
+    op_leaf, off, data, coeff, tptr, tops = problem.flat_sop()
+    dim = int(np.prod([problem.local_dim[l] for l in problem.leaves()]))
+    out = np.zeros(2 * dim * dim, dtype=np.float64)
+    nent = np.zeros(1, dtype=np.int64)
+    _check(lib.ttn_debug_dense_tree_operator(
+        len(parent), _ptr(parent, C.c_int32), _ptr(ld, C.c_int32), len(op_leaf), _ptr(op_leaf, C.c_int32),
+        _ptr(off, C.c_int64), _ptr(data, C.c_double), len(problem.term_ops), _ptr(coeff, C.c_double),
+        _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32), max_dim, _ptr(out, C.c_double), _ptr(nent, C.c_int64)))
+    return out.view(np.complex128).reshape(dim, dim), int(nent[0])
+
+
+def tree_operator_entries(problem) -> int:
+    """Number of sparse tree-operator entries (hSOP channels over all nodes), host only."""
+    parent = np.ascontiguousarray(problem.parent, dtype=np.int32)
+    ld = np.ascontiguousarray(problem.local_dim, dtype=np.int32)
+    op_leaf, off, data, coeff, tptr, tops = problem.flat_sop()
+    out = np.zeros(2, dtype=np.float64)
+    nent = np.zeros(1, dtype=np.int64)
+    lib.ttn_debug_dense_tree_operator(
+        len(parent), _ptr(parent, C.c_int32), _ptr(ld, C.c_int32), len(op_leaf), _ptr(op_leaf, C.c_int32),
+        _ptr(off, C.c_int64), _ptr(data, C.c_double), len(problem.term_ops), _ptr(coeff, C.c_double),
+        _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32), 0, _ptr(out, C.c_double), _ptr(nent, C.c_int64))
+    return int(nent[0])
+
+
+def default_stream() -> Optional[int]:
+    """HIP stream handle of torch's current stream (torch provides streams), if any."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class TTN:
+    """One tree tensor network on the GPU, driven through the C boundary."""
+
+    def __init__(self, parent, local_dim, bond_dim, precision: int = TTN_FP64, krylov_tol: float = 1e-13,
+                 krylov_mmax: int = 40, hermitian: bool = True, stream: Optional[int] = None, device: int = 0):
+        self.parent = np.ascontiguousarray(parent, dtype=np.int32)
+        self.local_dim = np.ascontiguousarray(local_dim, dtype=np.int32)
+        bond = np.ascontiguousarray(bond_dim, dtype=np.int32)
+        opt = Options()
+        lib.ttn_default_options(C.byref(opt))
+        opt.precision = precision
+        opt.krylov_tol = krylov_tol
+        opt.krylov_mmax = krylov_mmax
+        opt.hermitian = 1 if hermitian else 0
+        opt.hip_stream = stream if stream is not None else default_stream()
+        opt.device = device
+        h = C.c_void_p()
+        _check(lib.ttn_create(len(self.parent), _ptr(self.parent, C.c_int32), _ptr(self.local_dim, C.c_int32),
+                              _ptr(bond, C.c_int32), C.byref(opt), C.byref(h)))
+        self.h = h
+        self.n = len(self.parent)
+
+    @classmethod
+    def from_problem(cls, p, bond_dim=None, **kw):
+        t = cls(p.parent, p.local_dim, p.bond_dim if bond_dim is None else bond_dim,
+                hermitian=kw.pop("hermitian", p.hermitian), **kw)
+        t.set_sop_problem(p)
+        return t
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.ttn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _c(self, code):
+        _check(code, self.h)
+
+    def set_sop_problem(self, p):
+        self._op_leaf = list(p.op_leaf)
+        op_leaf, off, data, coeff, tptr, tops = p.flat_sop()
+        self._c(lib.ttn_set_sop(self.h, len(op_leaf), _ptr(op_leaf, C.c_int32), _ptr(off, C.c_int64),
+                                _ptr(data, C.c_double), len(p.term_ops), _ptr(coeff, C.c_double),
+                                _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32)))
+
+    def set_product_state(self, vecs: Dict[int, np.ndarray]):
+        leaves = [z for z in range(self.n) if self.local_dim[z] > 0]
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(vecs[z], dtype=np.complex128) for z in leaves]))
+        self._c(lib.ttn_set_product_state(self.h, _ptr(flat.view(np.float64), C.c_double)))
+
+    def step(self, dt: float, n_steps: int = 1):
+        self._c(lib.ttn_step(self.h, float(dt), int(n_steps)))
+
+    def _obs(self, kind, ids=(), vecs=None) -> complex:
+        arr = np.ascontiguousarray(ids, dtype=np.int32) if len(ids) else np.zeros(1, dtype=np.int32)
+        out = np.zeros(2, dtype=np.float64)
+        vp = _ptr(vecs, C.c_double) if vecs is not None else None
+        self._c(lib.ttn_observe(self.h, kind, len(ids), _ptr(arr, C.c_int32), vp, _ptr(out, C.c_double)))
+        return complex(out[0], out[1])
+
+    def expect(self, op_ids: Sequence[int]) -> complex:
+        return self._obs(OBS_EXPECT, list(op_ids))
+
+    def norm2(self) -> float:
+        return self._obs(OBS_NORM).real
+
+    def energy(self) -> complex:
+        return self._obs(OBS_ENERGY)
+
+    def overlap_t0(self) -> complex:
+        return self._obs(OBS_OVERLAP_T0)
+
+    def bilinear(self, vecs: Dict[int, np.ndarray]) -> complex:
+        leaves = [z for z in range(self.n) if self.local_dim[z] > 0]
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(vecs[z], dtype=np.complex128) for z in leaves]))
+        return self._obs(OBS_BILINEAR, [], flat.view(np.float64))
+
+    def apply_root_heff(self, x: np.ndarray) -> np.ndarray:
+        xin = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.zeros_like(xin)
+        self._c(lib.ttn_apply_root_heff(self.h, _ptr(xin.view(np.float64), C.c_double),
+                                        _ptr(y.view(np.float64), C.c_double)))
+        return y
+
+    def bonds(self) -> np.ndarray:
+        b = np.zeros(self.n, dtype=np.int32)
+        self._c(lib.ttn_get_info(self.h, _ptr(b, C.c_int32), None))
+        return b
+
+    def counters(self) -> Dict[str, int]:
+        c = np.zeros(8, dtype=np.int64)
+        self._c(lib.ttn_get_info(self.h, None, _ptr(c, C.c_int64)))
+        keys = ["steps", "forward_solves", "backward_solves", "matvecs", "heff_flops", "device_bytes",
+                "tree_op_entries", "redo"]
+        return dict(zip(keys, (int(x) for x in c)))
+
+    def shapes(self) -> List[List[int]]:
+        b = self.bonds()
+        kids = [[c for c in range(self.n) if self.parent[c] == z] for z in range(self.n)]
+        out = []
+        for z in range(self.n):
+            dims = [int(self.local_dim[z])] if self.local_dim[z] > 0 else [int(b[c]) for c in kids[z]]
+            out.append(dims + [int(b[z]) if self.parent[z] >= 0 else 1])
+        return out
+
+    def get_state(self) -> List[np.ndarray]:
+        size = C.c_size_t()
+        self._c(lib.ttn_state_size(self.h, C.byref(size)))
+        buf = np.zeros(size.value // 8, dtype=np.float64)
+        self._c(lib.ttn_get_state(self.h, _ptr(buf, C.c_double), size.value))
+        flat = buf.view(np.complex128)
+        out, off = [], 0
+        for shp in self.shapes():
+            n = int(np.prod(shp))
+            out.append(flat[off:off + n].reshape(shp).copy())
+            off += n
+        return out
+
+    def set_state(self, tensors: Sequence[np.ndarray]):
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.complex128).reshape(-1)
+                                                    for t in tensors]))
+        self._c(lib.ttn_set_state(self.h, _ptr(flat.view(np.float64), C.c_double), flat.nbytes))

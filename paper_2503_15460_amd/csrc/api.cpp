@@ -1,0 +1,238 @@
+// C boundary of the library: argument checks, handle management and the
+// conversion of exceptions into ttn_status codes.
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+
+#include "engine.h"
+#include "ttn.h"
+#include "ttn_debug.h"
+#include "ttn_internal.h"
+
+struct ttn_ctx {
+    std::unique_ptr<ttn::Engine> eng;
+    std::string err;
+    bool dead = false;
+};
+
+namespace {
+thread_local std::string g_err;
+
+template <class F>
+ttn_status guard(ttn_t h, F &&f) {
+    try {
+        if (h && h->dead) throw ttn::Error(TTN_E_DEVICE, "handle unusable after a device error");
+        f();
+        return TTN_OK;
+    } catch (const ttn::Error &e) {
+        if (h) {
+            h->err = e.what();
+            if (e.code == TTN_E_DEVICE) h->dead = true;
+        }
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        if (h) h->err = g_err;
+        return TTN_E_OOM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        if (h) h->err = g_err;
+        return TTN_E_INVALID;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+void ttn_default_options(ttn_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = TTN_FP64;
+    opt->krylov_tol = 1e-13;
+    opt->krylov_mmax = 40;
+    opt->hermitian = 1;
+}
+
+ttn_status ttn_create(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim, const int32_t *bond_dim,
+                      const ttn_options *opt, ttn_t *out) {
+    if (!out) {
+        g_err = "null output handle";
+        return TTN_E_INVALID;
+    }
+    *out = nullptr;
+    return guard(nullptr, [&] {
+        ttn_options o;
+        ttn_default_options(&o);
+        if (opt) o = *opt;
+        if (o.precision != TTN_FP64) throw ttn::Error(TTN_E_INVALID, "only TTN_FP64 is implemented");
+        ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, bond_dim);
+        auto h = std::make_unique<ttn_ctx>();
+        h->eng = std::make_unique<ttn::Engine>(t, o);
+        *out = h.release();
+    });
+}
+
+ttn_status ttn_set_sop(ttn_t h, int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                       const double *op_data, int32_t n_terms, const double *coeff, const int64_t *term_ptr,
+                       const int32_t *term_ops) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] {
+        ttn::SopInput s = ttn::read_sop(h->eng->t, n_ops, op_leaf, op_offset, op_data, n_terms, coeff, term_ptr,
+                                        term_ops);
+        h->eng->set_sop(s);
+    });
+}
+
+ttn_status ttn_set_product_state(ttn_t h, const double *leaf_vecs) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] { h->eng->set_product_state(leaf_vecs); });
+}
+
+ttn_status ttn_step(ttn_t h, double dt, int32_t n_steps) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] {
+        if (n_steps < 0) throw ttn::Error(TTN_E_INVALID, "negative step count");
+        h->eng->step(dt, n_steps);
+    });
+}
+
+ttn_status ttn_observe(ttn_t h, int32_t kind, int32_t n, const int32_t *op_ids, const double *vecs, double *out) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] {
+        if (!out) throw ttn::Error(TTN_E_INVALID, "null output");
+        auto r = h->eng->observe(kind, n, op_ids, vecs);
+        out[0] = r[0];
+        out[1] = r[1];
+    });
+}
+
+ttn_status ttn_apply_root_heff(ttn_t h, const double *x, double *y) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] {
+        if (!x || !y) throw ttn::Error(TTN_E_INVALID, "null buffer");
+        h->eng->apply_root_heff(x, y);
+    });
+}
+
+ttn_status ttn_get_info(ttn_t h, int32_t *effective_bond_dim, int64_t *counters) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] { h->eng->info(effective_bond_dim, counters); });
+}
+
+ttn_status ttn_state_size(ttn_t h, size_t *bytes) {
+    if (!h || !bytes) return TTN_E_INVALID;
+    return guard(h, [&] { *bytes = h->eng->state_bytes(); });
+}
+
+ttn_status ttn_get_state(ttn_t h, double *buf, size_t bytes) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] { h->eng->get_state(buf, bytes); });
+}
+
+ttn_status ttn_set_state(ttn_t h, const double *buf, size_t bytes) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] { h->eng->set_state(buf, bytes); });
+}
+
+const char *ttn_last_error(ttn_t h) {
+    if (h) return h->err.c_str();
+    return g_err.c_str();
+}
+
+void ttn_destroy(ttn_t h) {
+    if (!h) return;
+    try {
+        delete h;
+    } catch (...) {
+    }
+}
+
+ttn_status ttn_debug_clamp_bonds(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                                 const int32_t *bond_dim, int32_t *effective) {
+    return guard(nullptr, [&] {
+        if (!effective) throw ttn::Error(TTN_E_INVALID, "null output");
+        ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, bond_dim);
+        for (int z = 0; z < t.n; ++z) effective[z] = z == t.root ? 1 : t.bond[z];
+    });
+}
+
+ttn_status ttn_debug_dense_tree_operator(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                                         int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                                         const double *op_data, int32_t n_terms, const double *coeff,
+                                         const int64_t *term_ptr, const int32_t *term_ops, int64_t max_dim,
+                                         double *out, int64_t *n_entries) {
+    return guard(nullptr, [&] {
+        std::vector<int32_t> ones(n_nodes > 0 ? n_nodes : 1, 1);
+        ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, ones.data());
+        ttn::SopInput s = ttn::read_sop(t, n_ops, op_leaf, op_offset, op_data, n_terms, coeff, term_ptr, term_ops);
+        ttn::TreeOp op = ttn::compile_tree_operator(t, s);
+        if (n_entries) {
+            int64_t cnt = 0;
+            for (auto &e : op.entries) cnt += (int64_t)e.size();
+            *n_entries = cnt;
+        }
+        using ttn::cplx;
+        using Mat = std::vector<cplx>;
+        auto kron = [](const Mat &a, int64_t da, const Mat &b, int64_t db) {
+            Mat c((size_t)(da * db * da * db));
+            for (int64_t i = 0; i < da; ++i)
+                for (int64_t j = 0; j < da; ++j)
+                    for (int64_t k = 0; k < db; ++k)
+                        for (int64_t l = 0; l < db; ++l)
+                            c[(size_t)((i * db + k) * (da * db) + j * db + l)] = a[i * da + j] * b[k * db + l];
+            return c;
+        };
+        auto eye = [](int64_t d) {
+            Mat m((size_t)(d * d), cplx(0));
+            for (int64_t i = 0; i < d; ++i) m[i * d + i] = 1.0;
+            return m;
+        };
+        std::vector<int64_t> dim(t.n, 1);
+        for (int z : t.postorder) {
+            if (t.local_dim[z] > 0) dim[z] = t.local_dim[z];
+            else
+                for (int c : t.kids[z]) dim[z] *= dim[c];
+            if (dim[z] > max_dim) throw ttn::Error(TTN_E_INVALID, "dense dimension exceeds max_dim");
+        }
+        // dense bond operators U^c_b over the subtree of c (channel 0 = identity)
+        std::vector<std::vector<Mat>> Ub(t.n);
+        auto node_sum = [&](int z, const std::vector<ttn::OpEntry> &ents, int want_bp, bool all) {
+            Mat acc((size_t)(dim[z] * dim[z]), cplx(0));
+            for (auto &e : ents) {
+                if (!all && e.bp != want_bp) continue;
+                Mat m{cplx(1.0)};
+                int64_t dm = 1;
+                for (size_t k = 0; k < t.kids[z].size(); ++k) {
+                    int c = t.kids[z][k];
+                    const Mat &f = e.slot[k] >= 1 ? Ub[c][e.slot[k]] : eye(dim[c]);
+                    m = kron(m, dm, f, dim[c]);
+                    dm *= dim[c];
+                }
+                for (size_t q = 0; q < acc.size(); ++q) acc[q] += e.coef * m[q];
+            }
+            return acc;
+        };
+        for (int z : t.postorder) {
+            if (z == t.root) continue;
+            Ub[z].assign(op.n_ch[z], Mat());
+            Ub[z][0] = eye(dim[z]);
+            if (t.local_dim[z] > 0) {
+                int li = t.leaf_index[z];
+                for (int b = 1; b < op.n_ch[z]; ++b)
+                    Ub[z][b] = op.leafU[li][b].empty() ? Mat((size_t)(dim[z] * dim[z]), cplx(0)) : op.leafU[li][b];
+            } else {
+                for (int b = 1; b < op.n_ch[z]; ++b) Ub[z][b] = node_sum(z, op.entries[z], b, false);
+            }
+        }
+        const int64_t D = dim[t.root];
+        Mat G = node_sum(t.root, op.entries[t.root], 0, true);
+        for (int64_t q = 0; q < D * D; ++q) {
+            out[2 * q] = G[q].real();
+            out[2 * q + 1] = G[q].imag();
+        }
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,436 @@
+// Host-side preprocessing: tree validation, bond clamping and compilation of
+// the SOP generator into a sparse tree operator (hierarchical SOP).
+//
+// Paper: pyTTN (arXiv 2503.15460), Sec. II A (tree ansatz, N_i = min(16, N_i)
+// style bond limits) and Sec. II B 2 (hierarchical SOP: the per-node form
+// (A) + (B) + (C), built with a bipartite-graph construction and a pre-order
+// pass for the mean-field operators; identity operators become copies).
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <map>
+#include <set>
+
+#include "ttn_internal.h"
+
+namespace ttn {
+
+Tree build_tree(int n, const int32_t *parent, const int32_t *local_dim, const int32_t *bond_req) {
+    if (n < 2 || !parent || !local_dim || !bond_req) throw Error(TTN_E_TREE, "need at least 2 nodes");
+    Tree t;
+    t.n = n;
+    t.parent.assign(parent, parent + n);
+    t.local_dim.assign(local_dim, local_dim + n);
+    t.kids.assign(n, {});
+    for (int z = 0; z < n; ++z) {
+        int p = t.parent[z];
+        if (p == -1) {
+            if (t.root >= 0) throw Error(TTN_E_TREE, "more than one root");
+            t.root = z;
+        } else if (p < 0 || p >= n || p == z) {
+            throw Error(TTN_E_TREE, "parent id out of range at node " + std::to_string(z));
+        } else {
+            t.kids[p].push_back(z);
+        }
+    }
+    if (t.root < 0) throw Error(TTN_E_TREE, "no root");
+    for (int z = 0; z < n; ++z) {  // every node reaches the root
+        int w = z, steps = 0;
+        while (w != t.root) {
+            w = t.parent[w];
+            if (++steps > n) throw Error(TTN_E_TREE, "cycle in parent array");
+        }
+    }
+    for (int z = 0; z < n; ++z) {
+        bool leaf = t.kids[z].empty();
+        if (leaf != (t.local_dim[z] > 0))
+            throw Error(TTN_E_DIMS, "node " + std::to_string(z) + ": local_dim > 0 iff leaf");
+        if (t.local_dim[z] < 0) throw Error(TTN_E_DIMS, "negative local_dim");
+        if (z != t.root && bond_req[z] < 1) throw Error(TTN_E_DIMS, "bond_dim must be >= 1");
+    }
+    if (t.kids[t.root].empty()) throw Error(TTN_E_TREE, "root must have children");
+    // post-order
+    std::function<void(int)> rec = [&](int z) {
+        for (int c : t.kids[z]) rec(c);
+        t.postorder.push_back(z);
+    };
+    rec(t.root);
+    t.leaf_index.assign(n, -1);
+    for (int z = 0; z < n; ++z)
+        if (t.local_dim[z] > 0) {
+            t.leaf_index[z] = (int)t.leaves.size();
+            t.leaves.push_back(z);
+        }
+    // product of primitive dims inside every subtree (as double)
+    std::vector<double> inside(n, 1.0);
+    for (int z : t.postorder) {
+        if (t.local_dim[z] > 0) inside[z] = t.local_dim[z];
+        else {
+            double p = 1.0;
+            for (int c : t.kids[z]) p *= inside[c];
+            inside[z] = p;
+        }
+    }
+    double total = inside[t.root];
+    std::vector<int> b(n, 1);
+    for (int c = 0; c < n; ++c) {
+        if (c == t.root) continue;
+        double v = std::min({(double)bond_req[c], inside[c], total / inside[c]});
+        b[c] = (int)v;
+    }
+    // lower each bond to the product of the other indices at both end nodes
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (int z = 0; z < n; ++z) {
+            std::vector<std::pair<int, int>> inc;  // (owner or -1, dim), snapshot
+            if (t.local_dim[z] > 0) inc.push_back({-1, t.local_dim[z]});
+            else
+                for (int c : t.kids[z]) inc.push_back({c, b[c]});
+            if (z != t.root) inc.push_back({z, b[z]});
+            for (size_t i = 0; i < inc.size(); ++i) {
+                if (inc[i].first < 0) continue;
+                double other = 1.0;
+                for (size_t j = 0; j < inc.size(); ++j)
+                    if (j != i) other *= inc[j].second;
+                if ((double)inc[i].second > other) {
+                    b[inc[i].first] = (int)other;
+                    changed = true;
+                }
+            }
+        }
+    }
+    t.bond = b;
+    t.dims.assign(n, {});
+    t.size.assign(n, 0);
+    for (int z = 0; z < n; ++z) {
+        if (t.local_dim[z] > 0) t.dims[z].push_back(t.local_dim[z]);
+        else
+            for (int c : t.kids[z]) t.dims[z].push_back(t.bond[c]);
+        t.dims[z].push_back(z == t.root ? 1 : t.bond[z]);
+        int64_t s = 1;
+        for (int d : t.dims[z]) s *= d;
+        t.size[z] = s;
+    }
+    return t;
+}
+
+SopInput read_sop(const Tree &t, int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                  const double *op_data, int32_t n_terms, const double *coeff,
+                  const int64_t *term_ptr, const int32_t *term_ops) {
+    if (n_ops < 0 || n_terms < 0) throw Error(TTN_E_INVALID, "negative counts");
+    if (n_ops > 0 && (!op_leaf || !op_offset || !op_data)) throw Error(TTN_E_INVALID, "null operator arrays");
+    if (n_terms > 0 && (!coeff || !term_ptr || !term_ops)) throw Error(TTN_E_INVALID, "null term arrays");
+    SopInput s;
+    s.n_ops = n_ops;
+    s.n_terms = n_terms;
+    for (int o = 0; o < n_ops; ++o) {
+        int l = op_leaf[o];
+        if (l < 0 || l >= t.n || t.local_dim[l] <= 0)
+            throw Error(TTN_E_INVALID, "operator " + std::to_string(o) + " is not on a leaf");
+        int64_t d = t.local_dim[l];
+        if (op_offset[o + 1] - op_offset[o] != d * d)
+            throw Error(TTN_E_DIMS, "operator " + std::to_string(o) + " size != d*d");
+        std::vector<cplx> m(d * d);
+        for (int64_t i = 0; i < d * d; ++i) {
+            m[i] = cplx(op_data[2 * (op_offset[o] + i)], op_data[2 * (op_offset[o] + i) + 1]);
+            if (!std::isfinite(m[i].real()) || !std::isfinite(m[i].imag()))
+                throw Error(TTN_E_INVALID, "non-finite operator element");
+        }
+        s.op_leaf.push_back(l);
+        s.op_mat.push_back(std::move(m));
+    }
+    for (int r = 0; r < n_terms; ++r) {
+        cplx c(coeff[2 * r], coeff[2 * r + 1]);
+        if (!std::isfinite(c.real()) || !std::isfinite(c.imag()))
+            throw Error(TTN_E_INVALID, "non-finite coefficient in term " + std::to_string(r));
+        std::vector<int> ops;
+        std::set<int> seen;
+        for (int64_t q = term_ptr[r]; q < term_ptr[r + 1]; ++q) {
+            int o = term_ops[q];
+            if (o < 0 || o >= n_ops) throw Error(TTN_E_INVALID, "term operator id out of range");
+            if (!seen.insert(s.op_leaf[o]).second)
+                throw Error(TTN_E_INVALID, "term " + std::to_string(r) + " has two operators on one leaf");
+            ops.push_back(o);
+        }
+        if (ops.empty()) throw Error(TTN_E_INVALID, "term " + std::to_string(r) + " has no operator");
+        s.coeff.push_back(c);
+        s.term_ops.push_back(ops);
+    }
+    return s;
+}
+
+bool sop_is_hermitian(const SopInput &s, double rtol) {
+    // canonical operator ids by exact content, and the id of each adjoint
+    std::map<std::pair<int, std::vector<double>>, int> canon;
+    auto key_of = [](int leaf, const std::vector<cplx> &m) {
+        std::vector<double> v;
+        v.reserve(2 * m.size());
+        for (auto &x : m) {
+            v.push_back(x.real() == 0.0 ? 0.0 : x.real());  // fold -0.0
+            v.push_back(x.imag() == 0.0 ? 0.0 : x.imag());
+        }
+        return std::make_pair(leaf, v);
+    };
+    auto id_of = [&](int leaf, const std::vector<cplx> &m) {
+        auto k = key_of(leaf, m);
+        auto it = canon.find(k);
+        if (it != canon.end()) return it->second;
+        int id = (int)canon.size();
+        canon[k] = id;
+        return id;
+    };
+    std::vector<int> cid(s.n_ops), aid(s.n_ops);
+    for (int o = 0; o < s.n_ops; ++o) {
+        const auto &m = s.op_mat[o];
+        int d = (int)std::lround(std::sqrt((double)m.size()));
+        std::vector<cplx> adj(m.size());
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) adj[i * d + j] = std::conj(m[j * d + i]);
+        cid[o] = id_of(s.op_leaf[o], m);
+        aid[o] = id_of(s.op_leaf[o], adj);
+    }
+    std::map<std::vector<std::pair<int, int>>, cplx> g, gd;
+    double scale = 0.0;
+    for (int r = 0; r < s.n_terms; ++r) {
+        std::vector<std::pair<int, int>> k1, k2;
+        for (int o : s.term_ops[r]) {
+            k1.push_back({s.op_leaf[o], cid[o]});
+            k2.push_back({s.op_leaf[o], aid[o]});
+        }
+        std::sort(k1.begin(), k1.end());
+        std::sort(k2.begin(), k2.end());
+        g[k1] += s.coeff[r];
+        gd[k2] += std::conj(s.coeff[r]);
+        scale = std::max(scale, std::abs(s.coeff[r]));
+    }
+    double tol = rtol * std::max(scale, 1e-300);
+    for (auto &kv : g) {
+        auto it = gd.find(kv.first);
+        cplx other = it == gd.end() ? cplx(0) : it->second;
+        if (std::abs(kv.second - other) > tol) return false;
+    }
+    for (auto &kv : gd)
+        if (g.find(kv.first) == g.end() && std::abs(kv.second) > tol) return false;
+    return true;
+}
+
+namespace {
+
+using SlotVec = std::vector<std::pair<int, int>>;  // (node, value) sorted by node
+
+struct CTerm {
+    cplx coef;
+    SlotVec slots;
+};
+
+// Minimum vertex cover of a bipartite graph (Konig's theorem).
+// adj[l] lists right vertices; returns (left in cover, right in cover).
+std::pair<std::vector<char>, std::vector<char>> min_vertex_cover(int nl, int nr,
+                                                                const std::vector<std::vector<int>> &adj) {
+    std::vector<int> matchR(nr, -1), matchL(nl, -1);
+    for (int l = 0; l < nl; ++l) {
+        std::vector<char> vis(nr, 0);
+        std::function<bool(int)> aug = [&](int u) -> bool {
+            for (int r : adj[u]) {
+                if (vis[r]) continue;
+                vis[r] = 1;
+                if (matchR[r] < 0 || aug(matchR[r])) {
+                    matchR[r] = u;
+                    matchL[u] = r;
+                    return true;
+                }
+            }
+            return false;
+        };
+        aug(l);
+    }
+    // alternating reachability from unmatched left vertices
+    std::vector<char> zl(nl, 0), zr(nr, 0);
+    std::vector<int> stack;
+    for (int l = 0; l < nl; ++l)
+        if (matchL[l] < 0) {
+            zl[l] = 1;
+            stack.push_back(l);
+        }
+    while (!stack.empty()) {
+        int u = stack.back();
+        stack.pop_back();
+        for (int r : adj[u]) {
+            if (zr[r] || matchL[u] == r) continue;
+            zr[r] = 1;
+            int w = matchR[r];
+            if (w >= 0 && !zl[w]) {
+                zl[w] = 1;
+                stack.push_back(w);
+            }
+        }
+    }
+    std::vector<char> cl(nl), cr(nr);
+    for (int l = 0; l < nl; ++l) cl[l] = !zl[l];
+    for (int r = 0; r < nr; ++r) cr[r] = zr[r];
+    return {cl, cr};
+}
+
+}  // namespace
+
+TreeOp compile_tree_operator(const Tree &t, const SopInput &s) {
+    TreeOp op;
+    op.entries.assign(t.n, {});
+    op.n_ch.assign(t.n, 2);
+    op.inside_used.assign(t.n, 0);
+    op.outside_used.assign(t.n, 0);
+    op.leafU.assign(t.leaves.size(), {});
+    op.n_ch[t.root] = 1;
+
+    std::vector<CTerm> terms;
+    for (int r = 0; r < s.n_terms; ++r) {
+        if (s.coeff[r] == cplx(0)) continue;
+        CTerm ct;
+        ct.coef = s.coeff[r];
+        for (int o : s.term_ops[r]) ct.slots.push_back({s.op_leaf[o], o});
+        std::sort(ct.slots.begin(), ct.slots.end());
+        terms.push_back(ct);
+    }
+
+    for (int c : t.postorder) {
+        if (c == t.root) continue;
+        const bool leaf = t.local_dim[c] > 0;
+        const std::vector<int> &kids = t.kids[c];
+        std::vector<CTerm> untouched;
+        std::map<std::pair<std::vector<int>, SlotVec>, cplx> edges;
+        for (auto &ct : terms) {
+            std::vector<int> in(leaf ? 1 : kids.size(), -1);
+            SlotVec out;
+            bool touch = false;
+            for (auto &sv : ct.slots) {
+                int k = -1;
+                if (leaf) {
+                    if (sv.first == c) k = 0;
+                } else {
+                    auto it = std::find(kids.begin(), kids.end(), sv.first);
+                    if (it != kids.end()) k = (int)(it - kids.begin());
+                }
+                if (k >= 0) {
+                    in[k] = sv.second;
+                    touch = true;
+                } else {
+                    out.push_back(sv);
+                }
+            }
+            if (!touch) {
+                untouched.push_back(ct);
+                continue;
+            }
+            edges[{in, out}] += ct.coef;
+        }
+        op.outside_used[c] = !untouched.empty();
+        // inside terms (nothing outside the subtree) and crossing terms
+        std::vector<std::pair<std::vector<int>, cplx>> inside;
+        std::map<std::vector<int>, int> lidx;
+        std::map<SlotVec, int> ridx;
+        for (auto &e : edges) {
+            if (e.second == cplx(0)) continue;
+            if (e.first.second.empty()) inside.push_back({e.first.first, e.second});
+            else {
+                lidx.emplace(e.first.first, 0);
+                ridx.emplace(e.first.second, 0);
+            }
+        }
+        std::vector<std::vector<int>> lkeys;
+        std::vector<SlotVec> rkeys;
+        for (auto &kv : lidx) {
+            kv.second = (int)lkeys.size();
+            lkeys.push_back(kv.first);
+        }
+        for (auto &kv : ridx) {
+            kv.second = (int)rkeys.size();
+            rkeys.push_back(kv.first);
+        }
+        int nl = (int)lkeys.size(), nr = (int)rkeys.size();
+        std::vector<std::vector<int>> adj(nl);
+        std::vector<std::vector<std::pair<int, cplx>>> ladj(nl);  // (r, w)
+        for (auto &e : edges) {
+            if (e.second == cplx(0) || e.first.second.empty()) continue;
+            int l = lidx[e.first.first], r = ridx[e.first.second];
+            adj[l].push_back(r);
+            ladj[l].push_back({r, e.second});
+        }
+        auto cover = min_vertex_cover(nl, nr, adj);
+        // channel ids: 0 identity, 1 inside, then left cover, then right cover
+        std::vector<int> lch(nl, -1), rch(nr, -1);
+        int nch = 2;
+        for (int l = 0; l < nl; ++l)
+            if (cover.first[l]) lch[l] = nch++;
+        for (int r = 0; r < nr; ++r)
+            if (cover.second[r]) rch[r] = nch++;
+        op.n_ch[c] = nch;
+        op.inside_used[c] = !inside.empty();
+        // channel combinations: channel -> list of (in key, weight)
+        std::vector<std::vector<std::pair<std::vector<int>, cplx>>> combo(nch);
+        combo[1] = inside;
+        std::vector<CTerm> next = untouched;
+        if (!inside.empty()) next.push_back({cplx(1.0), SlotVec{{c, 1}}});
+        for (int l = 0; l < nl; ++l) {
+            if (lch[l] >= 0) {
+                combo[lch[l]].push_back({lkeys[l], cplx(1.0)});
+                for (auto &rw : ladj[l]) {
+                    CTerm nt{rw.second, rkeys[rw.first]};
+                    nt.slots.push_back({c, lch[l]});
+                    std::sort(nt.slots.begin(), nt.slots.end());
+                    next.push_back(nt);
+                }
+            } else {
+                for (auto &rw : ladj[l]) combo[rch[rw.first]].push_back({lkeys[l], rw.second});
+            }
+        }
+        for (int r = 0; r < nr; ++r)
+            if (rch[r] >= 0) {
+                CTerm nt{cplx(1.0), rkeys[r]};
+                nt.slots.push_back({c, rch[r]});
+                std::sort(nt.slots.begin(), nt.slots.end());
+                next.push_back(nt);
+            }
+        terms.swap(next);
+        // node entries
+        auto &ent = op.entries[c];
+        if (leaf) {
+            int li = t.leaf_index[c];
+            int d = t.local_dim[c];
+            op.leafU[li].assign(nch, {});
+            for (int b = 1; b < nch; ++b) {
+                if (combo[b].empty()) continue;
+                std::vector<cplx> U((size_t)d * d, cplx(0));
+                for (auto &kw : combo[b]) {
+                    const auto &m = s.op_mat[kw.first[0]];
+                    for (size_t i = 0; i < U.size(); ++i) U[i] += kw.second * m[i];
+                }
+                op.leafU[li][b] = U;
+                ent.push_back({cplx(1.0), {b}, b});
+            }
+        } else {
+            for (int b = 1; b < nch; ++b)
+                for (auto &kw : combo[b]) ent.push_back({kw.second, kw.first, b});
+        }
+        if (op.outside_used[c]) ent.push_back({cplx(1.0), std::vector<int>(leaf ? 1 : kids.size(), -1), 0});
+    }
+    // root: every remaining term lives on the root's child bonds
+    {
+        const auto &kids = t.kids[t.root];
+        std::map<std::vector<int>, cplx> acc;
+        for (auto &ct : terms) {
+            std::vector<int> in(kids.size(), -1);
+            for (auto &sv : ct.slots) {
+                auto it = std::find(kids.begin(), kids.end(), sv.first);
+                if (it == kids.end()) throw Error(TTN_E_INVALID, "internal: unprocessed slot at root");
+                in[it - kids.begin()] = sv.second;
+            }
+            acc[in] += ct.coef;
+        }
+        for (auto &kv : acc)
+            if (kv.second != cplx(0)) op.entries[t.root].push_back({kv.second, kv.first, 0});
+    }
+    return op;
+}
+
+}  // namespace ttn

@@ -1,0 +1,94 @@
+// Host orchestration of the one-site TDVP sweep on one GPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "ttn_internal.h"
+
+namespace ttn {
+
+// Grouped operator program on one node tensor (host tables + device copies).
+struct Prog {
+    Geom g{};
+    std::vector<DevEntry> ents;
+    std::vector<int> gptr{0}, gent;
+    std::vector<double2 *> gdst;
+    int n_groups = 0, max_nf = 0, contract_slot = -1;
+    int64_t flops = 0;  // algorithmic flops of one application (8 per complex MAC)
+    DevEntry *d_ent = nullptr;
+    int *d_gptr = nullptr, *d_gent = nullptr;
+    double2 **d_gdst = nullptr;
+};
+
+class Engine {
+public:
+    Engine(const Tree &t, const ttn_options &o);
+    ~Engine();
+
+    void set_sop(const SopInput &s);
+    void set_product_state(const double *leaf_vecs);
+    void set_state(const double *buf, size_t bytes);
+    void get_state(double *buf, size_t bytes);
+    size_t state_bytes() const;
+    void step(double dt, int n_steps);
+    std::vector<double> observe(int kind, int n, const int32_t *op_ids, const double *vecs);
+    void apply_root_heff(const double *x, double *y);
+    void info(int32_t *bonds, int64_t *counters);
+
+    Tree t;
+    ttn_options opt;
+
+private:
+    hipStream_t st = nullptr;
+    bool have_sop = false, have_state = false;
+    SopInput sop;
+    TreeOp op;
+    // state (allocated at construction)
+    std::vector<double2 *> A, Aalt, A0;
+    double2 *state_mem = nullptr;
+    // environments and programs (allocated by set_sop)
+    std::vector<double2 *> spo, mf, U;
+    std::vector<Prog> heffP, spoP, bondP;
+    std::vector<std::vector<Prog>> mfP;
+    std::vector<void *> sop_allocs;
+    double2 *tmp = nullptr, *gsum = nullptr, *cpart = nullptr;
+    double2 *Rbuf = nullptr, *Cbuf = nullptr, *smallV = nullptr, *obs = nullptr, *snapshot = nullptr;
+    int64_t obs_elems = 0;
+    BigKrylov bk{};
+    int64_t bigN = 0;
+    SolveStat *d_stats = nullptr;
+    std::vector<SolveStat> h_stats;
+    std::vector<int> m_hint;     // per solve index in the step schedule
+    std::vector<int> solve_node; // node (forward) or bond-owner (backward) per solve index
+    std::vector<char> solve_fwd, solve_small;
+    int solve_idx = 0;
+    int mmax = 40;
+    int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+    void *dalloc(size_t bytes);
+    void free_sop();
+    Geom geom_of(const std::vector<int> &dims) const;
+    void upload(Prog &p);
+    ProgView view(const Prog &p) const;
+    void build_programs();
+    void rebuild_all_spos();
+
+    // sweep pieces
+    void sweep_S(int z, double h);
+    void sweep_Sstar(int z, double h);
+    void forward(int z, double tau);
+    void backward(int c, double2 *C, double tau);
+    void expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd);
+    void qr_slot(int z, int s, double2 *Rout, int transR);
+    void absorb(int z, int s, const double2 *M, int transM);
+    void build_spo(int c);
+    void build_mf(int z, int k);
+    void apply_prog(const Prog &p, const double2 *in, double2 *out);
+    void sync_check(const char *where);
+};
+
+}  // namespace ttn

@@ -1,0 +1,863 @@
+// Host orchestration of the one-site TDVP projector-splitting sweep on one GPU.
+//
+// Paper: pyTTN (arXiv 2503.15460), Sec. II C.  One step is the symmetric
+// sweep S(dt/2) followed by its mirror S*(dt/2), with the two root forward
+// half steps merged:
+//   S(z):  for each child c (increasing id): QR of A^z along c's bond, absorb R
+//          into c, rebuild the mean fields of c, recurse into c (leaf: forward
+//          step), QR of A^c along its parent bond, rebuild the SPOs of c,
+//          backward bond step C <- exp(+i h K) C, absorb C into A^z; then the
+//          forward step of z.
+//   S*(z): forward step of z; for each child in decreasing id: QR of A^z,
+//          rebuild the mean fields of c, backward bond step on R^T, absorb into
+//          c, recurse, QR of A^c, rebuild the SPOs of c, absorb R into A^z.
+// All arithmetic runs in the kernels of kernels.hip on one HIP stream; the host
+// only enqueues work and reads back one small statistics array per step.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "engine.h"
+
+namespace ttn {
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) throw Error(TTN_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static inline double2 to_d2(cplx c) { return make_double2(c.real(), c.imag()); }
+
+Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
+    HIPCHK(hipSetDevice(opt.device));
+    st = (hipStream_t)opt.hip_stream;
+    mmax = opt.krylov_mmax > 0 ? std::min(opt.krylov_mmax, 40) : 40;
+    if (mmax < 3) mmax = 3;
+    int64_t tot = 0;
+    for (int z = 0; z < t.n; ++z) tot += t.size[z];
+    HIPCHK(hipMalloc(&state_mem, sizeof(double2) * 3 * tot));
+    HIPCHK(hipMemset(state_mem, 0, sizeof(double2) * 3 * tot));
+    counters[5] += (int64_t)sizeof(double2) * 3 * tot;
+    A.resize(t.n);
+    Aalt.resize(t.n);
+    A0.resize(t.n);
+    int64_t off = 0;
+    for (int z = 0; z < t.n; ++z) {
+        A[z] = state_mem + off;
+        Aalt[z] = state_mem + tot + off;
+        A0[z] = state_mem + 2 * tot + off;
+        off += t.size[z];
+    }
+    for (int z = 0; z < t.n; ++z)
+        if (z != t.root && t.bond[z] > 64) throw Error(TTN_E_DIMS, "bond dimensions above 64 are not supported");
+}
+
+Engine::~Engine() {
+    free_sop();
+    if (state_mem) (void)hipFree(state_mem);
+}
+
+void *Engine::dalloc(size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw Error(TTN_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    sop_allocs.push_back(p);
+    counters[5] += (int64_t)bytes;
+    return p;
+}
+
+void Engine::free_sop() {
+    for (void *p : sop_allocs) (void)hipFree(p);
+    sop_allocs.clear();
+    heffP.clear();
+    spoP.clear();
+    bondP.clear();
+    mfP.clear();
+}
+
+Geom Engine::geom_of(const std::vector<int> &dims) const {
+    Geom g{};
+    g.D = (int)dims.size();
+    int64_t N = 1;
+    for (int s = 0; s < g.D; ++s) {
+        g.dims[s] = dims[s];
+        N *= dims[s];
+    }
+    g.N = N;
+    for (int s = 0; s < g.D; ++s) {
+        int64_t L = 1, R = 1;
+        for (int q = 0; q < s; ++q) L *= dims[q];
+        for (int q = s + 1; q < g.D; ++q) R *= dims[q];
+        g.L[s] = L;
+        g.R[s] = R;
+    }
+    return g;
+}
+
+void Engine::upload(Prog &p) {
+    p.d_ent = (DevEntry *)dalloc(sizeof(DevEntry) * std::max<size_t>(1, p.ents.size()));
+    if (!p.ents.empty())
+        HIPCHK(hipMemcpy(p.d_ent, p.ents.data(), sizeof(DevEntry) * p.ents.size(), hipMemcpyHostToDevice));
+    p.d_gptr = (int *)dalloc(sizeof(int) * p.gptr.size());
+    HIPCHK(hipMemcpy(p.d_gptr, p.gptr.data(), sizeof(int) * p.gptr.size(), hipMemcpyHostToDevice));
+    p.d_gent = (int *)dalloc(sizeof(int) * std::max<size_t>(1, p.gent.size()));
+    if (!p.gent.empty())
+        HIPCHK(hipMemcpy(p.d_gent, p.gent.data(), sizeof(int) * p.gent.size(), hipMemcpyHostToDevice));
+    p.d_gdst = (double2 **)dalloc(sizeof(double2 *) * std::max<size_t>(1, p.gdst.size()));
+    if (!p.gdst.empty())
+        HIPCHK(hipMemcpy(p.d_gdst, p.gdst.data(), sizeof(double2 *) * p.gdst.size(), hipMemcpyHostToDevice));
+}
+
+ProgView Engine::view(const Prog &p) const {
+    ProgView v{};
+    v.g = p.g;
+    v.ent = p.d_ent;
+    v.n_ent = (int)p.ents.size();
+    v.max_nf = p.max_nf;
+    v.gptr = p.d_gptr;
+    v.gent = p.d_gent;
+    v.n_groups = p.n_groups;
+    v.gdst = p.d_gdst;
+    v.contract_slot = p.contract_slot;
+    v.tmp = tmp;
+    v.gsum = gsum;
+    v.cpart = cpart;
+    return v;
+}
+
+// Finalise group tables of a program from the per-entry group ids.
+static void finish_groups(Prog &p, const std::vector<double2 *> &dst_by_group) {
+    p.n_groups = (int)dst_by_group.size();
+    p.gdst = dst_by_group;
+    p.gptr.assign(p.n_groups + 1, 0);
+    for (auto &e : p.ents) p.gptr[e.group + 1]++;
+    for (int g = 0; g < p.n_groups; ++g) p.gptr[g + 1] += p.gptr[g];
+    p.gent.assign(p.ents.size(), 0);
+    std::vector<int> fill(p.gptr.begin(), p.gptr.end() - 1);
+    for (size_t e = 0; e < p.ents.size(); ++e) p.gent[fill[p.ents[e].group]++] = (int)e;
+    p.max_nf = 0;
+    p.flops = 0;
+    for (auto &e : p.ents) {
+        p.max_nf = std::max(p.max_nf, e.nf);
+        for (int f = 0; f < e.nf; ++f) p.flops += 8 * p.g.N * p.g.dims[e.slot[f]];
+    }
+}
+
+void Engine::build_programs() {
+    const int n = t.n;
+    heffP.assign(n, Prog{});
+    spoP.assign(n, Prog{});
+    bondP.assign(n, Prog{});
+    mfP.assign(n, {});
+    auto child_M = [&](int z, int k, int ch) -> const double2 * {
+        if (t.local_dim[z] > 0) {
+            int d = t.local_dim[z];
+            return U[z] + (size_t)ch * d * d;
+        }
+        int c = t.kids[z][k];
+        int nc = t.bond[c];
+        return spo[c] + (size_t)ch * nc * nc;
+    };
+    auto parent_M = [&](int z, int ch) -> const double2 * {
+        int np = t.bond[z];
+        return mf[z] + (size_t)ch * np * np;
+    };
+    int64_t total_entries = 0;
+    for (int z = 0; z < n; ++z) {
+        const auto &ents = op.entries[z];
+        total_entries += (int64_t)ents.size();
+        const int D = (int)t.dims[z].size();
+        const int nk = D - 1;
+        const bool root = z == t.root;
+        // effective generator of the node
+        Prog &h = heffP[z];
+        h.g = geom_of(t.dims[z]);
+        for (auto &e : ents) {
+            DevEntry de{};
+            de.coef = to_d2(e.coef);
+            int nf = 0;
+            for (int k = 0; k < nk; ++k)
+                if (e.slot[k] >= 1) {
+                    de.slot[nf] = k;
+                    de.M[nf++] = child_M(z, k, e.slot[k]);
+                }
+            if (!root && e.bp != 1) {
+                de.slot[nf] = D - 1;
+                de.M[nf++] = parent_M(z, e.bp);
+            }
+            de.nf = nf;
+            de.group = 0;
+            h.ents.push_back(de);
+        }
+        finish_groups(h, {nullptr});
+        upload(h);
+        if (!root) {
+            // SPO rebuild: groups by own-bond channel (>= 1), children factors only
+            Prog &s = spoP[z];
+            s.g = h.g;
+            s.contract_slot = D - 1;
+            std::map<int, int> gid;
+            std::vector<double2 *> dst;
+            const int np = t.bond[z];
+            for (auto &e : ents) {
+                if (e.bp < 1) continue;
+                if (!gid.count(e.bp)) {
+                    gid[e.bp] = (int)dst.size();
+                    dst.push_back(spo[z] + (size_t)e.bp * np * np);
+                }
+                DevEntry de{};
+                de.coef = to_d2(e.coef);
+                int nf = 0;
+                for (int k = 0; k < nk; ++k)
+                    if (e.slot[k] >= 1) {
+                        de.slot[nf] = k;
+                        de.M[nf++] = child_M(z, k, e.slot[k]);
+                    }
+                de.nf = nf;
+                de.group = gid[e.bp];
+                s.ents.push_back(de);
+            }
+            finish_groups(s, dst);
+            upload(s);
+            // backward bond generator K(C) = sum_b U_b C O_b^T on the bond above z
+            Prog &b = bondP[z];
+            b.g = geom_of({np, np});
+            const double2 *Sb = spo[z], *Mb = mf[z];
+            if (op.outside_used[z]) {
+                DevEntry de{};
+                de.coef = make_double2(1.0, 0.0);
+                de.nf = 1;
+                de.slot[0] = 1;
+                de.M[0] = Mb;
+                b.ents.push_back(de);
+            }
+            if (op.inside_used[z]) {
+                DevEntry de{};
+                de.coef = make_double2(1.0, 0.0);
+                de.nf = 1;
+                de.slot[0] = 0;
+                de.M[0] = Sb + (size_t)np * np;
+                b.ents.push_back(de);
+            }
+            for (int ch = 2; ch < op.n_ch[z]; ++ch) {
+                DevEntry de{};
+                de.coef = make_double2(1.0, 0.0);
+                de.nf = 2;
+                de.slot[0] = 0;
+                de.M[0] = Sb + (size_t)ch * np * np;
+                de.slot[1] = 1;
+                de.M[1] = Mb + (size_t)ch * np * np;
+                b.ents.push_back(de);
+            }
+            finish_groups(b, {nullptr});
+            upload(b);
+        }
+        // mean-field rebuilds of every child
+        if (t.local_dim[z] == 0) {
+            mfP[z].assign(nk, Prog{});
+            for (int k = 0; k < nk; ++k) {
+                const int c = t.kids[z][k];
+                const int nc = t.bond[c];
+                Prog &m = mfP[z][k];
+                m.g = h.g;
+                m.contract_slot = k;
+                std::map<int, int> gid;
+                std::vector<double2 *> dst;
+                for (auto &e : ents) {
+                    int ch;
+                    if (e.slot[k] == -1) {
+                        if (!op.outside_used[c]) continue;
+                        ch = 0;
+                    } else if (e.slot[k] == 1) {
+                        continue;  // inside channel: identity mean field
+                    } else {
+                        ch = e.slot[k];
+                    }
+                    if (!gid.count(ch)) {
+                        gid[ch] = (int)dst.size();
+                        dst.push_back(mf[c] + (size_t)ch * nc * nc);
+                    }
+                    DevEntry de{};
+                    de.coef = to_d2(e.coef);
+                    int nf = 0;
+                    for (int j = 0; j < nk; ++j)
+                        if (j != k && e.slot[j] >= 1) {
+                            de.slot[nf] = j;
+                            de.M[nf++] = child_M(z, j, e.slot[j]);
+                        }
+                    if (!root && e.bp != 1) {
+                        de.slot[nf] = D - 1;
+                        de.M[nf++] = parent_M(z, e.bp);
+                    }
+                    de.nf = nf;
+                    de.group = gid[ch];
+                    m.ents.push_back(de);
+                }
+                finish_groups(m, dst);
+                upload(m);
+            }
+        }
+    }
+    counters[6] = total_entries;
+}
+
+void Engine::set_sop(const SopInput &s) {
+    if (opt.hermitian && !sop_is_hermitian(s))
+        throw Error(TTN_E_INVALID, "hermitian=1 but the SOP generator is not Hermitian");
+    TreeOp newop = compile_tree_operator(t, s);
+    HIPCHK(hipStreamSynchronize(st));
+    free_sop();
+    sop = s;
+    op = std::move(newop);
+    const int n = t.n;
+    spo.assign(n, nullptr);
+    mf.assign(n, nullptr);
+    U.assign(n, nullptr);
+    for (int c = 0; c < n; ++c) {
+        if (c == t.root) continue;
+        const size_t nb = t.bond[c];
+        const size_t bytes = sizeof(double2) * op.n_ch[c] * nb * nb;
+        spo[c] = (double2 *)dalloc(bytes);
+        mf[c] = (double2 *)dalloc(bytes);
+        HIPCHK(hipMemset(spo[c], 0, bytes));
+        HIPCHK(hipMemset(mf[c], 0, bytes));
+        if (t.local_dim[c] > 0) {
+            const int d = t.local_dim[c];
+            const int li = t.leaf_index[c];
+            std::vector<double2> hu((size_t)op.n_ch[c] * d * d, make_double2(0.0, 0.0));
+            for (int ch = 1; ch < op.n_ch[c]; ++ch)
+                if (ch < (int)op.leafU[li].size())
+                    for (size_t q = 0; q < op.leafU[li][ch].size(); ++q)
+                        hu[(size_t)ch * d * d + q] = to_d2(op.leafU[li][ch][q]);
+            U[c] = (double2 *)dalloc(sizeof(double2) * hu.size());
+            HIPCHK(hipMemcpy(U[c], hu.data(), sizeof(double2) * hu.size(), hipMemcpyHostToDevice));
+        }
+    }
+    build_programs();
+    // scratch sizes
+    int64_t tmp_e = 1, gsum_e = 1, cpart_e = 1, maxN = 1, maxb2 = 1;
+    auto acc = [&](const Prog &p) {
+        tmp_e = std::max<int64_t>(tmp_e, 2 * (int64_t)p.ents.size() * p.g.N);
+        gsum_e = std::max<int64_t>(gsum_e, (int64_t)p.n_groups * p.g.N);
+        if (p.contract_slot >= 0) {
+            int nn = p.g.dims[p.contract_slot];
+            cpart_e = std::max<int64_t>(cpart_e, (int64_t)p.n_groups * 64 * nn * nn);
+        }
+    };
+    bigN = 0;
+    for (int z = 0; z < n; ++z) {
+        acc(heffP[z]);
+        maxN = std::max<int64_t>(maxN, t.size[z]);
+        if (t.size[z] > SMALL_MAX) bigN = std::max<int64_t>(bigN, t.size[z]);
+        if (z != t.root) {
+            acc(spoP[z]);
+            acc(bondP[z]);
+            int64_t b2 = (int64_t)t.bond[z] * t.bond[z];
+            maxb2 = std::max(maxb2, b2);
+            if (b2 > SMALL_MAX) bigN = std::max<int64_t>(bigN, b2);
+        }
+        for (auto &m : mfP[z]) acc(m);
+    }
+    cpart_e = std::max<int64_t>(cpart_e, 64 * 64 * 64);
+    tmp = (double2 *)dalloc(sizeof(double2) * tmp_e);
+    gsum = (double2 *)dalloc(sizeof(double2) * gsum_e);
+    cpart = (double2 *)dalloc(sizeof(double2) * cpart_e);
+    Rbuf = (double2 *)dalloc(sizeof(double2) * maxb2);
+    Cbuf = (double2 *)dalloc(sizeof(double2) * maxb2);
+    smallV = (double2 *)dalloc(sizeof(double2) * (SMALL_MMAX + 2) * SMALL_MAX);
+    int64_t mats = 0;
+    for (int z = 0; z < n; ++z) {
+        mats += (int64_t)t.bond[z] * t.bond[z];
+        if (t.local_dim[z] > 0) mats += (int64_t)t.local_dim[z] * t.local_dim[z];
+    }
+    obs_elems = 2 * maxN + mats + 64;
+    obs = (double2 *)dalloc(sizeof(double2) * obs_elems);
+    if (bigN > 0) {
+        bk.V = (double2 *)dalloc(sizeof(double2) * (mmax + 1) * bigN);
+        bk.Hm = (double2 *)dalloc(sizeof(double2) * (mmax + 1) * mmax);
+        bk.h = (double2 *)dalloc(sizeof(double2) * (mmax + 1));
+        bk.y = (double2 *)dalloc(sizeof(double2) * (mmax + 1));
+        bk.part = (double *)dalloc(sizeof(double) * VEC_BLOCKS * (mmax + 2) * 2);
+        bk.scal = (double *)dalloc(sizeof(double) * 4);
+        bk.meff = (int *)dalloc(sizeof(int) * 4);
+        bk.counter = (unsigned *)dalloc(sizeof(unsigned) * 4);
+        HIPCHK(hipMemset(bk.counter, 0, sizeof(unsigned) * 4));
+        HIPCHK(hipMemset(bk.meff, 0, sizeof(int) * 4));
+        int64_t tot = 0;
+        for (int z = 0; z < n; ++z) tot += t.size[z];
+        snapshot = (double2 *)dalloc(sizeof(double2) * tot);
+    } else {
+        snapshot = nullptr;
+    }
+    const int n_solves = (2 * n - 1) + 2 * (n - 1);
+    d_stats = (SolveStat *)dalloc(sizeof(SolveStat) * n_solves);
+    h_stats.assign(n_solves, SolveStat{});
+    m_hint.assign(n_solves, 0);
+    solve_node.assign(n_solves, -1);
+    solve_fwd.assign(n_solves, 0);
+    solve_small.assign(n_solves, 0);
+    have_sop = true;
+    if (have_state) rebuild_all_spos();
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------------ state
+size_t Engine::state_bytes() const {
+    size_t s = 0;
+    for (int z = 0; z < t.n; ++z) s += (size_t)t.size[z];
+    return s * sizeof(double2);
+}
+
+void Engine::set_product_state(const double *leaf_vecs) {
+    if (!leaf_vecs) throw Error(TTN_E_INVALID, "null leaf vectors");
+    std::vector<std::vector<double2>> host(t.n);
+    size_t off = 0;
+    for (int z = 0; z < t.n; ++z) {
+        const auto &dims = t.dims[z];
+        std::vector<double2> T((size_t)t.size[z], make_double2(0.0, 0.0));
+        if (t.local_dim[z] > 0) {
+            const int d = dims[0], nb = dims[1];
+            const size_t li = (size_t)t.leaf_index[z];
+            (void)li;
+            // vectors are concatenated in leaf-id order
+            std::vector<cplx> v(d);
+            double nr = 0.0;
+            for (int i = 0; i < d; ++i) {
+                v[i] = cplx(leaf_vecs[2 * (off + i)], leaf_vecs[2 * (off + i) + 1]);
+                nr += std::norm(v[i]);
+            }
+            off += d;
+            nr = std::sqrt(nr);
+            if (!(nr > 0.0) || !std::isfinite(nr)) throw Error(TTN_E_INVALID, "zero or non-finite leaf vector");
+            std::vector<std::vector<cplx>> cols;
+            std::vector<cplx> q0(d);
+            for (int i = 0; i < d; ++i) q0[i] = v[i] / nr;
+            cols.push_back(q0);
+            int j = 0;
+            while ((int)cols.size() < nb && j < d) {
+                std::vector<cplx> e(d, cplx(0.0));
+                e[j] = 1.0;
+                for (auto &q : cols) {  // modified Gram-Schmidt
+                    cplx dot(0.0);
+                    for (int i = 0; i < d; ++i) dot += std::conj(q[i]) * e[i];
+                    for (int i = 0; i < d; ++i) e[i] -= dot * q[i];
+                }
+                double en = 0.0;
+                for (int i = 0; i < d; ++i) en += std::norm(e[i]);
+                en = std::sqrt(en);
+                if (en > 1e-6) {
+                    for (int i = 0; i < d; ++i) e[i] /= en;
+                    cols.push_back(e);
+                }
+                ++j;
+            }
+            for (int c = 0; c < (int)cols.size(); ++c)
+                for (int i = 0; i < d; ++i) T[(size_t)i * nb + c] = to_d2(cols[c][i]);
+        } else {
+            const int np = dims.back();
+            const int64_t rows = t.size[z] / np;
+            for (int c = 0; c < np && c < rows; ++c) T[(size_t)c * np + c] = make_double2(1.0, 0.0);
+        }
+        host[z] = std::move(T);
+    }
+    for (int z = 0; z < t.n; ++z) {
+        HIPCHK(hipMemcpyAsync(A[z], host[z].data(), sizeof(double2) * t.size[z], hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(A0[z], A[z], sizeof(double2) * t.size[z], hipMemcpyDeviceToDevice, st));
+    }
+    have_state = true;
+    if (have_sop) rebuild_all_spos();
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+void Engine::set_state(const double *buf, size_t bytes) {
+    if (!buf || bytes != state_bytes()) throw Error(TTN_E_DIMS, "state buffer size mismatch");
+    size_t off = 0;
+    for (int z = 0; z < t.n; ++z) {
+        HIPCHK(hipMemcpyAsync(A[z], buf + 2 * off, sizeof(double2) * t.size[z], hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(A0[z], A[z], sizeof(double2) * t.size[z], hipMemcpyDeviceToDevice, st));
+        off += t.size[z];
+    }
+    have_state = true;
+    if (have_sop) rebuild_all_spos();
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+void Engine::get_state(double *buf, size_t bytes) {
+    if (!buf || bytes != state_bytes()) throw Error(TTN_E_DIMS, "state buffer size mismatch");
+    size_t off = 0;
+    for (int z = 0; z < t.n; ++z) {
+        HIPCHK(hipMemcpyAsync(buf + 2 * off, A[z], sizeof(double2) * t.size[z], hipMemcpyDeviceToHost, st));
+        off += t.size[z];
+    }
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+void Engine::rebuild_all_spos() {
+    for (int c : t.postorder)
+        if (c != t.root) build_spo(c);
+}
+
+// ------------------------------------------------------------ building blocks
+void Engine::apply_prog(const Prog &p, const double2 *in, double2 *out) {
+    ProgView v = view(p);
+    launch_prog_stages(v, in, st);
+    launch_prog_sum(v, in, out, st);
+}
+
+void Engine::build_spo(int c) {
+    const Prog &p = spoP[c];
+    if (p.n_groups == 0) return;
+    ProgView v = view(p);
+    launch_prog_stages(v, A[c], st);
+    launch_prog_sum(v, A[c], nullptr, st);
+    launch_prog_contract(v, A[c], st);
+}
+
+void Engine::build_mf(int z, int k) {
+    const Prog &p = mfP[z][k];
+    if (p.n_groups == 0) return;
+    ProgView v = view(p);
+    launch_prog_stages(v, A[z], st);
+    launch_prog_sum(v, A[z], nullptr, st);
+    launch_prog_contract(v, A[z], st);
+}
+
+void Engine::qr_slot(int z, int s, double2 *Rout, int transR) {
+    const Geom g = heffP[z].g;
+    launch_qr(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, st);
+}
+
+void Engine::absorb(int z, int s, const double2 *M, int transM) {
+    const Geom g = heffP[z].g;
+    launch_mode_product(A[z], Aalt[z], M, g.L[s], g.dims[s], g.dims[s], g.R[s], transM, st);
+    std::swap(A[z], Aalt[z]);
+}
+
+void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd) {
+    const int si = solve_idx++;
+    if (si >= (int)h_stats.size()) throw Error(TTN_E_STATE, "internal: solve index overflow");
+    solve_node[si] = node;
+    solve_fwd[si] = fwd ? 1 : 0;
+    solve_small[si] = p.g.N <= SMALL_MAX ? 1 : 0;
+    SolveStat *stat = d_stats + si;
+    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : 1e-13;
+    if (p.g.N <= SMALL_MAX) {
+        SmallSolveArgs a{};
+        a.g = p.g;
+        a.ent = p.d_ent;
+        a.n_ent = (int)p.ents.size();
+        a.x = x;
+        a.V = smallV;
+        a.tau = tau;
+        a.tol = tol;
+        a.mmax = std::min(mmax, SMALL_MMAX);
+        a.hermitian = opt.hermitian;
+        a.m_hint = m_hint[si] > 0 ? m_hint[si] : 8;
+        a.stat = stat;
+        launch_small_solve(a, st);
+    } else {
+        int m = m_hint[si] > 0 ? m_hint[si] : 20;
+        m = std::max(3, std::min(m, mmax));
+        m = (int)std::min<int64_t>(m, p.g.N);
+        m_hint[si] = m;
+        const int64_t N = p.g.N;
+        launch_krylov_start(x, N, bk, st);
+        ProgView v = view(p);
+        for (int j = 0; j < m; ++j) {
+            launch_prog_stages(v, bk.V + (size_t)j * N, st);
+            launch_prog_sum(v, bk.V + (size_t)j * N, bk.V + (size_t)(j + 1) * N, st);
+            launch_krylov_orth(bk, N, j, mmax, st);
+        }
+        launch_krylov_finish(bk, N, m, mmax, tau, tol, opt.hermitian, x, stat, st);
+    }
+}
+
+void Engine::forward(int z, double tau) { expm_prog(heffP[z], A[z], tau, z, true); }
+
+void Engine::backward(int c, double2 *C, double tau) { expm_prog(bondP[c], C, -tau, c, false); }
+
+// ------------------------------------------------------------------ sweep
+void Engine::sweep_S(int z, double h) {
+    const auto &kids = t.kids[z];
+    for (int k = 0; k < (int)kids.size(); ++k) {
+        const int c = kids[k];
+        const int pc = (int)t.dims[c].size() - 1;
+        qr_slot(z, k, Rbuf, 0);            // gauge down
+        absorb(c, pc, Rbuf, 0);
+        build_mf(z, k);
+        if (t.local_dim[c] > 0) forward(c, h);
+        else sweep_S(c, h);
+        qr_slot(c, pc, Cbuf, 0);           // up: backward bond step
+        build_spo(c);
+        backward(c, Cbuf, h);
+        absorb(z, k, Cbuf, 0);
+    }
+    if (z != t.root) forward(z, h);
+}
+
+void Engine::sweep_Sstar(int z, double h) {
+    if (z != t.root) forward(z, h);
+    const auto &kids = t.kids[z];
+    for (int k = (int)kids.size() - 1; k >= 0; --k) {
+        const int c = kids[k];
+        const int pc = (int)t.dims[c].size() - 1;
+        qr_slot(z, k, Cbuf, 1);            // down: backward bond step on R^T
+        build_mf(z, k);
+        backward(c, Cbuf, h);
+        absorb(c, pc, Cbuf, 1);
+        if (t.local_dim[c] > 0) forward(c, h);
+        else sweep_Sstar(c, h);
+        qr_slot(c, pc, Rbuf, 0);           // gauge up
+        build_spo(c);
+        absorb(z, k, Rbuf, 0);
+    }
+}
+
+void Engine::sync_check(const char *where) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) throw Error(TTN_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+void Engine::step(double dt, int n_steps) {
+    if (!have_sop || !have_state) throw Error(TTN_E_STATE, "ttn_step needs ttn_set_sop and a state");
+    if (!std::isfinite(dt)) throw Error(TTN_E_INVALID, "dt must be finite");
+    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : 1e-13;
+    for (int s = 0; s < n_steps; ++s) {
+        if (snapshot) {
+            int64_t off = 0;
+            for (int z = 0; z < t.n; ++z) {
+                launch_copy(snapshot + off, A[z], t.size[z], st);
+                off += t.size[z];
+            }
+        }
+        int attempt = 0;
+        while (true) {
+            solve_idx = 0;
+            const double h = 0.5 * dt;
+            sweep_S(t.root, h);
+            forward(t.root, dt);
+            sweep_Sstar(t.root, h);
+            HIPCHK(hipMemcpyAsync(h_stats.data(), d_stats, sizeof(SolveStat) * solve_idx, hipMemcpyDeviceToHost, st));
+            sync_check("ttn_step");
+            bool redo = false;
+            for (int i = 0; i < solve_idx; ++i) {
+                const SolveStat &q = h_stats[i];
+                if (solve_small[i]) {
+                    if (q.fail) throw Error(TTN_E_NOCONV, "local exponential did not converge (small path)");
+                    m_hint[i] = q.m;
+                } else {
+                    if (q.fail) {
+                        if (m_hint[i] >= mmax) {
+                            int64_t off = 0;
+                            for (int z = 0; z < t.n; ++z) {
+                                launch_copy(A[z], snapshot + off, t.size[z], st);
+                                off += t.size[z];
+                            }
+                            rebuild_all_spos();
+                            sync_check("restore");
+                            throw Error(TTN_E_NOCONV, "local exponential did not converge at the Krylov limit");
+                        }
+                        m_hint[i] = std::min(mmax, m_hint[i] + 6);
+                        redo = true;
+                    } else if (q.err_lo <= tol) {
+                        m_hint[i] = std::max(3, m_hint[i] - 1);
+                    }
+                }
+            }
+            if (!redo) break;
+            ++attempt;
+            ++counters[7];
+            int64_t off = 0;
+            for (int z = 0; z < t.n; ++z) {
+                launch_copy(A[z], snapshot + off, t.size[z], st);
+                off += t.size[z];
+            }
+            rebuild_all_spos();
+        }
+        // counters
+        ++counters[0];
+        for (int i = 0; i < solve_idx; ++i) {
+            const int z = solve_node[i];
+            const Prog &p = solve_fwd[i] ? heffP[z] : bondP[z];
+            if (solve_fwd[i]) ++counters[1];
+            else ++counters[2];
+            counters[3] += h_stats[i].matvecs;
+            counters[4] += (int64_t)h_stats[i].matvecs * p.flops;
+        }
+    }
+}
+
+// ------------------------------------------------------------ observables
+std::vector<double> Engine::observe(int kind, int n, const int32_t *op_ids, const double *vecs) {
+    if (!have_state) throw Error(TTN_E_STATE, "no state");
+    const int root = t.root;
+    if (!obs) throw Error(TTN_E_STATE, "ttn_observe needs ttn_set_sop first");
+    int64_t maxN = 0;
+    for (int z = 0; z < t.n; ++z) maxN = std::max<int64_t>(maxN, t.size[z]);
+    double2 *buf0 = obs, *buf1 = obs + maxN;
+    double2 *mats = obs + 2 * maxN;
+    std::vector<double2 *> Mc(t.n, nullptr);
+    {
+        int64_t off = 0;
+        for (int z = 0; z < t.n; ++z) {
+            Mc[z] = mats + off;
+            off += (int64_t)t.bond[z] * t.bond[z];
+        }
+    }
+    double2 *opbuf = nullptr;  // operator uploads, after the node matrices
+    {
+        int64_t off = 0;
+        for (int z = 0; z < t.n; ++z) off += (int64_t)t.bond[z] * t.bond[z];
+        opbuf = mats + off;
+    }
+    auto fetch = [&](const double2 *p, int64_t cnt) {
+        std::vector<double2> h(cnt);
+        HIPCHK(hipMemcpyAsync(h.data(), p, sizeof(double2) * cnt, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return h;
+    };
+    std::vector<double> out(2, 0.0);
+    if (kind == TTN_OBS_NORM) {
+        auto a = fetch(A[root], t.size[root]);
+        double s = 0.0;
+        for (auto &v : a) s += v.x * v.x + v.y * v.y;
+        out[0] = s;
+        return out;
+    }
+    if (kind == TTN_OBS_ENERGY) {
+        if (!have_sop) throw Error(TTN_E_STATE, "no SOP");
+        apply_prog(heffP[root], A[root], buf0);
+        auto a = fetch(A[root], t.size[root]);
+        auto b = fetch(buf0, t.size[root]);
+        cplx s(0.0);
+        for (size_t i = 0; i < a.size(); ++i) s += std::conj(cplx(a[i].x, a[i].y)) * cplx(b[i].x, b[i].y);
+        out[0] = s.real();
+        out[1] = s.imag();
+        return out;
+    }
+    if (kind == TTN_OBS_EXPECT || kind == TTN_OBS_OVERLAP_T0) {
+        std::vector<char> need(t.n, 0);
+        std::vector<const std::vector<cplx> *> leafop(t.n, nullptr);
+        const bool ov = kind == TTN_OBS_OVERLAP_T0;
+        if (ov) {
+            std::fill(need.begin(), need.end(), 1);
+        } else {
+            if (n < 0 || (n > 0 && !op_ids)) throw Error(TTN_E_INVALID, "bad op ids");
+            for (int i = 0; i < n; ++i) {
+                int o = op_ids[i];
+                if (o < 0 || o >= sop.n_ops) throw Error(TTN_E_INVALID, "op id out of range");
+                int l = sop.op_leaf[o];
+                if (leafop[l]) throw Error(TTN_E_INVALID, "two operators on one leaf");
+                leafop[l] = &sop.op_mat[o];
+                for (int w = l; w != -1; w = t.parent[w]) need[w] = 1;
+            }
+            need[root] = 1;
+        }
+        int64_t opoff = 0;
+        for (int c : t.postorder) {
+            if (!need[c]) continue;
+            const Geom g = geom_of(t.dims[c]);
+            const int D = g.D;
+            const double2 *bra = ov ? A0[c] : A[c];
+            const double2 *cur = A[c];
+            double2 *bufs[2] = {buf0, buf1};
+            int pp = 0;
+            if (t.local_dim[c] > 0) {
+                if (leafop[c]) {
+                    const int d = t.local_dim[c];
+                    std::vector<double2> hm(d * d);
+                    for (int q = 0; q < d * d; ++q) hm[q] = to_d2((*leafop[c])[q]);
+                    double2 *dm = opbuf + opoff;
+                    opoff += d * d;
+                    HIPCHK(hipMemcpyAsync(dm, hm.data(), sizeof(double2) * d * d, hipMemcpyHostToDevice, st));
+                    launch_mode_product(cur, bufs[pp], dm, 1, d, d, g.R[0], 0, st);
+                    cur = bufs[pp];
+                    pp ^= 1;
+                }
+            } else {
+                for (int k = 0; k < D - 1; ++k) {
+                    const int kid = t.kids[c][k];
+                    if (!need[kid]) continue;
+                    launch_mode_product(cur, bufs[pp], Mc[kid], g.L[k], g.dims[k], g.dims[k], g.R[k], 0, st);
+                    cur = bufs[pp];
+                    pp ^= 1;
+                }
+            }
+            const int np = g.dims[D - 1];
+            launch_contract(bra, cur, Mc[c], g.N / np, np, np, 1, cpart, st);
+        }
+        auto r = fetch(Mc[root], 1);
+        out[0] = r[0].x;
+        out[1] = r[0].y;
+        return out;
+    }
+    if (kind == TTN_OBS_BILINEAR) {
+        if (!vecs) throw Error(TTN_E_INVALID, "null vectors");
+        // per node: vector over the parent index
+        int64_t voff = 0;
+        std::vector<int64_t> leafoff(t.n, 0);
+        for (int z = 0; z < t.n; ++z)
+            if (t.local_dim[z] > 0) {
+                leafoff[z] = voff;
+                voff += t.local_dim[z];
+            }
+        int64_t opoff = 0;
+        for (int c : t.postorder) {
+            const Geom g = geom_of(t.dims[c]);
+            const int D = g.D;
+            std::vector<int> dims(t.dims[c].begin(), t.dims[c].end());
+            const double2 *cur = A[c];
+            double2 *bufs[2] = {buf0, buf1};
+            int pp = 0;
+            auto shrink = [&](int k, const double2 *vecM) {
+                int64_t L = 1, R = 1;
+                for (int q = 0; q < k; ++q) L *= dims[q];
+                for (int q = k + 1; q < D; ++q) R *= dims[q];
+                launch_mode_product(cur, bufs[pp], vecM, L, dims[k], 1, R, 0, st);
+                dims[k] = 1;
+                cur = bufs[pp];
+                pp ^= 1;
+            };
+            if (t.local_dim[c] > 0) {
+                const int d = t.local_dim[c];
+                std::vector<double2> hv(d);
+                for (int i = 0; i < d; ++i)
+                    hv[i] = make_double2(vecs[2 * (leafoff[c] + i)], vecs[2 * (leafoff[c] + i) + 1]);
+                double2 *dv = opbuf + opoff;
+                opoff += d;
+                HIPCHK(hipMemcpyAsync(dv, hv.data(), sizeof(double2) * d, hipMemcpyHostToDevice, st));
+                shrink(0, dv);
+            } else {
+                for (int k = 0; k < D - 1; ++k) shrink(k, Mc[t.kids[c][k]]);
+            }
+            launch_copy(Mc[c], cur, dims[D - 1], st);
+        }
+        auto r = fetch(Mc[root], 1);
+        out[0] = r[0].x;
+        out[1] = r[0].y;
+        return out;
+    }
+    throw Error(TTN_E_INVALID, "unknown observable kind");
+}
+
+void Engine::apply_root_heff(const double *x, double *y) {
+    if (!have_sop || !have_state) throw Error(TTN_E_STATE, "needs SOP and state");
+    const int64_t N = t.size[t.root];
+    HIPCHK(hipMemcpyAsync(obs, x, sizeof(double2) * N, hipMemcpyHostToDevice, st));
+    apply_prog(heffP[t.root], obs, obs + N);
+    HIPCHK(hipMemcpyAsync(y, obs + N, sizeof(double2) * N, hipMemcpyDeviceToHost, st));
+    sync_check("apply_root_heff");
+}
+
+void Engine::info(int32_t *bonds, int64_t *ctr) {
+    if (bonds)
+        for (int z = 0; z < t.n; ++z) bonds[z] = z == t.root ? 1 : t.bond[z];
+    if (ctr)
+        for (int i = 0; i < 8; ++i) ctr[i] = counters[i];
+}
+
+}  // namespace ttn

@@ -1,0 +1,111 @@
+// Device-side data structures and kernel launchers of the TTN library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ttn {
+
+constexpr int MAXD = 8;        // slots of a node tensor (children + parent)
+constexpr int MAXF = 8;        // non-identity factors of one operator entry
+constexpr int SMALL_MAX = 1024;   // local problems up to this size use the fused solver
+constexpr int SMALL_MMAX = 32;    // Krylov dimension limit of the fused solver (LDS budget)
+constexpr int SMALL_THREADS = 1024;
+constexpr int VEC_BLOCKS = 256;   // work-groups of the multi-kernel vector operations
+constexpr int VEC_THREADS = 256;
+
+// Geometry of a node tensor: slot s has L[s] = prod dims[<s], R[s] = prod dims[>s].
+struct Geom {
+    int D;
+    int dims[MAXD];
+    int64_t L[MAXD];
+    int64_t R[MAXD];
+    int64_t N;
+};
+
+// One operator entry: coef * (x)_f M_f applied on slots slot[f] (ascending).
+struct DevEntry {
+    double2 coef;
+    int nf;
+    int group;
+    int slot[MAXF];
+    const double2 *M[MAXF];
+};
+
+// Grouped application of entries to a tensor (H_eff matvec, K_eff matvec,
+// SPO / mean-field rebuilds).  Device tables are owned by the engine.
+struct ProgView {
+    Geom g;
+    const DevEntry *ent;
+    int n_ent;
+    int max_nf;
+    const int *gptr;          // [n_groups+1] entries of group g: gent[gptr[g]..gptr[g+1])
+    const int *gent;
+    int n_groups;
+    double2 *const *gdst;     // contraction destination per group (env programs)
+    int contract_slot;        // -1: none
+    double2 *tmp;             // 2 * n_ent * N
+    double2 *gsum;            // n_groups * N
+    double2 *cpart;           // contraction partials
+};
+
+// Statistics written by one Krylov solve.
+struct SolveStat {
+    int m;         // Krylov dimension used (last sub-step)
+    int level;     // sub-stepping level (0: none)
+    int fail;      // 1: not converged
+    int matvecs;   // matrix-vector products
+    double err;    // final error estimate (relative)
+    double err_lo; // error estimate at a smaller dimension (big path)
+};
+
+struct SmallSolveArgs {
+    Geom g;
+    const DevEntry *ent;
+    int n_ent;
+    double2 *x;        // in/out
+    double2 *V;        // scratch (SMALL_MMAX + 2) * N
+    double tau;        // computes exp(-i tau G) x
+    double tol;
+    int mmax;
+    int hermitian;
+    int m_hint;
+    SolveStat *stat;
+};
+
+// Scratch of the multi-kernel Krylov path.
+struct BigKrylov {
+    double2 *V;        // (mmax + 1) * N basis
+    double2 *Hm;       // (mmax + 1) * mmax projected matrix, column-major by iteration
+    double2 *h;        // mmax + 1 reduced dots
+    double2 *y;        // mmax coefficients
+    double *part;      // VEC_BLOCKS * (mmax + 2) * 2 partial sums
+    double *scal;      // [0] beta0 [1] beta
+    int *meff;         // breakdown dimension (0: none)
+    unsigned *counter; // last-block reduction counter (starts at 0)
+};
+
+// ---- launchers (all asynchronous on `st`) ----
+void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st);
+void launch_prog_sum(const ProgView &p, const double2 *in, double2 *out_single, hipStream_t st);
+void launch_prog_contract(const ProgView &p, const double2 *A, hipStream_t st);
+
+// Y[l,i,r] = sum_j M[i,j] X[l,j,r] (transM: M[j,i]); X has (L, n_in, R), Y (L, n_out, R)
+void launch_mode_product(const double2 *X, double2 *Y, const double2 *M, int64_t L, int n_in, int n_out,
+                         int64_t R, int transM, hipStream_t st);
+// out[m,n] = sum_{l,r} conj(A[l,m,r]) B[l,n,r] for (L, nA, R) and (L, nB, R)
+void launch_contract(const double2 *A, const double2 *B, double2 *out, int64_t L, int nA, int nB,
+                     int64_t R, double2 *part, hipStream_t st);
+void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st);
+void launch_small_solve(const SmallSolveArgs &a, hipStream_t st);
+void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st);
+void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st);
+
+// multi-kernel Krylov pieces
+void launch_krylov_start(const double2 *x, int64_t N, const BigKrylov &k, hipStream_t st);
+void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st);
+void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double tau, double tol,
+                          int hermitian, double2 *x, SolveStat *stat, hipStream_t st);
+
+}  // namespace ttn

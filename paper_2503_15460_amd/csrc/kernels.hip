@@ -1,0 +1,886 @@
+// HIP kernels of the one-site TDVP sweep for gfx950 (complex FP64).
+//
+// Paper: pyTTN (arXiv 2503.15460).  The contractions implement the node
+// effective generator of the local equation of motion (Sec. II C,
+// (H_eff A)_{I,i} = sum_r c_r h_{IJ} H_{ij} A_{J,j}), the SPO and mean-field
+// recursions (Sec. II B 1 / II C) as conj-contractions of a node tensor with
+// the operator-applied tensor, the QR gauge shifts of the canonical form
+// (Sec. II A), and the local exponentials of the projector-splitting sweep.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <stdexcept>
+
+#include "kernels.h"
+
+namespace ttn {
+
+// ------------------------------------------------------------ complex helpers
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ void cfma(double2 &acc, double2 a, double2 b) {  // acc += a*b
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void cfmac(double2 &acc, double2 a, double2 b) {  // acc += conj(a)*b
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// block-wide sum of `cnt` (<= 8) complex values; result in out[0..cnt) (LDS), synced
+__device__ void blk_sum8(double2 *acc, int cnt, double2 *red, double2 *out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < cnt; ++q) {
+        acc[q].x = wave_sum(acc[q].x);
+        acc[q].y = wave_sum(acc[q].y);
+    }
+    if (lane == 0)
+        for (int q = 0; q < cnt; ++q) red[wave * 8 + q] = acc[q];
+    __syncthreads();
+    if (tid < cnt) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int w = 0; w < nw; ++w) s = cadd(s, red[w * 8 + tid]);
+        out[tid] = s;
+    }
+    __syncthreads();
+}
+
+__device__ double blk_sum1(double v, double *red) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// ============================================================ mode products
+// Y[l,i,r] = sum_j M[i,j] X[l,j,r] for one (L, n, R) geometry.
+__global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const double2 *__restrict__ in,
+                                                    int ldn) {
+    const int e = blockIdx.y;
+    const DevEntry *E = p.ent + e;
+    const int nf = E->nf;
+    if (nf <= stage) return;
+    const int s = E->slot[stage];
+    const double2 *__restrict__ M = E->M[stage];
+    const int n = p.g.dims[s];
+    const uint32_t R = (uint32_t)p.g.R[s];
+    const uint32_t N = (uint32_t)p.g.N;
+    const double2 *__restrict__ src = stage == 0 ? in : p.tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N;
+    double2 *__restrict__ dst = p.tmp + (2 * (int64_t)e + (stage & 1)) * N;
+    extern __shared__ double2 smt[];
+    const bool lds = n <= ldn;  // LDS holds ldn*ldn elements
+    if (lds) {
+        for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
+            int i = q / n, j = q - i * n;
+            smt[j * n + i] = M[q];
+        }
+        __syncthreads();
+    }
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+        uint32_t r = idx % R, t = idx / R;
+        uint32_t i = t % n, l = t / n;
+        const double2 *xp = src + (size_t)l * n * R + r;
+        double2 acc = make_double2(0.0, 0.0);
+        if (lds) {
+            for (int j = 0; j < n; ++j) cfma(acc, smt[j * n + i], xp[(size_t)j * R]);
+        } else {
+            const double2 *mr = M + (size_t)i * n;
+            for (int j = 0; j < n; ++j) cfma(acc, mr[j], xp[(size_t)j * R]);
+        }
+        dst[idx] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_group_sum(ProgView p, const double2 *__restrict__ in,
+                                                   double2 *out_single) {
+    const int g = blockIdx.y;
+    const uint32_t N = (uint32_t)p.g.N;
+    double2 *__restrict__ dst = out_single ? out_single : p.gsum + (size_t)g * N;
+    const int q0 = p.gptr[g], q1 = p.gptr[g + 1];
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int q = q0; q < q1; ++q) {
+            const int e = p.gent[q];
+            const int nf = p.ent[e].nf;
+            const double2 *src = nf == 0 ? in : p.tmp + (2 * (size_t)e + ((nf - 1) & 1)) * N;
+            cfma(acc, p.ent[e].coef, src[idx]);
+        }
+        dst[idx] = acc;
+    }
+}
+
+// generic single mode product with rectangular M (n_out x n_in)
+__global__ void __launch_bounds__(256) k_mode_single(const double2 *__restrict__ X, double2 *__restrict__ Y,
+                                                     const double2 *__restrict__ M, uint32_t L, int nin,
+                                                     int nout, uint32_t R, int transM) {
+    const uint32_t NY = L * (uint32_t)nout * R;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < NY; idx += gridDim.x * blockDim.x) {
+        uint32_t r = idx % R, t = idx / R;
+        uint32_t i = t % nout, l = t / nout;
+        const double2 *xp = X + (size_t)l * nin * R + r;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int j = 0; j < nin; ++j) {
+            double2 m = transM ? M[(size_t)j * nout + i] : M[(size_t)i * nin + j];
+            cfma(acc, m, xp[(size_t)j * R]);
+        }
+        Y[idx] = acc;
+    }
+}
+
+// ============================================================ contractions
+// out[m,n] = sum_{l,r} conj(A[l,m,r]) B[l,n,r]; pass 1 writes per-block partials.
+constexpr int CT_ROWS = 32;
+constexpr int CT_MAXOUT = 16;  // outputs per thread (nA*nB <= 256*16)
+
+__global__ void __launch_bounds__(256) k_contract_part(const double2 *__restrict__ A, const double2 *__restrict__ Bbase,
+                                                       int64_t bstride, uint32_t L, int nA, int nB, uint32_t R,
+                                                       double2 *__restrict__ part) {
+    const int g = blockIdx.y;
+    const double2 *__restrict__ B = Bbase + (size_t)g * bstride;
+    const uint32_t rows = L * R;
+    const uint32_t per = (rows + gridDim.x - 1) / gridDim.x;
+    const uint32_t r0 = blockIdx.x * per, r1 = min(rows, r0 + per);
+    extern __shared__ double2 sct[];
+    double2 *As = sct;                 // CT_ROWS * nA
+    double2 *Bs = sct + CT_ROWS * nA;  // CT_ROWS * nB
+    const int nout = nA * nB;
+    double2 acc[CT_MAXOUT];
+    for (int q = 0; q < CT_MAXOUT; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (uint32_t t0 = r0; t0 < r1; t0 += CT_ROWS) {
+        const int tr = (int)min((uint32_t)CT_ROWS, r1 - t0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < CT_ROWS * nA; q += blockDim.x) {
+            int t = q % CT_ROWS, m = q / CT_ROWS;
+            double2 v = make_double2(0.0, 0.0);
+            if (t < tr) {
+                uint32_t rho = t0 + t, l = rho / R, r = rho % R;
+                v = A[((size_t)l * nA + m) * R + r];
+            }
+            As[t * nA + m] = v;
+        }
+        for (int q = threadIdx.x; q < CT_ROWS * nB; q += blockDim.x) {
+            int t = q % CT_ROWS, m = q / CT_ROWS;
+            double2 v = make_double2(0.0, 0.0);
+            if (t < tr) {
+                uint32_t rho = t0 + t, l = rho / R, r = rho % R;
+                v = B[((size_t)l * nB + m) * R + r];
+            }
+            Bs[t * nB + m] = v;
+        }
+        __syncthreads();
+        for (int q = 0; q < CT_MAXOUT; ++q) {
+            int o = threadIdx.x + q * blockDim.x;
+            if (o >= nout) break;
+            int m = o / nB, nn = o - m * nB;
+            double2 a = acc[q];
+            for (int t = 0; t < tr; ++t) cfmac(a, As[t * nA + m], Bs[t * nB + nn]);
+            acc[q] = a;
+        }
+    }
+    for (int q = 0; q < CT_MAXOUT; ++q) {
+        int o = threadIdx.x + q * blockDim.x;
+        if (o >= nout) break;
+        part[((size_t)g * gridDim.x + blockIdx.x) * nout + o] = acc[q];
+    }
+}
+
+__global__ void k_contract_reduce(const double2 *__restrict__ part, int nblk, int nout,
+                                  double2 *const *gdst, double2 *single) {
+    const int g = blockIdx.y;
+    double2 *dst = single ? single : gdst[g];
+    for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < nout; o += gridDim.x * blockDim.x) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int b = 0; b < nblk; ++b) s = cadd(s, part[((size_t)g * nblk + b) * nout + o]);
+        dst[o] = s;
+    }
+}
+
+static int contract_blocks(uint32_t rows) {
+    int b = (int)((rows + 255) / 256);
+    return b < 1 ? 1 : (b > 64 ? 64 : b);
+}
+
+// ============================================================ QR (Householder)
+// In-place thin QR of the matrix with rows (l, r) and columns j of A[l, j, r]
+// (the index j moved last, other indices in row-major order), following the
+// LAPACK zgeqr2 / zung2r convention.  One work-group.
+__device__ __forceinline__ size_t qr_addr(uint32_t rho, int j, int n, uint32_t R) {
+    return ((size_t)(rho / R) * n + j) * R + (rho % R);
+}
+
+__global__ void __launch_bounds__(1024) k_qr(double2 *A, uint32_t L, int n, uint32_t R, double2 *Rout, int transR) {
+    const uint32_t m = L * R;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ double2 tau_s[64];
+    __shared__ double2 wcol[64];
+    __shared__ double2 red2[16 * 64];
+    __shared__ double red1[16];
+    __shared__ double2 sc[2];  // [0] tau, [1] 1/(alpha-beta)
+    const int CP = 64;            // column slots per pass
+    const int RP = nt / CP;       // row phases
+    const int jc = tid % CP, rp = tid / CP;
+    for (int i = 0; i < n; ++i) {
+        double part = 0.0;
+        for (uint32_t rho = i + 1 + tid; rho < m; rho += nt) part += cabs2(A[qr_addr(rho, i, n, R)]);
+        double xn2 = blk_sum1(part, red1);
+        double2 alpha = A[qr_addr(i, i, n, R)];
+        if (tid == 0) {
+            if (xn2 == 0.0 && alpha.y == 0.0) {
+                sc[0] = make_double2(0.0, 0.0);
+                sc[1] = make_double2(0.0, 0.0);
+            } else {
+                double beta = -copysign(sqrt(cabs2(alpha) + xn2), alpha.x);
+                sc[0] = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                sc[1] = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+                A[qr_addr(i, i, n, R)] = make_double2(beta, 0.0);
+            }
+        }
+        __syncthreads();
+        const double2 tau = sc[0], scl = sc[1];
+        if (tid == 0) tau_s[i] = tau;
+        if (tau.x == 0.0 && tau.y == 0.0) {
+            __syncthreads();
+            continue;
+        }
+        for (uint32_t rho = i + 1 + tid; rho < m; rho += nt) {
+            size_t a = qr_addr(rho, i, n, R);
+            A[a] = cmul(A[a], scl);
+        }
+        __syncthreads();
+        // trailing columns: w_j = sum_rho conj(v_rho) A(rho, j); A -= conj(tau) v w_j
+        for (int j0 = i + 1; j0 < n; j0 += CP) {
+            const int j = j0 + jc;
+            double2 acc = make_double2(0.0, 0.0);
+            if (j < n) {
+                for (uint32_t rho = i + rp; rho < m; rho += RP) {
+                    double2 v = rho == (uint32_t)i ? make_double2(1.0, 0.0) : A[qr_addr(rho, i, n, R)];
+                    cfmac(acc, v, A[qr_addr(rho, j, n, R)]);
+                }
+            }
+            red2[rp * CP + jc] = acc;
+            __syncthreads();
+            if (rp == 0) {
+                double2 s = make_double2(0.0, 0.0);
+                for (int q = 0; q < RP; ++q) s = cadd(s, red2[q * CP + jc]);
+                wcol[jc] = s;
+            }
+            __syncthreads();
+            if (j < n) {
+                const double2 ctau = make_double2(tau.x, -tau.y);
+                const double2 f = cmul(ctau, wcol[jc]);
+                for (uint32_t rho = i + rp; rho < m; rho += RP) {
+                    double2 v = rho == (uint32_t)i ? make_double2(1.0, 0.0) : A[qr_addr(rho, i, n, R)];
+                    size_t a = qr_addr(rho, j, n, R);
+                    A[a] = csub(A[a], cmul(v, f));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // R factor
+    for (int q = tid; q < n * n; q += nt) {
+        int i = q / n, j = q % n;
+        double2 v = j >= i ? A[qr_addr(i, j, n, R)] : make_double2(0.0, 0.0);
+        if (transR) Rout[j * n + i] = v;
+        else Rout[i * n + j] = v;
+    }
+    __syncthreads();
+    // form Q in place (zung2r)
+    for (int i = n - 1; i >= 0; --i) {
+        const double2 tau = tau_s[i];
+        for (int j0 = i + 1; j0 < n; j0 += CP) {
+            const int j = j0 + jc;
+            double2 acc = make_double2(0.0, 0.0);
+            if (j < n) {
+                for (uint32_t rho = i + rp; rho < m; rho += RP) {
+                    double2 v = rho == (uint32_t)i ? make_double2(1.0, 0.0) : A[qr_addr(rho, i, n, R)];
+                    cfmac(acc, v, A[qr_addr(rho, j, n, R)]);
+                }
+            }
+            red2[rp * CP + jc] = acc;
+            __syncthreads();
+            if (rp == 0) {
+                double2 s = make_double2(0.0, 0.0);
+                for (int q = 0; q < RP; ++q) s = cadd(s, red2[q * CP + jc]);
+                wcol[jc] = s;
+            }
+            __syncthreads();
+            if (j < n) {
+                const double2 f = cmul(tau, wcol[jc]);
+                for (uint32_t rho = i + rp; rho < m; rho += RP) {
+                    double2 v = rho == (uint32_t)i ? make_double2(1.0, 0.0) : A[qr_addr(rho, i, n, R)];
+                    size_t a = qr_addr(rho, j, n, R);
+                    A[a] = csub(A[a], cmul(v, f));
+                }
+            }
+            __syncthreads();
+        }
+        const double2 mt = make_double2(-tau.x, -tau.y);
+        for (uint32_t rho = tid; rho < m; rho += nt) {
+            size_t a = qr_addr(rho, i, n, R);
+            if (rho > (uint32_t)i) A[a] = cmul(mt, A[a]);
+            else if (rho == (uint32_t)i) A[a] = make_double2(1.0 - tau.x, -tau.y);
+            else A[a] = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+    }
+}
+
+// ============================================================ small matrix exponential
+// y = exp(X) e_0 for X = -i tau H (H m x m row-major in LDS, m <= SMALL_MMAX), by
+// Taylor series of degree 14 after scaling to ||X||_1 <= 1/2, then squaring.
+// ws: 3*m*m complex LDS.  All threads of the block must call.
+__device__ void blk_expm_col0(const double2 *H, int ldh, int m, double tau, double2 *ws, double *red,
+                              double2 *y) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double2 *X = ws, *P = ws + m * m, *T = ws + 2 * m * m;
+    for (int q = tid; q < m * m; q += nt) {
+        int i = q / m, j = q % m;
+        double2 h = H[i * ldh + j];
+        X[q] = make_double2(tau * h.y, -tau * h.x);
+    }
+    __syncthreads();
+    double cs = 0.0;
+    if (tid < m)
+        for (int i = 0; i < m; ++i) cs += sqrt(cabs2(X[i * m + tid]));
+    // max over columns via reduction of maxima
+    const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
+    for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
+    if (lane == 0) red[wave] = cs;
+    __syncthreads();
+    double nrm = 0.0;
+    for (int w = 0; w < nw; ++w) nrm = fmax(nrm, red[w]);
+    int s = 0;
+    while (nrm > 0.5 && s < 60) {
+        nrm *= 0.5;
+        ++s;
+    }
+    const double scale = ldexp(1.0, -s);
+    __syncthreads();
+    for (int q = tid; q < m * m; q += nt) {
+        X[q] = cscale(X[q], scale);
+        P[q] = make_double2((q / m) == (q % m) ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int k = 14; k >= 1; --k) {
+        for (int q = tid; q < m * m; q += nt) {
+            int i = q / m, c = q % m;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int t = 0; t < m; ++t) cfma(acc, X[i * m + t], P[t * m + c]);
+            T[q] = acc;
+        }
+        __syncthreads();
+        const double inv = 1.0 / k;
+        for (int q = tid; q < m * m; q += nt) {
+            double2 v = cscale(T[q], inv);
+            if ((q / m) == (q % m)) v.x += 1.0;
+            P[q] = v;
+        }
+        __syncthreads();
+    }
+    for (int r = 0; r < s; ++r) {
+        for (int q = tid; q < m * m; q += nt) {
+            int i = q / m, c = q % m;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int t = 0; t < m; ++t) cfma(acc, P[i * m + t], P[t * m + c]);
+            T[q] = acc;
+        }
+        __syncthreads();
+        for (int q = tid; q < m * m; q += nt) P[q] = T[q];
+        __syncthreads();
+    }
+    for (int i = tid; i < m; i += nt) y[i] = P[i * m];
+    __syncthreads();
+}
+
+// ============================================================ fused small solver
+__device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M, const Geom &g, int s) {
+    const int n = g.dims[s];
+    const uint32_t R = (uint32_t)g.R[s], N = (uint32_t)g.N;
+    for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) {
+        uint32_t r = idx % R, t = idx / R;
+        uint32_t i = t % n, l = t / n;
+        const double2 *xp = src + (size_t)l * n * R + r;
+        const double2 *mr = M + (size_t)i * n;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int j = 0; j < n; ++j) cfma(acc, mr[j], xp[(size_t)j * R]);
+        dst[idx] = acc;
+    }
+}
+
+__device__ void blk_matvec(const SmallSolveArgs &a, const double2 *v, double2 *w, double2 *t1, double2 *t2) {
+    const uint32_t N = (uint32_t)a.g.N;
+    for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) w[idx] = make_double2(0.0, 0.0);
+    for (int e = 0; e < a.n_ent; ++e) {
+        const DevEntry *E = a.ent + e;
+        const int nf = E->nf;
+        const double2 *cur = v;
+        for (int f = 0; f < nf; ++f) {
+            double2 *dst = (f & 1) ? t2 : t1;
+            __syncthreads();
+            blk_mode_lds(cur, dst, E->M[f], a.g, E->slot[f]);
+            cur = dst;
+        }
+        __syncthreads();
+        const double2 c = E->coef;
+        for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) cfma(w[idx], c, cur[idx]);
+    }
+    __syncthreads();
+}
+
+// One Krylov exponential x <- exp(-i tau G) x; returns true when converged.
+__device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x, double2 *v, double2 *w,
+                                double2 *t1, double2 *t2, double2 *Hm, double2 *ex, double2 *red8, double *red1,
+                                double2 *hbuf, double2 *ybuf, int &m_used, int &matvecs, double &err_out) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t N = (uint32_t)a.g.N;
+    const int mmax = a.mmax;
+    double2 *V = a.V;
+    double part = 0.0;
+    for (uint32_t idx = tid; idx < N; idx += nt) part += cabs2(x[idx]);
+    const double beta0 = sqrt(blk_sum1(part, red1));
+    if (beta0 == 0.0) {
+        m_used = 0;
+        err_out = 0.0;
+        return true;
+    }
+    for (uint32_t idx = tid; idx < N; idx += nt) {
+        double2 q = cscale(x[idx], 1.0 / beta0);
+        v[idx] = q;
+        V[idx] = q;
+    }
+    for (int q = tid; q < (mmax + 1) * mmax; q += nt) Hm[q] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int j = 0; j < mmax; ++j) {
+        blk_matvec(a, v, w, t1, t2);
+        ++matvecs;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i0 = 0; i0 <= j; i0 += 8) {
+                const int cnt = min(8, j + 1 - i0);
+                double2 acc[8];
+                for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+                for (uint32_t idx = tid; idx < N; idx += nt) {
+                    const double2 wv = w[idx];
+                    for (int q = 0; q < cnt; ++q) cfmac(acc[q], V[(size_t)(i0 + q) * N + idx], wv);
+                }
+                blk_sum8(acc, cnt, red8, hbuf + i0);
+            }
+            for (uint32_t idx = tid; idx < N; idx += nt) {
+                double2 wv = w[idx];
+                for (int i = 0; i <= j; ++i) wv = csub(wv, cmul(hbuf[i], V[(size_t)i * N + idx]));
+                w[idx] = wv;
+            }
+            if (tid <= j) Hm[tid * mmax + j] = cadd(Hm[tid * mmax + j], hbuf[tid]);
+            __syncthreads();
+        }
+        part = 0.0;
+        for (uint32_t idx = tid; idx < N; idx += nt) part += cabs2(w[idx]);
+        const double beta = sqrt(blk_sum1(part, red1));
+        if (tid == 0) Hm[(j + 1) * mmax + j] = make_double2(beta, 0.0);
+        __syncthreads();
+        const bool breakdown = beta <= 1e-14 * beta0;
+        if (breakdown || j + 1 >= a.m_hint - 2 || j == mmax - 1) {
+            // projected matrix of dimension j+1 (tridiagonal for Hermitian G)
+            double2 *Hs = ex;  // (j+1)^2 staging, then expm workspace after it
+            const int m = j + 1;
+            for (int q = tid; q < m * m; q += nt) {
+                int r = q / m, c = q % m;
+                double2 h;
+                if (a.hermitian) {
+                    if (r == c) h = make_double2(Hm[r * mmax + r].x, 0.0);
+                    else if (r == c + 1) h = Hm[r * mmax + c];
+                    else if (c == r + 1) h = Hm[c * mmax + r];
+                    else h = make_double2(0.0, 0.0);
+                } else {
+                    h = Hm[r * mmax + c];
+                }
+                Hs[q] = h;
+            }
+            __syncthreads();
+            blk_expm_col0(Hs, m, m, tau, ex + m * m, red1, ybuf);
+            const double err = beta0 * beta * sqrt(cabs2(ybuf[j]));
+            if (breakdown || err <= a.tol * beta0) {
+                for (uint32_t idx = tid; idx < N; idx += nt) {
+                    double2 acc = make_double2(0.0, 0.0);
+                    for (int i = 0; i <= j; ++i) cfma(acc, ybuf[i], V[(size_t)i * N + idx]);
+                    x[idx] = cscale(acc, beta0);
+                }
+                m_used = j + 1;
+                err_out = breakdown ? 0.0 : err / beta0;
+                __syncthreads();
+                return true;
+            }
+            err_out = err / beta0;
+        }
+        if (j == mmax - 1) break;
+        const double ib = 1.0 / beta;
+        for (uint32_t idx = tid; idx < N; idx += nt) {
+            double2 q = cscale(w[idx], ib);
+            v[idx] = q;
+            V[(size_t)(j + 1) * N + idx] = q;
+        }
+        __syncthreads();
+    }
+    m_used = mmax;
+    return false;
+}
+
+__global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a) {
+    extern __shared__ double2 sm[];
+    const uint32_t N = (uint32_t)a.g.N;
+    const int mmax = a.mmax;
+    double2 *v = sm, *w = v + N, *t1 = w + N, *t2 = t1 + N;
+    double2 *Hm = t2 + N;
+    double2 *ex = Hm + (mmax + 1) * mmax;   // (mmax^2 staging) + 3 mmax^2 workspace
+    double2 *red8 = ex + 4 * mmax * mmax;   // 16 * 8
+    double2 *hbuf = red8 + 16 * 8;          // mmax + 1
+    double2 *ybuf = hbuf + (mmax + 1);      // mmax
+    double *red1 = reinterpret_cast<double *>(ybuf + mmax);  // 16
+    double2 *x = a.x;
+    double2 *xorig = a.V + (size_t)(SMALL_MMAX + 1) * N;
+    for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) xorig[idx] = x[idx];
+    __syncthreads();
+    int m_used = 0, matvecs = 0, level = 0;
+    double err = 0.0;
+    bool ok = false;
+    for (level = 0; level <= 8; ++level) {
+        if (level > 0) {
+            for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) x[idx] = xorig[idx];
+            __syncthreads();
+        }
+        const int nsub = 1 << level;
+        ok = true;
+        for (int q = 0; q < nsub && ok; ++q)
+            ok = blk_krylov_once(a, a.tau / nsub, x, v, w, t1, t2, Hm, ex, red8, red1, hbuf, ybuf, m_used,
+                                 matvecs, err);
+        if (ok) break;
+    }
+    if (threadIdx.x == 0 && a.stat) {
+        a.stat->m = m_used;
+        a.stat->level = ok ? level : -1;
+        a.stat->fail = ok ? 0 : 1;
+        a.stat->matvecs = matvecs;
+        a.stat->err = err;
+        a.stat->err_lo = 0.0;
+    }
+}
+
+size_t small_solve_lds_bytes(int64_t N, int mmax) {
+    return sizeof(double2) * (size_t)(4 * N + (mmax + 1) * mmax + 4 * mmax * mmax + 16 * 8 + (mmax + 1) + mmax) +
+           16 * sizeof(double);
+}
+
+// ============================================================ multi-kernel Krylov
+// Last-block reduction: every block stores its partials, the block that
+// finishes last (atomic ticket) sums them in a fixed order.
+__device__ bool last_block_ticket(unsigned *counter) {
+    __shared__ int is_last;
+    __threadfence();  // every thread releases its partial-sum stores device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last != 0;
+}
+
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_norm0(const double2 *__restrict__ x, uint32_t N, BigKrylov k) {
+    __shared__ double red1[16];
+    double part = 0.0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) part += cabs2(x[i]);
+    double s = blk_sum1(part, red1);
+    if (threadIdx.x == 0) k.part[blockIdx.x] = s;
+    if (last_block_ticket(k.counter)) {
+        double t = 0.0;
+        if (threadIdx.x == 0) {
+            for (unsigned b = 0; b < gridDim.x; ++b) t += k.part[b];
+            k.scal[0] = sqrt(t);
+            *k.meff = 0;
+            *k.counter = 0;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_scale0(const double2 *__restrict__ x, uint32_t N, BigKrylov k) {
+    const double b0 = k.scal[0];
+    const double ib = b0 > 0.0 ? 1.0 / b0 : 0.0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+        k.V[i] = cscale(x[i], ib);
+}
+
+// pass = 0: partial dots of w = V[j+1] against V[0..j] -> h, Hm[:, j] = h
+// pass = 1,2: w -= V h, then (pass 1) dots again (Hm += h) / (pass 2) norm
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_orth(BigKrylov k, uint32_t N, int j, int mmax, int pass) {
+    if (*k.meff) return;
+    __shared__ double2 red8[16 * 8];
+    __shared__ double2 hb[64];
+    __shared__ double red1[16];
+    const int nv = j + 1;
+    double2 *w = k.V + (size_t)(j + 1) * N;
+    if (pass > 0) {
+        for (int q = threadIdx.x; q < nv; q += blockDim.x) hb[q] = k.h[q];
+        __syncthreads();
+        for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+            double2 wv = w[idx];
+            for (int i = 0; i < nv; ++i) wv = csub(wv, cmul(hb[i], k.V[(size_t)i * N + idx]));
+            w[idx] = wv;
+        }
+    }
+    const int K = (pass < 2) ? nv : 1;
+    double *part = k.part;
+    if (pass < 2) {
+        for (int i0 = 0; i0 < nv; i0 += 8) {
+            const int cnt = min(8, nv - i0);
+            double2 acc[8];
+            for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+            for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+                const double2 wv = w[idx];
+                for (int q = 0; q < cnt; ++q) cfmac(acc[q], k.V[(size_t)(i0 + q) * N + idx], wv);
+            }
+            blk_sum8(acc, cnt, red8, hb + i0);
+        }
+        if (threadIdx.x < nv) {
+            part[2 * ((size_t)blockIdx.x * K + threadIdx.x)] = hb[threadIdx.x].x;
+            part[2 * ((size_t)blockIdx.x * K + threadIdx.x) + 1] = hb[threadIdx.x].y;
+        }
+    } else {
+        double p = 0.0;
+        for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x)
+            p += cabs2(w[idx]);
+        double s = blk_sum1(p, red1);
+        if (threadIdx.x == 0) part[2 * (size_t)blockIdx.x] = s;
+    }
+    if (last_block_ticket(k.counter)) {
+        if (pass < 2) {
+            for (int q = threadIdx.x; q < nv; q += blockDim.x) {
+                double2 s = make_double2(0.0, 0.0);
+                for (unsigned b = 0; b < gridDim.x; ++b)
+                    s = cadd(s, make_double2(part[2 * ((size_t)b * K + q)], part[2 * ((size_t)b * K + q) + 1]));
+                k.h[q] = s;
+                double2 *hcol = k.Hm + (size_t)j * (mmax + 1);
+                hcol[q] = pass == 0 ? s : cadd(hcol[q], s);
+            }
+        } else if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += part[2 * (size_t)b];
+            const double beta = sqrt(s);
+            k.scal[1] = beta;
+            k.Hm[(size_t)j * (mmax + 1) + j + 1] = make_double2(beta, 0.0);
+            if (beta <= 1e-14 * k.scal[0]) *k.meff = j + 1;
+        }
+        if (threadIdx.x == 0) *k.counter = 0;
+    }
+}
+
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_normalize(BigKrylov k, uint32_t N, int j) {
+    if (*k.meff) return;
+    const double ib = 1.0 / k.scal[1];
+    double2 *w = k.V + (size_t)(j + 1) * N;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x)
+        w[idx] = cscale(w[idx], ib);
+}
+
+// exp of the projected matrix (one work-group); y = beta0 exp(-i tau H_m) e_0
+__global__ void __launch_bounds__(1024) k_kry_expm(BigKrylov k, int m, int mmax, double tau, double tol,
+                                                   int hermitian, SolveStat *stat) {
+    extern __shared__ double2 sme[];
+    __shared__ double red1[16];
+    const int meff = *k.meff;
+    const int mm = meff ? meff : m;
+    double2 *Hs = sme;               // mm^2
+    double2 *ws = sme + mm * mm;     // 3 mm^2
+    double2 *y = ws + 3 * mm * mm;   // mm
+    const double beta0 = k.scal[0];
+    double errs[2] = {0.0, 0.0};
+    for (int pass = 0; pass < 2; ++pass) {
+        const int md = pass == 0 ? mm : mm - 2;
+        if (md < 1) break;
+        for (int q = threadIdx.x; q < md * md; q += blockDim.x) {
+            int r = q / md, c = q % md;
+            double2 h;
+            const double2 *col = k.Hm + (size_t)c * (mmax + 1);
+            if (hermitian) {
+                if (r == c) h = make_double2(col[r].x, 0.0);
+                else if (r == c + 1) h = col[r];
+                else if (c == r + 1) h = k.Hm[(size_t)r * (mmax + 1) + c];
+                else h = make_double2(0.0, 0.0);
+            } else {
+                h = col[r];
+            }
+            Hs[q] = h;
+        }
+        __syncthreads();
+        blk_expm_col0(Hs, md, md, tau, ws, red1, y);
+        const double hnext = k.Hm[(size_t)(md - 1) * (mmax + 1) + md].x;
+        errs[pass] = (pass == 0 && meff) ? 0.0 : hnext * sqrt(cabs2(y[md - 1]));
+        if (pass == 0) {
+            for (int q = threadIdx.x; q < mm; q += blockDim.x) k.y[q] = cscale(y[q], beta0);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && stat) {
+        stat->m = mm;
+        stat->level = 0;
+        stat->fail = errs[0] > tol ? 1 : 0;
+        stat->matvecs = mm;
+        stat->err = errs[0];
+        stat->err_lo = (mm - 2 >= 1) ? errs[1] : 1.0;
+    }
+}
+
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_combine(BigKrylov k, uint32_t N, int m, double2 *x) {
+    const int meff = *k.meff;
+    const int mm = meff ? meff : m;
+    __shared__ double2 yb[64];
+    for (int q = threadIdx.x; q < mm; q += blockDim.x) yb[q] = k.y[q];
+    __syncthreads();
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = 0; i < mm; ++i) cfma(acc, yb[i], k.V[(size_t)i * N + idx]);
+        x[idx] = acc;
+    }
+}
+
+// ============================================================ misc
+__global__ void k_copy(double2 *dst, const double2 *src, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+__global__ void k_transpose(double2 *dst, const double2 *src, int n) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n * n; q += gridDim.x * blockDim.x) {
+        int i = q / n, j = q % n;
+        dst[j * n + i] = src[q];
+    }
+}
+
+// ============================================================ launchers
+static inline unsigned grid_for(int64_t n, int threads, int cap = 2048) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st) {
+    if (p.n_ent == 0) return;
+    int maxn = 0;
+    for (int s = 0; s < p.g.D; ++s) maxn = maxn > p.g.dims[s] ? maxn : p.g.dims[s];
+    const int ldn = maxn <= 64 ? maxn : 0;
+    const size_t lds = sizeof(double2) * (size_t)ldn * ldn;
+    for (int s = 0; s < p.max_nf; ++s) {
+        dim3 grid(grid_for(p.g.N, 256), p.n_ent);
+        hipLaunchKernelGGL(k_mode_stage, grid, dim3(256), lds, st, p, s, in, ldn);
+    }
+}
+
+void launch_prog_sum(const ProgView &p, const double2 *in, double2 *out_single, hipStream_t st) {
+    dim3 grid(grid_for(p.g.N, 256), out_single ? 1 : p.n_groups);
+    hipLaunchKernelGGL(k_group_sum, grid, dim3(256), 0, st, p, in, out_single);
+}
+
+void launch_prog_contract(const ProgView &p, const double2 *A, hipStream_t st) {
+    const int s = p.contract_slot;
+    const int n = p.g.dims[s];
+    const uint32_t L = (uint32_t)p.g.L[s], R = (uint32_t)p.g.R[s];
+    const int nb = contract_blocks(L * R);
+    const size_t lds = sizeof(double2) * (size_t)CT_ROWS * 2 * n;
+    hipLaunchKernelGGL(k_contract_part, dim3(nb, p.n_groups), dim3(256), lds, st, A, (const double2 *)p.gsum,
+                       p.g.N, L, n, n, R, p.cpart);
+    hipLaunchKernelGGL(k_contract_reduce, dim3(grid_for(n * n, 256), p.n_groups), dim3(256), 0, st,
+                       (const double2 *)p.cpart, nb, n * n, p.gdst, (double2 *)nullptr);
+}
+
+void launch_mode_product(const double2 *X, double2 *Y, const double2 *M, int64_t L, int n_in, int n_out,
+                         int64_t R, int transM, hipStream_t st) {
+    const int64_t NY = L * n_out * R;
+    hipLaunchKernelGGL(k_mode_single, dim3(grid_for(NY, 256)), dim3(256), 0, st, X, Y, M, (uint32_t)L, n_in,
+                       n_out, (uint32_t)R, transM);
+}
+
+void launch_contract(const double2 *A, const double2 *B, double2 *out, int64_t L, int nA, int nB, int64_t R,
+                     double2 *part, hipStream_t st) {
+    const int nb = contract_blocks((uint32_t)(L * R));
+    const size_t lds = sizeof(double2) * (size_t)CT_ROWS * (nA + nB);
+    hipLaunchKernelGGL(k_contract_part, dim3(nb, 1), dim3(256), lds, st, A, B, (int64_t)0, (uint32_t)L, nA, nB,
+                       (uint32_t)R, part);
+    hipLaunchKernelGGL(k_contract_reduce, dim3(grid_for(nA * nB, 256), 1), dim3(256), 0, st,
+                       (const double2 *)part, nb, nA * nB, (double2 *const *)nullptr, out);
+}
+
+void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st) {
+    hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, st, A, (uint32_t)L, n, (uint32_t)R, Rout, transR);
+}
+
+void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
+    const size_t lds = small_solve_lds_bytes(a.g.N, a.mmax);
+    if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds > 160 * 1024)
+        throw std::runtime_error("small solve out of range");
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute((const void *)k_small_solve, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(SMALL_THREADS), lds, st, a);
+}
+
+void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256)), dim3(256), 0, st, dst, src, (uint32_t)n);
+}
+
+void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_transpose, dim3(grid_for((int64_t)n * n, 256)), dim3(256), 0, st, dst, src, n);
+}
+
+void launch_krylov_start(const double2 *x, int64_t N, const BigKrylov &k, hipStream_t st) {
+    hipLaunchKernelGGL(k_kry_norm0, dim3(VEC_BLOCKS), dim3(VEC_THREADS), 0, st, x, (uint32_t)N, k);
+    hipLaunchKernelGGL(k_kry_scale0, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, x, (uint32_t)N, k);
+}
+
+void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st) {
+    for (int pass = 0; pass < 3; ++pass)
+        hipLaunchKernelGGL(k_kry_orth, dim3(VEC_BLOCKS), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, pass);
+    hipLaunchKernelGGL(k_kry_normalize, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, k,
+                       (uint32_t)N, j);
+}
+
+void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double tau, double tol, int hermitian,
+                          double2 *x, SolveStat *stat, hipStream_t st) {
+    const size_t lds = sizeof(double2) * (size_t)(4 * m * m + m);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute((const void *)k_kry_expm, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_kry_expm, dim3(1), dim3(1024), lds, st, k, m, mmax, tau, tol, hermitian, stat);
+    hipLaunchKernelGGL(k_kry_combine, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, m,
+                       x);
+}
+
+}  // namespace ttn

@@ -1,0 +1,157 @@
+"""GPU parity: the HIP path (through the C boundary) against the CPU oracle.
+
+Tolerances: the FP64 path must reproduce the oracle's observables to 1e-10
+absolute (the unitary observables are O(1)); the measured rounding jitter of
+the oracle itself on these runs is ~1e-13, and both sides stop their local
+Krylov exponentials at a 1e-13 relative error estimate.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from workloads import heom_sbm_problem, random_isometric_state, sbm_problem, vibronic_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_15460_amd as mod
+    return mod
+
+
+def _pair(T, p, bond=None, state=None, **kw):
+    g = T.TTN.from_problem(p, bond_dim=bond, **kw)
+    o = Oracle(p, bond_dim=bond)
+    assert np.array_equal(g.bonds(), o.bond)
+    if state is None:
+        g.set_product_state(p.init_vecs)
+        o.set_product_state(p.init_vecs)
+    else:
+        g.set_state(state)
+        o.set_state(state)
+    return g, o
+
+
+def _gauge_free_overlap(a_tensors, b_tensors, o):
+    return o._contract(a_tensors, b_tensors, {})
+
+
+def test_root_heff_brute(T):
+    """H_eff at the root (children SPOs from the env kernels) equals the oracle's."""
+    p = sbm_problem(n_modes=4, d=6, bond=4, alpha=0.4)
+    o0 = Oracle(p)
+    st = random_isometric_state(p.parent, p.local_dim, o0.bond, seed=21)
+    g, o = _pair(T, p, state=st)
+    rng = np.random.default_rng(1)
+    shp = o.A[o.root].shape
+    x = rng.normal(size=shp) + 1j * rng.normal(size=shp)
+    y = g.apply_root_heff(x.reshape(-1)).reshape(shp)
+    ref = o.heff(o.root, x)
+    assert np.abs(y - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_observables_match(T):
+    p = sbm_problem(n_modes=4, d=6, bond=4, alpha=0.4)
+    o0 = Oracle(p)
+    st = random_isometric_state(p.parent, p.local_dim, o0.bond, seed=22)
+    g, o = _pair(T, p, state=st)
+    assert abs(g.norm2() - o.norm2()) < 1e-12
+    assert abs(g.energy() - o.energy()) < 1e-12
+    for name in ("sz", "sx"):
+        assert abs(g.expect(p.observables[name]) - o.expect(p.observables[name])) < 1e-12
+    b1 = p.leaf_names["b1"]
+    S = p.leaf_names["S"]
+    ids = [p.observables["sz"][0], p.op_leaf.index(b1) if b1 in p.op_leaf else None]
+    ids = [i for i in ids if i is not None]
+    assert abs(g.expect(ids) - o.expect(ids)) < 1e-12
+    vecs = {z: np.random.default_rng(z).normal(size=p.local_dim[z]) + 0j for z in p.leaves()}
+    assert abs(g.bilinear(vecs) - o.bilinear(vecs)) < 1e-12
+    g.step(p.dt, 3)
+    for _ in range(3):
+        o.step(p.dt)
+    assert abs(g.overlap_t0() - o.overlap_t0()) < 1e-11
+
+
+def test_sbm4_product_state_parity(T):
+    """Spin-boson, 4 modes x 8 levels, binary tree, bond 4, 100 steps dt = 0.05."""
+    p = sbm_problem(n_modes=4, d=8, bond=4)
+    g, o = _pair(T, p)
+    sz_g, sz_o = [], []
+    for _ in range(100):
+        g.step(p.dt)
+        o.step(p.dt)
+        sz_g.append(g.expect(p.observables["sz"]))
+        sz_o.append(o.expect(p.observables["sz"]))
+    sz_g, sz_o = np.array(sz_g), np.array(sz_o)
+    assert np.abs(sz_g - sz_o).max() < TOL
+    assert abs(g.norm2() - 1.0) < 1e-12
+    # identical Householder convention: node tensors agree element-wise
+    for a, b in zip(g.get_state(), o.state()):
+        assert np.abs(a - b).max() < 1e-9
+    c = g.counters()
+    assert c["steps"] == 100 and c["forward_solves"] == 100 * (2 * p.n_nodes - 1)
+    assert c["backward_solves"] == 100 * 2 * (p.n_nodes - 1)
+
+
+def test_big_path_random_state_parity(T):
+    """Nodes above the fused-solver size exercise the multi-kernel Krylov path."""
+    p = sbm_problem(n_modes=8, d=6, bond=16, alpha=0.3, dt=0.05)
+    o0 = Oracle(p)
+    assert max(int(np.prod(o0.shape(z))) for z in range(p.n_nodes)) > 1024
+    st = random_isometric_state(p.parent, p.local_dim, o0.bond, seed=5)
+    g, o = _pair(T, p, state=st)
+    e0 = o.energy()
+    for _ in range(4):
+        g.step(p.dt)
+        o.step(p.dt)
+        assert abs(g.expect(p.observables["sz"]) - o.expect(p.observables["sz"])) < TOL
+    assert abs(g.energy() - e0) < 1e-9 * abs(e0)
+    assert abs(abs(_gauge_free_overlap(g.get_state(), o.state(), o)) - 1.0) < 1e-10
+
+
+def test_reduced_vibronic_parity(T):
+    """Vibronic 2-state model, 8 modes, 3-layer tree, populations and a(t)."""
+    p = vibronic_problem(n_modes=8, dmin=4, dmax=6, leaf_bond=4, l_bond=6, m_bond=8, dt=0.5)
+    g, o = _pair(T, p)
+    for s in range(6):
+        g.step(p.dt)
+        o.step(p.dt)
+        for name in ("P0", "P1"):
+            assert abs(g.expect(p.observables[name]) - o.expect(p.observables[name])) < TOL
+        assert abs(g.overlap_t0() - o.overlap_t0()) < TOL
+
+
+def test_negative_dt_reverses(T):
+    p = sbm_problem(n_modes=4, d=6, bond=4, alpha=0.3)
+    o0 = Oracle(p)
+    st = random_isometric_state(p.parent, p.local_dim, o0.bond, seed=9)
+    g, o = _pair(T, p, state=st)
+    g.step(p.dt, 10)
+    ref = g.get_state()
+    g.step(p.dt, 5)
+    g.step(-p.dt, 5)
+    assert abs(abs(_gauge_free_overlap(ref, g.get_state(), o)) - 1.0) < 1e-11
+
+
+def test_non_hermitian_rejected_with_lanczos(T):
+    p = heom_sbm_problem(K=1, levels=3)
+    with pytest.raises(T.TTNError) as e:
+        T.TTN.from_problem(p, hermitian=True)
+    assert "E_INVALID" in str(e.value)
+
+
+def test_state_errors(T):
+    p = sbm_problem(n_modes=2, d=3, bond=2)
+    g = T.TTN(p.parent, p.local_dim, p.bond_dim)
+    with pytest.raises(T.TTNError) as e:
+        g.step(0.1)
+    assert "E_STATE" in str(e.value)
+    g.set_sop_problem(p)
+    with pytest.raises(T.TTNError):
+        g.set_state([np.zeros(1)])

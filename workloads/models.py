@@ -227,10 +227,12 @@ def vibronic_problem(seed: int = 2, n_modes: int = 24, dmin: int = 8, dmax: int 
         for s in range(2):
             gq = float(np.clip(rng.normal(0.0, 0.05), -0.25 * omega[i], 0.25 * omega[i]))
             add_term(p, c * gq, [op(E, f"P{s}", P[s]), op(qs[i], "q2", bos[i]["q2"])])
-    n_bil = 40
+    n_within_max = 6 * n_groups
+    n_bil = min(40, n_modes * (n_modes - 1) // 4)
+    n_within = min(3 * n_bil // 4, n_within_max)
     pairs = set()
     while len(pairs) < n_bil:
-        if len(pairs) < 3 * n_bil // 4:
+        if len(pairs) < n_within:
             grp = groups[rng.integers(n_groups)]
             i, j = sorted(rng.choice(grp, size=2, replace=False))
         else:
