@@ -25,7 +25,8 @@ What it follows (paper: pyTTN, arXiv 2503.15460):
   followed by its mirror S*(dt/2), children in increasing id order in S and in
   decreasing order in S*, with the two root forward half steps merged into
   one full step.
-* QR gauge shifts in the LAPACK Householder convention (numpy.linalg.qr).
+* QR gauge shifts by Householder reflections in the LAPACK convention, with a
+  relative zero-snap of 1e-12 for the rank-deficient factors of product states.
 * Local exponentials: dense ``expm`` for local problems up to ``dense_max``
   unknowns, otherwise Lanczos (Hermitian) or Arnoldi (non-Hermitian) with full
   re-orthogonalisation and an a-posteriori error estimate.
@@ -128,7 +129,10 @@ def contract_except(A: np.ndarray, B: np.ndarray, axis: int) -> np.ndarray:
     return a.conj().T @ b
 
 
-def householder_qr_lapack(M: np.ndarray):
+SNAP = 1e-12  # relative zero-snap of the QR (reading of the unstated QR convention)
+
+
+def householder_qr_lapack(M: np.ndarray, snap: float = 0.0):
     """Thin QR by Householder reflections in the LAPACK zgeqr2/zung2r convention.
 
     Each reflector is ``H = I - tau v v^H`` with ``v_0 = 1``; for a column
@@ -136,16 +140,29 @@ def householder_qr_lapack(M: np.ndarray):
     otherwise ``beta = -sign(Re alpha) |(alpha, x)|``, ``tau = (beta -
     alpha)/beta``, ``v = (1, x/(alpha - beta))``.  The factorisation applies
     ``H^H`` to the trailing columns and ``Q = H_1 ... H_n`` restricted to the
-    first ``n`` columns.  Plain loops; used to pin numpy's convention.
+    first ``n`` columns.  Plain loops.
+
+    ``snap > 0``: a sub-column with ``|x| <= snap |M|_F`` is set to exactly zero
+    (and so is ``Im alpha`` when ``|Im alpha| <= snap |M|_F``) before the
+    reflector is formed, so that rounding noise in structurally empty columns
+    cannot choose the completion of a rank-deficient factor.  ``snap = 0`` is
+    plain LAPACK (pinned against numpy.linalg.qr).
     """
     A = np.array(M, dtype=np.complex128, copy=True)
     m, n = A.shape
     k = min(m, n)
+    thr = snap * np.linalg.norm(A)
     taus = np.zeros(k, dtype=np.complex128)
     for i in range(k):
-        alpha = A[i, i]
         x = A[i + 1:, i]
         xnorm = np.linalg.norm(x)
+        if snap > 0.0 and xnorm <= thr:
+            A[i + 1:, i] = 0.0
+            xnorm = 0.0
+            if abs(A[i, i].imag) <= thr:
+                A[i, i] = A[i, i].real
+        alpha = A[i, i]
+        x = A[i + 1:, i]
         if xnorm == 0.0 and alpha.imag == 0.0:
             tau = 0.0
         else:
@@ -538,10 +555,13 @@ class Oracle:
     # ---------------------------------------------------------- gauge
     @staticmethod
     def qr_along(A: np.ndarray, axis: int):
-        """QR of A matricised with ``axis`` as the columns (rows: other indices in order)."""
+        """QR of A matricised with ``axis`` as the columns (rows: other indices in order).
+
+        LAPACK-convention Householder with the relative zero-snap ``SNAP``.
+        """
         M = np.moveaxis(A, axis, -1)
         shp = M.shape
-        Q, R = np.linalg.qr(M.reshape(-1, shp[-1]))
+        Q, R = householder_qr_lapack(M.reshape(-1, shp[-1]), snap=SNAP)
         return np.moveaxis(Q.reshape(shp[:-1] + (Q.shape[1],)), -1, axis), R
 
     # ---------------------------------------------------------- sweeps

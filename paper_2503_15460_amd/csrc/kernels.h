@@ -14,6 +14,10 @@ constexpr int SMALL_MMAX = 32;    // Krylov dimension limit of the fused solver 
 constexpr int SMALL_THREADS = 1024;
 constexpr int VEC_BLOCKS = 256;   // work-groups of the multi-kernel vector operations
 constexpr int VEC_THREADS = 256;
+// QR zero-snap: Householder sub-columns with norm <= QR_SNAP * |M|_F are treated
+// as exactly zero, so that rounding noise in structurally empty columns of a
+// product state cannot choose the completion of a rank-deficient factor.
+constexpr double QR_SNAP = 1e-12;
 
 // Geometry of a node tensor: slot s has L[s] = prod dims[<s], R[s] = prod dims[>s].
 struct Geom {

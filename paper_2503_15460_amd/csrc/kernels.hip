@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <stdexcept>
+#include <string>
 
 #include "kernels.h"
 
@@ -234,7 +235,8 @@ __device__ __forceinline__ size_t qr_addr(uint32_t rho, int j, int n, uint32_t R
     return ((size_t)(rho / R) * n + j) * R + (rho % R);
 }
 
-__global__ void __launch_bounds__(1024) k_qr(double2 *A, uint32_t L, int n, uint32_t R, double2 *Rout, int transR) {
+__global__ void __launch_bounds__(1024) k_qr(double2 *A, uint32_t L, int n, uint32_t R, double2 *Rout, int transR,
+                                             double snap) {
     const uint32_t m = L * R;
     const int tid = threadIdx.x, nt = blockDim.x;
     __shared__ double2 tau_s[64];
@@ -245,10 +247,23 @@ __global__ void __launch_bounds__(1024) k_qr(double2 *A, uint32_t L, int n, uint
     const int CP = 64;            // column slots per pass
     const int RP = nt / CP;       // row phases
     const int jc = tid % CP, rp = tid / CP;
+    // zero-snap threshold: sub-columns below snap * |M|_F count as exactly zero
+    double fro = 0.0;
+    for (uint32_t q = tid; q < m * (uint32_t)n; q += nt) fro += cabs2(A[q]);
+    const double thr = snap * sqrt(blk_sum1(fro, red1));
     for (int i = 0; i < n; ++i) {
         double part = 0.0;
         for (uint32_t rho = i + 1 + tid; rho < m; rho += nt) part += cabs2(A[qr_addr(rho, i, n, R)]);
         double xn2 = blk_sum1(part, red1);
+        if (snap > 0.0 && sqrt(xn2) <= thr) {
+            for (uint32_t rho = i + 1 + tid; rho < m; rho += nt) A[qr_addr(rho, i, n, R)] = make_double2(0.0, 0.0);
+            xn2 = 0.0;
+            if (tid == 0) {
+                double2 a = A[qr_addr(i, i, n, R)];
+                if (fabs(a.y) <= thr) A[qr_addr(i, i, n, R)] = make_double2(a.x, 0.0);
+            }
+            __syncthreads();
+        }
         double2 alpha = A[qr_addr(i, i, n, R)];
         if (tid == 0) {
             if (xn2 == 0.0 && alpha.y == 0.0) {
@@ -781,6 +796,14 @@ __global__ void k_transpose(double2 *dst, const double2 *src, int n) {
 }
 
 // ============================================================ launchers
+// Raise a kernel's dynamic LDS limit when a launch needs more than the default
+// 64 KiB (gfx950 work-groups may use up to 160 KiB).
+static void set_lds_limit(const void *fn, size_t bytes) {
+    if (bytes <= 64 * 1024) return;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) throw std::runtime_error(std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+}
+
 static inline unsigned grid_for(int64_t n, int threads, int cap = 2048) {
     int64_t b = (n + threads - 1) / threads;
     if (b < 1) b = 1;
@@ -835,18 +858,15 @@ void launch_contract(const double2 *A, const double2 *B, double2 *out, int64_t L
 }
 
 void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st) {
-    hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, st, A, (uint32_t)L, n, (uint32_t)R, Rout, transR);
+    if (n > 64 || L * R < n) throw std::runtime_error("QR shape out of range");
+    hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, st, A, (uint32_t)L, n, (uint32_t)R, Rout, transR, QR_SNAP);
 }
 
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     const size_t lds = small_solve_lds_bytes(a.g.N, a.mmax);
     if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds > 160 * 1024)
         throw std::runtime_error("small solve out of range");
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipFuncSetAttribute((const void *)k_small_solve, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+    set_lds_limit((const void *)k_small_solve, lds);
     hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(SMALL_THREADS), lds, st, a);
 }
 
@@ -873,11 +893,7 @@ void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStrea
 void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double tau, double tol, int hermitian,
                           double2 *x, SolveStat *stat, hipStream_t st) {
     const size_t lds = sizeof(double2) * (size_t)(4 * m * m + m);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipFuncSetAttribute((const void *)k_kry_expm, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+    set_lds_limit((const void *)k_kry_expm, lds);
     hipLaunchKernelGGL(k_kry_expm, dim3(1), dim3(1024), lds, st, k, m, mmax, tau, tol, hermitian, stat);
     hipLaunchKernelGGL(k_kry_combine, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, m,
                        x);

