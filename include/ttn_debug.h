@@ -30,6 +30,16 @@ ttn_status ttn_debug_dense_tree_operator(int32_t n_nodes, const int32_t *parent,
 ttn_status ttn_debug_clamp_bonds(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
                                  const int32_t *bond_dim, int32_t *effective);
 
+/* Householder QR of a dense complex matrix on the GPU with the library's own
+ * kernels (LAPACK convention with the zero-snap of the sweep's gauge shifts).
+ * m (x) in row-major (rows, cols), rows >= cols, cols <= 64; q_out receives
+ * (rows, cols) and r_out (cols, cols), all complex interleaved host buffers.
+ * variant 0: one work-group; 1: many work-groups (one launch per column).
+ * Uses device 0 and the null stream; allocates and frees its own device memory.
+ * Errors: TTN_E_INVALID (shape), TTN_E_DEVICE. */
+ttn_status ttn_debug_qr(int64_t rows, int32_t cols, const double *m, int32_t variant, double *q_out,
+                        double *r_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ OBS_EXPECT, OBS_NORM, OBS_ENERGY, OBS_OVERLAP_T0, OBS_BILINEAR = 0, 1, 2, 3, 4
 EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product_state", "ttn_step",
             "ttn_observe", "ttn_apply_root_heff", "ttn_get_info", "ttn_state_size", "ttn_get_state",
             "ttn_set_state", "ttn_last_error", "ttn_destroy", "ttn_debug_dense_tree_operator",
-            "ttn_debug_clamp_bonds"]
+            "ttn_debug_clamp_bonds", "ttn_debug_qr"]
 
 
 class Options(C.Structure):
@@ -64,6 +64,7 @@ def _load():
         "ttn_debug_dense_tree_operator": (C.c_int32, [C.c_int32, i32p, i32p, C.c_int32, i32p, i64p, dp,
                                                       C.c_int32, dp, i64p, i32p, C.c_int64, dp, i64p]),
         "ttn_debug_clamp_bonds": (C.c_int32, [C.c_int32, i32p, i32p, i32p, i32p]),
+        "ttn_debug_qr": (C.c_int32, [C.c_int64, C.c_int32, dp, C.c_int32, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -108,6 +109,17 @@ def dense_tree_operator(problem, max_dim: int = 4096):
         _ptr(off, C.c_int64), _ptr(data, C.c_double), len(problem.term_ops), _ptr(coeff, C.c_double),
         _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32), max_dim, _ptr(out, C.c_double), _ptr(nent, C.c_int64)))
     return out.view(np.complex128).reshape(dim, dim), int(nent[0])
+
+
+def gpu_qr(M: np.ndarray, variant: int):
+    """Q, R of the library's Householder QR kernels (variant 0: one work-group, 1: many)."""
+    A = np.ascontiguousarray(M, dtype=np.complex128)
+    rows, cols = A.shape
+    Q = np.zeros_like(A)
+    R = np.zeros((cols, cols), dtype=np.complex128)
+    _check(lib.ttn_debug_qr(rows, cols, _ptr(A.view(np.float64), C.c_double), variant,
+                            _ptr(Q.view(np.float64), C.c_double), _ptr(R.view(np.float64), C.c_double)))
+    return Q, R
 
 
 def tree_operator_entries(problem) -> int:

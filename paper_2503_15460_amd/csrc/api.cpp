@@ -235,4 +235,12 @@ ttn_status ttn_debug_dense_tree_operator(int32_t n_nodes, const int32_t *parent,
     });
 }
 
+ttn_status ttn_debug_qr(int64_t rows, int32_t cols, const double *m, int32_t variant, double *q_out,
+                        double *r_out) {
+    return guard(nullptr, [&] {
+        if (!m || !q_out || !r_out) throw ttn::Error(TTN_E_INVALID, "null buffer");
+        ttn::debug_qr(rows, cols, m, variant, q_out, r_out);
+    });
+}
+
 }  // extern "C"

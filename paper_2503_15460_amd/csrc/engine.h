@@ -59,6 +59,7 @@ private:
     double2 *Rbuf = nullptr, *Cbuf = nullptr, *smallV = nullptr, *obs = nullptr, *snapshot = nullptr;
     int64_t obs_elems = 0;
     BigKrylov bk{};
+    QRWork qrw{};
     int64_t bigN = 0;
     SolveStat *d_stats = nullptr;
     std::vector<SolveStat> h_stats;
@@ -90,5 +91,7 @@ private:
     void apply_prog(const Prog &p, const double2 *in, double2 *out);
     void sync_check(const char *where);
 };
+
+void debug_qr(int64_t rows, int cols, const double *m, int variant, double *q_out, double *r_out);
 
 }  // namespace ttn

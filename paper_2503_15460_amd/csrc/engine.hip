@@ -392,6 +392,19 @@ void Engine::set_sop(const SopInput &s) {
     } else {
         snapshot = nullptr;
     }
+    // many-work-group QR scratch
+    qrw.tau = (double2 *)dalloc(sizeof(double2) * 64);
+    qrw.scl = (double2 *)dalloc(sizeof(double2) * 64);
+    qrw.diag = (double2 *)dalloc(sizeof(double2) * 64);
+    qrw.snapped = (int *)dalloc(sizeof(int) * 64);
+    qrw.w = (double2 *)dalloc(sizeof(double2) * 64 * 64);
+    qrw.rowi = (double2 *)dalloc(sizeof(double2) * 64);
+    qrw.part = (double *)dalloc(sizeof(double) * QRM_BLOCKS_MAX * (2 + 2 * 64));
+    qrw.S = (double2 *)dalloc(sizeof(double2) * QRM_BLOCKS_MAX * 64 * 63 / 2);
+    qrw.K = (double2 *)dalloc(sizeof(double2) * 64 * 64);
+    qrw.thr = (double *)dalloc(sizeof(double) * 4);
+    qrw.counter = (unsigned *)dalloc(sizeof(unsigned) * 4);
+    HIPCHK(hipMemset(qrw.counter, 0, sizeof(unsigned) * 4));
     const int n_solves = (2 * n - 1) + 2 * (n - 1);
     d_stats = (SolveStat *)dalloc(sizeof(SolveStat) * n_solves);
     h_stats.assign(n_solves, SolveStat{});
@@ -527,7 +540,8 @@ void Engine::build_mf(int z, int k) {
 
 void Engine::qr_slot(int z, int s, double2 *Rout, int transR) {
     const Geom g = heffP[z].g;
-    launch_qr(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, st);
+    if (g.N >= QR_MULTI_MIN) launch_qr_multi(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st);
+    else launch_qr(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, st);
 }
 
 void Engine::absorb(int z, int s, const double2 *M, int transM) {
@@ -851,6 +865,49 @@ void Engine::apply_root_heff(const double *x, double *y) {
     apply_prog(heffP[t.root], obs, obs + N);
     HIPCHK(hipMemcpyAsync(y, obs + N, sizeof(double2) * N, hipMemcpyDeviceToHost, st));
     sync_check("apply_root_heff");
+}
+
+void debug_qr(int64_t rows, int cols, const double *m, int variant, double *q_out, double *r_out) {
+    if (rows < cols || cols < 1 || cols > 64) throw Error(TTN_E_INVALID, "QR shape out of range");
+    const size_t nm = (size_t)rows * cols;
+    std::vector<void *> mem;
+    auto alloc = [&](size_t bytes) {
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, bytes < 16 ? 16 : bytes));
+        mem.push_back(p);
+        return p;
+    };
+    try {
+        double2 *A = (double2 *)alloc(sizeof(double2) * nm);
+        double2 *Rd = (double2 *)alloc(sizeof(double2) * cols * cols);
+        HIPCHK(hipMemcpy(A, m, sizeof(double2) * nm, hipMemcpyHostToDevice));
+        if (variant == 0) {
+            launch_qr(A, rows, cols, 1, Rd, 0, nullptr);
+        } else {
+            QRWork q{};
+            q.tau = (double2 *)alloc(sizeof(double2) * 64);
+            q.scl = (double2 *)alloc(sizeof(double2) * 64);
+            q.diag = (double2 *)alloc(sizeof(double2) * 64);
+            q.snapped = (int *)alloc(sizeof(int) * 64);
+            q.w = (double2 *)alloc(sizeof(double2) * 64 * 64);
+            q.rowi = (double2 *)alloc(sizeof(double2) * 64);
+            q.part = (double *)alloc(sizeof(double) * QRM_BLOCKS_MAX * (2 + 2 * 64));
+            q.S = (double2 *)alloc(sizeof(double2) * QRM_BLOCKS_MAX * 64 * 63 / 2);
+            q.K = (double2 *)alloc(sizeof(double2) * 64 * 64);
+            q.thr = (double *)alloc(sizeof(double) * 4);
+            q.counter = (unsigned *)alloc(sizeof(unsigned) * 4);
+            HIPCHK(hipMemset(q.counter, 0, sizeof(unsigned) * 4));
+            launch_qr_multi(A, rows, cols, 1, Rd, 0, q, nullptr);
+        }
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(q_out, A, sizeof(double2) * nm, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(r_out, Rd, sizeof(double2) * cols * cols, hipMemcpyDeviceToHost));
+    } catch (...) {
+        for (void *p : mem) (void)hipFree(p);
+        throw;
+    }
+    for (void *p : mem) (void)hipFree(p);
 }
 
 void Engine::info(int32_t *bonds, int64_t *ctr) {

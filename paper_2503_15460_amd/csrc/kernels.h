@@ -90,6 +90,21 @@ struct BigKrylov {
     unsigned *counter; // last-block reduction counter (starts at 0)
 };
 
+// Scratch of the many-work-group Householder QR.
+constexpr int QRM_BLOCKS_MAX = 256;
+constexpr int64_t QR_MULTI_MIN = 16384;  // matrices with at least this many elements use the many-work-group QR
+struct QRWork {
+    double2 *tau, *scl, *diag;  // [64] per reflector
+    int *snapped;               // [64]
+    double2 *w;                 // [64*64] w[i*64+j] = v_i^H a_j
+    double2 *rowi;              // [64] row i of the current column step
+    double *part;               // [QRM_BLOCKS_MAX * (2 + 2*64)]
+    double2 *S;                 // [QRM_BLOCKS_MAX * 64*63/2] partial reflector Gram
+    double2 *K;                 // [64*64] T V_top^H
+    double *thr;                // [1] snap threshold
+    unsigned *counter;          // last-block ticket (starts at 0)
+};
+
 // ---- launchers (all asynchronous on `st`) ----
 void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st);
 void launch_prog_sum(const ProgView &p, const double2 *in, double2 *out_single, hipStream_t st);
@@ -102,6 +117,8 @@ void launch_mode_product(const double2 *X, double2 *Y, const double2 *M, int64_t
 void launch_contract(const double2 *A, const double2 *B, double2 *out, int64_t L, int nA, int nB,
                      int64_t R, double2 *part, hipStream_t st);
 void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st);
+void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
+                     hipStream_t st);
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st);
 void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st);
 void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st);

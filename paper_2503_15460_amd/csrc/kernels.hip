@@ -79,6 +79,37 @@ __device__ double blk_sum1(double v, double *red) {
     return s;
 }
 
+// Last-block reduction: every block stores its partials, the block that
+// finishes last (atomic ticket) sums them in a fixed order.
+__device__ bool last_block_ticket(unsigned *counter) {
+    __shared__ int is_last;
+    __threadfence();  // every thread releases its partial-sum stores device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last != 0;
+}
+
+// out[q] = sum_b part[b * stride + q] for q < K (doubles), by the whole block in
+// groups of 8 lanes per value (call from the last block only).
+__device__ void blk_reduce_partials(const double *part, int nb, int stride, int K, double *out) {
+    const int sub = threadIdx.x & 7;
+    for (int q0 = 0; q0 < K; q0 += (int)blockDim.x / 8) {
+        const int q = q0 + (int)threadIdx.x / 8;
+        double acc = 0.0;
+        if (q < K)
+            for (int b = sub; b < nb; b += 8) acc += part[(size_t)b * stride + q];
+        acc += __shfl_xor(acc, 4, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        acc += __shfl_xor(acc, 1, 64);
+        if (q < K && sub == 0) out[q] = acc;
+    }
+}
+
 // ============================================================ mode products
 // Y[l,i,r] = sum_j M[i,j] X[l,j,r] for one (L, n, R) geometry.
 __global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const double2 *__restrict__ in,
@@ -367,6 +398,252 @@ __global__ void __launch_bounds__(1024) k_qr(double2 *A, uint32_t L, int n, uint
     }
 }
 
+// ============================================================ QR (many work-groups)
+// The same Householder reflectors (LAPACK convention and zero-snap) computed by
+// one launch per column: launch i applies reflector i-1 to the work-group's own
+// rows and, in the same pass, reduces the norm of column i below the diagonal
+// and its unscaled inner products g_j = x_i^H a_j with the trailing columns
+// (v_i^H a_j = a_ij + conj(1/(alpha-beta)) g_j needs no second pass).  The last
+// work-group to finish forms tau_i, beta_i and w_ij.  Q = I - V T V^H (compact
+// WY form, T from the reflector Gram matrix) is built by two final launches.
+constexpr int QRM_MAXN = 64;
+constexpr int QRM_THREADS = 256;
+
+__device__ __forceinline__ double2 qr_v(const double2 *A, uint32_t rho, int k, int n, uint32_t R) {
+    // reflector k at row rho: 0 above the diagonal, 1 on it, stored below it
+    if (rho < (uint32_t)k) return make_double2(0.0, 0.0);
+    if (rho == (uint32_t)k) return make_double2(1.0, 0.0);
+    return A[qr_addr(rho, k, n, R)];
+}
+
+// apply reflector k (already decided) to the rows [r0, r1): scale its column,
+// set the diagonal, update trailing columns j > k
+__device__ void qrm_apply(double2 *A, uint32_t r0, uint32_t r1, int k, int n, uint32_t R, const QRWork &q) {
+    const double2 tau = q.tau[k], scl = q.scl[k];
+    const int snapped = q.snapped[k];
+    const bool has = tau.x != 0.0 || tau.y != 0.0;
+    const uint32_t lo = max(r0, (uint32_t)k + 1);
+    for (uint32_t rho = lo + threadIdx.x; rho < r1; rho += blockDim.x) {
+        size_t a = qr_addr(rho, k, n, R);
+        if (snapped) A[a] = make_double2(0.0, 0.0);
+        else if (has) A[a] = cmul(A[a], scl);
+    }
+    if (threadIdx.x == 0 && (uint32_t)k >= r0 && (uint32_t)k < r1) A[qr_addr(k, k, n, R)] = q.diag[k];
+    __syncthreads();
+    if (!has) return;
+    const double2 ct = make_double2(tau.x, -tau.y);
+    const int nt = n - k - 1;
+    if (nt <= 0) return;
+    const uint32_t rs = max(r0, (uint32_t)k);
+    const uint32_t rows = r1 > rs ? r1 - rs : 0;
+    for (uint32_t e = threadIdx.x; e < rows * (uint32_t)nt; e += blockDim.x) {
+        const uint32_t rho = rs + e / nt;
+        const int j = k + 1 + (int)(e % nt);
+        const double2 v = qr_v(A, rho, k, n, R);
+        const size_t a = qr_addr(rho, j, n, R);
+        A[a] = csub(A[a], cmul(v, cmul(ct, q.w[k * QRM_MAXN + j])));
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(QRM_THREADS) k_qrm_step(double2 *A, uint32_t L, int n, uint32_t R, int i,
+                                                          uint32_t rows_per, QRWork q, double snap) {
+    const uint32_t m = L * R;
+    const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
+    const int tid = threadIdx.x;
+    __shared__ double2 red2[4 * 64];
+    __shared__ double red1[16];
+    if (i > 0) qrm_apply(A, r0, r1, i - 1, n, R, q);
+    // partial sums of column i
+    const int K = 2 + 2 * QRM_MAXN;  // doubles per block: xn2, fro, g_j (complex)
+    double *part = q.part + (size_t)blockIdx.x * K;
+    double xp = 0.0, fp = 0.0;
+    const uint32_t lo = max(r0, (uint32_t)i + 1);
+    for (uint32_t rho = lo + tid; rho < r1; rho += blockDim.x) xp += cabs2(A[qr_addr(rho, i, n, R)]);
+    if (i == 0)
+        for (uint32_t e = tid; e < (r1 - r0) * (uint32_t)n; e += blockDim.x)
+            fp += cabs2(A[qr_addr(r0 + e / n, e % n, n, R)]);
+    const double xs = blk_sum1(xp, red1);
+    const double fs = blk_sum1(fp, red1);
+    const int jc = tid % 64, rp = tid / 64;  // 64 column slots x 4 row phases
+    const int j = i + 1 + jc;
+    double2 acc = make_double2(0.0, 0.0);
+    if (j < n)
+        for (uint32_t rho = lo + rp; rho < r1; rho += 4) cfmac(acc, A[qr_addr(rho, i, n, R)], A[qr_addr(rho, j, n, R)]);
+    red2[rp * 64 + jc] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        part[0] = xs;
+        part[1] = fs;
+    }
+    if (rp == 0 && j < n) {
+        double2 g = cadd(cadd(red2[jc], red2[64 + jc]), cadd(red2[128 + jc], red2[192 + jc]));
+        part[2 + 2 * j] = g.x;
+        part[3 + 2 * j] = g.y;
+    }
+    if ((uint32_t)i >= r0 && (uint32_t)i < r1)
+        for (int c = i + tid; c < n; c += blockDim.x) q.rowi[c] = A[qr_addr(i, c, n, R)];
+    if (last_block_ticket(q.counter)) {
+        __shared__ double sums[2 + 2 * QRM_MAXN];
+        __shared__ double2 sc[2];
+        blk_reduce_partials(q.part, gridDim.x, K, 2 + 2 * n, sums);
+        __syncthreads();
+        if (tid == 0) {
+            double xn2 = sums[0];
+            if (i == 0) q.thr[0] = snap * sqrt(sums[1]);
+            const double thr = q.thr[0];
+            double2 alpha = q.rowi[i];
+            int snapped = 0;
+            if (snap > 0.0 && sqrt(xn2) <= thr) {
+                snapped = 1;
+                xn2 = 0.0;
+                if (fabs(alpha.y) <= thr) alpha.y = 0.0;
+            }
+            double2 tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0), diag = alpha;
+            if (!(xn2 == 0.0 && alpha.y == 0.0)) {
+                const double beta = -copysign(sqrt(cabs2(alpha) + xn2), alpha.x);
+                tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                scl = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+                diag = make_double2(beta, 0.0);
+            }
+            q.tau[i] = tau;
+            q.scl[i] = scl;
+            q.diag[i] = diag;
+            q.snapped[i] = snapped;
+            sc[0] = scl;
+            sc[1] = make_double2((double)snapped, 0.0);
+        }
+        __syncthreads();
+        const double2 cs = make_double2(sc[0].x, -sc[0].y);
+        const bool snapped = sc[1].x != 0.0;
+        for (int c = i + 1 + tid; c < n; c += blockDim.x) {
+            const double2 g = snapped ? make_double2(0.0, 0.0) : make_double2(sums[2 + 2 * c], sums[3 + 2 * c]);
+            q.w[i * QRM_MAXN + c] = cadd(q.rowi[c], cmul(cs, g));
+        }
+        if (tid == 0) *q.counter = 0;
+    }
+}
+
+// applies the last reflector, writes R, reduces the reflector Gram matrix and
+// (last block) builds K = T V_top^H
+__global__ void __launch_bounds__(QRM_THREADS) k_qrm_finish(double2 *A, uint32_t L, int n, uint32_t R,
+                                                            uint32_t rows_per, QRWork q, double2 *Rout, int transR) {
+    const uint32_t m = L * R;
+    const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
+    const int tid = threadIdx.x;
+    qrm_apply(A, r0, r1, n - 1, n, R, q);
+    if (blockIdx.x == 0) {
+        for (int e = tid; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            const double2 v = j >= i ? A[qr_addr(i, j, n, R)] : make_double2(0.0, 0.0);
+            if (transR) Rout[j * n + i] = v;
+            else Rout[i * n + j] = v;
+        }
+    }
+    // partial Gram S[k][l] = sum_rho conj(V[rho,k]) V[rho,l], k < l, over own rows
+    const int npair = n * (n - 1) / 2;
+    double2 *Sp = q.S + (size_t)blockIdx.x * npair;
+    for (int pidx = tid; pidx < npair; pidx += blockDim.x) {
+        // decode pair index -> (k, l) with k < l
+        int k = 0, rem = pidx;
+        while (rem >= n - 1 - k) {
+            rem -= n - 1 - k;
+            ++k;
+        }
+        const int l = k + 1 + rem;
+        double2 acc = make_double2(0.0, 0.0);
+        for (uint32_t rho = max(r0, (uint32_t)l); rho < r1; ++rho)
+            cfmac(acc, qr_v(A, rho, k, n, R), qr_v(A, rho, l, n, R));
+        Sp[pidx] = acc;
+    }
+    if (last_block_ticket(q.counter)) {
+        extern __shared__ double2 sq[];
+        double2 *T = sq;              // n*n
+        double2 *S = sq + n * n;      // n*n
+        for (int e = tid; e < n * n; e += blockDim.x) {
+            T[e] = make_double2(0.0, 0.0);
+            S[e] = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        {
+            const int sub = tid & 7;
+            const double *Sd = reinterpret_cast<const double *>(q.S);
+            for (int p0 = 0; p0 < 2 * npair; p0 += (int)blockDim.x / 8) {
+                const int pq = p0 + tid / 8;  // double index: pair pq/2, component pq%2
+                double acc = 0.0;
+                if (pq < 2 * npair)
+                    for (unsigned b = sub; b < gridDim.x; b += 8) acc += Sd[(size_t)b * 2 * npair + pq];
+                acc += __shfl_xor(acc, 4, 64);
+                acc += __shfl_xor(acc, 2, 64);
+                acc += __shfl_xor(acc, 1, 64);
+                if (pq < 2 * npair && sub == 0) {
+                    int k = 0, rem = pq / 2;
+                    while (rem >= n - 1 - k) {
+                        rem -= n - 1 - k;
+                        ++k;
+                    }
+                    const int l = k + 1 + rem;
+                    double *dst = reinterpret_cast<double *>(&S[k * n + l]);
+                    dst[pq % 2] = acc;
+                }
+            }
+        }
+        __syncthreads();
+        // T (upper triangular): T_ii = tau_i, T[0:i, i] = -tau_i T[0:i,0:i] S[0:i, i]
+        for (int i = 0; i < n; ++i) {
+            const double2 ti = q.tau[i];
+            double2 val = make_double2(0.0, 0.0);
+            if (tid < i) {
+                for (int l = tid; l < i; ++l) cfma(val, T[tid * n + l], S[l * n + i]);
+                val = cmul(make_double2(-ti.x, -ti.y), val);
+            }
+            __syncthreads();
+            if (tid < i) T[tid * n + i] = val;
+            if (tid == 0) T[i * n + i] = ti;
+            __syncthreads();
+        }
+        // K[i][c] = sum_l T[i][l] conj(Vtop[c][l])
+        for (int e = tid; e < n * n; e += blockDim.x) {
+            const int i = e / n, c = e % n;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int l = i; l < n; ++l) {
+                const double2 v = qr_v(A, (uint32_t)c, l, n, R);
+                acc = cadd(acc, cmul(T[i * n + l], make_double2(v.x, -v.y)));
+            }
+            q.K[e] = acc;
+        }
+        if (tid == 0) *q.counter = 0;
+    }
+}
+
+// Q[rho, c] = delta_{rho c} - sum_i V[rho, i] K[i, c], in place, tiles of 16 rows
+__global__ void __launch_bounds__(QRM_THREADS) k_qrm_formq(double2 *A, uint32_t L, int n, uint32_t R,
+                                                           uint32_t rows_per, QRWork q) {
+    const uint32_t m = L * R;
+    const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
+    extern __shared__ double2 sf[];
+    double2 *Ks = sf;           // n*n
+    double2 *Vt = sf + n * n;   // 16*n
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) Ks[e] = q.K[e];
+    for (uint32_t t0 = r0; t0 < r1; t0 += 16) {
+        const uint32_t tr = min(16u, r1 - t0);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < tr * (uint32_t)n; e += blockDim.x) {
+            const uint32_t rho = t0 + e / n;
+            const int k = (int)(e % n);
+            Vt[e] = qr_v(A, rho, k, n, R);
+        }
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < tr * (uint32_t)n; e += blockDim.x) {
+            const uint32_t rr = e / n, rho = t0 + rr;
+            const int c = (int)(e % n);
+            double2 acc = make_double2(rho == (uint32_t)c ? 1.0 : 0.0, 0.0);
+            for (int i = 0; i < n; ++i) acc = csub(acc, cmul(Vt[rr * n + i], Ks[i * n + c]));
+            A[qr_addr(rho, c, n, R)] = acc;
+        }
+    }
+}
+
 // ============================================================ small matrix exponential
 // y = exp(X) e_0 for X = -i tau H (H m x m row-major in LDS, m <= SMALL_MMAX), by
 // Taylor series of degree 14 after scaling to ||X||_1 <= 1/2, then squaring.
@@ -612,21 +889,6 @@ size_t small_solve_lds_bytes(int64_t N, int mmax) {
 }
 
 // ============================================================ multi-kernel Krylov
-// Last-block reduction: every block stores its partials, the block that
-// finishes last (atomic ticket) sums them in a fixed order.
-__device__ bool last_block_ticket(unsigned *counter) {
-    __shared__ int is_last;
-    __threadfence();  // every thread releases its partial-sum stores device-wide
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last != 0;
-}
-
 __global__ void __launch_bounds__(VEC_THREADS) k_kry_norm0(const double2 *__restrict__ x, uint32_t N, BigKrylov k) {
     __shared__ double red1[16];
     double part = 0.0;
@@ -694,19 +956,19 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_orth(BigKrylov k, uint32_t 
         if (threadIdx.x == 0) part[2 * (size_t)blockIdx.x] = s;
     }
     if (last_block_ticket(k.counter)) {
+        __shared__ double sums[2 * 64];
+        const int nd = pass < 2 ? 2 * nv : 1;
+        blk_reduce_partials(part, gridDim.x, pass < 2 ? 2 * K : 2, nd, sums);
+        __syncthreads();
         if (pass < 2) {
             for (int q = threadIdx.x; q < nv; q += blockDim.x) {
-                double2 s = make_double2(0.0, 0.0);
-                for (unsigned b = 0; b < gridDim.x; ++b)
-                    s = cadd(s, make_double2(part[2 * ((size_t)b * K + q)], part[2 * ((size_t)b * K + q) + 1]));
+                const double2 s = make_double2(sums[2 * q], sums[2 * q + 1]);
                 k.h[q] = s;
                 double2 *hcol = k.Hm + (size_t)j * (mmax + 1);
                 hcol[q] = pass == 0 ? s : cadd(hcol[q], s);
             }
         } else if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += part[2 * (size_t)b];
-            const double beta = sqrt(s);
+            const double beta = sqrt(sums[0]);
             k.scal[1] = beta;
             k.Hm[(size_t)j * (mmax + 1) + j + 1] = make_double2(beta, 0.0);
             if (beta <= 1e-14 * k.scal[0]) *k.meff = j + 1;
@@ -862,6 +1124,26 @@ void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int trans
     hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, st, A, (uint32_t)L, n, (uint32_t)R, Rout, transR, QR_SNAP);
 }
 
+void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
+                     hipStream_t st) {
+    const int64_t m = L * R;
+    if (n > QRM_MAXN || m < n) throw std::runtime_error("QR shape out of range");
+    int64_t rows_per = (m + QRM_BLOCKS_MAX - 1) / QRM_BLOCKS_MAX;
+    if (rows_per < 64) rows_per = 64;
+    const unsigned nb = (unsigned)((m + rows_per - 1) / rows_per);
+    for (int i = 0; i < n; ++i)
+        hipLaunchKernelGGL(k_qrm_step, dim3(nb), dim3(QRM_THREADS), 0, st, A, (uint32_t)L, n, (uint32_t)R, i,
+                           (uint32_t)rows_per, q, QR_SNAP);
+    const size_t lds_fin = sizeof(double2) * 2 * n * n;
+    set_lds_limit((const void *)k_qrm_finish, lds_fin);
+    hipLaunchKernelGGL(k_qrm_finish, dim3(nb), dim3(QRM_THREADS), lds_fin, st, A, (uint32_t)L, n, (uint32_t)R,
+                       (uint32_t)rows_per, q, Rout, transR);
+    const size_t lds_q = sizeof(double2) * (size_t)(n * n + 16 * n);
+    set_lds_limit((const void *)k_qrm_formq, lds_q);
+    hipLaunchKernelGGL(k_qrm_formq, dim3(nb), dim3(QRM_THREADS), lds_q, st, A, (uint32_t)L, n, (uint32_t)R,
+                       (uint32_t)rows_per, q);
+}
+
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     const size_t lds = small_solve_lds_bytes(a.g.N, a.mmax);
     if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds > 160 * 1024)
@@ -878,14 +1160,20 @@ void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_transpose, dim3(grid_for((int64_t)n * n, 256)), dim3(256), 0, st, dst, src, n);
 }
 
+static unsigned vec_blocks(int64_t N) {
+    int64_t b = (N + 1023) / 1024;
+    return (unsigned)(b < 1 ? 1 : (b > VEC_BLOCKS ? VEC_BLOCKS : b));
+}
+
 void launch_krylov_start(const double2 *x, int64_t N, const BigKrylov &k, hipStream_t st) {
-    hipLaunchKernelGGL(k_kry_norm0, dim3(VEC_BLOCKS), dim3(VEC_THREADS), 0, st, x, (uint32_t)N, k);
+    hipLaunchKernelGGL(k_kry_norm0, dim3(vec_blocks(N)), dim3(VEC_THREADS), 0, st, x, (uint32_t)N, k);
     hipLaunchKernelGGL(k_kry_scale0, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, x, (uint32_t)N, k);
 }
 
 void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st) {
+    const unsigned nb = vec_blocks(N);
     for (int pass = 0; pass < 3; ++pass)
-        hipLaunchKernelGGL(k_kry_orth, dim3(VEC_BLOCKS), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, pass);
+        hipLaunchKernelGGL(k_kry_orth, dim3(nb), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, pass);
     hipLaunchKernelGGL(k_kry_normalize, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, k,
                        (uint32_t)N, j);
 }

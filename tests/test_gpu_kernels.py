@@ -1,0 +1,63 @@
+"""GPU kernel checks against the oracle's definitions (through the C boundary)."""
+import numpy as np
+import pytest
+
+from oracle import Oracle, householder_qr_lapack
+from oracle.ttn_oracle import SNAP
+from workloads import random_isometric_state, sbm_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_15460_amd as mod
+    return mod
+
+
+def _cases():
+    rng = np.random.default_rng(12)
+    out = []
+    for (m, n) in [(7, 4), (40, 16), (4096, 20), (8192, 8), (5120, 16), (300, 64), (20000, 33)]:
+        M = rng.normal(size=(m, n)) + 1j * rng.normal(size=(m, n))
+        out.append(("random", M))
+    # product-state-like rank deficient: a single nonzero column, exact zeros elsewhere
+    M = np.zeros((4096, 16), dtype=np.complex128)
+    M[:, 0] = rng.normal(size=4096)
+    M[5, 3] = 0.25 + 0.5j
+    out.append(("rankdef", M))
+    # rank deficient with rounding-size noise in the empty columns
+    N = M + 1e-17 * (rng.normal(size=M.shape) + 1j * rng.normal(size=M.shape))
+    out.append(("noisy_rankdef", N))
+    return out
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_qr_matches_oracle_householder(T, variant):
+    for name, M in _cases():
+        if variant == 0 and M.size > 200_000:
+            continue
+        Q, R = T.gpu_qr(M, variant)
+        Qo, Ro = householder_qr_lapack(M, snap=SNAP)
+        scale = max(1.0, np.abs(M).max())
+        assert np.abs(Q - Qo).max() < 1e-12, (name, M.shape, np.abs(Q - Qo).max())
+        assert np.abs(R - Ro).max() < 1e-12 * scale, (name, M.shape)
+        assert np.abs(Q.conj().T @ Q - np.eye(M.shape[1])).max() < 1e-12
+
+
+def test_large_node_parity(T):
+    """Spin-boson with bond 32: nodes of 32^3 elements use the many-work-group QR."""
+    p = sbm_problem(n_modes=8, d=8, bond=32, alpha=0.3, dt=0.05)
+    o0 = Oracle(p)
+    assert max(int(np.prod(o0.shape(z))) for z in range(p.n_nodes)) >= 16384
+    st = random_isometric_state(p.parent, p.local_dim, o0.bond, seed=6)
+    g = T.TTN.from_problem(p)
+    g.set_state(st)
+    o0.set_state(st)
+    for _ in range(3):
+        g.step(p.dt)
+        o0.step(p.dt)
+        assert abs(g.expect(p.observables["sz"]) - o0.expect(p.observables["sz"])) < 1e-10
