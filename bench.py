@@ -1,0 +1,134 @@
+#!/usr/bin/env python3
+"""Throughput of the one-site TDVP sweep on one MI355X.
+
+Workload: the synthetic 2-state / 24-mode vibronic-coupling model (seed 2;
+3-layer tree R(E, M1, M2), M(L, L, L), L(4 modes), bonds 8/16/20, mode bases
+8-32 levels, ~150 SOP terms), complex128, dt = 0.5 fs, from the product state
+|s=1>|0...0>.  One step = one symmetric projector-splitting sweep
+(ttn_step(dt)); the metric is sweeps per second with the state resident on
+the GPU, plus the H_eff flop rate.
+
+Prints ONE JSON line.  A separate short pass with the library's launch
+profiler (HIP events around every kernel launch) gives the dominant kernel's
+average launch duration and its roofline numbers; the oracle (CPU) is timed on
+a one-step sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix = vector)
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+
+
+def roofline(stats, step_ms):
+    """Roofline numbers of the kernel with the largest total time."""
+    top = max(stats, key=lambda r: r["total_ms"])
+    avg_s = top["total_ms"] / 1e3 / top["calls"]
+    flops = top["flops"] / top["calls"]
+    byts = top["bytes"] / top["calls"]
+    intensity = flops / byts if byts > 0 else float("inf")
+    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if flops > 0 and intensity >= ridge:
+        ach = flops / avg_s / 1e12
+        r = dict(bound="mfma", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s", frac=ach / PEAK_FP64_TFLOPS)
+    else:
+        ach = byts / avg_s / 1e9
+        r = dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s", frac=ach / PEAK_HBM_GBS)
+    r.update(kernel=top["name"], avg_launch_us=avg_s * 1e6, launches_per_step=None, traffic=None)
+    return r
+
+
+def cpu_baseline(problem, steps: int):
+    """The oracle (numpy complex128) on the host cores: seconds for `steps` sweeps."""
+    from oracle import Oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = Oracle(problem)
+    o.set_product_state(problem.init_vecs)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.step(problem.dt)
+    dt = time.perf_counter() - t0
+    return dict(value=steps / dt, unit="sweeps/s", cores=threads, kind="oracle",
+                sample=f"{steps} sweep(s) of the same 24-mode vibronic workload from the product state")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs the sweep on one GPU only (the sweep of one tree is sequential; "
+              "see the design notes for how instances would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2503_15460_amd as T
+    from workloads import vibronic_problem
+
+    torch.cuda.init()
+    torch.zeros(1, device="cuda:0")
+    p = vibronic_problem()
+    g = T.TTN.from_problem(p)
+    g.set_product_state(p.init_vecs)
+    g.step(p.dt, args.warmup)
+    torch.cuda.synchronize()
+    c0 = g.counters()
+    t0 = time.perf_counter()
+    g.step(p.dt, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    c1 = g.counters()
+    sweeps_per_s = args.steps / elapsed
+    heff_tflops = (c1["heff_flops"] - c0["heff_flops"]) / elapsed / 1e12
+    pops = [g.expect(p.observables[k]).real for k in ("P0", "P1")]
+
+    # profiled pass (separate from the timed region)
+    T.profile_begin()
+    g.step(p.dt, args.profile_steps)
+    torch.cuda.synchronize()
+    stats = T.profile_end()
+    roof = roofline(stats, 1e3 * elapsed / args.steps)
+    top = roof["kernel"]
+    roof["launches_per_step"] = next(r["calls"] for r in stats if r["name"] == top) / args.profile_steps
+
+    out = {
+        "metric": "TDVP sweeps/s + H_eff TFLOP/s (% MFMA peak), FP32-mixed vs FP64 at stated err",
+        "value": sweeps_per_s,
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic (seeded 2-state 24-mode vibronic model standing in for pyrazine)",
+        "config": {"workload": "vibronic24: 2 states x 24 modes (d 8-32), ~150 SOP terms, tree R(E,M,M) M(L,L,L) "
+                               "L(4 modes), bonds 8/16/20, dt 0.5 fs, product initial state, FP64",
+                   "precision": "fp64", "heff_tflops": heff_tflops,
+                   "heff_frac_fp64_peak": heff_tflops / PEAK_FP64_TFLOPS,
+                   "populations_after": pops, "redo_steps": c1["redo"] - c0["redo"]},
+        "roofline": roof,
+        "kernels": sorted(({k: (v if k != "name" else v) for k, v in r.items()} for r in stats),
+                          key=lambda r: -r["total_ms"])[:8],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

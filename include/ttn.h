@@ -22,10 +22,9 @@
  *   - All pointer arguments are HOST pointers owned by the caller.  The library
  *     copies what it needs during the call and never keeps a caller pointer.
  *   - Complex numbers are two consecutive doubles (re, im).
- *   - The library owns all device memory of a handle (or sub-allocates the
- *     workspace given with ttn_bind_workspace).  A handle is not thread safe and
- *     runs all its work on one HIP stream (ttn_options.hip_stream, or the null
- *     stream).
+ *   - The library owns all device memory of a handle.  A handle is not thread
+ *     safe and runs all its work on one HIP stream (ttn_options.hip_stream, for
+ *     example a PyTorch stream, or the null stream).
  *   - Time evolution is d/dt psi = -i G psi (G = H/hbar for unitary models).
  *
  * Tensor layout (used by ttn_get_state / ttn_set_state)
@@ -163,6 +162,24 @@ ttn_status ttn_state_size(ttn_t h, size_t *bytes);
  * and makes the state Psi(0).  Errors: TTN_E_DIMS, TTN_E_STATE, TTN_E_DEVICE. */
 ttn_status ttn_get_state(ttn_t h, double *buf, size_t bytes);
 ttn_status ttn_set_state(ttn_t h, const double *buf, size_t bytes);
+
+/* Kernel launch profile.  ttn_profile_begin switches on event timing of every
+ * kernel launch of the library (HIP events recorded on the launch's stream;
+ * adds a little overhead per launch) and clears earlier records.
+ * ttn_profile_end synchronises the device, switches the timing off and writes
+ * one row per kernel name: launches, summed duration, and the algorithmic
+ * flops (8 per complex MAC) and bytes of those launches as modelled by the
+ * library.  n_rows receives the number of rows (at most max_rows written).
+ * The profiler is process wide (all handles).  Errors: TTN_E_DEVICE. */
+typedef struct {
+    char name[48];
+    int64_t calls;
+    double total_ms;
+    double flops;
+    double bytes;
+} ttn_kernel_stat;
+ttn_status ttn_profile_begin(void);
+ttn_status ttn_profile_end(ttn_kernel_stat *rows, int32_t max_rows, int32_t *n_rows);
 
 /* Per-handle message of the last error (NULL handle: last error of this
  * thread).  The string is owned by the library. */

@@ -26,13 +26,18 @@ OBS_EXPECT, OBS_NORM, OBS_ENERGY, OBS_OVERLAP_T0, OBS_BILINEAR = 0, 1, 2, 3, 4
 EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product_state", "ttn_step",
             "ttn_observe", "ttn_apply_root_heff", "ttn_get_info", "ttn_state_size", "ttn_get_state",
             "ttn_set_state", "ttn_last_error", "ttn_destroy", "ttn_debug_dense_tree_operator",
-            "ttn_debug_clamp_bonds", "ttn_debug_qr"]
+            "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end"]
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("krylov_tol", C.c_double), ("krylov_mmax", C.c_int32),
                 ("hermitian", C.c_int32), ("hip_stream", C.c_void_p), ("device", C.c_int32),
                 ("use_graph", C.c_int32), ("seed", C.c_uint64)]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("calls", C.c_int64), ("total_ms", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
 
 
 class TTNError(RuntimeError):
@@ -65,6 +70,8 @@ def _load():
                                                       C.c_int32, dp, i64p, i32p, C.c_int64, dp, i64p]),
         "ttn_debug_clamp_bonds": (C.c_int32, [C.c_int32, i32p, i32p, i32p, i32p]),
         "ttn_debug_qr": (C.c_int32, [C.c_int64, C.c_int32, dp, C.c_int32, dp, dp]),
+        "ttn_profile_begin": (C.c_int32, []),
+        "ttn_profile_end": (C.c_int32, [C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -120,6 +127,20 @@ def gpu_qr(M: np.ndarray, variant: int):
     _check(lib.ttn_debug_qr(rows, cols, _ptr(A.view(np.float64), C.c_double), variant,
                             _ptr(Q.view(np.float64), C.c_double), _ptr(R.view(np.float64), C.c_double)))
     return Q, R
+
+
+def profile_begin():
+    """Start event timing of every kernel launch (process wide)."""
+    _check(lib.ttn_profile_begin())
+
+
+def profile_end() -> List[Dict[str, float]]:
+    """Stop timing; per kernel name: calls, total_ms, flops, bytes."""
+    rows = (KernelStat * 64)()
+    n = C.c_int32()
+    _check(lib.ttn_profile_end(rows, 64, C.byref(n)))
+    return [dict(name=rows[i].name.decode(), calls=int(rows[i].calls), total_ms=rows[i].total_ms,
+                 flops=rows[i].flops, bytes=rows[i].bytes) for i in range(min(n.value, 64))]
 
 
 def tree_operator_entries(problem) -> int:

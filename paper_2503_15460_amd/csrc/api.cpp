@@ -136,6 +136,30 @@ ttn_status ttn_set_state(ttn_t h, const double *buf, size_t bytes) {
     return guard(h, [&] { h->eng->set_state(buf, bytes); });
 }
 
+ttn_status ttn_profile_begin(void) {
+    return guard(nullptr, [&] { ttn::profile_enable(true); });
+}
+
+ttn_status ttn_profile_end(ttn_kernel_stat *rows, int32_t max_rows, int32_t *n_rows) {
+    return guard(nullptr, [&] {
+        auto st = ttn::profile_collect();
+        ttn::profile_enable(false);
+        int32_t k = 0;
+        for (auto &r : st) {
+            if (rows && k < max_rows) {
+                std::memset(rows[k].name, 0, sizeof(rows[k].name));
+                std::strncpy(rows[k].name, r.name.c_str(), sizeof(rows[k].name) - 1);
+                rows[k].calls = r.calls;
+                rows[k].total_ms = r.ms;
+                rows[k].flops = r.flops;
+                rows[k].bytes = r.bytes;
+            }
+            ++k;
+        }
+        if (n_rows) *n_rows = k;
+    });
+}
+
 const char *ttn_last_error(ttn_t h) {
     if (h) return h->err.c_str();
     return g_err.c_str();

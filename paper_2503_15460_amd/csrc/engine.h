@@ -19,6 +19,7 @@ struct Prog {
     std::vector<double2 *> gdst;
     int n_groups = 0, max_nf = 0, contract_slot = -1;
     int64_t flops = 0;  // algorithmic flops of one application (8 per complex MAC)
+    double sflops[MAXF] = {0}, sbytes[MAXF] = {0};  // per stage launch
     DevEntry *d_ent = nullptr;
     int *d_gptr = nullptr, *d_gent = nullptr;
     double2 **d_gdst = nullptr;
@@ -84,6 +85,7 @@ private:
     void forward(int z, double tau);
     void backward(int c, double2 *C, double tau);
     void expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd);
+    bool use_fused(const Prog &p) const;
     void qr_slot(int z, int s, double2 *Rout, int transR);
     void absorb(int z, int s, const double2 *M, int transM);
     void build_spo(int c);

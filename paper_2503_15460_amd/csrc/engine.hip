@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 
 #include "engine.h"
@@ -125,6 +127,10 @@ ProgView Engine::view(const Prog &p) const {
     v.tmp = tmp;
     v.gsum = gsum;
     v.cpart = cpart;
+    for (int f = 0; f < MAXF; ++f) {
+        v.sflops[f] = p.sflops[f];
+        v.sbytes[f] = p.sbytes[f];
+    }
     return v;
 }
 
@@ -140,9 +146,15 @@ static void finish_groups(Prog &p, const std::vector<double2 *> &dst_by_group) {
     for (size_t e = 0; e < p.ents.size(); ++e) p.gent[fill[p.ents[e].group]++] = (int)e;
     p.max_nf = 0;
     p.flops = 0;
+    for (int f = 0; f < MAXF; ++f) p.sflops[f] = p.sbytes[f] = 0.0;
     for (auto &e : p.ents) {
         p.max_nf = std::max(p.max_nf, e.nf);
-        for (int f = 0; f < e.nf; ++f) p.flops += 8 * p.g.N * p.g.dims[e.slot[f]];
+        for (int f = 0; f < e.nf; ++f) {
+            const int n = p.g.dims[e.slot[f]];
+            p.flops += 8 * p.g.N * n;
+            p.sflops[f] += 8.0 * p.g.N * n;
+            p.sbytes[f] += 16.0 * (2.0 * p.g.N + (double)n * n);
+        }
     }
 }
 
@@ -351,13 +363,13 @@ void Engine::set_sop(const SopInput &s) {
     for (int z = 0; z < n; ++z) {
         acc(heffP[z]);
         maxN = std::max<int64_t>(maxN, t.size[z]);
-        if (t.size[z] > SMALL_MAX) bigN = std::max<int64_t>(bigN, t.size[z]);
+        if (!use_fused(heffP[z])) bigN = std::max<int64_t>(bigN, t.size[z]);
         if (z != t.root) {
             acc(spoP[z]);
             acc(bondP[z]);
             int64_t b2 = (int64_t)t.bond[z] * t.bond[z];
             maxb2 = std::max(maxb2, b2);
-            if (b2 > SMALL_MAX) bigN = std::max<int64_t>(bigN, b2);
+            if (!use_fused(bondP[z])) bigN = std::max<int64_t>(bigN, b2);
         }
         for (auto &m : mfP[z]) acc(m);
     }
@@ -550,15 +562,23 @@ void Engine::absorb(int z, int s, const double2 *M, int transM) {
     std::swap(A[z], Aalt[z]);
 }
 
+// The fused one-work-group solver takes two-slot problems and problems with
+// few entries (its generic matvec applies entries one after the other); all
+// other local exponentials use the multi-kernel Krylov path.
+bool Engine::use_fused(const Prog &p) const {
+    return p.g.N <= SMALL_MAX && (p.g.D == 2 || (int64_t)p.ents.size() * p.g.N <= SMALL_SEQ_WORK);
+}
+
 void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd) {
     const int si = solve_idx++;
     if (si >= (int)h_stats.size()) throw Error(TTN_E_STATE, "internal: solve index overflow");
     solve_node[si] = node;
     solve_fwd[si] = fwd ? 1 : 0;
-    solve_small[si] = p.g.N <= SMALL_MAX ? 1 : 0;
+    const bool fused = use_fused(p);
+    solve_small[si] = fused ? 1 : 0;
     SolveStat *stat = d_stats + si;
     const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : 1e-13;
-    if (p.g.N <= SMALL_MAX) {
+    if (fused) {
         SmallSolveArgs a{};
         a.g = p.g;
         a.ent = p.d_ent;
@@ -571,8 +591,18 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
         a.hermitian = opt.hermitian;
         a.m_hint = m_hint[si] > 0 ? m_hint[si] : 8;
         a.stat = stat;
+        // two-slot problems use the batched matvec when its temporaries fit in LDS
+        int nA = 0;
+        for (auto &e : p.ents)
+            if (e.nf >= 1 && e.slot[e.nf - 1] == 1) ++nA;
+        a.nA = nA;
+        a.batched = (p.g.D == 2 && nA <= SMALL_MAXENT && p.g.dims[0] * p.g.dims[0] <= SMALL_UB &&
+                     small_solve_lds_bytes(p.g.N, a.mmax, 1, nA) + SMALL_MAXENT * sizeof(int) <= 160 * 1024)
+                        ? 1
+                        : 0;
         launch_small_solve(a, st);
     } else {
+        if (!bk.V) throw Error(TTN_E_STATE, "internal: Krylov scratch not allocated");
         int m = m_hint[si] > 0 ? m_hint[si] : 20;
         m = std::max(3, std::min(m, mmax));
         m = (int)std::min<int64_t>(m, p.g.N);
@@ -691,6 +721,15 @@ void Engine::step(double dt, int n_steps) {
                 off += t.size[z];
             }
             rebuild_all_spos();
+        }
+        if (profile_enabled()) {  // H_eff work done inside the fused solver launches
+            double f = 0.0;
+            for (int i = 0; i < solve_idx; ++i)
+                if (solve_small[i]) {
+                    const Prog &p = solve_fwd[i] ? heffP[solve_node[i]] : bondP[solve_node[i]];
+                    f += (double)h_stats[i].matvecs * (double)p.flops;
+                }
+            profile_add_flops("k_small_solve", f);
         }
         // counters
         ++counters[0];

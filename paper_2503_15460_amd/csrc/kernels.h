@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
+#include <vector>
 
 namespace ttn {
 
@@ -52,6 +54,8 @@ struct ProgView {
     double2 *tmp;             // 2 * n_ent * N
     double2 *gsum;            // n_groups * N
     double2 *cpart;           // contraction partials
+    double sflops[MAXF];      // algorithmic flops / bytes of each stage launch (host side)
+    double sbytes[MAXF];
 };
 
 // Statistics written by one Krylov solve.
@@ -75,8 +79,14 @@ struct SmallSolveArgs {
     int mmax;
     int hermitian;
     int m_hint;
+    int batched;       // two-slot problem with the batched matvec
+    int nA;            // entries with a slot-1 factor (batched)
     SolveStat *stat;
 };
+constexpr int SMALL_MAXENT = 128;  // entries of the batched two-slot matvec
+constexpr int SMALL_UB = 2048;     // LDS elements for staged slot-0 operators (batched matvec)
+constexpr int64_t SMALL_SEQ_WORK = 8192;  // entries x elements limit of the fused solver's generic matvec
+size_t small_solve_lds_bytes(int64_t N, int mmax, int batched, int nA);
 
 // Scratch of the multi-kernel Krylov path.
 struct BigKrylov {
@@ -104,6 +114,17 @@ struct QRWork {
     double *thr;                // [1] snap threshold
     unsigned *counter;          // last-block ticket (starts at 0)
 };
+
+// ---- launch profiler (off by default) ----
+struct KernelStat {
+    std::string name;
+    long long calls = 0;
+    double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+void profile_enable(bool enable);
+bool profile_enabled();
+void profile_add_flops(const char *name, double flops);
+std::vector<KernelStat> profile_collect();
 
 // ---- launchers (all asynchronous on `st`) ----
 void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st);

@@ -9,8 +9,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
+#include <map>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 
@@ -83,14 +86,14 @@ __device__ double blk_sum1(double v, double *red) {
 // finishes last (atomic ticket) sums them in a fixed order.
 __device__ bool last_block_ticket(unsigned *counter) {
     __shared__ int is_last;
-    __threadfence();  // every thread releases its partial-sum stores device-wide
-    __syncthreads();
+    __syncthreads();  // the block's partial-sum stores have reached L2
     if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
+        __threadfence();  // release, covering the block's stores ordered by the barrier
+        const unsigned prev = atomicAdd(counter, 1u);
         is_last = (prev == gridDim.x - 1);
+        if (is_last) __threadfence();  // acquire before reading the other blocks' partials
     }
     __syncthreads();
-    if (is_last) __threadfence();
     return is_last != 0;
 }
 
@@ -712,6 +715,17 @@ __device__ void blk_expm_col0(const double2 *H, int ldh, int m, double tau, doub
 }
 
 // ============================================================ fused small solver
+// One work-group owns a local problem of N <= SMALL_MAX elements (one element
+// per thread).  Krylov vectors live in global scratch (L2 resident), the
+// current vector, the matvec result and the temporaries in LDS.
+
+struct SmallLds {
+    double2 *v, *w, *r1, *Hm, *hbuf, *ybuf, *red;  // red: 16 waves x (mmax+1)
+    double2 *us;                                   // staged slot-0 operators (batched matvec)
+    double *red1;
+    int *e1;  // entries with a slot-1 factor (two-slot batched matvec)
+};
+
 __device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M, const Geom &g, int s) {
     const int n = g.dims[s];
     const uint32_t R = (uint32_t)g.R[s], N = (uint32_t)g.N;
@@ -726,7 +740,8 @@ __device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M,
     }
 }
 
-__device__ void blk_matvec(const SmallSolveArgs &a, const double2 *v, double2 *w, double2 *t1, double2 *t2) {
+// generic matvec: entries one after the other, factors applied slot by slot
+__device__ void blk_matvec_seq(const SmallSolveArgs &a, const double2 *v, double2 *w, double2 *t1, double2 *t2) {
     const uint32_t N = (uint32_t)a.g.N;
     for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) w[idx] = make_double2(0.0, 0.0);
     for (int e = 0; e < a.n_ent; ++e) {
@@ -746,17 +761,159 @@ __device__ void blk_matvec(const SmallSolveArgs &a, const double2 *v, double2 *w
     __syncthreads();
 }
 
+// two-slot local problems (leaves (d, n) and bond matrices (n, n)):
+//   phase A: T_e = X x_1 M1_e for every entry with a slot-1 factor
+//   phase B: Y = sum_e c_e (M0_e x_0 T_e)
+__device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double2 *w, double2 *T, const int *e1,
+                               double2 *Us) {
+    const int n0 = a.g.dims[0], n1 = a.g.dims[1];
+    const uint32_t N = (uint32_t)(n0 * n1);
+    const int na = a.nA;
+    for (uint32_t q = threadIdx.x; q < (uint32_t)na * N; q += blockDim.x) {
+        const uint32_t k = q / N, el = q - k * N;
+        const DevEntry *E = a.ent + e1[k];
+        const double2 *M1 = E->M[E->nf - 1];
+        const uint32_t ai = el / n1, p = el - ai * n1;
+        const double2 *xr = v + (size_t)ai * n1;
+        const double2 *mr = M1 + (size_t)p * n1;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int j = 0; j < n1; ++j) cfma(acc, mr[j], xr[j]);
+        T[q] = acc;
+    }
+    // phase B: slot-0 operators staged through LDS (coalesced loads), in groups
+    // of entries whose operators fit in SMALL_UB elements
+    constexpr int MAXO = SMALL_MAX / 256;  // outputs per thread (work-groups have >= 256 threads)
+    double2 acc[MAXO];
+#pragma unroll
+    for (int o = 0; o < MAXO; ++o) acc[o] = make_double2(0.0, 0.0);
+    const int nn0 = n0 * n0;
+    int e = 0, k = 0;
+    while (e < a.n_ent) {
+        int e_end = e, used = 0;
+        while (e_end < a.n_ent) {
+            const DevEntry *E = a.ent + e_end;
+            const bool has0 = E->nf >= 1 && E->slot[0] == 0;
+            const int need = has0 ? nn0 : 0;
+            if (used + need > SMALL_UB && e_end > e) break;
+            used += need;
+            ++e_end;
+        }
+        __syncthreads();  // previous group finished with Us
+        {
+            int off = 0;
+            for (int q = e; q < e_end; ++q) {
+                const DevEntry *E = a.ent + q;
+                if (E->nf >= 1 && E->slot[0] == 0) {
+                    for (int t = threadIdx.x; t < nn0; t += blockDim.x) Us[off + t] = E->M[0][t];
+                    off += nn0;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < MAXO; ++o) {
+            const uint32_t idx = threadIdx.x + o * blockDim.x;
+            if (idx >= N) break;
+            const uint32_t i = idx / n1, p = idx - i * n1;
+            int off = 0, kk = k;
+            double2 out = acc[o];
+            for (int q = e; q < e_end; ++q) {
+                const DevEntry *E = a.ent + q;
+                const int nf = E->nf;
+                const bool has0 = nf >= 1 && E->slot[0] == 0;
+                const bool has1 = nf >= 1 && E->slot[nf - 1] == 1;
+                const double2 *S = has1 ? T + (size_t)(kk++) * N : v;
+                double2 r = make_double2(0.0, 0.0);
+                if (has0) {
+                    const double2 *mr = Us + off + (size_t)i * n0;
+                    for (int j = 0; j < n0; ++j) cfma(r, mr[j], S[(size_t)j * n1 + p]);
+                    off += nn0;
+                } else {
+                    r = S[idx];
+                }
+                cfma(out, E->coef, r);
+            }
+            acc[o] = out;
+        }
+        for (int q = e; q < e_end; ++q) {
+            const DevEntry *E = a.ent + q;
+            if (E->nf >= 1 && E->slot[E->nf - 1] == 1) ++k;
+        }
+        e = e_end;
+    }
+#pragma unroll
+    for (int o = 0; o < MAXO; ++o) {
+        const uint32_t idx = threadIdx.x + o * blockDim.x;
+        if (idx < N) w[idx] = acc[o];
+    }
+    __syncthreads();
+}
+
+// h_i = <V_i, w> for i < nv (V in global); result in hbuf.  Basis loads are
+// issued eight at a time so their latencies overlap.
+__device__ void blk_dots(const double2 *V, uint32_t N, int nv, const double2 *w, double2 *red, double2 *hbuf,
+                         int ld) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int i0 = 0; i0 < nv; i0 += 8) {
+        double2 c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = make_double2(0.0, 0.0);
+        for (uint32_t idx = tid; idx < N; idx += blockDim.x) {
+            const double2 wv = w[idx];
+            double2 b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) b[q] = (i0 + q < nv) ? V[(size_t)(i0 + q) * N + idx] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cfmac(c[q], b[q], wv);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                c[q].x += __shfl_xor(c[q].x, off, 64);
+                c[q].y += __shfl_xor(c[q].y, off, 64);
+            }
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (i0 + q < nv) red[wave * ld + i0 + q] = c[q];
+    }
+    __syncthreads();
+    if (tid < nv) {
+        double2 sacc = make_double2(0.0, 0.0);
+        for (int q = 0; q < nw; ++q) sacc = cadd(sacc, red[q * ld + tid]);
+        hbuf[tid] = sacc;
+    }
+    __syncthreads();
+}
+
+// w[idx] -= sum_i h_i V_i[idx] for the thread's elements (loads eight at a time)
+__device__ void blk_sub_basis(const double2 *V, uint32_t N, int nv, const double2 *h, double2 *w) {
+    for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) {
+        double2 wv = w[idx];
+        for (int i0 = 0; i0 < nv; i0 += 8) {
+            double2 c[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = (i0 + q < nv) ? V[(size_t)(i0 + q) * N + idx] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (i0 + q < nv) wv = csub(wv, cmul(h[i0 + q], c[q]));
+        }
+        w[idx] = wv;
+    }
+}
+
 // One Krylov exponential x <- exp(-i tau G) x; returns true when converged.
-__device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x, double2 *v, double2 *w,
-                                double2 *t1, double2 *t2, double2 *Hm, double2 *ex, double2 *red8, double *red1,
-                                double2 *hbuf, double2 *ybuf, int &m_used, int &matvecs, double &err_out) {
+__device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x, const SmallLds &L, int &m_used,
+                                int &matvecs, double &err_out) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const uint32_t N = (uint32_t)a.g.N;
     const int mmax = a.mmax;
+    const int ld = mmax + 1;
     double2 *V = a.V;
     double part = 0.0;
     for (uint32_t idx = tid; idx < N; idx += nt) part += cabs2(x[idx]);
-    const double beta0 = sqrt(blk_sum1(part, red1));
+    const double beta0 = sqrt(blk_sum1(part, L.red1));
     if (beta0 == 0.0) {
         m_used = 0;
         err_out = 0.0;
@@ -764,65 +921,51 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
     }
     for (uint32_t idx = tid; idx < N; idx += nt) {
         double2 q = cscale(x[idx], 1.0 / beta0);
-        v[idx] = q;
+        L.v[idx] = q;
         V[idx] = q;
     }
-    for (int q = tid; q < (mmax + 1) * mmax; q += nt) Hm[q] = make_double2(0.0, 0.0);
+    for (int q = tid; q < (mmax + 1) * mmax; q += nt) L.Hm[q] = make_double2(0.0, 0.0);
     __syncthreads();
     for (int j = 0; j < mmax; ++j) {
-        blk_matvec(a, v, w, t1, t2);
+        if (a.batched) blk_matvec_two(a, L.v, L.w, L.r1, L.e1, L.us);
+        else blk_matvec_seq(a, L.v, L.w, L.r1, L.r1 + N);
         ++matvecs;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int i0 = 0; i0 <= j; i0 += 8) {
-                const int cnt = min(8, j + 1 - i0);
-                double2 acc[8];
-                for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
-                for (uint32_t idx = tid; idx < N; idx += nt) {
-                    const double2 wv = w[idx];
-                    for (int q = 0; q < cnt; ++q) cfmac(acc[q], V[(size_t)(i0 + q) * N + idx], wv);
-                }
-                blk_sum8(acc, cnt, red8, hbuf + i0);
-            }
-            for (uint32_t idx = tid; idx < N; idx += nt) {
-                double2 wv = w[idx];
-                for (int i = 0; i <= j; ++i) wv = csub(wv, cmul(hbuf[i], V[(size_t)i * N + idx]));
-                w[idx] = wv;
-            }
-            if (tid <= j) Hm[tid * mmax + j] = cadd(Hm[tid * mmax + j], hbuf[tid]);
+        for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+            blk_dots(V, N, j + 1, L.w, L.red, L.hbuf, ld);
+            blk_sub_basis(V, N, j + 1, L.hbuf, L.w);
+            if (tid <= j) L.Hm[tid * mmax + j] = cadd(L.Hm[tid * mmax + j], L.hbuf[tid]);
             __syncthreads();
         }
         part = 0.0;
-        for (uint32_t idx = tid; idx < N; idx += nt) part += cabs2(w[idx]);
-        const double beta = sqrt(blk_sum1(part, red1));
-        if (tid == 0) Hm[(j + 1) * mmax + j] = make_double2(beta, 0.0);
+        for (uint32_t idx = tid; idx < N; idx += nt) part += cabs2(L.w[idx]);
+        const double beta = sqrt(blk_sum1(part, L.red1));
+        if (tid == 0) L.Hm[(j + 1) * mmax + j] = make_double2(beta, 0.0);
         __syncthreads();
         const bool breakdown = beta <= 1e-14 * beta0;
         if (breakdown || j + 1 >= a.m_hint - 2 || j == mmax - 1) {
             // projected matrix of dimension j+1 (tridiagonal for Hermitian G)
-            double2 *Hs = ex;  // (j+1)^2 staging, then expm workspace after it
+            double2 *Hs = L.r1;
             const int m = j + 1;
             for (int q = tid; q < m * m; q += nt) {
                 int r = q / m, c = q % m;
                 double2 h;
                 if (a.hermitian) {
-                    if (r == c) h = make_double2(Hm[r * mmax + r].x, 0.0);
-                    else if (r == c + 1) h = Hm[r * mmax + c];
-                    else if (c == r + 1) h = Hm[c * mmax + r];
+                    if (r == c) h = make_double2(L.Hm[r * mmax + r].x, 0.0);
+                    else if (r == c + 1) h = L.Hm[r * mmax + c];
+                    else if (c == r + 1) h = L.Hm[c * mmax + r];
                     else h = make_double2(0.0, 0.0);
                 } else {
-                    h = Hm[r * mmax + c];
+                    h = L.Hm[r * mmax + c];
                 }
                 Hs[q] = h;
             }
             __syncthreads();
-            blk_expm_col0(Hs, m, m, tau, ex + m * m, red1, ybuf);
-            const double err = beta0 * beta * sqrt(cabs2(ybuf[j]));
+            blk_expm_col0(Hs, m, m, tau, L.r1 + m * m, L.red1, L.ybuf);
+            const double err = beta0 * beta * sqrt(cabs2(L.ybuf[j]));
             if (breakdown || err <= a.tol * beta0) {
-                for (uint32_t idx = tid; idx < N; idx += nt) {
-                    double2 acc = make_double2(0.0, 0.0);
-                    for (int i = 0; i <= j; ++i) cfma(acc, ybuf[i], V[(size_t)i * N + idx]);
-                    x[idx] = cscale(acc, beta0);
-                }
+                for (uint32_t idx = tid; idx < N; idx += nt) x[idx] = make_double2(0.0, 0.0);
+                blk_sub_basis(V, N, j + 1, L.ybuf, x);  // x = -sum_i y_i V_i
+                for (uint32_t idx = tid; idx < N; idx += nt) x[idx] = cscale(x[idx], -beta0);
                 m_used = j + 1;
                 err_out = breakdown ? 0.0 : err / beta0;
                 __syncthreads();
@@ -833,8 +976,8 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
         if (j == mmax - 1) break;
         const double ib = 1.0 / beta;
         for (uint32_t idx = tid; idx < N; idx += nt) {
-            double2 q = cscale(w[idx], ib);
-            v[idx] = q;
+            double2 q = cscale(L.w[idx], ib);
+            L.v[idx] = q;
             V[(size_t)(j + 1) * N + idx] = q;
         }
         __syncthreads();
@@ -843,17 +986,35 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
     return false;
 }
 
+__host__ __device__ inline size_t small_r1_elems(int64_t N, int mmax, int batched, int nA) {
+    size_t a = batched ? (size_t)nA * N : 2 * (size_t)N;
+    size_t b = 4 * (size_t)mmax * mmax;
+    return a > b ? a : b;
+}
+
 __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a) {
     extern __shared__ double2 sm[];
+    __shared__ int e1[SMALL_MAXENT];
     const uint32_t N = (uint32_t)a.g.N;
     const int mmax = a.mmax;
-    double2 *v = sm, *w = v + N, *t1 = w + N, *t2 = t1 + N;
-    double2 *Hm = t2 + N;
-    double2 *ex = Hm + (mmax + 1) * mmax;   // (mmax^2 staging) + 3 mmax^2 workspace
-    double2 *red8 = ex + 4 * mmax * mmax;   // 16 * 8
-    double2 *hbuf = red8 + 16 * 8;          // mmax + 1
-    double2 *ybuf = hbuf + (mmax + 1);      // mmax
-    double *red1 = reinterpret_cast<double *>(ybuf + mmax);  // 16
+    SmallLds L;
+    L.v = sm;
+    L.w = L.v + N;
+    L.r1 = L.w + N;
+    L.Hm = L.r1 + small_r1_elems(N, mmax, a.batched, a.nA);
+    L.hbuf = L.Hm + (mmax + 1) * mmax;
+    L.ybuf = L.hbuf + (mmax + 1);
+    L.red = L.ybuf + mmax;
+    L.red1 = reinterpret_cast<double *>(L.red + 16 * (mmax + 1));
+    L.us = reinterpret_cast<double2 *>(L.red1 + 16);
+    L.e1 = e1;
+    if (threadIdx.x == 0 && a.batched) {
+        int k = 0;
+        for (int e = 0; e < a.n_ent; ++e) {
+            const DevEntry *E = a.ent + e;
+            if (E->nf >= 1 && E->slot[E->nf - 1] == 1) e1[k++] = e;
+        }
+    }
     double2 *x = a.x;
     double2 *xorig = a.V + (size_t)(SMALL_MMAX + 1) * N;
     for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) xorig[idx] = x[idx];
@@ -868,9 +1029,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
         }
         const int nsub = 1 << level;
         ok = true;
-        for (int q = 0; q < nsub && ok; ++q)
-            ok = blk_krylov_once(a, a.tau / nsub, x, v, w, t1, t2, Hm, ex, red8, red1, hbuf, ybuf, m_used,
-                                 matvecs, err);
+        for (int q = 0; q < nsub && ok; ++q) ok = blk_krylov_once(a, a.tau / nsub, x, L, m_used, matvecs, err);
         if (ok) break;
     }
     if (threadIdx.x == 0 && a.stat) {
@@ -883,8 +1042,9 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
     }
 }
 
-size_t small_solve_lds_bytes(int64_t N, int mmax) {
-    return sizeof(double2) * (size_t)(4 * N + (mmax + 1) * mmax + 4 * mmax * mmax + 16 * 8 + (mmax + 1) + mmax) +
+size_t small_solve_lds_bytes(int64_t N, int mmax, int batched, int nA) {
+    return sizeof(double2) * (size_t)(2 * N + small_r1_elems(N, mmax, batched, nA) + (mmax + 1) * mmax +
+                                      (mmax + 1) + mmax + 16 * (mmax + 1) + (batched ? SMALL_UB : 0)) +
            16 * sizeof(double);
 }
 
@@ -1057,6 +1217,78 @@ __global__ void k_transpose(double2 *dst, const double2 *src, int n) {
     }
 }
 
+// ============================================================ launch profiler
+// Optional: every launch bracketed by two HIP events on its stream; per kernel
+// name the summed elapsed time, call count and algorithmic flops / bytes.
+namespace prof {
+struct Rec {
+    const char *name;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+static bool on = false;
+static std::vector<hipEvent_t> pool;
+static size_t used = 0;
+static std::vector<Rec> recs;
+static std::map<std::string, double> extra_flops;
+static hipEvent_t take() {
+    if (used == pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+        pool.push_back(e);
+    }
+    return pool[used++];
+}
+}  // namespace prof
+
+#define TTN_LAUNCH(NAME, FL, BY, KER, GRID, BLOCK, LDS, ST, ...)                                     \
+    do {                                                                                             \
+        hipEvent_t ea_ = nullptr, eb_ = nullptr;                                                     \
+        if (prof::on) {                                                                              \
+            ea_ = prof::take();                                                                      \
+            eb_ = prof::take();                                                                      \
+            (void)hipEventRecord(ea_, ST);                                                           \
+        }                                                                                            \
+        hipLaunchKernelGGL(KER, GRID, BLOCK, LDS, ST, __VA_ARGS__);                                  \
+        if (prof::on) {                                                                              \
+            (void)hipEventRecord(eb_, ST);                                                           \
+            prof::recs.push_back({NAME, ea_, eb_, (double)(FL), (double)(BY)});                      \
+        }                                                                                            \
+    } while (0)
+
+void profile_enable(bool enable) {
+    prof::on = enable;
+    prof::used = 0;
+    prof::recs.clear();
+    prof::extra_flops.clear();
+}
+
+bool profile_enabled() { return prof::on; }
+
+void profile_add_flops(const char *name, double flops) { prof::extra_flops[name] += flops; }
+
+std::vector<KernelStat> profile_collect() {
+    if (hipDeviceSynchronize() != hipSuccess) throw std::runtime_error("hipDeviceSynchronize failed");
+    std::map<std::string, KernelStat> agg;
+    for (auto &r : prof::recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) throw std::runtime_error("hipEventElapsedTime failed");
+        KernelStat &k = agg[r.name];
+        k.name = r.name;
+        k.calls += 1;
+        k.ms += ms;
+        k.flops += r.flops;
+        k.bytes += r.bytes;
+    }
+    for (auto &kv : prof::extra_flops) agg[kv.first].flops += kv.second;
+    std::vector<KernelStat> out;
+    for (auto &kv : agg) out.push_back(kv.second);
+    prof::used = 0;
+    prof::recs.clear();
+    prof::extra_flops.clear();
+    return out;
+}
+
 // ============================================================ launchers
 // Raise a kernel's dynamic LDS limit when a launch needs more than the default
 // 64 KiB (gfx950 work-groups may use up to 160 KiB).
@@ -1081,13 +1313,14 @@ void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st) {
     const size_t lds = sizeof(double2) * (size_t)ldn * ldn;
     for (int s = 0; s < p.max_nf; ++s) {
         dim3 grid(grid_for(p.g.N, 256), p.n_ent);
-        hipLaunchKernelGGL(k_mode_stage, grid, dim3(256), lds, st, p, s, in, ldn);
+        TTN_LAUNCH("k_mode_stage", p.sflops[s], p.sbytes[s], k_mode_stage, grid, dim3(256), lds, st, p, s, in, ldn);
     }
 }
 
 void launch_prog_sum(const ProgView &p, const double2 *in, double2 *out_single, hipStream_t st) {
     dim3 grid(grid_for(p.g.N, 256), out_single ? 1 : p.n_groups);
-    hipLaunchKernelGGL(k_group_sum, grid, dim3(256), 0, st, p, in, out_single);
+    TTN_LAUNCH("k_group_sum", 8.0 * p.g.N * p.n_ent, 16.0 * p.g.N * (p.n_ent + (out_single ? 1 : p.n_groups)),
+               k_group_sum, grid, dim3(256), 0, st, p, in, out_single);
 }
 
 void launch_prog_contract(const ProgView &p, const double2 *A, hipStream_t st) {
@@ -1096,32 +1329,36 @@ void launch_prog_contract(const ProgView &p, const double2 *A, hipStream_t st) {
     const uint32_t L = (uint32_t)p.g.L[s], R = (uint32_t)p.g.R[s];
     const int nb = contract_blocks(L * R);
     const size_t lds = sizeof(double2) * (size_t)CT_ROWS * 2 * n;
-    hipLaunchKernelGGL(k_contract_part, dim3(nb, p.n_groups), dim3(256), lds, st, A, (const double2 *)p.gsum,
-                       p.g.N, L, n, n, R, p.cpart);
-    hipLaunchKernelGGL(k_contract_reduce, dim3(grid_for(n * n, 256), p.n_groups), dim3(256), 0, st,
-                       (const double2 *)p.cpart, nb, n * n, p.gdst, (double2 *)nullptr);
+    TTN_LAUNCH("k_contract_part", 8.0 * p.g.N * n * p.n_groups, 16.0 * p.g.N * (1 + p.n_groups), k_contract_part,
+               dim3(nb, p.n_groups), dim3(256), lds, st, A, (const double2 *)p.gsum, p.g.N, L, n, n, R, p.cpart);
+    TTN_LAUNCH("k_contract_reduce", 2.0 * nb * n * n * p.n_groups, 16.0 * nb * n * n * p.n_groups, k_contract_reduce,
+               dim3(grid_for(n * n, 256), p.n_groups), dim3(256), 0, st, (const double2 *)p.cpart, nb, n * n, p.gdst,
+               (double2 *)nullptr);
 }
 
 void launch_mode_product(const double2 *X, double2 *Y, const double2 *M, int64_t L, int n_in, int n_out,
                          int64_t R, int transM, hipStream_t st) {
     const int64_t NY = L * n_out * R;
-    hipLaunchKernelGGL(k_mode_single, dim3(grid_for(NY, 256)), dim3(256), 0, st, X, Y, M, (uint32_t)L, n_in,
-                       n_out, (uint32_t)R, transM);
+    TTN_LAUNCH("k_mode_single", 8.0 * NY * n_in, 16.0 * (L * n_in * R + NY + (int64_t)n_in * n_out), k_mode_single,
+               dim3(grid_for(NY, 256)), dim3(256), 0, st, X, Y, M, (uint32_t)L, n_in, n_out, (uint32_t)R, transM);
 }
 
 void launch_contract(const double2 *A, const double2 *B, double2 *out, int64_t L, int nA, int nB, int64_t R,
                      double2 *part, hipStream_t st) {
     const int nb = contract_blocks((uint32_t)(L * R));
     const size_t lds = sizeof(double2) * (size_t)CT_ROWS * (nA + nB);
-    hipLaunchKernelGGL(k_contract_part, dim3(nb, 1), dim3(256), lds, st, A, B, (int64_t)0, (uint32_t)L, nA, nB,
-                       (uint32_t)R, part);
-    hipLaunchKernelGGL(k_contract_reduce, dim3(grid_for(nA * nB, 256), 1), dim3(256), 0, st,
-                       (const double2 *)part, nb, nA * nB, (double2 *const *)nullptr, out);
+    TTN_LAUNCH("k_contract_part", 8.0 * L * R * nA * nB, 16.0 * L * R * (nA + nB), k_contract_part, dim3(nb, 1),
+               dim3(256), lds, st, A, B, (int64_t)0, (uint32_t)L, nA, nB, (uint32_t)R, part);
+    TTN_LAUNCH("k_contract_reduce", 2.0 * nb * nA * nB, 16.0 * nb * nA * nB, k_contract_reduce,
+               dim3(grid_for(nA * nB, 256), 1), dim3(256), 0, st, (const double2 *)part, nb, nA * nB,
+               (double2 *const *)nullptr, out);
 }
 
 void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st) {
     if (n > 64 || L * R < n) throw std::runtime_error("QR shape out of range");
-    hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, st, A, (uint32_t)L, n, (uint32_t)R, Rout, transR, QR_SNAP);
+    const double mm = (double)L * R;
+    TTN_LAUNCH("k_qr", 16.0 * mm * n * n, 16.0 * mm * n * 4, k_qr, dim3(1), dim3(1024), 0, st, A, (uint32_t)L, n,
+               (uint32_t)R, Rout, transR, QR_SNAP);
 }
 
 void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
@@ -1132,32 +1369,45 @@ void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int
     if (rows_per < 64) rows_per = 64;
     const unsigned nb = (unsigned)((m + rows_per - 1) / rows_per);
     for (int i = 0; i < n; ++i)
-        hipLaunchKernelGGL(k_qrm_step, dim3(nb), dim3(QRM_THREADS), 0, st, A, (uint32_t)L, n, (uint32_t)R, i,
-                           (uint32_t)rows_per, q, QR_SNAP);
+        TTN_LAUNCH("k_qrm_step", 16.0 * m * (n - i), 32.0 * m * (n - i), k_qrm_step, dim3(nb), dim3(QRM_THREADS), 0, st,
+                   A, (uint32_t)L, n, (uint32_t)R, i, (uint32_t)rows_per, q, QR_SNAP);
     const size_t lds_fin = sizeof(double2) * 2 * n * n;
     set_lds_limit((const void *)k_qrm_finish, lds_fin);
-    hipLaunchKernelGGL(k_qrm_finish, dim3(nb), dim3(QRM_THREADS), lds_fin, st, A, (uint32_t)L, n, (uint32_t)R,
-                       (uint32_t)rows_per, q, Rout, transR);
+    TTN_LAUNCH("k_qrm_finish", 4.0 * m * n * n, 16.0 * m * n, k_qrm_finish, dim3(nb), dim3(QRM_THREADS), lds_fin, st,
+               A, (uint32_t)L, n, (uint32_t)R, (uint32_t)rows_per, q, Rout, transR);
     const size_t lds_q = sizeof(double2) * (size_t)(n * n + 16 * n);
     set_lds_limit((const void *)k_qrm_formq, lds_q);
-    hipLaunchKernelGGL(k_qrm_formq, dim3(nb), dim3(QRM_THREADS), lds_q, st, A, (uint32_t)L, n, (uint32_t)R,
-                       (uint32_t)rows_per, q);
+    TTN_LAUNCH("k_qrm_formq", 8.0 * m * n * n, 32.0 * m * n, k_qrm_formq, dim3(nb), dim3(QRM_THREADS), lds_q, st, A,
+               (uint32_t)L, n, (uint32_t)R, (uint32_t)rows_per, q);
 }
 
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
-    const size_t lds = small_solve_lds_bytes(a.g.N, a.mmax);
-    if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds > 160 * 1024)
+    const size_t lds = small_solve_lds_bytes(a.g.N, a.mmax, a.batched, a.nA);
+    if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds + SMALL_MAXENT * sizeof(int) > 160 * 1024 ||
+        (a.batched && (a.g.D != 2 || a.nA > SMALL_MAXENT || a.g.dims[0] * a.g.dims[0] > SMALL_UB)))
         throw std::runtime_error("small solve out of range");
     set_lds_limit((const void *)k_small_solve, lds);
-    hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(SMALL_THREADS), lds, st, a);
+    // work-group size: the problem size rounded up to a wavefront, capped
+    static int cap = -1;
+    if (cap < 0) {
+        const char *env = getenv("TTN_SMALL_THREADS");
+        cap = env ? atoi(env) : 512;
+        if (cap < 64 || cap > SMALL_THREADS) cap = 512;
+    }
+    int threads = (int)((a.g.N + 63) / 64) * 64;
+    if (threads < 64) threads = 64;
+    if (threads > cap) threads = cap;
+    if (a.batched && threads < 256) threads = 256;  // the batched matvec keeps N/256 outputs per thread
+    TTN_LAUNCH("k_small_solve", 0.0, 0.0, k_small_solve, dim3(1), dim3(threads), lds, st, a);
 }
 
 void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256)), dim3(256), 0, st, dst, src, (uint32_t)n);
+    TTN_LAUNCH("k_copy", 0.0, 32.0 * n, k_copy, dim3(grid_for(n, 256)), dim3(256), 0, st, dst, src, (uint32_t)n);
 }
 
 void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_transpose, dim3(grid_for((int64_t)n * n, 256)), dim3(256), 0, st, dst, src, n);
+    TTN_LAUNCH("k_transpose", 0.0, 32.0 * n * n, k_transpose, dim3(grid_for((int64_t)n * n, 256)), dim3(256), 0, st,
+               dst, src, n);
 }
 
 static unsigned vec_blocks(int64_t N) {
@@ -1166,15 +1416,20 @@ static unsigned vec_blocks(int64_t N) {
 }
 
 void launch_krylov_start(const double2 *x, int64_t N, const BigKrylov &k, hipStream_t st) {
-    hipLaunchKernelGGL(k_kry_norm0, dim3(vec_blocks(N)), dim3(VEC_THREADS), 0, st, x, (uint32_t)N, k);
-    hipLaunchKernelGGL(k_kry_scale0, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, x, (uint32_t)N, k);
+    TTN_LAUNCH("k_kry_norm0", 4.0 * N, 16.0 * N, k_kry_norm0, dim3(vec_blocks(N)), dim3(VEC_THREADS), 0, st, x,
+               (uint32_t)N, k);
+    TTN_LAUNCH("k_kry_scale0", 2.0 * N, 32.0 * N, k_kry_scale0, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0,
+               st, x, (uint32_t)N, k);
 }
 
 void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st) {
     const unsigned nb = vec_blocks(N);
     for (int pass = 0; pass < 3; ++pass)
-        hipLaunchKernelGGL(k_kry_orth, dim3(nb), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, pass);
-    hipLaunchKernelGGL(k_kry_normalize, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, k,
+        TTN_LAUNCH("k_kry_orth", 8.0 * N * (j + 1) * (pass == 0 ? 1 : (pass == 1 ? 2 : 1)) + 4.0 * N,
+                   16.0 * N * ((pass == 0 ? 1 : 2) * (j + 1) + (pass == 0 ? 1 : 2)), k_kry_orth, dim3(nb),
+                   dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, pass);
+    TTN_LAUNCH("k_kry_normalize", 2.0 * N, 32.0 * N, k_kry_normalize, dim3(grid_for(N, VEC_THREADS)),
+               dim3(VEC_THREADS), 0, st, k,
                        (uint32_t)N, j);
 }
 
@@ -1182,8 +1437,10 @@ void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double
                           double2 *x, SolveStat *stat, hipStream_t st) {
     const size_t lds = sizeof(double2) * (size_t)(4 * m * m + m);
     set_lds_limit((const void *)k_kry_expm, lds);
-    hipLaunchKernelGGL(k_kry_expm, dim3(1), dim3(1024), lds, st, k, m, mmax, tau, tol, hermitian, stat);
-    hipLaunchKernelGGL(k_kry_combine, dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, m,
+    TTN_LAUNCH("k_kry_expm", 0.0, 0.0, k_kry_expm, dim3(1), dim3(1024), lds, st, k, m, mmax, tau, tol, hermitian,
+               stat);
+    TTN_LAUNCH("k_kry_combine", 8.0 * N * m, 16.0 * N * (m + 1), k_kry_combine, dim3(grid_for(N, VEC_THREADS)),
+               dim3(VEC_THREADS), 0, st, k, (uint32_t)N, m,
                        x);
 }
 
