@@ -723,7 +723,8 @@ struct SmallLds {
     double2 *v, *w, *r1, *Hm, *hbuf, *ybuf, *red;  // red: 16 waves x (mmax+1)
     double2 *us;                                   // staged slot-0 operators (batched matvec)
     double *red1;
-    int *e1;  // entries with a slot-1 factor (two-slot batched matvec)
+    int *e1;   // entries with a slot-1 factor (two-slot batched matvec)
+    int *tix;  // per entry: index of its slot-1 temporary, -1 if none
 };
 
 __device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M, const Geom &g, int s) {
@@ -765,7 +766,7 @@ __device__ void blk_matvec_seq(const SmallSolveArgs &a, const double2 *v, double
 //   phase A: T_e = X x_1 M1_e for every entry with a slot-1 factor
 //   phase B: Y = sum_e c_e (M0_e x_0 T_e)
 __device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double2 *w, double2 *T, const int *e1,
-                               double2 *Us) {
+                               const int *tix, double2 *Us) {
     const int n0 = a.g.dims[0], n1 = a.g.dims[1];
     const uint32_t N = (uint32_t)(n0 * n1);
     const int na = a.nA;
@@ -780,81 +781,52 @@ __device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double
         for (int j = 0; j < n1; ++j) cfma(acc, mr[j], xr[j]);
         T[q] = acc;
     }
-    // phase B: slot-0 operators staged through LDS (coalesced loads), in groups
-    // of entries whose operators fit in SMALL_UB elements
-    constexpr int MAXO = SMALL_MAX / 256;  // outputs per thread (work-groups have >= 256 threads)
-    double2 acc[MAXO];
-#pragma unroll
-    for (int o = 0; o < MAXO; ++o) acc[o] = make_double2(0.0, 0.0);
-    const int nn0 = n0 * n0;
-    int e = 0, k = 0;
-    while (e < a.n_ent) {
-        int e_end = e, used = 0;
-        while (e_end < a.n_ent) {
-            const DevEntry *E = a.ent + e_end;
-            const bool has0 = E->nf >= 1 && E->slot[0] == 0;
-            const int need = has0 ? nn0 : 0;
-            if (used + need > SMALL_UB && e_end > e) break;
-            used += need;
-            ++e_end;
-        }
-        __syncthreads();  // previous group finished with Us
-        {
-            int off = 0;
-            for (int q = e; q < e_end; ++q) {
-                const DevEntry *E = a.ent + q;
-                if (E->nf >= 1 && E->slot[0] == 0) {
-                    for (int t = threadIdx.x; t < nn0; t += blockDim.x) Us[off + t] = E->M[0][t];
-                    off += nn0;
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int o = 0; o < MAXO; ++o) {
-            const uint32_t idx = threadIdx.x + o * blockDim.x;
-            if (idx >= N) break;
+    __syncthreads();
+    // phase B: entries split over G thread groups (round robin), partial sums in LDS
+    const int Np = (int)((N + 63) / 64) * 64;
+    int G = (int)blockDim.x / Np;
+    if (G < 1) G = 1;
+    const int gsz = G > 1 ? Np : (int)blockDim.x;  // one group strides over the whole work-group
+    const int grp = (int)threadIdx.x / gsz, o = (int)threadIdx.x - grp * gsz;
+    if (grp < G) {
+        for (uint32_t idx = o; idx < N; idx += gsz) {
             const uint32_t i = idx / n1, p = idx - i * n1;
-            int off = 0, kk = k;
-            double2 out = acc[o];
-            for (int q = e; q < e_end; ++q) {
-                const DevEntry *E = a.ent + q;
+            double2 out = make_double2(0.0, 0.0);
+            for (int e = grp; e < a.n_ent; e += G) {
+                const DevEntry *E = a.ent + e;
                 const int nf = E->nf;
                 const bool has0 = nf >= 1 && E->slot[0] == 0;
-                const bool has1 = nf >= 1 && E->slot[nf - 1] == 1;
-                const double2 *S = has1 ? T + (size_t)(kk++) * N : v;
+                const int k = tix[e];
+                const double2 *S = k >= 0 ? T + (size_t)k * N : v;
                 double2 r = make_double2(0.0, 0.0);
                 if (has0) {
-                    const double2 *mr = Us + off + (size_t)i * n0;
+                    const double2 *mr = E->M[0] + (size_t)i * n0;
                     for (int j = 0; j < n0; ++j) cfma(r, mr[j], S[(size_t)j * n1 + p]);
-                    off += nn0;
                 } else {
                     r = S[idx];
                 }
                 cfma(out, E->coef, r);
             }
-            acc[o] = out;
+            Us[(size_t)grp * N + idx] = out;
         }
-        for (int q = e; q < e_end; ++q) {
-            const DevEntry *E = a.ent + q;
-            if (E->nf >= 1 && E->slot[E->nf - 1] == 1) ++k;
-        }
-        e = e_end;
     }
-#pragma unroll
-    for (int o = 0; o < MAXO; ++o) {
-        const uint32_t idx = threadIdx.x + o * blockDim.x;
-        if (idx < N) w[idx] = acc[o];
+    __syncthreads();
+    for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) {
+        double2 out = Us[idx];
+        for (int g = 1; g < G; ++g) out = cadd(out, Us[(size_t)g * N + idx]);
+        w[idx] = out;
     }
     __syncthreads();
 }
 
 // h_i = <V_i, w> for i < nv (V in global); result in hbuf.  Basis loads are
 // issued eight at a time so their latencies overlap.
+// With want_norm, hbuf[nv] additionally receives (|w|^2, 0).
 __device__ void blk_dots(const double2 *V, uint32_t N, int nv, const double2 *w, double2 *red, double2 *hbuf,
-                         int ld) {
+                         int ld, bool want_norm = false) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
-    for (int i0 = 0; i0 < nv; i0 += 8) {
+    const int nt = want_norm ? nv + 1 : nv;
+    for (int i0 = 0; i0 < nt; i0 += 8) {
         double2 c[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) c[q] = make_double2(0.0, 0.0);
@@ -862,7 +834,8 @@ __device__ void blk_dots(const double2 *V, uint32_t N, int nv, const double2 *w,
             const double2 wv = w[idx];
             double2 b[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) b[q] = (i0 + q < nv) ? V[(size_t)(i0 + q) * N + idx] : make_double2(0.0, 0.0);
+            for (int q = 0; q < 8; ++q)
+                b[q] = (i0 + q < nv) ? V[(size_t)(i0 + q) * N + idx] : (i0 + q == nv ? wv : make_double2(0.0, 0.0));
 #pragma unroll
             for (int q = 0; q < 8; ++q) cfmac(c[q], b[q], wv);
         }
@@ -876,10 +849,10 @@ __device__ void blk_dots(const double2 *V, uint32_t N, int nv, const double2 *w,
         if (lane == 0)
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                if (i0 + q < nv) red[wave * ld + i0 + q] = c[q];
+                if (i0 + q < nt) red[wave * ld + i0 + q] = c[q];
     }
     __syncthreads();
-    if (tid < nv) {
+    if (tid < nt) {
         double2 sacc = make_double2(0.0, 0.0);
         for (int q = 0; q < nw; ++q) sacc = cadd(sacc, red[q * ld + tid]);
         hbuf[tid] = sacc;
@@ -927,18 +900,22 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
     for (int q = tid; q < (mmax + 1) * mmax; q += nt) L.Hm[q] = make_double2(0.0, 0.0);
     __syncthreads();
     for (int j = 0; j < mmax; ++j) {
-        if (a.batched) blk_matvec_two(a, L.v, L.w, L.r1, L.e1, L.us);
+        if (a.batched) blk_matvec_two(a, L.v, L.w, L.r1, L.e1, L.tix, L.us);
         else blk_matvec_seq(a, L.v, L.w, L.r1, L.r1 + N);
         ++matvecs;
+        double wn2 = 0.0;
         for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-            blk_dots(V, N, j + 1, L.w, L.red, L.hbuf, ld);
+            // the second pass also reduces |w|^2: |w - V h|^2 = |w|^2 - |h|^2 (h ~ eps there)
+            blk_dots(V, N, j + 1, L.w, L.red, L.hbuf, ld, pass == 1);
+            if (pass == 1) {
+                wn2 = L.hbuf[j + 1].x;
+                for (int i = 0; i <= j; ++i) wn2 -= cabs2(L.hbuf[i]);
+            }
             blk_sub_basis(V, N, j + 1, L.hbuf, L.w);
             if (tid <= j) L.Hm[tid * mmax + j] = cadd(L.Hm[tid * mmax + j], L.hbuf[tid]);
             __syncthreads();
         }
-        part = 0.0;
-        for (uint32_t idx = tid; idx < N; idx += nt) part += cabs2(L.w[idx]);
-        const double beta = sqrt(blk_sum1(part, L.red1));
+        const double beta = sqrt(fmax(wn2, 0.0));
         if (tid == 0) L.Hm[(j + 1) * mmax + j] = make_double2(beta, 0.0);
         __syncthreads();
         const bool breakdown = beta <= 1e-14 * beta0;
@@ -995,6 +972,7 @@ __host__ __device__ inline size_t small_r1_elems(int64_t N, int mmax, int batche
 __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a) {
     extern __shared__ double2 sm[];
     __shared__ int e1[SMALL_MAXENT];
+    __shared__ int tix[SMALL_MAXENT];
     const uint32_t N = (uint32_t)a.g.N;
     const int mmax = a.mmax;
     SmallLds L;
@@ -1008,11 +986,17 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
     L.red1 = reinterpret_cast<double *>(L.red + 16 * (mmax + 1));
     L.us = reinterpret_cast<double2 *>(L.red1 + 16);
     L.e1 = e1;
+    L.tix = tix;
     if (threadIdx.x == 0 && a.batched) {
         int k = 0;
         for (int e = 0; e < a.n_ent; ++e) {
             const DevEntry *E = a.ent + e;
-            if (E->nf >= 1 && E->slot[E->nf - 1] == 1) e1[k++] = e;
+            if (E->nf >= 1 && E->slot[E->nf - 1] == 1) {
+                tix[e] = k;
+                e1[k++] = e;
+            } else {
+                tix[e] = -1;
+            }
         }
     }
     double2 *x = a.x;
@@ -1384,7 +1368,7 @@ void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     const size_t lds = small_solve_lds_bytes(a.g.N, a.mmax, a.batched, a.nA);
     if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds + SMALL_MAXENT * sizeof(int) > 160 * 1024 ||
-        (a.batched && (a.g.D != 2 || a.nA > SMALL_MAXENT || a.g.dims[0] * a.g.dims[0] > SMALL_UB)))
+        (a.batched && (a.g.D != 2 || a.n_ent > SMALL_MAXENT || a.g.dims[0] * a.g.dims[0] > SMALL_UB)))
         throw std::runtime_error("small solve out of range");
     set_lds_limit((const void *)k_small_solve, lds);
     // work-group size: the problem size rounded up to a wavefront, capped
@@ -1397,7 +1381,7 @@ void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     int threads = (int)((a.g.N + 63) / 64) * 64;
     if (threads < 64) threads = 64;
     if (threads > cap) threads = cap;
-    if (a.batched && threads < 256) threads = 256;  // the batched matvec keeps N/256 outputs per thread
+    if (a.batched && threads < 256) threads = 256;  // phase B splits the entries over the spare threads
     TTN_LAUNCH("k_small_solve", 0.0, 0.0, k_small_solve, dim3(1), dim3(threads), lds, st, a);
 }
 
