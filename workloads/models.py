@@ -334,7 +334,8 @@ def exciton_problem(seed: int = 3, n_states: int = 10, n_modes: int = 120, dmin:
 
 def heom_sbm_problem(K: int = 16, levels: int = 10, eps: float = 0.5, delta: float = 1.0,
                      lam: float = 0.2, gam: float = 1.0, T: float = 1.0, bonds=(10, 16, 24, 32, 48),
-                     dt: float = 0.0075, n_steps: int = 4000, name: str = "heom_sbm") -> Problem:
+                     dt: float = 0.0075, n_steps: int = 4000, rho0=None,
+                     name: str = "heom_sbm") -> Problem:
     """Free-pole HEOM of the spin-boson model in bosonic-operator form.
 
     Generator ``G`` with ``d/dt |rho) = -i G |rho)`` (Eq. for the HEOM in
@@ -346,6 +347,7 @@ def heom_sbm_problem(K: int = 16, levels: int = 10, eps: float = 0.5, delta: flo
     with ``L_s = H_s^L - H_s^R``, row-major vec so ``X^L = X (x) 1`` and
     ``X^R = 1 (x) X^T``.  The system leaf is the 4-dim Liouville space; the
     2K auxiliary modes (m_k, n~_k adjacent) form a balanced binary subtree.
+    ``rho0`` is the initial 2 x 2 system density matrix (default |up><up|).
     """
     beta = 1.0 / T
     alphas, nus = debye_matsubara(lam, gam, beta, K)
@@ -379,8 +381,9 @@ def heom_sbm_problem(K: int = 16, levels: int = 10, eps: float = 0.5, delta: flo
         add_term(p, -np.conj(a) / sa, [op(S, "SR", SR), op(t, "adag", bo["adag"])])
         add_term(p, sa, [op(S, "Sm", SL - SR), op(m, "a", bo["a"])])
         add_term(p, sa, [op(S, "Sm", SL - SR), op(t, "a", bo["a"])])
-    rho0 = np.array([[1, 0], [0, 0]], dtype=np.complex128)
-    p.init_vecs[S] = rho0.reshape(-1)
+    if rho0 is None:
+        rho0 = np.array([[1, 0], [0, 0]], dtype=np.complex128)
+    p.init_vecs[S] = np.asarray(rho0, dtype=np.complex128).reshape(-1)
     for k in range(n_aux):
         leaf = p.leaf_names[f"m{k // 2}" if k % 2 == 0 else f"t{k // 2}"]
         v = np.zeros(levels, dtype=np.complex128)
