@@ -207,4 +207,4 @@ def test_heom_arnoldi_parity(T, K, levels, bonds, n_steps, tol):
         g.step(p.dt)
         o.step(p.dt)
         assert np.abs(_heom_obs(g, p) - _heom_obs(o, p)).max() < tol
-    assert abs(_heom_obs(g, p)[1] - 1.0) < 1e-10
+    assert abs(_heom_obs(g, p)[1] - 1.0) < tol
