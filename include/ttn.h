@@ -53,8 +53,13 @@ typedef int32_t ttn_status;
 #define TTN_E_NOCONV (-6)  /* local exponential did not converge */
 #define TTN_E_STATE (-7)   /* call out of order (e.g. ttn_step before ttn_set_sop) */
 
-/* precision of the H_eff / environment contractions; QR, Krylov
- * orthogonalisation and the small projected exponential always run in FP64 */
+/* Precision of the H_eff / environment contractions.  TTN_FP32: the operator
+ * stages, group sums and environment contractions of the multi-kernel path run
+ * in complex FP32 with FP32 accumulation (the FP64 state is rounded when read,
+ * results are widened when written); node tensors, environments, QR gauge
+ * shifts, Krylov orthogonalisation and the small projected exponential stay
+ * FP64, and local problems of at most 1024 elements keep the fused FP64 solver.
+ * Observables are then accurate to the FP32 contractions (about 1e-6). */
 #define TTN_FP64 0
 #define TTN_FP32 1
 
@@ -69,7 +74,7 @@ typedef struct ttn_ctx *ttn_t;
 
 typedef struct {
     int32_t precision;   /* TTN_FP64 or TTN_FP32 */
-    double krylov_tol;   /* local exponential error target, relative (0 -> 1e-13) */
+    double krylov_tol;   /* local exponential error target, relative (0 -> 1e-13, FP32: 1e-10) */
     int32_t krylov_mmax; /* max Krylov dimension per solve (0 -> 40) */
     int32_t hermitian;   /* 1: Lanczos (G must be Hermitian), 0: Arnoldi */
     void *hip_stream;    /* hipStream_t for all work of the handle, NULL = null stream */

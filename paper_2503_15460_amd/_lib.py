@@ -171,7 +171,7 @@ def default_stream() -> Optional[int]:
 class TTN:
     """One tree tensor network on the GPU, driven through the C boundary."""
 
-    def __init__(self, parent, local_dim, bond_dim, precision: int = TTN_FP64, krylov_tol: float = 1e-13,
+    def __init__(self, parent, local_dim, bond_dim, precision: int = TTN_FP64, krylov_tol: float = 0.0,
                  krylov_mmax: int = 40, hermitian: bool = True, stream: Optional[int] = None, device: int = 0):
         self.parent = np.ascontiguousarray(parent, dtype=np.int32)
         self.local_dim = np.ascontiguousarray(local_dim, dtype=np.int32)

@@ -127,9 +127,11 @@ ProgView Engine::view(const Prog &p) const {
     v.tmp = tmp;
     v.gsum = gsum;
     v.cpart = cpart;
+    v.f32 = opt.precision == TTN_FP32 ? 1 : 0;
     for (int f = 0; f < MAXF; ++f) {
         v.sflops[f] = p.sflops[f];
-        v.sbytes[f] = p.sbytes[f];
+        // FP32 temporaries: stage 0 reads FP64 and writes FP32, later stages FP32 both ways
+        v.sbytes[f] = v.f32 ? p.sbytes[f] * (f == 0 ? 0.75 : 0.5) : p.sbytes[f];
     }
     return v;
 }
@@ -577,7 +579,7 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
     const bool fused = use_fused(p);
     solve_small[si] = fused ? 1 : 0;
     SolveStat *stat = d_stats + si;
-    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : 1e-13;
+    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP32 ? 1e-10 : 1e-13);
     if (fused) {
         SmallSolveArgs a{};
         a.g = p.g;
@@ -669,7 +671,7 @@ void Engine::sync_check(const char *where) {
 void Engine::step(double dt, int n_steps) {
     if (!have_sop || !have_state) throw Error(TTN_E_STATE, "ttn_step needs ttn_set_sop and a state");
     if (!std::isfinite(dt)) throw Error(TTN_E_INVALID, "dt must be finite");
-    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : 1e-13;
+    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP32 ? 1e-10 : 1e-13);
     for (int s = 0; s < n_steps; ++s) {
         if (snapshot) {
             int64_t off = 0;

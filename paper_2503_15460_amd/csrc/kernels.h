@@ -51,8 +51,9 @@ struct ProgView {
     int n_groups;
     double2 *const *gdst;     // contraction destination per group (env programs)
     int contract_slot;        // -1: none
-    double2 *tmp;             // 2 * n_ent * N
-    double2 *gsum;            // n_groups * N
+    int f32;                  // 1: stages, group sums and contractions in complex FP32
+    double2 *tmp;             // 2 * n_ent * N (float2 elements in the FP32 mode)
+    double2 *gsum;            // n_groups * N (float2 elements in the FP32 mode)
     double2 *cpart;           // contraction partials
     double sflops[MAXF];      // algorithmic flops / bytes of each stage launch (host side)
     double sbytes[MAXF];

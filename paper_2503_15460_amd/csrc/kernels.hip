@@ -38,6 +38,32 @@ __device__ __forceinline__ void cfmac(double2 &acc, double2 a, double2 b) {  // 
     acc.y = fma(a.x, b.y, acc.y);
     acc.y = fma(-a.y, b.x, acc.y);
 }
+// single-precision forms for the FP32 contraction mode
+__device__ __forceinline__ void cfma(float2 &acc, float2 a, float2 b) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void cfmac(float2 &acc, float2 a, float2 b) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(-a.y, b.x, acc.y);
+}
+// element conversions between the storage type of a buffer and the compute type
+template <typename T> __device__ __forceinline__ T cvt(double2 a);
+template <> __device__ __forceinline__ double2 cvt<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 cvt<float2>(double2 a) {
+    return make_float2((float)a.x, (float)a.y);
+}
+template <typename T> __device__ __forceinline__ T cvt(float2 a);
+template <> __device__ __forceinline__ double2 cvt<double2>(float2 a) { return make_double2(a.x, a.y); }
+template <> __device__ __forceinline__ float2 cvt<float2>(float2 a) { return a; }
+template <typename T> __device__ __forceinline__ T czero();
+template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ float2 czero<float2>() { return make_float2(0.0f, 0.0f); }
+
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
@@ -114,9 +140,11 @@ __device__ void blk_reduce_partials(const double *part, int nb, int stride, int 
 }
 
 // ============================================================ mode products
-// Y[l,i,r] = sum_j M[i,j] X[l,j,r] for one (L, n, R) geometry.
-__global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const double2 *__restrict__ in,
-                                                    int ldn) {
+// Y[l,i,r] = sum_j M[i,j] X[l,j,r] for one (L, n, R) geometry.  TS is the
+// element type read (the FP64 input at stage 0, the temporaries afterwards), T
+// the compute and temporary type (double2, or float2 in the FP32 mode).
+template <typename TS, typename T>
+__global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const TS *__restrict__ in, int ldn) {
     const int e = blockIdx.y;
     const DevEntry *E = p.ent + e;
     const int nf = E->nf;
@@ -126,47 +154,56 @@ __global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const
     const int n = p.g.dims[s];
     const uint32_t R = (uint32_t)p.g.R[s];
     const uint32_t N = (uint32_t)p.g.N;
-    const double2 *__restrict__ src = stage == 0 ? in : p.tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N;
-    double2 *__restrict__ dst = p.tmp + (2 * (int64_t)e + (stage & 1)) * N;
-    extern __shared__ double2 smt[];
+    T *tmp = reinterpret_cast<T *>(p.tmp);
+    const TS *__restrict__ src =
+        stage == 0 ? in : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
+    T *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
+    extern __shared__ double2 smt_raw[];
+    T *smt = reinterpret_cast<T *>(smt_raw);
     const bool lds = n <= ldn;  // LDS holds ldn*ldn elements
     if (lds) {
         for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
             int i = q / n, j = q - i * n;
-            smt[j * n + i] = M[q];
+            smt[j * n + i] = cvt<T>(M[q]);
         }
         __syncthreads();
     }
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
         uint32_t r = idx % R, t = idx / R;
         uint32_t i = t % n, l = t / n;
-        const double2 *xp = src + (size_t)l * n * R + r;
-        double2 acc = make_double2(0.0, 0.0);
+        const TS *xp = src + (size_t)l * n * R + r;
+        T acc = czero<T>();
         if (lds) {
-            for (int j = 0; j < n; ++j) cfma(acc, smt[j * n + i], xp[(size_t)j * R]);
+            for (int j = 0; j < n; ++j) cfma(acc, smt[j * n + i], cvt<T>(xp[(size_t)j * R]));
         } else {
             const double2 *mr = M + (size_t)i * n;
-            for (int j = 0; j < n; ++j) cfma(acc, mr[j], xp[(size_t)j * R]);
+            for (int j = 0; j < n; ++j) cfma(acc, cvt<T>(mr[j]), cvt<T>(xp[(size_t)j * R]));
         }
         dst[idx] = acc;
     }
 }
 
+// Coefficient-weighted sum of the entries of each group.  Entries without
+// factors read the FP64 input; the others read their last temporary (type T).
+// Output: out_single (FP64, one group) or the group sums p.gsum (type T).
+template <typename T>
 __global__ void __launch_bounds__(256) k_group_sum(ProgView p, const double2 *__restrict__ in,
                                                    double2 *out_single) {
     const int g = blockIdx.y;
     const uint32_t N = (uint32_t)p.g.N;
-    double2 *__restrict__ dst = out_single ? out_single : p.gsum + (size_t)g * N;
+    const T *tmp = reinterpret_cast<const T *>(p.tmp);
+    T *gs = reinterpret_cast<T *>(p.gsum) + (size_t)g * N;
     const int q0 = p.gptr[g], q1 = p.gptr[g + 1];
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
-        double2 acc = make_double2(0.0, 0.0);
+        T acc = czero<T>();
         for (int q = q0; q < q1; ++q) {
             const int e = p.gent[q];
             const int nf = p.ent[e].nf;
-            const double2 *src = nf == 0 ? in : p.tmp + (2 * (size_t)e + ((nf - 1) & 1)) * N;
-            cfma(acc, p.ent[e].coef, src[idx]);
+            const T v = nf == 0 ? cvt<T>(in[idx]) : tmp[(2 * (size_t)e + ((nf - 1) & 1)) * N + idx];
+            cfma(acc, cvt<T>(p.ent[e].coef), v);
         }
-        dst[idx] = acc;
+        if (out_single) out_single[idx] = cvt<double2>(acc);
+        else gs[idx] = acc;
     }
 }
 
@@ -193,35 +230,38 @@ __global__ void __launch_bounds__(256) k_mode_single(const double2 *__restrict__
 constexpr int CT_ROWS = 32;
 constexpr int CT_MAXOUT = 16;  // outputs per thread (nA*nB <= 256*16)
 
-__global__ void __launch_bounds__(256) k_contract_part(const double2 *__restrict__ A, const double2 *__restrict__ Bbase,
+// T is the compute type and the element type of B (the group sums in the FP32
+// mode); A is always FP64; partials are written in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) k_contract_part(const double2 *__restrict__ A, const T *__restrict__ Bbase,
                                                        int64_t bstride, uint32_t L, int nA, int nB, uint32_t R,
                                                        double2 *__restrict__ part) {
     const int g = blockIdx.y;
-    const double2 *__restrict__ B = Bbase + (size_t)g * bstride;
+    const T *__restrict__ B = Bbase + (size_t)g * bstride;
     const uint32_t rows = L * R;
     const uint32_t per = (rows + gridDim.x - 1) / gridDim.x;
     const uint32_t r0 = blockIdx.x * per, r1 = min(rows, r0 + per);
-    extern __shared__ double2 sct[];
-    double2 *As = sct;                 // CT_ROWS * nA
-    double2 *Bs = sct + CT_ROWS * nA;  // CT_ROWS * nB
+    extern __shared__ double2 sct_raw[];
+    T *As = reinterpret_cast<T *>(sct_raw);  // CT_ROWS * nA
+    T *Bs = As + CT_ROWS * nA;                // CT_ROWS * nB
     const int nout = nA * nB;
-    double2 acc[CT_MAXOUT];
-    for (int q = 0; q < CT_MAXOUT; ++q) acc[q] = make_double2(0.0, 0.0);
+    T acc[CT_MAXOUT];
+    for (int q = 0; q < CT_MAXOUT; ++q) acc[q] = czero<T>();
     for (uint32_t t0 = r0; t0 < r1; t0 += CT_ROWS) {
         const int tr = (int)min((uint32_t)CT_ROWS, r1 - t0);
         __syncthreads();
         for (int q = threadIdx.x; q < CT_ROWS * nA; q += blockDim.x) {
             int t = q % CT_ROWS, m = q / CT_ROWS;
-            double2 v = make_double2(0.0, 0.0);
+            T v = czero<T>();
             if (t < tr) {
                 uint32_t rho = t0 + t, l = rho / R, r = rho % R;
-                v = A[((size_t)l * nA + m) * R + r];
+                v = cvt<T>(A[((size_t)l * nA + m) * R + r]);
             }
             As[t * nA + m] = v;
         }
         for (int q = threadIdx.x; q < CT_ROWS * nB; q += blockDim.x) {
             int t = q % CT_ROWS, m = q / CT_ROWS;
-            double2 v = make_double2(0.0, 0.0);
+            T v = czero<T>();
             if (t < tr) {
                 uint32_t rho = t0 + t, l = rho / R, r = rho % R;
                 v = B[((size_t)l * nB + m) * R + r];
@@ -233,7 +273,7 @@ __global__ void __launch_bounds__(256) k_contract_part(const double2 *__restrict
             int o = threadIdx.x + q * blockDim.x;
             if (o >= nout) break;
             int m = o / nB, nn = o - m * nB;
-            double2 a = acc[q];
+            T a = acc[q];
             for (int t = 0; t < tr; ++t) cfmac(a, As[t * nA + m], Bs[t * nB + nn]);
             acc[q] = a;
         }
@@ -241,7 +281,7 @@ __global__ void __launch_bounds__(256) k_contract_part(const double2 *__restrict
     for (int q = 0; q < CT_MAXOUT; ++q) {
         int o = threadIdx.x + q * blockDim.x;
         if (o >= nout) break;
-        part[((size_t)g * gridDim.x + blockIdx.x) * nout + o] = acc[q];
+        part[((size_t)g * gridDim.x + blockIdx.x) * nout + o] = cvt<double2>(acc[q]);
     }
 }
 
@@ -1297,14 +1337,31 @@ void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st) {
     const size_t lds = sizeof(double2) * (size_t)ldn * ldn;
     for (int s = 0; s < p.max_nf; ++s) {
         dim3 grid(grid_for(p.g.N, 256), p.n_ent);
-        TTN_LAUNCH("k_mode_stage", p.sflops[s], p.sbytes[s], k_mode_stage, grid, dim3(256), lds, st, p, s, in, ldn);
+        if (p.f32) {
+            const size_t l32 = lds / 2;
+            if (s == 0)
+                TTN_LAUNCH("k_mode_stage_f32", p.sflops[s], p.sbytes[s], (k_mode_stage<double2, float2>), grid,
+                           dim3(256), l32, st, p, s, in, ldn);
+            else
+                TTN_LAUNCH("k_mode_stage_f32", p.sflops[s], p.sbytes[s], (k_mode_stage<float2, float2>), grid,
+                           dim3(256), l32, st, p, s, (const float2 *)nullptr, ldn);
+        } else {
+            TTN_LAUNCH("k_mode_stage", p.sflops[s], p.sbytes[s], (k_mode_stage<double2, double2>), grid, dim3(256),
+                       lds, st, p, s, in, ldn);
+        }
     }
 }
 
 void launch_prog_sum(const ProgView &p, const double2 *in, double2 *out_single, hipStream_t st) {
     dim3 grid(grid_for(p.g.N, 256), out_single ? 1 : p.n_groups);
-    TTN_LAUNCH("k_group_sum", 8.0 * p.g.N * p.n_ent, 16.0 * p.g.N * (p.n_ent + (out_single ? 1 : p.n_groups)),
-               k_group_sum, grid, dim3(256), 0, st, p, in, out_single);
+    const double es = p.f32 ? 8.0 : 16.0;
+    const double by = es * p.g.N * p.n_ent + (out_single ? 16.0 : es * p.n_groups) * p.g.N;
+    if (p.f32)
+        TTN_LAUNCH("k_group_sum_f32", 8.0 * p.g.N * p.n_ent, by, k_group_sum<float2>, grid, dim3(256), 0, st, p, in,
+                   out_single);
+    else
+        TTN_LAUNCH("k_group_sum", 8.0 * p.g.N * p.n_ent, by, k_group_sum<double2>, grid, dim3(256), 0, st, p, in,
+                   out_single);
 }
 
 void launch_prog_contract(const ProgView &p, const double2 *A, hipStream_t st) {
@@ -1313,8 +1370,14 @@ void launch_prog_contract(const ProgView &p, const double2 *A, hipStream_t st) {
     const uint32_t L = (uint32_t)p.g.L[s], R = (uint32_t)p.g.R[s];
     const int nb = contract_blocks(L * R);
     const size_t lds = sizeof(double2) * (size_t)CT_ROWS * 2 * n;
-    TTN_LAUNCH("k_contract_part", 8.0 * p.g.N * n * p.n_groups, 16.0 * p.g.N * (1 + p.n_groups), k_contract_part,
-               dim3(nb, p.n_groups), dim3(256), lds, st, A, (const double2 *)p.gsum, p.g.N, L, n, n, R, p.cpart);
+    if (p.f32)
+        TTN_LAUNCH("k_contract_part_f32", 8.0 * p.g.N * n * p.n_groups, 16.0 * p.g.N + 8.0 * p.g.N * p.n_groups,
+                   k_contract_part<float2>, dim3(nb, p.n_groups), dim3(256), lds / 2, st, A,
+                   (const float2 *)p.gsum, p.g.N, L, n, n, R, p.cpart);
+    else
+        TTN_LAUNCH("k_contract_part", 8.0 * p.g.N * n * p.n_groups, 16.0 * p.g.N * (1 + p.n_groups),
+                   k_contract_part<double2>, dim3(nb, p.n_groups), dim3(256), lds, st, A, (const double2 *)p.gsum,
+                   p.g.N, L, n, n, R, p.cpart);
     TTN_LAUNCH("k_contract_reduce", 2.0 * nb * n * n * p.n_groups, 16.0 * nb * n * n * p.n_groups, k_contract_reduce,
                dim3(grid_for(n * n, 256), p.n_groups), dim3(256), 0, st, (const double2 *)p.cpart, nb, n * n, p.gdst,
                (double2 *)nullptr);
@@ -1331,7 +1394,7 @@ void launch_contract(const double2 *A, const double2 *B, double2 *out, int64_t L
                      double2 *part, hipStream_t st) {
     const int nb = contract_blocks((uint32_t)(L * R));
     const size_t lds = sizeof(double2) * (size_t)CT_ROWS * (nA + nB);
-    TTN_LAUNCH("k_contract_part", 8.0 * L * R * nA * nB, 16.0 * L * R * (nA + nB), k_contract_part, dim3(nb, 1),
+    TTN_LAUNCH("k_contract_part", 8.0 * L * R * nA * nB, 16.0 * L * R * (nA + nB), k_contract_part<double2>, dim3(nb, 1),
                dim3(256), lds, st, A, B, (int64_t)0, (uint32_t)L, nA, nB, (uint32_t)R, part);
     TTN_LAUNCH("k_contract_reduce", 2.0 * nb * nA * nB, 16.0 * nb * nA * nB, k_contract_reduce,
                dim3(grid_for(nA * nB, 256), 1), dim3(256), 0, st, (const double2 *)part, nb, nA * nB,

@@ -347,6 +347,16 @@ def test_jitter_floor_spin_boson():
     assert np.abs(a - b).max() < 1e-12
 
 
+def test_fp32_noise_floor_vibronic_product_state():
+    """FP32-size noise (1e-7 relative) before every QR moves the product-state
+    vibronic run by ~3e-3: the floor of any FP32-contraction run from this start."""
+    p = vibronic_problem(n_modes=8, dmin=4, dmax=6, leaf_bond=4, l_bond=6, m_bond=8, dt=0.5)
+    a = _noisy_traj(p, 0.0, 6, "P1")
+    b = _noisy_traj(p, 1e-7, 6, "P1")
+    J32 = np.abs(a - b).max()
+    assert 1e-3 < J32 < 1e-2
+
+
 def test_jitter_floor_vibronic_product_state():
     """Product-state vibronic runs are sensitive to rounding through the small
     singular values of the first steps; the measured floor J bounds parity."""
