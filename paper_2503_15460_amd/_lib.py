@@ -49,6 +49,12 @@ class TTNError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
+    # SONAME as the system one the library links), and stream handles cross the
+    # boundary.  Loading torch first makes the dynamic loader bind the library
+    # to torch's runtime; loaded the other way round, two runtimes coexist and
+    # the library's one does not see the device.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     i32p, i64p, dp = C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)

@@ -53,6 +53,7 @@ private:
     double2 *state_mem = nullptr;
     // environments and programs (allocated by set_sop)
     std::vector<double2 *> spo, mf, U;
+    std::vector<std::vector<int>> ulo, uhi;  // band of each leaf channel operator
     std::vector<Prog> heffP, spoP, bondP;
     std::vector<std::vector<Prog>> mfP;
     std::vector<void *> sop_allocs;

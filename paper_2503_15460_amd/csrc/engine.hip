@@ -66,6 +66,12 @@ void *Engine::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) throw Error(TTN_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    // recycled device memory holds stale values: every buffer starts at zero
+    e = hipMemset(p, 0, bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        throw Error(TTN_E_DEVICE, std::string("hipMemset failed: ") + hipGetErrorString(e));
+    }
     sop_allocs.push_back(p);
     counters[5] += (int64_t)bytes;
     return p;
@@ -136,6 +142,13 @@ ProgView Engine::view(const Prog &p) const {
     return v;
 }
 
+// An entry with every factor band unset (finish_groups makes unset bands dense).
+static DevEntry blank_entry() {
+    DevEntry de{};
+    for (int f = 0; f < MAXF; ++f) de.lo[f] = de.hi[f] = -1;
+    return de;
+}
+
 // Finalise group tables of a program from the per-entry group ids.
 static void finish_groups(Prog &p, const std::vector<double2 *> &dst_by_group) {
     p.n_groups = (int)dst_by_group.size();
@@ -153,9 +166,13 @@ static void finish_groups(Prog &p, const std::vector<double2 *> &dst_by_group) {
         p.max_nf = std::max(p.max_nf, e.nf);
         for (int f = 0; f < e.nf; ++f) {
             const int n = p.g.dims[e.slot[f]];
-            p.flops += 8 * p.g.N * n;
-            p.sflops[f] += 8.0 * p.g.N * n;
-            p.sbytes[f] += 16.0 * (2.0 * p.g.N + (double)n * n);
+            if (e.lo[f] < 0 || e.lo[f] > n - 1) e.lo[f] = n - 1;  // unset: dense
+            if (e.hi[f] < 0 || e.hi[f] > n - 1) e.hi[f] = n - 1;
+            // algorithmic work of a banded factor: the band only
+            const int w = std::min(n, e.lo[f] + e.hi[f] + 1);
+            p.flops += 8 * p.g.N * w;
+            p.sflops[f] += 8.0 * p.g.N * w;
+            p.sbytes[f] += 16.0 * (2.0 * p.g.N + (double)n * w);
         }
     }
 }
@@ -175,6 +192,13 @@ void Engine::build_programs() {
         int nc = t.bond[c];
         return spo[c] + (size_t)ch * nc * nc;
     };
+    // band of a child factor (leaf operators may be banded; SPOs are dense)
+    auto child_band = [&](DevEntry &de, int f, int z, int ch) {
+        if (t.local_dim[z] > 0 && ch < (int)ulo[z].size()) {
+            de.lo[f] = ulo[z][ch];
+            de.hi[f] = uhi[z][ch];
+        }
+    };
     auto parent_M = [&](int z, int ch) -> const double2 * {
         int np = t.bond[z];
         return mf[z] + (size_t)ch * np * np;
@@ -190,12 +214,13 @@ void Engine::build_programs() {
         Prog &h = heffP[z];
         h.g = geom_of(t.dims[z]);
         for (auto &e : ents) {
-            DevEntry de{};
+            DevEntry de = blank_entry();
             de.coef = to_d2(e.coef);
             int nf = 0;
             for (int k = 0; k < nk; ++k)
                 if (e.slot[k] >= 1) {
                     de.slot[nf] = k;
+                    child_band(de, nf, z, e.slot[k]);
                     de.M[nf++] = child_M(z, k, e.slot[k]);
                 }
             if (!root && e.bp != 1) {
@@ -222,12 +247,13 @@ void Engine::build_programs() {
                     gid[e.bp] = (int)dst.size();
                     dst.push_back(spo[z] + (size_t)e.bp * np * np);
                 }
-                DevEntry de{};
+                DevEntry de = blank_entry();
                 de.coef = to_d2(e.coef);
                 int nf = 0;
                 for (int k = 0; k < nk; ++k)
                     if (e.slot[k] >= 1) {
                         de.slot[nf] = k;
+                        child_band(de, nf, z, e.slot[k]);
                         de.M[nf++] = child_M(z, k, e.slot[k]);
                     }
                 de.nf = nf;
@@ -241,7 +267,7 @@ void Engine::build_programs() {
             b.g = geom_of({np, np});
             const double2 *Sb = spo[z], *Mb = mf[z];
             if (op.outside_used[z]) {
-                DevEntry de{};
+                DevEntry de = blank_entry();
                 de.coef = make_double2(1.0, 0.0);
                 de.nf = 1;
                 de.slot[0] = 1;
@@ -249,7 +275,7 @@ void Engine::build_programs() {
                 b.ents.push_back(de);
             }
             if (op.inside_used[z]) {
-                DevEntry de{};
+                DevEntry de = blank_entry();
                 de.coef = make_double2(1.0, 0.0);
                 de.nf = 1;
                 de.slot[0] = 0;
@@ -257,7 +283,7 @@ void Engine::build_programs() {
                 b.ents.push_back(de);
             }
             for (int ch = 2; ch < op.n_ch[z]; ++ch) {
-                DevEntry de{};
+                DevEntry de = blank_entry();
                 de.coef = make_double2(1.0, 0.0);
                 de.nf = 2;
                 de.slot[0] = 0;
@@ -294,12 +320,13 @@ void Engine::build_programs() {
                         gid[ch] = (int)dst.size();
                         dst.push_back(mf[c] + (size_t)ch * nc * nc);
                     }
-                    DevEntry de{};
+                    DevEntry de = blank_entry();
                     de.coef = to_d2(e.coef);
                     int nf = 0;
                     for (int j = 0; j < nk; ++j)
                         if (j != k && e.slot[j] >= 1) {
                             de.slot[nf] = j;
+                            child_band(de, nf, z, e.slot[j]);
                             de.M[nf++] = child_M(z, j, e.slot[j]);
                         }
                     if (!root && e.bp != 1) {
@@ -330,6 +357,8 @@ void Engine::set_sop(const SopInput &s) {
     spo.assign(n, nullptr);
     mf.assign(n, nullptr);
     U.assign(n, nullptr);
+    ulo.assign(n, {});
+    uhi.assign(n, {});
     for (int c = 0; c < n; ++c) {
         if (c == t.root) continue;
         const size_t nb = t.bond[c];
@@ -346,6 +375,22 @@ void Engine::set_sop(const SopInput &s) {
                 if (ch < (int)op.leafU[li].size())
                     for (size_t q = 0; q < op.leafU[li][ch].size(); ++q)
                         hu[(size_t)ch * d * d + q] = to_d2(op.leafU[li][ch][q]);
+            // band of every channel operator (exact zeros outside i - lo <= j <= i + hi)
+            ulo[c].assign(op.n_ch[c], d - 1);
+            uhi[c].assign(op.n_ch[c], d - 1);
+            for (int ch = 1; ch < op.n_ch[c]; ++ch) {
+                int lo = 0, hi = 0;
+                for (int i = 0; i < d; ++i)
+                    for (int j = 0; j < d; ++j) {
+                        const double2 v = hu[(size_t)ch * d * d + (size_t)i * d + j];
+                        if (v.x != 0.0 || v.y != 0.0) {
+                            lo = std::max(lo, i - j);
+                            hi = std::max(hi, j - i);
+                        }
+                    }
+                ulo[c][ch] = lo;
+                uhi[c][ch] = hi;
+            }
             U[c] = (double2 *)dalloc(sizeof(double2) * hu.size());
             HIPCHK(hipMemcpy(U[c], hu.data(), sizeof(double2) * hu.size(), hipMemcpyHostToDevice));
         }
@@ -693,7 +738,16 @@ void Engine::step(double dt, int n_steps) {
             for (int i = 0; i < solve_idx; ++i) {
                 const SolveStat &q = h_stats[i];
                 if (solve_small[i]) {
-                    if (q.fail) throw Error(TTN_E_NOCONV, "local exponential did not converge (small path)");
+                    if (q.fail) {
+                        char msg[256];
+                        const int zn = solve_node[i];
+                        const int64_t Nn = solve_fwd[i] ? t.size[zn] : (int64_t)t.bond[zn] * t.bond[zn];
+                        snprintf(msg, sizeof msg,
+                                 "local exponential did not converge (fused solver; %s solve %d at node %d, "
+                                 "N=%lld, m=%d, matvecs=%d, err=%.3g)",
+                                 solve_fwd[i] ? "forward" : "backward", i, zn, (long long)Nn, q.m, q.matvecs, q.err);
+                        throw Error(TTN_E_NOCONV, msg);
+                    }
                     m_hint[i] = q.m;
                 } else {
                     if (q.fail) {

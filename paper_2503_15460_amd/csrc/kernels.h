@@ -31,11 +31,16 @@ struct Geom {
 };
 
 // One operator entry: coef * (x)_f M_f applied on slots slot[f] (ascending).
+// Factor f is banded: M[i][j] == 0 unless i - lo[f] <= j <= i + hi[f] (dense
+// factors carry lo = hi = n - 1).  Leaf operators in a number basis (ladder,
+// position, number operators and their sums) are detected as banded.
 struct DevEntry {
     double2 coef;
     int nf;
     int group;
     int slot[MAXF];
+    int lo[MAXF];
+    int hi[MAXF];
     const double2 *M[MAXF];
 };
 

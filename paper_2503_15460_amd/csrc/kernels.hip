@@ -158,6 +158,7 @@ __global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const
     const TS *__restrict__ src =
         stage == 0 ? in : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
     T *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
+    const int blo = E->lo[stage], bhi = E->hi[stage];
     extern __shared__ double2 smt_raw[];
     T *smt = reinterpret_cast<T *>(smt_raw);
     const bool lds = n <= ldn;  // LDS holds ldn*ldn elements
@@ -173,11 +174,12 @@ __global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const
         uint32_t i = t % n, l = t / n;
         const TS *xp = src + (size_t)l * n * R + r;
         T acc = czero<T>();
+        const int j0 = max(0, (int)i - blo), j1 = min(n - 1, (int)i + bhi);
         if (lds) {
-            for (int j = 0; j < n; ++j) cfma(acc, smt[j * n + i], cvt<T>(xp[(size_t)j * R]));
+            for (int j = j0; j <= j1; ++j) cfma(acc, smt[j * n + i], cvt<T>(xp[(size_t)j * R]));
         } else {
             const double2 *mr = M + (size_t)i * n;
-            for (int j = 0; j < n; ++j) cfma(acc, cvt<T>(mr[j]), cvt<T>(xp[(size_t)j * R]));
+            for (int j = j0; j <= j1; ++j) cfma(acc, cvt<T>(mr[j]), cvt<T>(xp[(size_t)j * R]));
         }
         dst[idx] = acc;
     }
@@ -767,7 +769,8 @@ struct SmallLds {
     int *tix;  // per entry: index of its slot-1 temporary, -1 if none
 };
 
-__device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M, const Geom &g, int s) {
+__device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M, const Geom &g, int s, int blo,
+                             int bhi) {
     const int n = g.dims[s];
     const uint32_t R = (uint32_t)g.R[s], N = (uint32_t)g.N;
     for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) {
@@ -776,7 +779,8 @@ __device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M,
         const double2 *xp = src + (size_t)l * n * R + r;
         const double2 *mr = M + (size_t)i * n;
         double2 acc = make_double2(0.0, 0.0);
-        for (int j = 0; j < n; ++j) cfma(acc, mr[j], xp[(size_t)j * R]);
+        const int j0 = max(0, (int)i - blo), j1 = min(n - 1, (int)i + bhi);
+        for (int j = j0; j <= j1; ++j) cfma(acc, mr[j], xp[(size_t)j * R]);
         dst[idx] = acc;
     }
 }
@@ -792,7 +796,7 @@ __device__ void blk_matvec_seq(const SmallSolveArgs &a, const double2 *v, double
         for (int f = 0; f < nf; ++f) {
             double2 *dst = (f & 1) ? t2 : t1;
             __syncthreads();
-            blk_mode_lds(cur, dst, E->M[f], a.g, E->slot[f]);
+            blk_mode_lds(cur, dst, E->M[f], a.g, E->slot[f], E->lo[f], E->hi[f]);
             cur = dst;
         }
         __syncthreads();
@@ -813,12 +817,14 @@ __device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double
     for (uint32_t q = threadIdx.x; q < (uint32_t)na * N; q += blockDim.x) {
         const uint32_t k = q / N, el = q - k * N;
         const DevEntry *E = a.ent + e1[k];
-        const double2 *M1 = E->M[E->nf - 1];
+        const int f1 = E->nf - 1;
+        const double2 *M1 = E->M[f1];
         const uint32_t ai = el / n1, p = el - ai * n1;
         const double2 *xr = v + (size_t)ai * n1;
         const double2 *mr = M1 + (size_t)p * n1;
         double2 acc = make_double2(0.0, 0.0);
-        for (int j = 0; j < n1; ++j) cfma(acc, mr[j], xr[j]);
+        const int j0 = max(0, (int)p - E->lo[f1]), j1 = min(n1 - 1, (int)p + E->hi[f1]);
+        for (int j = j0; j <= j1; ++j) cfma(acc, mr[j], xr[j]);
         T[q] = acc;
     }
     __syncthreads();
@@ -841,7 +847,8 @@ __device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double
                 double2 r = make_double2(0.0, 0.0);
                 if (has0) {
                     const double2 *mr = E->M[0] + (size_t)i * n0;
-                    for (int j = 0; j < n0; ++j) cfma(r, mr[j], S[(size_t)j * n1 + p]);
+                    const int j0 = max(0, (int)i - E->lo[0]), j1 = min(n0 - 1, (int)i + E->hi[0]);
+                    for (int j = j0; j <= j1; ++j) cfma(r, mr[j], S[(size_t)j * n1 + p]);
                 } else {
                     r = S[idx];
                 }
@@ -1194,7 +1201,8 @@ __global__ void __launch_bounds__(1024) k_kry_expm(BigKrylov k, int m, int mmax,
                 else if (c == r + 1) h = k.Hm[(size_t)r * (mmax + 1) + c];
                 else h = make_double2(0.0, 0.0);
             } else {
-                h = col[r];
+                // upper Hessenberg: entries below the subdiagonal are never written
+                h = r <= c + 1 ? col[r] : make_double2(0.0, 0.0);
             }
             Hs[q] = h;
         }
