@@ -20,6 +20,8 @@ struct Prog {
     int n_groups = 0, max_nf = 0, contract_slot = -1;
     int64_t flops = 0;  // algorithmic flops of one application (8 per complex MAC)
     double sflops[MAXF] = {0}, sbytes[MAXF] = {0};  // per stage launch
+    int snmin[MAXF] = {0}, snmax[MAXF] = {0};        // factor dims at each stage
+    int stile[MAXF] = {0};                           // 1: every factor of the stage is dense, n <= 64
     DevEntry *d_ent = nullptr;
     int *d_gptr = nullptr, *d_gent = nullptr;
     double2 **d_gdst = nullptr;

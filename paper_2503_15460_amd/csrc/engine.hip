@@ -138,6 +138,9 @@ ProgView Engine::view(const Prog &p) const {
         v.sflops[f] = p.sflops[f];
         // FP32 temporaries: stage 0 reads FP64 and writes FP32, later stages FP32 both ways
         v.sbytes[f] = v.f32 ? p.sbytes[f] * (f == 0 ? 0.75 : 0.5) : p.sbytes[f];
+        v.snmin[f] = p.snmin[f];
+        v.snmax[f] = p.snmax[f];
+        v.stile[f] = p.stile[f];
     }
     return v;
 }
@@ -161,13 +164,21 @@ static void finish_groups(Prog &p, const std::vector<double2 *> &dst_by_group) {
     for (size_t e = 0; e < p.ents.size(); ++e) p.gent[fill[p.ents[e].group]++] = (int)e;
     p.max_nf = 0;
     p.flops = 0;
-    for (int f = 0; f < MAXF; ++f) p.sflops[f] = p.sbytes[f] = 0.0;
+    for (int f = 0; f < MAXF; ++f) {
+        p.sflops[f] = p.sbytes[f] = 0.0;
+        p.snmin[f] = 1 << 30;
+        p.snmax[f] = 0;
+        p.stile[f] = 1;
+    }
     for (auto &e : p.ents) {
         p.max_nf = std::max(p.max_nf, e.nf);
         for (int f = 0; f < e.nf; ++f) {
             const int n = p.g.dims[e.slot[f]];
+            p.snmin[f] = std::min(p.snmin[f], n);
+            p.snmax[f] = std::max(p.snmax[f], n);
             if (e.lo[f] < 0 || e.lo[f] > n - 1) e.lo[f] = n - 1;  // unset: dense
             if (e.hi[f] < 0 || e.hi[f] > n - 1) e.hi[f] = n - 1;
+            if (n > 64 || e.lo[f] < n - 1 || e.hi[f] < n - 1) p.stile[f] = 0;
             // algorithmic work of a banded factor: the band only
             const int w = std::min(n, e.lo[f] + e.hi[f] + 1);
             p.flops += 8 * p.g.N * w;

@@ -62,6 +62,8 @@ struct ProgView {
     double2 *cpart;           // contraction partials
     double sflops[MAXF];      // algorithmic flops / bytes of each stage launch (host side)
     double sbytes[MAXF];
+    int snmin[MAXF], snmax[MAXF];  // smallest / largest factor dimension of each stage
+    int stile[MAXF];               // stage runs on the tiled kernel (dense factors, n <= 64)
 };
 
 // Statistics written by one Krylov solve.

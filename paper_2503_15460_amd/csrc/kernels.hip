@@ -185,6 +185,98 @@ __global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const
     }
 }
 
+// Tiled mode product for stages whose factors are all dense with n <= 64.
+// A work-group computes all rows i (padded to NP = RG * TI) of CW = CG * TC
+// columns c = l * R + r, with the contraction index j staged through LDS in
+// chunks of KC together with the matching columns of M.  Thread (cg, rg) keeps
+// a TI x TC register block: rows rg + RG * a, columns cg + CG * b, so that each
+// LDS value feeds TI or TC complex FMAs.
+constexpr int MT_KC = 16;
+
+template <typename TS, typename T, int TI, int RG>
+__global__ void __launch_bounds__(256) k_mode_tile(ProgView p, int stage, const TS *__restrict__ in) {
+    constexpr int CG = 256 / RG;
+    constexpr int TC = 4;
+    constexpr int CW = CG * TC;
+    constexpr int NP = RG * TI;
+    constexpr int KC = MT_KC;
+    const int e = blockIdx.y;
+    const DevEntry *E = p.ent + e;
+    if (E->nf <= stage) return;
+    const int s = E->slot[stage];
+    const int n = p.g.dims[s];
+    const uint32_t R = (uint32_t)p.g.R[s];
+    const uint32_t N = (uint32_t)p.g.N;
+    const uint32_t ncol = N / (uint32_t)n;
+    const uint32_t c0 = blockIdx.x * (uint32_t)CW;
+    if (c0 >= ncol) return;
+    const double2 *__restrict__ M = E->M[stage];
+    T *tmp = reinterpret_cast<T *>(p.tmp);
+    const TS *__restrict__ src =
+        stage == 0 ? in : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
+    T *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
+    __shared__ T Ms[KC * NP];  // Ms[k * NP + i] = M[i][j0 + k]
+    __shared__ T Xs[KC * CW];  // Xs[k * CW + cc] = X[j0 + k] of column c0 + cc
+    const int tid = threadIdx.x;
+    const int cg = tid % CG, rg = tid / CG;
+    T acc[TI][TC];
+#pragma unroll
+    for (int a = 0; a < TI; ++a)
+#pragma unroll
+        for (int b = 0; b < TC; ++b) acc[a][b] = czero<T>();
+    const uint32_t nR = (uint32_t)n * R;
+    for (int j0 = 0; j0 < n; j0 += KC) {
+        __syncthreads();
+        for (int q = tid; q < KC * NP; q += 256) {
+            const int k = q / NP, i = q - k * NP;
+            Ms[q] = (i < n && j0 + k < n) ? cvt<T>(M[(size_t)i * n + j0 + k]) : czero<T>();
+        }
+        if (R == 1) {  // columns are rows of a row-major (ncol, n) matrix: j fastest
+            for (int q = tid; q < KC * CW; q += 256) {
+                const int k = q % KC, cc = q / KC;
+                const uint32_t c = c0 + cc;
+                Xs[k * CW + cc] = (c < ncol && j0 + k < n) ? cvt<T>(src[(size_t)c * n + j0 + k]) : czero<T>();
+            }
+        } else {
+            for (int q = tid; q < KC * CW; q += 256) {
+                const int k = q / CW, cc = q - k * CW;
+                const uint32_t c = c0 + cc;
+                T v = czero<T>();
+                if (c < ncol && j0 + k < n) {
+                    const uint32_t l = c / R, r = c - l * R;
+                    v = cvt<T>(src[(size_t)l * nR + (size_t)(j0 + k) * R + r]);
+                }
+                Xs[q] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < KC; ++k) {
+            T av[TI], bv[TC];
+#pragma unroll
+            for (int a = 0; a < TI; ++a) av[a] = Ms[k * NP + rg + RG * a];
+#pragma unroll
+            for (int b = 0; b < TC; ++b) bv[b] = Xs[k * CW + cg + CG * b];
+#pragma unroll
+            for (int a = 0; a < TI; ++a)
+#pragma unroll
+                for (int b = 0; b < TC; ++b) cfma(acc[a][b], av[a], bv[b]);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < TC; ++b) {
+        const uint32_t c = c0 + cg + CG * b;
+        if (c >= ncol) continue;
+        const uint32_t l = c / R, r = c - l * R;
+        T *yp = dst + (size_t)l * nR + r;
+#pragma unroll
+        for (int a = 0; a < TI; ++a) {
+            const int i = rg + RG * a;
+            if (i < n) yp[(size_t)i * R] = acc[a][b];
+        }
+    }
+}
+
 // Coefficient-weighted sum of the entries of each group.  Entries without
 // factors read the FP64 input; the others read their last temporary (type T).
 // Output: out_single (FP64, one group) or the group sums p.gsum (type T).
@@ -1337,6 +1429,31 @@ static inline unsigned grid_for(int64_t n, int threads, int cap = 2048) {
     return (unsigned)b;
 }
 
+// tiled stage: the row padding NP = RG * TI is chosen from the stage's largest factor
+template <typename TS, typename T>
+static void launch_mode_tile_t(const ProgView &p, int s, const TS *in, hipStream_t st, const char *name) {
+    const int nmax = p.snmax[s];
+    const uint32_t maxcol = (uint32_t)(p.g.N / p.snmin[s]);
+    auto go = [&](auto kern, int cw) {
+        dim3 grid((maxcol + cw - 1) / cw, p.n_ent);
+        TTN_LAUNCH(name, p.sflops[s], p.sbytes[s], kern, grid, dim3(256), 0, st, p, s, in);
+    };
+    if (nmax <= 8) go(k_mode_tile<TS, T, 1, 8>, 128);
+    else if (nmax <= 16) go(k_mode_tile<TS, T, 1, 16>, 64);
+    else if (nmax <= 32) go(k_mode_tile<TS, T, 2, 16>, 64);
+    else if (nmax <= 48) go(k_mode_tile<TS, T, 3, 16>, 64);
+    else go(k_mode_tile<TS, T, 4, 16>, 64);
+}
+
+static void launch_mode_tile(const ProgView &p, int s, const double2 *in, hipStream_t st) {
+    if (p.f32) {
+        if (s == 0) launch_mode_tile_t<double2, float2>(p, s, in, st, "k_mode_tile_f32");
+        else launch_mode_tile_t<float2, float2>(p, s, (const float2 *)nullptr, st, "k_mode_tile_f32");
+    } else {
+        launch_mode_tile_t<double2, double2>(p, s, in, st, "k_mode_tile");
+    }
+}
+
 void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st) {
     if (p.n_ent == 0) return;
     int maxn = 0;
@@ -1344,6 +1461,10 @@ void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st) {
     const int ldn = maxn <= 64 ? maxn : 0;
     const size_t lds = sizeof(double2) * (size_t)ldn * ldn;
     for (int s = 0; s < p.max_nf; ++s) {
+        if (p.stile[s]) {
+            launch_mode_tile(p, s, in, st);
+            continue;
+        }
         dim3 grid(grid_for(p.g.N, 256), p.n_ent);
         if (p.f32) {
             const size_t l32 = lds / 2;
