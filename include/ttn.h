@@ -71,6 +71,7 @@ typedef int32_t ttn_status;
 #define TTN_OBS_BILINEAR 4    /* (b|Psi) = sum_x b_x Psi_x, b a product vector (no conj.) */
 
 typedef struct ttn_ctx *ttn_t;
+typedef struct ttn_batch_ctx *ttn_batch_t;
 
 typedef struct {
     int32_t precision;   /* TTN_FP64 or TTN_FP32 */
@@ -83,7 +84,8 @@ typedef struct {
     uint64_t seed;       /* reserved */
 } ttn_options;
 
-/* Fill *opt with the defaults (FP64, tol 1e-13, mmax 40, Hermitian). */
+/* Fill *opt with the defaults (FP64, tol 0 = the precision's default, mmax 40,
+ * Hermitian). */
 void ttn_default_options(ttn_options *opt);
 
 /* Create a tree tensor network.
@@ -185,6 +187,31 @@ typedef struct {
 } ttn_kernel_stat;
 ttn_status ttn_profile_begin(void);
 ttn_status ttn_profile_end(ttn_kernel_stat *rows, int32_t max_rows, int32_t *n_rows);
+
+/* Batches: many independent instances (trajectories, parameter sweeps, uneven
+ * trees and bond dimensions) advanced together.  Each instance keeps its own
+ * tensors, operator and Krylov hints; the batch gives the instances
+ * n_streams HIP streams (round robin; <= 0 -> 8, at most one per instance,
+ * default priority), enqueues one step of every instance before waiting for
+ * any, so that their sweeps overlap on the device.  Results are those of
+ * ttn_step on each instance alone.
+ *   ttn_batch_create: insts[n] are created handles (same device, each in at
+ *     most one batch, not repeated); while in the batch an instance runs on a
+ *     batch stream, ttn_batch_destroy gives it back its own.  The handles stay
+ *     owned by the caller; destroying one removes it from its batch.
+ *     Errors: TTN_E_INVALID, TTN_E_DEVICE.
+ *   ttn_batch_step: n_steps steps; dt[i] is instance i's step (insertion
+ *     order).  Every instance needs an operator and a state.  On an error the
+ *     instances have completed different numbers of steps; the failing
+ *     instance is named by ttn_batch_last_error and keeps the state of
+ *     ttn_step's error behaviour.  Errors: those of ttn_step.
+ *   ttn_batch_last_error: message of the last failed batch call (NULL batch:
+ *     last error of this thread), owned by the library.
+ */
+ttn_status ttn_batch_create(int32_t n, ttn_t const *insts, int32_t n_streams, ttn_batch_t *out);
+ttn_status ttn_batch_step(ttn_batch_t b, const double *dt, int32_t n_steps);
+const char *ttn_batch_last_error(ttn_batch_t b);
+void ttn_batch_destroy(ttn_batch_t b);
 
 /* Per-handle message of the last error (NULL handle: last error of this
  * thread).  The string is owned by the library. */

@@ -26,7 +26,8 @@ OBS_EXPECT, OBS_NORM, OBS_ENERGY, OBS_OVERLAP_T0, OBS_BILINEAR = 0, 1, 2, 3, 4
 EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product_state", "ttn_step",
             "ttn_observe", "ttn_apply_root_heff", "ttn_get_info", "ttn_state_size", "ttn_get_state",
             "ttn_set_state", "ttn_last_error", "ttn_destroy", "ttn_debug_dense_tree_operator",
-            "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end"]
+            "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end",
+            "ttn_batch_create", "ttn_batch_step", "ttn_batch_last_error", "ttn_batch_destroy"]
 
 
 class Options(C.Structure):
@@ -78,6 +79,10 @@ def _load():
         "ttn_debug_qr": (C.c_int32, [C.c_int64, C.c_int32, dp, C.c_int32, dp, dp]),
         "ttn_profile_begin": (C.c_int32, []),
         "ttn_profile_end": (C.c_int32, [C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
+        "ttn_batch_create": (C.c_int32, [C.c_int32, C.POINTER(P), C.c_int32, C.POINTER(P)]),
+        "ttn_batch_step": (C.c_int32, [P, dp, C.c_int32]),
+        "ttn_batch_last_error": (C.c_char_p, [P]),
+        "ttn_batch_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -298,3 +303,33 @@ class TTN:
         flat = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.complex128).reshape(-1)
                                                     for t in tensors]))
         self._c(lib.ttn_set_state(self.h, _ptr(flat.view(np.float64), C.c_double), flat.nbytes))
+
+
+class TTNBatch:
+    """Instances advanced together (``ttn_batch_*``): their sweeps overlap on
+    the device through the batch's HIP streams.  The TTN objects stay usable
+    (observables, states) and must outlive the batch."""
+
+    def __init__(self, insts: Sequence[TTN], n_streams: int = 0):
+        self.insts = list(insts)
+        arr = (C.c_void_p * len(self.insts))(*[t.h.value if isinstance(t.h, C.c_void_p) else t.h
+                                               for t in self.insts])
+        h = C.c_void_p()
+        code = lib.ttn_batch_create(len(self.insts), arr, int(n_streams), C.byref(h))
+        if code != TTN_OK:
+            raise TTNError(code, lib.ttn_batch_last_error(None).decode())
+        self.h = h
+
+    def step(self, dt, n_steps: int = 1):
+        dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (len(self.insts),)))
+        code = lib.ttn_batch_step(self.h, _ptr(dts, C.c_double), int(n_steps))
+        if code != TTN_OK:
+            raise TTNError(code, lib.ttn_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.ttn_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -17,7 +17,7 @@ SOURCES = ["compile.cpp", "api.cpp", "engine.hip", "kernels.hip"]
 ARCH = os.environ.get("TTN_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
-         # packed FP32 instructions stay off (GPU machine notes)
+         # no packed FP32 arithmetic instructions in any device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC, "-Wno-unused-command-line-argument"]
 

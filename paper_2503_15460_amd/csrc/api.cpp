@@ -2,6 +2,7 @@
 // conversion of exceptions into ttn_status codes.
 #include <cstring>
 #include <functional>
+#include <vector>
 #include <memory>
 #include <string>
 
@@ -14,6 +15,17 @@ struct ttn_ctx {
     std::unique_ptr<ttn::Engine> eng;
     std::string err;
     bool dead = false;
+    struct ttn_batch_ctx *batch = nullptr;  // batch the handle currently belongs to
+};
+
+// Instances advanced together: each instance runs on one of the batch's HIP
+// streams (round robin), so the sweeps of different instances overlap on the
+// device while the host enqueues them one after the other.
+struct ttn_batch_ctx {
+    std::vector<ttn_t> insts;
+    std::vector<hipStream_t> own;      // each instance's stream before joining
+    std::vector<hipStream_t> streams;  // created by the batch, default priority
+    std::string err;
 };
 
 namespace {
@@ -50,7 +62,7 @@ void ttn_default_options(ttn_options *opt) {
     if (!opt) return;
     std::memset(opt, 0, sizeof(*opt));
     opt->precision = TTN_FP64;
-    opt->krylov_tol = 1e-13;
+    opt->krylov_tol = 0.0;
     opt->krylov_mmax = 40;
     opt->hermitian = 1;
 }
@@ -97,6 +109,109 @@ ttn_status ttn_step(ttn_t h, double dt, int32_t n_steps) {
         if (n_steps < 0) throw ttn::Error(TTN_E_INVALID, "negative step count");
         h->eng->step(dt, n_steps);
     });
+}
+
+ttn_status ttn_batch_create(int32_t n, ttn_t const *insts, int32_t n_streams, ttn_batch_t *out) {
+    if (!out) {
+        g_err = "null output handle";
+        return TTN_E_INVALID;
+    }
+    *out = nullptr;
+    return guard(nullptr, [&] {
+        if (n < 1 || !insts) throw ttn::Error(TTN_E_INVALID, "empty batch");
+        for (int32_t i = 0; i < n; ++i) {
+            if (!insts[i]) throw ttn::Error(TTN_E_INVALID, "null instance handle");
+            if (insts[i]->dead) throw ttn::Error(TTN_E_DEVICE, "instance unusable after a device error");
+            if (insts[i]->batch) throw ttn::Error(TTN_E_INVALID, "instance already belongs to a batch");
+            for (int32_t j = 0; j < i; ++j)
+                if (insts[j] == insts[i]) throw ttn::Error(TTN_E_INVALID, "instance listed twice");
+            if (insts[i]->eng->opt.device != insts[0]->eng->opt.device)
+                throw ttn::Error(TTN_E_INVALID, "instances on different devices");
+        }
+        int ns = n_streams > 0 ? n_streams : 8;
+        if (ns > n) ns = n;
+        if (ns > 64) ns = 64;
+        auto b = std::make_unique<ttn_batch_ctx>();
+        hipError_t e = hipSetDevice(insts[0]->eng->opt.device);
+        for (int i = 0; i < ns && e == hipSuccess; ++i) {
+            hipStream_t s = nullptr;
+            e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+            if (e == hipSuccess) b->streams.push_back(s);
+        }
+        if (e != hipSuccess) {
+            for (auto s : b->streams) (void)hipStreamDestroy(s);
+            throw ttn::Error(TTN_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            b->insts.push_back(insts[i]);
+            b->own.push_back(insts[i]->eng->stream());
+            insts[i]->eng->set_stream(b->streams[i % ns]);
+            insts[i]->batch = b.get();
+        }
+        *out = b.release();
+    });
+}
+
+ttn_status ttn_batch_step(ttn_batch_t b, const double *dt, int32_t n_steps) {
+    if (!b) return TTN_E_INVALID;
+    const int n = (int)b->insts.size();
+    int cur = -1;  // instance being handled when an error is raised
+    ttn_status rc = guard(nullptr, [&] {
+        if (!dt) throw ttn::Error(TTN_E_INVALID, "null time steps");
+        if (n_steps < 0) throw ttn::Error(TTN_E_INVALID, "negative step count");
+        for (int i = 0; i < n; ++i)
+            if (b->insts[i]->dead) throw ttn::Error(TTN_E_DEVICE, "instance unusable after a device error");
+        for (cur = 0; cur < n; ++cur) b->insts[cur]->eng->check_ready(dt[cur]);
+        for (int s = 0; s < n_steps; ++s) {
+            for (cur = 0; cur < n; ++cur) b->insts[cur]->eng->enqueue_step(dt[cur]);
+            // finish every instance (each one's bookkeeping stays consistent), then report the first error
+            int bad = -1;
+            ttn_status bad_code = TTN_OK;
+            std::string bad_msg;
+            for (int i = 0; i < n; ++i) {
+                try {
+                    b->insts[i]->eng->finish_step(dt[i]);
+                } catch (const ttn::Error &e) {
+                    if (bad < 0) {
+                        bad = i;
+                        bad_code = e.code;
+                        bad_msg = e.what();
+                    }
+                }
+            }
+            if (bad >= 0) {
+                cur = bad;
+                throw ttn::Error(bad_code, bad_msg);
+            }
+        }
+        cur = -1;
+    });
+    if (rc != TTN_OK) {
+        b->err = g_err;
+        if (cur >= 0 && cur < n) {
+            b->err = "instance " + std::to_string(cur) + ": " + g_err;
+            b->insts[cur]->err = g_err;
+            if (rc == TTN_E_DEVICE) b->insts[cur]->dead = true;
+        }
+        // leave every instance idle: drain whatever was enqueued
+        for (auto s : b->streams) (void)hipStreamSynchronize(s);
+    }
+    return rc;
+}
+
+const char *ttn_batch_last_error(ttn_batch_t b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+void ttn_batch_destroy(ttn_batch_t b) {
+    if (!b) return;
+    for (size_t i = 0; i < b->insts.size(); ++i) {
+        try {
+            b->insts[i]->eng->set_stream(b->own[i]);
+        } catch (...) {
+        }
+        b->insts[i]->batch = nullptr;
+    }
+    for (auto s : b->streams) (void)hipStreamDestroy(s);
+    delete b;
 }
 
 ttn_status ttn_observe(ttn_t h, int32_t kind, int32_t n, const int32_t *op_ids, const double *vecs, double *out) {
@@ -169,6 +284,16 @@ const char *ttn_last_error(ttn_t h) {
 void ttn_destroy(ttn_t h) {
     if (!h) return;
     try {
+        if (h->batch) {  // leave the batch first
+            ttn_batch_ctx *b = h->batch;
+            for (size_t i = 0; i < b->insts.size(); ++i)
+                if (b->insts[i] == h) {
+                    b->insts.erase(b->insts.begin() + i);
+                    b->own.erase(b->own.begin() + i);
+                    break;
+                }
+            (void)hipStreamSynchronize(h->eng->stream());
+        }
         delete h;
     } catch (...) {
     }

@@ -38,6 +38,12 @@ public:
     void get_state(double *buf, size_t bytes);
     size_t state_bytes() const;
     void step(double dt, int n_steps);
+    // split form of one step for instances advanced together (batches)
+    void enqueue_step(double dt);
+    void finish_step(double dt);
+    void set_stream(hipStream_t s);
+    void check_ready(double dt) const;
+    hipStream_t stream() const { return st; }
     std::vector<double> observe(int kind, int n, const int32_t *op_ids, const double *vecs);
     void apply_root_heff(const double *x, double *y);
     void info(int32_t *bonds, int64_t *counters);
@@ -66,7 +72,9 @@ private:
     QRWork qrw{};
     int64_t bigN = 0;
     SolveStat *d_stats = nullptr;
-    std::vector<SolveStat> h_stats;
+    SolveStat *h_stats = nullptr;  // pinned host copy
+    int n_stats = 0;
+    hipEvent_t step_done = nullptr;
     std::vector<int> m_hint;     // per solve index in the step schedule
     std::vector<int> solve_node; // node (forward) or bond-owner (backward) per solve index
     std::vector<char> solve_fwd, solve_small;
@@ -95,6 +103,9 @@ private:
     void build_mf(int z, int k);
     void apply_prog(const Prog &p, const double2 *in, double2 *out);
     void sync_check(const char *where);
+    void save_snapshot();
+    void restore_snapshot();
+    void enqueue_sweep(double dt);
 };
 
 void debug_qr(int64_t rows, int cols, const double *m, int variant, double *q_out, double *r_out);

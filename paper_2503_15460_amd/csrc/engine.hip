@@ -54,11 +54,19 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
     }
     for (int z = 0; z < t.n; ++z)
         if (z != t.root && t.bond[z] > 64) throw Error(TTN_E_DIMS, "bond dimensions above 64 are not supported");
+    HIPCHK(hipEventCreateWithFlags(&step_done, hipEventDisableTiming));
 }
 
 Engine::~Engine() {
     free_sop();
+    if (h_stats) (void)hipHostFree(h_stats);
+    if (step_done) (void)hipEventDestroy(step_done);
     if (state_mem) (void)hipFree(state_mem);
+}
+
+void Engine::set_stream(hipStream_t s) {
+    HIPCHK(hipStreamSynchronize(st));
+    st = s;
 }
 
 void *Engine::dalloc(size_t bytes) {
@@ -456,11 +464,11 @@ void Engine::set_sop(const SopInput &s) {
         bk.counter = (unsigned *)dalloc(sizeof(unsigned) * 4);
         HIPCHK(hipMemset(bk.counter, 0, sizeof(unsigned) * 4));
         HIPCHK(hipMemset(bk.meff, 0, sizeof(int) * 4));
+    }
+    {  // copy of the state taken at the start of every step (restored on failure)
         int64_t tot = 0;
         for (int z = 0; z < n; ++z) tot += t.size[z];
         snapshot = (double2 *)dalloc(sizeof(double2) * tot);
-    } else {
-        snapshot = nullptr;
     }
     // many-work-group QR scratch
     qrw.tau = (double2 *)dalloc(sizeof(double2) * 64);
@@ -477,7 +485,12 @@ void Engine::set_sop(const SopInput &s) {
     HIPCHK(hipMemset(qrw.counter, 0, sizeof(unsigned) * 4));
     const int n_solves = (2 * n - 1) + 2 * (n - 1);
     d_stats = (SolveStat *)dalloc(sizeof(SolveStat) * n_solves);
-    h_stats.assign(n_solves, SolveStat{});
+    // pinned, so that the per-step statistics copy stays asynchronous
+    if (h_stats) (void)hipHostFree(h_stats);
+    h_stats = nullptr;
+    n_stats = n_solves;
+    HIPCHK(hipHostMalloc((void **)&h_stats, sizeof(SolveStat) * n_solves, hipHostMallocDefault));
+    std::memset(h_stats, 0, sizeof(SolveStat) * n_solves);
     m_hint.assign(n_solves, 0);
     solve_node.assign(n_solves, -1);
     solve_fwd.assign(n_solves, 0);
@@ -629,7 +642,7 @@ bool Engine::use_fused(const Prog &p) const {
 
 void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd) {
     const int si = solve_idx++;
-    if (si >= (int)h_stats.size()) throw Error(TTN_E_STATE, "internal: solve index overflow");
+    if (si >= n_stats) throw Error(TTN_E_STATE, "internal: solve index overflow");
     solve_node[si] = node;
     solve_fwd[si] = fwd ? 1 : 0;
     const bool fused = use_fused(p);
@@ -724,90 +737,116 @@ void Engine::sync_check(const char *where) {
     if (e != hipSuccess) throw Error(TTN_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-void Engine::step(double dt, int n_steps) {
+void Engine::check_ready(double dt) const {
     if (!have_sop || !have_state) throw Error(TTN_E_STATE, "ttn_step needs ttn_set_sop and a state");
     if (!std::isfinite(dt)) throw Error(TTN_E_INVALID, "dt must be finite");
+}
+
+void Engine::save_snapshot() {
+    if (!snapshot) return;
+    int64_t off = 0;
+    for (int z = 0; z < t.n; ++z) {
+        launch_copy(snapshot + off, A[z], t.size[z], st);
+        off += t.size[z];
+    }
+}
+
+void Engine::restore_snapshot() {
+    int64_t off = 0;
+    for (int z = 0; z < t.n; ++z) {
+        launch_copy(A[z], snapshot + off, t.size[z], st);
+        off += t.size[z];
+    }
+    rebuild_all_spos();
+}
+
+// Enqueue one sweep and the asynchronous copy of its solve statistics; nothing
+// here waits for the device.
+void Engine::enqueue_sweep(double dt) {
+    solve_idx = 0;
+    const double h = 0.5 * dt;
+    sweep_S(t.root, h);
+    forward(t.root, dt);
+    sweep_Sstar(t.root, h);
+    HIPCHK(hipMemcpyAsync(h_stats, d_stats, sizeof(SolveStat) * solve_idx, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(step_done, st));
+}
+
+void Engine::enqueue_step(double dt) {
+    check_ready(dt);
+    save_snapshot();
+    enqueue_sweep(dt);
+}
+
+// Wait for the enqueued sweep, update the Krylov dimension hints and, if a
+// multi-kernel solve missed its tolerance, restore the snapshot and run the
+// sweep again (synchronously) with larger dimensions.
+void Engine::finish_step(double dt) {
     const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP32 ? 1e-10 : 1e-13);
-    for (int s = 0; s < n_steps; ++s) {
-        if (snapshot) {
-            int64_t off = 0;
-            for (int z = 0; z < t.n; ++z) {
-                launch_copy(snapshot + off, A[z], t.size[z], st);
-                off += t.size[z];
-            }
-        }
-        int attempt = 0;
-        while (true) {
-            solve_idx = 0;
-            const double h = 0.5 * dt;
-            sweep_S(t.root, h);
-            forward(t.root, dt);
-            sweep_Sstar(t.root, h);
-            HIPCHK(hipMemcpyAsync(h_stats.data(), d_stats, sizeof(SolveStat) * solve_idx, hipMemcpyDeviceToHost, st));
-            sync_check("ttn_step");
-            bool redo = false;
-            for (int i = 0; i < solve_idx; ++i) {
-                const SolveStat &q = h_stats[i];
-                if (solve_small[i]) {
-                    if (q.fail) {
-                        char msg[256];
-                        const int zn = solve_node[i];
-                        const int64_t Nn = solve_fwd[i] ? t.size[zn] : (int64_t)t.bond[zn] * t.bond[zn];
-                        snprintf(msg, sizeof msg,
-                                 "local exponential did not converge (fused solver; %s solve %d at node %d, "
-                                 "N=%lld, m=%d, matvecs=%d, err=%.3g)",
-                                 solve_fwd[i] ? "forward" : "backward", i, zn, (long long)Nn, q.m, q.matvecs, q.err);
-                        throw Error(TTN_E_NOCONV, msg);
-                    }
-                    m_hint[i] = q.m;
-                } else {
-                    if (q.fail) {
-                        if (m_hint[i] >= mmax) {
-                            int64_t off = 0;
-                            for (int z = 0; z < t.n; ++z) {
-                                launch_copy(A[z], snapshot + off, t.size[z], st);
-                                off += t.size[z];
-                            }
-                            rebuild_all_spos();
-                            sync_check("restore");
-                            throw Error(TTN_E_NOCONV, "local exponential did not converge at the Krylov limit");
-                        }
-                        m_hint[i] = std::min(mmax, m_hint[i] + 6);
-                        redo = true;
-                    } else if (q.err_lo <= tol) {
-                        m_hint[i] = std::max(3, m_hint[i] - 1);
-                    }
-                }
-            }
-            if (!redo) break;
-            ++attempt;
-            ++counters[7];
-            int64_t off = 0;
-            for (int z = 0; z < t.n; ++z) {
-                launch_copy(A[z], snapshot + off, t.size[z], st);
-                off += t.size[z];
-            }
-            rebuild_all_spos();
-        }
-        if (profile_enabled()) {  // H_eff work done inside the fused solver launches
-            double f = 0.0;
-            for (int i = 0; i < solve_idx; ++i)
-                if (solve_small[i]) {
-                    const Prog &p = solve_fwd[i] ? heffP[solve_node[i]] : bondP[solve_node[i]];
-                    f += (double)h_stats[i].matvecs * (double)p.flops;
-                }
-            profile_add_flops("k_small_solve", f);
-        }
-        // counters
-        ++counters[0];
+    while (true) {
+        hipError_t e = hipEventSynchronize(step_done);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) throw Error(TTN_E_DEVICE, std::string("ttn_step: ") + hipGetErrorString(e));
+        bool redo = false;
         for (int i = 0; i < solve_idx; ++i) {
-            const int z = solve_node[i];
-            const Prog &p = solve_fwd[i] ? heffP[z] : bondP[z];
-            if (solve_fwd[i]) ++counters[1];
-            else ++counters[2];
-            counters[3] += h_stats[i].matvecs;
-            counters[4] += (int64_t)h_stats[i].matvecs * p.flops;
+            const SolveStat &q = h_stats[i];
+            if (solve_small[i]) {
+                if (q.fail) {
+                    char msg[256];
+                    const int zn = solve_node[i];
+                    const int64_t Nn = solve_fwd[i] ? t.size[zn] : (int64_t)t.bond[zn] * t.bond[zn];
+                    snprintf(msg, sizeof msg,
+                             "local exponential did not converge (fused solver; %s solve %d at node %d, "
+                             "N=%lld, m=%d, matvecs=%d, err=%.3g)",
+                             solve_fwd[i] ? "forward" : "backward", i, zn, (long long)Nn, q.m, q.matvecs, q.err);
+                    restore_snapshot();
+                    sync_check("restore");
+                    throw Error(TTN_E_NOCONV, msg);
+                }
+                m_hint[i] = q.m;
+            } else {
+                if (q.fail) {
+                    if (m_hint[i] >= mmax) {
+                        restore_snapshot();
+                        sync_check("restore");
+                        throw Error(TTN_E_NOCONV, "local exponential did not converge at the Krylov limit");
+                    }
+                    m_hint[i] = std::min(mmax, m_hint[i] + 6);
+                    redo = true;
+                } else if (q.err_lo <= tol) {
+                    m_hint[i] = std::max(3, m_hint[i] - 1);
+                }
+            }
         }
+        if (!redo) break;
+        ++counters[7];
+        restore_snapshot();
+        enqueue_sweep(dt);
+    }
+    if (profile_enabled()) {  // H_eff work done inside the fused solver launches
+        double f = 0.0;
+        for (int i = 0; i < solve_idx; ++i)
+            if (solve_small[i]) {
+                const Prog &p = solve_fwd[i] ? heffP[solve_node[i]] : bondP[solve_node[i]];
+                f += (double)h_stats[i].matvecs * (double)p.flops;
+            }
+        profile_add_flops("k_small_solve", f);
+    }
+    ++counters[0];
+    for (int i = 0; i < solve_idx; ++i) {
+        const int z = solve_node[i];
+        const Prog &p = solve_fwd[i] ? heffP[z] : bondP[z];
+        if (solve_fwd[i]) ++counters[1];
+        else ++counters[2];
+        counters[3] += h_stats[i].matvecs;
+        counters[4] += (int64_t)h_stats[i].matvecs * p.flops;
+    }
+}
+
+void Engine::step(double dt, int n_steps) {
+    for (int s = 0; s < n_steps; ++s) {
+        enqueue_step(dt);
+        finish_step(dt);
     }
 }
 
