@@ -34,7 +34,8 @@ ttn_status ttn_debug_clamp_bonds(int32_t n_nodes, const int32_t *parent, const i
  * kernels (LAPACK convention with the zero-snap of the sweep's gauge shifts).
  * m (x) in row-major (rows, cols), rows >= cols, cols <= 64; q_out receives
  * (rows, cols) and r_out (cols, cols), all complex interleaved host buffers.
- * variant 0: one work-group; 1: many work-groups (one launch per column).
+ * variant 0: one work-group; 1: many work-groups (one launch per column);
+ * 2: many work-groups in one cooperative launch (grid-wide barriers).
  * Uses device 0 and the null stream; allocates and frees its own device memory.
  * Errors: TTN_E_INVALID (shape), TTN_E_DEVICE. */
 ttn_status ttn_debug_qr(int64_t rows, int32_t cols, const double *m, int32_t variant, double *q_out,

@@ -73,6 +73,7 @@ private:
     int64_t bigN = 0;
     SolveStat *d_stats = nullptr;
     SolveStat *h_stats = nullptr;  // pinned host copy
+    unsigned *h_flags = nullptr;   // pinned: [0] failure flag of the cooperative QR barrier
     int n_stats = 0;
     hipEvent_t step_done = nullptr;
     std::vector<int> m_hint;     // per solve index in the step schedule

@@ -60,6 +60,7 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
 Engine::~Engine() {
     free_sop();
     if (h_stats) (void)hipHostFree(h_stats);
+    if (h_flags) (void)hipHostFree(h_flags);
     if (step_done) (void)hipEventDestroy(step_done);
     if (state_mem) (void)hipFree(state_mem);
 }
@@ -483,6 +484,8 @@ void Engine::set_sop(const SopInput &s) {
     qrw.thr = (double *)dalloc(sizeof(double) * 4);
     qrw.counter = (unsigned *)dalloc(sizeof(unsigned) * 4);
     HIPCHK(hipMemset(qrw.counter, 0, sizeof(unsigned) * 4));
+    qrw.cpart = (double *)dalloc(sizeof(double) * 2 * QRM_BLOCKS_MAX * QRC_REC);
+    qrw.bar = (unsigned *)dalloc(sizeof(unsigned) * 192);
     const int n_solves = (2 * n - 1) + 2 * (n - 1);
     d_stats = (SolveStat *)dalloc(sizeof(SolveStat) * n_solves);
     // pinned, so that the per-step statistics copy stays asynchronous
@@ -491,6 +494,8 @@ void Engine::set_sop(const SopInput &s) {
     n_stats = n_solves;
     HIPCHK(hipHostMalloc((void **)&h_stats, sizeof(SolveStat) * n_solves, hipHostMallocDefault));
     std::memset(h_stats, 0, sizeof(SolveStat) * n_solves);
+    if (!h_flags) HIPCHK(hipHostMalloc((void **)&h_flags, sizeof(unsigned) * 4, hipHostMallocDefault));
+    std::memset(h_flags, 0, sizeof(unsigned) * 4);
     m_hint.assign(n_solves, 0);
     solve_node.assign(n_solves, -1);
     solve_fwd.assign(n_solves, 0);
@@ -623,8 +628,12 @@ void Engine::build_mf(int z, int k) {
 
 void Engine::qr_slot(int z, int s, double2 *Rout, int transR) {
     const Geom g = heffP[z].g;
-    if (g.N >= QR_MULTI_MIN) launch_qr_multi(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st);
-    else launch_qr(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, st);
+    if (g.N >= QR_MULTI_MIN) {
+        if (!launch_qr_coop(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st))
+            launch_qr_multi(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st);
+    } else {
+        launch_qr(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, st);
+    }
 }
 
 void Engine::absorb(int z, int s, const double2 *M, int transM) {
@@ -769,6 +778,7 @@ void Engine::enqueue_sweep(double dt) {
     forward(t.root, dt);
     sweep_Sstar(t.root, h);
     HIPCHK(hipMemcpyAsync(h_stats, d_stats, sizeof(SolveStat) * solve_idx, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_flags, qrw.bar + 128, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(step_done, st));
 }
 
@@ -787,6 +797,7 @@ void Engine::finish_step(double dt) {
         hipError_t e = hipEventSynchronize(step_done);
         if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) throw Error(TTN_E_DEVICE, std::string("ttn_step: ") + hipGetErrorString(e));
+        if (h_flags[0]) throw Error(TTN_E_DEVICE, "grid-wide barrier of the cooperative QR timed out");
         bool redo = false;
         for (int i = 0; i < solve_idx; ++i) {
             const SolveStat &q = h_stats[i];
@@ -1042,7 +1053,17 @@ void debug_qr(int64_t rows, int cols, const double *m, int variant, double *q_ou
             q.thr = (double *)alloc(sizeof(double) * 4);
             q.counter = (unsigned *)alloc(sizeof(unsigned) * 4);
             HIPCHK(hipMemset(q.counter, 0, sizeof(unsigned) * 4));
-            launch_qr_multi(A, rows, cols, 1, Rd, 0, q, nullptr);
+            q.cpart = (double *)alloc(sizeof(double) * 2 * QRM_BLOCKS_MAX * QRC_REC);
+            q.bar = (unsigned *)alloc(sizeof(unsigned) * 192);
+            HIPCHK(hipMemset(q.bar, 0, sizeof(unsigned) * 192));
+            if (variant == 1) launch_qr_multi(A, rows, cols, 1, Rd, 0, q, nullptr);
+            else if (!launch_qr_coop(A, rows, cols, 1, Rd, 0, q, nullptr))
+                throw Error(TTN_E_INVALID, "cooperative QR grid cannot be co-resident");
+            if (variant == 2) {
+                unsigned flag = 0;
+                HIPCHK(hipMemcpy(&flag, q.bar + 128, sizeof(unsigned), hipMemcpyDeviceToHost));
+                if (flag) throw Error(TTN_E_DEVICE, "grid-wide barrier of the cooperative QR timed out");
+            }
         }
         HIPCHK(hipDeviceSynchronize());
         HIPCHK(hipGetLastError());

@@ -8,6 +8,7 @@
 // (Sec. II A), and the local exponentials of the projector-splitting sweep.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <map>
@@ -778,6 +779,289 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qrm_formq(double2 *A, uint32_t 
             for (int i = 0; i < n; ++i) acc = csub(acc, cmul(Vt[rr * n + i], Ks[i * n + c]));
             A[qr_addr(rho, c, n, R)] = acc;
         }
+    }
+}
+
+// ============================================================ QR (one cooperative launch)
+constexpr int QRC_STAGE = 4096;  // doubles of LDS staging for the per-column reduction
+// Grid-wide barrier for a co-resident grid: bar[0] counts arrivals, bar[64]
+// is the generation (separate cache lines).  The last block to arrive resets
+// the count and advances the generation, which the others wait for; a bounded
+// spin records a failure in bar[128] instead of waiting for ever.
+__device__ void grid_barrier(unsigned *bar, unsigned nblocks) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned *arrive = bar, *gen = bar + 64;
+        const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned prev = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == nblocks - 1) {
+            __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1u << 24)) {
+                    __hip_atomic_store(bar + 128, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// The reflectors of k_qrm_step / k_qrm_finish / k_qrm_formq in a single launch:
+// every work-group owns rows [r0, r1); after each column's partial sums a
+// grid-wide barrier lets every work-group reduce them in the same fixed order,
+// so all work-groups hold identical reflector parameters in LDS and apply
+// them to their rows without another launch.  Partials are double-buffered by
+// column parity (a work-group may write column i+1 while another still reads
+// column i).
+// The work-group's rows stay in LDS (At, row-major (rows_per, n)) from the
+// first load to the final write of Q; only the per-column partial records,
+// the reflector Gram partials and K pass through global memory.
+__device__ __forceinline__ double2 tile_v(const double2 *At, uint32_t r0, uint32_t rho, int k, int n) {
+    if (rho < (uint32_t)k) return make_double2(0.0, 0.0);
+    if (rho == (uint32_t)k) return make_double2(1.0, 0.0);
+    return At[(size_t)(rho - r0) * n + k];
+}
+
+__global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L, int n, uint32_t R,
+                                                          uint32_t rows_per, QRWork q, double2 *Rout, int transR,
+                                                          double snap) {
+    extern __shared__ double2 sq[];
+    const uint32_t m = L * R;
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t r0 = b * rows_per, r1 = min(m, r0 + rows_per);
+    const uint32_t nr = r1 - r0;
+    const int tid = threadIdx.x;
+    double2 *At = sq;                          // nr * n
+    double2 *aux = sq + (size_t)rows_per * n;  // staging / T,S / K
+    __shared__ double2 s_w[QRM_MAXN];
+    __shared__ double2 s_tau, s_scl, s_diag;
+    __shared__ int s_snapped;
+    __shared__ double s_thr;
+    __shared__ double s_sum[QRC_REC];
+    __shared__ double2 red2[256];
+    __shared__ double red1[16];
+    for (uint32_t e = tid; e < nr * (uint32_t)n; e += blockDim.x) {
+        const uint32_t rho = r0 + e / n;
+        At[e] = A[qr_addr(rho, (int)(e % n), n, R)];
+    }
+    __syncthreads();
+    for (int i = 0; i <= n; ++i) {
+        if (i > 0) {  // apply reflector k = i - 1 to the own rows
+            const int k = i - 1;
+            const double2 tau = s_tau, scl = s_scl;
+            const bool has = tau.x != 0.0 || tau.y != 0.0;
+            const uint32_t lo = max(r0, (uint32_t)k + 1);
+            for (uint32_t rho = lo + tid; rho < r1; rho += blockDim.x) {
+                double2 &a = At[(size_t)(rho - r0) * n + k];
+                if (s_snapped) a = make_double2(0.0, 0.0);
+                else if (has) a = cmul(a, scl);
+            }
+            if (tid == 0 && (uint32_t)k >= r0 && (uint32_t)k < r1) At[(size_t)(k - r0) * n + k] = s_diag;
+            __syncthreads();
+            const int nt = n - k - 1;
+            if (has && nt > 0) {
+                const double2 ct = make_double2(tau.x, -tau.y);
+                const uint32_t rs = max(r0, (uint32_t)k);
+                const uint32_t rows = r1 > rs ? r1 - rs : 0;
+                for (uint32_t e = tid; e < rows * (uint32_t)nt; e += blockDim.x) {
+                    const uint32_t rho = rs + e / nt;
+                    const int j = k + 1 + (int)(e % nt);
+                    const double2 v = tile_v(At, r0, rho, k, n);
+                    double2 &a = At[(size_t)(rho - r0) * n + j];
+                    a = csub(a, cmul(v, cmul(ct, s_w[j])));
+                }
+            }
+            __syncthreads();
+        }
+        if (i == n) break;
+        // partial sums of column i over the own rows
+        double *rec = q.cpart + ((size_t)(i & 1) * QRM_BLOCKS_MAX + b) * QRC_REC;
+        double xp = 0.0, fp = 0.0;
+        const uint32_t lo = max(r0, (uint32_t)i + 1);
+        for (uint32_t rho = lo + tid; rho < r1; rho += blockDim.x) xp += cabs2(At[(size_t)(rho - r0) * n + i]);
+        if (i == 0)
+            for (uint32_t e = tid; e < nr * (uint32_t)n; e += blockDim.x) fp += cabs2(At[e]);
+        const double xs = blk_sum1(xp, red1);
+        const double fs = blk_sum1(fp, red1);
+        const int nt = n - i - 1;
+        const int P = nt > 0 ? (int)blockDim.x / nt : 0;  // row phases per trailing column
+        if (nt > 0 && tid < P * nt) {
+            const int jc = tid % nt, ph = tid / nt;
+            const int j = i + 1 + jc;
+            double2 acc = make_double2(0.0, 0.0);
+            for (uint32_t rho = lo + ph; rho < r1; rho += P) {
+                const double2 *row = At + (size_t)(rho - r0) * n;
+                cfmac(acc, row[i], row[j]);
+            }
+            red2[ph * nt + jc] = acc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            rec[0] = xs;
+            rec[1] = fs;
+        }
+        if (tid < nt) {
+            double2 g = make_double2(0.0, 0.0);
+            for (int ph = 0; ph < P; ++ph) g = cadd(g, red2[ph * nt + tid]);
+            const int j = i + 1 + tid;
+            rec[2 + 2 * j] = g.x;
+            rec[3 + 2 * j] = g.y;
+        }
+        if ((uint32_t)i >= r0 && (uint32_t)i < r1)
+            for (int c = i + tid; c < n; c += blockDim.x) {
+                const double2 v = At[(size_t)(i - r0) * n + c];
+                rec[2 + 2 * QRM_MAXN + 2 * c] = v.x;
+                rec[3 + 2 * QRM_MAXN + 2 * c] = v.y;
+            }
+        grid_barrier(q.bar, G);
+        // every work-group reduces the partials in the same order: chunks of
+        // values are staged through LDS with independent loads, then 8 lanes
+        // per value sum strided partials and combine them by shuffles
+        const double *recs = q.cpart + (size_t)(i & 1) * QRM_BLOCKS_MAX * QRC_REC;
+        const uint32_t own = (uint32_t)i / rows_per;
+        {
+            double *stage = reinterpret_cast<double *>(aux);  // QRC_STAGE doubles
+            const int nv = 2 + 2 * n;
+            const int ch = max(1, min(32, QRC_STAGE / (int)G));
+            for (int v0 = 0; v0 < nv; v0 += ch) {
+                const int cnt = min(ch, nv - v0);
+                for (int e = tid; e < (int)G * cnt; e += blockDim.x) {
+                    const int bb = e / cnt, t = e - bb * cnt;
+                    stage[e] = recs[(size_t)bb * QRC_REC + v0 + t];
+                }
+                __syncthreads();
+                const int t = tid / 8, sub = tid & 7;
+                double sacc = 0.0;
+                if (t < cnt)
+                    for (int bb = sub; bb < (int)G; bb += 8) sacc += stage[bb * cnt + t];
+                sacc += __shfl_xor(sacc, 4, 64);
+                sacc += __shfl_xor(sacc, 2, 64);
+                sacc += __shfl_xor(sacc, 1, 64);
+                if (t < cnt && sub == 0) s_sum[v0 + t] = sacc;
+                __syncthreads();
+            }
+        }
+        for (int t = tid; t < 2 * n; t += blockDim.x)
+            s_sum[2 + 2 * QRM_MAXN + t] = recs[(size_t)own * QRC_REC + 2 + 2 * QRM_MAXN + t];
+        __syncthreads();
+        if (tid == 0) {
+            double xn2 = s_sum[0];
+            if (i == 0) s_thr = snap * sqrt(s_sum[1]);
+            const double thr = s_thr;
+            double2 alpha = make_double2(s_sum[2 + 2 * QRM_MAXN + 2 * i], s_sum[3 + 2 * QRM_MAXN + 2 * i]);
+            int snapped = 0;
+            if (snap > 0.0 && sqrt(xn2) <= thr) {
+                snapped = 1;
+                xn2 = 0.0;
+                if (fabs(alpha.y) <= thr) alpha.y = 0.0;
+            }
+            double2 tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0), diag = alpha;
+            if (!(xn2 == 0.0 && alpha.y == 0.0)) {
+                const double beta = -copysign(sqrt(cabs2(alpha) + xn2), alpha.x);
+                tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                scl = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+                diag = make_double2(beta, 0.0);
+            }
+            s_tau = tau;
+            s_scl = scl;
+            s_diag = diag;
+            s_snapped = snapped;
+            if (b == 0) q.tau[i] = tau;
+        }
+        __syncthreads();
+        {
+            const double2 cs = make_double2(s_scl.x, -s_scl.y);
+            for (int c = i + 1 + tid; c < n; c += blockDim.x) {
+                const double2 g = s_snapped ? make_double2(0.0, 0.0) : make_double2(s_sum[2 + 2 * c], s_sum[3 + 2 * c]);
+                const double2 rowc = make_double2(s_sum[2 + 2 * QRM_MAXN + 2 * c], s_sum[3 + 2 * QRM_MAXN + 2 * c]);
+                s_w[c] = cadd(rowc, cmul(cs, g));
+            }
+        }
+        __syncthreads();
+    }
+    // R factor (rows 0..n-1 live in work-group 0 since rows_per >= n)
+    if (b == 0)
+        for (int e = tid; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            const double2 v = j >= i ? At[(size_t)i * n + j] : make_double2(0.0, 0.0);
+            if (transR) Rout[j * n + i] = v;
+            else Rout[i * n + j] = v;
+        }
+    // partial reflector Gram matrix S[k][l] = sum_rho conj(V[rho,k]) V[rho,l], k < l, over the own rows
+    const int npair = n * (n - 1) / 2;
+    double2 *Sp = q.S + (size_t)b * npair;
+    for (int pidx = tid; pidx < npair; pidx += blockDim.x) {
+        int k = 0, rem = pidx;
+        while (rem >= n - 1 - k) {
+            rem -= n - 1 - k;
+            ++k;
+        }
+        const int l = k + 1 + rem;
+        double2 sacc = make_double2(0.0, 0.0);
+        for (uint32_t rho = max(r0, (uint32_t)l); rho < r1; ++rho)
+            cfmac(sacc, tile_v(At, r0, rho, k, n), tile_v(At, r0, rho, l, n));
+        Sp[pidx] = sacc;
+    }
+    grid_barrier(q.bar, G);
+    if (b == 0) {  // T (compact WY) and K = T V_top^H, as in k_qrm_finish
+        double2 *T = aux;          // n*n
+        double2 *S = aux + n * n;  // n*n
+        for (int e = tid; e < n * n; e += blockDim.x) {
+            T[e] = make_double2(0.0, 0.0);
+            S[e] = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int pidx = tid; pidx < npair; pidx += blockDim.x) {
+            double2 sacc = make_double2(0.0, 0.0);
+            for (uint32_t bb = 0; bb < G; ++bb) sacc = cadd(sacc, q.S[(size_t)bb * npair + pidx]);
+            int k = 0, rem = pidx;
+            while (rem >= n - 1 - k) {
+                rem -= n - 1 - k;
+                ++k;
+            }
+            S[k * n + k + 1 + rem] = sacc;
+        }
+        __syncthreads();
+        for (int i = 0; i < n; ++i) {
+            const double2 ti = q.tau[i];
+            double2 val = make_double2(0.0, 0.0);
+            if (tid < i) {
+                for (int l = tid; l < i; ++l) cfma(val, T[tid * n + l], S[l * n + i]);
+                val = cmul(make_double2(-ti.x, -ti.y), val);
+            }
+            __syncthreads();
+            if (tid < i) T[tid * n + i] = val;
+            if (tid == 0) T[i * n + i] = ti;
+            __syncthreads();
+        }
+        for (int e = tid; e < n * n; e += blockDim.x) {
+            const int i = e / n, c = e % n;
+            double2 kacc = make_double2(0.0, 0.0);
+            for (int l = i; l < n; ++l) {
+                const double2 v = tile_v(At, 0, (uint32_t)c, l, n);
+                kacc = cadd(kacc, cmul(T[i * n + l], make_double2(v.x, -v.y)));
+            }
+            q.K[e] = kacc;
+        }
+    }
+    grid_barrier(q.bar, G);
+    // Q[rho, c] = delta - sum_i V[rho, i] K[i, c] on the own rows, written to A
+    double2 *Ks = aux;
+    for (int e = tid; e < n * n; e += blockDim.x) Ks[e] = q.K[e];
+    __syncthreads();
+    for (uint32_t e = tid; e < nr * (uint32_t)n; e += blockDim.x) {
+        const uint32_t rr = e / n, rho = r0 + rr;
+        const int c = (int)(e % n);
+        double2 qacc = make_double2(rho == (uint32_t)c ? 1.0 : 0.0, 0.0);
+        for (int i = 0; i < n; ++i) qacc = csub(qacc, cmul(tile_v(At, r0, rho, i, n), Ks[i * n + c]));
+        A[qr_addr(rho, c, n, R)] = qacc;
     }
 }
 
@@ -1555,6 +1839,58 @@ void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int
     set_lds_limit((const void *)k_qrm_formq, lds_q);
     TTN_LAUNCH("k_qrm_formq", 8.0 * m * n * n, 32.0 * m * n, k_qrm_formq, dim3(nb), dim3(QRM_THREADS), lds_q, st, A,
                (uint32_t)L, n, (uint32_t)R, (uint32_t)rows_per, q);
+}
+
+bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
+                    hipStream_t st) {
+    const int64_t m = L * R;
+    if (n > QRM_MAXN || m < n) throw std::runtime_error("QR shape out of range");
+    // LDS: the row tile plus an auxiliary region (reduction staging, T and S, K)
+    const size_t aux = std::max<size_t>((size_t)2 * n * n, QRC_STAGE / 2);
+    const size_t budget = 150 * 1024 / sizeof(double2);  // elements
+    if (aux + (size_t)64 * n > budget) return false;
+    const int64_t tile_rows = (int64_t)((budget - aux) / n);
+    // about 2048 matrix elements per work-group, within the tile
+    int64_t rows_per = std::max<int64_t>(64, (2048 + n - 1) / n);
+    if (rows_per > tile_rows) rows_per = tile_rows;
+    if ((m + rows_per - 1) / rows_per > QRM_BLOCKS_MAX) rows_per = (m + QRM_BLOCKS_MAX - 1) / QRM_BLOCKS_MAX;
+    if (rows_per > tile_rows || rows_per < n) return false;
+    const unsigned nb = (unsigned)((m + rows_per - 1) / rows_per);
+    const size_t lds = sizeof(double2) * ((size_t)rows_per * n + aux);
+    set_lds_limit((const void *)k_qr_coop, lds);
+    // co-residency of the whole grid (queried once per device and LDS size)
+    static std::map<std::pair<int, size_t>, int> cap;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    auto key = std::make_pair(dev, lds);
+    if (!cap.count(key)) {
+        int per_cu = 0, cus = 0, coop = 0;
+        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_qr_coop, QRM_THREADS, lds) !=
+                hipSuccess)
+            cap[key] = 0;
+        else
+            cap[key] = per_cu * cus;
+    }
+    if ((int)nb > cap[key] || nb > (unsigned)QRM_BLOCKS_MAX) return false;
+    uint32_t Lu = (uint32_t)L, Ru = (uint32_t)R, rp = (uint32_t)rows_per;
+    double snap = QR_SNAP;
+    QRWork qq = q;
+    void *args[] = {&A, &Lu, &n, &Ru, &rp, &qq, &Rout, &transR, &snap};
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (prof::on) {
+        ea = prof::take();
+        eb = prof::take();
+        (void)hipEventRecord(ea, st);
+    }
+    hipError_t e = hipLaunchCooperativeKernel((const void *)k_qr_coop, dim3(nb), dim3(QRM_THREADS), args, lds, st);
+    if (e != hipSuccess) throw std::runtime_error(std::string("hipLaunchCooperativeKernel: ") + hipGetErrorString(e));
+    if (prof::on) {
+        (void)hipEventRecord(eb, st);
+        prof::recs.push_back({"k_qr_coop", ea, eb, 16.0 * (double)m * n * n, 32.0 * (double)m * n});
+    }
+    return true;
 }
 
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {

@@ -35,10 +35,12 @@ def _cases():
     return out
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_qr_matches_oracle_householder(T, variant):
     for name, M in _cases():
         if variant == 0 and M.size > 200_000:
+            continue
+        if variant == 2 and M.shape[1] > 48:  # the LDS-resident cooperative QR takes n <= 48
             continue
         Q, R = T.gpu_qr(M, variant)
         Qo, Ro = householder_qr_lapack(M, snap=SNAP)
