@@ -19,11 +19,14 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix = vector)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 (matrix = vector)
 
 # Kernels whose arithmetic is plain FP64 vector FMA code (no matrix-core
 # instructions): their compute peak is the FP64 vector rate, 256 CUs x 2.4 GHz
@@ -67,6 +70,94 @@ def timed_run(T, p, precision, steps, warmup):
     return g, elapsed, c0, g.counters()
 
 
+def fp32_error(T, p, steps: int):
+    """Largest difference of populations and autocorrelation between the FP32
+    and FP64 modes over `steps` sweeps from a seeded full-rank state (from the
+    product state, rounding-size differences are amplified by the
+    rank-deficient first QRs and say nothing about the FP32 contractions)."""
+    from workloads import random_isometric_state
+    runs = []
+    for prec in (T.TTN_FP64, T.TTN_FP32):
+        g = T.TTN.from_problem(p, precision=prec)
+        st = random_isometric_state(p.parent, p.local_dim, g.bonds(), seed=2)
+        g.set_state(st)
+        obs = []
+        for _ in range(steps):
+            g.step(p.dt)
+            obs += [g.expect(p.observables["P0"]), g.expect(p.observables["P1"]), g.overlap_t0()]
+        runs.append(np.array(obs))
+        g.close()
+    return {"max_abs": float(np.abs(runs[0] - runs[1]).max()), "observables": "P0, P1, a(t)",
+            "start": "seeded full-rank isometric state", "steps": steps}
+
+
+def exciton_run(T, steps: int):
+    """The 10-state / 120-mode exciton model (bonds 32-64), FP64 and FP32 modes:
+    sweeps/s, H_eff flop rate and the FP32 population error against FP64."""
+    import torch
+    from workloads import exciton_problem
+    p = exciton_problem()
+    out, pops = {}, {}
+    for prec, name in ((T.TTN_FP64, "fp64"), (T.TTN_FP32, "fp32")):
+        g, el, c0, c1 = timed_run(T, p, prec, steps, 1)
+        pops[name] = np.array([g.expect(p.observables[f"P{k}"]).real for k in range(10)])
+        T.profile_begin()
+        g.step(p.dt)
+        torch.cuda.synchronize()
+        st = T.profile_end()
+        tile = [r for r in st if r["name"].startswith("k_mode_tile")]
+        tms = sum(r["total_ms"] for r in tile)
+        tfl = sum(r["flops"] for r in tile)
+        out[name] = {"value": steps / el, "unit": "sweeps/s", "ms_per_step": 1e3 * el / steps,
+                     "heff_tflops": (c1["heff_flops"] - c0["heff_flops"]) / el / 1e12,
+                     "k_mode_tile_tflops": tfl / tms / 1e9 if tms > 0 else None,
+                     "k_mode_tile_frac": (tfl / tms / 1e9) / (PEAK_FP64_TFLOPS if prec == T.TTN_FP64 else
+                                                              PEAK_FP32_TFLOPS) if tms > 0 else None,
+                     "device_gib": c1["device_bytes"] / 2**30}
+        g.close()
+    out["fp32_max_abs_population_diff_vs_fp64"] = float(np.abs(pops["fp64"] - pops["fp32"]).max())
+    out["workload"] = ("exciton10x120: 10 states, 120 modes in 60 composite leaves (d 36-144), 1500 SOP terms, "
+                       "tree R(E,A,A) A(B,B,B) B(C,C) C(5 leaves), bonds 8/32/48/64, dt 0.5 fs, product start, "
+                       f"{1 + steps} sweeps")
+    return out
+
+
+def batch_run(T, n_inst: int, steps: int):
+    """Uneven spin-boson instances (8-64 modes, 6-16 levels, bonds 8-48): one
+    at a time in FP64 against one batch (FP64 and FP32) on 8 streams."""
+    import torch
+    from workloads import batch_sbm_problems
+    probs = batch_sbm_problems(seed=5, n_inst=n_inst)
+    dts = np.array([p.dt for p in probs])
+    res = {}
+    for prec, name in ((T.TTN_FP64, "fp64"), (T.TTN_FP32, "fp32")):
+        gs = []
+        for p in probs:
+            g = T.TTN.from_problem(p, precision=prec)
+            g.set_product_state(p.init_vecs)
+            g.step(p.dt)
+            gs.append(g)
+        torch.cuda.synchronize()
+        if prec == T.TTN_FP64:
+            t0 = time.perf_counter()
+            for g, p in zip(gs, probs):
+                g.step(p.dt, steps)
+            torch.cuda.synchronize()
+            res["sequential_fp64"] = n_inst * steps / (time.perf_counter() - t0)
+        b = T.TTNBatch(gs, n_streams=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(dts, steps)
+        torch.cuda.synchronize()
+        res[f"batched_{name}"] = n_inst * steps / (time.perf_counter() - t0)
+        b.close()
+        for g in gs:
+            g.close()
+    return {"unit": "instance-sweeps/s", **res,
+            "speedup_batched_fp32_vs_sequential_fp64": res["batched_fp32"] / res["sequential_fp64"],
+            "workload": f"{n_inst} of the 256 seeded uneven spin-boson instances (seed 5), {steps} timed sweeps each"}
+
+
 def cpu_baseline(problem, steps: int):
     """The oracle (numpy complex128) on the host cores: seconds for `steps` sweeps."""
     from oracle import Oracle
@@ -90,6 +181,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-contraction comparison run")
+    ap.add_argument("--no-extra", action="store_true", help="skip the exciton and batched-instance lines")
+    ap.add_argument("--batch-instances", type=int, default=8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -122,13 +215,10 @@ def main():
     fp32 = None
     if not args.no_fp32:
         g32, el32, d0, d1 = timed_run(T, p, T.TTN_FP32, args.steps, args.warmup)
-        pops32 = [g32.expect(p.observables[k]).real for k in ("P0", "P1")]
+        g32.close()
         fp32 = {"value": args.steps / el32, "unit": "sweeps/s", "ms_per_step": 1e3 * el32 / args.steps,
                 "heff_tflops": (d1["heff_flops"] - d0["heff_flops"]) / el32 / 1e12,
-                "max_abs_population_diff_vs_fp64": max(abs(a - b) for a, b in zip(pops, pops32)),
-                "note": "product-state start: FP32-size rounding alone moves this run's populations by up to "
-                        "~3e-3 (measured on the oracle); full-rank starts agree with the FP64 oracle to 1e-4"}
-        g32.close()
+                "error_vs_fp64": fp32_error(T, p, steps=5)}
 
     out = {
         "metric": "TDVP sweeps/s + H_eff TFLOP/s (% MFMA peak), FP32-mixed vs FP64 at stated err",
@@ -153,6 +243,9 @@ def main():
         "kernels": sorted(({k: (v if k != "name" else v) for k, v in r.items()} for r in stats),
                           key=lambda r: -r["total_ms"])[:8],
     }
+    if not args.no_extra:
+        out["config"]["exciton10x120"] = exciton_run(T, 1)
+        out["config"]["batched_instances"] = batch_run(T, args.batch_instances, 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)

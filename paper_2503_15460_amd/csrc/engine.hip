@@ -677,7 +677,7 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
             if (e.nf >= 1 && e.slot[e.nf - 1] == 1) ++nA;
         a.nA = nA;
         a.batched = (p.g.D == 2 && (int)p.ents.size() <= SMALL_MAXENT && p.g.dims[0] * p.g.dims[0] <= SMALL_UB &&
-                     small_solve_lds_bytes(p.g.N, a.mmax, 1, nA) + SMALL_MAXENT * sizeof(int) <= 160 * 1024)
+                     small_solve_lds_bytes(p.g.N, a.mmax, 1, nA) + SMALL_STATIC_LDS <= 160 * 1024)
                         ? 1
                         : 0;
         launch_small_solve(a, st);

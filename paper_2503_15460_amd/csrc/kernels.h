@@ -94,6 +94,8 @@ struct SmallSolveArgs {
 constexpr int SMALL_MAXENT = 128;  // entries of the batched two-slot matvec
 constexpr int SMALL_UB = 2048;     // LDS elements for staged slot-0 operators (batched matvec)
 constexpr int64_t SMALL_SEQ_WORK = 8192;  // entries x elements limit of the fused solver's generic matvec
+// static LDS of the fused solver: two int tables and the staged entry fields per entry, plus reduction scratch
+constexpr size_t SMALL_STATIC_LDS = (size_t)SMALL_MAXENT * (2 * sizeof(int) + 48) + 1024;
 size_t small_solve_lds_bytes(int64_t N, int mmax, int batched, int nA);
 
 // Scratch of the multi-kernel Krylov path.

@@ -1137,12 +1137,23 @@ __device__ void blk_expm_col0(const double2 *H, int ldh, int m, double tau, doub
 // per thread).  Krylov vectors live in global scratch (L2 resident), the
 // current vector, the matvec result and the temporaries in LDS.
 
+// entry fields the two-slot matvec reads, staged in LDS once per solve
+struct EntLite {
+    double2 coef;
+    const double2 *M0;  // slot-0 factor (null: identity on slot 0)
+    const double2 *M1;  // slot-1 factor (null: identity on slot 1)
+    int lo0, hi0, lo1, hi1;
+};
+
+static_assert(sizeof(EntLite) <= 48, "EntLite must fit the static LDS budget of the fused solver");
+
 struct SmallLds {
     double2 *v, *w, *r1, *Hm, *hbuf, *ybuf, *red;  // red: 16 waves x (mmax+1)
-    double2 *us;                                   // staged slot-0 operators (batched matvec)
+    double2 *us;                                   // partial sums of the entry groups (batched matvec)
     double *red1;
-    int *e1;   // entries with a slot-1 factor (two-slot batched matvec)
-    int *tix;  // per entry: index of its slot-1 temporary, -1 if none
+    int *e1;        // entries with a slot-1 factor (two-slot batched matvec)
+    int *tix;       // per entry: index of its slot-1 temporary, -1 if none
+    EntLite *ents;  // per entry (batched matvec)
 };
 
 __device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M, const Geom &g, int s, int blo,
@@ -1186,20 +1197,19 @@ __device__ void blk_matvec_seq(const SmallSolveArgs &a, const double2 *v, double
 //   phase A: T_e = X x_1 M1_e for every entry with a slot-1 factor
 //   phase B: Y = sum_e c_e (M0_e x_0 T_e)
 __device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double2 *w, double2 *T, const int *e1,
-                               const int *tix, double2 *Us) {
+                               const int *tix, double2 *Us, const EntLite *L_ents) {
     const int n0 = a.g.dims[0], n1 = a.g.dims[1];
     const uint32_t N = (uint32_t)(n0 * n1);
     const int na = a.nA;
+    const EntLite *ents = L_ents;
     for (uint32_t q = threadIdx.x; q < (uint32_t)na * N; q += blockDim.x) {
         const uint32_t k = q / N, el = q - k * N;
-        const DevEntry *E = a.ent + e1[k];
-        const int f1 = E->nf - 1;
-        const double2 *M1 = E->M[f1];
+        const EntLite &E = ents[e1[k]];
         const uint32_t ai = el / n1, p = el - ai * n1;
         const double2 *xr = v + (size_t)ai * n1;
-        const double2 *mr = M1 + (size_t)p * n1;
+        const double2 *mr = E.M1 + (size_t)p * n1;
         double2 acc = make_double2(0.0, 0.0);
-        const int j0 = max(0, (int)p - E->lo[f1]), j1 = min(n1 - 1, (int)p + E->hi[f1]);
+        const int j0 = max(0, (int)p - E.lo1), j1 = min(n1 - 1, (int)p + E.hi1);
         for (int j = j0; j <= j1; ++j) cfma(acc, mr[j], xr[j]);
         T[q] = acc;
     }
@@ -1215,20 +1225,18 @@ __device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double
             const uint32_t i = idx / n1, p = idx - i * n1;
             double2 out = make_double2(0.0, 0.0);
             for (int e = grp; e < a.n_ent; e += G) {
-                const DevEntry *E = a.ent + e;
-                const int nf = E->nf;
-                const bool has0 = nf >= 1 && E->slot[0] == 0;
+                const EntLite &E = ents[e];
                 const int k = tix[e];
                 const double2 *S = k >= 0 ? T + (size_t)k * N : v;
                 double2 r = make_double2(0.0, 0.0);
-                if (has0) {
-                    const double2 *mr = E->M[0] + (size_t)i * n0;
-                    const int j0 = max(0, (int)i - E->lo[0]), j1 = min(n0 - 1, (int)i + E->hi[0]);
+                if (E.M0) {
+                    const double2 *mr = E.M0 + (size_t)i * n0;
+                    const int j0 = max(0, (int)i - E.lo0), j1 = min(n0 - 1, (int)i + E.hi0);
                     for (int j = j0; j <= j1; ++j) cfma(r, mr[j], S[(size_t)j * n1 + p]);
                 } else {
                     r = S[idx];
                 }
-                cfma(out, E->coef, r);
+                cfma(out, E.coef, r);
             }
             Us[(size_t)grp * N + idx] = out;
         }
@@ -1323,7 +1331,7 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
     for (int q = tid; q < (mmax + 1) * mmax; q += nt) L.Hm[q] = make_double2(0.0, 0.0);
     __syncthreads();
     for (int j = 0; j < mmax; ++j) {
-        if (a.batched) blk_matvec_two(a, L.v, L.w, L.r1, L.e1, L.tix, L.us);
+        if (a.batched) blk_matvec_two(a, L.v, L.w, L.r1, L.e1, L.tix, L.us, L.ents);
         else blk_matvec_seq(a, L.v, L.w, L.r1, L.r1 + N);
         ++matvecs;
         double wn2 = 0.0;
@@ -1396,6 +1404,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
     extern __shared__ double2 sm[];
     __shared__ int e1[SMALL_MAXENT];
     __shared__ int tix[SMALL_MAXENT];
+    __shared__ EntLite ents[SMALL_MAXENT];
     const uint32_t N = (uint32_t)a.g.N;
     const int mmax = a.mmax;
     SmallLds L;
@@ -1410,15 +1419,35 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
     L.us = reinterpret_cast<double2 *>(L.red1 + 16);
     L.e1 = e1;
     L.tix = tix;
-    if (threadIdx.x == 0 && a.batched) {
-        int k = 0;
-        for (int e = 0; e < a.n_ent; ++e) {
+    L.ents = ents;
+    if (a.batched) {
+        // one thread per entry stages its fields (independent loads), then
+        // thread 0 numbers the entries with a slot-1 factor from LDS
+        for (int e = threadIdx.x; e < a.n_ent; e += blockDim.x) {
             const DevEntry *E = a.ent + e;
-            if (E->nf >= 1 && E->slot[E->nf - 1] == 1) {
-                tix[e] = k;
-                e1[k++] = e;
-            } else {
-                tix[e] = -1;
+            const int nf = E->nf;
+            EntLite el;
+            el.coef = E->coef;
+            const bool has0 = nf >= 1 && E->slot[0] == 0;
+            const bool has1 = nf >= 1 && E->slot[nf - 1] == 1;
+            el.M0 = has0 ? E->M[0] : nullptr;
+            el.lo0 = has0 ? E->lo[0] : 0;
+            el.hi0 = has0 ? E->hi[0] : 0;
+            el.M1 = has1 ? E->M[nf - 1] : nullptr;
+            el.lo1 = has1 ? E->lo[nf - 1] : 0;
+            el.hi1 = has1 ? E->hi[nf - 1] : 0;
+            ents[e] = el;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int k = 0;
+            for (int e = 0; e < a.n_ent; ++e) {
+                if (ents[e].M1) {
+                    tix[e] = k;
+                    e1[k++] = e;
+                } else {
+                    tix[e] = -1;
+                }
             }
         }
     }
@@ -1895,7 +1924,7 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
 
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     const size_t lds = small_solve_lds_bytes(a.g.N, a.mmax, a.batched, a.nA);
-    if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds + SMALL_MAXENT * sizeof(int) > 160 * 1024 ||
+    if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds + SMALL_STATIC_LDS > 160 * 1024 ||
         (a.batched && (a.g.D != 2 || a.n_ent > SMALL_MAXENT || a.g.dims[0] * a.g.dims[0] > SMALL_UB)))
         throw std::runtime_error("small solve out of range");
     set_lds_limit((const void *)k_small_solve, lds);
