@@ -55,6 +55,27 @@ def roofline(stats):
     return r
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading for a
+    plain copy kernel of known size), or None when there is none or the kernel
+    sources changed after the counters were taken (SHA-256 of kernels.hip)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_vibronic24_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2503_15460_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic: "):
+            rec = json.loads(line[len("traffic: "):])
+    if not rec:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernels_hip_sha256"):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def timed_run(T, p, precision, steps, warmup):
     """Sweeps of the workload from its product state; returns (handle, seconds, counters before, after)."""
     import torch
@@ -210,6 +231,7 @@ def main():
     roof = roofline(stats)
     top = roof["kernel"]
     roof["launches_per_step"] = next(r["calls"] for r in stats if r["name"] == top) / args.profile_steps
+    roof["traffic"] = measured_traffic(top)
 
     # the same run with the FP32 contraction mode (same steps from the same start)
     fp32 = None
