@@ -124,19 +124,31 @@ __device__ bool last_block_ticket(unsigned *counter) {
     return is_last != 0;
 }
 
-// out[q] = sum_b part[b * stride + q] for q < K (doubles), by the whole block in
-// groups of 8 lanes per value (call from the last block only).
-__device__ void blk_reduce_partials(const double *part, int nb, int stride, int K, double *out) {
-    const int sub = threadIdx.x & 7;
-    for (int q0 = 0; q0 < K; q0 += (int)blockDim.x / 8) {
-        const int q = q0 + (int)threadIdx.x / 8;
+
+// Last-block reduction of per-block partial sums: out[q] = sum_b part[b * stride + q]
+// for q < K.  Chunks of the partials are first staged in LDS with independent
+// loads (all threads), then 8 lanes per value sum strided partials in a fixed
+// order and combine them by shuffles.  stage: LDS scratch of KRY_STAGE doubles.
+constexpr int KRY_STAGE = 4096;
+__device__ void blk_reduce_staged(const double *part, int nb, int stride, int K, double *out, double *stage) {
+    const int tid = threadIdx.x;
+    const int ch = max(1, min((int)blockDim.x / 8, KRY_STAGE / nb));  // values per chunk
+    for (int v0 = 0; v0 < K; v0 += ch) {
+        const int cnt = min(ch, K - v0);
+        for (int e = tid; e < nb * cnt; e += blockDim.x) {
+            const int b = e / cnt, t = e - b * cnt;
+            stage[e] = part[(size_t)b * stride + v0 + t];
+        }
+        __syncthreads();
+        const int t = tid / 8, sub = tid & 7;
         double acc = 0.0;
-        if (q < K)
-            for (int b = sub; b < nb; b += 8) acc += part[(size_t)b * stride + q];
+        if (t < cnt)
+            for (int b = sub; b < nb; b += 8) acc += stage[b * cnt + t];
         acc += __shfl_xor(acc, 4, 64);
         acc += __shfl_xor(acc, 2, 64);
         acc += __shfl_xor(acc, 1, 64);
-        if (q < K && sub == 0) out[q] = acc;
+        if (t < cnt && sub == 0) out[v0 + t] = acc;
+        __syncthreads();
     }
 }
 
@@ -624,7 +636,8 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qrm_step(double2 *A, uint32_t L
     if (last_block_ticket(q.counter)) {
         __shared__ double sums[2 + 2 * QRM_MAXN];
         __shared__ double2 sc[2];
-        blk_reduce_partials(q.part, gridDim.x, K, 2 + 2 * n, sums);
+        __shared__ double stage[KRY_STAGE];
+        blk_reduce_staged(q.part, gridDim.x, K, 2 + 2 * n, sums, stage);
         __syncthreads();
         if (tid == 0) {
             double xn2 = sums[0];
@@ -1492,10 +1505,11 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_norm0(const double2 *__rest
     double s = blk_sum1(part, red1);
     if (threadIdx.x == 0) k.part[blockIdx.x] = s;
     if (last_block_ticket(k.counter)) {
-        double t = 0.0;
+        __shared__ double stage[KRY_STAGE];
+        __shared__ double tot[1];
+        blk_reduce_staged(k.part, gridDim.x, 1, 1, tot, stage);
         if (threadIdx.x == 0) {
-            for (unsigned b = 0; b < gridDim.x; ++b) t += k.part[b];
-            k.scal[0] = sqrt(t);
+            k.scal[0] = sqrt(tot[0]);
             *k.meff = 0;
             *k.counter = 0;
         }
@@ -1509,15 +1523,20 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_scale0(const double2 *__res
         k.V[i] = cscale(x[i], ib);
 }
 
-// pass = 0: partial dots of w = V[j+1] against V[0..j] -> h, Hm[:, j] = h
-// pass = 1,2: w -= V h, then (pass 1) dots again (Hm += h) / (pass 2) norm
+// Classical Gram-Schmidt, twice, for w = V[j+1] against V[0..j]:
+//   pass 0: h0 = V^H w                                  -> Hm[:, j] = h0
+//   pass 1: w -= V h0; h1 = V^H w and |w|^2               -> Hm[:, j] += h1,
+//           beta^2 = |w|^2 - |h1|^2 (h1 is rounding-size, no cancellation)
+// k_kry_finalize then forms (w - V h1) / beta.
 __global__ void __launch_bounds__(VEC_THREADS) k_kry_orth(BigKrylov k, uint32_t N, int j, int mmax, int pass) {
     if (*k.meff) return;
     __shared__ double2 red8[16 * 8];
     __shared__ double2 hb[64];
     __shared__ double red1[16];
+    __shared__ double stage[KRY_STAGE];
     const int nv = j + 1;
     double2 *w = k.V + (size_t)(j + 1) * N;
+    double wn = 0.0;
     if (pass > 0) {
         for (int q = threadIdx.x; q < nv; q += blockDim.x) hb[q] = k.h[q];
         __syncthreads();
@@ -1525,60 +1544,67 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_orth(BigKrylov k, uint32_t 
             double2 wv = w[idx];
             for (int i = 0; i < nv; ++i) wv = csub(wv, cmul(hb[i], k.V[(size_t)i * N + idx]));
             w[idx] = wv;
+            wn += cabs2(wv);
         }
+        __syncthreads();
     }
-    const int K = (pass < 2) ? nv : 1;
+    const int K = nv + 1;  // doubles pairs per block: h (complex) and |w|^2
     double *part = k.part;
-    if (pass < 2) {
-        for (int i0 = 0; i0 < nv; i0 += 8) {
-            const int cnt = min(8, nv - i0);
-            double2 acc[8];
-            for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
-            for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
-                const double2 wv = w[idx];
-                for (int q = 0; q < cnt; ++q) cfmac(acc[q], k.V[(size_t)(i0 + q) * N + idx], wv);
-            }
-            blk_sum8(acc, cnt, red8, hb + i0);
+    for (int i0 = 0; i0 < nv; i0 += 8) {
+        const int cnt = min(8, nv - i0);
+        double2 acc[8];
+        for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+        for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+            const double2 wv = w[idx];
+            for (int q = 0; q < cnt; ++q) cfmac(acc[q], k.V[(size_t)(i0 + q) * N + idx], wv);
         }
-        if (threadIdx.x < nv) {
-            part[2 * ((size_t)blockIdx.x * K + threadIdx.x)] = hb[threadIdx.x].x;
-            part[2 * ((size_t)blockIdx.x * K + threadIdx.x) + 1] = hb[threadIdx.x].y;
-        }
-    } else {
-        double p = 0.0;
-        for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x)
-            p += cabs2(w[idx]);
-        double s = blk_sum1(p, red1);
-        if (threadIdx.x == 0) part[2 * (size_t)blockIdx.x] = s;
+        blk_sum8(acc, cnt, red8, hb + i0);
+    }
+    const double wns = pass == 1 ? blk_sum1(wn, red1) : 0.0;
+    if (threadIdx.x < nv) {
+        part[2 * ((size_t)blockIdx.x * K + threadIdx.x)] = hb[threadIdx.x].x;
+        part[2 * ((size_t)blockIdx.x * K + threadIdx.x) + 1] = hb[threadIdx.x].y;
+    }
+    if (threadIdx.x == 0) {
+        part[2 * ((size_t)blockIdx.x * K + nv)] = wns;
+        part[2 * ((size_t)blockIdx.x * K + nv) + 1] = 0.0;
     }
     if (last_block_ticket(k.counter)) {
-        __shared__ double sums[2 * 64];
-        const int nd = pass < 2 ? 2 * nv : 1;
-        blk_reduce_partials(part, gridDim.x, pass < 2 ? 2 * K : 2, nd, sums);
+        __shared__ double sums[2 * 65];
+        blk_reduce_staged(part, gridDim.x, 2 * K, 2 * K, sums, stage);
         __syncthreads();
-        if (pass < 2) {
-            for (int q = threadIdx.x; q < nv; q += blockDim.x) {
-                const double2 s = make_double2(sums[2 * q], sums[2 * q + 1]);
-                k.h[q] = s;
-                double2 *hcol = k.Hm + (size_t)j * (mmax + 1);
-                hcol[q] = pass == 0 ? s : cadd(hcol[q], s);
-            }
-        } else if (threadIdx.x == 0) {
-            const double beta = sqrt(sums[0]);
+        double2 *hcol = k.Hm + (size_t)j * (mmax + 1);
+        for (int q = threadIdx.x; q < nv; q += blockDim.x) {
+            const double2 sv = make_double2(sums[2 * q], sums[2 * q + 1]);
+            k.h[q] = sv;
+            hcol[q] = pass == 0 ? sv : cadd(hcol[q], sv);
+        }
+        if (pass == 1 && threadIdx.x == 0) {
+            double b2 = sums[2 * nv];
+            for (int q = 0; q < nv; ++q) b2 -= sums[2 * q] * sums[2 * q] + sums[2 * q + 1] * sums[2 * q + 1];
+            const double beta = sqrt(fmax(b2, 0.0));
             k.scal[1] = beta;
-            k.Hm[(size_t)j * (mmax + 1) + j + 1] = make_double2(beta, 0.0);
+            hcol[j + 1] = make_double2(beta, 0.0);
             if (beta <= 1e-14 * k.scal[0]) *k.meff = j + 1;
         }
         if (threadIdx.x == 0) *k.counter = 0;
     }
 }
 
-__global__ void __launch_bounds__(VEC_THREADS) k_kry_normalize(BigKrylov k, uint32_t N, int j) {
+// w = (w - V h1) / beta (no-op after a breakdown)
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_finalize(BigKrylov k, uint32_t N, int j) {
     if (*k.meff) return;
+    __shared__ double2 hb[64];
+    const int nv = j + 1;
+    for (int q = threadIdx.x; q < nv; q += blockDim.x) hb[q] = k.h[q];
+    __syncthreads();
     const double ib = 1.0 / k.scal[1];
     double2 *w = k.V + (size_t)(j + 1) * N;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x)
-        w[idx] = cscale(w[idx], ib);
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+        double2 wv = w[idx];
+        for (int i = 0; i < nv; ++i) wv = csub(wv, cmul(hb[i], k.V[(size_t)i * N + idx]));
+        w[idx] = cscale(wv, ib);
+    }
 }
 
 // exp of the projected matrix (one work-group); y = beta0 exp(-i tau H_m) e_0
@@ -1965,13 +1991,13 @@ void launch_krylov_start(const double2 *x, int64_t N, const BigKrylov &k, hipStr
 
 void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st) {
     const unsigned nb = vec_blocks(N);
-    for (int pass = 0; pass < 3; ++pass)
-        TTN_LAUNCH("k_kry_orth", 8.0 * N * (j + 1) * (pass == 0 ? 1 : (pass == 1 ? 2 : 1)) + 4.0 * N,
-                   16.0 * N * ((pass == 0 ? 1 : 2) * (j + 1) + (pass == 0 ? 1 : 2)), k_kry_orth, dim3(nb),
-                   dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, pass);
-    TTN_LAUNCH("k_kry_normalize", 2.0 * N, 32.0 * N, k_kry_normalize, dim3(grid_for(N, VEC_THREADS)),
-               dim3(VEC_THREADS), 0, st, k,
-                       (uint32_t)N, j);
+    const double nv = j + 1;
+    TTN_LAUNCH("k_kry_orth", 8.0 * N * nv, 16.0 * N * (nv + 1), k_kry_orth, dim3(nb), dim3(VEC_THREADS), 0, st, k,
+               (uint32_t)N, j, mmax, 0);
+    TTN_LAUNCH("k_kry_orth", 16.0 * N * nv + 4.0 * N, 16.0 * N * (2 * nv + 2), k_kry_orth, dim3(nb),
+               dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, 1);
+    TTN_LAUNCH("k_kry_finalize", 8.0 * N * nv + 2.0 * N, 16.0 * N * (nv + 2), k_kry_finalize,
+               dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j);
 }
 
 void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double tau, double tol, int hermitian,
