@@ -62,6 +62,11 @@ typedef int32_t ttn_status;
  * Observables are then accurate to the FP32 contractions (about 1e-6). */
 #define TTN_FP64 0
 #define TTN_FP32 1
+/* TTN_BF16X3: as TTN_FP32, and the dense operator stages whose factors have
+ * dimensions 24..64 run on the matrix cores with split precision: each FP32
+ * operand is split into bf16 hi + lo and products are taken as hi*hi + hi*lo +
+ * lo*hi with FP32 accumulation (about 1e-5 relative per contraction). */
+#define TTN_BF16X3 2
 
 /* observable kinds for ttn_observe */
 #define TTN_OBS_EXPECT 0      /* <Psi| prod_i op_ids[i] |Psi>, ops on distinct leaves */
@@ -74,8 +79,8 @@ typedef struct ttn_ctx *ttn_t;
 typedef struct ttn_batch_ctx *ttn_batch_t;
 
 typedef struct {
-    int32_t precision;   /* TTN_FP64 or TTN_FP32 */
-    double krylov_tol;   /* local exponential error target, relative (0 -> 1e-13, FP32: 1e-10) */
+    int32_t precision;   /* TTN_FP64, TTN_FP32 or TTN_BF16X3 */
+    double krylov_tol;   /* local exponential error target, relative (0 -> 1e-13, FP32/BF16X3: 1e-10) */
     int32_t krylov_mmax; /* max Krylov dimension per solve (0 -> 40) */
     int32_t hermitian;   /* 1: Lanczos (G must be Hermitian), 0: Arnoldi */
     void *hip_stream;    /* hipStream_t for all work of the handle, NULL = null stream */

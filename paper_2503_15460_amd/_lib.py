@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("TTN_LIBRARY", os.path.join(HERE, "libttn.so"))
 TTN_OK = 0
 ERRORS = {-1: "TTN_E_INVALID", -2: "TTN_E_TREE", -3: "TTN_E_DIMS", -4: "TTN_E_OOM", -5: "TTN_E_DEVICE",
           -6: "TTN_E_NOCONV", -7: "TTN_E_STATE"}
-TTN_FP64, TTN_FP32 = 0, 1
+TTN_FP64, TTN_FP32, TTN_BF16X3 = 0, 1, 2
 OBS_EXPECT, OBS_NORM, OBS_ENERGY, OBS_OVERLAP_T0, OBS_BILINEAR = 0, 1, 2, 3, 4
 
 # every symbol declared in include/ttn.h and include/ttn_debug.h

@@ -78,8 +78,8 @@ ttn_status ttn_create(int32_t n_nodes, const int32_t *parent, const int32_t *loc
         ttn_options o;
         ttn_default_options(&o);
         if (opt) o = *opt;
-        if (o.precision != TTN_FP64 && o.precision != TTN_FP32)
-            throw ttn::Error(TTN_E_INVALID, "precision must be TTN_FP64 or TTN_FP32");
+        if (o.precision != TTN_FP64 && o.precision != TTN_FP32 && o.precision != TTN_BF16X3)
+            throw ttn::Error(TTN_E_INVALID, "precision must be TTN_FP64, TTN_FP32 or TTN_BF16X3");
         ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, bond_dim);
         auto h = std::make_unique<ttn_ctx>();
         h->eng = std::make_unique<ttn::Engine>(t, o);

@@ -66,6 +66,7 @@ private:
     std::vector<std::vector<Prog>> mfP;
     std::vector<void *> sop_allocs;
     double2 *tmp = nullptr, *gsum = nullptr, *cpart = nullptr;
+    unsigned short *mprep = nullptr;  // BF16x3 split factors
     double2 *Rbuf = nullptr, *Cbuf = nullptr, *smallV = nullptr, *obs = nullptr, *snapshot = nullptr;
     int64_t obs_elems = 0;
     BigKrylov bk{};

@@ -142,7 +142,9 @@ ProgView Engine::view(const Prog &p) const {
     v.tmp = tmp;
     v.gsum = gsum;
     v.cpart = cpart;
-    v.f32 = opt.precision == TTN_FP32 ? 1 : 0;
+    v.f32 = (opt.precision == TTN_FP32 || opt.precision == TTN_BF16X3) ? 1 : 0;
+    v.bf16x3 = opt.precision == TTN_BF16X3 ? 1 : 0;
+    v.mprep = mprep;
     for (int f = 0; f < MAXF; ++f) {
         v.sflops[f] = p.sflops[f];
         // FP32 temporaries: stage 0 reads FP64 and writes FP32, later stages FP32 both ways
@@ -442,6 +444,17 @@ void Engine::set_sop(const SopInput &s) {
     }
     cpart_e = std::max<int64_t>(cpart_e, 64 * 64 * 64);
     tmp = (double2 *)dalloc(sizeof(double2) * tmp_e);
+    if (opt.precision == TTN_BF16X3) {  // split factors of the matrix-core stages
+        size_t ents = 1;
+        for (int z = 0; z < n; ++z) {
+            ents = std::max(ents, heffP[z].ents.size());
+            if (z != t.root) ents = std::max(ents, std::max(spoP[z].ents.size(), bondP[z].ents.size()));
+            for (auto &m : mfP[z]) ents = std::max(ents, m.ents.size());
+        }
+        mprep = (unsigned short *)dalloc(sizeof(unsigned short) * ents * 2 * 128 * 128);
+    } else {
+        mprep = nullptr;
+    }
     gsum = (double2 *)dalloc(sizeof(double2) * gsum_e);
     cpart = (double2 *)dalloc(sizeof(double2) * cpart_e);
     Rbuf = (double2 *)dalloc(sizeof(double2) * maxb2);
@@ -657,7 +670,7 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
     const bool fused = use_fused(p);
     solve_small[si] = fused ? 1 : 0;
     SolveStat *stat = d_stats + si;
-    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP32 ? 1e-10 : 1e-13);
+    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP64 ? 1e-13 : 1e-10);
     if (fused) {
         SmallSolveArgs a{};
         a.g = p.g;
@@ -792,7 +805,7 @@ void Engine::enqueue_step(double dt) {
 // multi-kernel solve missed its tolerance, restore the snapshot and run the
 // sweep again (synchronously) with larger dimensions.
 void Engine::finish_step(double dt) {
-    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP32 ? 1e-10 : 1e-13);
+    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP64 ? 1e-13 : 1e-10);
     while (true) {
         hipError_t e = hipEventSynchronize(step_done);
         if (e == hipSuccess) e = hipGetLastError();

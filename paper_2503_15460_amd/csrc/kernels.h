@@ -57,6 +57,8 @@ struct ProgView {
     double2 *const *gdst;     // contraction destination per group (env programs)
     int contract_slot;        // -1: none
     int f32;                  // 1: stages, group sums and contractions in complex FP32
+    int bf16x3;               // 1 (with f32): dense stages with factors of 24..64 on BF16x3 MFMA
+    unsigned short *mprep;    // bf16 hi/lo realified factors, n_ent * 2 * 128 * 128 (BF16x3 mode)
     double2 *tmp;             // 2 * n_ent * N (float2 elements in the FP32 mode)
     double2 *gsum;            // n_groups * N (float2 elements in the FP32 mode)
     double2 *cpart;           // contraction partials

@@ -290,6 +290,154 @@ __global__ void __launch_bounds__(256) k_mode_tile(ProgView p, int stage, const 
     }
 }
 
+// ------------------------------------------------------------ BF16x3 MFMA stage
+// Complex mode product as one real GEMM per column tile.  Realified with
+// interleaved parts: row 2i+a and column 2j+b of Mt hold the 2x2 real block
+// [[Re, -Im], [Im, Re]] of M[i][j]; Xt row 2j+b holds part b of X[j].  The
+// realified dimension RD = 32 RT covers 2n.  Every FP32 operand is split into
+// bf16 hi + lo and the product taken as hi*hi + hi*lo + lo*hi
+// (v_mfma_f32_32x32x8 bf16, FP32 accumulation; the dropped lo*lo term is
+// ~2^-16 relative).  Mt of every entry is split once per stage launch by
+// k_mfma_prep; a work-group (4 waves x 32 columns) stages chunks of 32
+// realified K of Mt and Xt in LDS; each wave holds all RT row tiles of its
+// columns.
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ void bf16_split(float x, unsigned short &hi, unsigned short &lo) {
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - __uint_as_float((unsigned)hi << 16));
+}
+
+constexpr int MF_CW = 128;  // columns per work-group
+constexpr int MF_KC = 32;   // realified K per LDS chunk
+constexpr int MF_KP = MF_KC / 4 + 1;  // bf4 per LDS row (one of padding)
+
+// Mt hi / lo of every entry with a factor at this stage: mprep[(e * 2 + h) * RD * RD + row * RD + col]
+__global__ void __launch_bounds__(256) k_mfma_prep(ProgView p, int stage, int RD, unsigned short *mprep) {
+    const int e = blockIdx.y;
+    const DevEntry *E = p.ent + e;
+    if (E->nf <= stage) return;
+    const int n = p.g.dims[E->slot[stage]];
+    const double2 *M = E->M[stage];
+    unsigned short *hi = mprep + (size_t)e * 2 * RD * RD, *lo = hi + (size_t)RD * RD;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < RD * RD; q += gridDim.x * blockDim.x) {
+        const int row = q / RD, col = q - row * RD;
+        const int i = row >> 1, j = col >> 1, a = row & 1, b2 = col & 1;
+        float v = 0.0f;
+        if (i < n && j < n) {
+            const double2 m = M[(size_t)i * n + j];
+            v = a == 0 ? (b2 == 0 ? (float)m.x : -(float)m.y) : (b2 == 0 ? (float)m.y : (float)m.x);
+        }
+        unsigned short h, l;
+        bf16_split(v, h, l);
+        hi[q] = h;
+        lo[q] = l;
+    }
+}
+
+template <typename TS, int RT>
+__global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const TS *__restrict__ in,
+                                                   const unsigned short *__restrict__ mprep) {
+    constexpr int RD = 32 * RT;
+    __shared__ bf4 Ah[RD * MF_KP], Al[RD * MF_KP];
+    __shared__ bf4 Bh[MF_CW * MF_KP], Bl[MF_CW * MF_KP];  // [col][k / 4]
+    const int e = blockIdx.y;
+    const DevEntry *E = p.ent + e;
+    if (E->nf <= stage) return;
+    const int s = E->slot[stage];
+    const int n = p.g.dims[s];
+    const uint32_t R = (uint32_t)p.g.R[s];
+    const uint32_t N = (uint32_t)p.g.N;
+    const uint32_t ncol = N / (uint32_t)n;
+    const uint32_t c0 = blockIdx.x * (uint32_t)MF_CW;
+    if (c0 >= ncol) return;
+    const unsigned short *mhi = mprep + (size_t)e * 2 * RD * RD, *mlo = mhi + (size_t)RD * RD;
+    float2 *tmp = reinterpret_cast<float2 *>(p.tmp);
+    const TS *__restrict__ src =
+        stage == 0 ? in : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
+    float2 *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nR = (uint32_t)n * R;
+    f32x16 acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[t][v] = 0.0f;
+    const int kmax = min(RD, 2 * n);
+    for (int k0 = 0; k0 < kmax; k0 += MF_KC) {
+        __syncthreads();
+        // Mt chunk: RD rows x 32 columns as bf4 groups (8-byte copies)
+        for (int q = tid; q < RD * (MF_KC / 4); q += 256) {
+            const int row = q / (MF_KC / 4), g = q - row * (MF_KC / 4);
+            Ah[row * MF_KP + g] = *reinterpret_cast<const bf4 *>(mhi + (size_t)row * RD + k0 + 4 * g);
+            Al[row * MF_KP + g] = *reinterpret_cast<const bf4 *>(mlo + (size_t)row * RD + k0 + 4 * g);
+        }
+        // Xt chunk: 16 complex j per column, both parts from one load
+        const int j0 = k0 / 2;
+        for (int q = tid; q < MF_CW * (MF_KC / 2); q += 256) {
+            int cc, jj;
+            if (R == 1) {  // columns are rows of a row-major (ncol, n) matrix: j fastest
+                jj = q % (MF_KC / 2);
+                cc = q / (MF_KC / 2);
+            } else {
+                cc = q % MF_CW;
+                jj = q / MF_CW;
+            }
+            const int j = j0 + jj;
+            const uint32_t c = c0 + cc;
+            float vr = 0.0f, vi = 0.0f;
+            if (c < ncol && j < n) {
+                const uint32_t l = c / R, r = c - l * R;
+                const TS x = src[(size_t)l * nR + (size_t)j * R + r];
+                vr = (float)x.x;
+                vi = (float)x.y;
+            }
+            unsigned short hr, lr, hi2, li;
+            bf16_split(vr, hr, lr);
+            bf16_split(vi, hi2, li);
+            short *bh = reinterpret_cast<short *>(Bh + cc * MF_KP);
+            short *bl = reinterpret_cast<short *>(Bl + cc * MF_KP);
+            bh[2 * jj] = (short)hr;
+            bh[2 * jj + 1] = (short)hi2;
+            bl[2 * jj] = (short)lr;
+            bl[2 * jj + 1] = (short)li;
+        }
+        __syncthreads();
+        const int col = wave * 32 + (lane & 31);
+        const int kg = lane >> 5;  // this lane's group of 4 within each 8-wide K step
+#pragma unroll
+        for (int ks = 0; ks < MF_KC / 4; ks += 2) {
+            const bf4 bh = Bh[col * MF_KP + ks + kg], bl = Bl[col * MF_KP + ks + kg];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const int row = t * 32 + (lane & 31);
+                const bf4 ah = Ah[row * MF_KP + ks + kg], al = Al[row * MF_KP + ks + kg];
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // the lane holds rows t*32 + (v/4)*8 + (lane/32)*4 + v%4: pairs (2i, 2i+1) in (v, v+1), v even
+    const uint32_t c = c0 + wave * 32 + (lane & 31);
+    if (c < ncol) {
+        const uint32_t l = c / R, r = c - l * R;
+        float2 *yp = dst + (size_t)l * nR + r;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 16; v += 2) {
+                const int i = (t * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3)) >> 1;
+                if (i < n) yp[(size_t)i * R] = make_float2(acc[t][v], acc[t][v + 1]);
+            }
+    }
+}
+
 // Coefficient-weighted sum of the entries of each group.  Entries without
 // factors read the FP64 input; the others read their last temporary (type T).
 // Output: out_single (FP64, one group) or the group sums p.gsum (type T).
@@ -1784,7 +1932,39 @@ static void launch_mode_tile_t(const ProgView &p, int s, const TS *in, hipStream
     else go(k_mode_tile<TS, T, 4, 16>, 64);
 }
 
+static void launch_mode_mfma(const ProgView &p, int s, const double2 *in, hipStream_t st) {
+    const uint32_t maxcol = (uint32_t)(p.g.N / p.snmin[s]);
+    dim3 grid((maxcol + MF_CW - 1) / MF_CW, p.n_ent);
+    const int RT = (p.snmax[s] + 15) / 16;
+    const int RD = 32 * RT;
+    TTN_LAUNCH("k_mfma_prep", 0.0, 4.0 * RD * RD * p.n_ent, k_mfma_prep, dim3(4, p.n_ent), dim3(256), 0, st, p, s,
+               RD, p.mprep);
+    const unsigned short *mp = p.mprep;
+    const float2 *none = nullptr;
+#define TTN_MFMA_CASE(RTV)                                                                                      \
+    case RTV:                                                                                                   \
+        if (s == 0)                                                                                             \
+            TTN_LAUNCH("k_mode_mfma", p.sflops[s], p.sbytes[s], (k_mode_mfma<double2, RTV>), grid, dim3(256), 0, \
+                       st, p, s, in, mp);                                                                       \
+        else                                                                                                    \
+            TTN_LAUNCH("k_mode_mfma", p.sflops[s], p.sbytes[s], (k_mode_mfma<float2, RTV>), grid, dim3(256), 0,  \
+                       st, p, s, none, mp);                                                                     \
+        break;
+    switch (RT) {
+        TTN_MFMA_CASE(2)
+        TTN_MFMA_CASE(3)
+        TTN_MFMA_CASE(4)
+    default: throw std::runtime_error("MFMA stage shape out of range");
+    }
+#undef TTN_MFMA_CASE
+}
+
 static void launch_mode_tile(const ProgView &p, int s, const double2 *in, hipStream_t st) {
+    // BF16x3 mode: dense stages with factors of 24..64 on the matrix cores
+    if (p.bf16x3 && p.mprep && p.snmin[s] >= 24 && p.snmax[s] <= 64) {
+        launch_mode_mfma(p, s, in, st);
+        return;
+    }
     if (p.f32) {
         if (s == 0) launch_mode_tile_t<double2, float2>(p, s, in, st, "k_mode_tile_f32");
         else launch_mode_tile_t<float2, float2>(p, s, (const float2 *)nullptr, st, "k_mode_tile_f32");
