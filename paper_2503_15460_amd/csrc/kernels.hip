@@ -369,17 +369,24 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[t][v] = 0.0f;
     const int kmax = min(RD, 2 * n);
-    for (int k0 = 0; k0 < kmax; k0 += MF_KC) {
-        __syncthreads();
-        // Mt chunk: RD rows x 32 columns as bf4 groups (8-byte copies)
-        for (int q = tid; q < RD * (MF_KC / 4); q += 256) {
+    // software pipeline: the global loads of chunk k0 + 32 are in flight while
+    // the matrix cores work on chunk k0
+    constexpr int MQ = RD * (MF_KC / 4) / 256;   // bf4 of each Mt chunk array per thread
+    constexpr int XQ = MF_CW * (MF_KC / 2) / 256;  // complex X values per thread
+    bf4 mh[MQ], ml[MQ];
+    float2 xv[XQ];
+    auto load_chunk = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < MQ; ++u) {
+            const int q = tid + 256 * u;
             const int row = q / (MF_KC / 4), g = q - row * (MF_KC / 4);
-            Ah[row * MF_KP + g] = *reinterpret_cast<const bf4 *>(mhi + (size_t)row * RD + k0 + 4 * g);
-            Al[row * MF_KP + g] = *reinterpret_cast<const bf4 *>(mlo + (size_t)row * RD + k0 + 4 * g);
+            mh[u] = *reinterpret_cast<const bf4 *>(mhi + (size_t)row * RD + k0 + 4 * g);
+            ml[u] = *reinterpret_cast<const bf4 *>(mlo + (size_t)row * RD + k0 + 4 * g);
         }
-        // Xt chunk: 16 complex j per column, both parts from one load
         const int j0 = k0 / 2;
-        for (int q = tid; q < MF_CW * (MF_KC / 2); q += 256) {
+#pragma unroll
+        for (int u = 0; u < XQ; ++u) {
+            const int q = tid + 256 * u;
             int cc, jj;
             if (R == 1) {  // columns are rows of a row-major (ncol, n) matrix: j fastest
                 jj = q % (MF_KC / 2);
@@ -390,16 +397,37 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
             }
             const int j = j0 + jj;
             const uint32_t c = c0 + cc;
-            float vr = 0.0f, vi = 0.0f;
+            float2 v = make_float2(0.0f, 0.0f);
             if (c < ncol && j < n) {
                 const uint32_t l = c / R, r = c - l * R;
                 const TS x = src[(size_t)l * nR + (size_t)j * R + r];
-                vr = (float)x.x;
-                vi = (float)x.y;
+                v = make_float2((float)x.x, (float)x.y);
+            }
+            xv[u] = v;
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int u = 0; u < MQ; ++u) {
+            const int q = tid + 256 * u;
+            const int row = q / (MF_KC / 4), g = q - row * (MF_KC / 4);
+            Ah[row * MF_KP + g] = mh[u];
+            Al[row * MF_KP + g] = ml[u];
+        }
+#pragma unroll
+        for (int u = 0; u < XQ; ++u) {
+            const int q = tid + 256 * u;
+            int cc, jj;
+            if (R == 1) {
+                jj = q % (MF_KC / 2);
+                cc = q / (MF_KC / 2);
+            } else {
+                cc = q % MF_CW;
+                jj = q / MF_CW;
             }
             unsigned short hr, lr, hi2, li;
-            bf16_split(vr, hr, lr);
-            bf16_split(vi, hi2, li);
+            bf16_split(xv[u].x, hr, lr);
+            bf16_split(xv[u].y, hi2, li);
             short *bh = reinterpret_cast<short *>(Bh + cc * MF_KP);
             short *bl = reinterpret_cast<short *>(Bl + cc * MF_KP);
             bh[2 * jj] = (short)hr;
@@ -407,9 +435,15 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
             bl[2 * jj] = (short)lr;
             bl[2 * jj + 1] = (short)li;
         }
-        __syncthreads();
-        const int col = wave * 32 + (lane & 31);
-        const int kg = lane >> 5;  // this lane's group of 4 within each 8-wide K step
+    };
+    load_chunk(0);
+    store_chunk();
+    __syncthreads();
+    const int col = wave * 32 + (lane & 31);
+    const int kg = lane >> 5;  // this lane's group of 4 within each 8-wide K step
+    for (int k0 = 0; k0 < kmax; k0 += MF_KC) {
+        const bool more = k0 + MF_KC < kmax;
+        if (more) load_chunk(k0 + MF_KC);
 #pragma unroll
         for (int ks = 0; ks < MF_KC / 4; ks += 2) {
             const bf4 bh = Bh[col * MF_KP + ks + kg], bl = Bl[col * MF_KP + ks + kg];
@@ -421,6 +455,11 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
                 acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[t], 0, 0, 0);
                 acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[t], 0, 0, 0);
             }
+        }
+        if (more) {
+            __syncthreads();
+            store_chunk();
+            __syncthreads();
         }
     }
     // the lane holds rows t*32 + (v/4)*8 + (lane/32)*4 + v%4: pairs (2i, 2i+1) in (v, v+1), v even
