@@ -1,0 +1,72 @@
+"""Exciton-model trees on the GPU against the oracle: nodes with five composite
+leaves (6 tensor slots), one-child nodes and a 3-state electronic leaf; the
+FP64 path to 1e-10, the FP32 and BF16x3 modes to 1e-4 on populations and the
+autocorrelation (full-rank starts)."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from workloads import exciton_problem, random_isometric_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_15460_amd as mod
+    return mod
+
+
+def _obs(src, p):
+    return np.array([src.expect(p.observables[f"P{k}"]) for k in range(3)] + [src.overlap_t0()])
+
+
+def _reference(p, st, n):
+    o = Oracle(p)
+    o.set_state(st)
+    out = []
+    for _ in range(n):
+        o.step(p.dt)
+        out.append(_obs(o, p))
+    return np.array(out)
+
+
+def _run(T, p, st, n, precision):
+    g = T.TTN.from_problem(p, precision=precision)
+    g.set_state(st)
+    T.profile_begin()
+    out = []
+    for _ in range(n):
+        g.step(p.dt)
+        out.append(_obs(g, p))
+    names = {r["name"] for r in T.profile_end()}
+    g.close()
+    return np.array(out), names
+
+
+def test_exciton_tree_fp64_parity(T):
+    p = exciton_problem(n_states=3, n_modes=40, dmin=2, dmax=3, leaf_bond=3, c_bond=6, b_bond=8, a_bond=10,
+                        n_inter=8)
+    st = random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=12)
+    ref = _reference(p, st, 3)
+    got, _ = _run(T, p, st, 3, T.TTN_FP64)
+    assert np.abs(got - ref).max() < 1e-10
+
+
+def test_exciton_tree_mixed_precisions(T):
+    """Bonds of 24: the two-child nodes' stages qualify for the matrix cores."""
+    p = exciton_problem(n_states=3, n_modes=40, dmin=2, dmax=3, leaf_bond=3, c_bond=24, b_bond=24, a_bond=24,
+                        n_inter=8)
+    st = random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=13)
+    ref = _reference(p, st, 2)
+    got, _ = _run(T, p, st, 2, T.TTN_FP64)
+    assert np.abs(got - ref).max() < 1e-10
+    for prec in (T.TTN_FP32, T.TTN_BF16X3):
+        got, names = _run(T, p, st, 2, prec)
+        err = np.abs(got - ref).max()
+        print(f"precision {prec}: max error {err:.2e}")
+        assert err < 1e-4
+        assert ("k_mode_mfma" in names) == (prec == T.TTN_BF16X3)
