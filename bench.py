@@ -151,6 +151,35 @@ def exciton_run(T, steps: int):
     return out
 
 
+def heom_run(T, steps: int):
+    """HEOM spin-boson (Debye bath, K = 16 poles, 32 auxiliary modes x 10
+    levels, bonds 10-48, Arnoldi): FP64 and FP32 sweeps/s and the FP32
+    difference of <sigma_z> and Tr rho_S against FP64."""
+    from workloads import heom_sbm_problem
+    p = heom_sbm_problem()
+    S = p.leaf_names["S"]
+
+    def obs(g):
+        out = []
+        for key in ("bra_sz", "bra_tr"):
+            bra = {z: np.eye(p.local_dim[z])[0].astype(np.complex128) for z in p.leaves()}
+            bra[S] = p.meta[key]
+            out.append(g.bilinear(bra))
+        return np.array(out)
+    out, vals = {}, {}
+    for prec, name in ((T.TTN_FP64, "fp64"), (T.TTN_FP32, "fp32")):
+        g, el, c0, c1 = timed_run(T, p, prec, steps, 1)
+        vals[name] = obs(g)
+        out[name] = {"value": steps / el, "unit": "sweeps/s", "ms_per_step": 1e3 * el / steps,
+                     "heff_tflops": (c1["heff_flops"] - c0["heff_flops"]) / el / 1e12}
+        g.close()
+    out["sigma_z_trace_fp64"] = [float(vals["fp64"][0].real), float(vals["fp64"][1].real)]
+    out["fp32_max_abs_diff_vs_fp64"] = float(np.abs(vals["fp64"] - vals["fp32"]).max())
+    out["workload"] = (f"heom_sbm: eps 0.5, Delta 1, Debye lambda 0.2 gamma 1 T 1, 16 poles, 32 auxiliary modes x "
+                       f"10 levels, binary tree, bonds 10-48, non-Hermitian (Arnoldi), dt 0.0075, {1 + steps} sweeps")
+    return out
+
+
 def batch_run(T, n_inst: int, steps: int):
     """Uneven spin-boson instances (8-64 modes, 6-16 levels, bonds 8-48): one
     at a time in FP64 against one batch (FP64 and FP32) on 8 streams."""
@@ -275,6 +304,7 @@ def main():
     }
     if not args.no_extra:
         out["config"]["exciton10x120"] = exciton_run(T, 1)
+        out["config"]["heom_sbm"] = heom_run(T, 3)
         out["config"]["batched_instances"] = batch_run(T, args.batch_instances, 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)

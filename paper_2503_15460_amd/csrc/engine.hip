@@ -641,12 +641,12 @@ void Engine::build_mf(int z, int k) {
 
 void Engine::qr_slot(int z, int s, double2 *Rout, int transR) {
     const Geom g = heffP[z].g;
-    if (g.N >= QR_MULTI_MIN) {
-        if (!launch_qr_coop(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st))
-            launch_qr_multi(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st);
-    } else {
-        launch_qr(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, st);
-    }
+    // wide factors of mid-size tensors also leave the single work-group kernel:
+    // its column loop is sequential on one compute unit
+    const bool coop = g.N >= QR_MULTI_MIN || (g.N >= 4096 && g.dims[s] >= 16);
+    if (coop && launch_qr_coop(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st)) return;
+    if (g.N >= QR_MULTI_MIN) launch_qr_multi(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st);
+    else launch_qr(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, st);
 }
 
 void Engine::absorb(int z, int s, const double2 *M, int transM) {
