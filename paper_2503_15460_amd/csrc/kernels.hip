@@ -1301,21 +1301,22 @@ __device__ void blk_expm_col0(const double2 *H, int ldh, int m, double tau, doub
         P[q] = make_double2((q / m) == (q % m) ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
+    // Horner form P <- I + X P / k and the squarings, ping-ponging between two
+    // buffers (one barrier per product)
     for (int k = 14; k >= 1; --k) {
+        const double inv = 1.0 / k;
         for (int q = tid; q < m * m; q += nt) {
             int i = q / m, c = q % m;
             double2 acc = make_double2(0.0, 0.0);
             for (int t = 0; t < m; ++t) cfma(acc, X[i * m + t], P[t * m + c]);
+            acc = cscale(acc, inv);
+            if (i == c) acc.x += 1.0;
             T[q] = acc;
         }
         __syncthreads();
-        const double inv = 1.0 / k;
-        for (int q = tid; q < m * m; q += nt) {
-            double2 v = cscale(T[q], inv);
-            if ((q / m) == (q % m)) v.x += 1.0;
-            P[q] = v;
-        }
-        __syncthreads();
+        double2 *sw = P;
+        P = T;
+        T = sw;
     }
     for (int r = 0; r < s; ++r) {
         for (int q = tid; q < m * m; q += nt) {
@@ -1325,8 +1326,9 @@ __device__ void blk_expm_col0(const double2 *H, int ldh, int m, double tau, doub
             T[q] = acc;
         }
         __syncthreads();
-        for (int q = tid; q < m * m; q += nt) P[q] = T[q];
-        __syncthreads();
+        double2 *sw = P;
+        P = T;
+        T = sw;
     }
     for (int i = tid; i < m; i += nt) y[i] = P[i * m];
     __syncthreads();
@@ -1550,7 +1552,7 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
         if (tid == 0) L.Hm[(j + 1) * mmax + j] = make_double2(beta, 0.0);
         __syncthreads();
         const bool breakdown = beta <= 1e-14 * beta0;
-        if (breakdown || j + 1 >= a.m_hint - 2 || j == mmax - 1) {
+        if (breakdown || j + 1 >= a.m_hint - 1 || j == mmax - 1) {
             // projected matrix of dimension j+1 (tridiagonal for Hermitian G)
             double2 *Hs = L.r1;
             const int m = j + 1;
