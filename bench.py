@@ -269,6 +269,16 @@ def main():
     top = roof["kernel"]
     roof["launches_per_step"] = next(r["calls"] for r in stats if r["name"] == top) / args.profile_steps
     roof["traffic"] = measured_traffic(top)
+    # the H_eff stage kernel of the same pass against its own (HBM) roofline
+    tile = [r for r in stats if r["name"] == "k_mode_tile"]
+    stage_roof = None
+    if tile:
+        r = tile[0]
+        s_avg = r["total_ms"] / 1e3 / r["calls"]
+        gbs = r["bytes"] / r["calls"] / s_avg / 1e9
+        stage_roof = {"kernel": "k_mode_tile", "bound": "hbm", "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
+                      "frac": gbs / PEAK_HBM_GBS, "tflops": r["flops"] / r["calls"] / s_avg / 1e12,
+                      "avg_launch_us": s_avg * 1e6, "launches_per_step": r["calls"] / args.profile_steps}
 
     # the same run with the FP32 contraction mode (same steps from the same start)
     fp32 = None
@@ -297,7 +307,7 @@ def main():
                    "precision": "fp64", "heff_tflops": heff_tflops,
                    "heff_frac_fp64_peak": heff_tflops / PEAK_FP64_TFLOPS,
                    "populations_after": pops, "redo_steps": c1["redo"] - c0["redo"],
-                   "fp32_mixed": fp32},
+                   "fp32_mixed": fp32, "heff_stage_roofline": stage_roof},
         "roofline": roof,
         "kernels": sorted(({k: (v if k != "name" else v) for k, v in r.items()} for r in stats),
                           key=lambda r: -r["total_ms"])[:8],

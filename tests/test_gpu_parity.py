@@ -208,3 +208,22 @@ def test_heom_arnoldi_parity(T, K, levels, bonds, n_steps, tol):
         o.step(p.dt)
         assert np.abs(_heom_obs(g, p) - _heom_obs(o, p)).max() < tol
     assert abs(_heom_obs(g, p)[1] - 1.0) < tol
+
+
+@pytest.mark.parametrize("bond", [4, 16])  # fused solver only / also the multi-kernel path
+def test_noconv_restores_state(T, bond):
+    """A Krylov limit far too small for the step: TTN_E_NOCONV, and the state
+    is the one before the failed step (the step is not half applied)."""
+    p = sbm_problem(n_modes=8 if bond == 16 else 4, d=6, bond=bond, alpha=0.3)
+    st = random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=3)
+    g = T.TTN.from_problem(p, krylov_mmax=6)
+    g.set_state(st)
+    g.step(1e-5)  # converges within the limit
+    before = g.get_state()
+    with pytest.raises(T.TTNError) as e:
+        g.step(50.0)
+    assert "E_NOCONV" in str(e.value)
+    after = g.get_state()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    g.step(1e-5)  # the handle stays usable
