@@ -693,6 +693,12 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
                      small_solve_lds_bytes(p.g.N, a.mmax, 1, nA) + SMALL_STATIC_LDS <= 160 * 1024)
                         ? 1
                         : 0;
+        // the Krylov basis in LDS when it fits beside the solver's other LDS data
+        a.vlds = small_solve_lds_bytes(p.g.N, a.mmax, a.batched, nA) + small_solve_vlds_bytes(p.g.N, a.mmax) +
+                         SMALL_STATIC_LDS <=
+                     160 * 1024
+                     ? 1
+                     : 0;
         launch_small_solve(a, st);
     } else {
         if (!bk.V) throw Error(TTN_E_STATE, "internal: Krylov scratch not allocated");

@@ -12,7 +12,7 @@ namespace ttn {
 constexpr int MAXD = 8;        // slots of a node tensor (children + parent)
 constexpr int MAXF = 8;        // non-identity factors of one operator entry
 constexpr int SMALL_MAX = 1024;   // local problems up to this size use the fused solver
-constexpr int SMALL_MMAX = 32;    // Krylov dimension limit of the fused solver (LDS budget)
+constexpr int SMALL_MMAX = 24;    // Krylov dimension limit of the fused solver (LDS budget; sub-steps beyond)
 constexpr int SMALL_THREADS = 1024;
 constexpr int VEC_BLOCKS = 256;   // work-groups of the multi-kernel vector operations
 constexpr int VEC_THREADS = 256;
@@ -90,15 +90,18 @@ struct SmallSolveArgs {
     int hermitian;
     int m_hint;
     int batched;       // two-slot problem with the batched matvec
+    int vlds;          // 1: the Krylov basis lives in LDS (when it fits), else in V
     int nA;            // entries with a slot-1 factor (batched)
     SolveStat *stat;
 };
 constexpr int SMALL_MAXENT = 128;  // entries of the batched two-slot matvec
-constexpr int SMALL_UB = 2048;     // LDS elements for staged slot-0 operators (batched matvec)
+constexpr int SMALL_UB = 2048;     // slot-0 operator size limit of the batched two-slot matvec
+constexpr int SMALL_US = 1024;     // LDS elements for the entry-group partial sums (batched matvec)
 constexpr int64_t SMALL_SEQ_WORK = 8192;  // entries x elements limit of the fused solver's generic matvec
 // static LDS of the fused solver: two int tables and the staged entry fields per entry, plus reduction scratch
 constexpr size_t SMALL_STATIC_LDS = (size_t)SMALL_MAXENT * (2 * sizeof(int) + 48) + 1024;
 size_t small_solve_lds_bytes(int64_t N, int mmax, int batched, int nA);
+inline size_t small_solve_vlds_bytes(int64_t N, int mmax) { return 16 * (size_t)(mmax + 1) * N; }
 
 // Scratch of the multi-kernel Krylov path.
 struct BigKrylov {

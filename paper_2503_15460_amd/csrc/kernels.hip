@@ -1350,12 +1350,13 @@ struct EntLite {
 static_assert(sizeof(EntLite) <= 48, "EntLite must fit the static LDS budget of the fused solver");
 
 struct SmallLds {
-    double2 *v, *w, *r1, *Hm, *hbuf, *ybuf, *red;  // red: 16 waves x (mmax+1)
+    double2 *v, *w, *r1, *Hm, *hbuf, *ybuf;
     double2 *us;                                   // partial sums of the entry groups (batched matvec)
     double *red1;
     int *e1;        // entries with a slot-1 factor (two-slot batched matvec)
     int *tix;       // per entry: index of its slot-1 temporary, -1 if none
     EntLite *ents;  // per entry (batched matvec)
+    double2 *vb;    // Krylov basis in LDS ((mmax + 1) x N) when args.vlds
 };
 
 __device__ void blk_mode_lds(const double2 *src, double2 *dst, const double2 *M, const Geom &g, int s, int blo,
@@ -1452,43 +1453,25 @@ __device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double
     __syncthreads();
 }
 
-// h_i = <V_i, w> for i < nv (V in global); result in hbuf.  Basis loads are
-// issued eight at a time so their latencies overlap.
+// h_i = <V_i, w> for i < nv; result in hbuf.  One wavefront per basis vector
+// (round robin): its lanes stride over the elements and a single wavefront
+// reduction finishes the dot, so each wave reduces only its own vectors.
 // With want_norm, hbuf[nv] additionally receives (|w|^2, 0).
-__device__ void blk_dots(const double2 *V, uint32_t N, int nv, const double2 *w, double2 *red, double2 *hbuf,
-                         int ld, bool want_norm = false) {
+__device__ void blk_dots(const double2 *V, uint32_t N, int nv, const double2 *w, double2 *hbuf,
+                         bool want_norm = false) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
     const int nt = want_norm ? nv + 1 : nv;
-    for (int i0 = 0; i0 < nt; i0 += 8) {
-        double2 c[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) c[q] = make_double2(0.0, 0.0);
-        for (uint32_t idx = tid; idx < N; idx += blockDim.x) {
-            const double2 wv = w[idx];
-            double2 b[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                b[q] = (i0 + q < nv) ? V[(size_t)(i0 + q) * N + idx] : (i0 + q == nv ? wv : make_double2(0.0, 0.0));
-#pragma unroll
-            for (int q = 0; q < 8; ++q) cfmac(c[q], b[q], wv);
+    for (int i = wave; i < nt; i += nw) {
+        double2 c = make_double2(0.0, 0.0);
+        if (i < nv) {
+            const double2 *vi = V + (size_t)i * N;
+            for (uint32_t idx = lane; idx < N; idx += 64) cfmac(c, vi[idx], w[idx]);
+        } else {
+            for (uint32_t idx = lane; idx < N; idx += 64) c.x += cabs2(w[idx]);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                c[q].x += __shfl_xor(c[q].x, off, 64);
-                c[q].y += __shfl_xor(c[q].y, off, 64);
-            }
-        if (lane == 0)
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (i0 + q < nt) red[wave * ld + i0 + q] = c[q];
-    }
-    __syncthreads();
-    if (tid < nt) {
-        double2 sacc = make_double2(0.0, 0.0);
-        for (int q = 0; q < nw; ++q) sacc = cadd(sacc, red[q * ld + tid]);
-        hbuf[tid] = sacc;
+        c.x = wave_sum(c.x);
+        c.y = wave_sum(c.y);
+        if (lane == 0) hbuf[i] = c;
     }
     __syncthreads();
 }
@@ -1515,8 +1498,7 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
     const int tid = threadIdx.x, nt = blockDim.x;
     const uint32_t N = (uint32_t)a.g.N;
     const int mmax = a.mmax;
-    const int ld = mmax + 1;
-    double2 *V = a.V;
+    double2 *V = a.vlds ? L.vb : a.V;
     double part = 0.0;
     for (uint32_t idx = tid; idx < N; idx += nt) part += cabs2(x[idx]);
     const double beta0 = sqrt(blk_sum1(part, L.red1));
@@ -1539,7 +1521,7 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
         double wn2 = 0.0;
         for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
             // the second pass also reduces |w|^2: |w - V h|^2 = |w|^2 - |h|^2 (h ~ eps there)
-            blk_dots(V, N, j + 1, L.w, L.red, L.hbuf, ld, pass == 1);
+            blk_dots(V, N, j + 1, L.w, L.hbuf, pass == 1);
             if (pass == 1) {
                 wn2 = L.hbuf[j + 1].x;
                 for (int i = 0; i <= j; ++i) wn2 -= cabs2(L.hbuf[i]);
@@ -1616,9 +1598,9 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
     L.Hm = L.r1 + small_r1_elems(N, mmax, a.batched, a.nA);
     L.hbuf = L.Hm + (mmax + 1) * mmax;
     L.ybuf = L.hbuf + (mmax + 1);
-    L.red = L.ybuf + mmax;
-    L.red1 = reinterpret_cast<double *>(L.red + 16 * (mmax + 1));
+    L.red1 = reinterpret_cast<double *>(L.ybuf + mmax);
     L.us = reinterpret_cast<double2 *>(L.red1 + 16);
+    L.vb = L.us + (a.batched ? SMALL_US : 0);
     L.e1 = e1;
     L.tix = tix;
     L.ents = ents;
@@ -1682,7 +1664,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
 
 size_t small_solve_lds_bytes(int64_t N, int mmax, int batched, int nA) {
     return sizeof(double2) * (size_t)(2 * N + small_r1_elems(N, mmax, batched, nA) + (mmax + 1) * mmax +
-                                      (mmax + 1) + mmax + 16 * (mmax + 1) + (batched ? SMALL_UB : 0)) +
+                                      (mmax + 1) + mmax + (batched ? SMALL_US : 0)) +
            16 * sizeof(double);
 }
 
@@ -2170,7 +2152,8 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
 }
 
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
-    const size_t lds = small_solve_lds_bytes(a.g.N, a.mmax, a.batched, a.nA);
+    const size_t lds0 = small_solve_lds_bytes(a.g.N, a.mmax, a.batched, a.nA);
+    const size_t lds = lds0 + (a.vlds ? small_solve_vlds_bytes(a.g.N, a.mmax) : 0);
     if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds + SMALL_STATIC_LDS > 160 * 1024 ||
         (a.batched && (a.g.D != 2 || a.n_ent > SMALL_MAXENT || a.g.dims[0] * a.g.dims[0] > SMALL_UB)))
         throw std::runtime_error("small solve out of range");
