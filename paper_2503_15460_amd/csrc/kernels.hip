@@ -79,24 +79,6 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// block-wide sum of `cnt` (<= 8) complex values; result in out[0..cnt) (LDS), synced
-__device__ void blk_sum8(double2 *acc, int cnt, double2 *red, double2 *out) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
-    for (int q = 0; q < cnt; ++q) {
-        acc[q].x = wave_sum(acc[q].x);
-        acc[q].y = wave_sum(acc[q].y);
-    }
-    if (lane == 0)
-        for (int q = 0; q < cnt; ++q) red[wave * 8 + q] = acc[q];
-    __syncthreads();
-    if (tid < cnt) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int w = 0; w < nw; ++w) s = cadd(s, red[w * 8 + tid]);
-        out[tid] = s;
-    }
-    __syncthreads();
-}
-
 __device__ double blk_sum1(double v, double *red) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
     v = wave_sum(v);
@@ -1701,7 +1683,6 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_scale0(const double2 *__res
 // k_kry_finalize then forms (w - V h1) / beta.
 __global__ void __launch_bounds__(VEC_THREADS) k_kry_orth(BigKrylov k, uint32_t N, int j, int mmax, int pass) {
     if (*k.meff) return;
-    __shared__ double2 red8[16 * 8];
     __shared__ double2 hb[64];
     __shared__ double red1[16];
     __shared__ double stage[KRY_STAGE];
@@ -1721,15 +1702,22 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_orth(BigKrylov k, uint32_t 
     }
     const int K = nv + 1;  // doubles pairs per block: h (complex) and |w|^2
     double *part = k.part;
-    for (int i0 = 0; i0 < nv; i0 += 8) {
-        const int cnt = min(8, nv - i0);
-        double2 acc[8];
-        for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
-        for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
-            const double2 wv = w[idx];
-            for (int q = 0; q < cnt; ++q) cfmac(acc[q], k.V[(size_t)(i0 + q) * N + idx], wv);
+    {  // one wavefront per basis vector over the block's elements, one wave reduction per dot
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        const uint32_t stride = gridDim.x * blockDim.x;
+        for (int i = wave; i < nv; i += nw) {
+            const double2 *vi = k.V + (size_t)i * N;
+            double2 c = make_double2(0.0, 0.0);
+            for (uint32_t base = blockIdx.x * blockDim.x; base < N; base += stride)
+                for (uint32_t t = lane; t < blockDim.x; t += 64) {
+                    const uint32_t idx = base + t;
+                    if (idx < N) cfmac(c, vi[idx], w[idx]);
+                }
+            c.x = wave_sum(c.x);
+            c.y = wave_sum(c.y);
+            if (lane == 0) hb[i] = c;
         }
-        blk_sum8(acc, cnt, red8, hb + i0);
+        __syncthreads();
     }
     const double wns = pass == 1 ? blk_sum1(wn, red1) : 0.0;
     if (threadIdx.x < nv) {
