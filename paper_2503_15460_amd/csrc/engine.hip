@@ -693,12 +693,24 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
                      small_solve_lds_bytes(p.g.N, a.mmax, 1, nA) + SMALL_STATIC_LDS <= 160 * 1024)
                         ? 1
                         : 0;
-        // the Krylov basis in LDS when it fits beside the solver's other LDS data
-        a.vlds = small_solve_lds_bytes(p.g.N, a.mmax, a.batched, nA) + small_solve_vlds_bytes(p.g.N, a.mmax) +
-                         SMALL_STATIC_LDS <=
-                     160 * 1024
-                     ? 1
-                     : 0;
+        // LDS beyond the solver's own data: first the factor matrices (read on
+        // every matvec), then the Krylov basis, each when it fits
+        size_t lds = small_solve_lds_bytes(p.g.N, a.mmax, a.batched, nA) + SMALL_STATIC_LDS;
+        a.mlds = 0;
+        a.mlds_elems = 0;
+        if (a.batched) {
+            int64_t elems = 0;
+            for (auto &e : p.ents) {
+                if (e.nf >= 1 && e.slot[0] == 0) elems += (int64_t)p.g.dims[0] * p.g.dims[0];
+                if (e.nf >= 1 && e.slot[e.nf - 1] == 1) elems += (int64_t)p.g.dims[1] * p.g.dims[1];
+            }
+            if (lds + sizeof(double2) * (size_t)elems <= 160 * 1024) {
+                a.mlds = 1;
+                a.mlds_elems = (int)elems;
+                lds += sizeof(double2) * (size_t)elems;
+            }
+        }
+        a.vlds = lds + small_solve_vlds_bytes(p.g.N, a.mmax) <= 160 * 1024 ? 1 : 0;
         launch_small_solve(a, st);
     } else {
         if (!bk.V) throw Error(TTN_E_STATE, "internal: Krylov scratch not allocated");

@@ -91,6 +91,8 @@ struct SmallSolveArgs {
     int m_hint;
     int batched;       // two-slot problem with the batched matvec
     int vlds;          // 1: the Krylov basis lives in LDS (when it fits), else in V
+    int mlds;          // 1: the factor matrices are copied to LDS (batched matvec, when they fit)
+    int mlds_elems;    // their total size in complex elements
     int nA;            // entries with a slot-1 factor (batched)
     SolveStat *stat;
 };
@@ -98,8 +100,8 @@ constexpr int SMALL_MAXENT = 128;  // entries of the batched two-slot matvec
 constexpr int SMALL_UB = 2048;     // slot-0 operator size limit of the batched two-slot matvec
 constexpr int SMALL_US = 1024;     // LDS elements for the entry-group partial sums (batched matvec)
 constexpr int64_t SMALL_SEQ_WORK = 8192;  // entries x elements limit of the fused solver's generic matvec
-// static LDS of the fused solver: two int tables and the staged entry fields per entry, plus reduction scratch
-constexpr size_t SMALL_STATIC_LDS = (size_t)SMALL_MAXENT * (2 * sizeof(int) + 48) + 1024;
+// static LDS of the fused solver: three int tables and the staged entry fields per entry, plus reduction scratch
+constexpr size_t SMALL_STATIC_LDS = (size_t)SMALL_MAXENT * (3 * sizeof(int) + 48) + 1024;
 size_t small_solve_lds_bytes(int64_t N, int mmax, int batched, int nA);
 inline size_t small_solve_vlds_bytes(int64_t N, int mmax) { return 16 * (size_t)(mmax + 1) * N; }
 

@@ -1338,6 +1338,7 @@ struct SmallLds {
     int *e1;        // entries with a slot-1 factor (two-slot batched matvec)
     int *tix;       // per entry: index of its slot-1 temporary, -1 if none
     EntLite *ents;  // per entry (batched matvec)
+    double2 *mb;    // the entries' factor matrices in LDS when args.mlds
     double2 *vb;    // Krylov basis in LDS ((mmax + 1) x N) when args.vlds
 };
 
@@ -1571,6 +1572,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
     __shared__ int e1[SMALL_MAXENT];
     __shared__ int tix[SMALL_MAXENT];
     __shared__ EntLite ents[SMALL_MAXENT];
+    __shared__ int moff[SMALL_MAXENT];
     const uint32_t N = (uint32_t)a.g.N;
     const int mmax = a.mmax;
     SmallLds L;
@@ -1582,7 +1584,8 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
     L.ybuf = L.hbuf + (mmax + 1);
     L.red1 = reinterpret_cast<double *>(L.ybuf + mmax);
     L.us = reinterpret_cast<double2 *>(L.red1 + 16);
-    L.vb = L.us + (a.batched ? SMALL_US : 0);
+    L.mb = L.us + (a.batched ? SMALL_US : 0);
+    L.vb = L.mb + (a.mlds ? a.mlds_elems : 0);
     L.e1 = e1;
     L.tix = tix;
     L.ents = ents;
@@ -1605,8 +1608,9 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
             ents[e] = el;
         }
         __syncthreads();
+        const int n0 = a.g.dims[0], n1 = a.g.dims[1];
         if (threadIdx.x == 0) {
-            int k = 0;
+            int k = 0, off = 0;
             for (int e = 0; e < a.n_ent; ++e) {
                 if (ents[e].M1) {
                     tix[e] = k;
@@ -1614,6 +1618,25 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
                 } else {
                     tix[e] = -1;
                 }
+                moff[e] = off;
+                off += (ents[e].M0 ? n0 * n0 : 0) + (ents[e].M1 ? n1 * n1 : 0);
+            }
+        }
+        __syncthreads();
+        if (a.mlds) {
+            // the factor matrices are read on every matvec: copy them to LDS once
+            for (int e = 0; e < a.n_ent; ++e) {
+                double2 *dst = L.mb + moff[e];
+                const double2 *m0 = ents[e].M0, *m1 = ents[e].M1;
+                const int s0 = m0 ? n0 * n0 : 0, s1 = m1 ? n1 * n1 : 0;
+                for (int q = threadIdx.x; q < s0 + s1; q += blockDim.x) dst[q] = q < s0 ? m0[q] : m1[q - s0];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < a.n_ent; e += blockDim.x) {
+                double2 *base = L.mb + moff[e];
+                const bool has0 = ents[e].M0 != nullptr;
+                if (has0) ents[e].M0 = base;
+                if (ents[e].M1) ents[e].M1 = base + (has0 ? n0 * n0 : 0);
             }
         }
     }
@@ -2141,7 +2164,9 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
 
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     const size_t lds0 = small_solve_lds_bytes(a.g.N, a.mmax, a.batched, a.nA);
-    const size_t lds = lds0 + (a.vlds ? small_solve_vlds_bytes(a.g.N, a.mmax) : 0);
+    const size_t lds = lds0 + (a.vlds ? small_solve_vlds_bytes(a.g.N, a.mmax) : 0) +
+                       (a.mlds ? sizeof(double2) * (size_t)a.mlds_elems : 0);
+    if (a.mlds && !a.batched) throw std::runtime_error("factor staging needs the batched matvec");
     if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || lds + SMALL_STATIC_LDS > 160 * 1024 ||
         (a.batched && (a.g.D != 2 || a.n_ent > SMALL_MAXENT || a.g.dims[0] * a.g.dims[0] > SMALL_UB)))
         throw std::runtime_error("small solve out of range");
