@@ -499,6 +499,7 @@ void Engine::set_sop(const SopInput &s) {
     HIPCHK(hipMemset(qrw.counter, 0, sizeof(unsigned) * 4));
     qrw.cpart = (double *)dalloc(sizeof(double) * 2 * QRM_BLOCKS_MAX * QRC_REC);
     qrw.bar = (unsigned *)dalloc(sizeof(unsigned) * 192);
+    qrw.bar_base = 0;
     const int n_solves = (2 * n - 1) + 2 * (n - 1);
     d_stats = (SolveStat *)dalloc(sizeof(SolveStat) * n_solves);
     // pinned, so that the per-step statistics copy stays asynchronous

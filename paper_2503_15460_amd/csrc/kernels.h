@@ -132,6 +132,7 @@ struct QRWork {
     unsigned *counter;          // last-block ticket (starts at 0)
     double *cpart;              // [2][QRM_BLOCKS_MAX][QRC_REC] column partials of the cooperative QR
     unsigned *bar;              // [192] grid barrier of the cooperative QR (starts at 0); bar[128] != 0: failed
+    unsigned long long bar_base;  // arrivals counted in bar[0..1] by the launches made so far (host side)
 };
 constexpr int QRC_REC = 2 + 4 * 64;  // xn2, fro, g_j (complex), row i (complex)
 
@@ -162,7 +163,7 @@ void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int
                      hipStream_t st);
 // the same reflectors in one cooperative launch (grid-wide barriers between columns);
 // returns false (nothing launched) when the grid cannot be co-resident
-bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
+bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, QRWork &q,
                     hipStream_t st);
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st);
 void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st);

@@ -7,6 +7,7 @@
 // the operator-applied tensor, the QR gauge shifts of the canonical form
 // (Sec. II A), and the local exponentials of the projector-splitting sweep.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -966,28 +967,23 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qrm_formq(double2 *A, uint32_t 
 
 // ============================================================ QR (one cooperative launch)
 constexpr int QRC_STAGE = 4096;  // doubles of LDS staging for the per-column reduction
-// Grid-wide barrier for a co-resident grid: bar[0] counts arrivals, bar[64]
-// is the generation (separate cache lines).  The last block to arrive resets
-// the count and advances the generation, which the others wait for; a bounded
-// spin records a failure in bar[128] instead of waiting for ever.
-__device__ void grid_barrier(unsigned *bar, unsigned nblocks) {
+// Grid-wide barrier for a co-resident grid: every work-group adds one to a
+// 64-bit arrival counter that only grows and waits until it reaches `target`
+// (the host advances its base by the arrivals of each launch, so no reset and
+// no second generation word sit on the critical path).  A bounded spin records
+// a failure in *fail instead of waiting for ever; the arrival itself is never
+// skipped, so the count stays consistent after a failure.
+__device__ void grid_barrier(unsigned long long *cnt, unsigned long long target, unsigned *fail) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned *arrive = bar, *gen = bar + 64;
-        const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
-        const unsigned prev = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nblocks - 1) {
-            __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1u << 24)) {
-                    __hip_atomic_store(bar + 128, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
+        __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1u << 24)) {
+                __hip_atomic_store(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
             }
         }
         __threadfence();
@@ -1029,6 +1025,8 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
     __shared__ double s_sum[QRC_REC];
     __shared__ double2 red2[256];
     __shared__ double red1[16];
+    unsigned long long *bar_cnt = reinterpret_cast<unsigned long long *>(q.bar);
+    unsigned long long bar_tgt = q.bar_base;
     for (uint32_t e = tid; e < nr * (uint32_t)n; e += blockDim.x) {
         const uint32_t rho = r0 + e / n;
         At[e] = A[qr_addr(rho, (int)(e % n), n, R)];
@@ -1070,8 +1068,12 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
         for (uint32_t rho = lo + tid; rho < r1; rho += blockDim.x) xp += cabs2(At[(size_t)(rho - r0) * n + i]);
         if (i == 0)
             for (uint32_t e = tid; e < nr * (uint32_t)n; e += blockDim.x) fp += cabs2(At[e]);
-        const double xs = blk_sum1(xp, red1);
-        const double fs = blk_sum1(fp, red1);
+        xp = wave_sum(xp);
+        fp = wave_sum(fp);
+        if ((tid & 63) == 0) {
+            red1[tid >> 6] = xp;
+            red1[8 + (tid >> 6)] = fp;
+        }
         const int nt = n - i - 1;
         const int P = nt > 0 ? (int)blockDim.x / nt : 0;  // row phases per trailing column
         if (nt > 0 && tid < P * nt) {
@@ -1086,6 +1088,11 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
         }
         __syncthreads();
         if (tid == 0) {
+            double xs = 0.0, fs = 0.0;
+            for (int w = 0; w < ((int)blockDim.x + 63) >> 6; ++w) {
+                xs += red1[w];
+                fs += red1[8 + w];
+            }
             rec[0] = xs;
             rec[1] = fs;
         }
@@ -1102,16 +1109,20 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
                 rec[2 + 2 * QRM_MAXN + 2 * c] = v.x;
                 rec[3 + 2 * QRM_MAXN + 2 * c] = v.y;
             }
-        grid_barrier(q.bar, G);
+        grid_barrier(bar_cnt, bar_tgt += G, q.bar + 128);
         // every work-group reduces the partials in the same order: chunks of
         // values are staged through LDS with independent loads, then 8 lanes
         // per value sum strided partials and combine them by shuffles
         const double *recs = q.cpart + (size_t)(i & 1) * QRM_BLOCKS_MAX * QRC_REC;
         const uint32_t own = (uint32_t)i / rows_per;
+        // the owner's row i is independent of the sums: its loads go out first
+        for (int t = tid; t < 2 * n; t += blockDim.x)
+            s_sum[2 + 2 * QRM_MAXN + t] = recs[(size_t)own * QRC_REC + 2 + 2 * QRM_MAXN + t];
         {
             double *stage = reinterpret_cast<double *>(aux);  // QRC_STAGE doubles
             const int nv = 2 + 2 * n;
-            const int ch = max(1, min(32, QRC_STAGE / (int)G));
+            const int ch = max(1, min(nv, QRC_STAGE / (int)G));
+            const int groups = (int)blockDim.x / 8;
             for (int v0 = 0; v0 < nv; v0 += ch) {
                 const int cnt = min(ch, nv - v0);
                 for (int e = tid; e < (int)G * cnt; e += blockDim.x) {
@@ -1119,20 +1130,20 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
                     stage[e] = recs[(size_t)bb * QRC_REC + v0 + t];
                 }
                 __syncthreads();
-                const int t = tid / 8, sub = tid & 7;
-                double sacc = 0.0;
-                if (t < cnt)
-                    for (int bb = sub; bb < (int)G; bb += 8) sacc += stage[bb * cnt + t];
-                sacc += __shfl_xor(sacc, 4, 64);
-                sacc += __shfl_xor(sacc, 2, 64);
-                sacc += __shfl_xor(sacc, 1, 64);
-                if (t < cnt && sub == 0) s_sum[v0 + t] = sacc;
+                const int sub = tid & 7;
+                for (int t0 = 0; t0 < cnt; t0 += groups) {  // uniform trip count: every lane shuffles
+                    const int t = t0 + tid / 8;
+                    double sacc = 0.0;
+                    if (t < cnt)
+                        for (int bb = sub; bb < (int)G; bb += 8) sacc += stage[bb * cnt + t];
+                    sacc += __shfl_xor(sacc, 4, 64);
+                    sacc += __shfl_xor(sacc, 2, 64);
+                    sacc += __shfl_xor(sacc, 1, 64);
+                    if (t < cnt && sub == 0) s_sum[v0 + t] = sacc;
+                }
                 __syncthreads();
             }
         }
-        for (int t = tid; t < 2 * n; t += blockDim.x)
-            s_sum[2 + 2 * QRM_MAXN + t] = recs[(size_t)own * QRC_REC + 2 + 2 * QRM_MAXN + t];
-        __syncthreads();
         if (tid == 0) {
             double xn2 = s_sum[0];
             if (i == 0) s_thr = snap * sqrt(s_sum[1]);
@@ -1191,7 +1202,7 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
             cfmac(sacc, tile_v(At, r0, rho, k, n), tile_v(At, r0, rho, l, n));
         Sp[pidx] = sacc;
     }
-    grid_barrier(q.bar, G);
+    grid_barrier(bar_cnt, bar_tgt += G, q.bar + 128);
     if (b == 0) {  // T (compact WY) and K = T V_top^H, as in k_qrm_finish
         double2 *T = aux;          // n*n
         double2 *S = aux + n * n;  // n*n
@@ -1233,7 +1244,7 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
             q.K[e] = kacc;
         }
     }
-    grid_barrier(q.bar, G);
+    grid_barrier(bar_cnt, bar_tgt += G, q.bar + 128);
     // Q[rho, c] = delta - sum_i V[rho, i] K[i, c] on the own rows, written to A
     double2 *Ks = aux;
     for (int e = tid; e < n * n; e += blockDim.x) Ks[e] = q.K[e];
@@ -1863,8 +1874,11 @@ __global__ void k_transpose(double2 *dst, const double2 *src, int n) {
 }
 
 // ============================================================ launch profiler
-// Optional: every launch bracketed by two HIP events on its stream; per kernel
-// name the summed elapsed time, call count and algorithmic flops / bytes.
+// Optional: every launch carries a start and a stop HIP event that the runtime
+// stamps from the dispatch itself (hipExtLaunchKernelGGL), so the elapsed time
+// is the kernel's own execution time without the marker packets a pair of
+// hipEventRecord calls would add; per kernel name the summed elapsed time, call
+// count and algorithmic flops / bytes.
 namespace prof {
 struct Rec {
     const char *name;
@@ -1888,16 +1902,12 @@ static hipEvent_t take() {
 
 #define TTN_LAUNCH(NAME, FL, BY, KER, GRID, BLOCK, LDS, ST, ...)                                     \
     do {                                                                                             \
-        hipEvent_t ea_ = nullptr, eb_ = nullptr;                                                     \
         if (prof::on) {                                                                              \
-            ea_ = prof::take();                                                                      \
-            eb_ = prof::take();                                                                      \
-            (void)hipEventRecord(ea_, ST);                                                           \
-        }                                                                                            \
-        hipLaunchKernelGGL(KER, GRID, BLOCK, LDS, ST, __VA_ARGS__);                                  \
-        if (prof::on) {                                                                              \
-            (void)hipEventRecord(eb_, ST);                                                           \
+            hipEvent_t ea_ = prof::take(), eb_ = prof::take();                                       \
+            hipExtLaunchKernelGGL(KER, dim3(GRID), dim3(BLOCK), LDS, ST, ea_, eb_, 0, __VA_ARGS__);   \
             prof::recs.push_back({NAME, ea_, eb_, (double)(FL), (double)(BY)});                      \
+        } else {                                                                                     \
+            hipLaunchKernelGGL(KER, GRID, BLOCK, LDS, ST, __VA_ARGS__);                              \
         }                                                                                            \
     } while (0)
 
@@ -2110,7 +2120,7 @@ void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int
                (uint32_t)L, n, (uint32_t)R, (uint32_t)rows_per, q);
 }
 
-bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
+bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, QRWork &q,
                     hipStream_t st) {
     const int64_t m = L * R;
     if (n > QRM_MAXN || m < n) throw std::runtime_error("QR shape out of range");
@@ -2155,6 +2165,7 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     }
     hipError_t e = hipLaunchCooperativeKernel((const void *)k_qr_coop, dim3(nb), dim3(QRM_THREADS), args, lds, st);
     if (e != hipSuccess) throw std::runtime_error(std::string("hipLaunchCooperativeKernel: ") + hipGetErrorString(e));
+    q.bar_base += (unsigned long long)nb * (unsigned long long)(n + 2);  // n column barriers, Gram, K
     if (prof::on) {
         (void)hipEventRecord(eb, st);
         prof::recs.push_back({"k_qr_coop", ea, eb, 16.0 * (double)m * n * n, 32.0 * (double)m * n});
