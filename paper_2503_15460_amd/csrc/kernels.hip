@@ -1404,10 +1404,15 @@ __device__ void blk_matvec_two(const SmallSolveArgs &a, const double2 *v, double
         const EntLite &E = ents[e1[k]];
         const uint32_t ai = el / n1, p = el - ai * n1;
         const double2 *xr = v + (size_t)ai * n1;
-        const double2 *mr = E.M1 + (size_t)p * n1;
         double2 acc = make_double2(0.0, 0.0);
         const int j0 = max(0, (int)p - E.lo1), j1 = min(n1 - 1, (int)p + E.hi1);
-        for (int j = j0; j <= j1; ++j) cfma(acc, mr[j], xr[j]);
+        if (a.mlds) {  // LDS copy is transposed: neighbouring lanes (p) read neighbouring words
+            const double2 *mc = E.M1 + p;
+            for (int j = j0; j <= j1; ++j) cfma(acc, mc[(size_t)j * n1], xr[j]);
+        } else {
+            const double2 *mr = E.M1 + (size_t)p * n1;
+            for (int j = j0; j <= j1; ++j) cfma(acc, mr[j], xr[j]);
+        }
         T[q] = acc;
     }
     __syncthreads();
@@ -1640,7 +1645,15 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a)
                 double2 *dst = L.mb + moff[e];
                 const double2 *m0 = ents[e].M0, *m1 = ents[e].M1;
                 const int s0 = m0 ? n0 * n0 : 0, s1 = m1 ? n1 * n1 : 0;
-                for (int q = threadIdx.x; q < s0 + s1; q += blockDim.x) dst[q] = q < s0 ? m0[q] : m1[q - s0];
+                // slot-1 factors are stored transposed (phase A reads them by column)
+                for (int q = threadIdx.x; q < s0 + s1; q += blockDim.x) {
+                    if (q < s0) {
+                        dst[q] = m0[q];
+                    } else {
+                        const int t = q - s0, j = t / n1, p = t - j * n1;
+                        dst[q] = m1[p * n1 + j];
+                    }
+                }
             }
             __syncthreads();
             for (int e = threadIdx.x; e < a.n_ent; e += blockDim.x) {
@@ -2192,7 +2205,11 @@ void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     int threads = (int)((a.g.N + 63) / 64) * 64;
     if (threads < 64) threads = 64;
     if (threads > cap) threads = cap;
-    if (a.batched && threads < 256) threads = 256;  // phase B splits the entries over the spare threads
+    // batched: phase B splits the entries over the spare threads; beyond ~100
+    // elements a full 1024-thread work-group (four waves per SIMD) hides the
+    // LDS latency of the matvec and of the Gram-Schmidt dots better
+    if (a.batched && threads < 256) threads = 256;
+    if (a.batched && a.g.N > 96) threads = SMALL_THREADS;
     TTN_LAUNCH("k_small_solve", 0.0, 0.0, k_small_solve, dim3(1), dim3(threads), lds, st, a);
 }
 
