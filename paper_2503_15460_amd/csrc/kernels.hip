@@ -967,6 +967,7 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qrm_formq(double2 *A, uint32_t 
 
 // ============================================================ QR (one cooperative launch)
 constexpr int QRC_STAGE = 4096;  // doubles of LDS staging for the per-column reduction
+constexpr int PROF_TS_MAX = 8192;  // cooperative launches the launch profiler times per collection
 // Grid-wide barrier for a co-resident grid: every work-group adds one to a
 // 64-bit arrival counter that only grows and waits until it reaches `target`
 // (the host advances its base by the arrivals of each launch, so no reset and
@@ -1009,8 +1010,11 @@ __device__ __forceinline__ double2 tile_v(const double2 *At, uint32_t r0, uint32
 
 __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L, int n, uint32_t R,
                                                           uint32_t rows_per, QRWork q, double2 *Rout, int transR,
-                                                          double snap) {
+                                                          double snap, unsigned long long *ts) {
     extern __shared__ double2 sq[];
+    // launch profiler only: earliest work-group start and latest end on the
+    // device's constant-rate clock (a cooperative launch takes no dispatch events)
+    if (ts && threadIdx.x == 0) atomicMin(ts, (unsigned long long)wall_clock64());
     const uint32_t m = L * R;
     const uint32_t G = gridDim.x, b = blockIdx.x;
     const uint32_t r0 = b * rows_per, r1 = min(m, r0 + rows_per);
@@ -1255,6 +1259,10 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
         double2 qacc = make_double2(rho == (uint32_t)c ? 1.0 : 0.0, 0.0);
         for (int i = 0; i < n; ++i) qacc = csub(qacc, cmul(tile_v(At, r0, rho, i, n), Ks[i * n + c]));
         A[qr_addr(rho, c, n, R)] = qacc;
+    }
+    if (ts) {
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(ts + PROF_TS_MAX, (unsigned long long)wall_clock64());
     }
 }
 
@@ -1895,10 +1903,37 @@ __global__ void k_transpose(double2 *dst, const double2 *src, int n) {
 namespace prof {
 struct Rec {
     const char *name;
-    hipEvent_t a, b;
+    hipEvent_t a, b;  // dispatch-stamped events, or null for a kernel-clock slot
     double flops, bytes;
+    int ts_slot;  // >= 0: duration from the kernel's own start / end clock readings
 };
 static bool on = false;
+// kernel-clock slots: ts[i] = earliest start, ts[PROF_TS_MAX + i] = latest end
+static unsigned long long *ts = nullptr;
+static int ts_used = 0;
+static bool ts_fresh = false;  // slots initialised for the current collection
+static double ts_khz = 0.0;
+static unsigned long long *take_ts() {
+    if (!ts) {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0 ||
+            hipMalloc((void **)&ts, sizeof(unsigned long long) * 2 * PROF_TS_MAX) != hipSuccess)
+            throw std::runtime_error("launch profiler: kernel clock unavailable");
+        ts_khz = khz;
+    }
+    if (!ts_fresh) {  // starts to the maximum, ends to zero
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemset(ts, 0xff, sizeof(unsigned long long) * PROF_TS_MAX) != hipSuccess ||
+            hipMemset(ts + PROF_TS_MAX, 0, sizeof(unsigned long long) * PROF_TS_MAX) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+            throw std::runtime_error("launch profiler: kernel clock slots");
+        ts_used = 0;
+        ts_fresh = true;
+    }
+    if (ts_used >= PROF_TS_MAX) throw std::runtime_error("launch profiler: too many cooperative launches to time");
+    return ts + ts_used++;
+}
 static std::vector<hipEvent_t> pool;
 static size_t used = 0;
 static std::vector<Rec> recs;
@@ -1918,7 +1953,7 @@ static hipEvent_t take() {
         if (prof::on) {                                                                              \
             hipEvent_t ea_ = prof::take(), eb_ = prof::take();                                       \
             hipExtLaunchKernelGGL(KER, dim3(GRID), dim3(BLOCK), LDS, ST, ea_, eb_, 0, __VA_ARGS__);   \
-            prof::recs.push_back({NAME, ea_, eb_, (double)(FL), (double)(BY)});                      \
+            prof::recs.push_back({NAME, ea_, eb_, (double)(FL), (double)(BY), -1});                  \
         } else {                                                                                     \
             hipLaunchKernelGGL(KER, GRID, BLOCK, LDS, ST, __VA_ARGS__);                              \
         }                                                                                            \
@@ -1929,6 +1964,8 @@ void profile_enable(bool enable) {
     prof::used = 0;
     prof::recs.clear();
     prof::extra_flops.clear();
+    prof::ts_used = 0;
+    prof::ts_fresh = false;  // slots are initialised at the first cooperative launch
 }
 
 bool profile_enabled() { return prof::on; }
@@ -1938,9 +1975,22 @@ void profile_add_flops(const char *name, double flops) { prof::extra_flops[name]
 std::vector<KernelStat> profile_collect() {
     if (hipDeviceSynchronize() != hipSuccess) throw std::runtime_error("hipDeviceSynchronize failed");
     std::map<std::string, KernelStat> agg;
+    std::vector<unsigned long long> tsv;
+    if (prof::ts && prof::ts_fresh && prof::ts_used > 0) {
+        tsv.resize(2 * PROF_TS_MAX);
+        if (hipMemcpy(tsv.data(), prof::ts, sizeof(unsigned long long) * 2 * PROF_TS_MAX, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            throw std::runtime_error("launch profiler: kernel clock read-back");
+    }
     for (auto &r : prof::recs) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) throw std::runtime_error("hipEventElapsedTime failed");
+        if (r.ts_slot >= 0) {
+            if (tsv.empty()) throw std::runtime_error("launch profiler: kernel clock slots lost");
+            const unsigned long long t0 = tsv[r.ts_slot], t1 = tsv[PROF_TS_MAX + r.ts_slot];
+            ms = t1 > t0 ? (float)((double)(t1 - t0) / prof::ts_khz) : 0.f;
+        } else if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            throw std::runtime_error("hipEventElapsedTime failed");
+        }
         KernelStat &k = agg[r.name];
         k.name = r.name;
         k.calls += 1;
@@ -1954,6 +2004,8 @@ std::vector<KernelStat> profile_collect() {
     prof::used = 0;
     prof::recs.clear();
     prof::extra_flops.clear();
+    prof::ts_used = 0;
+    prof::ts_fresh = false;
     return out;
 }
 
@@ -2169,20 +2221,17 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     uint32_t Lu = (uint32_t)L, Ru = (uint32_t)R, rp = (uint32_t)rows_per;
     double snap = QR_SNAP;
     QRWork qq = q;
-    void *args[] = {&A, &Lu, &n, &Ru, &rp, &qq, &Rout, &transR, &snap};
-    hipEvent_t ea = nullptr, eb = nullptr;
+    unsigned long long *ts = nullptr;
+    int slot = -1;
     if (prof::on) {
-        ea = prof::take();
-        eb = prof::take();
-        (void)hipEventRecord(ea, st);
+        ts = prof::take_ts();
+        slot = (int)(ts - prof::ts);
     }
+    void *args[] = {&A, &Lu, &n, &Ru, &rp, &qq, &Rout, &transR, &snap, &ts};
     hipError_t e = hipLaunchCooperativeKernel((const void *)k_qr_coop, dim3(nb), dim3(QRM_THREADS), args, lds, st);
     if (e != hipSuccess) throw std::runtime_error(std::string("hipLaunchCooperativeKernel: ") + hipGetErrorString(e));
     q.bar_base += (unsigned long long)nb * (unsigned long long)(n + 2);  // n column barriers, Gram, K
-    if (prof::on) {
-        (void)hipEventRecord(eb, st);
-        prof::recs.push_back({"k_qr_coop", ea, eb, 16.0 * (double)m * n * n, 32.0 * (double)m * n});
-    }
+    if (prof::on) prof::recs.push_back({"k_qr_coop", nullptr, nullptr, 16.0 * (double)m * n * n, 32.0 * (double)m * n, slot});
     return true;
 }
 

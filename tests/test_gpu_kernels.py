@@ -63,3 +63,28 @@ def test_large_node_parity(T):
         g.step(p.dt)
         o0.step(p.dt)
         assert abs(g.expect(p.observables["sz"]) - o0.expect(p.observables["sz"])) < 1e-10
+
+
+def test_launch_profiler_times_every_kernel(T):
+    """The launch profiler reports positive times for every kernel of a sweep,
+    including the cooperative QR (timed from the kernel's own clock), and the
+    summed kernel time stays below the wall time of the profiled sweep."""
+    import time
+    import torch
+    p = sbm_problem(n_modes=8, d=8, bond=32, alpha=0.3, dt=0.05)
+    g = T.TTN.from_problem(p)
+    g.set_state(random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=6))
+    g.step(p.dt)
+    torch.cuda.synchronize()
+    T.profile_begin()
+    t0 = time.perf_counter()
+    g.step(p.dt)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    rows = T.profile_end()
+    names = {r["name"] for r in rows}
+    assert "k_qr_coop" in names
+    for r in rows:
+        assert r["calls"] > 0 and r["total_ms"] > 0.0, r
+    assert sum(r["total_ms"] for r in rows) < wall_ms
+    g.close()
