@@ -244,7 +244,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the sweep on one GPU only (the sweep of one tree is sequential; "
+        print("bench.py: the sweep runs on one GPU only (the sweep of one tree is sequential; "
               "see the design notes for how instances would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
