@@ -121,6 +121,22 @@ def _vib():
     return vibronic_problem(n_modes=8, dmin=4, dmax=6, leaf_bond=4, l_bond=6, m_bond=8, dt=0.5)
 
 
+def test_vibronic24_full_size_sweep(T):
+    """The benchmarked workload itself (2 states x 24 modes, d 8-32, bonds
+    8/16/20, FP64: the kernels and launch shapes bench.py times), one sweep
+    from a seeded full-rank state: populations, autocorrelation and the
+    gauge-free overlap of the two states agree with the oracle to 1e-10."""
+    p = vibronic_problem()
+    st = random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=24)
+    g, o = _pair(T, p, state=st)
+    g.step(p.dt)
+    o.step(p.dt)
+    for name in ("P0", "P1"):
+        assert abs(g.expect(p.observables[name]) - o.expect(p.observables[name])) < TOL
+    assert abs(g.overlap_t0() - o.overlap_t0()) < TOL
+    assert abs(abs(_gauge_free_overlap(g.get_state(), o.state(), o)) - 1.0) < 1e-10
+
+
 def test_reduced_vibronic_random_state_parity(T):
     """Vibronic 2-state model, 8 modes, 3-layer tree (nodes with 3 and 4
     children, both Krylov paths), full-rank start: strict FP64 parity."""
