@@ -70,3 +70,32 @@ def test_exciton_tree_mixed_precisions(T):
         print(f"precision {prec}: max error {err:.2e}")
         assert err < 1e-4
         assert ("k_mode_mfma" in names) == (prec == T.TTN_BF16X3)
+
+
+def test_exciton10x120_full_size_properties(T):
+    """The full exciton workload (10 states, 120 modes, bonds 8/32/48/64,
+    1500 SOP terms: nodes of 7.08M elements, the sizes bench.py times), one
+    sweep from the product state. The oracle cannot run this size, so the
+    checks are properties that hold at any size: the FP64 sweep keeps the norm
+    and the energy (time-independent Hermitian generator), and the BF16x3 mode
+    (FP64 QR and Krylov around bf16 matrix-core stages) keeps the norm and stays
+    within the rounding floor of product-state starts (3e-3) of the FP64
+    populations."""
+    p = exciton_problem()
+    g = T.TTN.from_problem(p, precision=T.TTN_FP64)
+    g.set_product_state(p.init_vecs)
+    e0 = g.energy()
+    g.step(p.dt)
+    ref = _obs(g, p)
+    assert abs(g.norm2() - 1.0) < 1e-10
+    assert abs(g.energy() - e0) < 1e-9 * abs(e0)
+    g.close()
+    g = T.TTN.from_problem(p, precision=T.TTN_BF16X3)
+    g.set_product_state(p.init_vecs)
+    g.step(p.dt)
+    got = _obs(g, p)
+    assert abs(g.norm2() - 1.0) < 1e-9
+    g.close()
+    err = np.abs(got - ref).max()
+    print(f"BF16x3 vs FP64 after one sweep: {err:.2e}")
+    assert err < 3e-3
