@@ -226,6 +226,19 @@ def test_heom_arnoldi_parity(T, K, levels, bonds, n_steps, tol):
     assert abs(_heom_obs(g, p)[1] - 1.0) < tol
 
 
+def test_heom_full_size_sweep(T):
+    """The benchmarked HEOM workload (16 Debye poles, 32 auxiliary modes x 10
+    levels, bonds 10-48, dt 0.0075, Arnoldi): one sweep from the physical
+    product state, <sigma_z> and Tr rho_S against the oracle."""
+    p = heom_sbm_problem()
+    g, o = _pair(T, p, hermitian=False)
+    g.step(p.dt)
+    o.step(p.dt)
+    d = np.abs(_heom_obs(g, p) - _heom_obs(o, p)).max()
+    print(f"full-size HEOM sweep: max difference {d:.2e}")
+    assert d < TOL
+
+
 @pytest.mark.parametrize("bond", [4, 16])  # fused solver only / also the multi-kernel path
 def test_noconv_restores_state(T, bond):
     """A Krylov limit far too small for the step: TTN_E_NOCONV, and the state
