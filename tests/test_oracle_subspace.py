@@ -1,0 +1,133 @@
+"""Pins of the oracle's subspace expansion (Sec. II D), all on the CPU.
+
+The spawned functions must reduce the squared error of the time derivative,
+||(1 - P_T) G Psi||^2 with P_T the projector onto the one-site tangent space,
+by exactly the sum of the spawned sigma_s^2.  The tangent space here is built
+independently of the residual formula: the span of the state's derivatives
+with respect to every node tensor, from dense vectors.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle, dense_sop, full_state
+from oracle.subspace import expand, move_centre_down, residual, spawn
+from workloads import random_isometric_state, sbm_problem
+
+
+def _node_derivatives(o, z):
+    """Columns d Psi / d A^z (all other tensors fixed), dense."""
+    shp = o.A[z].shape
+    saved = o.A[z]
+    cols = []
+    for j in range(int(np.prod(shp))):
+        e = np.zeros(int(np.prod(shp)), dtype=np.complex128)
+        e[j] = 1.0
+        o.A[z] = e.reshape(shp)
+        cols.append(full_state(o.parent, o.local_dim, o.A))
+    o.A[z] = saved
+    return np.stack(cols, axis=1)
+
+
+def _tdvp_error2(o, G):
+    """||(1 - P_T) G Psi||^2: the part of the exact derivative the one-site TDVP misses."""
+    D = np.concatenate([_node_derivatives(o, z) for z in range(o.n)], axis=1)
+    U, s, _ = np.linalg.svd(D, full_matrices=False)
+    U = U[:, : int(np.sum(s > 1e-10 * s[0]))]
+    g = G @ full_state(o.parent, o.local_dim, o.A)
+    return float(np.linalg.norm(g - U @ (U.conj().T @ g)) ** 2)
+
+
+def _setup(bond, seed):
+    p = sbm_problem(n_modes=4, d=3, bond=bond, alpha=0.4)
+    o = Oracle(p)
+    o.set_state(random_isometric_state(p.parent, p.local_dim, o.bond, seed=seed))
+    return p, o, dense_sop(p)
+
+
+def _names(o):
+    B = o.kids[o.root][1]
+    B1 = o.kids[B][0]
+    return B, B1, o.kids[B1][1]
+
+
+@pytest.mark.parametrize("which", ["interior", "leaf"])
+def test_spawned_functions_remove_their_share_of_the_error(which):
+    """Centre at z, new functions of the child c: E - E_aug = sum sigma_s^2."""
+    p, o, G = _setup(bond=2, seed=3)
+    B, B1, leaf = _names(o)
+    if which == "interior":  # 4 x 4 children space, bond 2: two new functions
+        move_centre_down(o, [B])
+        z, c, n_new = B, B1, 2
+    else:  # leaf of dimension 3, bond 2: one direction left
+        move_centre_down(o, [B, B1])
+        z, c, n_new = B1, leaf, 1
+    k = o.kids[z].index(c)
+    psi = full_state(o.parent, o.local_dim, o.A)
+    e0 = _tdvp_error2(o, G)
+    s, vecs = spawn(o, z, k, G, dt=1.0, eps_s=1e-8, chi_max=o.bond[c] + 2, centre="z")
+    assert vecs.shape[1] == n_new and s[n_new - 1] > 1e-3 * s[0] > 0.0
+    assert np.abs(vecs.conj().T @ o.A[c].reshape(vecs.shape[0], -1)).max() < 1e-12  # orthogonal to the old ones
+    expand(o, z, k, vecs, centre="z")
+    assert np.abs(full_state(o.parent, o.local_dim, o.A) - psi).max() < 1e-14       # state unchanged
+    e1 = _tdvp_error2(o, G)
+    assert abs((e0 - e1) - np.sum(s[:n_new] ** 2)) < 1e-10 * e0
+
+
+def test_spawned_hole_functions_remove_their_share_of_the_error():
+    """Centre at c, new single hole functions of c: E - E_aug = sum sigma_s^2."""
+    p, o, G = _setup(bond=2, seed=4)
+    B, B1, _ = _names(o)
+    move_centre_down(o, [B, B1])
+    z, c = B, B1
+    k = o.kids[z].index(c)
+    psi = full_state(o.parent, o.local_dim, o.A)
+    e0 = _tdvp_error2(o, G)
+    s, vecs = spawn(o, z, k, G, dt=1.0, eps_s=0.0, chi_max=o.bond[c] + 1, centre="c")
+    assert vecs.shape[1] == 1 and s[0] > 0.0
+    expand(o, z, k, vecs, centre="c")
+    assert np.abs(full_state(o.parent, o.local_dim, o.A) - psi).max() < 1e-14
+    e1 = _tdvp_error2(o, G)
+    assert abs((e0 - e1) - s[0] ** 2) < 1e-10 * e0
+
+
+def test_a_random_direction_gains_less_than_the_dominant_one():
+    """Any other orthonormal new function removes at most sigma_0^2 (Delta's top eigenvalue)."""
+    p, o, G = _setup(bond=2, seed=5)
+    B, B1, _ = _names(o)
+    move_centre_down(o, [B])
+    k = o.kids[B].index(B1)
+    s, _ = spawn(o, B, k, G, dt=1.0, eps_s=0.0, chi_max=o.bond[B1] + 1, centre="z")
+    e0 = _tdvp_error2(o, G)
+    Ac = o.A[B1].reshape(-1, o.A[B1].shape[-1])
+    rng = np.random.default_rng(0)
+    v = rng.normal(size=Ac.shape[0]) + 1j * rng.normal(size=Ac.shape[0])
+    v -= Ac @ (Ac.conj().T @ v)
+    v /= np.linalg.norm(v)
+    expand(o, B, k, v[:, None], centre="z")
+    gain = e0 - _tdvp_error2(o, G)
+    assert -1e-12 < gain < s[0] ** 2 * (1 + 1e-10)
+
+
+def test_complete_bond_has_nothing_to_spawn():
+    """A bond at its clamp maximum already spans the whole space below c: R = 0."""
+    p, o, G = _setup(bond=100, seed=6)
+    B, B1, _ = _names(o)
+    move_centre_down(o, [B])
+    k = o.kids[B].index(B1)
+    assert o.bond[B1] == int(np.prod(o.A[B1].shape[:-1]))
+    assert np.abs(residual(o, B, k, G, centre="z")).max() < 1e-12
+
+
+def test_spawning_rule_threshold_and_cap():
+    """dt sigma >= eps_S decides, in decreasing order, within chi_max."""
+    p, o, G = _setup(bond=2, seed=7)
+    B, B1, _ = _names(o)
+    move_centre_down(o, [B])
+    k = o.kids[B].index(B1)
+    s, _ = spawn(o, B, k, G, dt=1.0, eps_s=0.0, chi_max=10, centre="z")
+    dt = 0.05
+    eps = dt * 0.5 * (s[0] + s[1])  # between the first two
+    _, v = spawn(o, B, k, G, dt=dt, eps_s=eps, chi_max=10, centre="z")
+    assert v.shape[1] == 1
+    _, v = spawn(o, B, k, G, dt=dt, eps_s=0.0, chi_max=o.bond[B1], centre="z")
+    assert v.shape[1] == 0
