@@ -379,7 +379,7 @@ def test_heom_pure_dephasing_closed_form():
     """Delta = 0, one Debye pole, full bonds: the coherence follows
     rho_updn(0) e^{-i eps t} exp(-Gamma(t)), Gamma(t) = 4 Re sum_k alpha_k
     [t/nu_k - (1 - e^{-nu_k t})/nu_k^2] (second-order cumulant, exact for a
-    Gaussian bath), and the trace stays 1 (Sec. II D 3)."""
+    Gaussian bath), and the trace stays 1 (Sec. II E 3)."""
     rho0 = 0.5 * np.ones((2, 2), dtype=np.complex128)
     p = heom_sbm_problem(K=1, levels=10, delta=0.0, rho0=rho0, bonds=(10_000,), dt=0.05)
     o = Oracle(p)

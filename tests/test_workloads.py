@@ -10,7 +10,7 @@ from workloads.models import debye_matsubara, gauss_rule, ohmic_discretisation, 
 
 @pytest.mark.parametrize("n", [4, 16, 64])
 def test_gauss_rule_moments(n):
-    """The N-point rule integrates w^k J(w) exactly for k <= 2N-1 (Sec. II D 1)."""
+    """The N-point rule integrates w^k J(w) exactly for k <= 2N-1 (Sec. II E 1)."""
     alpha, wc = 0.1, 5.0
     W = 10 * wc
     w, a = gauss_rule(lambda x: ohmic_J(x, alpha, wc), 0.0, W, n)

@@ -13,7 +13,7 @@ bond dimensions) with ``numpy.random.default_rng(seed)`` in a fixed order.
 * ``exciton_problem``: 10-state / 120-mode linear vibronic exciton model with
   composite (mode-combined) leaves (Sec. IV B).
 * ``heom_sbm_problem``: free-pole HEOM in bosonic-operator form for the
-  spin-boson model with a Debye bath (Sec. II D 3).
+  spin-boson model with a Debye bath (Sec. II E 3).
 * ``batch_sbm_problems``: many independent spin-boson instances of uneven size.
 """
 from __future__ import annotations
@@ -79,7 +79,7 @@ def ohmic_J(w, alpha: float, wc: float):
 
 
 def gauss_rule(J, wmin: float, wmax: float, n: int, nquad: int = 4000):
-    """N-point Gauss rule for the weight J(w) on [wmin, wmax] (Sec. II D 1).
+    """N-point Gauss rule for the weight J(w) on [wmin, wmax] (Sec. II E 1).
 
     The recurrence coefficients of the orthonormal polynomials are obtained with
     the discretised Stieltjes (Lanczos) procedure on a fine Gauss-Legendre
@@ -339,7 +339,7 @@ def heom_sbm_problem(K: int = 16, levels: int = 10, eps: float = 0.5, delta: flo
     """Free-pole HEOM of the spin-boson model in bosonic-operator form.
 
     Generator ``G`` with ``d/dt |rho) = -i G |rho)`` (Eq. for the HEOM in
-    operator form, Sec. II D 3, with the main text's scaling of the up/down
+    operator form, Sec. II E 3, with the main text's scaling of the up/down
     couplings):
     ``G = L_s - i sum_k (nu_k n_k + nu_k^* nt_k)
           + sum_k [alpha_k/sqrt|alpha_k| S^L a_k^dag - alpha_k^*/sqrt|alpha_k| S^R at_k^dag]
