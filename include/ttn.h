@@ -137,8 +137,9 @@ ttn_status ttn_set_product_state(ttn_t h, const double *leaf_vecs);
 /* Advance n_steps steps of dt (dt may be negative).  One step is the symmetric
  * projector-splitting sweep S(dt/2) S*(dt/2) with the two root forward half
  * steps merged (2N-1 forward, 2(N-1) backward local exponentials, 4(N-1) QRs).
- * Errors: TTN_E_STATE, TTN_E_NOCONV (state restored to before the failed
- * step), TTN_E_DEVICE. */
+ * n_steps = 0 does nothing.
+ * Errors: TTN_E_INVALID (n_steps < 0, dt not finite), TTN_E_STATE,
+ * TTN_E_NOCONV (state restored to before the failed step), TTN_E_DEVICE. */
 ttn_status ttn_step(ttn_t h, double dt, int32_t n_steps);
 
 /* Observables; out receives complex values (2 doubles each), caller-owned.

@@ -180,6 +180,36 @@ def test_negative_dt_reverses(T):
     assert abs(abs(_gauge_free_overlap(ref, g.get_state(), o)) - 1.0) < 1e-11
 
 
+def test_degenerate_cases(T):
+    """Smallest tree (root with two leaves, complete bonds): 20 sweeps equal the
+    exact propagator exp(-i G t) psi0 and the oracle; a sweep with dt = 0
+    leaves the state unchanged (up to rounding, the gauge may flip signs) and
+    zero sweeps leave the tensors bit for bit."""
+    from scipy.linalg import expm
+    from oracle import dense_sop
+    p = sbm_problem(n_modes=1, d=3, bond=4, dt=0.05)
+    g, o = _pair(T, p)
+    psi0 = full_state(p.parent, p.local_dim, g.get_state())
+    for _ in range(20):
+        g.step(p.dt)
+        o.step(p.dt)
+    exact = expm(-1j * 20 * p.dt * dense_sop(p)) @ psi0
+    assert np.abs(full_state(p.parent, p.local_dim, g.get_state()) - exact).max() < 1e-10
+    assert abs(g.expect(p.observables["sz"]) - o.expect(p.observables["sz"])) < TOL
+    before = g.get_state()
+    g.step(0.0)
+    after = full_state(p.parent, p.local_dim, g.get_state())
+    assert np.abs(after - full_state(p.parent, p.local_dim, before)).max() < 1e-13
+    before = g.get_state()
+    g.step(p.dt, 0)
+    for bad in ((float("nan"), 1), (float("inf"), 1), (p.dt, -1)):
+        with pytest.raises(T.TTNError) as e:
+            g.step(*bad)
+        assert "E_INVALID" in str(e.value)
+    for x, y in zip(before, g.get_state()):
+        assert np.array_equal(x, y)
+
+
 def test_non_hermitian_rejected_with_lanczos(T):
     p = heom_sbm_problem(K=1, levels=3)
     with pytest.raises(T.TTNError) as e:
