@@ -166,3 +166,174 @@ def expand(o: Oracle, z: int, k: int, vecs: np.ndarray, centre: str) -> None:
         pad = np.zeros(below + (s,), dtype=np.complex128)
         o.A[c] = np.concatenate([o.A[c], pad], axis=-1)
     o.bond[c] += s
+
+
+# ------------------------------------------------------ one-site-cost form
+# The same residual without forming X: the two-site generator is kept as a
+# list of (coefficient, factors below c, factors outside c) built from the
+# environments the sweep maintains, and X acts on a vector through the two
+# node tensors one after the other, A^z then A^c (or back), which costs about
+# one single-site matvec; the dominant singular pairs then come from a
+# Krylov (Golub-Kahan-Lanczos) iteration, the iterative route Sec. II D takes.
+
+def two_site_terms(o: Oracle, z: int, k: int):
+    """The two-site generator at (z, c = k-th child) as (coef, below factors, outside factors).
+
+    Factor dictionaries map an axis of the two-site tensor (indices below c,
+    then A^z's indices without k) to a matrix; SPOs of c's children (or c's
+    own leaf operators) act below, SPOs of z's other children and z's mean
+    field act outside.  Terms confined to one of these pieces enter through
+    the aggregated "in" / "out" environments, every other term individually.
+    """
+    c = o.kids[z][k]
+    nbel = o.A[c].ndim - 1
+    ckids = o.kids[c]
+    zother = [cj for j, cj in enumerate(o.kids[z]) if j != k]
+    ax = {cj: nbel + i for i, cj in enumerate(zother)}
+    pax = nbel + len(zother)
+    has_out = z != o.root
+    out = []
+    # aggregates
+    if o.local_dim[c] > 0:
+        loc = [r for r in range(len(o.terms)) if o.inside(r, c)]
+        if loc:
+            out.append((1.0, {0: sum(o.coef[r] * o.terms[r][c] for r in loc)}, {}))
+    else:
+        for j, cj in enumerate(ckids):
+            if "in" in o.spo[cj]:
+                out.append((1.0, {j: o.spo[cj]["in"]}, {}))
+    for cj in zother:
+        if "in" in o.spo[cj]:
+            out.append((1.0, {}, {ax[cj]: o.spo[cj]["in"]}))
+    if has_out and "out" in o.mf[z]:
+        out.append((1.0, {}, {pax: o.mf[z]["out"]}))
+    # terms spanning two or more pieces
+    for r in range(len(o.terms)):
+        below_hit = ([0] if o.touches(r, c) else []) if o.local_dim[c] > 0 else \
+            [j for j, cj in enumerate(ckids) if o.touches(r, cj)]
+        other_hit = [cj for cj in zother if o.touches(r, cj)]
+        outside_hit = has_out and o.touches_outside(r, z)
+        if len(below_hit) + len(other_hit) + int(outside_hit) < 2:
+            continue  # confined to one piece: part of an aggregate above
+        # spanning several pieces, the term crosses each of them: own SPOs / mean field
+        if o.local_dim[c] > 0:
+            fb = {0: o.terms[r][c]} if below_hit else {}
+        else:
+            fb = {j: o.spo[ckids[j]][r] for j in below_hit}
+        fo = {ax[cj]: o.spo[cj][r] for cj in other_hit}
+        if outside_hit:
+            fo[pax] = o.mf[z][r]
+        out.append((o.coef[r], fb, fo))
+    return out
+
+
+def _apply(X: np.ndarray, factors, conj: bool = False, transpose: bool = False, shift: int = 0) -> np.ndarray:
+    for axis, M in factors.items():
+        M2 = M.T if transpose else M
+        X = mode_product(X, M2.conj() if conj else M2, axis - shift)
+    return X
+
+
+def heff2(o: Oracle, z: int, k: int, T: np.ndarray) -> np.ndarray:
+    """Two-site generator applied to a two-site tensor T (below c, then outside c)."""
+    Y = np.zeros_like(T)
+    for coef, fb, fo in two_site_terms(o, z, k):
+        Y += coef * _apply(_apply(T, fb), fo)
+    return Y
+
+
+class ResidualOperator:
+    """R = (1 - P_c) X (1 - P_o^T) applied to vectors at one-site cost.
+
+    X w = sum_t c_t F_t,below A^c (A^z^T (F_t,outside^T w)): per term the
+    outside factors act on w, the result is contracted with A^z down to the
+    bond, expanded through A^c and the factors below c act last.  X^dag runs
+    the same chain backwards with conjugated factors.
+    """
+
+    def __init__(self, o: Oracle, z: int, k: int, centre: str):
+        c = o.kids[z][k]
+        self.below = o.A[c].shape[:-1]
+        self.outside = o.A[z].shape[:k] + o.A[z].shape[k + 1:]
+        self.nbel = len(self.below)
+        self.nb, self.no = int(np.prod(self.below)), int(np.prod(self.outside))
+        self.Ac = o.A[c].reshape(self.nb, -1)
+        self.Az = np.moveaxis(o.A[z], k, -1).reshape(self.no, -1)
+        if centre not in ("z", "c"):
+            raise ValueError(centre)
+        self.Pc = _span_projector(self.Ac)
+        self.Po = _span_projector(self.Az)
+        self.terms = two_site_terms(o, z, k)
+
+    def X(self, w: np.ndarray) -> np.ndarray:
+        W = w.reshape(self.outside)
+        y = np.zeros(self.nb, dtype=np.complex128)
+        for coef, fb, fo in self.terms:
+            u = _apply(W, fo, transpose=True, shift=self.nbel).reshape(-1)
+            t = self.Ac @ (self.Az.T @ u)
+            y += coef * _apply(t.reshape(self.below), fb).reshape(-1)
+        return y
+
+    def XH(self, y: np.ndarray) -> np.ndarray:
+        Y = y.reshape(self.below)
+        w = np.zeros(self.no, dtype=np.complex128)
+        for coef, fb, fo in self.terms:
+            u = _apply(Y, fb, conj=True, transpose=True).reshape(-1)
+            t = self.Az.conj() @ (self.Ac.conj().T @ u)
+            w += np.conj(coef) * _apply(t.reshape(self.outside), fo, conj=True, shift=self.nbel).reshape(-1)
+        return w
+
+    def R(self, w: np.ndarray) -> np.ndarray:
+        w = w - self.Po.T @ w
+        y = self.X(w)
+        return y - self.Pc @ y
+
+    def RH(self, y: np.ndarray) -> np.ndarray:
+        y = y - self.Pc @ y
+        w = self.XH(y)
+        return w - self.Po.conj() @ w
+
+
+def krylov_singular(op: ResidualOperator, m: int, start: np.ndarray):
+    """Golub-Kahan-Lanczos bidiagonalisation of R with full re-orthogonalisation.
+
+    ``start`` is a (seeded) vector below c; the iteration starts from
+    R^dag start, so it stays in the row space of R (at most nb dimensional)
+    and m = nb steps reproduce the dense singular values.  Returns the
+    singular values of the bidiagonal and the corresponding approximate left
+    (below c) and right (outside c) singular vectors of R, largest first.
+    """
+    q = op.RH(start)
+    if np.linalg.norm(q) == 0.0:
+        return np.zeros(0), np.zeros((op.nb, 0), dtype=np.complex128), np.zeros((op.no, 0), dtype=np.complex128)
+    q = q / np.linalg.norm(q)
+    Q, P, alpha, beta = [q], [], [], []
+    for j in range(m):
+        p = op.R(Q[-1])
+        if P:
+            p -= beta[-1] * P[-1]
+            for v in P:  # full re-orthogonalisation
+                p -= np.vdot(v, p) * v
+        a = np.linalg.norm(p)
+        if a <= 1e-14:
+            break
+        P.append(p / a)
+        alpha.append(a)
+        qn = op.RH(P[-1]) - a * Q[-1]
+        for v in Q:
+            qn -= np.vdot(v, qn) * v
+        b = np.linalg.norm(qn)
+        if b <= 1e-14 or j == m - 1:
+            break
+        Q.append(qn / b)
+        beta.append(b)
+    n = len(alpha)
+    if n == 0:  # R vanishes on the start vector's Krylov space
+        return np.zeros(0), np.zeros((op.nb, 0), dtype=np.complex128), np.zeros((op.no, 0), dtype=np.complex128)
+    B = np.diag(np.asarray(alpha, dtype=np.complex128))
+    for i in range(n - 1):
+        B[i, i + 1] = beta[i]
+    Ub, s, Vbh = np.linalg.svd(B)
+    left = np.stack(P[:n], axis=1) @ Ub
+    right = np.stack(Q[:n], axis=1) @ Vbh.conj().T
+    return s, left, right

@@ -131,3 +131,72 @@ def test_spawning_rule_threshold_and_cap():
     assert v.shape[1] == 1
     _, v = spawn(o, B, k, G, dt=dt, eps_s=0.0, chi_max=o.bond[B1], centre="z")
     assert v.shape[1] == 0
+
+
+# ------------------------------------------- one-site-cost form vs the definition
+def _configs():
+    """(path of the centre from the root, z, child c, centre side) on the 4-mode tree."""
+    def make(o):
+        B, B1, leaf = _names(o)
+        return [([B], B, B1, "z"), ([B, B1], B1, leaf, "z"), ([B, B1], B, B1, "c"),
+                ([B, B1, leaf], B1, leaf, "c")]
+    return make
+
+
+def _centred(p, state, path):
+    from oracle.ttn_oracle import mode_product
+    o = Oracle(p, hermitian=False)
+    o.set_state(state)
+    z = o.root
+    for c in path:  # gauge shift with mean fields, as the sweep does on its way down
+        k = o.kids[z].index(c)
+        Q, R = o.qr_along(o.A[z], k)
+        o.A[z] = Q
+        o.A[c] = mode_product(o.A[c], R, o.A[c].ndim - 1)
+        o.build_mf(z, k)
+        z = c
+    return o
+
+
+def _nonhermitian_sbm():
+    from workloads.models import boson_ops
+    p = sbm_problem(n_modes=4, d=3, bond=2, alpha=0.4)
+    p.term_ops.append([p.observables["sx"][0], p.add_op(p.leaf_names["b1"], boson_ops(3)["q2"]),
+                       p.add_op(p.leaf_names["b2"], boson_ops(3)["q"])])
+    p.coeff = np.append(p.coeff, 0.3 - 0.1j)
+    return p
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_one_site_cost_form_matches_the_definition(idx):
+    """The two-site generator from the sweep's environments equals V2^dag G V2;
+    R and R^dag applied through A^z and A^c equal the dense residual; the
+    Golub-Kahan-Lanczos singular pairs (started in R's row space, nb steps)
+    equal the dense SVD, singular vectors up to phase."""
+    from oracle.subspace import ResidualOperator, heff2, krylov_singular, two_site_embedding
+    p = _nonhermitian_sbm()
+    G = dense_sop(p)
+    st = random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=11)
+    path, z, c, side = _configs()(Oracle(p))[idx]
+    o = _centred(p, st, path)
+    k = o.kids[z].index(c)
+    rng = np.random.default_rng(idx)
+    V2, below, outside = two_site_embedding(o, z, k)
+    T = rng.normal(size=below + outside) + 1j * rng.normal(size=below + outside)
+    ref = (V2.conj().T @ G @ V2 @ T.reshape(-1)).reshape(T.shape)
+    assert np.abs(heff2(o, z, k, T) - ref).max() < 1e-12 * np.abs(ref).max()
+    Rd = residual(o, z, k, G, side)
+    op = ResidualOperator(o, z, k, side)
+    w = rng.normal(size=op.no) + 1j * rng.normal(size=op.no)
+    y = rng.normal(size=op.nb) + 1j * rng.normal(size=op.nb)
+    scale = max(np.abs(Rd).max(), 1.0)
+    assert np.abs(op.R(w) - Rd @ w).max() < 1e-12 * scale * np.abs(w).sum()
+    assert np.abs(op.RH(y) - Rd.conj().T @ y).max() < 1e-12 * scale * np.abs(y).sum()
+    U, s, Vh = np.linalg.svd(Rd)
+    sk, L, Rv = krylov_singular(op, op.nb, rng.normal(size=op.nb) + 1j * rng.normal(size=op.nb))
+    r = int(np.sum(s > 1e-10 * max(s[0], 1e-300)))
+    assert len(sk) >= r
+    assert np.abs(sk[:r] - s[:r]).max() < 1e-12 * max(s[0], 1.0)
+    for i in range(r):  # simple singular values here: vectors agree up to a phase
+        assert abs(abs(np.vdot(U[:, i], L[:, i])) - 1.0) < 1e-10
+        assert abs(abs(np.vdot(Vh[i].conj(), Rv[:, i])) - 1.0) < 1e-10
