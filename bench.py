@@ -313,9 +313,15 @@ def main():
                           key=lambda r: -r["total_ms"])[:8],
     }
     if not args.no_extra:
-        out["config"]["exciton10x120"] = exciton_run(T, 1)
-        out["config"]["heom_sbm"] = heom_run(T, 3)
-        out["config"]["batched_instances"] = batch_run(T, args.batch_instances, 1)
+        # the other workloads are context lines: a failure there is recorded, and
+        # the headline line is still printed
+        for key, fn in (("exciton10x120", lambda: exciton_run(T, 1)), ("heom_sbm", lambda: heom_run(T, 3)),
+                        ("batched_instances", lambda: batch_run(T, args.batch_instances, 1))):
+            try:
+                out["config"][key] = fn()
+            except (T.TTNError, RuntimeError, MemoryError) as e:
+                out["config"][key] = {"error": str(e)}
+                print(f"bench.py: {key} failed: {e}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)
