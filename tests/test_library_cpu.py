@@ -88,3 +88,17 @@ def test_invalid_sop_rejected():
     with pytest.raises(T.TTNError) as e:
         T.dense_tree_operator(p)
     assert "E_INVALID" in str(e.value)
+
+
+@pytest.mark.parametrize("where", ["coefficient", "operator"])
+def test_non_finite_sop_rejected(where):
+    """A NaN coefficient or an infinite operator entry is refused on the host."""
+    p = sbm_problem(n_modes=2, d=2, bond=2)
+    if where == "coefficient":
+        p.coeff = np.array(p.coeff, dtype=np.complex128)
+        p.coeff[1] = complex(np.nan, 0.0)
+    else:
+        p.op_mats[p.observables["sz"][0]] = np.array([[np.inf, 0], [0, -1]], dtype=np.complex128)
+    with pytest.raises(T.TTNError) as e:
+        T.dense_tree_operator(p)
+    assert "E_INVALID" in str(e.value)
