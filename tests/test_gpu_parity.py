@@ -210,6 +210,29 @@ def test_degenerate_cases(T):
         assert np.array_equal(x, y)
 
 
+def test_checkpoint_resume(T):
+    """ttn_get_state / ttn_set_state as checkpoint and resume: a fresh handle
+    loaded with the saved tensors continues the run (environments are rebuilt
+    from the tensors; only the Krylov dimension hints start afresh, so the
+    two runs agree to the Krylov tolerance, not bit for bit)."""
+    p = _vib()
+    st = random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=17)
+    g = T.TTN.from_problem(p)
+    g.set_state(st)
+    g.step(p.dt, 4)
+    saved = g.get_state()
+    g.step(p.dt, 4)
+    h = T.TTN.from_problem(p)
+    h.set_state(saved)
+    h.step(p.dt, 4)
+    for name in ("P0", "P1"):
+        assert abs(g.expect(p.observables[name]) - h.expect(p.observables[name])) < 1e-11
+    o = Oracle(p)
+    assert abs(abs(_gauge_free_overlap(g.get_state(), h.get_state(), o)) - 1.0) < 1e-11
+    g.close()
+    h.close()
+
+
 def test_non_hermitian_rejected_with_lanczos(T):
     p = heom_sbm_problem(K=1, levels=3)
     with pytest.raises(T.TTNError) as e:
