@@ -22,14 +22,14 @@ What it follows (paper: pyTTN, arXiv 2503.15460, Sec. II D):
 Reading (the paper defers the details to its reference on MCTDH spawning):
 with X the two-site projection of G Psi, matricised as (indices below c) x
 (indices outside c), the error restricted to the two-site space and
-orthogonal to the one-site tangent space is R = (1 - P_c) X (1 - P_o), where
-P_c projects onto the span of c's current functions (the columns of A^c) and
-P_o onto the span the current coefficients reach on the outside (the row
-space of A^z along bond k).  Delta = R R^dag, so the spawned functions are
-the dominant left singular vectors of R and lambda_s = sigma_s^2; moving up,
-the roles swap: P_o becomes the projector onto the current single hole
-functions and P_c the column space of the centre A^c, and the new single hole
-functions are the dominant right singular vectors.
+orthogonal to the one-site tangent space is R = (1 - P_c) X (1 - P_o^T),
+where P_c projects onto the column space of A^c (c's current functions, or
+the centre's columns) and P_o onto the column space of A^z matricised along
+bond k (the outside functions the bond reaches); the transpose appears
+because X's rows are coordinate vectors on the outside.  Delta = R R^dag, so
+new functions below the bond are the dominant left singular vectors of R
+(lambda_s = sigma_s^2) and new functions outside it the conjugated dominant
+right singular vectors.  The formula holds with the centre at z or at c.
 
 Everything here uses dense vectors of the whole state: X = V2^dag G Psi with
 V2 the orthonormal two-site embedding, SVDs from numpy.  It is exact up to
@@ -95,11 +95,11 @@ def two_site_embedding(o: Oracle, z: int, k: int) -> Tuple[np.ndarray, Tuple[int
 
 
 def residual(o: Oracle, z: int, k: int, G: np.ndarray, centre: str) -> np.ndarray:
-    """R = (1 - P_c) X (1 - P_o) for the bond (z, k-th child), matricised (below c) x (outside c).
+    """R = (1 - P_c) X (1 - P_o^T) for the bond (z, k-th child), matricised (below c) x (outside c).
 
-    ``centre`` is "z" (spawning functions of c: P_c from the isometry A^c,
-    P_o from the row space of A^z along k) or "c" (spawning single hole
-    functions: P_o from the isometry A^z, P_c from the column space of A^c).
+    ``centre`` names where the orthogonality centre is, "z" or "c"; the node
+    on the other side of the bond must be an isometry toward it (checked), so
+    that the two-site embedding is orthonormal.
     """
     c = o.kids[z][k]
     V2, below, outside = two_site_embedding(o, z, k)
@@ -123,32 +123,51 @@ def residual(o: Oracle, z: int, k: int, G: np.ndarray, centre: str) -> np.ndarra
     return (I_b - Pc) @ X @ (I_o - Po.T)
 
 
-def spawn(o: Oracle, z: int, k: int, G: np.ndarray, dt: float, eps_s: float, chi_max: int,
-          centre: str) -> Tuple[np.ndarray, np.ndarray]:
-    """Singular values of R and the functions to add (columns), by the spawning rule.
+def _room(o: Oracle, z: int, k: int, chi_max: int) -> int:
+    """How many functions the bond (z, k-th child) may still gain: up to chi_max
+    and up to what both sides can hold as orthonormal columns (the rows of A^c
+    below the bond and of A^z along it), so every matricisation keeps rows >=
+    columns."""
+    c = o.kids[z][k]
+    nb = int(np.prod(o.A[c].shape[:-1]))
+    no = int(np.prod(o.A[z].shape[:k] + o.A[z].shape[k + 1:]))
+    return max(0, min(chi_max, nb, no) - o.A[c].shape[-1])
 
-    Functions are taken in decreasing sigma while |dt| sigma >= eps_s and the
-    bond stays within chi_max.  centre "z": left singular vectors (new
-    functions of c, in the basis below c); centre "c": right singular vectors
-    conjugated (new single hole functions, in the basis outside c).
-    """
-    R = residual(o, z, k, G, centre)
-    U, s, Vh = np.linalg.svd(R, full_matrices=False)
-    n_now = o.A[o.kids[z][k]].shape[-1]
-    room = max(0, chi_max - n_now)
+
+def _take(s: np.ndarray, dt: float, eps_s: float, room: int) -> int:
     take = 0
     while take < min(room, s.size) and abs(dt) * s[take] >= eps_s:
         take += 1
-    vecs = U[:, :take] if centre == "z" else Vh[:take].T  # outside: conjugated right singular vectors
-    return s, vecs
+    return take
 
 
-def expand(o: Oracle, z: int, k: int, vecs: np.ndarray, centre: str) -> None:
+def spawn(o: Oracle, z: int, k: int, G: np.ndarray, dt: float, eps_s: float, chi_max: int,
+          centre: str, side: str) -> Tuple[np.ndarray, np.ndarray]:
+    """Singular values of R and the functions to add (columns), by the spawning rule.
+
+    Functions are taken in decreasing sigma while |dt| sigma >= eps_s and the
+    bond stays within chi_max and within what both sides can hold.  side
+    "below": left singular vectors (new functions of c, basis below c);
+    "outside": conjugated right singular vectors (new single hole functions,
+    basis outside c).
+    """
+    R = residual(o, z, k, G, centre)
+    U, s, Vh = np.linalg.svd(R, full_matrices=False)
+    take = _take(s, dt, eps_s, _room(o, z, k, chi_max))
+    if side == "below":
+        return s, U[:, :take]
+    if side == "outside":
+        return s, Vh[:take].T
+    raise ValueError(side)
+
+
+def expand(o: Oracle, z: int, k: int, vecs: np.ndarray, side: str) -> None:
     """Widen the bond (z, k-th child) by the given orthonormal functions, zero coefficients.
 
-    centre "z": the columns of A^c gain ``vecs`` (basis below c) and A^z gains
-    zero slices along k; centre "c": A^z gains ``vecs`` as new columns along k
-    (basis outside c) and A^c gains zero slices along its parent index.
+    side "below": A^c gains ``vecs`` as new columns (basis below c) and A^z
+    zero slices along k; side "outside": A^z gains ``vecs`` as new slices
+    along k (basis outside c) and A^c zero columns.  Either way the state is
+    unchanged; which tensor is the centre does not matter.
     """
     c = o.kids[z][k]
     s = vecs.shape[1]
@@ -156,15 +175,17 @@ def expand(o: Oracle, z: int, k: int, vecs: np.ndarray, centre: str) -> None:
         return
     below = o.A[c].shape[:-1]
     outside = o.A[z].shape[:k] + o.A[z].shape[k + 1:]
-    if centre == "z":
+    if side == "below":
         o.A[c] = np.concatenate([o.A[c], vecs.reshape(below + (s,))], axis=-1)
         pad = np.zeros(o.A[z].shape[:k] + (s,) + o.A[z].shape[k + 1:], dtype=np.complex128)
         o.A[z] = np.concatenate([o.A[z], pad], axis=k)
-    else:
+    elif side == "outside":
         new = np.moveaxis(vecs.reshape(outside + (s,)), -1, k)
         o.A[z] = np.concatenate([o.A[z], new], axis=k)
         pad = np.zeros(below + (s,), dtype=np.complex128)
         o.A[c] = np.concatenate([o.A[c], pad], axis=-1)
+    else:
+        raise ValueError(side)
     o.bond[c] += s
 
 
@@ -251,7 +272,7 @@ class ResidualOperator:
     the same chain backwards with conjugated factors.
     """
 
-    def __init__(self, o: Oracle, z: int, k: int, centre: str):
+    def __init__(self, o: Oracle, z: int, k: int):
         c = o.kids[z][k]
         self.below = o.A[c].shape[:-1]
         self.outside = o.A[z].shape[:k] + o.A[z].shape[k + 1:]
@@ -259,8 +280,6 @@ class ResidualOperator:
         self.nb, self.no = int(np.prod(self.below)), int(np.prod(self.outside))
         self.Ac = o.A[c].reshape(self.nb, -1)
         self.Az = np.moveaxis(o.A[z], k, -1).reshape(self.no, -1)
-        if centre not in ("z", "c"):
-            raise ValueError(centre)
         self.Pc = _span_projector(self.Ac)
         self.Po = _span_projector(self.Az)
         self.terms = two_site_terms(o, z, k)
@@ -337,3 +356,104 @@ def krylov_singular(op: ResidualOperator, m: int, start: np.ndarray):
     left = np.stack(P[:n], axis=1) @ Ub
     right = np.stack(Q[:n], axis=1) @ Vbh.conj().T
     return s, left, right
+
+
+# ------------------------------------------------------ the adaptive sweep
+def spawn_krylov(o: Oracle, z: int, k: int, dt: float, eps_s: float, chi_max: int, side: str,
+                 rng: np.random.Generator) -> np.ndarray:
+    """New functions for the bond (z, k-th child) by the one-site-cost route.
+
+    Golub-Kahan-Lanczos on R with as many steps as R has rows below c (exact
+    on the trees this oracle handles), then the spawning rule of ``spawn``.
+    Columns are orthonormal and orthogonal to the current functions on that
+    side of the bond.
+    """
+    op = ResidualOperator(o, z, k)
+    start = rng.normal(size=op.nb) + 1j * rng.normal(size=op.nb)
+    s, left, right = krylov_singular(op, op.nb, start)
+    take = _take(s, dt, eps_s, _room(o, z, k, chi_max))
+    return left[:, :take] if side == "below" else right[:, :take].conj()
+
+
+class AdaptiveOracle(Oracle):
+    """The projector-splitting sweep with subspace expansion at the bond crossings.
+
+    Sec. II D widens a bond with zero coefficients (the state is unchanged)
+    when the orthogonality centre crosses it.  Reading: in the splitting, the
+    evolution of the bond space is counted by the forward steps on both sides
+    and subtracted once by the backward bond step, so the widening must come
+    after the forward step of the side that does not see the new directions
+    and before the bond step and the forward step of the side that does.  Per
+    bond (z above c):
+
+    * S (going up, forward steps after the children): with the centre at c,
+      after c's forward step and before the QR, backward bond step and z's
+      forward step, new functions below the bond (new SPFs of c);
+    * S* (going down, forward steps before the children): with the centre at
+      z, after z's forward step and before the QR, backward bond step and c's
+      forward step, new single hole functions of c.
+
+    Widening elsewhere (e.g. with the centre at z before S's gauge-only move
+    down) either loses the new directions in the next QR or counts them twice.
+    ``chi_max`` caps every bond, ``eps_s`` is the spawning tolerance
+    (criterion |h| sigma >= eps_s with h the substep), ``seed`` seeds the
+    Krylov start vectors.
+    """
+
+    def __init__(self, problem, eps_s: float, chi_max: int, seed: int = 0, **kw):
+        super().__init__(problem, **kw)
+        self.eps_s, self.chi_max = eps_s, chi_max
+        self.rng = np.random.default_rng(seed)
+        self.spawned = 0
+
+    def _grow(self, z: int, k: int, h: float, side: str) -> bool:
+        vecs = spawn_krylov(self, z, k, h, self.eps_s, self.chi_max, side, self.rng)
+        if vecs.shape[1] == 0:
+            return False
+        expand(self, z, k, vecs, side)
+        self.spawned += vecs.shape[1]
+        return True
+
+    def _S(self, z: int, h: float) -> None:
+        for k, c in enumerate(self.kids[z]):
+            Q, R = self.qr_along(self.A[z], k)           # gauge down
+            self.A[z] = Q
+            self.A[c] = mode_product(self.A[c], R, self.A[c].ndim - 1)
+            self.build_mf(z, k)
+            if self.local_dim[c] > 0:
+                self.forward(c, h)
+            else:
+                self._S(c, h)
+            if self._grow(z, k, h, "below"):             # centre at c: new functions of c
+                self.build_mf(z, k)
+            pax = self.A[c].ndim - 1                      # up: backward bond step
+            Q, R = self.qr_along(self.A[c], pax)
+            self.A[c] = Q
+            self.build_spo(c)
+            C = self.backward(c, R, h)
+            self.A[z] = mode_product(self.A[z], C, k)
+        if z != self.root:
+            self.forward(z, h)
+
+    def _Sstar(self, z: int, h: float) -> None:
+        if z != self.root:
+            self.forward(z, h)
+        kids = self.kids[z]
+        for k in range(len(kids) - 1, -1, -1):
+            c = kids[k]
+            if self._grow(z, k, h, "outside"):           # centre at z: new hole functions of c
+                self.build_spo(c)
+            Q, R = self.qr_along(self.A[z], k)           # down: backward bond step
+            self.A[z] = Q
+            self.build_mf(z, k)
+            C = self.backward(c, R.T, h)
+            self.A[c] = mode_product(self.A[c], C.T, self.A[c].ndim - 1)
+            if self.local_dim[c] > 0:
+                self.forward(c, h)
+            else:
+                self._Sstar(c, h)
+            pax = self.A[c].ndim - 1                      # gauge up
+            Q, R = self.qr_along(self.A[c], pax)
+            self.A[c] = Q
+            self.build_spo(c)
+            self.A[z] = mode_product(self.A[z], R, k)

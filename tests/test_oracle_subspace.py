@@ -64,10 +64,10 @@ def test_spawned_functions_remove_their_share_of_the_error(which):
     k = o.kids[z].index(c)
     psi = full_state(o.parent, o.local_dim, o.A)
     e0 = _tdvp_error2(o, G)
-    s, vecs = spawn(o, z, k, G, dt=1.0, eps_s=1e-8, chi_max=o.bond[c] + 2, centre="z")
+    s, vecs = spawn(o, z, k, G, dt=1.0, eps_s=1e-8, chi_max=o.bond[c] + 2, centre="z", side="below")
     assert vecs.shape[1] == n_new and s[n_new - 1] > 1e-3 * s[0] > 0.0
     assert np.abs(vecs.conj().T @ o.A[c].reshape(vecs.shape[0], -1)).max() < 1e-12  # orthogonal to the old ones
-    expand(o, z, k, vecs, centre="z")
+    expand(o, z, k, vecs, side="below")
     assert np.abs(full_state(o.parent, o.local_dim, o.A) - psi).max() < 1e-14       # state unchanged
     e1 = _tdvp_error2(o, G)
     assert abs((e0 - e1) - np.sum(s[:n_new] ** 2)) < 1e-10 * e0
@@ -82,9 +82,9 @@ def test_spawned_hole_functions_remove_their_share_of_the_error():
     k = o.kids[z].index(c)
     psi = full_state(o.parent, o.local_dim, o.A)
     e0 = _tdvp_error2(o, G)
-    s, vecs = spawn(o, z, k, G, dt=1.0, eps_s=0.0, chi_max=o.bond[c] + 1, centre="c")
+    s, vecs = spawn(o, z, k, G, dt=1.0, eps_s=0.0, chi_max=o.bond[c] + 1, centre="c", side="outside")
     assert vecs.shape[1] == 1 and s[0] > 0.0
-    expand(o, z, k, vecs, centre="c")
+    expand(o, z, k, vecs, side="outside")
     assert np.abs(full_state(o.parent, o.local_dim, o.A) - psi).max() < 1e-14
     e1 = _tdvp_error2(o, G)
     assert abs((e0 - e1) - s[0] ** 2) < 1e-10 * e0
@@ -96,14 +96,14 @@ def test_a_random_direction_gains_less_than_the_dominant_one():
     B, B1, _ = _names(o)
     move_centre_down(o, [B])
     k = o.kids[B].index(B1)
-    s, _ = spawn(o, B, k, G, dt=1.0, eps_s=0.0, chi_max=o.bond[B1] + 1, centre="z")
+    s, _ = spawn(o, B, k, G, dt=1.0, eps_s=0.0, chi_max=o.bond[B1] + 1, centre="z", side="below")
     e0 = _tdvp_error2(o, G)
     Ac = o.A[B1].reshape(-1, o.A[B1].shape[-1])
     rng = np.random.default_rng(0)
     v = rng.normal(size=Ac.shape[0]) + 1j * rng.normal(size=Ac.shape[0])
     v -= Ac @ (Ac.conj().T @ v)
     v /= np.linalg.norm(v)
-    expand(o, B, k, v[:, None], centre="z")
+    expand(o, B, k, v[:, None], side="below")
     gain = e0 - _tdvp_error2(o, G)
     assert -1e-12 < gain < s[0] ** 2 * (1 + 1e-10)
 
@@ -124,12 +124,12 @@ def test_spawning_rule_threshold_and_cap():
     B, B1, _ = _names(o)
     move_centre_down(o, [B])
     k = o.kids[B].index(B1)
-    s, _ = spawn(o, B, k, G, dt=1.0, eps_s=0.0, chi_max=10, centre="z")
+    s, _ = spawn(o, B, k, G, dt=1.0, eps_s=0.0, chi_max=10, centre="z", side="below")
     dt = 0.05
     eps = dt * 0.5 * (s[0] + s[1])  # between the first two
-    _, v = spawn(o, B, k, G, dt=dt, eps_s=eps, chi_max=10, centre="z")
+    _, v = spawn(o, B, k, G, dt=dt, eps_s=eps, chi_max=10, centre="z", side="below")
     assert v.shape[1] == 1
-    _, v = spawn(o, B, k, G, dt=dt, eps_s=0.0, chi_max=o.bond[B1], centre="z")
+    _, v = spawn(o, B, k, G, dt=dt, eps_s=0.0, chi_max=o.bond[B1], centre="z", side="below")
     assert v.shape[1] == 0
 
 
@@ -186,7 +186,7 @@ def test_one_site_cost_form_matches_the_definition(idx):
     ref = (V2.conj().T @ G @ V2 @ T.reshape(-1)).reshape(T.shape)
     assert np.abs(heff2(o, z, k, T) - ref).max() < 1e-12 * np.abs(ref).max()
     Rd = residual(o, z, k, G, side)
-    op = ResidualOperator(o, z, k, side)
+    op = ResidualOperator(o, z, k)
     w = rng.normal(size=op.no) + 1j * rng.normal(size=op.no)
     y = rng.normal(size=op.nb) + 1j * rng.normal(size=op.nb)
     scale = max(np.abs(Rd).max(), 1.0)
@@ -200,3 +200,60 @@ def test_one_site_cost_form_matches_the_definition(idx):
     for i in range(r):  # simple singular values here: vectors agree up to a phase
         assert abs(abs(np.vdot(U[:, i], L[:, i])) - 1.0) < 1e-10
         assert abs(abs(np.vdot(Vh[i].conj(), Rv[:, i])) - 1.0) < 1e-10
+
+
+# ------------------------------------------------------------ the adaptive sweep
+def _exact_errors(p, runs, n_steps):
+    from scipy.linalg import expm
+    G = dense_sop(p)
+    psi0 = full_state(p.parent, p.local_dim, runs[0].state())
+    for _ in range(n_steps):
+        for o in runs:
+            o.step(p.dt)
+    ex = expm(-1j * n_steps * p.dt * G) @ psi0
+    return [float(np.linalg.norm(full_state(p.parent, p.local_dim, o.state()) - ex)) for o in runs]
+
+
+def test_adaptive_sweep_without_spawning_is_the_fixed_sweep():
+    from oracle.subspace import AdaptiveOracle
+    p = sbm_problem(n_modes=4, d=3, bond=2, alpha=0.4, dt=0.05)
+    a = Oracle(p)
+    b = AdaptiveOracle(p, eps_s=np.inf, chi_max=100, seed=1)
+    for o in (a, b):
+        o.set_product_state(p.init_vecs)
+        for _ in range(5):
+            o.step(p.dt)
+    assert b.spawned == 0
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+
+
+def test_adaptive_sweep_converges_to_the_exact_propagator():
+    """Spin-boson, 4 modes, bonds starting at 2 (below the complete bonds): with
+    a small spawning tolerance the bonds grow and the run approaches
+    exp(-i G t) psi0 (complete bonds make the sweep exact); a looser tolerance
+    spawns less and lands in between; norm and energy stay conserved, every
+    bond stays within chi_max and every non-root tensor an isometry."""
+    from oracle.subspace import AdaptiveOracle
+    p = sbm_problem(n_modes=4, d=3, bond=2, alpha=0.4, dt=0.05)
+    fixed = Oracle(p)
+    tight = AdaptiveOracle(p, eps_s=1e-8, chi_max=100, seed=1)
+    loose = AdaptiveOracle(p, eps_s=1e-5, chi_max=100, seed=1)
+    capped = AdaptiveOracle(p, eps_s=1e-8, chi_max=4, seed=1)
+    runs = [fixed, tight, loose, capped]
+    for o in runs:
+        o.set_product_state(p.init_vecs)
+    e0 = [o.energy() for o in runs]
+    ef, et, el, ec = _exact_errors(p, runs, 20)
+    assert et < 1e-5 and et < 1e-3 * ef
+    assert et < el < ef
+    assert tight.spawned > loose.spawned > 0
+    assert max(capped.bond) <= 4 and ec < ef
+    for o, e in zip(runs, e0):
+        assert abs(o.norm2() - 1.0) < 1e-12
+        assert abs(o.energy() - e) < 1e-12 * abs(e)
+        for z in range(o.n):
+            if z == o.root:
+                continue
+            M = o.A[z].reshape(-1, o.A[z].shape[-1])
+            assert np.abs(M.conj().T @ M - np.eye(M.shape[1])).max() < 1e-12
