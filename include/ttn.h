@@ -176,9 +176,11 @@ ttn_status ttn_state_size(ttn_t h, size_t *bytes);
 ttn_status ttn_get_state(ttn_t h, double *buf, size_t bytes);
 ttn_status ttn_set_state(ttn_t h, const double *buf, size_t bytes);
 
-/* Kernel launch profile.  ttn_profile_begin switches on event timing of every
- * kernel launch of the library (HIP events recorded on the launch's stream;
- * adds a little overhead per launch) and clears earlier records.
+/* Kernel launch profile.  ttn_profile_begin switches on timing of every
+ * kernel launch of the library and clears earlier records: ordinary launches
+ * carry a start and a stop event stamped from the dispatch itself, the
+ * cooperative QR reads the device's constant-rate clock at its first
+ * work-group start and last end (adds a little overhead per launch).
  * ttn_profile_end synchronises the device, switches the timing off and writes
  * one row per kernel name: launches, summed duration, and the algorithmic
  * flops (8 per complex MAC) and bytes of those launches as modelled by the
