@@ -9,9 +9,10 @@ Workload: the synthetic 2-state / 24-mode vibronic-coupling model (seed 2;
 the GPU, plus the H_eff flop rate.
 
 Prints ONE JSON line.  A separate short pass with the library's launch
-profiler (HIP events around every kernel launch) gives the dominant kernel's
-average launch duration and its roofline numbers; the oracle (CPU) is timed on
-a one-step sample of the same workload.
+profiler (dispatch-stamped HIP events per launch; the cooperative QR from its
+own clock readings) gives the dominant kernel's average launch duration and
+its roofline numbers; the oracle (CPU) is timed on a one-step sample of the
+same workload.
 """
 import argparse
 import json

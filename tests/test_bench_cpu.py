@@ -1,0 +1,56 @@
+"""Host logic of bench.py: roofline classification, the PMC traffic record,
+the one-GPU guard (no GPU needed)."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _row(name, calls, ms, flops, byts):
+    return {"name": name, "calls": calls, "total_ms": ms, "flops": flops, "bytes": byts}
+
+
+def test_roofline_takes_the_kernel_with_the_largest_total_time():
+    stats = [_row("k_mode_tile", 100, 2.0, 1e9, 3e8), _row("k_qr_coop", 10, 3.0, 1.2e8, 2.2e7)]
+    r = bench.roofline(stats)
+    assert r["kernel"] == "k_qr_coop"
+    assert abs(r["avg_launch_us"] - 300.0) < 1e-9
+    # intensity 5.5 flop/B is below the FP64 ridge (78.6 TF / 8 TB/s = 9.8): HBM bound
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["achieved"] - 2.2e6 / 300e-6 / 1e9) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / bench.PEAK_HBM_GBS) < 1e-15
+
+
+def test_roofline_compute_bound_classes():
+    # no modelled bytes: compute bound; plain FP64 vector code reports "alu"
+    r = bench.roofline([_row("k_small_solve", 10, 1.0, 1e7, 0.0)])
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == bench.PEAK_FP64_TFLOPS
+    r = bench.roofline([_row("k_some_mfma_kernel", 10, 1.0, 1e9, 1e6)])
+    assert r["bound"] == "mfma"
+
+
+def test_traffic_record_follows_the_kernel_sources():
+    path = os.path.join(ROOT, "profiles", "k_qr_coop_vibronic24_hbm_traffic.md")
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic: "):
+            rec = json.loads(line[len("traffic: "):])
+    assert rec is not None and rec["kernel"] == "k_qr_coop"
+    got = bench.measured_traffic("k_qr_coop")
+    import hashlib
+    src = os.path.join(ROOT, "paper_2503_15460_amd", "csrc", "kernels.hip")
+    same = hashlib.sha256(open(src, "rb").read()).hexdigest() == rec["kernels_hip_sha256"]
+    assert got == (rec["bytes_per_launch"] if same else None)
+    assert abs(rec["bytes_per_launch"] - rec["fetch_bytes_per_launch"] - rec["write_bytes_per_launch"]) <= 1
+    assert bench.measured_traffic("no_such_kernel") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
