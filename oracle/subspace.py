@@ -1,8 +1,11 @@
-"""Subspace expansion by the two-site energy variance, written out densely.
+"""Subspace expansion by the two-site energy variance (bond-dimension adaptation).
 
 TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle/``).  There is no
-HIP counterpart of this module: it fixes what a bond expansion must compute,
-on trees small enough for dense vectors.
+HIP counterpart of this module.  It holds three things, each pinned against
+the one before: the dense definition of what a bond expansion computes (small
+trees), the one-site-cost form of the same residual with a Krylov iteration
+for its dominant singular pairs, and the projector-splitting sweep with the
+expansions at the bond crossings.
 
 What it follows (paper: pyTTN, arXiv 2503.15460, Sec. II D):
 
@@ -16,8 +19,11 @@ What it follows (paper: pyTTN, arXiv 2503.15460, Sec. II D):
 * Functions are spawned along the eigenvectors of Delta with the largest
   eigenvalues lambda_s, while dt sqrt(lambda_s) >= eps_S (TDVP: c = dt), up to
   a maximum bond dimension.  By the symmetry of the mixed-canonical gauge the
-  same construction with the centre at c spawns single hole functions of c
-  (new functions of everything outside c) when the sweep moves up.
+  same construction spawns single hole functions of c (new functions of
+  everything outside c); each bond is tried once per direction of the sweep.
+* Only the dominant eigenpairs are needed, and the operator can act on
+  single-site objects at about single-site cost, so they come from a Krylov
+  iteration rather than a dense two-site decomposition.
 
 Reading (the paper defers the details to its reference on MCTDH spawning):
 with X the two-site projection of G Psi, matricised as (indices below c) x
@@ -31,9 +37,11 @@ new functions below the bond are the dominant left singular vectors of R
 (lambda_s = sigma_s^2) and new functions outside it the conjugated dominant
 right singular vectors.  The formula holds with the centre at z or at c.
 
-Everything here uses dense vectors of the whole state: X = V2^dag G Psi with
-V2 the orthonormal two-site embedding, SVDs from numpy.  It is exact up to
-rounding and meant for a few hundred to a few thousand basis states.
+The dense definition uses vectors of the whole state: X = V2^dag G Psi with
+V2 the orthonormal two-site embedding, SVDs from numpy; it is exact up to
+rounding and meant for a few hundred to a few thousand basis states.  Where
+the sweep widens which side of a bond is a further reading, stated in
+``AdaptiveOracle``.
 """
 from __future__ import annotations
 
