@@ -187,6 +187,73 @@ def test_time_reversibility():
     assert abs(abs(ov) - 1.0) < 1e-11
 
 
+# ------------------------------------ energy and a(t) against dense forms
+def _dense_run(seed, n_steps):
+    """Oracle on a small tree from a seeded full-rank state, with its dense
+    state before and after ``n_steps`` steps and the dense generator."""
+    p = sbm_problem(n_modes=3, d=4, bond=3, alpha=0.4, dt=0.07)
+    o = Oracle(p)
+    o.set_state(random_isometric_state(p.parent, p.local_dim, o.bond, seed=seed))
+    psi0 = o.dense_state()
+    for _ in range(n_steps):
+        o.step(p.dt)
+    return p, o, psi0, o.dense_state(), dense_sop(p)
+
+
+def test_energy_is_the_dense_expectation_value():
+    """<Psi|G|Psi> from the tree contraction equals psi^H G psi of the dense state
+    (every SOP term with its coefficient; Sec. II B 1)."""
+    p, o, _, psi, G = _dense_run(21, 4)
+    ref = np.vdot(psi, G @ psi)
+    e = o.energy()
+    assert abs(e - ref) < 1e-12 * max(1.0, abs(ref))
+    # a non-Hermitian generator (complex coefficients): the raw value, complex
+    q = sbm_problem(n_modes=3, d=4, bond=3, alpha=0.4)
+    q.coeff = [c * (1.0 + 0.3j * ((i % 3) - 1)) for i, c in enumerate(q.coeff)]
+    oq = Oracle(q, hermitian=False)
+    oq.set_state(random_isometric_state(q.parent, q.local_dim, oq.bond, seed=22))
+    psi_q = oq.dense_state()
+    ref_q = np.vdot(psi_q, dense_sop(q) @ psi_q)
+    assert abs(ref_q.imag) > 1e-3
+    assert abs(oq.energy() - ref_q) < 1e-12 * max(1.0, abs(ref_q))
+
+
+def test_overlap_t0_is_the_dense_autocorrelation():
+    """a(t) = <Psi(0)|Psi(t)> (Sec. IV A) as a complex number: bra conjugated,
+    the phase of the propagated state kept."""
+    p, o, psi0, psi, G = _dense_run(23, 6)
+    ref = np.vdot(psi0, psi)
+    a = o.overlap_t0()
+    assert abs(ref) < 0.999 and abs(ref.imag) > 1e-3  # a phase that a conjugation error would flip
+    assert abs(a - ref) < 1e-12
+    # and against exact propagation: at full bonds the sweep is exact
+    q = sbm_problem(n_modes=2, d=4, bond=10_000, alpha=0.5, dt=0.05)
+    oq = Oracle(q)
+    oq.set_state(random_isometric_state(q.parent, q.local_dim, oq.bond, seed=24))
+    phi0 = oq.dense_state()
+    for _ in range(8):
+        oq.step(q.dt)
+    exact = np.vdot(phi0, sla.expm(-1j * dense_sop(q) * q.dt * 8) @ phi0)
+    assert abs(oq.overlap_t0() - exact) < 1e-11
+
+
+def test_krylov_substepping_matches_dense_expm():
+    """A Krylov space too small for the step forces the halving branch; the
+    sub-stepped result is still exp(-i tau G) v (Hermitian and not)."""
+    from oracle import expm_krylov
+    rng = np.random.default_rng(5)
+    n = 200
+    A = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    A /= np.linalg.norm(A, 2)
+    v = rng.normal(size=n) + 1j * rng.normal(size=n)
+    for herm, G, tau in ((True, A + A.conj().T, 2.0), (False, A, 2.0)):
+        cnt = [0]
+        y = expm_krylov(lambda x: G @ x, v, tau, hermitian=herm, tol=1e-13, mmax=8, dense_max=0, counter=cnt)
+        # one solve of dimension <= 8 cannot reach 1e-13 at this |tau G|: it sub-stepped
+        assert cnt[0] > 8 * 4
+        assert np.abs(y - sla.expm(-1j * tau * G) @ v).max() < 1e-11 * np.linalg.norm(v)
+
+
 # ------------------------------------------- P7: brute-force projections
 def _embedding(o, z):
     """Dense V with psi = V vec(A^z) for the current tensors (A^z varied)."""
