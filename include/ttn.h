@@ -17,8 +17,10 @@
  * Conventions common to every call
  *   - Every function returns a ttn_status: TTN_OK (0) or a negative error.
  *     After an error, ttn_last_error() returns a message; the state of the
- *     handle is unchanged, except after TTN_E_DEVICE, which leaves the handle
- *     unusable (destroy it).
+ *     handle is unchanged, with two exceptions: TTN_E_DEVICE leaves the handle
+ *     unusable (destroy it), and ttn_set_sop failing with TTN_E_OOM leaves the
+ *     handle without an operator (set one again before stepping or observing).
+ *     A sweep stopped by a failed kernel launch reports TTN_E_DEVICE.
  *   - All pointer arguments are HOST pointers owned by the caller.  The library
  *     copies what it needs during the call and never keeps a caller pointer.
  *   - Complex numbers are two consecutive doubles (re, im).
@@ -59,7 +61,9 @@ typedef int32_t ttn_status;
  * results are widened when written); node tensors, environments, QR gauge
  * shifts, Krylov orthogonalisation and the small projected exponential stay
  * FP64, and local problems of at most 1024 elements keep the fused FP64 solver.
- * Observables are then accurate to the FP32 contractions (about 1e-6). */
+ * From a full-rank state observables stay within about 1e-6 of FP64 over tens
+ * of steps; from a product state the rank-deficient first gauge shifts amplify
+ * rounding of any precision (FP64 included) to about 1e-3 in the first steps. */
 #define TTN_FP64 0
 #define TTN_FP32 1
 /* TTN_BF16X3: as TTN_FP32, and the dense operator stages whose factors have
@@ -79,14 +83,23 @@ typedef struct ttn_ctx *ttn_t;
 typedef struct ttn_batch_ctx *ttn_batch_t;
 
 typedef struct {
-    int32_t precision;   /* TTN_FP64, TTN_FP32 or TTN_BF16X3 */
-    double krylov_tol;   /* local exponential error target, relative (0 -> 1e-13, FP32/BF16X3: 1e-10) */
-    int32_t krylov_mmax; /* max Krylov dimension per solve (0 -> 40) */
-    int32_t hermitian;   /* 1: Lanczos (G must be Hermitian), 0: Arnoldi */
-    void *hip_stream;    /* hipStream_t for all work of the handle, NULL = null stream */
-    int32_t device;      /* HIP device ordinal */
-    int32_t use_graph;   /* reserved, 0 */
-    uint64_t seed;       /* reserved */
+    int32_t precision;      /* TTN_FP64, TTN_FP32 or TTN_BF16X3 */
+    double krylov_tol;      /* local exponential error target, relative (0 -> 1e-13, FP32/BF16X3: 1e-10) */
+    int32_t krylov_mmax;    /* max Krylov dimension per solve (0 -> 40) */
+    int32_t hermitian;      /* 1: Lanczos (G must be Hermitian), 0: Arnoldi */
+    void *hip_stream;       /* hipStream_t for all work of the handle, NULL = null stream */
+    void *workspace;        /* optional DEVICE buffer (caller-owned, on `device`, >= 256-byte aligned)
+                               that holds the sweep's scratch: contraction temporaries, Krylov
+                               bases, QR work arrays, the step snapshot.  NULL: the library
+                               allocates the scratch itself.  Must stay valid until
+                               ttn_destroy; ttn_set_sop fails with TTN_E_OOM when
+                               workspace_bytes is below what the operator needs
+                               (ttn_workspace_size reports it, also after that failure). */
+    size_t workspace_bytes; /* size of `workspace` in bytes */
+    int32_t use_graph;      /* reserved, must be 0 */
+    int32_t autotune;       /* reserved, must be 0 */
+    int32_t device;         /* HIP device ordinal */
+    uint64_t seed;          /* reserved (the sweep draws no random numbers) */
 } ttn_options;
 
 /* Fill *opt with the defaults (FP64, tol 0 = the precision's default, mmax 40,
@@ -96,14 +109,17 @@ void ttn_default_options(ttn_options *opt);
 /* Create a tree tensor network.
  *   n_nodes   number of nodes (>= 2)
  *   parent    [n_nodes] parent id, exactly one -1 (the root); children of a node
- *             are ordered by increasing node id
+ *             are ordered by increasing node id; a node has at most 7 children
+ *             (node tensors have at most 8 indices)
  *   local_dim [n_nodes] primitive dimension d > 0 for leaves, 0 for interior nodes
  *   bond_dim  [n_nodes] requested number of SPFs on the bond to the parent
  *             (ignored for the root).  Requests the tree cannot support are
  *             clamped: n = min(request, prod dims below, prod dims above), then
  *             lowered until every matricisation has rows >= columns.  The
- *             effective values are returned by ttn_get_info.
- * Errors: TTN_E_TREE (not a tree), TTN_E_DIMS (leaf/interior dims invalid),
+ *             effective values are returned by ttn_get_info; effective bonds
+ *             above 64 are refused (TTN_E_DIMS).
+ * Errors: TTN_E_TREE (not a tree, or a node with more than 7 children),
+ *         TTN_E_DIMS (leaf/interior dims invalid), TTN_E_INVALID (options),
  *         TTN_E_DEVICE.  On success *out receives the handle. */
 ttn_status ttn_create(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
                       const int32_t *bond_dim, const ttn_options *opt, ttn_t *out);
@@ -118,18 +134,27 @@ ttn_status ttn_create(int32_t n_nodes, const int32_t *parent, const int32_t *loc
  * The generator is compiled into a hierarchical SOP (sparse tree operator)
  * whose bond operators are chosen by a minimum vertex cover of the bipartite
  * term graph of every bond (Sec. II B 2).  With hermitian=1, G is checked for
- * Hermiticity (operators and coefficients) and TTN_E_INVALID is returned if it
- * is not.  Device environments are rebuilt if a state is already set.
- * Errors: TTN_E_INVALID, TTN_E_DIMS, TTN_E_OOM, TTN_E_DEVICE. */
+ * Hermiticity: ||G - G^dag||_F <= 1e-7 ||G||_F, evaluated from the leaf
+ * operators and coefficients (traces of products of leaf operators, never the
+ * dense matrix; operators on one leaf that agree to 1e-12 relative count as
+ * one), and TTN_E_INVALID is returned if it fails.  Device environments are
+ * rebuilt if a state is already set.  Argument errors (TTN_E_INVALID,
+ * TTN_E_DIMS) leave the handle unchanged; after TTN_E_OOM or TTN_E_DEVICE it
+ * has no operator.
+ * Errors: TTN_E_INVALID, TTN_E_DIMS, TTN_E_OOM (device memory, or the
+ * caller's workspace too small), TTN_E_DEVICE. */
 ttn_status ttn_set_sop(ttn_t h, int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
                        const double *op_data, int32_t n_terms, const double *coeff,
                        const int64_t *term_ptr, const int32_t *term_ops);
 
-/* Product initial state: leaf_vecs holds one complex vector of length d per
- * leaf, concatenated in increasing leaf id.  Unoccupied single-particle
- * functions are completed with unit vectors (leaf: modified Gram-Schmidt of
- * e_0, e_1, ... against the given vector, skipping residuals below 1e-6;
- * interior node: the first n columns of the identity; root: e_(0..0)).
+/* Product initial state (the Hartree product the paper starts its
+ * propagations from, Secs. III and IV A, where the unoccupied single-particle
+ * functions are included in the initial tensors).  leaf_vecs holds one complex
+ * vector of length d per leaf, concatenated in increasing leaf id.  The
+ * unoccupied functions are completed with unit vectors (leaf: modified
+ * Gram-Schmidt of e_0, e_1, ... against the given vector, skipping residuals
+ * below 1e-6; interior node: the first n columns of the identity; root:
+ * e_(0..0)).
  * This state becomes Psi(0) for TTN_OBS_OVERLAP_T0.
  * Errors: TTN_E_STATE (no SOP yet), TTN_E_INVALID (zero vector), TTN_E_DEVICE. */
 ttn_status ttn_set_product_state(ttn_t h, const double *leaf_vecs);
@@ -165,6 +190,11 @@ ttn_status ttn_apply_root_heff(ttn_t h, const double *x, double *y);
  * MAC), bytes of device memory in use, tree-operator entries, redo count}.
  * Either pointer may be NULL. */
 ttn_status ttn_get_info(ttn_t h, int32_t *effective_bond_dim, int64_t *counters);
+
+/* Bytes of device scratch the handle's current operator needs (the size a
+ * caller-provided ttn_options.workspace must have); 0 before ttn_set_sop.  Also
+ * valid after ttn_set_sop failed with TTN_E_OOM. */
+ttn_status ttn_workspace_size(ttn_t h, size_t *bytes);
 
 /* Size in bytes (complex128 elements * 16) of the state for get/set_state. */
 ttn_status ttn_state_size(ttn_t h, size_t *bytes);
@@ -227,6 +257,12 @@ const char *ttn_last_error(ttn_t h);
 
 /* Release all resources of the handle. */
 void ttn_destroy(ttn_t h);
+
+/* Release the library's process-wide device resources (the launch profiler's
+ * clock slots and event pool).  Call after destroying every handle and before
+ * the HIP runtime is torn down (e.g. from an exit hook); the library stays
+ * usable and re-creates them on demand. */
+void ttn_release_process_resources(void);
 
 #ifdef __cplusplus
 }

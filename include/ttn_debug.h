@@ -25,6 +25,26 @@ ttn_status ttn_debug_dense_tree_operator(int32_t n_nodes, const int32_t *parent,
                                          const int64_t *term_ptr, const int32_t *term_ops, int64_t max_dim,
                                          double *out, int64_t *n_entries);
 
+/* ||G - G^dag||_F / ||G||_F of an SOP generator (arguments as for ttn_create
+ * and ttn_set_sop), the quantity ttn_set_sop checks when hermitian = 1,
+ * computed from traces of products of leaf operators; host only.
+ * Errors: TTN_E_TREE, TTN_E_DIMS, TTN_E_INVALID. */
+ttn_status ttn_debug_hermiticity_defect(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                                        int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                                        const double *op_data, int32_t n_terms, const double *coeff,
+                                        const int64_t *term_ptr, const int32_t *term_ops, double *defect);
+
+/* Size of the compiled sparse tree operator per node (host only): n_channels
+ * [n_nodes] receives the number of channels on the bond above each node (the
+ * root: 1), n_entries [n_nodes] the number of operator entries of each node.
+ * Either output may be NULL.  Arguments as for ttn_create / ttn_set_sop.
+ * Errors: TTN_E_TREE, TTN_E_DIMS, TTN_E_INVALID. */
+ttn_status ttn_debug_tree_operator_stats(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                                         int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                                         const double *op_data, int32_t n_terms, const double *coeff,
+                                         const int64_t *term_ptr, const int32_t *term_ops, int32_t *n_channels,
+                                         int32_t *n_entries);
+
 /* Effective (clamped) bond dimensions for a tree, host only.
  * Errors: TTN_E_TREE, TTN_E_DIMS. */
 ttn_status ttn_debug_clamp_bonds(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,

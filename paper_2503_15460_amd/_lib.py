@@ -7,9 +7,11 @@ there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
-from typing import Dict, List, Optional, Sequence
+import weakref
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -27,13 +29,16 @@ EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product
             "ttn_observe", "ttn_apply_root_heff", "ttn_get_info", "ttn_state_size", "ttn_get_state",
             "ttn_set_state", "ttn_last_error", "ttn_destroy", "ttn_debug_dense_tree_operator",
             "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end",
-            "ttn_batch_create", "ttn_batch_step", "ttn_batch_last_error", "ttn_batch_destroy"]
+            "ttn_batch_create", "ttn_batch_step", "ttn_batch_last_error", "ttn_batch_destroy",
+            "ttn_workspace_size", "ttn_release_process_resources", "ttn_debug_hermiticity_defect",
+            "ttn_debug_tree_operator_stats"]
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("krylov_tol", C.c_double), ("krylov_mmax", C.c_int32),
-                ("hermitian", C.c_int32), ("hip_stream", C.c_void_p), ("device", C.c_int32),
-                ("use_graph", C.c_int32), ("seed", C.c_uint64)]
+                ("hermitian", C.c_int32), ("hip_stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t), ("use_graph", C.c_int32), ("autotune", C.c_int32),
+                ("device", C.c_int32), ("seed", C.c_uint64)]
 
 
 class KernelStat(C.Structure):
@@ -47,16 +52,52 @@ class TTNError(RuntimeError):
         self.code = code
 
 
+def _runtime_file(handle, symbol: bytes) -> str:
+    """Path of the shared object that provides ``symbol`` as seen from ``handle``."""
+    class DlInfo(C.Structure):
+        _fields_ = [("dli_fname", C.c_char_p), ("dli_fbase", C.c_void_p), ("dli_sname", C.c_char_p),
+                    ("dli_saddr", C.c_void_p)]
+    libdl = C.CDLL(None)
+    libdl.dlsym.restype = C.c_void_p
+    libdl.dlsym.argtypes = [C.c_void_p, C.c_char_p]
+    libdl.dladdr.argtypes = [C.c_void_p, C.POINTER(DlInfo)]
+    addr = libdl.dlsym(handle, symbol)
+    info = DlInfo()
+    if not addr or not libdl.dladdr(addr, C.byref(info)) or not info.dli_fname:
+        return ""
+    return os.path.realpath(info.dli_fname.decode())
+
+
+def _check_one_hip_runtime(lib) -> None:
+    """The library must use the HIP runtime torch has loaded: one runtime per
+    process (two would each own the device and tear it down twice at exit)."""
+    import torch
+    mine = _runtime_file(lib._handle, b"hipMalloc")
+    torch_lib = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+    theirs = ""
+    if os.path.exists(torch_lib):
+        theirs = _runtime_file(C.CDLL(torch_lib)._handle, b"hipMalloc")
+    mapped = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 6 and "libamdhip64" in parts[-1]:
+                mapped.add(os.path.realpath(parts[-1]))
+    if not mine or (theirs and mine != theirs) or len(mapped) > 1:
+        raise ImportError(f"libttn.so would use the HIP runtime {mine or '?'} while torch uses "
+                          f"{theirs or '?'} (mapped: {sorted(mapped)}): one runtime per process is required")
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
     # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
     # SONAME as the system one the library links), and stream handles cross the
     # boundary.  Loading torch first makes the dynamic loader bind the library
-    # to torch's runtime; loaded the other way round, two runtimes coexist and
-    # the library's one does not see the device.
+    # to torch's runtime; the check below makes that an enforced invariant.
     import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
+    _check_one_hip_runtime(lib)
     P = C.c_void_p
     i32p, i64p, dp = C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)
     sig = {
@@ -83,6 +124,12 @@ def _load():
         "ttn_batch_step": (C.c_int32, [P, dp, C.c_int32]),
         "ttn_batch_last_error": (C.c_char_p, [P]),
         "ttn_batch_destroy": (None, [P]),
+        "ttn_workspace_size": (C.c_int32, [P, C.POINTER(C.c_size_t)]),
+        "ttn_debug_tree_operator_stats": (C.c_int32, [C.c_int32, i32p, i32p, C.c_int32, i32p, i64p, dp, C.c_int32,
+                                                      dp, i64p, i32p, i32p, i32p]),
+        "ttn_debug_hermiticity_defect": (C.c_int32, [C.c_int32, i32p, i32p, C.c_int32, i32p, i64p, dp, C.c_int32,
+                                                     dp, i64p, i32p, dp]),
+        "ttn_release_process_resources": (None, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -92,6 +139,20 @@ def _load():
 
 
 lib = _load()
+
+# Handles still open at interpreter exit are destroyed by an exit hook, before
+# module teardown and before the HIP runtime and any profiler attached to it
+# shut down, and the library's process-wide resources are released after them.
+_LIVE: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _release_at_exit():
+    for obj in [o for o in list(_LIVE) if isinstance(o, TTNBatch)]:
+        obj.close()
+    for obj in list(_LIVE):
+        obj.close()
+    lib.ttn_release_process_resources()
 
 
 def _ptr(a: np.ndarray, ctype):
@@ -127,6 +188,34 @@ def dense_tree_operator(problem, max_dim: int = 4096):
         _ptr(off, C.c_int64), _ptr(data, C.c_double), len(problem.term_ops), _ptr(coeff, C.c_double),
         _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32), max_dim, _ptr(out, C.c_double), _ptr(nent, C.c_int64)))
     return out.view(np.complex128).reshape(dim, dim), int(nent[0])
+
+
+def tree_operator_stats(problem):
+    """(channels on the bond above each node, operator entries of each node) of
+    the compiled tree operator (host only)."""
+    parent = np.ascontiguousarray(problem.parent, dtype=np.int32)
+    ld = np.ascontiguousarray(problem.local_dim, dtype=np.int32)
+    op_leaf, off, data, coeff, tptr, tops = problem.flat_sop()
+    ch = np.zeros(len(parent), dtype=np.int32)
+    ent = np.zeros(len(parent), dtype=np.int32)
+    _check(lib.ttn_debug_tree_operator_stats(
+        len(parent), _ptr(parent, C.c_int32), _ptr(ld, C.c_int32), len(op_leaf), _ptr(op_leaf, C.c_int32),
+        _ptr(off, C.c_int64), _ptr(data, C.c_double), len(problem.term_ops), _ptr(coeff, C.c_double),
+        _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32), _ptr(ch, C.c_int32), _ptr(ent, C.c_int32)))
+    return ch, ent
+
+
+def hermiticity_defect(problem) -> float:
+    """||G - G^dag||_F / ||G||_F as the library checks it (host only)."""
+    parent = np.ascontiguousarray(problem.parent, dtype=np.int32)
+    ld = np.ascontiguousarray(problem.local_dim, dtype=np.int32)
+    op_leaf, off, data, coeff, tptr, tops = problem.flat_sop()
+    out = np.zeros(1, dtype=np.float64)
+    _check(lib.ttn_debug_hermiticity_defect(
+        len(parent), _ptr(parent, C.c_int32), _ptr(ld, C.c_int32), len(op_leaf), _ptr(op_leaf, C.c_int32),
+        _ptr(off, C.c_int64), _ptr(data, C.c_double), len(problem.term_ops), _ptr(coeff, C.c_double),
+        _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32), _ptr(out, C.c_double)))
+    return float(out[0])
 
 
 def gpu_qr(M: np.ndarray, variant: int):
@@ -183,7 +272,8 @@ class TTN:
     """One tree tensor network on the GPU, driven through the C boundary."""
 
     def __init__(self, parent, local_dim, bond_dim, precision: int = TTN_FP64, krylov_tol: float = 0.0,
-                 krylov_mmax: int = 40, hermitian: bool = True, stream: Optional[int] = None, device: int = 0):
+                 krylov_mmax: int = 40, hermitian: bool = True, stream: Optional[int] = None, device: int = 0,
+                 workspace: Optional[Tuple[int, int]] = None):
         self.parent = np.ascontiguousarray(parent, dtype=np.int32)
         self.local_dim = np.ascontiguousarray(local_dim, dtype=np.int32)
         bond = np.ascontiguousarray(bond_dim, dtype=np.int32)
@@ -195,11 +285,15 @@ class TTN:
         opt.hermitian = 1 if hermitian else 0
         opt.hip_stream = stream if stream is not None else default_stream()
         opt.device = device
+        if workspace is not None:  # (device pointer, bytes), caller-owned
+            opt.workspace = int(workspace[0])
+            opt.workspace_bytes = int(workspace[1])
         h = C.c_void_p()
         _check(lib.ttn_create(len(self.parent), _ptr(self.parent, C.c_int32), _ptr(self.local_dim, C.c_int32),
                               _ptr(bond, C.c_int32), C.byref(opt), C.byref(h)))
         self.h = h
         self.n = len(self.parent)
+        _LIVE.add(self)
 
     @classmethod
     def from_problem(cls, p, bond_dim=None, **kw):
@@ -265,6 +359,12 @@ class TTN:
                                         _ptr(y.view(np.float64), C.c_double)))
         return y
 
+    def workspace_size(self) -> int:
+        """Scratch bytes the current operator needs (a caller workspace's size)."""
+        b = C.c_size_t()
+        self._c(lib.ttn_workspace_size(self.h, C.byref(b)))
+        return int(b.value)
+
     def bonds(self) -> np.ndarray:
         b = np.zeros(self.n, dtype=np.int32)
         self._c(lib.ttn_get_info(self.h, _ptr(b, C.c_int32), None))
@@ -319,6 +419,7 @@ class TTNBatch:
         if code != TTN_OK:
             raise TTNError(code, lib.ttn_batch_last_error(None).decode())
         self.h = h
+        _LIVE.add(self)
 
     def step(self, dt, n_steps: int = 1):
         dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (len(self.insts),)))

@@ -1,5 +1,6 @@
 // C boundary of the library: argument checks, handle management and the
 // conversion of exceptions into ttn_status codes.
+#include <cstdint>
 #include <cstring>
 #include <functional>
 #include <vector>
@@ -30,6 +31,20 @@ struct ttn_batch_ctx {
 
 namespace {
 thread_local std::string g_err;
+
+// A sweep that stops on anything but a library error (a failed launch, a host
+// allocation) has been partly applied: report it as a device error, which
+// makes the handle unusable.
+template <class F>
+void sweep_guard(F &&f) {
+    try {
+        f();
+    } catch (const ttn::Error &) {
+        throw;
+    } catch (const std::exception &e) {
+        throw ttn::Error(TTN_E_DEVICE, std::string("sweep aborted: ") + e.what());
+    }
+}
 
 template <class F>
 ttn_status guard(ttn_t h, F &&f) {
@@ -80,6 +95,9 @@ ttn_status ttn_create(int32_t n_nodes, const int32_t *parent, const int32_t *loc
         if (opt) o = *opt;
         if (o.precision != TTN_FP64 && o.precision != TTN_FP32 && o.precision != TTN_BF16X3)
             throw ttn::Error(TTN_E_INVALID, "precision must be TTN_FP64, TTN_FP32 or TTN_BF16X3");
+        if (o.use_graph != 0 || o.autotune != 0) throw ttn::Error(TTN_E_INVALID, "use_graph and autotune must be 0");
+        if (o.workspace && ((uintptr_t)o.workspace % 256 != 0))
+            throw ttn::Error(TTN_E_INVALID, "workspace must be 256-byte aligned");
         ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, bond_dim);
         auto h = std::make_unique<ttn_ctx>();
         h->eng = std::make_unique<ttn::Engine>(t, o);
@@ -107,7 +125,7 @@ ttn_status ttn_step(ttn_t h, double dt, int32_t n_steps) {
     if (!h) return TTN_E_INVALID;
     return guard(h, [&] {
         if (n_steps < 0) throw ttn::Error(TTN_E_INVALID, "negative step count");
-        h->eng->step(dt, n_steps);
+        sweep_guard([&] { h->eng->step(dt, n_steps); });
     });
 }
 
@@ -163,14 +181,14 @@ ttn_status ttn_batch_step(ttn_batch_t b, const double *dt, int32_t n_steps) {
             if (b->insts[i]->dead) throw ttn::Error(TTN_E_DEVICE, "instance unusable after a device error");
         for (cur = 0; cur < n; ++cur) b->insts[cur]->eng->check_ready(dt[cur]);
         for (int s = 0; s < n_steps; ++s) {
-            for (cur = 0; cur < n; ++cur) b->insts[cur]->eng->enqueue_step(dt[cur]);
+            for (cur = 0; cur < n; ++cur) sweep_guard([&] { b->insts[cur]->eng->enqueue_step(dt[cur]); });
             // finish every instance (each one's bookkeeping stays consistent), then report the first error
             int bad = -1;
             ttn_status bad_code = TTN_OK;
             std::string bad_msg;
             for (int i = 0; i < n; ++i) {
                 try {
-                    b->insts[i]->eng->finish_step(dt[i]);
+                    sweep_guard([&] { b->insts[i]->eng->finish_step(dt[i]); });
                 } catch (const ttn::Error &e) {
                     if (bad < 0) {
                         bad = i;
@@ -235,6 +253,19 @@ ttn_status ttn_apply_root_heff(ttn_t h, const double *x, double *y) {
 ttn_status ttn_get_info(ttn_t h, int32_t *effective_bond_dim, int64_t *counters) {
     if (!h) return TTN_E_INVALID;
     return guard(h, [&] { h->eng->info(effective_bond_dim, counters); });
+}
+
+ttn_status ttn_workspace_size(ttn_t h, size_t *bytes) {
+    if (!h || !bytes) return TTN_E_INVALID;
+    *bytes = h->eng->workspace_need();
+    return TTN_OK;
+}
+
+void ttn_release_process_resources(void) {
+    try {
+        ttn::release_process_resources();
+    } catch (...) {
+    }
 }
 
 ttn_status ttn_state_size(ttn_t h, size_t *bytes) {
@@ -381,6 +412,36 @@ ttn_status ttn_debug_dense_tree_operator(int32_t n_nodes, const int32_t *parent,
         for (int64_t q = 0; q < D * D; ++q) {
             out[2 * q] = G[q].real();
             out[2 * q + 1] = G[q].imag();
+        }
+    });
+}
+
+ttn_status ttn_debug_hermiticity_defect(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                                        int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                                        const double *op_data, int32_t n_terms, const double *coeff,
+                                        const int64_t *term_ptr, const int32_t *term_ops, double *defect) {
+    return guard(nullptr, [&] {
+        if (!defect) throw ttn::Error(TTN_E_INVALID, "null output");
+        std::vector<int32_t> ones(n_nodes > 0 ? n_nodes : 1, 1);
+        ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, ones.data());
+        ttn::SopInput s = ttn::read_sop(t, n_ops, op_leaf, op_offset, op_data, n_terms, coeff, term_ptr, term_ops);
+        *defect = ttn::sop_hermiticity_defect(s, 1e-12);
+    });
+}
+
+ttn_status ttn_debug_tree_operator_stats(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
+                                         int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
+                                         const double *op_data, int32_t n_terms, const double *coeff,
+                                         const int64_t *term_ptr, const int32_t *term_ops, int32_t *n_channels,
+                                         int32_t *n_entries) {
+    return guard(nullptr, [&] {
+        std::vector<int32_t> ones(n_nodes > 0 ? n_nodes : 1, 1);
+        ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, ones.data());
+        ttn::SopInput s = ttn::read_sop(t, n_ops, op_leaf, op_offset, op_data, n_terms, coeff, term_ptr, term_ops);
+        ttn::TreeOp op = ttn::compile_tree_operator(t, s);
+        for (int z = 0; z < t.n; ++z) {
+            if (n_channels) n_channels[z] = op.n_ch[z];
+            if (n_entries) n_entries[z] = (int32_t)op.entries[z].size();
         }
     });
 }

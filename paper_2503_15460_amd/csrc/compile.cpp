@@ -49,6 +49,10 @@ Tree build_tree(int n, const int32_t *parent, const int32_t *local_dim, const in
         if (z != t.root && bond_req[z] < 1) throw Error(TTN_E_DIMS, "bond_dim must be >= 1");
     }
     if (t.kids[t.root].empty()) throw Error(TTN_E_TREE, "root must have children");
+    for (int z = 0; z < n; ++z)
+        if ((int)t.kids[z].size() > MAX_CHILDREN)
+            throw Error(TTN_E_TREE, "node " + std::to_string(z) + " has more than " + std::to_string(MAX_CHILDREN) +
+                                        " children");
     // post-order
     std::function<void(int)> rec = [&](int z) {
         for (int c : t.kids[z]) rec(c);
@@ -160,60 +164,113 @@ SopInput read_sop(const Tree &t, int32_t n_ops, const int32_t *op_leaf, const in
     return s;
 }
 
-bool sop_is_hermitian(const SopInput &s, double rtol) {
-    // canonical operator ids by exact content, and the id of each adjoint
-    std::map<std::pair<int, std::vector<double>>, int> canon;
-    auto key_of = [](int leaf, const std::vector<cplx> &m) {
-        std::vector<double> v;
-        v.reserve(2 * m.size());
-        for (auto &x : m) {
-            v.push_back(x.real() == 0.0 ? 0.0 : x.real());  // fold -0.0
-            v.push_back(x.imag() == 0.0 ? 0.0 : x.imag());
-        }
-        return std::make_pair(leaf, v);
+// ||G - G^dag||_F against ||G||_F from the leaf operators and coefficients.
+// Operators on one leaf that agree to `cluster` (relative Frobenius) are given
+// one id, and so are adjoints; the two operator strings of G and G^dag are
+// collected with their summed coefficients.  For two strings a, b the trace
+// Tr(S_a^dag S_b) / prod d_l is the product over the leaves either string
+// touches of Tr(X^dag Y) / d_l (X or Y the identity where a string has no
+// operator), so ||.||_F^2 / prod d_l is a double sum over the strings that
+// never forms a dense matrix.
+double sop_hermiticity_defect(const SopInput &s, double cluster) {
+    // per leaf: representative matrices of the distinct operators
+    int nleaf = 1;
+    for (int o = 0; o < s.n_ops; ++o) nleaf = std::max(nleaf, s.op_leaf[o] + 1);
+    std::vector<std::vector<std::vector<cplx>>> reps(nleaf);
+    auto fro = [](const std::vector<cplx> &m) {
+        double a = 0.0;
+        for (auto &x : m) a += std::norm(x);
+        return std::sqrt(a);
     };
     auto id_of = [&](int leaf, const std::vector<cplx> &m) {
-        auto k = key_of(leaf, m);
-        auto it = canon.find(k);
-        if (it != canon.end()) return it->second;
-        int id = (int)canon.size();
-        canon[k] = id;
-        return id;
+        auto &v = reps[leaf];
+        const double nm = fro(m);
+        for (size_t k = 0; k < v.size(); ++k) {
+            double d2 = 0.0;
+            for (size_t q = 0; q < m.size(); ++q) d2 += std::norm(m[q] - v[k][q]);
+            if (std::sqrt(d2) <= cluster * std::max(nm, fro(v[k]))) return (int)k;
+        }
+        v.push_back(m);
+        return (int)v.size() - 1;
     };
     std::vector<int> cid(s.n_ops), aid(s.n_ops);
     for (int o = 0; o < s.n_ops; ++o) {
         const auto &m = s.op_mat[o];
-        int d = (int)std::lround(std::sqrt((double)m.size()));
+        const int d = (int)std::lround(std::sqrt((double)m.size()));
         std::vector<cplx> adj(m.size());
         for (int i = 0; i < d; ++i)
-            for (int j = 0; j < d; ++j) adj[i * d + j] = std::conj(m[j * d + i]);
+            for (int j = 0; j < d; ++j) adj[(size_t)i * d + j] = std::conj(m[(size_t)j * d + i]);
         cid[o] = id_of(s.op_leaf[o], m);
         aid[o] = id_of(s.op_leaf[o], adj);
     }
-    std::map<std::vector<std::pair<int, int>>, cplx> g, gd;
-    double scale = 0.0;
-    for (int r = 0; r < s.n_terms; ++r) {
-        std::vector<std::pair<int, int>> k1, k2;
-        for (int o : s.term_ops[r]) {
-            k1.push_back({s.op_leaf[o], cid[o]});
-            k2.push_back({s.op_leaf[o], aid[o]});
+    // Gram tables per leaf: g[x][y] = Tr(X^dag Y)/d, plus tr[y] = Tr(Y)/d
+    std::vector<std::vector<std::vector<cplx>>> gram(nleaf);
+    std::vector<std::vector<cplx>> trn(nleaf);
+    for (int leaf = 0; leaf < nleaf; ++leaf) {
+        const auto &v = reps[leaf];
+        if (v.empty()) continue;
+        const int d = (int)std::lround(std::sqrt((double)v[0].size()));
+        auto &g = gram[leaf];
+        auto &tr = trn[leaf];
+        g.assign(v.size(), std::vector<cplx>(v.size(), cplx(0)));
+        tr.assign(v.size(), cplx(0));
+        for (size_t x = 0; x < v.size(); ++x) {
+            for (int i = 0; i < d; ++i) tr[x] += v[x][(size_t)i * d + i];
+            tr[x] /= (double)d;
+            for (size_t y = 0; y < v.size(); ++y) {
+                cplx a(0);
+                for (size_t q = 0; q < v[x].size(); ++q) a += std::conj(v[x][q]) * v[y][q];
+                g[x][y] = a / (double)d;
+            }
         }
-        std::sort(k1.begin(), k1.end());
-        std::sort(k2.begin(), k2.end());
-        g[k1] += s.coeff[r];
-        gd[k2] += std::conj(s.coeff[r]);
-        scale = std::max(scale, std::abs(s.coeff[r]));
     }
-    double tol = rtol * std::max(scale, 1e-300);
-    for (auto &kv : g) {
-        auto it = gd.find(kv.first);
-        cplx other = it == gd.end() ? cplx(0) : it->second;
-        if (std::abs(kv.second - other) > tol) return false;
+    using Str = std::vector<std::pair<int, int>>;  // (leaf, operator id), sorted by leaf
+    std::map<Str, cplx> G, D;
+    for (int r = 0; r < s.n_terms; ++r) {
+        Str a, b;
+        for (int o : s.term_ops[r]) {
+            a.push_back({s.op_leaf[o], cid[o]});
+            b.push_back({s.op_leaf[o], aid[o]});
+        }
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        G[a] += s.coeff[r];
+        D[a] += s.coeff[r];
+        D[b] -= std::conj(s.coeff[r]);
     }
-    for (auto &kv : gd)
-        if (g.find(kv.first) == g.end() && std::abs(kv.second) > tol) return false;
-    return true;
+    auto norm2 = [&](const std::map<Str, cplx> &T) {
+        std::vector<std::pair<const Str *, cplx>> v;
+        for (auto &kv : T)
+            if (kv.second != cplx(0)) v.push_back({&kv.first, kv.second});
+        double acc = 0.0;
+        for (size_t i = 0; i < v.size(); ++i)
+            for (size_t j = 0; j < v.size(); ++j) {
+                const Str &a = *v[i].first, &b = *v[j].first;
+                cplx f(1.0);
+                size_t p = 0, q = 0;
+                while (p < a.size() || q < b.size()) {
+                    if (q == b.size() || (p < a.size() && a[p].first < b[q].first)) {
+                        f *= std::conj(trn[a[p].first][a[p].second]);
+                        ++p;
+                    } else if (p == a.size() || b[q].first < a[p].first) {
+                        f *= trn[b[q].first][b[q].second];
+                        ++q;
+                    } else {
+                        f *= gram[a[p].first][a[p].second][b[q].second];
+                        ++p;
+                        ++q;
+                    }
+                }
+                acc += (std::conj(v[i].second) * v[j].second * f).real();
+            }
+        return std::max(acc, 0.0);
+    };
+    const double g2 = norm2(G);
+    if (g2 == 0.0) return 0.0;
+    return std::sqrt(norm2(D) / g2);
 }
+
+bool sop_is_hermitian(const SopInput &s, double rtol) { return sop_hermiticity_defect(s, 1e-12) <= rtol; }
 
 namespace {
 

@@ -47,6 +47,7 @@ public:
     std::vector<double> observe(int kind, int n, const int32_t *op_ids, const double *vecs);
     void apply_root_heff(const double *x, double *y);
     void info(int32_t *bonds, int64_t *counters);
+    size_t workspace_need() const { return ws_need; }
 
     Tree t;
     ttn_options opt;
@@ -83,6 +84,7 @@ private:
     int solve_idx = 0;
     int mmax = 40;
     int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    size_t ws_need = 0;  // scratch bytes of the current operator (workspace size)
 
     void *dalloc(size_t bytes);
     void free_sop();

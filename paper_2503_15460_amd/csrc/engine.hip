@@ -24,6 +24,9 @@
 
 namespace ttn {
 
+static_assert(MAX_CHILDREN + 1 <= MAXD, "node tensors must fit the slot arrays");
+static_assert(MAX_CHILDREN + 1 <= MAXF, "operator entries must fit the factor arrays");
+
 #define HIPCHK(x)                                                                                  \
     do {                                                                                           \
         hipError_t e_ = (x);                                                                       \
@@ -87,6 +90,7 @@ void *Engine::dalloc(size_t bytes) {
 }
 
 void Engine::free_sop() {
+    have_sop = false;
     for (void *p : sop_allocs) (void)hipFree(p);
     sop_allocs.clear();
     heffP.clear();
@@ -443,7 +447,12 @@ void Engine::set_sop(const SopInput &s) {
         for (auto &m : mfP[z]) acc(m);
     }
     cpart_e = std::max<int64_t>(cpart_e, 64 * 64 * 64);
-    tmp = (double2 *)dalloc(sizeof(double2) * tmp_e);
+    // scratch: every buffer below is either allocated here or carved from the
+    // caller's workspace (256-byte aligned pieces, zeroed)
+    std::vector<std::pair<void **, size_t>> want;
+    auto need = [&](auto **ptr, size_t bytes) { want.push_back({(void **)ptr, bytes < 16 ? 16 : bytes}); };
+    need(&tmp, sizeof(double2) * tmp_e);
+    mprep = nullptr;
     if (opt.precision == TTN_BF16X3) {  // split factors of the matrix-core stages
         size_t ents = 1;
         for (int z = 0; z < n; ++z) {
@@ -451,57 +460,70 @@ void Engine::set_sop(const SopInput &s) {
             if (z != t.root) ents = std::max(ents, std::max(spoP[z].ents.size(), bondP[z].ents.size()));
             for (auto &m : mfP[z]) ents = std::max(ents, m.ents.size());
         }
-        mprep = (unsigned short *)dalloc(sizeof(unsigned short) * ents * 2 * 128 * 128);
-    } else {
-        mprep = nullptr;
+        need(&mprep, sizeof(unsigned short) * ents * 2 * 128 * 128);
     }
-    gsum = (double2 *)dalloc(sizeof(double2) * gsum_e);
-    cpart = (double2 *)dalloc(sizeof(double2) * cpart_e);
-    Rbuf = (double2 *)dalloc(sizeof(double2) * maxb2);
-    Cbuf = (double2 *)dalloc(sizeof(double2) * maxb2);
-    smallV = (double2 *)dalloc(sizeof(double2) * (SMALL_MMAX + 2) * SMALL_MAX);
+    need(&gsum, sizeof(double2) * gsum_e);
+    need(&cpart, sizeof(double2) * cpart_e);
+    need(&Rbuf, sizeof(double2) * maxb2);
+    need(&Cbuf, sizeof(double2) * maxb2);
+    need(&smallV, sizeof(double2) * (SMALL_MMAX + 2) * SMALL_MAX);
     int64_t mats = 0;
     for (int z = 0; z < n; ++z) {
         mats += (int64_t)t.bond[z] * t.bond[z];
         if (t.local_dim[z] > 0) mats += (int64_t)t.local_dim[z] * t.local_dim[z];
     }
     obs_elems = 2 * maxN + mats + 64;
-    obs = (double2 *)dalloc(sizeof(double2) * obs_elems);
+    need(&obs, sizeof(double2) * obs_elems);
+    bk = BigKrylov{};
     if (bigN > 0) {
-        bk.V = (double2 *)dalloc(sizeof(double2) * (mmax + 1) * bigN);
-        bk.Hm = (double2 *)dalloc(sizeof(double2) * (mmax + 1) * mmax);
-        bk.h = (double2 *)dalloc(sizeof(double2) * (mmax + 1));
-        bk.y = (double2 *)dalloc(sizeof(double2) * (mmax + 1));
-        bk.part = (double *)dalloc(sizeof(double) * VEC_BLOCKS * (mmax + 2) * 2);
-        bk.scal = (double *)dalloc(sizeof(double) * 4);
-        bk.meff = (int *)dalloc(sizeof(int) * 4);
-        bk.counter = (unsigned *)dalloc(sizeof(unsigned) * 4);
-        HIPCHK(hipMemset(bk.counter, 0, sizeof(unsigned) * 4));
-        HIPCHK(hipMemset(bk.meff, 0, sizeof(int) * 4));
+        need(&bk.V, sizeof(double2) * (mmax + 1) * bigN);
+        need(&bk.Hm, sizeof(double2) * (mmax + 1) * mmax);
+        need(&bk.h, sizeof(double2) * (mmax + 1));
+        need(&bk.y, sizeof(double2) * (mmax + 1));
+        need(&bk.part, sizeof(double) * VEC_BLOCKS * (mmax + 2) * 2);
+        need(&bk.scal, sizeof(double) * 4);
+        need(&bk.meff, sizeof(int) * 4);
+        need(&bk.counter, sizeof(unsigned) * 4);
     }
     {  // copy of the state taken at the start of every step (restored on failure)
         int64_t tot = 0;
         for (int z = 0; z < n; ++z) tot += t.size[z];
-        snapshot = (double2 *)dalloc(sizeof(double2) * tot);
+        need(&snapshot, sizeof(double2) * tot);
     }
     // many-work-group QR scratch
-    qrw.tau = (double2 *)dalloc(sizeof(double2) * 64);
-    qrw.scl = (double2 *)dalloc(sizeof(double2) * 64);
-    qrw.diag = (double2 *)dalloc(sizeof(double2) * 64);
-    qrw.snapped = (int *)dalloc(sizeof(int) * 64);
-    qrw.w = (double2 *)dalloc(sizeof(double2) * 64 * 64);
-    qrw.rowi = (double2 *)dalloc(sizeof(double2) * 64);
-    qrw.part = (double *)dalloc(sizeof(double) * QRM_BLOCKS_MAX * (2 + 2 * 64));
-    qrw.S = (double2 *)dalloc(sizeof(double2) * QRM_BLOCKS_MAX * 64 * 63 / 2);
-    qrw.K = (double2 *)dalloc(sizeof(double2) * 64 * 64);
-    qrw.thr = (double *)dalloc(sizeof(double) * 4);
-    qrw.counter = (unsigned *)dalloc(sizeof(unsigned) * 4);
-    HIPCHK(hipMemset(qrw.counter, 0, sizeof(unsigned) * 4));
-    qrw.cpart = (double *)dalloc(sizeof(double) * 2 * QRM_BLOCKS_MAX * QRC_REC);
-    qrw.bar = (unsigned *)dalloc(sizeof(unsigned) * 192);
+    need(&qrw.tau, sizeof(double2) * 64);
+    need(&qrw.scl, sizeof(double2) * 64);
+    need(&qrw.diag, sizeof(double2) * 64);
+    need(&qrw.snapped, sizeof(int) * 64);
+    need(&qrw.w, sizeof(double2) * 64 * 64);
+    need(&qrw.rowi, sizeof(double2) * 64);
+    need(&qrw.part, sizeof(double) * QRM_BLOCKS_MAX * (2 + 2 * 64));
+    need(&qrw.S, sizeof(double2) * QRM_BLOCKS_MAX * 64 * 63 / 2);
+    need(&qrw.K, sizeof(double2) * 64 * 64);
+    need(&qrw.thr, sizeof(double) * 4);
+    need(&qrw.counter, sizeof(unsigned) * 4);
+    need(&qrw.cpart, sizeof(double) * 2 * QRM_BLOCKS_MAX * QRC_REC);
+    need(&qrw.bar, sizeof(unsigned) * 192);
     qrw.bar_base = 0;
     const int n_solves = (2 * n - 1) + 2 * (n - 1);
-    d_stats = (SolveStat *)dalloc(sizeof(SolveStat) * n_solves);
+    need(&d_stats, sizeof(SolveStat) * n_solves);
+    size_t total = 0;
+    for (auto &w : want) total += (w.second + 255) / 256 * 256;
+    ws_need = total;
+    if (opt.workspace) {
+        if (total > opt.workspace_bytes)
+            throw Error(TTN_E_OOM, "workspace too small: the operator needs " + std::to_string(total) +
+                                       " bytes of scratch, the workspace has " + std::to_string(opt.workspace_bytes));
+        char *base = (char *)opt.workspace;
+        HIPCHK(hipMemset(base, 0, total));
+        size_t off = 0;
+        for (auto &w : want) {
+            *w.first = base + off;
+            off += (w.second + 255) / 256 * 256;
+        }
+    } else {
+        for (auto &w : want) *w.first = dalloc(w.second);
+    }
     // pinned, so that the per-step statistics copy stays asynchronous
     if (h_stats) (void)hipHostFree(h_stats);
     h_stats = nullptr;
@@ -923,6 +945,8 @@ std::vector<double> Engine::observe(int kind, int n, const int32_t *op_ids, cons
         return h;
     };
     std::vector<double> out(2, 0.0);
+    // host staging of uploads: kept until the final fetch synchronises the stream
+    std::vector<std::vector<double2>> staging;
     if (kind == TTN_OBS_NORM) {
         auto a = fetch(A[root], t.size[root]);
         double s = 0.0;
@@ -971,7 +995,8 @@ std::vector<double> Engine::observe(int kind, int n, const int32_t *op_ids, cons
             if (t.local_dim[c] > 0) {
                 if (leafop[c]) {
                     const int d = t.local_dim[c];
-                    std::vector<double2> hm(d * d);
+                    staging.emplace_back(d * d);
+                    std::vector<double2> &hm = staging.back();
                     for (int q = 0; q < d * d; ++q) hm[q] = to_d2((*leafop[c])[q]);
                     double2 *dm = opbuf + opoff;
                     opoff += d * d;
@@ -1026,7 +1051,8 @@ std::vector<double> Engine::observe(int kind, int n, const int32_t *op_ids, cons
             };
             if (t.local_dim[c] > 0) {
                 const int d = t.local_dim[c];
-                std::vector<double2> hv(d);
+                staging.emplace_back(d);
+                std::vector<double2> &hv = staging.back();
                 for (int i = 0; i < d; ++i)
                     hv[i] = make_double2(vecs[2 * (leafoff[c] + i)], vecs[2 * (leafoff[c] + i) + 1]);
                 double2 *dv = opbuf + opoff;

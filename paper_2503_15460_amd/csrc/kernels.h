@@ -146,6 +146,14 @@ void profile_enable(bool enable);
 bool profile_enabled();
 void profile_add_flops(const char *name, double flops);
 std::vector<KernelStat> profile_collect();
+// frees the profiler's device clock slots and event pool (re-created on demand)
+void release_process_resources();
+// while one lives, launches made by this thread are not timed (no events created)
+struct ProfileSuspend {
+    ProfileSuspend();
+    ~ProfileSuspend();
+    bool prev;
+};
 
 // ---- launchers (all asynchronous on `st`) ----
 void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st);

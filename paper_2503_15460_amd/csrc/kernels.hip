@@ -1908,6 +1908,7 @@ struct Rec {
     int ts_slot;  // >= 0: duration from the kernel's own start / end clock readings
 };
 static bool on = false;
+static thread_local bool suspended = false;  // this thread's launches go untimed
 // kernel-clock slots: ts[i] = earliest start, ts[PROF_TS_MAX + i] = latest end
 static unsigned long long *ts = nullptr;
 static int ts_used = 0;
@@ -1931,7 +1932,7 @@ static unsigned long long *take_ts() {
         ts_used = 0;
         ts_fresh = true;
     }
-    if (ts_used >= PROF_TS_MAX) throw std::runtime_error("launch profiler: too many cooperative launches to time");
+    if (ts_used >= PROF_TS_MAX) return nullptr;  // slots exhausted: the launch runs untimed
     return ts + ts_used++;
 }
 static std::vector<hipEvent_t> pool;
@@ -1950,7 +1951,7 @@ static hipEvent_t take() {
 
 #define TTN_LAUNCH(NAME, FL, BY, KER, GRID, BLOCK, LDS, ST, ...)                                     \
     do {                                                                                             \
-        if (prof::on) {                                                                              \
+        if (prof::on && !prof::suspended) {                                                          \
             hipEvent_t ea_ = prof::take(), eb_ = prof::take();                                       \
             hipExtLaunchKernelGGL(KER, dim3(GRID), dim3(BLOCK), LDS, ST, ea_, eb_, 0, __VA_ARGS__);   \
             prof::recs.push_back({NAME, ea_, eb_, (double)(FL), (double)(BY), -1});                  \
@@ -1969,6 +1970,22 @@ void profile_enable(bool enable) {
 }
 
 bool profile_enabled() { return prof::on; }
+
+ProfileSuspend::ProfileSuspend() : prev(prof::suspended) { prof::suspended = true; }
+ProfileSuspend::~ProfileSuspend() { prof::suspended = prev; }
+
+void release_process_resources() {
+    prof::on = false;
+    prof::recs.clear();
+    prof::extra_flops.clear();
+    for (hipEvent_t e : prof::pool) (void)hipEventDestroy(e);
+    prof::pool.clear();
+    prof::used = 0;
+    if (prof::ts) (void)hipFree(prof::ts);
+    prof::ts = nullptr;
+    prof::ts_used = 0;
+    prof::ts_fresh = false;
+}
 
 void profile_add_flops(const char *name, double flops) { prof::extra_flops[name] += flops; }
 
@@ -2223,15 +2240,16 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     QRWork qq = q;
     unsigned long long *ts = nullptr;
     int slot = -1;
-    if (prof::on) {
+    if (prof::on && !prof::suspended) {
         ts = prof::take_ts();
-        slot = (int)(ts - prof::ts);
+        if (ts) slot = (int)(ts - prof::ts);
     }
     void *args[] = {&A, &Lu, &n, &Ru, &rp, &qq, &Rout, &transR, &snap, &ts};
     hipError_t e = hipLaunchCooperativeKernel((const void *)k_qr_coop, dim3(nb), dim3(QRM_THREADS), args, lds, st);
     if (e != hipSuccess) throw std::runtime_error(std::string("hipLaunchCooperativeKernel: ") + hipGetErrorString(e));
     q.bar_base += (unsigned long long)nb * (unsigned long long)(n + 2);  // n column barriers, Gram, K
-    if (prof::on) prof::recs.push_back({"k_qr_coop", nullptr, nullptr, 16.0 * (double)m * n * n, 32.0 * (double)m * n, slot});
+    if (prof::on && slot >= 0)
+        prof::recs.push_back({"k_qr_coop", nullptr, nullptr, 16.0 * (double)m * n * n, 32.0 * (double)m * n, slot});
     return true;
 }
 

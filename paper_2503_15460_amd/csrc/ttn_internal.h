@@ -19,6 +19,9 @@ struct Error : std::runtime_error {
     Error(ttn_status c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
 
+// Children per node: node tensors have at most 8 indices (children + parent).
+constexpr int MAX_CHILDREN = 7;
+
 // Tree geometry after validation and bond clamping.
 struct Tree {
     int n = 0, root = -1;
@@ -72,9 +75,11 @@ SopInput read_sop(const Tree &t, int32_t n_ops, const int32_t *op_leaf, const in
                   const double *op_data, int32_t n_terms, const double *coeff,
                   const int64_t *term_ptr, const int32_t *term_ops);
 
-// True if G^dagger equals G term by term (adjoint strings matched with
-// conjugated coefficients, operator matrices compared exactly).
-bool sop_is_hermitian(const SopInput &s, double rtol = 1e-12);
+// ||G - G^dag||_F / ||G||_F from the leaf operators and coefficients (leaf
+// operators that agree to `cluster` relative are identified first).
+double sop_hermiticity_defect(const SopInput &s, double cluster);
+// True if ||G - G^dag||_F <= rtol ||G||_F.
+bool sop_is_hermitian(const SopInput &s, double rtol = 1e-7);
 
 TreeOp compile_tree_operator(const Tree &t, const SopInput &s);
 

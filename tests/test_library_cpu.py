@@ -18,7 +18,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     names = set()
-    for h in ("ttn.h", "ttn_debug.h"):
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
         src = open(os.path.join(ROOT, "include", h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         names |= set(re.findall(r"\b(ttn_[a-z_0-9]+)\s*\(", src))
@@ -102,3 +104,56 @@ def test_non_finite_sop_rejected(where):
     with pytest.raises(T.TTNError) as e:
         T.dense_tree_operator(p)
     assert "E_INVALID" in str(e.value)
+
+
+def test_node_with_too_many_children_is_refused():
+    """Node tensors carry at most 8 indices: a root with 8 leaf children is a
+    legal tree shape the library does not take (TTN_E_TREE, not a crash)."""
+    ok = T.clamp_bonds([-1] + [0] * 7, [0] + [2] * 7, [1] + [2] * 7)  # 7 children: accepted
+    assert ok.tolist() == [1] + [2] * 7
+    with pytest.raises(T.TTNError) as e:
+        T.clamp_bonds([-1] + [0] * 8, [0] + [2] * 8, [1] + [2] * 8)
+    assert "E_TREE" in str(e.value)
+
+
+def _dense_defect(p):
+    G = dense_sop(p)
+    return np.linalg.norm(G - G.conj().T) / np.linalg.norm(G)
+
+
+def test_hermiticity_defect_is_the_dense_norm():
+    """The host check of hermitian = 1 evaluates ||G - G^dag||_F / ||G||_F from
+    the leaf operators; it equals the norm of the dense matrices."""
+    p = sbm_problem(n_modes=3, d=3, bond=3)
+    assert T.hermiticity_defect(p) < 1e-14
+    h = heom_sbm_problem(K=1, levels=3)  # non-Hermitian generator
+    d_dense, d_lib = _dense_defect(h), T.hermiticity_defect(h)
+    assert d_dense > 1e-2 and abs(d_lib - d_dense) < 1e-10 * d_dense
+    # Hermitian only as a sum: sigma_+ and sigma_- written as separate terms
+    q = sbm_problem(n_modes=2, d=3, bond=3)
+    sp = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+    spin = q.op_leaf[q.observables["sz"][0]]
+    q.op_leaf = list(q.op_leaf) + [spin, spin]
+    q.op_mats = list(q.op_mats) + [sp, sp.conj().T]
+    n = len(q.op_leaf)
+    q.term_ops = list(q.term_ops) + [[n - 2], [n - 1]]
+    q.coeff = np.append(np.asarray(q.coeff, dtype=np.complex128), [0.3 + 0.2j, 0.3 - 0.2j])
+    assert T.hermiticity_defect(q) < 1e-12 and _dense_defect(q) < 1e-14
+    q.coeff[-1] = 0.3 + 0.2j  # now not Hermitian
+    d_dense, d_lib = _dense_defect(q), T.hermiticity_defect(q)
+    assert d_dense > 1e-2 and abs(d_lib - d_dense) < 1e-10 * d_dense
+
+
+def test_numerically_hermitian_operator_is_accepted():
+    """A leaf operator that is Hermitian up to rounding (not bit-symmetric)
+    passes the check; a perturbation above the tolerance does not."""
+    p = sbm_problem(n_modes=2, d=4, bond=3)
+    o = p.observables["sz"][0]
+    m = np.array(p.op_mats[o], dtype=np.complex128)
+    m[0, 1] += 1e-15
+    p.op_mats[o] = m
+    assert T.hermiticity_defect(p) < 1e-12
+    m = m.copy()
+    m[0, 1] += 1e-3
+    p.op_mats[o] = m
+    assert T.hermiticity_defect(p) > 1e-7
