@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the one-site TDVP sweep on one MI355X.
 
-Workload: the synthetic 2-state / 24-mode vibronic-coupling model (seed 2;
-3-layer tree R(E, M1, M2), M(L, L, L), L(4 modes), bonds 8/16/20, mode bases
-8-32 levels, ~150 SOP terms), complex128, dt = 0.5 fs, from the product state
-|s=1>|0...0>.  One step = one symmetric projector-splitting sweep
-(ttn_step(dt)); the metric is sweeps per second with the state resident on
-the GPU, plus the H_eff flop rate.
+Headline workload: the synthetic 10-state / 120-mode donor-acceptor exciton
+model (seed 3; 120 modes paired into 60 composite leaves of 36-144 levels,
+1500 SOP terms; tree R(E, A1, A2), A(B, B, B), B(C, C), C(5 leaves), bonds
+8/32/48/64: node tensors up to 48 x 48 x 48 x 64 = 7.08M elements), dt 0.5 fs,
+from the product state |0>|vac>.  One step = one symmetric projector-splitting
+sweep (ttn_step(dt)).  The metric is sweeps per second with the state resident
+on the GPU in the FP32-mixed form (effective-generator and environment
+contractions in complex FP32; QR, Krylov and the projected exponential in
+FP64) against the FP64 form, with the H_eff flop rate and the error of every
+population and of a(t) against FP64 from a seeded full-rank start.
 
-Prints ONE JSON line.  A separate short pass with the library's launch
-profiler (dispatch-stamped HIP events per launch; the cooperative QR from its
-own clock readings) gives the dominant kernel's average launch duration and
-its roofline numbers; the oracle (CPU) is timed on a one-step sample of the
-same workload.
+Prints ONE JSON line.  A separate profiled sweep (dispatch-stamped HIP events
+per launch; the cooperative QR from its own clock readings) gives the
+dominant kernel's average launch duration and its roofline numbers; the
+oracle (CPU) is timed on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,45 +29,57 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix = vector)
-PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
-PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 (matrix = vector)
+PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 (matrix = vector)
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (matrix = vector)
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 
-# Kernels whose arithmetic is plain FP64 vector FMA code (no matrix-core
-# instructions): their compute peak is the FP64 vector rate, 256 CUs x 2.4 GHz
-# x 128 flop/clk/CU = 78.6 TFLOP/s.
-ALU_KERNELS = {"k_small_solve", "k_mode_stage", "k_group_sum", "k_contract_part", "k_kry_orth", "k_qr",
-               "k_qrm_step", "k_qrm_finish", "k_mode_single"}
+HEADLINE = "fp32"  # the FP32-mixed form
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+# Compute peak of each kernel family: plain FMA code runs at the vector rate of
+# its precision (256 CUs x 2.4 GHz x 128 (FP64) or 256 (FP32) flop/clk/CU);
+# the BF16x3 stage runs on the bf16 matrix cores.
+KERNEL_PEAK = [("k_mode_mfma", "mfma", PEAK_BF16_TFLOPS), ("_f32", "alu", PEAK_FP32_TFLOPS)]
 
 
-def roofline(stats):
-    """Roofline numbers of the kernel with the largest total time."""
+def kernel_peak(name: str):
+    for key, bound, peak in KERNEL_PEAK:
+        if key in name:
+            return bound, peak
+    return "alu", PEAK_FP64_TFLOPS
+
+
+def roofline(stats, steps: int, workload: str):
+    """Roofline numbers of the kernel with the largest total time: algorithmic
+    flops and bytes per launch (the library's model of each launch) over the
+    average launch duration, against the compute peak of its precision or the
+    HBM peak, whichever bounds it at its arithmetic intensity."""
     top = max(stats, key=lambda r: r["total_ms"])
     avg_s = top["total_ms"] / 1e3 / top["calls"]
     flops = top["flops"] / top["calls"]
     byts = top["bytes"] / top["calls"]
+    bound, peak = kernel_peak(top["name"])
+    ridge = peak * 1e12 / (PEAK_HBM_GBS * 1e9)
     intensity = flops / byts if byts > 0 else float("inf")
-    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
     if flops > 0 and intensity >= ridge:
         ach = flops / avg_s / 1e12
-        bound = "alu" if top["name"] in ALU_KERNELS else "mfma"
-        r = dict(bound=bound, achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s", frac=ach / PEAK_FP64_TFLOPS)
+        r = dict(bound=bound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak)
     else:
         ach = byts / avg_s / 1e9
         r = dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s", frac=ach / PEAK_HBM_GBS)
     r.update(kernel=top["name"], avg_launch_us=avg_s * 1e6, flops_per_launch=flops, bytes_per_launch=byts,
-             launches_per_step=None, traffic=None)
+             launches_per_step=top["calls"] / steps, traffic=measured_traffic(top["name"], workload))
     return r
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading for a
     plain copy kernel of known size), or None when there is none or the kernel
     sources changed after the counters were taken (SHA-256 of kernels.hip)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_vibronic24_hbm_traffic.md")
+    safe = "".join(ch if ch.isalnum() or ch == "_" else "_" for ch in kernel).strip("_")
+    path = os.path.join(ROOT, "profiles", f"{safe}_{workload}_hbm_traffic.md")
     src = os.path.join(ROOT, "paper_2503_15460_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
@@ -71,15 +87,14 @@ def measured_traffic(kernel: str):
     for line in open(path):
         if line.startswith("traffic: "):
             rec = json.loads(line[len("traffic: "):])
-    if not rec:
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernels_hip_sha256"):
+    if not rec or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernels_hip_sha256"):
         return None
     return rec["bytes_per_launch"]
 
 
-def timed_run(T, p, precision, steps, warmup):
-    """Sweeps of the workload from its product state; returns (handle, seconds, counters before, after)."""
+def timed_run(T, p, precision, steps, warmup, keep=False):
+    """`warmup` then `steps` timed sweeps from the product state; returns a dict
+    (and the open handle when keep)."""
     import torch
     g = T.TTN.from_problem(p, precision=precision)
     g.set_product_state(p.init_vecs)
@@ -89,70 +104,136 @@ def timed_run(T, p, precision, steps, warmup):
     t0 = time.perf_counter()
     g.step(p.dt, steps)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    return g, elapsed, c0, g.counters()
-
-
-def fp32_error(T, p, steps: int):
-    """Largest difference of populations and autocorrelation between the FP32
-    and FP64 modes over `steps` sweeps from a seeded full-rank state (from the
-    product state, rounding-size differences are amplified by the
-    rank-deficient first QRs and say nothing about the FP32 contractions)."""
-    from workloads import random_isometric_state
-    runs = []
-    for prec in (T.TTN_FP64, T.TTN_FP32):
-        g = T.TTN.from_problem(p, precision=prec)
-        st = random_isometric_state(p.parent, p.local_dim, g.bonds(), seed=2)
-        g.set_state(st)
-        obs = []
-        for _ in range(steps):
-            g.step(p.dt)
-            obs += [g.expect(p.observables["P0"]), g.expect(p.observables["P1"]), g.overlap_t0()]
-        runs.append(np.array(obs))
-        g.close()
-    return {"max_abs": float(np.abs(runs[0] - runs[1]).max()), "observables": "P0, P1, a(t)",
-            "start": "seeded full-rank isometric state", "steps": steps}
-
-
-def exciton_run(T, steps: int):
-    """The 10-state / 120-mode exciton model (bonds 32-64), FP64 and FP32 modes:
-    sweeps/s, H_eff flop rate and the FP32 population error against FP64."""
-    import torch
-    from workloads import exciton_problem
-    p = exciton_problem()
-    out, pops = {}, {}
-    for prec, name in ((T.TTN_FP64, "fp64"), (T.TTN_FP32, "fp32"), (T.TTN_BF16X3, "bf16x3")):
-        g, el, c0, c1 = timed_run(T, p, prec, steps, 1)
-        pops[name] = np.array([g.expect(p.observables[f"P{k}"]).real for k in range(10)])
-        T.profile_begin()
-        g.step(p.dt)
-        torch.cuda.synchronize()
-        st = T.profile_end()
-        kname = "k_mode_mfma" if prec == T.TTN_BF16X3 else "k_mode_tile"
-        tile = [r for r in st if r["name"].startswith(kname)]
-        tms = sum(r["total_ms"] for r in tile)
-        tfl = sum(r["flops"] for r in tile)
-        peak = {T.TTN_FP64: PEAK_FP64_TFLOPS, T.TTN_FP32: PEAK_FP32_TFLOPS, T.TTN_BF16X3: PEAK_BF16_TFLOPS}[prec]
-        out[name] = {"value": steps / el, "unit": "sweeps/s", "ms_per_step": 1e3 * el / steps,
-                     "heff_tflops": (c1["heff_flops"] - c0["heff_flops"]) / el / 1e12,
-                     "stage_kernel": kname,
-                     "stage_tflops": tfl / tms / 1e9 if tms > 0 else None,
-                     "stage_frac": (tfl / tms / 1e9) / peak if tms > 0 else None,
-                     "stage_peak_tflops": peak,
-                     "device_gib": c1["device_bytes"] / 2**30}
-        g.close()
-    out["fp32_max_abs_population_diff_vs_fp64"] = float(np.abs(pops["fp64"] - pops["fp32"]).max())
-    out["bf16x3_max_abs_population_diff_vs_fp64"] = float(np.abs(pops["fp64"] - pops["bf16x3"]).max())
-    out["note"] = ("stage_tflops counts algorithmic complex flops (8 per MAC); BF16x3 executes three bf16 "
-                   "matrix-core products per real product and its peak is the dense bf16 one. Product-state "
-                   "start: population differences include the rank-deficient-QR amplification of rounding")
-    out["workload"] = ("exciton10x120: 10 states, 120 modes in 60 composite leaves (d 36-144), 1500 SOP terms, "
-                       "tree R(E,A,A) A(B,B,B) B(C,C) C(5 leaves), bonds 8/32/48/64, dt 0.5 fs, product start, "
-                       f"{1 + steps} sweeps")
+    el = time.perf_counter() - t0
+    c1 = g.counters()
+    out = {"value": steps / el, "unit": "sweeps/s", "ms_per_step": 1e3 * el / steps,
+           "heff_tflops": (c1["heff_flops"] - c0["heff_flops"]) / el / 1e12,
+           "matvecs_per_step": (c1["matvecs"] - c0["matvecs"]) / steps, "redo_steps": c1["redo"] - c0["redo"],
+           "device_gib": c1["device_bytes"] / 2**30}
+    if keep:
+        return out, g
+    g.close()
     return out
 
 
-def heom_run(T, steps: int):
+def profiled_sweep(T, g, p, steps=1):
+    import torch
+    T.profile_begin()
+    g.step(p.dt, steps)
+    torch.cuda.synchronize()
+    return T.profile_end()
+
+
+def stage_rate(stats, precision):
+    """Rate of the H_eff / environment stage kernels of a profiled sweep."""
+    name = "k_mode_mfma" if precision == PRECISIONS["bf16x3"] else "k_mode_tile"
+    rows = [r for r in stats if r["name"].startswith(name)]
+    ms = sum(r["total_ms"] for r in rows)
+    fl = sum(r["flops"] for r in rows)
+    if ms <= 0:
+        return None
+    peak = {0: PEAK_FP64_TFLOPS, 1: PEAK_FP32_TFLOPS, 2: PEAK_BF16_TFLOPS}[precision]
+    return {"kernel": name, "tflops": fl / ms / 1e9, "frac": fl / ms / 1e9 / peak, "peak_tflops": peak,
+            "share_of_sweep_kernel_time": ms / sum(r["total_ms"] for r in stats)}
+
+
+def error_vs_fp64(T, p, obs, precisions, steps, seed):
+    """Largest difference of each observable between each mixed form and FP64
+    over `steps` sweeps from a seeded full-rank isometric state (from the
+    product state, the rank-deficient first QRs amplify rounding of any
+    precision and say nothing about the contractions)."""
+    from workloads import random_isometric_state
+    bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
+    st = random_isometric_state(p.parent, p.local_dim, bonds, seed=seed)
+    runs = {}
+    for name in ["fp64"] + list(precisions):
+        g = T.TTN.from_problem(p, precision=PRECISIONS[name])
+        g.set_state(st)
+        rows = []
+        for _ in range(steps):
+            g.step(p.dt)
+            rows.append([g.expect(p.observables[k]) for k in obs] + [g.overlap_t0()])
+        runs[name] = np.array(rows)
+        g.close()
+    out = {"start": f"seeded full-rank isometric state (seed {seed})", "steps": steps,
+           "observables": list(obs) + ["a(t)"]}
+    for name in precisions:
+        d = np.abs(runs[name] - runs["fp64"]).max(axis=0)
+        out[name] = {"max_abs": float(d.max()), "per_observable": [float(x) for x in d]}
+    return out
+
+
+def cpu_oracle_sample(p, a_matvecs_per_step: float, a_node: int, n_terms_sample: int, threads: int):
+    """The oracle on the host: its effective-generator application at an A node
+    (7.08M elements) is the sweep's dominant local operation.  A sample of its
+    per-term products (the code path Oracle.heff runs for every crossing term,
+    on random environment matrices of the right shapes) is timed, scaled to the
+    node's full term list and to the A-node matvecs of one sweep; all other work
+    of the sweep is left out, so the rate is an upper bound on the oracle's."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Oracle
+    o = Oracle(p)
+    kids = o.kids[a_node]
+    pax = len(kids)
+    # the terms Oracle.heff applies one by one at this node: touching it, not
+    # lying inside one child (those are summed into the child's inside channel)
+    crossing = [r for r in range(len(o.terms))
+                if o.touches(r, a_node) and not any(o.inside(r, c) for c in kids)]
+    rng = np.random.default_rng(0)
+    shp = o.shape(a_node)
+    X = rng.normal(size=shp) + 1j * rng.normal(size=shp)
+    sample = sorted(rng.choice(len(crossing), size=min(n_terms_sample, len(crossing)), replace=False))
+    facs = []
+    for i in sample:
+        r = crossing[i]
+        f = {k: rng.normal(size=(shp[k], shp[k])) + 0j for k, c in enumerate(kids) if o.touches(r, c)}
+        if o.touches_outside(r, a_node):
+            f[pax] = rng.normal(size=(shp[pax], shp[pax])) + 0j
+        facs.append((r, f))
+    with threadpool_limits(limits=threads):
+        o._apply_factors(X, facs[0][1])  # warm-up
+        t0 = time.perf_counter()
+        for r, f in facs:
+            _ = o.coef[r] * o._apply_factors(X, f)
+        el = time.perf_counter() - t0
+    per_term = el / len(facs)
+    t_matvec = per_term * len(crossing)
+    t_step = t_matvec * a_matvecs_per_step
+    return {"value": 1.0 / t_step, "unit": "sweeps/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{len(facs)} of the {len(crossing)} per-term products of the oracle's H_eff application at "
+                       f"an A node ({int(np.prod(shp))} elements), {el:.1f} s, scaled to the full term list and to "
+                       f"the {a_matvecs_per_step:.0f} A-node matvecs of one sweep (all other work left out: an "
+                       f"upper bound on the oracle's rate)"),
+            "seconds_per_step_estimate": t_step}
+
+
+def vibronic_line(T, steps, warmup, cpu):
+    """Secondary line: the 2-state / 24-mode vibronic model (bonds 8/16/20) in
+    FP64 and FP32-mixed, and the oracle on one sweep of it."""
+    from workloads import vibronic_problem
+    p = vibronic_problem()
+    out = {"workload": "vibronic24: 2 states x 24 modes (d 8-32), ~150 SOP terms, tree R(E,M,M) M(L,L,L) "
+                       "L(4 modes), bonds 8/16/20, dt 0.5 fs, product initial state"}
+    out["fp64"], g = timed_run(T, p, 0, steps, warmup, keep=True)
+    st = profiled_sweep(T, g, p, 2)
+    out["fp64"]["roofline"] = roofline(st, 2, "vibronic24")
+    g.close()
+    out["fp32"] = timed_run(T, p, 1, steps, warmup)
+    out["fp32"]["error_vs_fp64"] = error_vs_fp64(T, p, ["P0", "P1"], ["fp32"], 5, 2)
+    if cpu:
+        from oracle import Oracle
+        o = Oracle(p)
+        o.set_product_state(p.init_vecs)
+        t0 = time.perf_counter()
+        o.step(p.dt)
+        out["cpu_oracle"] = {"value": 1.0 / (time.perf_counter() - t0), "unit": "sweeps/s",
+                             "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                             "sample": "one sweep from the product state"}
+    return out
+
+
+def heom_line(T, steps: int):
     """HEOM spin-boson (Debye bath, K = 16 poles, 32 auxiliary modes x 10
     levels, bonds 10-48, Arnoldi): FP64 and FP32 sweeps/s and the FP32
     difference of <sigma_z> and Tr rho_S against FP64."""
@@ -168,11 +249,9 @@ def heom_run(T, steps: int):
             out.append(g.bilinear(bra))
         return np.array(out)
     out, vals = {}, {}
-    for prec, name in ((T.TTN_FP64, "fp64"), (T.TTN_FP32, "fp32")):
-        g, el, c0, c1 = timed_run(T, p, prec, steps, 1)
+    for name in ("fp64", "fp32"):
+        out[name], g = timed_run(T, p, PRECISIONS[name], steps, 1, keep=True)
         vals[name] = obs(g)
-        out[name] = {"value": steps / el, "unit": "sweeps/s", "ms_per_step": 1e3 * el / steps,
-                     "heff_tflops": (c1["heff_flops"] - c0["heff_flops"]) / el / 1e12}
         g.close()
     out["sigma_z_trace_fp64"] = [float(vals["fp64"][0].real), float(vals["fp64"][1].real)]
     out["fp32_max_abs_diff_vs_fp64"] = float(np.abs(vals["fp64"] - vals["fp32"]).max())
@@ -181,29 +260,29 @@ def heom_run(T, steps: int):
     return out
 
 
-def batch_run(T, n_inst: int, steps: int):
+def batch_line(T, n_inst: int, steps: int):
     """Uneven spin-boson instances (8-64 modes, 6-16 levels, bonds 8-48): one
-    at a time in FP64 against one batch (FP64 and FP32) on 8 streams."""
+    at a time in FP64 against one batch (FP64 and FP32)."""
     import torch
     from workloads import batch_sbm_problems
     probs = batch_sbm_problems(seed=5, n_inst=n_inst)
     dts = np.array([p.dt for p in probs])
     res = {}
-    for prec, name in ((T.TTN_FP64, "fp64"), (T.TTN_FP32, "fp32")):
+    for name in ("fp64", "fp32"):
         gs = []
         for p in probs:
-            g = T.TTN.from_problem(p, precision=prec)
+            g = T.TTN.from_problem(p, precision=PRECISIONS[name])
             g.set_product_state(p.init_vecs)
             g.step(p.dt)
             gs.append(g)
         torch.cuda.synchronize()
-        if prec == T.TTN_FP64:
+        if name == "fp64":
             t0 = time.perf_counter()
             for g, p in zip(gs, probs):
                 g.step(p.dt, steps)
             torch.cuda.synchronize()
             res["sequential_fp64"] = n_inst * steps / (time.perf_counter() - t0)
-        b = T.TTNBatch(gs, n_streams=8)
+        b = T.TTNBatch(gs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.step(dts, steps)
@@ -217,30 +296,16 @@ def batch_run(T, n_inst: int, steps: int):
             "workload": f"{n_inst} of the 256 seeded uneven spin-boson instances (seed 5), {steps} timed sweeps each"}
 
 
-def cpu_baseline(problem, steps: int):
-    """The oracle (numpy complex128) on the host cores: seconds for `steps` sweeps."""
-    from oracle import Oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    o = Oracle(problem)
-    o.set_product_state(problem.init_vecs)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        o.step(problem.dt)
-    dt = time.perf_counter() - t0
-    return dict(value=steps / dt, unit="sweeps/s", cores=threads, kind="oracle",
-                sample=f"{steps} sweep(s) of the same 24-mode vibronic workload from the product state")
-
-
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--profile-steps", type=int, default=2)
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--error-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-contraction comparison run")
-    ap.add_argument("--no-extra", action="store_true", help="skip the exciton and batched-instance lines")
+    ap.add_argument("--no-error", action="store_true", help="skip the error runs from a full-rank start")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--only", choices=list(PRECISIONS), help="time one precision only (profiling runs)")
     ap.add_argument("--batch-instances", type=int, default=8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -251,80 +316,80 @@ def main():
 
     import torch
     import paper_2503_15460_amd as T
-    from workloads import vibronic_problem
+    from workloads import exciton_problem
 
     torch.cuda.init()
     torch.zeros(1, device="cuda:0")
-    p = vibronic_problem()
-    g, elapsed, c0, c1 = timed_run(T, p, T.TTN_FP64, args.steps, args.warmup)
-    sweeps_per_s = args.steps / elapsed
-    heff_tflops = (c1["heff_flops"] - c0["heff_flops"]) / elapsed / 1e12
-    pops = [g.expect(p.observables[k]).real for k in ("P0", "P1")]
-
-    # profiled pass (separate from the timed region)
-    T.profile_begin()
-    g.step(p.dt, args.profile_steps)
-    torch.cuda.synchronize()
-    stats = T.profile_end()
-    roof = roofline(stats)
-    top = roof["kernel"]
-    roof["launches_per_step"] = next(r["calls"] for r in stats if r["name"] == top) / args.profile_steps
-    roof["traffic"] = measured_traffic(top)
-    # the H_eff stage kernel of the same pass against its own (HBM) roofline
-    tile = [r for r in stats if r["name"] == "k_mode_tile"]
-    stage_roof = None
-    if tile:
-        r = tile[0]
-        s_avg = r["total_ms"] / 1e3 / r["calls"]
-        gbs = r["bytes"] / r["calls"] / s_avg / 1e9
-        stage_roof = {"kernel": "k_mode_tile", "bound": "hbm", "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
-                      "frac": gbs / PEAK_HBM_GBS, "tflops": r["flops"] / r["calls"] / s_avg / 1e12,
-                      "avg_launch_us": s_avg * 1e6, "launches_per_step": r["calls"] / args.profile_steps}
-
-    # the same run with the FP32 contraction mode (same steps from the same start)
-    fp32 = None
-    if not args.no_fp32:
-        g32, el32, d0, d1 = timed_run(T, p, T.TTN_FP32, args.steps, args.warmup)
-        g32.close()
-        fp32 = {"value": args.steps / el32, "unit": "sweeps/s", "ms_per_step": 1e3 * el32 / args.steps,
-                "heff_tflops": (d1["heff_flops"] - d0["heff_flops"]) / el32 / 1e12,
-                "error_vs_fp64": fp32_error(T, p, steps=5)}
-
+    p = exciton_problem()
+    names = [args.only] if args.only else ["fp64", "fp32", "bf16x3"]
+    runs, rooflines, a_matvecs = {}, {}, None
+    for name in names:
+        prec = PRECISIONS[name]
+        r, g = timed_run(T, p, prec, args.steps, args.warmup, keep=True)
+        print(f"bench.py: exciton10x120 {name}: {r['ms_per_step']:.0f} ms/sweep", file=sys.stderr, flush=True)
+        st = profiled_sweep(T, g, p)
+        r["stage"] = stage_rate(st, prec)
+        rooflines[name] = roofline(st, 1, "exciton10x120")
+        r["top_kernels"] = [{k: v for k, v in x.items()} for x in sorted(st, key=lambda x: -x["total_ms"])[:6]]
+        if name == "fp64" or a_matvecs is None:
+            node, fwd, mv = g.step_solves()
+            root = [z for z in range(p.n_nodes) if p.parent[z] < 0][0]
+            a_nodes = [z for z in range(p.n_nodes) if p.parent[z] == root and p.local_dim[z] == 0]
+            a_matvecs = (float(sum(m for z, f, m in zip(node, fwd, mv) if f and z in a_nodes)) / len(a_nodes),
+                         a_nodes[0])
+        g.close()
+        runs[name] = r
+    head = args.only or HEADLINE
+    hr = runs[head]
+    peak = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "bf16x3": PEAK_BF16_TFLOPS}
+    config = {
+        "workload": ("exciton10x120: 10 electronic states x 120 modes paired into 60 composite leaves (d 36-144), "
+                     "1500 SOP terms, tree R(E,A1,A2) A(B,B,B) B(C,C) C(5 leaves), bonds 8/32/48/64 (node tensors "
+                     "up to 48x48x48x64), dt 0.5 fs, product initial state, fixed bonds"),
+        "precision": {"fp64": "FP64", "fp32": "FP32-mixed: H_eff / environment contractions complex FP32, "
+                      "QR / Krylov / projected exponential FP64",
+                      "bf16x3": "BF16x3-mixed: as FP32-mixed, dense stages on bf16 matrix cores with hi/lo split"}[head],
+        "heff_tflops": hr["heff_tflops"], "heff_frac_peak": hr["heff_tflops"] / peak[head],
+        "runs": runs,
+    }
+    if "fp64" in runs and head != "fp64":
+        config["speedup_vs_fp64"] = hr["value"] / runs["fp64"]["value"]
+    if not args.no_error and not args.only:
+        config["error_vs_fp64"] = error_vs_fp64(T, p, [f"P{k}" for k in range(10)], ["fp32", "bf16x3"],
+                                                args.error_steps, 3)
     out = {
         "metric": "TDVP sweeps/s + H_eff TFLOP/s (% MFMA peak), FP32-mixed vs FP64 at stated err",
-        "value": sweeps_per_s,
+        "value": hr["value"],
         "unit": "sweeps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": hr["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
-        "data": "synthetic (seeded 2-state 24-mode vibronic model standing in for pyrazine)",
-        "config": {"workload": "vibronic24: 2 states x 24 modes (d 8-32), ~150 SOP terms, tree R(E,M,M) M(L,L,L) "
-                               "L(4 modes), bonds 8/16/20, dt 0.5 fs, product initial state, FP64",
-                   "precision": "fp64", "heff_tflops": heff_tflops,
-                   "heff_frac_fp64_peak": heff_tflops / PEAK_FP64_TFLOPS,
-                   "populations_after": pops, "redo_steps": c1["redo"] - c0["redo"],
-                   "fp32_mixed": fp32, "heff_stage_roofline": stage_roof},
-        "roofline": roof,
-        "kernels": sorted(({k: (v if k != "name" else v) for k, v in r.items()} for r in stats),
-                          key=lambda r: -r["total_ms"])[:8],
+        "dtype": {"fp64": "c128", "fp32": "c64+c128", "bf16x3": "bf16x3+c128"}[head],
+        "data": "synthetic (seeded 10-state 120-mode exciton model standing in for P3HT:PCBM)",
+        "config": config,
+        "roofline": rooflines[head],
     }
     if not args.no_extra:
-        # the other workloads are context lines: a failure there is recorded, and
-        # the headline line is still printed
-        for key, fn in (("exciton10x120", lambda: exciton_run(T, 1)), ("heom_sbm", lambda: heom_run(T, 3)),
-                        ("batched_instances", lambda: batch_run(T, args.batch_instances, 1))):
+        # context lines: a failure there is recorded and the headline still printed
+        for key, fn in (("vibronic24", lambda: vibronic_line(T, 30, 3, not args.no_cpu_baseline)),
+                        ("heom_sbm", lambda: heom_line(T, 3)),
+                        ("batched_instances", lambda: batch_line(T, args.batch_instances, 1))):
             try:
-                out["config"][key] = fn()
+                config[key] = fn()
             except (T.TTNError, RuntimeError, MemoryError) as e:
-                out["config"][key] = {"error": str(e)}
+                config[key] = {"error": str(e)}
                 print(f"bench.py: {key} failed: {e}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cb = cpu_oracle_sample(p, a_matvecs[0], a_matvecs[1], 6, threads)
+        one = cpu_oracle_sample(p, a_matvecs[0], a_matvecs[1], 3, 1)
+        cb["value_1_thread"] = one["value"]
+        cb["sample_1_thread"] = one["sample"]
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

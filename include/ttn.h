@@ -191,6 +191,14 @@ ttn_status ttn_apply_root_heff(ttn_t h, const double *x, double *y);
  * Either pointer may be NULL. */
 ttn_status ttn_get_info(ttn_t h, int32_t *effective_bond_dim, int64_t *counters);
 
+/* Local exponentials of the last completed step, in sweep order: for each
+ * solve i < *n_solves (at most max_solves written) node[i] is the node of a
+ * forward solve or the node below the bond of a backward solve, forward[i] is
+ * 1 or 0, matvecs[i] the effective-generator applications it took.  Any
+ * output may be NULL.  Errors: TTN_E_STATE (no step yet). */
+ttn_status ttn_get_step_solves(ttn_t h, int32_t max_solves, int32_t *node, int32_t *forward, int32_t *matvecs,
+                               int32_t *n_solves);
+
 /* Bytes of device scratch the handle's current operator needs (the size a
  * caller-provided ttn_options.workspace must have); 0 before ttn_set_sop.  Also
  * valid after ttn_set_sop failed with TTN_E_OOM. */

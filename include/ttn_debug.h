@@ -34,16 +34,22 @@ ttn_status ttn_debug_hermiticity_defect(int32_t n_nodes, const int32_t *parent, 
                                         const double *op_data, int32_t n_terms, const double *coeff,
                                         const int64_t *term_ptr, const int32_t *term_ops, double *defect);
 
-/* Size of the compiled sparse tree operator per node (host only): n_channels
- * [n_nodes] receives the number of channels on the bond above each node (the
- * root: 1), n_entries [n_nodes] the number of operator entries of each node.
- * Either output may be NULL.  Arguments as for ttn_create / ttn_set_sop.
+/* Size of the compiled sparse tree operator per node (host only), each output
+ * [n_nodes] and optional (NULL):
+ *   n_channels    channels on the bond above each node (the root: 1)
+ *   n_entries     operator entries of each node (hierarchical SOP)
+ *   n_merged      products the node's effective generator applies after the
+ *                 node-form compression (products equal in every factor but
+ *                 one summed into one; Sec. II B 2, terms (B) and (C))
+ *   n_sop_terms   SOP terms crossing the bond above each node (a plain SOP
+ *                 keeps one SPO and one mean field per such term; root: 0)
+ * Arguments as for ttn_create / ttn_set_sop.
  * Errors: TTN_E_TREE, TTN_E_DIMS, TTN_E_INVALID. */
 ttn_status ttn_debug_tree_operator_stats(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,
                                          int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
                                          const double *op_data, int32_t n_terms, const double *coeff,
                                          const int64_t *term_ptr, const int32_t *term_ops, int32_t *n_channels,
-                                         int32_t *n_entries);
+                                         int32_t *n_entries, int32_t *n_merged, int32_t *n_sop_terms);
 
 /* Effective (clamped) bond dimensions for a tree, host only.
  * Errors: TTN_E_TREE, TTN_E_DIMS. */

@@ -31,7 +31,7 @@ EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product
             "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end",
             "ttn_batch_create", "ttn_batch_step", "ttn_batch_last_error", "ttn_batch_destroy",
             "ttn_workspace_size", "ttn_release_process_resources", "ttn_debug_hermiticity_defect",
-            "ttn_debug_tree_operator_stats"]
+            "ttn_debug_tree_operator_stats", "ttn_get_step_solves"]
 
 
 class Options(C.Structure):
@@ -125,8 +125,9 @@ def _load():
         "ttn_batch_last_error": (C.c_char_p, [P]),
         "ttn_batch_destroy": (None, [P]),
         "ttn_workspace_size": (C.c_int32, [P, C.POINTER(C.c_size_t)]),
+        "ttn_get_step_solves": (C.c_int32, [P, C.c_int32, i32p, i32p, i32p, i32p]),
         "ttn_debug_tree_operator_stats": (C.c_int32, [C.c_int32, i32p, i32p, C.c_int32, i32p, i64p, dp, C.c_int32,
-                                                      dp, i64p, i32p, i32p, i32p]),
+                                                      dp, i64p, i32p, i32p, i32p, i32p, i32p]),
         "ttn_debug_hermiticity_defect": (C.c_int32, [C.c_int32, i32p, i32p, C.c_int32, i32p, i64p, dp, C.c_int32,
                                                      dp, i64p, i32p, dp]),
         "ttn_release_process_resources": (None, []),
@@ -190,19 +191,20 @@ def dense_tree_operator(problem, max_dim: int = 4096):
     return out.view(np.complex128).reshape(dim, dim), int(nent[0])
 
 
-def tree_operator_stats(problem):
-    """(channels on the bond above each node, operator entries of each node) of
-    the compiled tree operator (host only)."""
+def tree_operator_stats(problem) -> Dict[str, np.ndarray]:
+    """Per node of the compiled tree operator (host only): channels on the bond
+    above it, operator entries, products after the node-form compression, and
+    the plain-SOP terms crossing the bond above it."""
     parent = np.ascontiguousarray(problem.parent, dtype=np.int32)
     ld = np.ascontiguousarray(problem.local_dim, dtype=np.int32)
     op_leaf, off, data, coeff, tptr, tops = problem.flat_sop()
-    ch = np.zeros(len(parent), dtype=np.int32)
-    ent = np.zeros(len(parent), dtype=np.int32)
+    out = {k: np.zeros(len(parent), dtype=np.int32) for k in ("channels", "entries", "merged", "sop_terms")}
     _check(lib.ttn_debug_tree_operator_stats(
         len(parent), _ptr(parent, C.c_int32), _ptr(ld, C.c_int32), len(op_leaf), _ptr(op_leaf, C.c_int32),
         _ptr(off, C.c_int64), _ptr(data, C.c_double), len(problem.term_ops), _ptr(coeff, C.c_double),
-        _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32), _ptr(ch, C.c_int32), _ptr(ent, C.c_int32)))
-    return ch, ent
+        _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32), _ptr(out["channels"], C.c_int32),
+        _ptr(out["entries"], C.c_int32), _ptr(out["merged"], C.c_int32), _ptr(out["sop_terms"], C.c_int32)))
+    return out
 
 
 def hermiticity_defect(problem) -> float:
@@ -364,6 +366,16 @@ class TTN:
         b = C.c_size_t()
         self._c(lib.ttn_workspace_size(self.h, C.byref(b)))
         return int(b.value)
+
+    def step_solves(self):
+        """(node, forward flag, matvecs) of every local exponential of the last step."""
+        cap = 4 * self.n + 8
+        node, fwd, mv = (np.zeros(cap, dtype=np.int32) for _ in range(3))
+        n = C.c_int32()
+        self._c(lib.ttn_get_step_solves(self.h, cap, _ptr(node, C.c_int32), _ptr(fwd, C.c_int32),
+                                        _ptr(mv, C.c_int32), C.byref(n)))
+        k = min(n.value, cap)
+        return node[:k], fwd[:k], mv[:k]
 
     def bonds(self) -> np.ndarray:
         b = np.zeros(self.n, dtype=np.int32)

@@ -255,6 +255,15 @@ ttn_status ttn_get_info(ttn_t h, int32_t *effective_bond_dim, int64_t *counters)
     return guard(h, [&] { h->eng->info(effective_bond_dim, counters); });
 }
 
+ttn_status ttn_get_step_solves(ttn_t h, int32_t max_solves, int32_t *node, int32_t *forward, int32_t *matvecs,
+                               int32_t *n_solves) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] {
+        const int n = h->eng->step_solves(max_solves, node, forward, matvecs);
+        if (n_solves) *n_solves = n;
+    });
+}
+
 ttn_status ttn_workspace_size(ttn_t h, size_t *bytes) {
     if (!h || !bytes) return TTN_E_INVALID;
     *bytes = h->eng->workspace_need();
@@ -433,15 +442,52 @@ ttn_status ttn_debug_tree_operator_stats(int32_t n_nodes, const int32_t *parent,
                                          int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
                                          const double *op_data, int32_t n_terms, const double *coeff,
                                          const int64_t *term_ptr, const int32_t *term_ops, int32_t *n_channels,
-                                         int32_t *n_entries) {
+                                         int32_t *n_entries, int32_t *n_merged, int32_t *n_sop_terms) {
     return guard(nullptr, [&] {
         std::vector<int32_t> ones(n_nodes > 0 ? n_nodes : 1, 1);
         ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, ones.data());
         ttn::SopInput s = ttn::read_sop(t, n_ops, op_leaf, op_offset, op_data, n_terms, coeff, term_ptr, term_ops);
         ttn::TreeOp op = ttn::compile_tree_operator(t, s);
+        // leaves below every node
+        std::vector<std::vector<char>> below(t.n, std::vector<char>(t.n, 0));
+        for (int z : t.postorder) {
+            if (t.local_dim[z] > 0) below[z][z] = 1;
+            for (int c : t.kids[z])
+                for (int l = 0; l < t.n; ++l) below[z][l] |= below[c][l];
+        }
         for (int z = 0; z < t.n; ++z) {
             if (n_channels) n_channels[z] = op.n_ch[z];
             if (n_entries) n_entries[z] = (int32_t)op.entries[z].size();
+            if (n_merged) {  // the effective generator's products, as the engine builds them
+                const int D = (int)t.dims[z].size();
+                std::vector<ttn::MergeItem> items;
+                for (auto &e : op.entries[z]) {
+                    ttn::MergeItem it;
+                    for (int k = 0; k < D - 1; ++k)
+                        if (e.slot[k] >= 1) {
+                            it.slot[it.nf] = k;
+                            it.id[it.nf++] = (int64_t)k << 32 | e.slot[k];
+                        }
+                    if (z != t.root && e.bp != 1) {
+                        it.slot[it.nf] = D - 1;
+                        it.id[it.nf++] = (int64_t)(D - 1) << 32 | e.bp;
+                    }
+                    items.push_back(it);
+                }
+                int cnt = (int)items.size();
+                for (auto &m : ttn::plan_entry_merge(items)) cnt -= (int)m.members.size() - 1;
+                n_merged[z] = cnt;
+            }
+            if (n_sop_terms) {
+                int cnt = 0;
+                if (z != t.root)
+                    for (int r = 0; r < s.n_terms; ++r) {
+                        bool in = false, out = false;
+                        for (int o : s.term_ops[r]) (below[z][s.op_leaf[o]] ? in : out) = true;
+                        if (in && out) ++cnt;
+                    }
+                n_sop_terms[z] = cnt;
+            }
         }
     });
 }

@@ -490,4 +490,38 @@ TreeOp compile_tree_operator(const Tree &t, const SopInput &s) {
     return op;
 }
 
+// Greedy: every (item, position) gives a candidate key (group, number of
+// factors, position, slots, ids of the other factors); the largest candidate
+// sets are taken first and every item joins at most one set.
+std::vector<MergeSet> plan_entry_merge(const std::vector<MergeItem> &items) {
+    const int ne = (int)items.size();
+    std::map<std::vector<int64_t>, std::vector<int>> buckets;
+    for (int e = 0; e < ne; ++e) {
+        const MergeItem &E = items[e];
+        for (int f = 0; f < E.nf; ++f) {
+            std::vector<int64_t> key = {E.group, E.nf, f};
+            for (int g = 0; g < E.nf; ++g) {
+                key.push_back(E.slot[g]);
+                if (g != f) key.push_back(E.id[g]);
+            }
+            buckets[key].push_back(e);
+        }
+    }
+    std::vector<std::pair<int, const std::vector<int64_t> *>> order;
+    for (auto &kv : buckets)
+        if (kv.second.size() >= 2) order.push_back({(int)kv.second.size(), &kv.first});
+    std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::vector<char> used(ne, 0);
+    std::vector<MergeSet> out;
+    for (auto &o : order) {
+        MergeSet m{(int)(*o.second)[2], {}};
+        for (int e : buckets[*o.second])
+            if (!used[e]) m.members.push_back(e);
+        if (m.members.size() < 2) continue;
+        for (int e : m.members) used[e] = 1;
+        out.push_back(std::move(m));
+    }
+    return out;
+}
+
 }  // namespace ttn

@@ -25,6 +25,12 @@ struct Prog {
     DevEntry *d_ent = nullptr;
     int *d_gptr = nullptr, *d_gent = nullptr;
     double2 **d_gdst = nullptr;
+    // merged entries: their factor matrices are recombined before every use
+    std::vector<CombJob> cjobs;
+    std::vector<CombSrc> csrcs;
+    int comb_max_n2 = 0;
+    CombJob *d_cjobs = nullptr;
+    CombSrc *d_csrcs = nullptr;
 };
 
 class Engine {
@@ -48,6 +54,7 @@ public:
     void apply_root_heff(const double *x, double *y);
     void info(int32_t *bonds, int64_t *counters);
     size_t workspace_need() const { return ws_need; }
+    int step_solves(int max, int32_t *node, int32_t *fwd, int32_t *matvecs) const;
 
     Tree t;
     ttn_options opt;
@@ -90,6 +97,8 @@ private:
     void free_sop();
     Geom geom_of(const std::vector<int> &dims) const;
     void upload(Prog &p);
+    void merge_entries(Prog &p);
+    void prep(const Prog &p);
     ProgView view(const Prog &p) const;
     void build_programs();
     void rebuild_all_spos();

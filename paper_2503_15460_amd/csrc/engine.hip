@@ -130,6 +130,80 @@ void Engine::upload(Prog &p) {
     p.d_gdst = (double2 **)dalloc(sizeof(double2 *) * std::max<size_t>(1, p.gdst.size()));
     if (!p.gdst.empty())
         HIPCHK(hipMemcpy(p.d_gdst, p.gdst.data(), sizeof(double2 *) * p.gdst.size(), hipMemcpyHostToDevice));
+    if (!p.cjobs.empty()) {
+        p.d_cjobs = (CombJob *)dalloc(sizeof(CombJob) * p.cjobs.size());
+        HIPCHK(hipMemcpy(p.d_cjobs, p.cjobs.data(), sizeof(CombJob) * p.cjobs.size(), hipMemcpyHostToDevice));
+        p.d_csrcs = (CombSrc *)dalloc(sizeof(CombSrc) * p.csrcs.size());
+        HIPCHK(hipMemcpy(p.d_csrcs, p.csrcs.data(), sizeof(CombSrc) * p.csrcs.size(), hipMemcpyHostToDevice));
+    }
+}
+
+// Entries of one group that carry the same factors on every slot but one are
+// summed into a single entry whose factor on that slot is the coefficient-
+// weighted sum of theirs (the node form (B) + (C) of the hierarchical SOP:
+// sum_e c_e (x)_f M_ef = (x)_{f != s} M_f (x) (sum_e c_e M_es) when the other
+// factors coincide).  The summed factors are recombined on the device before
+// every use of the program (prep), since the environments they are made of
+// change during the sweep.
+void Engine::merge_entries(Prog &p) {
+    const int ne = (int)p.ents.size();
+    if (ne < 2) return;
+    std::vector<MergeItem> items(ne);
+    for (int e = 0; e < ne; ++e) {
+        const DevEntry &E = p.ents[e];
+        items[e].group = E.group;
+        items[e].nf = E.nf;
+        for (int f = 0; f < E.nf; ++f) {
+            items[e].slot[f] = E.slot[f];
+            items[e].id[f] = (int64_t)(intptr_t)E.M[f];
+        }
+    }
+    const std::vector<MergeSet> plan = plan_entry_merge(items);
+    if (plan.empty()) return;
+    std::vector<char> used(ne, 0);
+    std::vector<DevEntry> out;
+    size_t elems = 0;
+    for (auto &m : plan) {
+        const int n = p.g.dims[p.ents[m.members[0]].slot[m.f]];
+        elems += (size_t)n * n;
+    }
+    double2 *buf = (double2 *)dalloc(sizeof(double2) * elems);
+    size_t off = 0;
+    for (auto &m : plan) {
+        const int f = m.f;
+        DevEntry d = p.ents[m.members[0]];
+        const int n = p.g.dims[d.slot[f]];
+        d.coef = make_double2(1.0, 0.0);
+        int lo = 0, hi = 0;
+        bool dense = false;
+        CombJob j{};
+        j.dst = buf + off;
+        j.n2 = n * n;
+        j.first = (int)p.csrcs.size();
+        j.count = (int)m.members.size();
+        for (int e : m.members) {
+            used[e] = 1;
+            const DevEntry &E = p.ents[e];
+            if (E.lo[f] < 0 || E.hi[f] < 0) dense = true;  // unset band: dense
+            lo = std::max(lo, E.lo[f]);
+            hi = std::max(hi, E.hi[f]);
+            p.csrcs.push_back({E.coef, E.M[f]});
+        }
+        d.lo[f] = dense ? -1 : lo;
+        d.hi[f] = dense ? -1 : hi;
+        d.M[f] = j.dst;
+        p.cjobs.push_back(j);
+        p.comb_max_n2 = std::max(p.comb_max_n2, j.n2);
+        off += (size_t)j.n2;
+        out.push_back(d);
+    }
+    for (int e = 0; e < ne; ++e)
+        if (!used[e]) out.push_back(p.ents[e]);
+    p.ents.swap(out);
+}
+
+void Engine::prep(const Prog &p) {
+    if (!p.cjobs.empty()) launch_combine(p.d_cjobs, p.d_csrcs, (int)p.cjobs.size(), p.comb_max_n2, st);
 }
 
 ProgView Engine::view(const Prog &p) const {
@@ -257,6 +331,7 @@ void Engine::build_programs() {
             de.group = 0;
             h.ents.push_back(de);
         }
+        merge_entries(h);
         finish_groups(h, {nullptr});
         upload(h);
         if (!root) {
@@ -286,6 +361,7 @@ void Engine::build_programs() {
                 de.group = gid[e.bp];
                 s.ents.push_back(de);
             }
+            merge_entries(s);
             finish_groups(s, dst);
             upload(s);
             // backward bond generator K(C) = sum_b U_b C O_b^T on the bond above z
@@ -363,6 +439,7 @@ void Engine::build_programs() {
                     de.group = gid[ch];
                     m.ents.push_back(de);
                 }
+                merge_entries(m);
                 finish_groups(m, dst);
                 upload(m);
             }
@@ -639,6 +716,7 @@ void Engine::rebuild_all_spos() {
 
 // ------------------------------------------------------------ building blocks
 void Engine::apply_prog(const Prog &p, const double2 *in, double2 *out) {
+    prep(p);
     ProgView v = view(p);
     launch_prog_stages(v, in, st);
     launch_prog_sum(v, in, out, st);
@@ -647,6 +725,7 @@ void Engine::apply_prog(const Prog &p, const double2 *in, double2 *out) {
 void Engine::build_spo(int c) {
     const Prog &p = spoP[c];
     if (p.n_groups == 0) return;
+    prep(p);
     ProgView v = view(p);
     launch_prog_stages(v, A[c], st);
     launch_prog_sum(v, A[c], nullptr, st);
@@ -656,6 +735,7 @@ void Engine::build_spo(int c) {
 void Engine::build_mf(int z, int k) {
     const Prog &p = mfP[z][k];
     if (p.n_groups == 0) return;
+    prep(p);
     ProgView v = view(p);
     launch_prog_stages(v, A[z], st);
     launch_prog_sum(v, A[z], nullptr, st);
@@ -694,6 +774,7 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
     solve_small[si] = fused ? 1 : 0;
     SolveStat *stat = d_stats + si;
     const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP64 ? 1e-13 : 1e-10);
+    prep(p);
     if (fused) {
         SmallSolveArgs a{};
         a.g = p.g;
@@ -1132,6 +1213,16 @@ void debug_qr(int64_t rows, int cols, const double *m, int variant, double *q_ou
         throw;
     }
     for (void *p : mem) (void)hipFree(p);
+}
+
+int Engine::step_solves(int max, int32_t *node, int32_t *fwd, int32_t *matvecs) const {
+    if (counters[0] == 0 || !h_stats) throw Error(TTN_E_STATE, "no completed step");
+    for (int i = 0; i < solve_idx && i < max; ++i) {
+        if (node) node[i] = solve_node[i];
+        if (fwd) fwd[i] = solve_fwd[i];
+        if (matvecs) matvecs[i] = h_stats[i].matvecs;
+    }
+    return solve_idx;
 }
 
 void Engine::info(int32_t *bonds, int64_t *ctr) {

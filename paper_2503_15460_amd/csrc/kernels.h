@@ -44,6 +44,20 @@ struct DevEntry {
     const double2 *M[MAXF];
 };
 
+// Linear combination of factor matrices, dst = sum_q coef_q src_q (n2
+// elements each): the factor of a merged operator entry (entries equal in all
+// factors but one are summed into one entry before a program is applied).
+struct CombJob {
+    double2 *dst;
+    int n2;     // elements of the matrix
+    int first;  // sources srcs[first .. first + count)
+    int count;
+};
+struct CombSrc {
+    double2 coef;
+    const double2 *src;
+};
+
 // Grouped application of entries to a tensor (H_eff matvec, K_eff matvec,
 // SPO / mean-field rebuilds).  Device tables are owned by the engine.
 struct ProgView {
@@ -175,6 +189,7 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
                     hipStream_t st);
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st);
 void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st);
+void launch_combine(const CombJob *jobs, const CombSrc *srcs, int n_jobs, int max_n2, hipStream_t st);
 void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st);
 
 // multi-kernel Krylov pieces

@@ -1884,6 +1884,18 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_combine(BigKrylov k, uint32
 }
 
 // ============================================================ misc
+__global__ void __launch_bounds__(256) k_combine(const CombJob *__restrict__ jobs, const CombSrc *__restrict__ srcs) {
+    const CombJob J = jobs[blockIdx.y];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < J.n2; i += gridDim.x * blockDim.x) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int q = 0; q < J.count; ++q) {
+            const CombSrc S = srcs[J.first + q];
+            cfma(acc, S.coef, S.src[i]);
+        }
+        J.dst[i] = acc;
+    }
+}
+
 __global__ void k_copy(double2 *dst, const double2 *src, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
 }
@@ -2282,6 +2294,12 @@ void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
 
 void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st) {
     TTN_LAUNCH("k_copy", 0.0, 32.0 * n, k_copy, dim3(grid_for(n, 256)), dim3(256), 0, st, dst, src, (uint32_t)n);
+}
+
+void launch_combine(const CombJob *jobs, const CombSrc *srcs, int n_jobs, int max_n2, hipStream_t st) {
+    if (n_jobs <= 0) return;
+    TTN_LAUNCH("k_combine", 0.0, 32.0 * max_n2 * n_jobs, k_combine, dim3(grid_for(max_n2, 256, 64), n_jobs),
+               dim3(256), 0, st, jobs, srcs);
 }
 
 void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st) {

@@ -83,4 +83,22 @@ bool sop_is_hermitian(const SopInput &s, double rtol = 1e-7);
 
 TreeOp compile_tree_operator(const Tree &t, const SopInput &s);
 
+// Node form of the operator (Sec. II B 2, terms (B) and (C)): products that
+// share every factor but one are summed into one product whose remaining
+// factor is the coefficient-weighted sum of theirs.  An item is one product:
+// its group (products of different groups are never combined), and per
+// factor position f the tensor slot and an identity of the factor (equal ids
+// mean the same matrix).  The plan lists the sets to combine, each with the
+// factor position f that is summed; items in no set stay as they are.
+struct MergeItem {
+    int group = 0, nf = 0;
+    int slot[8] = {0};
+    int64_t id[8] = {0};
+};
+struct MergeSet {
+    int f;
+    std::vector<int> members;
+};
+std::vector<MergeSet> plan_entry_merge(const std::vector<MergeItem> &items);
+
 }  // namespace ttn

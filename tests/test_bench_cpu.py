@@ -16,8 +16,8 @@ def _row(name, calls, ms, flops, byts):
 
 def test_roofline_takes_the_kernel_with_the_largest_total_time():
     stats = [_row("k_mode_tile", 100, 2.0, 1e9, 3e8), _row("k_qr_coop", 10, 3.0, 1.2e8, 2.2e7)]
-    r = bench.roofline(stats)
-    assert r["kernel"] == "k_qr_coop"
+    r = bench.roofline(stats, 2, "vibronic24")
+    assert r["kernel"] == "k_qr_coop" and r["launches_per_step"] == 5
     assert abs(r["avg_launch_us"] - 300.0) < 1e-9
     # intensity 5.5 flop/B is below the FP64 ridge (78.6 TF / 8 TB/s = 9.8): HBM bound
     assert r["bound"] == "hbm" and r["unit"] == "GB/s"
@@ -26,27 +26,39 @@ def test_roofline_takes_the_kernel_with_the_largest_total_time():
 
 
 def test_roofline_compute_bound_classes():
-    # no modelled bytes: compute bound; plain FP64 vector code reports "alu"
-    r = bench.roofline([_row("k_small_solve", 10, 1.0, 1e7, 0.0)])
+    # no modelled bytes: compute bound; plain FP64 vector code reports "alu" at the FP64 peak
+    r = bench.roofline([_row("k_small_solve", 10, 1.0, 1e7, 0.0)], 1, "x")
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == bench.PEAK_FP64_TFLOPS
-    r = bench.roofline([_row("k_some_mfma_kernel", 10, 1.0, 1e9, 1e6)])
-    assert r["bound"] == "mfma"
+    # FP32 vector code against the FP32 peak, the bf16 matrix-core stage against the bf16 peak
+    r = bench.roofline([_row("k_mode_tile_f32", 10, 1.0, 1e10, 1e7)], 1, "x")
+    assert r["bound"] == "alu" and r["peak"] == bench.PEAK_FP32_TFLOPS
+    r = bench.roofline([_row("k_mode_mfma", 10, 1.0, 1e11, 1e7)], 1, "x")
+    assert r["bound"] == "mfma" and r["peak"] == bench.PEAK_BF16_TFLOPS
+    # below the bf16 ridge (312 flop/B) the same kernel is HBM bound
+    r = bench.roofline([_row("k_mode_mfma", 10, 1.0, 1e9, 1e7)], 1, "x")
+    assert r["bound"] == "hbm"
 
 
 def test_traffic_record_follows_the_kernel_sources():
-    path = os.path.join(ROOT, "profiles", "k_qr_coop_vibronic24_hbm_traffic.md")
-    rec = None
-    for line in open(path):
-        if line.startswith("traffic: "):
-            rec = json.loads(line[len("traffic: "):])
-    assert rec is not None and rec["kernel"] == "k_qr_coop"
-    got = bench.measured_traffic("k_qr_coop")
     import hashlib
     src = os.path.join(ROOT, "paper_2503_15460_amd", "csrc", "kernels.hip")
-    same = hashlib.sha256(open(src, "rb").read()).hexdigest() == rec["kernels_hip_sha256"]
-    assert got == (rec["bytes_per_launch"] if same else None)
-    assert abs(rec["bytes_per_launch"] - rec["fetch_bytes_per_launch"] - rec["write_bytes_per_launch"]) <= 1
-    assert bench.measured_traffic("no_such_kernel") is None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    found = 0
+    for fn in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
+        if not fn.endswith("_hbm_traffic.md"):
+            continue
+        rec = None
+        for line in open(os.path.join(ROOT, "profiles", fn)):
+            if line.startswith("traffic: "):
+                rec = json.loads(line[len("traffic: "):])
+        assert rec is not None, fn
+        workload = rec["workload"]
+        got = bench.measured_traffic(rec["kernel"], workload)
+        assert got == (rec["bytes_per_launch"] if sha == rec["kernels_hip_sha256"] else None)
+        assert abs(rec["bytes_per_launch"] - rec["fetch_bytes_per_launch"] - rec["write_bytes_per_launch"]) <= 1
+        found += 1
+    assert found >= 1
+    assert bench.measured_traffic("no_such_kernel", "vibronic24") is None
 
 
 def test_more_than_one_gpu_is_refused():
