@@ -31,7 +31,7 @@ EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product
             "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end",
             "ttn_batch_create", "ttn_batch_step", "ttn_batch_last_error", "ttn_batch_destroy",
             "ttn_workspace_size", "ttn_release_process_resources", "ttn_debug_hermiticity_defect",
-            "ttn_debug_tree_operator_stats", "ttn_get_step_solves"]
+            "ttn_debug_tree_operator_stats", "ttn_get_step_solves", "ttn_qr_noalloc", "ttn_qr_noalloc_last_error"]
 
 
 class Options(C.Structure):

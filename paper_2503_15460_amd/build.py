@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libttn.so")
-SOURCES = ["compile.cpp", "api.cpp", "engine.hip", "kernels.hip"]
+SOURCES = ["compile.cpp", "api.cpp", "engine.hip", "kernels.hip", "noalloc.hip"]
 ARCH = os.environ.get("TTN_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
