@@ -96,10 +96,25 @@ typedef struct {
                                workspace_bytes is below what the operator needs
                                (ttn_workspace_size reports it, also after that failure). */
     size_t workspace_bytes; /* size of `workspace` in bytes */
-    int32_t use_graph;      /* reserved, must be 0 */
-    int32_t autotune;       /* reserved, must be 0 */
+    int32_t use_graph;      /* 1: each step is captured into a hipGraph once per (dt, Krylov dimension
+                               hints) and replayed from then on (one graph launch per step instead
+                               of hundreds of kernel launches); the gauge QRs then take the
+                               non-cooperative kernels.  A NULL hip_stream is replaced by a stream
+                               of the handle's own.  Not with spawn_tol > 0 (TTN_E_INVALID). */
+    int32_t autotune;       /* 1: ttn_set_sop times every register tile of the tiled operator stages on
+                               the handle's own programs and records the fastest in the process-wide
+                               tile table (see ttn_tile_table_*); stages already in the table are not
+                               timed again.  Results do not depend on the tile. */
     int32_t device;         /* HIP device ordinal */
-    uint64_t seed;          /* reserved (the sweep draws no random numbers) */
+    uint64_t seed;          /* seeds the start vectors of the subspace expansion's Krylov iteration */
+    double spawn_tol;       /* subspace expansion (Sec. II D): 0 = fixed bonds; > 0: when the sweep
+                               crosses a bond, new single-particle functions (going up) or single
+                               hole functions (going down) are added with zero coefficients along
+                               the dominant singular vectors sigma_s of the two-site residual
+                               while |dt/2| sigma_s >= spawn_tol, up to bond_max */
+    const int32_t *bond_max;/* [n_nodes] largest bond each bond may grow to (read by ttn_create,
+                               clamped like bond_dim; NULL: no growth).  Device memory is
+                               allocated for these bonds from the start. */
 } ttn_options;
 
 /* Fill *opt with the defaults (FP64, tol 0 = the precision's default, mmax 40,
@@ -256,6 +271,15 @@ ttn_status ttn_profile_end(ttn_kernel_stat *rows, int32_t max_rows, int32_t *n_r
  */
 ttn_status ttn_batch_create(int32_t n, ttn_t const *insts, int32_t n_streams, ttn_batch_t *out);
 ttn_status ttn_batch_step(ttn_batch_t b, const double *dt, int32_t n_steps);
+/* Lockstep mode (on = 1; 0 returns to the streams): every instance runs on the
+ * batch's first stream and a step proceeds in sweep layers, layer j running
+ * the j-th operation (QR with its environment update, local exponential,
+ * absorption) of every instance's sweep; the layer's local exponentials that
+ * fit the fused one-work-group solver go out as ONE grouped launch (one
+ * work-group per instance).  Results are those of ttn_step on each instance.
+ * Not with subspace expansion.  After a device error every instance of the
+ * batch is unusable.  Errors: TTN_E_INVALID, TTN_E_DEVICE. */
+ttn_status ttn_batch_set_lockstep(ttn_batch_t b, int32_t on);
 const char *ttn_batch_last_error(ttn_batch_t b);
 void ttn_batch_destroy(ttn_batch_t b);
 
@@ -265,6 +289,17 @@ const char *ttn_last_error(ttn_t h);
 
 /* Release all resources of the handle. */
 void ttn_destroy(ttn_t h);
+
+/* The process-wide tile table of the operator stages (filled by autotune = 1,
+ * consulted by every handle): save writes it as JSON (one entry per line:
+ * ["shape key", rows per thread, row groups, microseconds]), load merges such a
+ * file into it (entries with tiles this build lacks are skipped) and returns
+ * the number read, clear empties it.  Host only.
+ * Errors: TTN_E_INVALID (file cannot be opened). */
+ttn_status ttn_tile_table_save(const char *path);
+ttn_status ttn_tile_table_load(const char *path, int32_t *n_loaded);
+ttn_status ttn_tile_table_size(int64_t *n_entries);
+void ttn_tile_table_clear(void);
 
 /* Release the library's process-wide device resources (the launch profiler's
  * clock slots and event pool).  Call after destroying every handle and before

@@ -51,6 +51,10 @@ ttn_status ttn_debug_tree_operator_stats(int32_t n_nodes, const int32_t *parent,
                                          const int64_t *term_ptr, const int32_t *term_ops, int32_t *n_channels,
                                          int32_t *n_entries, int32_t *n_merged, int32_t *n_sop_terms);
 
+/* Number of step graphs a handle with use_graph = 1 has captured so far (a
+ * replayed step captures nothing).  Errors: TTN_E_INVALID. */
+ttn_status ttn_debug_graph_captures(ttn_t h, int64_t *captures);
+
 /* Effective (clamped) bond dimensions for a tree, host only.
  * Errors: TTN_E_TREE, TTN_E_DIMS. */
 ttn_status ttn_debug_clamp_bonds(int32_t n_nodes, const int32_t *parent, const int32_t *local_dim,

@@ -31,14 +31,17 @@ EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product
             "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end",
             "ttn_batch_create", "ttn_batch_step", "ttn_batch_last_error", "ttn_batch_destroy",
             "ttn_workspace_size", "ttn_release_process_resources", "ttn_debug_hermiticity_defect",
-            "ttn_debug_tree_operator_stats", "ttn_get_step_solves", "ttn_qr_noalloc", "ttn_qr_noalloc_last_error"]
+            "ttn_debug_tree_operator_stats", "ttn_get_step_solves", "ttn_qr_noalloc", "ttn_qr_noalloc_last_error",
+            "ttn_tile_table_save", "ttn_tile_table_load", "ttn_tile_table_size", "ttn_tile_table_clear",
+            "ttn_debug_graph_captures", "ttn_batch_set_lockstep"]
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("krylov_tol", C.c_double), ("krylov_mmax", C.c_int32),
                 ("hermitian", C.c_int32), ("hip_stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("use_graph", C.c_int32), ("autotune", C.c_int32),
-                ("device", C.c_int32), ("seed", C.c_uint64)]
+                ("device", C.c_int32), ("seed", C.c_uint64), ("spawn_tol", C.c_double),
+                ("bond_max", C.POINTER(C.c_int32))]
 
 
 class KernelStat(C.Structure):
@@ -126,6 +129,12 @@ def _load():
         "ttn_batch_destroy": (None, [P]),
         "ttn_workspace_size": (C.c_int32, [P, C.POINTER(C.c_size_t)]),
         "ttn_get_step_solves": (C.c_int32, [P, C.c_int32, i32p, i32p, i32p, i32p]),
+        "ttn_tile_table_save": (C.c_int32, [C.c_char_p]),
+        "ttn_tile_table_load": (C.c_int32, [C.c_char_p, i32p]),
+        "ttn_tile_table_size": (C.c_int32, [i64p]),
+        "ttn_tile_table_clear": (None, []),
+        "ttn_debug_graph_captures": (C.c_int32, [P, i64p]),
+        "ttn_batch_set_lockstep": (C.c_int32, [P, C.c_int32]),
         "ttn_debug_tree_operator_stats": (C.c_int32, [C.c_int32, i32p, i32p, C.c_int32, i32p, i64p, dp, C.c_int32,
                                                       dp, i64p, i32p, i32p, i32p, i32p, i32p]),
         "ttn_debug_hermiticity_defect": (C.c_int32, [C.c_int32, i32p, i32p, C.c_int32, i32p, i64p, dp, C.c_int32,
@@ -207,6 +216,28 @@ def tree_operator_stats(problem) -> Dict[str, np.ndarray]:
     return out
 
 
+def tile_table_save(path: str) -> None:
+    """Write the process-wide tile table (autotuner results) as JSON."""
+    _check(lib.ttn_tile_table_save(os.fsencode(path)))
+
+
+def tile_table_load(path: str) -> int:
+    """Merge a saved tile table into the process-wide one; returns the entries read."""
+    n = C.c_int32()
+    _check(lib.ttn_tile_table_load(os.fsencode(path), C.byref(n)))
+    return int(n.value)
+
+
+def tile_table_size() -> int:
+    n = C.c_int64()
+    _check(lib.ttn_tile_table_size(C.byref(n)))
+    return int(n.value)
+
+
+def tile_table_clear() -> None:
+    lib.ttn_tile_table_clear()
+
+
 def hermiticity_defect(problem) -> float:
     """||G - G^dag||_F / ||G||_F as the library checks it (host only)."""
     parent = np.ascontiguousarray(problem.parent, dtype=np.int32)
@@ -275,7 +306,8 @@ class TTN:
 
     def __init__(self, parent, local_dim, bond_dim, precision: int = TTN_FP64, krylov_tol: float = 0.0,
                  krylov_mmax: int = 40, hermitian: bool = True, stream: Optional[int] = None, device: int = 0,
-                 workspace: Optional[Tuple[int, int]] = None):
+                 workspace: Optional[Tuple[int, int]] = None, spawn_tol: float = 0.0, bond_max=None,
+                 seed: int = 0, autotune: bool = False, use_graph: bool = False):
         self.parent = np.ascontiguousarray(parent, dtype=np.int32)
         self.local_dim = np.ascontiguousarray(local_dim, dtype=np.int32)
         bond = np.ascontiguousarray(bond_dim, dtype=np.int32)
@@ -290,6 +322,13 @@ class TTN:
         if workspace is not None:  # (device pointer, bytes), caller-owned
             opt.workspace = int(workspace[0])
             opt.workspace_bytes = int(workspace[1])
+        opt.spawn_tol = float(spawn_tol)
+        opt.autotune = 1 if autotune else 0
+        opt.use_graph = 1 if use_graph else 0
+        opt.seed = int(seed)
+        if bond_max is not None:  # subspace expansion: per-node largest bonds
+            bm = np.ascontiguousarray(np.broadcast_to(np.asarray(bond_max, dtype=np.int32), self.parent.shape))
+            opt.bond_max = _ptr(bm, C.c_int32)
         h = C.c_void_p()
         _check(lib.ttn_create(len(self.parent), _ptr(self.parent, C.c_int32), _ptr(self.local_dim, C.c_int32),
                               _ptr(bond, C.c_int32), C.byref(opt), C.byref(h)))
@@ -377,6 +416,12 @@ class TTN:
         k = min(n.value, cap)
         return node[:k], fwd[:k], mv[:k]
 
+    def graph_captures(self) -> int:
+        """Step graphs captured so far (use_graph handles)."""
+        n = C.c_int64()
+        self._c(lib.ttn_debug_graph_captures(self.h, C.byref(n)))
+        return int(n.value)
+
     def bonds(self) -> np.ndarray:
         b = np.zeros(self.n, dtype=np.int32)
         self._c(lib.ttn_get_info(self.h, _ptr(b, C.c_int32), None))
@@ -422,7 +467,7 @@ class TTNBatch:
     the device through the batch's HIP streams.  The TTN objects stay usable
     (observables, states) and must outlive the batch."""
 
-    def __init__(self, insts: Sequence[TTN], n_streams: int = 0):
+    def __init__(self, insts: Sequence[TTN], n_streams: int = 0, lockstep: bool = False):
         self.insts = list(insts)
         arr = (C.c_void_p * len(self.insts))(*[t.h.value if isinstance(t.h, C.c_void_p) else t.h
                                                for t in self.insts])
@@ -432,6 +477,10 @@ class TTNBatch:
             raise TTNError(code, lib.ttn_batch_last_error(None).decode())
         self.h = h
         _LIVE.add(self)
+        if lockstep:
+            code = lib.ttn_batch_set_lockstep(self.h, 1)
+            if code != TTN_OK:
+                raise TTNError(code, lib.ttn_batch_last_error(None).decode())
 
     def step(self, dt, n_steps: int = 1):
         dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (len(self.insts),)))

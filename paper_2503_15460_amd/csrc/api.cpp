@@ -1,5 +1,6 @@
 // C boundary of the library: argument checks, handle management and the
 // conversion of exceptions into ttn_status codes.
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <functional>
@@ -27,6 +28,15 @@ struct ttn_batch_ctx {
     std::vector<hipStream_t> own;      // each instance's stream before joining
     std::vector<hipStream_t> streams;  // created by the batch, default priority
     std::string err;
+    // lockstep: every instance on streams[0]; layer j of a step runs the j-th
+    // operation of every instance's sweep, its fused solves as one launch
+    bool lockstep = false;
+    ttn::SmallSolveArgs *h_args = nullptr, *d_args = nullptr;  // pinned host / device argument arrays
+    size_t args_cap = 0;
+    ~ttn_batch_ctx() {
+        if (h_args) (void)hipHostFree(h_args);
+        if (d_args) (void)hipFree(d_args);
+    }
 };
 
 namespace {
@@ -95,10 +105,16 @@ ttn_status ttn_create(int32_t n_nodes, const int32_t *parent, const int32_t *loc
         if (opt) o = *opt;
         if (o.precision != TTN_FP64 && o.precision != TTN_FP32 && o.precision != TTN_BF16X3)
             throw ttn::Error(TTN_E_INVALID, "precision must be TTN_FP64, TTN_FP32 or TTN_BF16X3");
-        if (o.use_graph != 0 || o.autotune != 0) throw ttn::Error(TTN_E_INVALID, "use_graph and autotune must be 0");
+        if (o.use_graph != 0 && o.use_graph != 1) throw ttn::Error(TTN_E_INVALID, "use_graph must be 0 or 1");
+        if (o.use_graph && o.spawn_tol > 0.0)
+            throw ttn::Error(TTN_E_INVALID, "use_graph cannot be combined with subspace expansion");
+        if (o.autotune != 0 && o.autotune != 1) throw ttn::Error(TTN_E_INVALID, "autotune must be 0 or 1");
         if (o.workspace && ((uintptr_t)o.workspace % 256 != 0))
             throw ttn::Error(TTN_E_INVALID, "workspace must be 256-byte aligned");
-        ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, bond_dim);
+        if (!(o.spawn_tol >= 0.0) || !std::isfinite(o.spawn_tol))
+            throw ttn::Error(TTN_E_INVALID, "spawn_tol must be finite and >= 0");
+        ttn::Tree t = ttn::build_tree(n_nodes, parent, local_dim, bond_dim, o.bond_max);
+        o.bond_max = nullptr;  // copied into the tree; no caller pointer is kept
         auto h = std::make_unique<ttn_ctx>();
         h->eng = std::make_unique<ttn::Engine>(t, o);
         *out = h.release();
@@ -170,6 +186,65 @@ ttn_status ttn_batch_create(int32_t n, ttn_t const *insts, int32_t n_streams, tt
     });
 }
 
+ttn_status ttn_batch_set_lockstep(ttn_batch_t b, int32_t on) {
+    if (!b) return TTN_E_INVALID;
+    return guard(nullptr, [&] {
+        for (auto *h : b->insts)
+            if (h->dead) throw ttn::Error(TTN_E_DEVICE, "instance unusable after a device error");
+        b->lockstep = on != 0;
+        for (size_t i = 0; i < b->insts.size(); ++i)
+            b->insts[i]->eng->set_stream(b->lockstep ? b->streams[0] : b->streams[i % b->streams.size()]);
+    });
+}
+
+// One lockstep step of every instance: the schedules are recorded, then run
+// layer by layer; each layer's fused solves go out as one grouped launch.
+static void lockstep_step(ttn_batch_t b, const double *dt, int &cur) {
+    const int n = (int)b->insts.size();
+    std::vector<std::vector<std::function<void()>>> sched(n);
+    size_t L = 0;
+    for (cur = 0; cur < n; ++cur) {
+        sweep_guard([&] { sched[cur] = b->insts[cur]->eng->record_step(dt[cur]); });
+        L = std::max(L, sched[cur].size());
+    }
+    const size_t need = L * (size_t)n;
+    if (need > b->args_cap) {
+        if (b->h_args) (void)hipHostFree(b->h_args);
+        if (b->d_args) (void)hipFree(b->d_args);
+        b->h_args = b->d_args = nullptr;
+        b->args_cap = 0;
+        if (hipHostMalloc((void **)&b->h_args, sizeof(ttn::SmallSolveArgs) * need, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipMalloc((void **)&b->d_args, sizeof(ttn::SmallSolveArgs) * need) != hipSuccess)
+            throw ttn::Error(TTN_E_OOM, "lockstep argument arrays");
+        b->args_cap = need;
+    }
+    hipStream_t st = b->streams[0];
+    size_t used = 0;
+    std::vector<ttn::SmallSolveArgs> grp;
+    for (size_t j = 0; j < L; ++j) {
+        grp.clear();
+        for (cur = 0; cur < n; ++cur) {
+            if (j >= sched[cur].size()) continue;
+            ttn::Engine &e = *b->insts[cur]->eng;
+            e.defer_fused = true;
+            e.deferred.clear();
+            sweep_guard([&] { sched[cur][j](); });
+            e.defer_fused = false;
+            grp.insert(grp.end(), e.deferred.begin(), e.deferred.end());
+        }
+        cur = -1;
+        if (grp.empty()) continue;
+        std::memcpy(b->h_args + used, grp.data(), sizeof(ttn::SmallSolveArgs) * grp.size());
+        if (hipMemcpyAsync(b->d_args + used, b->h_args + used, sizeof(ttn::SmallSolveArgs) * grp.size(),
+                           hipMemcpyHostToDevice, st) != hipSuccess)
+            throw ttn::Error(TTN_E_DEVICE, "lockstep argument upload");
+        sweep_guard([&] { ttn::launch_small_solve_group(b->d_args + used, grp, st); });
+        used += grp.size();
+    }
+    for (cur = 0; cur < n; ++cur) sweep_guard([&] { b->insts[cur]->eng->finish_record(); });
+}
+
 ttn_status ttn_batch_step(ttn_batch_t b, const double *dt, int32_t n_steps) {
     if (!b) return TTN_E_INVALID;
     const int n = (int)b->insts.size();
@@ -181,7 +256,17 @@ ttn_status ttn_batch_step(ttn_batch_t b, const double *dt, int32_t n_steps) {
             if (b->insts[i]->dead) throw ttn::Error(TTN_E_DEVICE, "instance unusable after a device error");
         for (cur = 0; cur < n; ++cur) b->insts[cur]->eng->check_ready(dt[cur]);
         for (int s = 0; s < n_steps; ++s) {
-            for (cur = 0; cur < n; ++cur) sweep_guard([&] { b->insts[cur]->eng->enqueue_step(dt[cur]); });
+            if (b->lockstep) {
+                try {
+                    lockstep_step(b, dt, cur);
+                } catch (const ttn::Error &e) {
+                    if (e.code == TTN_E_DEVICE)  // schedules of every instance may be half run
+                        for (auto *h : b->insts) h->dead = true;
+                    throw;
+                }
+            } else {
+                for (cur = 0; cur < n; ++cur) sweep_guard([&] { b->insts[cur]->eng->enqueue_step(dt[cur]); });
+            }
             // finish every instance (each one's bookkeeping stays consistent), then report the first error
             int bad = -1;
             ttn_status bad_code = TTN_OK;
@@ -264,11 +349,49 @@ ttn_status ttn_get_step_solves(ttn_t h, int32_t max_solves, int32_t *node, int32
     });
 }
 
+ttn_status ttn_debug_graph_captures(ttn_t h, int64_t *captures) {
+    if (!h || !captures) return TTN_E_INVALID;
+    *captures = h->eng->graph_captures();
+    return TTN_OK;
+}
+
 ttn_status ttn_workspace_size(ttn_t h, size_t *bytes) {
     if (!h || !bytes) return TTN_E_INVALID;
     *bytes = h->eng->workspace_need();
     return TTN_OK;
 }
+
+ttn_status ttn_tile_table_save(const char *path) {
+    return guard(nullptr, [&] {
+        if (!path) throw ttn::Error(TTN_E_INVALID, "null path");
+        try {
+            ttn::tile_table_save(path);
+        } catch (const std::runtime_error &e) {
+            throw ttn::Error(TTN_E_INVALID, e.what());
+        }
+    });
+}
+
+ttn_status ttn_tile_table_load(const char *path, int32_t *n_loaded) {
+    return guard(nullptr, [&] {
+        if (!path) throw ttn::Error(TTN_E_INVALID, "null path");
+        int n = 0;
+        try {
+            n = ttn::tile_table_load(path);
+        } catch (const std::runtime_error &e) {
+            throw ttn::Error(TTN_E_INVALID, e.what());
+        }
+        if (n_loaded) *n_loaded = n;
+    });
+}
+
+ttn_status ttn_tile_table_size(int64_t *n_entries) {
+    if (!n_entries) return TTN_E_INVALID;
+    *n_entries = (int64_t)ttn::tile_table_size();
+    return TTN_OK;
+}
+
+void ttn_tile_table_clear(void) { ttn::tile_table_clear(); }
 
 void ttn_release_process_resources(void) {
     try {

@@ -15,7 +15,22 @@
 
 namespace ttn {
 
-Tree build_tree(int n, const int32_t *parent, const int32_t *local_dim, const int32_t *bond_req) {
+void Tree::update_dims() {
+    dims.assign(n, {});
+    size.assign(n, 0);
+    for (int z = 0; z < n; ++z) {
+        if (local_dim[z] > 0) dims[z].push_back(local_dim[z]);
+        else
+            for (int c : kids[z]) dims[z].push_back(bond[c]);
+        dims[z].push_back(z == root ? 1 : bond[z]);
+        int64_t s = 1;
+        for (int d : dims[z]) s *= d;
+        size[z] = s;
+    }
+}
+
+Tree build_tree(int n, const int32_t *parent, const int32_t *local_dim, const int32_t *bond_req,
+                const int32_t *bond_max) {
     if (n < 2 || !parent || !local_dim || !bond_req) throw Error(TTN_E_TREE, "need at least 2 nodes");
     Tree t;
     t.n = n;
@@ -75,47 +90,52 @@ Tree build_tree(int n, const int32_t *parent, const int32_t *local_dim, const in
             inside[z] = p;
         }
     }
-    double total = inside[t.root];
-    std::vector<int> b(n, 1);
-    for (int c = 0; c < n; ++c) {
-        if (c == t.root) continue;
-        double v = std::min({(double)bond_req[c], inside[c], total / inside[c]});
-        b[c] = (int)v;
-    }
-    // lower each bond to the product of the other indices at both end nodes
-    bool changed = true;
-    while (changed) {
-        changed = false;
-        for (int z = 0; z < n; ++z) {
-            std::vector<std::pair<int, int>> inc;  // (owner or -1, dim), snapshot
-            if (t.local_dim[z] > 0) inc.push_back({-1, t.local_dim[z]});
-            else
-                for (int c : t.kids[z]) inc.push_back({c, b[c]});
-            if (z != t.root) inc.push_back({z, b[z]});
-            for (size_t i = 0; i < inc.size(); ++i) {
-                if (inc[i].first < 0) continue;
-                double other = 1.0;
-                for (size_t j = 0; j < inc.size(); ++j)
-                    if (j != i) other *= inc[j].second;
-                if ((double)inc[i].second > other) {
-                    b[inc[i].first] = (int)other;
-                    changed = true;
+    const double total = inside[t.root];
+    auto clamp = [&](const int32_t *req) {
+        std::vector<int> b(n, 1);
+        for (int c = 0; c < n; ++c) {
+            if (c == t.root) continue;
+            double v = std::min({(double)req[c], inside[c], total / inside[c]});
+            b[c] = (int)v;
+        }
+        // lower each bond to the product of the other indices at both end nodes
+        bool changed = true;
+        while (changed) {
+            changed = false;
+            for (int z = 0; z < n; ++z) {
+                std::vector<std::pair<int, int>> inc;  // (owner or -1, dim), snapshot
+                if (t.local_dim[z] > 0) inc.push_back({-1, t.local_dim[z]});
+                else
+                    for (int c : t.kids[z]) inc.push_back({c, b[c]});
+                if (z != t.root) inc.push_back({z, b[z]});
+                for (size_t i = 0; i < inc.size(); ++i) {
+                    if (inc[i].first < 0) continue;
+                    double other = 1.0;
+                    for (size_t j = 0; j < inc.size(); ++j)
+                        if (j != i) other *= inc[j].second;
+                    if ((double)inc[i].second > other) {
+                        b[inc[i].first] = (int)other;
+                        changed = true;
+                    }
                 }
             }
         }
+        return b;
+    };
+    t.bond = clamp(bond_req);
+    t.cap = t.bond;
+    if (bond_max) {
+        for (int z = 0; z < n; ++z)
+            if (z != t.root && bond_max[z] < 1) throw Error(TTN_E_DIMS, "bond_max must be >= 1");
+        std::vector<int> c = clamp(bond_max);
+        for (int z = 0; z < n; ++z) t.cap[z] = std::max(t.bond[z], c[z]);
     }
-    t.bond = b;
-    t.dims.assign(n, {});
-    t.size.assign(n, 0);
-    for (int z = 0; z < n; ++z) {
-        if (t.local_dim[z] > 0) t.dims[z].push_back(t.local_dim[z]);
-        else
-            for (int c : t.kids[z]) t.dims[z].push_back(t.bond[c]);
-        t.dims[z].push_back(z == t.root ? 1 : t.bond[z]);
-        int64_t s = 1;
-        for (int d : t.dims[z]) s *= d;
-        t.size[z] = s;
-    }
+    std::swap(t.bond, t.cap);  // shapes at capacity first
+    t.update_dims();
+    t.capdims = t.dims;
+    t.capsize = t.size;
+    std::swap(t.bond, t.cap);
+    t.update_dims();
     return t;
 }
 

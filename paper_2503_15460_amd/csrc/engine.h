@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -25,7 +26,9 @@ struct Prog {
     DevEntry *d_ent = nullptr;
     int *d_gptr = nullptr, *d_gent = nullptr;
     double2 **d_gdst = nullptr;
+    int capdims[MAXD] = {0};  // slot dims at the bond capacity (buffers are sized for them)
     // merged entries: their factor matrices are recombined before every use
+    std::vector<double2 *> comb_bufs;  // one per summed factor, sized for the capacity
     std::vector<CombJob> cjobs;
     std::vector<CombSrc> csrcs;
     int comb_max_n2 = 0;
@@ -48,12 +51,20 @@ public:
     void enqueue_step(double dt);
     void finish_step(double dt);
     void set_stream(hipStream_t s);
+    // lockstep batches: the operations of one step as a schedule (snapshot
+    // already enqueued); fused solves met while defer_fused is set are left in
+    // `deferred` for a grouped launch; finish_record enqueues the statistics
+    std::vector<std::function<void()>> record_step(double dt);
+    void finish_record();
+    bool defer_fused = false;
+    std::vector<SmallSolveArgs> deferred;
     void check_ready(double dt) const;
     hipStream_t stream() const { return st; }
     std::vector<double> observe(int kind, int n, const int32_t *op_ids, const double *vecs);
     void apply_root_heff(const double *x, double *y);
     void info(int32_t *bonds, int64_t *counters);
     size_t workspace_need() const { return ws_need; }
+    int64_t graph_captures() const { return counters_graph_captures; }
     int step_solves(int max, int32_t *node, int32_t *fwd, int32_t *matvecs) const;
 
     Tree t;
@@ -62,6 +73,16 @@ public:
 private:
     hipStream_t st = nullptr;
     bool have_sop = false, have_state = false;
+    bool adaptive = false;  // subspace expansion on (spawn_tol > 0)
+    bool graph_mode = false;  // steps replayed from captured hipGraphs (use_graph)
+    hipStream_t own_stream = nullptr;
+    struct GraphEntry {
+        std::vector<int64_t> key;  // Krylov dimension hints and dt of the captured step
+        hipGraphExec_t exec;
+        int n_solves;
+    };
+    std::vector<GraphEntry> graphs;
+    int64_t counters_graph_captures = 0;
     SopInput sop;
     TreeOp op;
     // state (allocated at construction)
@@ -92,6 +113,23 @@ private:
     int mmax = 40;
     int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     size_t ws_need = 0;  // scratch bytes of the current operator (workspace size)
+    // subspace expansion: two-site programs of each bond (by the child node):
+    // OT = outside factors transposed (grouped by bond channel), OC = outside
+    // factors conjugated (entry inputs by channel), B = below factors (entry
+    // inputs by channel), BH = below factors conjugate-transposed (grouped)
+    struct TwoSite {
+        Prog OT, OC, B, BH;
+        std::vector<int> chans;
+    };
+    std::vector<TwoSite> tsP;
+    std::vector<int> snap_bond;
+    int gkl_m = 40;                       // largest Golub-Kahan-Lanczos dimension
+    double2 *ts_in = nullptr, *ts_s = nullptr, *ts_w1 = nullptr, *ts_w2 = nullptr, *ts_out = nullptr;
+    double2 *ts_R = nullptr, *ts_part = nullptr;
+    double *gkl_sc = nullptr;             // alpha[64] beta[64] s[64] U[64*64] V[64*64]
+    int *gkl_n = nullptr;
+    BigKrylov gkP{}, gkQ{};
+    uint64_t spawn_calls = 0;
 
     void *dalloc(size_t bytes);
     void free_sop();
@@ -101,6 +139,8 @@ private:
     void prep(const Prog &p);
     ProgView view(const Prog &p) const;
     void build_programs();
+    void build_node_programs(int z);
+    int capdim(const Prog &p, int slot) const;
     void rebuild_all_spos();
 
     // sweep pieces
@@ -111,6 +151,15 @@ private:
     void expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd);
     bool use_fused(const Prog &p) const;
     void qr_slot(int z, int s, double2 *Rout, int transR);
+    void qr_any(double2 *X, const Geom &g, int s, double2 *Rout, int transR);
+    // subspace expansion
+    bool spawn(int z, int k, double h, bool below);
+    void build_two_site(int z, int k);
+    void apply_R(int z, int k, const double2 *Qc, const double2 *Qo, const double2 *q, double2 *p);
+    void apply_RH(int z, int k, const double2 *Qc, const double2 *Qo, const double2 *y, double2 *w);
+    void project_out(const double2 *Q, int64_t L, int n, int64_t R, int conjQ, double2 *x);
+    void resize_psi0(int c, int nb_new);
+    void transform_factors(Prog &p, int mode);
     void absorb(int z, int s, const double2 *M, int transM);
     void build_spo(int c);
     void build_mf(int z, int k);
@@ -119,6 +168,11 @@ private:
     void save_snapshot();
     void restore_snapshot();
     void enqueue_sweep(double dt);
+    void enqueue_sweep_body(double dt);
+    void enqueue_stats();
+    void emit(std::function<void()> op);
+    std::vector<std::function<void()>> *rec = nullptr;  // schedule being recorded (lockstep batches)
+    void drop_graphs();
 };
 
 void debug_qr(int64_t rows, int cols, const double *m, int variant, double *q_out, double *r_out);

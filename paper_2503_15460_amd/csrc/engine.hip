@@ -18,7 +18,9 @@
 #include <cstring>
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
 #include <map>
+#include <set>
 
 #include "engine.h"
 
@@ -40,8 +42,17 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
     st = (hipStream_t)opt.hip_stream;
     mmax = opt.krylov_mmax > 0 ? std::min(opt.krylov_mmax, 40) : 40;
     if (mmax < 3) mmax = 3;
+    for (int z = 0; z < t.n; ++z)
+        if (z != t.root && t.cap[z] > 64) throw Error(TTN_E_DIMS, "bond dimensions above 64 are not supported");
+    adaptive = opt.spawn_tol > 0.0;
+    graph_mode = opt.use_graph != 0;
+    if (graph_mode && !st) {  // the null stream cannot be captured: a stream of the handle's own
+        HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+        st = own_stream;
+    }
+    // node tensors are allocated for the bond capacity (bonds may grow)
     int64_t tot = 0;
-    for (int z = 0; z < t.n; ++z) tot += t.size[z];
+    for (int z = 0; z < t.n; ++z) tot += t.capsize[z];
     HIPCHK(hipMalloc(&state_mem, sizeof(double2) * 3 * tot));
     HIPCHK(hipMemset(state_mem, 0, sizeof(double2) * 3 * tot));
     counters[5] += (int64_t)sizeof(double2) * 3 * tot;
@@ -53,15 +64,15 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
         A[z] = state_mem + off;
         Aalt[z] = state_mem + tot + off;
         A0[z] = state_mem + 2 * tot + off;
-        off += t.size[z];
+        off += t.capsize[z];
     }
-    for (int z = 0; z < t.n; ++z)
-        if (z != t.root && t.bond[z] > 64) throw Error(TTN_E_DIMS, "bond dimensions above 64 are not supported");
     HIPCHK(hipEventCreateWithFlags(&step_done, hipEventDisableTiming));
 }
 
 Engine::~Engine() {
+    drop_graphs();
     free_sop();
+    if (own_stream) (void)hipStreamDestroy(own_stream);
     if (h_stats) (void)hipHostFree(h_stats);
     if (h_flags) (void)hipHostFree(h_flags);
     if (step_done) (void)hipEventDestroy(step_done);
@@ -90,6 +101,7 @@ void *Engine::dalloc(size_t bytes) {
 }
 
 void Engine::free_sop() {
+    drop_graphs();
     have_sop = false;
     for (void *p : sop_allocs) (void)hipFree(p);
     sop_allocs.clear();
@@ -97,6 +109,7 @@ void Engine::free_sop() {
     spoP.clear();
     bondP.clear();
     mfP.clear();
+    tsP.clear();
 }
 
 Geom Engine::geom_of(const std::vector<int> &dims) const {
@@ -118,23 +131,36 @@ Geom Engine::geom_of(const std::vector<int> &dims) const {
     return g;
 }
 
+// Clear the host tables of a program, keeping its device tables and buffers.
+static void reset_host(Prog &p) {
+    p.ents.clear();
+    p.gptr.assign(1, 0);
+    p.gent.clear();
+    p.gdst.clear();
+    p.cjobs.clear();
+    p.csrcs.clear();
+    p.comb_max_n2 = 0;
+}
+
+// Dimension of `slot` of the program's node tensor at the bond capacity.
+int Engine::capdim(const Prog &p, int slot) const { return p.capdims[slot]; }
+
+// Device tables of a program are allocated at its first upload; later uploads
+// (after a bond changed size) copy into the same tables, whose sizes do not
+// change (the entry structure of a node does not depend on the bonds).
 void Engine::upload(Prog &p) {
-    p.d_ent = (DevEntry *)dalloc(sizeof(DevEntry) * std::max<size_t>(1, p.ents.size()));
-    if (!p.ents.empty())
-        HIPCHK(hipMemcpy(p.d_ent, p.ents.data(), sizeof(DevEntry) * p.ents.size(), hipMemcpyHostToDevice));
-    p.d_gptr = (int *)dalloc(sizeof(int) * p.gptr.size());
-    HIPCHK(hipMemcpy(p.d_gptr, p.gptr.data(), sizeof(int) * p.gptr.size(), hipMemcpyHostToDevice));
-    p.d_gent = (int *)dalloc(sizeof(int) * std::max<size_t>(1, p.gent.size()));
-    if (!p.gent.empty())
-        HIPCHK(hipMemcpy(p.d_gent, p.gent.data(), sizeof(int) * p.gent.size(), hipMemcpyHostToDevice));
-    p.d_gdst = (double2 **)dalloc(sizeof(double2 *) * std::max<size_t>(1, p.gdst.size()));
-    if (!p.gdst.empty())
-        HIPCHK(hipMemcpy(p.d_gdst, p.gdst.data(), sizeof(double2 *) * p.gdst.size(), hipMemcpyHostToDevice));
+    auto put = [&](auto *&dptr, const auto &vec) {
+        using T = std::remove_reference_t<decltype(vec[0])>;
+        if (!dptr) dptr = (std::remove_const_t<T> *)dalloc(sizeof(T) * std::max<size_t>(1, vec.size()));
+        if (!vec.empty()) HIPCHK(hipMemcpy((void *)dptr, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice));
+    };
+    put(p.d_ent, p.ents);
+    put(p.d_gptr, p.gptr);
+    put(p.d_gent, p.gent);
+    put(p.d_gdst, p.gdst);
     if (!p.cjobs.empty()) {
-        p.d_cjobs = (CombJob *)dalloc(sizeof(CombJob) * p.cjobs.size());
-        HIPCHK(hipMemcpy(p.d_cjobs, p.cjobs.data(), sizeof(CombJob) * p.cjobs.size(), hipMemcpyHostToDevice));
-        p.d_csrcs = (CombSrc *)dalloc(sizeof(CombSrc) * p.csrcs.size());
-        HIPCHK(hipMemcpy(p.d_csrcs, p.csrcs.data(), sizeof(CombSrc) * p.csrcs.size(), hipMemcpyHostToDevice));
+        put(p.d_cjobs, p.cjobs);
+        put(p.d_csrcs, p.csrcs);
     }
 }
 
@@ -162,13 +188,17 @@ void Engine::merge_entries(Prog &p) {
     if (plan.empty()) return;
     std::vector<char> used(ne, 0);
     std::vector<DevEntry> out;
-    size_t elems = 0;
-    for (auto &m : plan) {
-        const int n = p.g.dims[p.ents[m.members[0]].slot[m.f]];
-        elems += (size_t)n * n;
+    p.cjobs.clear();
+    p.csrcs.clear();
+    p.comb_max_n2 = 0;
+    if (p.comb_bufs.empty()) {  // one buffer per summed factor, at the capacity's size
+        for (auto &m : plan) {
+            const int n = capdim(p, p.ents[m.members[0]].slot[m.f]);
+            p.comb_bufs.push_back((double2 *)dalloc(sizeof(double2) * (size_t)n * n));
+        }
     }
-    double2 *buf = (double2 *)dalloc(sizeof(double2) * elems);
-    size_t off = 0;
+    if (p.comb_bufs.size() != plan.size()) throw Error(TTN_E_STATE, "internal: merge plan changed");
+    size_t qi = 0;
     for (auto &m : plan) {
         const int f = m.f;
         DevEntry d = p.ents[m.members[0]];
@@ -177,7 +207,7 @@ void Engine::merge_entries(Prog &p) {
         int lo = 0, hi = 0;
         bool dense = false;
         CombJob j{};
-        j.dst = buf + off;
+        j.dst = p.comb_bufs[qi++];
         j.n2 = n * n;
         j.first = (int)p.csrcs.size();
         j.count = (int)m.members.size();
@@ -194,7 +224,6 @@ void Engine::merge_entries(Prog &p) {
         d.M[f] = j.dst;
         p.cjobs.push_back(j);
         p.comb_max_n2 = std::max(p.comb_max_n2, j.n2);
-        off += (size_t)j.n2;
         out.push_back(d);
     }
     for (int e = 0; e < ne; ++e)
@@ -283,6 +312,20 @@ void Engine::build_programs() {
     spoP.assign(n, Prog{});
     bondP.assign(n, Prog{});
     mfP.assign(n, {});
+    int64_t total_entries = 0;
+    for (int z = 0; z < n; ++z) {
+        total_entries += (int64_t)op.entries[z].size();
+        build_node_programs(z);
+    }
+    counters[6] = total_entries;
+}
+
+// Host tables of every program of node z (effective generator, SPO rebuild,
+// bond generator of the bond above z, mean-field rebuilds of z's children) for
+// the current bonds, uploaded into the node's device tables.
+void Engine::build_node_programs(int z) {
+    const int n = t.n;
+    (void)n;
     auto child_M = [&](int z, int k, int ch) -> const double2 * {
         if (t.local_dim[z] > 0) {
             int d = t.local_dim[z];
@@ -303,16 +346,16 @@ void Engine::build_programs() {
         int np = t.bond[z];
         return mf[z] + (size_t)ch * np * np;
     };
-    int64_t total_entries = 0;
-    for (int z = 0; z < n; ++z) {
+    {
         const auto &ents = op.entries[z];
-        total_entries += (int64_t)ents.size();
         const int D = (int)t.dims[z].size();
         const int nk = D - 1;
         const bool root = z == t.root;
         // effective generator of the node
         Prog &h = heffP[z];
+        reset_host(h);
         h.g = geom_of(t.dims[z]);
+        for (int q = 0; q < D; ++q) h.capdims[q] = t.capdims[z][q];
         for (auto &e : ents) {
             DevEntry de = blank_entry();
             de.coef = to_d2(e.coef);
@@ -337,7 +380,9 @@ void Engine::build_programs() {
         if (!root) {
             // SPO rebuild: groups by own-bond channel (>= 1), children factors only
             Prog &s = spoP[z];
+            reset_host(s);
             s.g = h.g;
+            for (int q = 0; q < D; ++q) s.capdims[q] = t.capdims[z][q];
             s.contract_slot = D - 1;
             std::map<int, int> gid;
             std::vector<double2 *> dst;
@@ -366,7 +411,9 @@ void Engine::build_programs() {
             upload(s);
             // backward bond generator K(C) = sum_b U_b C O_b^T on the bond above z
             Prog &b = bondP[z];
+            reset_host(b);
             b.g = geom_of({np, np});
+            b.capdims[0] = b.capdims[1] = t.cap[z];
             const double2 *Sb = spo[z], *Mb = mf[z];
             if (op.outside_used[z]) {
                 DevEntry de = blank_entry();
@@ -399,12 +446,14 @@ void Engine::build_programs() {
         }
         // mean-field rebuilds of every child
         if (t.local_dim[z] == 0) {
-            mfP[z].assign(nk, Prog{});
+            if ((int)mfP[z].size() != nk) mfP[z].assign(nk, Prog{});
             for (int k = 0; k < nk; ++k) {
                 const int c = t.kids[z][k];
                 const int nc = t.bond[c];
                 Prog &m = mfP[z][k];
+                reset_host(m);
                 m.g = h.g;
+                for (int q = 0; q < D; ++q) m.capdims[q] = t.capdims[z][q];
                 m.contract_slot = k;
                 std::map<int, int> gid;
                 std::vector<double2 *> dst;
@@ -445,7 +494,6 @@ void Engine::build_programs() {
             }
         }
     }
-    counters[6] = total_entries;
 }
 
 void Engine::set_sop(const SopInput &s) {
@@ -464,7 +512,7 @@ void Engine::set_sop(const SopInput &s) {
     uhi.assign(n, {});
     for (int c = 0; c < n; ++c) {
         if (c == t.root) continue;
-        const size_t nb = t.bond[c];
+        const size_t nb = t.cap[c];  // environments sized for the bond capacity
         const size_t bytes = sizeof(double2) * op.n_ch[c] * nb * nb;
         spo[c] = (double2 *)dalloc(bytes);
         mf[c] = (double2 *)dalloc(bytes);
@@ -500,28 +548,57 @@ void Engine::set_sop(const SopInput &s) {
     }
     build_programs();
     // scratch sizes
+    // every size at the bond capacity (bonds may grow)
     int64_t tmp_e = 1, gsum_e = 1, cpart_e = 1, maxN = 1, maxb2 = 1;
+    auto capN = [](const Prog &p) {
+        int64_t v = 1;
+        for (int q = 0; q < p.g.D; ++q) v *= p.capdims[q];
+        return v;
+    };
+    auto fused_at = [](const Prog &p, int64_t N) {
+        return N <= SMALL_MAX && (p.g.D == 2 || (int64_t)p.ents.size() * N <= SMALL_SEQ_WORK);
+    };
     auto acc = [&](const Prog &p) {
-        tmp_e = std::max<int64_t>(tmp_e, 2 * (int64_t)p.ents.size() * p.g.N);
-        gsum_e = std::max<int64_t>(gsum_e, (int64_t)p.n_groups * p.g.N);
+        const int64_t N = capN(p);
+        tmp_e = std::max<int64_t>(tmp_e, 2 * (int64_t)p.ents.size() * N);
+        gsum_e = std::max<int64_t>(gsum_e, (int64_t)p.n_groups * N);
         if (p.contract_slot >= 0) {
-            int nn = p.g.dims[p.contract_slot];
+            int nn = p.capdims[p.contract_slot];
             cpart_e = std::max<int64_t>(cpart_e, (int64_t)p.n_groups * 64 * nn * nn);
         }
     };
     bigN = 0;
     for (int z = 0; z < n; ++z) {
         acc(heffP[z]);
-        maxN = std::max<int64_t>(maxN, t.size[z]);
-        if (!use_fused(heffP[z])) bigN = std::max<int64_t>(bigN, t.size[z]);
+        maxN = std::max<int64_t>(maxN, t.capsize[z]);
+        if (!fused_at(heffP[z], t.capsize[z])) bigN = std::max<int64_t>(bigN, t.capsize[z]);
         if (z != t.root) {
             acc(spoP[z]);
             acc(bondP[z]);
-            int64_t b2 = (int64_t)t.bond[z] * t.bond[z];
+            int64_t b2 = (int64_t)t.cap[z] * t.cap[z];
             maxb2 = std::max(maxb2, b2);
-            if (!use_fused(bondP[z])) bigN = std::max<int64_t>(bigN, b2);
+            if (!fused_at(bondP[z], b2)) bigN = std::max<int64_t>(bigN, b2);
         }
         for (auto &m : mfP[z]) acc(m);
+    }
+    // subspace expansion: the two-site programs and vectors of every bond
+    int64_t ts_v = 1, ts_no = 1, ts_nb = 1;
+    int ts_g = 1;
+    if (adaptive) {
+        tsP.assign(n, TwoSite{});
+        for (int c = 0; c < n; ++c) {
+            if (c == t.root) continue;
+            const int z = t.parent[c];
+            const int64_t no = t.capsize[z] / t.cap[c], nbel = t.capsize[c] / t.cap[c];
+            ts_no = std::max(ts_no, no);
+            ts_nb = std::max(ts_nb, nbel);
+            ts_g = std::max(ts_g, op.n_ch[c]);
+            tmp_e = std::max<int64_t>(tmp_e, 2 * (int64_t)op.entries[z].size() * no);
+            tmp_e = std::max<int64_t>(tmp_e, 2 * (int64_t)op.entries[c].size() * nbel);
+            gsum_e = std::max<int64_t>(gsum_e, (int64_t)op.n_ch[c] * std::max(no, nbel));
+        }
+        ts_v = std::max(ts_no, ts_nb);
+        gkl_m = std::min(40, mmax);
     }
     cpart_e = std::max<int64_t>(cpart_e, 64 * 64 * 64);
     // scratch: every buffer below is either allocated here or carved from the
@@ -546,7 +623,7 @@ void Engine::set_sop(const SopInput &s) {
     need(&smallV, sizeof(double2) * (SMALL_MMAX + 2) * SMALL_MAX);
     int64_t mats = 0;
     for (int z = 0; z < n; ++z) {
-        mats += (int64_t)t.bond[z] * t.bond[z];
+        mats += (int64_t)t.cap[z] * t.cap[z];
         if (t.local_dim[z] > 0) mats += (int64_t)t.local_dim[z] * t.local_dim[z];
     }
     obs_elems = 2 * maxN + mats + 64;
@@ -564,8 +641,31 @@ void Engine::set_sop(const SopInput &s) {
     }
     {  // copy of the state taken at the start of every step (restored on failure)
         int64_t tot = 0;
-        for (int z = 0; z < n; ++z) tot += t.size[z];
+        for (int z = 0; z < n; ++z) tot += t.capsize[z];
         need(&snapshot, sizeof(double2) * tot);
+    }
+    if (adaptive) {  // subspace expansion vectors, Krylov bases and the bidiagonal's SVD
+        need(&ts_in, sizeof(double2) * ts_g * ts_v);
+        need(&ts_s, sizeof(double2) * ts_g * 64);
+        need(&ts_w1, sizeof(double2) * ts_v);
+        need(&ts_w2, sizeof(double2) * ts_v);
+        need(&ts_out, sizeof(double2) * 64 * ts_v);
+        need(&ts_R, sizeof(double2) * 64 * 64);
+        need(&ts_part, sizeof(double2) * 64 * 64 * std::max(ts_g, 1));
+        need(&gkl_sc, sizeof(double) * (192 + 2 * 64 * 64));
+        need(&gkl_n, sizeof(int) * 4);
+        for (BigKrylov *k : {&gkP, &gkQ}) {
+            const int64_t N = k == &gkP ? ts_nb : ts_no;
+            *k = BigKrylov{};
+            need(&k->V, sizeof(double2) * (gkl_m + 1) * N);
+            need(&k->Hm, sizeof(double2) * (gkl_m + 1) * gkl_m);
+            need(&k->h, sizeof(double2) * (gkl_m + 1));
+            need(&k->y, sizeof(double2) * (gkl_m + 1));
+            need(&k->part, sizeof(double) * VEC_BLOCKS * (gkl_m + 2) * 2);
+            need(&k->scal, sizeof(double) * 4);
+            need(&k->meff, sizeof(int) * 4);
+            need(&k->counter, sizeof(unsigned) * 4);
+        }
     }
     // many-work-group QR scratch
     need(&qrw.tau, sizeof(double2) * 64);
@@ -614,6 +714,21 @@ void Engine::set_sop(const SopInput &s) {
     solve_fwd.assign(n_solves, 0);
     solve_small.assign(n_solves, 0);
     have_sop = true;
+    if (opt.autotune) {  // register tiles of every staged program, timed on the programs themselves
+        for (int z = 0; z < n; ++z) {
+            auto tune = [&](const Prog &p, const double2 *in) {
+                prep(p);
+                tune_prog_stages(view(p), in, st);
+            };
+            if (!use_fused(heffP[z])) tune(heffP[z], A[z]);
+            if (z != t.root) {
+                tune(spoP[z], A[z]);
+                if (!use_fused(bondP[z])) tune(bondP[z], Cbuf);
+            }
+            for (auto &m : mfP[z]) tune(m, A[z]);
+        }
+        sync_check("autotune");
+    }
     if (have_state) rebuild_all_spos();
     HIPCHK(hipStreamSynchronize(st));
 }
@@ -742,14 +857,15 @@ void Engine::build_mf(int z, int k) {
     launch_prog_contract(v, A[z], st);
 }
 
-void Engine::qr_slot(int z, int s, double2 *Rout, int transR) {
-    const Geom g = heffP[z].g;
+void Engine::qr_slot(int z, int s, double2 *Rout, int transR) { qr_any(A[z], heffP[z].g, s, Rout, transR); }
+
+void Engine::qr_any(double2 *X, const Geom &g, int s, double2 *Rout, int transR) {
     // wide factors of mid-size tensors also leave the single work-group kernel:
     // its column loop is sequential on one compute unit
     const bool coop = g.N >= QR_MULTI_MIN || (g.N >= 4096 && g.dims[s] >= 16);
-    if (coop && launch_qr_coop(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st)) return;
-    if (g.N >= QR_MULTI_MIN) launch_qr_multi(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st);
-    else launch_qr(A[z], g.L[s], g.dims[s], g.R[s], Rout, transR, st);
+    if (coop && !graph_mode && launch_qr_coop(X, g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st)) return;
+    if (g.N >= QR_MULTI_MIN) launch_qr_multi(X, g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st);
+    else launch_qr(X, g.L[s], g.dims[s], g.R[s], Rout, transR, st);
 }
 
 void Engine::absorb(int z, int s, const double2 *M, int transM) {
@@ -815,7 +931,8 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
             }
         }
         a.vlds = lds + small_solve_vlds_bytes(p.g.N, a.mmax) <= 160 * 1024 ? 1 : 0;
-        launch_small_solve(a, st);
+        if (defer_fused) deferred.push_back(a);  // launched with other instances' solves
+        else launch_small_solve(a, st);
     } else {
         if (!bk.V) throw Error(TTN_E_STATE, "internal: Krylov scratch not allocated");
         int m = m_hint[si] > 0 ? m_hint[si] : 20;
@@ -838,40 +955,363 @@ void Engine::forward(int z, double tau) { expm_prog(heffP[z], A[z], tau, z, true
 
 void Engine::backward(int c, double2 *C, double tau) { expm_prog(bondP[c], C, -tau, c, false); }
 
+// ------------------------------------------------------ subspace expansion
+// Paper Sec. II D: when the sweep crosses the bond between node z and its
+// k-th child c, the bond is widened by new functions with zero coefficients
+// along the dominant singular vectors of the two-site residual
+//   R = (1 - P_c) X (1 - P_o^T),  X = the two-site projection of G Psi,
+// matricised (indices below c) x (indices outside c), P_c the projector on the
+// columns of A^c and P_o on the columns of A^z along k.  X acts at one-site
+// cost through the bond's channels: the compiled operator splits G on this
+// bond as sum_b S_b (x) M_b, where S_b (below c) is the channel-b combination
+// of c's node entries and M_b (outside c) that of z's entries carrying channel
+// b on slot k, so X w = sum_b S_b A^c A^z^T M_b^T w.  The singular pairs come
+// from a Golub-Kahan-Lanczos bidiagonalisation with full re-orthogonalisation.
+
+// Replace every factor of p by its transformed copy (mode 1: transpose, 2:
+// conjugate, 3: conjugate transpose), recomputed by prep() before each use.
+void Engine::transform_factors(Prog &p, int mode) {
+    std::map<const double2 *, double2 *> done;
+    std::vector<std::pair<const double2 *, int>> order;
+    for (auto &e : p.ents)
+        for (int f = 0; f < e.nf; ++f)
+            if (!done.count(e.M[f])) {
+                done[e.M[f]] = nullptr;
+                order.push_back({e.M[f], p.g.dims[e.slot[f]]});
+            }
+    if (p.comb_bufs.empty()) {
+        for (auto &o : order) {
+            (void)o;
+            p.comb_bufs.push_back((double2 *)dalloc(sizeof(double2) * 64 * 64));
+        }
+    }
+    if (p.comb_bufs.size() != order.size()) throw Error(TTN_E_STATE, "internal: two-site factor count changed");
+    for (size_t q = 0; q < order.size(); ++q) {
+        CombJob j{};
+        j.dst = p.comb_bufs[q];
+        j.n = order[q].second;
+        j.n2 = j.n * j.n;
+        j.first = (int)p.csrcs.size();
+        j.count = 1;
+        j.mode = mode;
+        p.csrcs.push_back({make_double2(1.0, 0.0), order[q].first});
+        p.cjobs.push_back(j);
+        p.comb_max_n2 = std::max(p.comb_max_n2, j.n2);
+        done[order[q].first] = j.dst;
+    }
+    for (auto &e : p.ents)
+        for (int f = 0; f < e.nf; ++f) {
+            e.M[f] = done[e.M[f]];
+            if (mode & 1) std::swap(e.lo[f], e.hi[f]);  // the band of the transpose
+        }
+}
+
+// Host tables of the four two-site programs of the bond above c = kids[z][k]
+// for the current bonds (device tables allocated at the first build).
+void Engine::build_two_site(int z, int k) {
+    const int c = t.kids[z][k];
+    TwoSite &T = tsP[c];
+    const int D = (int)t.dims[z].size();
+    const bool root = z == t.root;
+    const int np = t.bond[z];
+    std::set<int> cb, zb;
+    for (auto &e : op.entries[c]) cb.insert(e.bp);
+    for (auto &e : op.entries[z]) zb.insert(e.slot[k] == -1 ? 0 : e.slot[k]);
+    T.chans.clear();
+    for (int b : cb)
+        if (zb.count(b)) T.chans.push_back(b);
+    std::map<int, int> gid;
+    for (size_t g = 0; g < T.chans.size(); ++g) gid[T.chans[g]] = (int)g;
+    const int G = (int)T.chans.size();
+    // outside geometry: z's slots with slot k of size 1; below geometry: c's
+    // slots with the parent slot of size 1
+    std::vector<int> dw = t.dims[z], dv = t.dims[c];
+    dw[k] = 1;
+    dv.back() = 1;
+    std::vector<int> cw = t.capdims[z], cv = t.capdims[c];
+    cw[k] = 1;
+    cv.back() = 1;
+    auto setg = [&](Prog &p, const std::vector<int> &d, const std::vector<int> &cd) {
+        reset_host(p);
+        p.g = geom_of(d);
+        for (size_t q = 0; q < cd.size(); ++q) p.capdims[q] = cd[q];
+    };
+    setg(T.OT, dw, cw);
+    setg(T.OC, dw, cw);
+    setg(T.B, dv, cv);
+    setg(T.BH, dv, cv);
+    for (auto &e : op.entries[z]) {
+        const int b = e.slot[k] == -1 ? 0 : e.slot[k];
+        if (!gid.count(b)) continue;
+        DevEntry de = blank_entry();
+        de.coef = to_d2(e.coef);
+        int nf = 0;
+        for (int j = 0; j < D - 1; ++j)
+            if (j != k && e.slot[j] >= 1) {
+                const int cj = t.kids[z][j];
+                de.slot[nf] = j;
+                de.M[nf++] = spo[cj] + (size_t)e.slot[j] * t.bond[cj] * t.bond[cj];
+            }
+        if (!root && e.bp != 1) {
+            de.slot[nf] = D - 1;
+            de.M[nf++] = mf[z] + (size_t)e.bp * np * np;
+        }
+        de.nf = nf;
+        DevEntry a = de, o = de;
+        a.group = gid[b];  // X: outside factors transposed, outputs by channel
+        T.OT.ents.push_back(a);
+        o.group = 0;  // X^dag: conjugated factors, each entry reads its channel's input
+        o.src = gid[b];
+        o.coef.y = -o.coef.y;
+        T.OC.ents.push_back(o);
+    }
+    const bool leaf = t.local_dim[c] > 0;
+    const int d = t.local_dim[c];
+    for (auto &e : op.entries[c]) {
+        if (!gid.count(e.bp)) continue;
+        DevEntry de = blank_entry();
+        de.coef = to_d2(e.coef);
+        int nf = 0;
+        if (leaf) {
+            if (e.slot[0] >= 1) {
+                de.slot[0] = 0;
+                if (e.slot[0] < (int)ulo[c].size()) {
+                    de.lo[0] = ulo[c][e.slot[0]];
+                    de.hi[0] = uhi[c][e.slot[0]];
+                }
+                de.M[nf++] = U[c] + (size_t)e.slot[0] * d * d;
+            }
+        } else {
+            for (int j = 0; j < (int)t.kids[c].size(); ++j)
+                if (e.slot[j] >= 1) {
+                    const int cj = t.kids[c][j];
+                    de.slot[nf] = j;
+                    de.M[nf++] = spo[cj] + (size_t)e.slot[j] * t.bond[cj] * t.bond[cj];
+                }
+        }
+        de.nf = nf;
+        DevEntry a = de, h = de;
+        a.group = 0;  // X: below factors, each entry reads its channel's input
+        a.src = gid[e.bp];
+        T.B.ents.push_back(a);
+        h.group = gid[e.bp];  // X^dag: conjugate-transposed factors, outputs by channel
+        h.coef.y = -h.coef.y;
+        T.BH.ents.push_back(h);
+    }
+    transform_factors(T.OT, 1);
+    transform_factors(T.OC, 2);
+    transform_factors(T.BH, 3);
+    finish_groups(T.OT, std::vector<double2 *>(G, nullptr));
+    finish_groups(T.OC, {nullptr});
+    finish_groups(T.B, {nullptr});
+    finish_groups(T.BH, std::vector<double2 *>(G, nullptr));
+    upload(T.OT);
+    upload(T.OC);
+    upload(T.B);
+    upload(T.BH);
+}
+
+// x <- x - Q op(Q)^H... : with the columns of the (L, n, R) tensor Q along its
+// middle index, x <- x - Q (Q^H x) (conjQ = 0) or x - conj(Q) (Q^T x) (conjQ = 1)
+void Engine::project_out(const double2 *Q, int64_t L, int n, int64_t R, int conjQ, double2 *x) {
+    launch_ts_contract(Q, L, n, R, conjQ ? 0 : 1, x, 0, 1, ts_s, ts_part, st);
+    launch_ts_expand(Q, L, n, R, conjQ ? 1 : 0, ts_s, 1, x, 1, x, st);
+}
+
+// p = R q (q outside c, p below c)
+void Engine::apply_R(int z, int k, const double2 *Qc, const double2 *Qo, const double2 *q, double2 *p) {
+    const int c = t.kids[z][k];
+    TwoSite &T = tsP[c];
+    const Geom gz = heffP[z].g;
+    const int nb = t.bond[c];
+    const int64_t no = t.size[z] / nb, nbel = t.size[c] / nb;
+    const int G = (int)T.chans.size();
+    launch_copy(ts_w1, q, no, st);
+    project_out(Qo, gz.L[k], nb, gz.R[k], 1, ts_w1);  // (1 - P_o^T) q
+    ProgView vo = view(T.OT);
+    vo.f32 = vo.bf16x3 = 0;
+    launch_prog_stages(vo, ts_w1, st);
+    launch_prog_sum(vo, ts_w1, nullptr, st);  // u_b = M_b^T q', channel sums
+    launch_ts_contract(A[z], gz.L[k], nb, gz.R[k], 0, gsum, no, G, ts_s, ts_part, st);   // A^z^T u_b
+    launch_ts_expand(A[c], nbel, nb, 1, 0, ts_s, G, nullptr, 0, ts_in, st);            // A^c (.)
+    ProgView vb = view(T.B);
+    vb.f32 = vb.bf16x3 = 0;
+    vb.in_stride = nbel;
+    launch_prog_stages(vb, ts_in, st);
+    launch_prog_sum(vb, ts_in, p, st);  // sum_b S_b v_b
+    project_out(Qc, nbel, nb, 1, 0, p);  // (1 - P_c) y
+}
+
+// w = R^dag y (y below c, w outside c)
+void Engine::apply_RH(int z, int k, const double2 *Qc, const double2 *Qo, const double2 *y, double2 *w) {
+    const int c = t.kids[z][k];
+    TwoSite &T = tsP[c];
+    const Geom gz = heffP[z].g;
+    const int nb = t.bond[c];
+    const int64_t nbel = t.size[c] / nb;
+    const int G = (int)T.chans.size();
+    launch_copy(ts_w2, y, nbel, st);
+    project_out(Qc, nbel, nb, 1, 0, ts_w2);  // (1 - P_c) y
+    ProgView vh = view(T.BH);
+    vh.f32 = vh.bf16x3 = 0;
+    launch_prog_stages(vh, ts_w2, st);
+    launch_prog_sum(vh, ts_w2, nullptr, st);  // S_b^dag y', channel sums
+    launch_ts_contract(A[c], nbel, nb, 1, 1, gsum, nbel, G, ts_s, ts_part, st);           // A^c^dag (.)
+    launch_ts_expand(A[z], gz.L[k], nb, gz.R[k], 1, ts_s, G, nullptr, 0, ts_in, st);     // conj(A^z) (.)
+    ProgView vc = view(T.OC);
+    vc.f32 = vc.bf16x3 = 0;
+    vc.in_stride = t.size[z] / nb;
+    launch_prog_stages(vc, ts_in, st);
+    launch_prog_sum(vc, ts_in, w, st);  // sum_b conj(M_b) q_b
+    project_out(Qo, gz.L[k], nb, gz.R[k], 1, w);  // (1 - conj(P_o)) w
+}
+
+// Zero-pad (or truncate the zero padding of) Psi(0) along the bond above c.
+void Engine::resize_psi0(int c, int nb_new) {
+    const int z = t.parent[c];
+    const int k = (int)(std::find(t.kids[z].begin(), t.kids[z].end(), c) - t.kids[z].begin());
+    const int nb = t.bond[c];
+    const Geom gz = geom_of(t.dims[z]);
+    const int64_t nbel = t.size[c] / nb;
+    launch_repack(A0[c], Aalt[c], nbel, nb, nb_new, 1, nullptr, 0, 0, st);
+    launch_copy(A0[c], Aalt[c], nbel * nb_new, st);
+    launch_repack(A0[z], Aalt[z], gz.L[k], nb, nb_new, gz.R[k], nullptr, 0, 0, st);
+    launch_copy(A0[z], Aalt[z], gz.L[k] * nb_new * gz.R[k], st);
+}
+
+// One expansion attempt at the bond above c = kids[z][k] with substep h.
+// below: centre at c, new functions of c (left singular vectors); otherwise
+// centre at z, new single hole functions of c (conjugated right singular
+// vectors).  Returns true when the bond grew (programs of z and c rebuilt).
+bool Engine::spawn(int z, int k, double h, bool below) {
+    const int c = t.kids[z][k];
+    const int nb = t.bond[c];
+    const int64_t no = t.size[z] / nb, nbel = t.size[c] / nb;
+    const int room = (int)std::min<int64_t>({(int64_t)t.cap[c], nbel, no}) - nb;
+    if (room <= 0) return false;
+    build_two_site(z, k);
+    for (Prog *p : {&tsP[c].OT, &tsP[c].OC, &tsP[c].BH}) prep(*p);
+    const Geom gz = heffP[z].g, gc = heffP[c].g;
+    // orthonormal bases of the two spans: the isometry where there is one, the
+    // Householder Q of a copy of the centre tensor otherwise
+    const double2 *Qc = A[c], *Qo = A[z];
+    if (below) {
+        launch_copy(Aalt[c], A[c], t.size[c], st);
+        qr_any(Aalt[c], gc, gc.D - 1, ts_R, 0);
+        Qc = Aalt[c];
+    } else {
+        launch_copy(Aalt[z], A[z], t.size[z], st);
+        qr_any(Aalt[z], gz, k, ts_R, 0);
+        Qo = Aalt[z];
+    }
+    const int m = (int)std::min<int64_t>({(int64_t)gkl_m, nbel, no});
+    double *alpha = gkl_sc, *beta = gkl_sc + 64, *sv = gkl_sc + 128, *Ub = gkl_sc + 192, *Vb = Ub + 64 * 64;
+    BigKrylov P = gkP, Q = gkQ;
+    // start in the row space of R: q_0 = R^dag u for a seeded u below c
+    launch_seed_vector(ts_out, nbel, opt.seed + 0x5851F42D4C957F2Dull * (++spawn_calls), st);
+    apply_RH(z, k, Qc, Qo, ts_out, ts_w1);
+    launch_krylov_start(ts_w1, no, Q, st);
+    for (int j = 0; j < m; ++j) {
+        double2 *pj = P.V + (size_t)j * nbel;
+        apply_R(z, k, Qc, Qo, Q.V + (size_t)j * no, pj);
+        if (j == 0) {
+            launch_krylov_start(pj, nbel, P, st);  // alpha_0
+            launch_copy_scalars(alpha, P.scal, 1, st);
+        } else {
+            launch_krylov_orth(P, nbel, j - 1, gkl_m, st);  // alpha_j
+            launch_copy_scalars(alpha + j, P.scal + 1, 1, st);
+        }
+        if (j == m - 1) break;
+        apply_RH(z, k, Qc, Qo, pj, Q.V + (size_t)(j + 1) * no);
+        launch_krylov_orth(Q, no, j, gkl_m, st);  // beta_j
+        launch_copy_scalars(beta + j, Q.scal + 1, 1, st);
+    }
+    launch_gkl_count(P.meff, Q.meff, alpha, m, gkl_n, st);
+    launch_bidiag_svd(alpha, beta, gkl_n, 64, sv, Ub, Vb, st);
+    double hs[65];
+    int hn = 0;
+    HIPCHK(hipMemcpyAsync(hs, sv, sizeof(double) * 64, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&hn, gkl_n, sizeof(int), hipMemcpyDeviceToHost, st));
+    sync_check("subspace expansion");
+    int take = 0;
+    while (take < std::min(room, hn) && std::fabs(h) * hs[take] >= opt.spawn_tol) ++take;
+    if (take == 0) return false;
+    if (below) {
+        launch_basis_combine(P.V, nbel, gkl_n, Ub, 64, take, ts_out, st);
+        launch_repack(A[c], Aalt[c], nbel, nb, nb + take, 1, ts_out, nbel, 0, st);
+        launch_repack(A[z], Aalt[z], gz.L[k], nb, nb + take, gz.R[k], nullptr, 0, 0, st);
+    } else {
+        launch_basis_combine(Q.V, no, gkl_n, Vb, 64, take, ts_out, st);
+        launch_repack(A[z], Aalt[z], gz.L[k], nb, nb + take, gz.R[k], ts_out, no, 1, st);
+        launch_repack(A[c], Aalt[c], nbel, nb, nb + take, 1, nullptr, 0, 0, st);
+    }
+    std::swap(A[c], Aalt[c]);
+    std::swap(A[z], Aalt[z]);
+    resize_psi0(c, nb + take);
+    t.bond[c] = nb + take;
+    t.update_dims();
+    build_node_programs(z);
+    build_node_programs(c);
+    return true;
+}
+
 // ------------------------------------------------------------------ sweep
+// Each operation of the sweep goes through emit(): run at once, or, while a
+// schedule is recorded (batches advanced in lockstep), appended to it.  The
+// solve operations are separate entries, so the j-th entries of several
+// instances' schedules can share one grouped launch of the fused solver.
+void Engine::emit(std::function<void()> op) {
+    if (rec) rec->push_back(std::move(op));
+    else op();
+}
+
 void Engine::sweep_S(int z, double h) {
     const auto &kids = t.kids[z];
     for (int k = 0; k < (int)kids.size(); ++k) {
         const int c = kids[k];
         const int pc = (int)t.dims[c].size() - 1;
-        qr_slot(z, k, Rbuf, 0);            // gauge down
-        absorb(c, pc, Rbuf, 0);
-        build_mf(z, k);
-        if (t.local_dim[c] > 0) forward(c, h);
+        emit([=] {
+            qr_slot(z, k, Rbuf, 0);  // gauge down
+            absorb(c, pc, Rbuf, 0);
+            build_mf(z, k);
+        });
+        if (t.local_dim[c] > 0) emit([=] { forward(c, h); });
         else sweep_S(c, h);
-        qr_slot(c, pc, Cbuf, 0);           // up: backward bond step
-        build_spo(c);
-        backward(c, Cbuf, h);
-        absorb(z, k, Cbuf, 0);
+        emit([=] {
+            if (adaptive && spawn(z, k, h, true)) build_mf(z, k);  // centre at c: new functions of c
+            const int pcn = (int)t.dims[c].size() - 1;
+            qr_slot(c, pcn, Cbuf, 0);  // up: backward bond step
+            build_spo(c);
+        });
+        emit([=] { backward(c, Cbuf, h); });
+        emit([=] { absorb(z, k, Cbuf, 0); });
     }
-    if (z != t.root) forward(z, h);
+    if (z != t.root) emit([=] { forward(z, h); });
 }
 
 void Engine::sweep_Sstar(int z, double h) {
-    if (z != t.root) forward(z, h);
+    if (z != t.root) emit([=] { forward(z, h); });
     const auto &kids = t.kids[z];
     for (int k = (int)kids.size() - 1; k >= 0; --k) {
         const int c = kids[k];
-        const int pc = (int)t.dims[c].size() - 1;
-        qr_slot(z, k, Cbuf, 1);            // down: backward bond step on R^T
-        build_mf(z, k);
-        backward(c, Cbuf, h);
-        absorb(c, pc, Cbuf, 1);
-        if (t.local_dim[c] > 0) forward(c, h);
+        emit([=] {
+            if (adaptive && spawn(z, k, h, false)) build_spo(c);  // centre at z: new hole functions of c
+            qr_slot(z, k, Cbuf, 1);  // down: backward bond step on R^T
+            build_mf(z, k);
+        });
+        emit([=] { backward(c, Cbuf, h); });
+        emit([=] {
+            const int pc = (int)t.dims[c].size() - 1;
+            absorb(c, pc, Cbuf, 1);
+        });
+        if (t.local_dim[c] > 0) emit([=] { forward(c, h); });
         else sweep_Sstar(c, h);
-        qr_slot(c, pc, Rbuf, 0);           // gauge up
-        build_spo(c);
-        absorb(z, k, Rbuf, 0);
+        emit([=] {
+            const int pc = (int)t.dims[c].size() - 1;
+            qr_slot(c, pc, Rbuf, 0);  // gauge up
+            build_spo(c);
+            absorb(z, k, Rbuf, 0);
+        });
     }
 }
 
@@ -888,6 +1328,7 @@ void Engine::check_ready(double dt) const {
 
 void Engine::save_snapshot() {
     if (!snapshot) return;
+    snap_bond = t.bond;
     int64_t off = 0;
     for (int z = 0; z < t.n; ++z) {
         launch_copy(snapshot + off, A[z], t.size[z], st);
@@ -896,6 +1337,17 @@ void Engine::save_snapshot() {
 }
 
 void Engine::restore_snapshot() {
+    if (adaptive && snap_bond != t.bond) {
+        // bonds grown during the failed step: Psi(0) loses its zero padding, the
+        // bonds and every program go back to the state of the snapshot
+        for (int c = 0; c < t.n; ++c)
+            if (c != t.root && t.bond[c] != snap_bond[c]) {
+                resize_psi0(c, snap_bond[c]);
+                t.bond[c] = snap_bond[c];
+                t.update_dims();
+            }
+        for (int z = 0; z < t.n; ++z) build_node_programs(z);
+    }
     int64_t off = 0;
     for (int z = 0; z < t.n; ++z) {
         launch_copy(A[z], snapshot + off, t.size[z], st);
@@ -907,20 +1359,102 @@ void Engine::restore_snapshot() {
 // Enqueue one sweep and the asynchronous copy of its solve statistics; nothing
 // here waits for the device.
 void Engine::enqueue_sweep(double dt) {
+    enqueue_sweep_body(dt);
+    HIPCHK(hipEventRecord(step_done, st));
+}
+
+void Engine::enqueue_sweep_body(double dt) {
     solve_idx = 0;
     const double h = 0.5 * dt;
     sweep_S(t.root, h);
-    forward(t.root, dt);
+    emit([=] { forward(t.root, dt); });
     sweep_Sstar(t.root, h);
+    enqueue_stats();
+}
+
+void Engine::enqueue_stats() {
     HIPCHK(hipMemcpyAsync(h_stats, d_stats, sizeof(SolveStat) * solve_idx, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_flags, qrw.bar + 128, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+}
+
+// Lockstep form of enqueue_step for batches: the snapshot is enqueued and the
+// sweep's operations are returned as a schedule instead of being run.
+std::vector<std::function<void()>> Engine::record_step(double dt) {
+    check_ready(dt);
+    if (adaptive) throw Error(TTN_E_INVALID, "lockstep batches do not take subspace expansion");
+    save_snapshot();
+    std::vector<std::function<void()>> ops;
+    rec = &ops;
+    solve_idx = 0;
+    const double h = 0.5 * dt;
+    try {
+        sweep_S(t.root, h);
+        emit([=] { forward(t.root, dt); });
+        sweep_Sstar(t.root, h);
+    } catch (...) {
+        rec = nullptr;
+        throw;
+    }
+    rec = nullptr;
+    return ops;
+}
+
+void Engine::finish_record() {
+    enqueue_stats();
     HIPCHK(hipEventRecord(step_done, st));
 }
 
 void Engine::enqueue_step(double dt) {
     check_ready(dt);
-    save_snapshot();
-    enqueue_sweep(dt);
+    if (!graph_mode || profile_enabled()) {
+        save_snapshot();
+        enqueue_sweep(dt);
+        return;
+    }
+    // hipGraph form: the launch sequence of a step (snapshot, sweep, statistics
+    // copy) depends only on dt and the Krylov dimension hints, so it is
+    // captured once per such key and replayed; the host-side bookkeeping of a
+    // sweep (solve indices, the even number of buffer swaps per node) comes out
+    // the same as in the capture
+    std::vector<int64_t> key(m_hint.begin(), m_hint.end());
+    int64_t dbits;
+    std::memcpy(&dbits, &dt, sizeof dbits);
+    key.push_back(dbits);
+    GraphEntry *ge = nullptr;
+    for (auto &g : graphs)
+        if (g.key == key) ge = &g;
+    if (!ge) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        try {
+            save_snapshot();
+            enqueue_sweep_body(dt);
+        } catch (...) {
+            (void)hipStreamEndCapture(st, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(st, &graph));
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) throw Error(TTN_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        if (graphs.size() >= 8) {  // keep the most recent keys
+            (void)hipGraphExecDestroy(graphs.front().exec);
+            graphs.erase(graphs.begin());
+        }
+        graphs.push_back({key, exec, solve_idx});
+        ge = &graphs.back();
+        ++counters_graph_captures;
+    }
+    solve_idx = ge->n_solves;
+    HIPCHK(hipGraphLaunch(ge->exec, st));
+    HIPCHK(hipEventRecord(step_done, st));
+}
+
+void Engine::drop_graphs() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
 }
 
 // Wait for the enqueued sweep, update the Krylov dimension hints and, if a

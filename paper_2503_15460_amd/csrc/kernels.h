@@ -38,6 +38,7 @@ struct DevEntry {
     double2 coef;
     int nf;
     int group;
+    int src;  // input slice the entry reads (ProgView::in_stride apart; 0 for ordinary programs)
     int slot[MAXF];
     int lo[MAXF];
     int hi[MAXF];
@@ -52,6 +53,8 @@ struct CombJob {
     int n2;     // elements of the matrix
     int first;  // sources srcs[first .. first + count)
     int count;
+    int n;      // rows = columns (for the transposing modes)
+    int mode;   // 0: sum coef src; 1: transpose; 2: conjugate; 3: conjugate transpose (coef applied as given)
 };
 struct CombSrc {
     double2 coef;
@@ -75,6 +78,7 @@ struct ProgView {
     unsigned short *mprep;    // bf16 hi/lo realified factors, n_ent * 2 * 128 * 128 (BF16x3 mode)
     double2 *tmp;             // 2 * n_ent * N (float2 elements in the FP32 mode)
     double2 *gsum;            // n_groups * N (float2 elements in the FP32 mode)
+    int64_t in_stride;        // distance of the input slices read by entries with src > 0
     double2 *cpart;           // contraction partials
     double sflops[MAXF];      // algorithmic flops / bytes of each stage launch (host side)
     double sbytes[MAXF];
@@ -171,6 +175,13 @@ struct ProfileSuspend {
 
 // ---- launchers (all asynchronous on `st`) ----
 void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st);
+// tile autotuner: time every admissible register tile of each tiled stage of p
+// and keep the fastest (process-wide table, keyed by the stage's shape)
+void tune_prog_stages(const ProgView &p, const double2 *in, hipStream_t st);
+size_t tile_table_size();
+void tile_table_save(const char *path);
+int tile_table_load(const char *path);
+void tile_table_clear();
 void launch_prog_sum(const ProgView &p, const double2 *in, double2 *out_single, hipStream_t st);
 void launch_prog_contract(const ProgView &p, const double2 *A, hipStream_t st);
 
@@ -188,8 +199,41 @@ void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int
 bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, QRWork &q,
                     hipStream_t st);
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st);
+// independent fused solves in one launch (work-group b takes d_args[b]; h_args
+// is the host copy of the same array, for the launch shape)
+void launch_small_solve_group(const SmallSolveArgs *d_args, const std::vector<SmallSolveArgs> &h_args,
+                              hipStream_t st);
 void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st);
 void launch_combine(const CombJob *jobs, const CombSrc *srcs, int n_jobs, int max_n2, hipStream_t st);
+
+// ---- subspace expansion pieces ----
+// out[g * n + j] = sum_{l,r} op(A[l, j, r]) B[g * bstride + l * R + r] for g < groups
+// (op: conj when conjA), through partial sums in `part`.
+void launch_ts_contract(const double2 *A, int64_t L, int n, int64_t R, int conjA, const double2 *B,
+                        int64_t bstride, int groups, double2 *out, double2 *part, hipStream_t st);
+// out[g * L * R + l * R + r] = base[...] - sum_j op(A[l, j, r]) S[g * n + j] (base NULL: no base,
+// the sum itself); op: conj when conjA
+void launch_ts_expand(const double2 *A, int64_t L, int n, int64_t R, int conjA, const double2 *S, int groups,
+                      const double2 *base, int negate, double2 *out, hipStream_t st);
+// Y[l, j, r] (slot size n_new) from X[l, j, r] (slot size n_old): copied for j < min(n_old, n_new),
+// beyond n_old taken from the vectors V (vector j - n_old at V + (j - n_old) * vstride, element l * R + r,
+// conjugated when conjV) or zero when V is NULL
+void launch_repack(const double2 *X, double2 *Y, int64_t L, int n_old, int n_new, int64_t R, const double2 *V,
+                   int64_t vstride, int conjV, hipStream_t st);
+// seeded complex start vector: re, im uniform in [-1, 1) from SplitMix64(seed + 2 i), (seed + 2 i + 1)
+void launch_seed_vector(double2 *v, int64_t N, uint64_t seed, hipStream_t st);
+// singular value decomposition of the real upper-bidiagonal matrix with diagonal alpha[0..n) and
+// superdiagonal beta[0..n-1), n read from nptr and at most 48 (one-sided Jacobi); s (descending),
+// U and V (n x n, column j belongs to s[j], row-major with leading dimension nmax)
+void launch_bidiag_svd(const double *alpha, const double *beta, const int *nptr, int nmax, double *s, double *U,
+                       double *V, hipStream_t st);
+// out[c * N + i] = sum_{q < n} W[q * ldw + c] V[q * N + i] for c < ncols (W real), n read from nptr
+void launch_basis_combine(const double2 *V, int64_t N, const int *nptr, const double *W, int ldw, int ncols,
+                          double2 *out, hipStream_t st);
+// n = dimension of the Golub-Kahan-Lanczos bidiagonal after m steps (breakdown flags of both bases)
+void launch_gkl_count(const int *meffP, const int *meffQ, const double *alpha0, int m, int *n, hipStream_t st);
+// dst[i] = src[i] for i < count (doubles), device to device in stream order
+void launch_copy_scalars(double *dst, const double *src, int count, hipStream_t st);
 void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st);
 
 // multi-kernel Krylov pieces

@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -152,7 +154,8 @@ __global__ void __launch_bounds__(256) k_mode_stage(ProgView p, int stage, const
     const uint32_t N = (uint32_t)p.g.N;
     T *tmp = reinterpret_cast<T *>(p.tmp);
     const TS *__restrict__ src =
-        stage == 0 ? in : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
+        stage == 0 ? in + (int64_t)E->src * p.in_stride
+                   : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
     T *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
     const int blo = E->lo[stage], bhi = E->hi[stage];
     extern __shared__ double2 smt_raw[];
@@ -209,7 +212,8 @@ __global__ void __launch_bounds__(256) k_mode_tile(ProgView p, int stage, const 
     const double2 *__restrict__ M = E->M[stage];
     T *tmp = reinterpret_cast<T *>(p.tmp);
     const TS *__restrict__ src =
-        stage == 0 ? in : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
+        stage == 0 ? in + (int64_t)E->src * p.in_stride
+                   : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
     T *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
     __shared__ T Ms[KC * NP];  // Ms[k * NP + i] = M[i][j0 + k]
     __shared__ T Xs[KC * CW];  // Xs[k * CW + cc] = X[j0 + k] of column c0 + cc
@@ -342,7 +346,8 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
     const unsigned short *mhi = mprep + (size_t)e * 2 * RD * RD, *mlo = mhi + (size_t)RD * RD;
     float2 *tmp = reinterpret_cast<float2 *>(p.tmp);
     const TS *__restrict__ src =
-        stage == 0 ? in : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
+        stage == 0 ? in + (int64_t)E->src * p.in_stride
+                   : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
     float2 *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nR = (uint32_t)n * R;
@@ -476,7 +481,8 @@ __global__ void __launch_bounds__(256) k_group_sum(ProgView p, const double2 *__
         for (int q = q0; q < q1; ++q) {
             const int e = p.gent[q];
             const int nf = p.ent[e].nf;
-            const T v = nf == 0 ? cvt<T>(in[idx]) : tmp[(2 * (size_t)e + ((nf - 1) & 1)) * N + idx];
+            const T v = nf == 0 ? cvt<T>(in[(int64_t)p.ent[e].src * p.in_stride + idx])
+                                : tmp[(2 * (size_t)e + ((nf - 1) & 1)) * N + idx];
             cfma(acc, cvt<T>(p.ent[e].coef), v);
         }
         if (out_single) out_single[idx] = cvt<double2>(acc);
@@ -1591,7 +1597,18 @@ __host__ __device__ inline size_t small_r1_elems(int64_t N, int mmax, int batche
     return a > b ? a : b;
 }
 
-__global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a) {
+__device__ void small_solve(const SmallSolveArgs &a);
+
+__global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallSolveArgs a) { small_solve(a); }
+
+// Grouped form: work-group b solves problem args[b] (independent problems of
+// several instances in one launch; dynamic LDS and threads for the largest).
+__global__ void __launch_bounds__(SMALL_THREADS) k_small_solve_group(const SmallSolveArgs *__restrict__ args) {
+    const SmallSolveArgs a = args[blockIdx.x];
+    small_solve(a);
+}
+
+__device__ void small_solve(const SmallSolveArgs &a) {
     extern __shared__ double2 sm[];
     __shared__ int e1[SMALL_MAXENT];
     __shared__ int tix[SMALL_MAXENT];
@@ -1887,10 +1904,14 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_combine(BigKrylov k, uint32
 __global__ void __launch_bounds__(256) k_combine(const CombJob *__restrict__ jobs, const CombSrc *__restrict__ srcs) {
     const CombJob J = jobs[blockIdx.y];
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < J.n2; i += gridDim.x * blockDim.x) {
+        // element read for output i: transposed modes read (col, row)
+        const int si = (J.mode & 1) ? (i % J.n) * J.n + i / J.n : i;
         double2 acc = make_double2(0.0, 0.0);
         for (int q = 0; q < J.count; ++q) {
             const CombSrc S = srcs[J.first + q];
-            cfma(acc, S.coef, S.src[i]);
+            double2 v = S.src[si];
+            if (J.mode & 2) v.y = -v.y;
+            cfma(acc, S.coef, v);
         }
         J.dst[i] = acc;
     }
@@ -1904,6 +1925,219 @@ __global__ void k_transpose(double2 *dst, const double2 *src, int n) {
         int i = q / n, j = q % n;
         dst[j * n + i] = src[q];
     }
+}
+
+// ============================================================ subspace expansion
+// out[g, j] = sum_{l,r} op(A[l, j, r]) B_g[l, r]: threads (j, row phase), rows of
+// the block's chunk; per-block partials reduced by k_ts_reduce.
+__global__ void __launch_bounds__(256) k_ts_contract_part(const double2 *__restrict__ A, uint32_t L, int n,
+                                                          uint32_t R, int conjA, const double2 *__restrict__ B,
+                                                          int64_t bstride, double2 *__restrict__ part) {
+    const int g = blockIdx.y;
+    const uint32_t rows = L * R;
+    const uint32_t per = (rows + gridDim.x - 1) / gridDim.x;
+    const uint32_t r0 = blockIdx.x * per, r1 = min(rows, r0 + per);
+    const int nph = (int)blockDim.x / 64;
+    const int j = threadIdx.x % 64, ph = threadIdx.x / 64;
+    const double2 *Bg = B + (int64_t)g * bstride;
+    double2 acc = make_double2(0.0, 0.0);
+    if (j < n)
+        for (uint32_t rho = r0 + ph; rho < r1; rho += nph) {
+            const uint32_t l = rho / R, r = rho - l * R;
+            double2 a = A[((size_t)l * n + j) * R + r];
+            if (conjA) a.y = -a.y;
+            cfma(acc, a, Bg[rho]);
+        }
+    __shared__ double2 red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (ph == 0 && j < n) {
+        double2 s = red[j];
+        for (int q = 1; q < nph; ++q) s = cadd(s, red[q * 64 + j]);
+        part[((size_t)g * gridDim.x + blockIdx.x) * n + j] = s;
+    }
+}
+
+__global__ void k_ts_reduce(const double2 *__restrict__ part, int nblk, int n, int groups, double2 *out) {
+    for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < n * groups; o += gridDim.x * blockDim.x) {
+        const int g = o / n, j = o - g * n;
+        double2 s = make_double2(0.0, 0.0);
+        for (int b = 0; b < nblk; ++b) s = cadd(s, part[((size_t)g * nblk + b) * n + j]);
+        out[o] = s;
+    }
+}
+
+// out[g, l, r] = (base ? base[g, l, r] : 0) -+ sum_j op(A[l, j, r]) S[g, j]: one row per
+// thread, eight groups at a time, S staged in LDS
+__global__ void __launch_bounds__(256) k_ts_expand(const double2 *__restrict__ A, uint32_t L, int n, uint32_t R,
+                                                   int conjA, const double2 *__restrict__ S, int groups,
+                                                   const double2 *__restrict__ base, int negate,
+                                                   double2 *__restrict__ out) {
+    extern __shared__ double2 Ss[];
+    for (int q = threadIdx.x; q < groups * n; q += blockDim.x) Ss[q] = S[q];
+    __syncthreads();
+    const uint32_t rows = L * R;
+    for (uint32_t rho = blockIdx.x * blockDim.x + threadIdx.x; rho < rows; rho += gridDim.x * blockDim.x) {
+        const uint32_t l = rho / R, r = rho - l * R;
+        const double2 *ap = A + (size_t)l * n * R + r;
+        for (int g0 = 0; g0 < groups; g0 += 8) {
+            double2 acc[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+            for (int j = 0; j < n; ++j) {
+                double2 a = ap[(size_t)j * R];
+                if (conjA) a.y = -a.y;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (g0 + q < groups) cfma(acc[q], a, Ss[(g0 + q) * n + j]);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (g0 + q < groups) {
+                    const size_t o = (size_t)(g0 + q) * rows + rho;
+                    double2 v = negate ? make_double2(-acc[q].x, -acc[q].y) : acc[q];
+                    if (base) v = cadd(base[o], v);
+                    out[o] = v;
+                }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_repack(const double2 *__restrict__ X, double2 *__restrict__ Y, uint32_t L,
+                                                int n_old, int n_new, uint32_t R, const double2 *__restrict__ V,
+                                                int64_t vstride, int conjV) {
+    const uint32_t NY = L * (uint32_t)n_new * R;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < NY; idx += gridDim.x * blockDim.x) {
+        const uint32_t r = idx % R, t = idx / R;
+        const int j = (int)(t % (uint32_t)n_new);
+        const uint32_t l = t / (uint32_t)n_new;
+        double2 v = make_double2(0.0, 0.0);
+        if (j < n_old) {
+            v = X[((size_t)l * n_old + j) * R + r];
+        } else if (V) {
+            v = V[(int64_t)(j - n_old) * vstride + (int64_t)l * R + r];
+            if (conjV) v.y = -v.y;
+        }
+        Y[idx] = v;
+    }
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    // SplitMix64 (Steele, Lea, Flood 2014): the state x advanced by the golden gamma, then mixed
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_seed_vector(double2 *v, uint32_t N, uint64_t seed) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const uint64_t a = splitmix64(seed + 2ull * i), b = splitmix64(seed + 2ull * i + 1ull);
+        v[i] = make_double2(2.0 * ((double)(a >> 11) * 0x1.0p-53) - 1.0, 2.0 * ((double)(b >> 11) * 0x1.0p-53) - 1.0);
+    }
+}
+
+// One-sided Jacobi SVD of the real n x n upper bidiagonal (one wavefront; row i
+// of the working matrix and of V on lane i).  Columns are rotated until every
+// pair is orthogonal to 1e-15 relative; singular values are the column norms.
+constexpr int SVD_NMAX = 48;  // largest bidiagonal (LDS of the working matrix and of V)
+__global__ void __launch_bounds__(64) k_bidiag_svd(const double *alpha, const double *beta, const int *nptr, int nmax,
+                                                   double *s_out, double *U, double *V) {
+    __shared__ double W[SVD_NMAX * SVD_NMAX], Vs[SVD_NMAX * SVD_NMAX], sv[SVD_NMAX];
+    __shared__ int perm[SVD_NMAX];
+    const int i = threadIdx.x;
+    const int n = min(*nptr, min(nmax, SVD_NMAX));
+    for (int q = i; q < SVD_NMAX * SVD_NMAX; q += 64) {
+        W[q] = 0.0;
+        Vs[q] = 0.0;
+    }
+    __syncthreads();
+    if (i < n) {
+        W[i * SVD_NMAX + i] = alpha[i];
+        if (i + 1 < n) W[i * SVD_NMAX + i + 1] = beta[i];
+        Vs[i * SVD_NMAX + i] = 1.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        int rotated = 0;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double ap = i < n ? W[i * SVD_NMAX + p] : 0.0, aq = i < n ? W[i * SVD_NMAX + q] : 0.0;
+                const double a = wave_sum(ap * ap), b = wave_sum(aq * aq), g = wave_sum(ap * aq);
+                if (fabs(g) <= 1e-15 * sqrt(a * b) || g == 0.0) continue;
+                rotated = 1;
+                const double zeta = (b - a) / (2.0 * g);
+                const double tn = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + tn * tn), sn = c * tn;
+                if (i < n) {
+                    W[i * SVD_NMAX + p] = c * ap - sn * aq;
+                    W[i * SVD_NMAX + q] = sn * ap + c * aq;
+                    const double vp = Vs[i * SVD_NMAX + p], vq = Vs[i * SVD_NMAX + q];
+                    Vs[i * SVD_NMAX + p] = c * vp - sn * vq;
+                    Vs[i * SVD_NMAX + q] = sn * vp + c * vq;
+                }
+                __syncthreads();
+            }
+        if (!rotated) break;
+    }
+    for (int j = 0; j < n; ++j) {
+        const double w = i < n ? W[i * SVD_NMAX + j] : 0.0;
+        const double nr = sqrt(wave_sum(w * w));
+        if (i == 0) sv[j] = nr;
+    }
+    __syncthreads();
+    if (i == 0) {  // descending order
+        for (int j = 0; j < n; ++j) perm[j] = j;
+        for (int a = 0; a < n; ++a)
+            for (int b = a + 1; b < n; ++b)
+                if (sv[perm[b]] > sv[perm[a]]) {
+                    const int t = perm[a];
+                    perm[a] = perm[b];
+                    perm[b] = t;
+                }
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const int c = perm[j];
+        const double sg = sv[c];
+        if (i == 0) s_out[j] = sg;
+        if (i < n) {
+            U[i * nmax + j] = sg > 0.0 ? W[i * SVD_NMAX + c] / sg : 0.0;
+            V[i * nmax + j] = Vs[i * SVD_NMAX + c];
+        }
+    }
+}
+
+__global__ void k_basis_combine(const double2 *__restrict__ V, uint32_t N, const int *nptr, const double *W, int ldw,
+                                int ncols, double2 *out) {
+    const int n = *nptr;
+    const int c = blockIdx.y;
+    if (c >= ncols) return;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int q = 0; q < n; ++q) {
+            const double w = W[q * ldw + c];
+            const double2 v = V[(size_t)q * N + i];
+            acc.x = fma(w, v.x, acc.x);
+            acc.y = fma(w, v.y, acc.y);
+        }
+        out[(size_t)c * N + i] = acc;
+    }
+}
+
+// Dimension of the Golub-Kahan-Lanczos bidiagonal after m steps: the first
+// vanishing alpha (left side) or beta (right side) ends it; alpha_0 = 0 leaves none.
+__global__ void k_gkl_count(const int *meffP, const int *meffQ, const double *alpha0, int m, int *n) {
+    if (threadIdx.x != 0) return;
+    int k = m;
+    if (*meffP > 0) k = min(k, *meffP);
+    if (*meffQ > 0) k = min(k, *meffQ);
+    if (!(*alpha0 > 0.0)) k = 0;
+    *n = k;
+}
+
+__global__ void k_copy_scalars(double *dst, const double *src, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
 }
 
 // ============================================================ launch profiler
@@ -2054,21 +2288,152 @@ static inline unsigned grid_for(int64_t n, int threads, int cap = 2048) {
     return (unsigned)b;
 }
 
-// tiled stage: the row padding NP = RG * TI is chosen from the stage's largest factor
+// ------------------------------------------------------------ tile autotuner
+// The tiled stage is instantiated for several register tiles (TI rows per
+// thread, RG row groups, NP = TI * RG >= the stage's largest factor).  Without
+// a table entry the tile comes from a fixed rule of the factor size; the
+// autotuner times every admissible tile on the stage itself (same program,
+// same launch shape) and records the fastest under a key of the stage's shape.
+// The tile does not change the order of any accumulation, so results are bit
+// for bit the same whichever tile runs.
+struct TileCand {
+    int ti, rg;
+};
+static const TileCand TILE_CANDS[] = {{1, 8}, {2, 8}, {4, 8}, {1, 16}, {2, 16}, {3, 16}, {4, 16}, {1, 32}, {2, 32}};
+struct TileChoice {
+    int ti, rg;
+    double us;
+};
+static std::map<std::string, TileChoice> &tile_table() {
+    static std::map<std::string, TileChoice> t;
+    return t;
+}
+
+static std::string tile_key(const ProgView &p, int s) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s|nmax=%d|nmin=%d|N=%lld|ents=%d|R1=%d", p.f32 ? "f32" : "f64", p.snmax[s],
+             p.snmin[s], (long long)p.g.N, p.n_ent, p.g.R[p.g.D - 1] == 1 ? 1 : 0);
+    return buf;
+}
+
+static TileCand tile_rule(int nmax) {
+    if (nmax <= 8) return {1, 8};
+    if (nmax <= 16) return {1, 16};
+    if (nmax <= 32) return {2, 16};
+    if (nmax <= 48) return {3, 16};
+    return {4, 16};
+}
+
 template <typename TS, typename T>
-static void launch_mode_tile_t(const ProgView &p, int s, const TS *in, hipStream_t st, const char *name) {
-    const int nmax = p.snmax[s];
+static void launch_tile_cfg(const ProgView &p, int s, const TS *in, hipStream_t st, const char *name, TileCand c) {
     const uint32_t maxcol = (uint32_t)(p.g.N / p.snmin[s]);
-    auto go = [&](auto kern, int cw) {
+    auto go = [&](auto kern, int rg) {
+        const int cw = 4 * (256 / rg);
         dim3 grid((maxcol + cw - 1) / cw, p.n_ent);
         TTN_LAUNCH(name, p.sflops[s], p.sbytes[s], kern, grid, dim3(256), 0, st, p, s, in);
     };
-    if (nmax <= 8) go(k_mode_tile<TS, T, 1, 8>, 128);
-    else if (nmax <= 16) go(k_mode_tile<TS, T, 1, 16>, 64);
-    else if (nmax <= 32) go(k_mode_tile<TS, T, 2, 16>, 64);
-    else if (nmax <= 48) go(k_mode_tile<TS, T, 3, 16>, 64);
-    else go(k_mode_tile<TS, T, 4, 16>, 64);
+#define TTN_TILE(TI, RG) \
+    if (c.ti == TI && c.rg == RG) return go(k_mode_tile<TS, T, TI, RG>, RG);
+    TTN_TILE(1, 8) TTN_TILE(2, 8) TTN_TILE(4, 8) TTN_TILE(1, 16) TTN_TILE(2, 16) TTN_TILE(3, 16) TTN_TILE(4, 16)
+    TTN_TILE(1, 32) TTN_TILE(2, 32)
+#undef TTN_TILE
+    throw std::runtime_error("tile configuration not instantiated");
 }
+
+// tiled stage: the tile from the autotuner's table, else from the rule
+template <typename TS, typename T>
+static void launch_mode_tile_t(const ProgView &p, int s, const TS *in, hipStream_t st, const char *name) {
+    TileCand c = tile_rule(p.snmax[s]);
+    auto &tab = tile_table();
+    if (!tab.empty()) {
+        auto it = tab.find(tile_key(p, s));
+        if (it != tab.end()) c = {it->second.ti, it->second.rg};
+    }
+    launch_tile_cfg<TS, T>(p, s, in, st, name, c);
+}
+
+template <typename TS, typename T>
+static void tune_stage(const ProgView &p, int s, const TS *in, hipStream_t st) {
+    const std::string key = tile_key(p, s);
+    if (tile_table().count(key)) return;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        throw std::runtime_error("autotuner: hipEventCreate failed");
+    TileChoice best{0, 0, 1e30};
+    const int nmax = p.snmax[s];
+    for (const TileCand &c : TILE_CANDS) {
+        const int np = c.ti * c.rg;
+        if (np < nmax || np > std::max(16, 2 * nmax)) continue;
+        launch_tile_cfg<TS, T>(p, s, in, st, "k_mode_tile_tune", c);  // warm-up
+        double t = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            float ms = 0.f;
+            if (hipEventRecord(a, st) != hipSuccess) throw std::runtime_error("autotuner: event record");
+            launch_tile_cfg<TS, T>(p, s, in, st, "k_mode_tile_tune", c);
+            if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                hipEventElapsedTime(&ms, a, b) != hipSuccess)
+                throw std::runtime_error("autotuner: timing failed");
+            t = std::min(t, 1e3 * (double)ms);
+        }
+        if (t < best.us) best = {c.ti, c.rg, t};
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (best.ti > 0) tile_table()[key] = best;
+}
+
+void tune_prog_stages(const ProgView &p, const double2 *in, hipStream_t st) {
+    if (p.n_ent == 0) return;
+    ProfileSuspend quiet;  // the trial launches are not part of any profile
+    for (int s = 0; s < p.max_nf; ++s) {
+        if (!p.stile[s] || (p.bf16x3 && p.mprep && p.snmin[s] >= 24 && p.snmax[s] <= 64)) continue;
+        if (p.f32) {
+            if (s == 0) tune_stage<double2, float2>(p, s, in, st);
+            else tune_stage<float2, float2>(p, s, (const float2 *)nullptr, st);
+        } else {
+            tune_stage<double2, double2>(p, s, in, st);
+        }
+    }
+}
+
+size_t tile_table_size() { return tile_table().size(); }
+
+// One entry per line: ["key", ti, rg, microseconds]
+void tile_table_save(const char *path) {
+    FILE *f = fopen(path, "w");
+    if (!f) throw std::runtime_error(std::string("cannot write ") + path);
+    fprintf(f, "{\"ttn_tile_table\": 1, \"entries\": [\n");
+    size_t i = 0;
+    for (auto &kv : tile_table())
+        fprintf(f, " [\"%s\", %d, %d, %.3f]%s\n", kv.first.c_str(), kv.second.ti, kv.second.rg, kv.second.us,
+                ++i < tile_table().size() ? "," : "");
+    fprintf(f, "]}\n");
+    fclose(f);
+}
+
+int tile_table_load(const char *path) {
+    FILE *f = fopen(path, "r");
+    if (!f) throw std::runtime_error(std::string("cannot read ") + path);
+    char line[512];
+    int n = 0;
+    while (fgets(line, sizeof line, f)) {
+        const char *q = strstr(line, "[\"");
+        if (!q) continue;
+        char key[256];
+        int ti = 0, rg = 0;
+        double us = 0.0;
+        if (sscanf(q, "[\"%255[^\"]\", %d, %d, %lf]", key, &ti, &rg, &us) != 4) continue;
+        bool ok = false;
+        for (const TileCand &c : TILE_CANDS) ok |= c.ti == ti && c.rg == rg;
+        if (!ok) continue;  // not a tile this build instantiates
+        tile_table()[key] = {ti, rg, us};
+        ++n;
+    }
+    fclose(f);
+    return n;
+}
+
+void tile_table_clear() { tile_table().clear(); }
 
 static void launch_mode_mfma(const ProgView &p, int s, const double2 *in, hipStream_t st) {
     const uint32_t maxcol = (uint32_t)(p.g.N / p.snmin[s]);
@@ -2265,6 +2630,31 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     return true;
 }
 
+static size_t small_solve_total_lds(const SmallSolveArgs &a) {
+    return small_solve_lds_bytes(a.g.N, a.mmax, a.batched, a.nA) + (a.vlds ? small_solve_vlds_bytes(a.g.N, a.mmax) : 0) +
+           (a.mlds ? sizeof(double2) * (size_t)a.mlds_elems : 0);
+}
+
+static int small_solve_threads(const SmallSolveArgs &a);
+
+void launch_small_solve_group(const SmallSolveArgs *d_args, const std::vector<SmallSolveArgs> &h_args,
+                              hipStream_t st) {
+    if (h_args.empty()) return;
+    size_t lds = 0;
+    int threads = 64;
+    for (auto &a : h_args) {
+        const size_t l = small_solve_total_lds(a);
+        if (a.g.N > SMALL_MAX || a.mmax > SMALL_MMAX || l + SMALL_STATIC_LDS > 160 * 1024 || (a.mlds && !a.batched) ||
+            (a.batched && (a.g.D != 2 || a.n_ent > SMALL_MAXENT || a.g.dims[0] * a.g.dims[0] > SMALL_UB)))
+            throw std::runtime_error("grouped small solve out of range");
+        lds = std::max(lds, l);
+        threads = std::max(threads, small_solve_threads(a));
+    }
+    set_lds_limit((const void *)k_small_solve_group, lds);
+    TTN_LAUNCH("k_small_solve", 0.0, 0.0, k_small_solve_group, dim3((unsigned)h_args.size()), dim3(threads), lds, st,
+               d_args);
+}
+
 void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     const size_t lds0 = small_solve_lds_bytes(a.g.N, a.mmax, a.batched, a.nA);
     const size_t lds = lds0 + (a.vlds ? small_solve_vlds_bytes(a.g.N, a.mmax) : 0) +
@@ -2274,7 +2664,11 @@ void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
         (a.batched && (a.g.D != 2 || a.n_ent > SMALL_MAXENT || a.g.dims[0] * a.g.dims[0] > SMALL_UB)))
         throw std::runtime_error("small solve out of range");
     set_lds_limit((const void *)k_small_solve, lds);
-    // work-group size: the problem size rounded up to a wavefront, capped
+    TTN_LAUNCH("k_small_solve", 0.0, 0.0, k_small_solve, dim3(1), dim3(small_solve_threads(a)), lds, st, a);
+}
+
+// work-group size: the problem size rounded up to a wavefront, capped
+static int small_solve_threads(const SmallSolveArgs &a) {
     static int cap = -1;
     if (cap < 0) {
         const char *env = getenv("TTN_SMALL_THREADS");
@@ -2289,7 +2683,7 @@ void launch_small_solve(const SmallSolveArgs &a, hipStream_t st) {
     // LDS latency of the matvec and of the Gram-Schmidt dots better
     if (a.batched && threads < 256) threads = 256;
     if (a.batched && a.g.N > 96) threads = SMALL_THREADS;
-    TTN_LAUNCH("k_small_solve", 0.0, 0.0, k_small_solve, dim3(1), dim3(threads), lds, st, a);
+    return threads;
 }
 
 void launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t st) {
@@ -2300,6 +2694,60 @@ void launch_combine(const CombJob *jobs, const CombSrc *srcs, int n_jobs, int ma
     if (n_jobs <= 0) return;
     TTN_LAUNCH("k_combine", 0.0, 32.0 * max_n2 * n_jobs, k_combine, dim3(grid_for(max_n2, 256, 64), n_jobs),
                dim3(256), 0, st, jobs, srcs);
+}
+
+void launch_ts_contract(const double2 *A, int64_t L, int n, int64_t R, int conjA, const double2 *B,
+                        int64_t bstride, int groups, double2 *out, double2 *part, hipStream_t st) {
+    if (n > 64 || groups < 1) throw std::runtime_error("two-site contraction shape out of range");
+    const int64_t rows = L * R;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(64, (rows + 1023) / 1024));
+    TTN_LAUNCH("k_ts_contract_part", 8.0 * rows * n * groups, 16.0 * rows * (n + groups), k_ts_contract_part,
+               dim3(nb, groups), dim3(256), 0, st, A, (uint32_t)L, n, (uint32_t)R, conjA, B, bstride, part);
+    TTN_LAUNCH("k_ts_reduce", 0.0, 16.0 * nb * n * groups, k_ts_reduce, dim3(grid_for((int64_t)n * groups, 256)),
+               dim3(256), 0, st, (const double2 *)part, nb, n, groups, out);
+}
+
+void launch_ts_expand(const double2 *A, int64_t L, int n, int64_t R, int conjA, const double2 *S, int groups,
+                      const double2 *base, int negate, double2 *out, hipStream_t st) {
+    if (n > 64 || groups < 1 || (size_t)groups * n * sizeof(double2) > 60 * 1024)
+        throw std::runtime_error("two-site expansion shape out of range");
+    const int64_t rows = L * R;
+    TTN_LAUNCH("k_ts_expand", 8.0 * rows * n * groups, 16.0 * rows * (n * ((groups + 7) / 8) + groups), k_ts_expand,
+               dim3(grid_for(rows, 256)), dim3(256), sizeof(double2) * groups * n, st, A, (uint32_t)L, n,
+               (uint32_t)R, conjA, S, groups, base, negate, out);
+}
+
+void launch_repack(const double2 *X, double2 *Y, int64_t L, int n_old, int n_new, int64_t R, const double2 *V,
+                   int64_t vstride, int conjV, hipStream_t st) {
+    const int64_t NY = L * n_new * R;
+    TTN_LAUNCH("k_repack", 0.0, 32.0 * NY, k_repack, dim3(grid_for(NY, 256)), dim3(256), 0, st, X, Y, (uint32_t)L,
+               n_old, n_new, (uint32_t)R, V, vstride, conjV);
+}
+
+void launch_seed_vector(double2 *v, int64_t N, uint64_t seed, hipStream_t st) {
+    TTN_LAUNCH("k_seed_vector", 0.0, 16.0 * N, k_seed_vector, dim3(grid_for(N, 256)), dim3(256), 0, st, v,
+               (uint32_t)N, seed);
+}
+
+void launch_bidiag_svd(const double *alpha, const double *beta, const int *nptr, int nmax, double *s, double *U,
+                       double *V, hipStream_t st) {
+    if (nmax < 1) throw std::runtime_error("bidiagonal SVD: bad leading dimension");
+    TTN_LAUNCH("k_bidiag_svd", 0.0, 0.0, k_bidiag_svd, dim3(1), dim3(64), 0, st, alpha, beta, nptr, nmax, s, U, V);
+}
+
+void launch_basis_combine(const double2 *V, int64_t N, const int *nptr, const double *W, int ldw, int ncols,
+                          double2 *out, hipStream_t st) {
+    if (ncols <= 0) return;
+    TTN_LAUNCH("k_basis_combine", 0.0, 16.0 * N * ncols, k_basis_combine, dim3(grid_for(N, 256), ncols), dim3(256), 0,
+               st, V, (uint32_t)N, nptr, W, ldw, ncols, out);
+}
+
+void launch_gkl_count(const int *meffP, const int *meffQ, const double *alpha0, int m, int *n, hipStream_t st) {
+    TTN_LAUNCH("k_gkl_count", 0.0, 0.0, k_gkl_count, dim3(1), dim3(64), 0, st, meffP, meffQ, alpha0, m, n);
+}
+
+void launch_copy_scalars(double *dst, const double *src, int count, hipStream_t st) {
+    TTN_LAUNCH("k_copy_scalars", 0.0, 16.0 * count, k_copy_scalars, dim3(1), dim3(64), 0, st, dst, src, count);
 }
 
 void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st) {

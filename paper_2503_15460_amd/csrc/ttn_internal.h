@@ -34,9 +34,19 @@ struct Tree {
     // leaf) followed by the parent bond (1 for the root)
     std::vector<std::vector<int>> dims;
     std::vector<int64_t> size;  // number of elements of each node tensor
+    // capacity: the largest bond each bond may reach (subspace expansion), with
+    // the node shapes and sizes at capacity; equal to the bonds without one
+    std::vector<int> cap;
+    std::vector<std::vector<int>> capdims;
+    std::vector<int64_t> capsize;
+    // recompute dims and size from bond
+    void update_dims();
 };
 
-Tree build_tree(int n, const int32_t *parent, const int32_t *local_dim, const int32_t *bond_req);
+// bond_max (may be NULL): per node, the largest bond the subspace expansion
+// may grow that bond to (clamped like the requests; never below the bond)
+Tree build_tree(int n, const int32_t *parent, const int32_t *local_dim, const int32_t *bond_req,
+                const int32_t *bond_max = nullptr);
 
 // One nonzero of a node's sparse tree-operator tensor (one hSOP channel).
 //   slot[k]: channel id on the bond of child k (>= 1), or -1 for the identity;

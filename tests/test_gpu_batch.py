@@ -25,6 +25,35 @@ def _make(T, p, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_lockstep_batch_equals_individual_steps(T, precision):
+    """Lockstep layers (one grouped launch of the fused solver per layer, all
+    instances on one stream) give the results of stepping each instance
+    alone; the grouped work-group can be wider than an instance's own, which
+    changes reduction order only (agreement to rounding)."""
+    probs = batch_sbm_problems(seed=11, n_inst=7, nmin=3, nmax=10, dmin=4, dmax=8, bmin=4, bmax=14)
+    batch = [_make(T, p, precision) for p in probs]
+    alone = [_make(T, p, precision) for p in probs]
+    dts = np.array([p.dt * (1.0 + 0.1 * i) for i, p in enumerate(probs)])
+    b = T.TTNBatch(batch, lockstep=True)
+    T.profile_begin()
+    b.step(dts, 4)
+    prof = {r["name"]: r for r in T.profile_end()}
+    T.profile_begin()
+    for g, dt in zip(alone, dts):
+        g.step(dt, 4)
+    prof_alone = {r["name"]: r for r in T.profile_end()}
+    for gb, ga, p in zip(batch, alone, probs):
+        assert gb.counters()["steps"] == 4
+        assert abs(gb.expect(p.observables["sz"]) - ga.expect(p.observables["sz"])) <= 1e-12
+        assert abs(gb.overlap_t0() - ga.overlap_t0()) <= 1e-12
+    # the instances' fused solves went out together: far fewer launches
+    print(f"fused-solver launches: {prof['k_small_solve']['calls']} lockstep, "
+          f"{prof_alone['k_small_solve']['calls']} one instance at a time")
+    assert prof["k_small_solve"]["calls"] < prof_alone["k_small_solve"]["calls"] / 2
+    b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_batch_equals_individual_steps(T, precision):
     probs = batch_sbm_problems(seed=11, n_inst=7, nmin=3, nmax=10, dmin=4, dmax=8, bmin=4, bmax=14)
     sizes = [max(int(np.prod(s)) for s in _make(T, p, precision).shapes()) for p in probs]
@@ -61,3 +90,29 @@ def test_batch_errors(T):
     assert "E_INVALID" in str(e.value)
     b.close()
     T.TTNBatch([ok]).close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-4)])
+def test_batch_of_seeded_instances_matches_oracle(T, precision, tol):
+    """The three smallest instances of the 256-instance seeded batch (seed 5;
+    uneven baths, cutoffs and bonds) stepped as one lockstep batch from |up>|0..0>
+    match the stored oracle runs instance by instance after every step (FP64
+    within 1e-9, FP32 contractions within 1e-4)."""
+    import golden_refs as G
+    picks = G.maker.c5_smallest()
+    recs = []
+    for i, p in picks:
+        recs.append(G.reference(f"c5_instance_{i}", p, T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)))
+    gs = [_make(T, p, precision) for _, p in picks]
+    b = T.TTNBatch(gs, lockstep=True)
+    got = []
+    for _ in range(3):
+        b.step(np.array([p.dt for _, p in picks]))
+        got.append([[g.expect(p.observables["sz"]), g.overlap_t0()] for g, (_, p) in zip(gs, picks)])
+    got = np.array(got)  # (steps, instance, observable)
+    for k, ((i, p), rec) in enumerate(zip(picks, recs)):
+        err = np.abs(got[:, k, :] - G.observables(rec)).max()
+        print(f"instance {i} ({p.meta['d']} levels, bond {p.meta['bond']}): max |d<sz>|, |d a(t)| {err:.2e}")
+        assert err < tol
+        assert abs(gs[k].norm2() - rec["norm2"]) < tol
+    b.close()

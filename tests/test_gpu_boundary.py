@@ -61,10 +61,10 @@ def test_caller_workspace(T, make):
 
 def test_reserved_options_refused(T):
     p = sbm_problem(n_modes=2, d=4, bond=2)
-    for field in ("use_graph", "autotune"):
+    for field, value in (("use_graph", 1), ("autotune", 2)):
         opt = T._lib.Options()
         T.lib.ttn_default_options(C.byref(opt))
-        setattr(opt, field, 1)
+        setattr(opt, field, value)
         h = C.c_void_p()
         par = np.ascontiguousarray(p.parent, dtype=np.int32)
         ld = np.ascontiguousarray(p.local_dim, dtype=np.int32)

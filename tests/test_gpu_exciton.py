@@ -72,6 +72,45 @@ def test_exciton_tree_mixed_precisions(T):
         assert ("k_mode_mfma" in names) == (prec == T.TTN_BF16X3)
 
 
+def _obs10(src, p):
+    return np.array([src.expect(p.observables[f"P{k}"]) for k in range(10)] + [src.overlap_t0()])
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-4), (2, 1e-4)])
+def test_c3_shaped_tree_parity(T, prec, tol):
+    """The exciton workload's tree at reduced size (10 states, 60 modes in 30
+    composite leaves, five-leaf C nodes, B(C, C), A1(B, B), A2(B), bonds
+    4/24/28/32: every stage factor of 24..32 qualifies for the matrix cores in
+    BF16x3; 735 SOP terms), three sweeps from a seeded full-rank state against
+    the stored oracle run, per precision: all ten populations and a(t) after
+    every sweep (FP64 to 1e-10, FP32 and BF16x3 contractions to 1e-4), FP64
+    also element-wise on sampled entries of every node tensor."""
+    import golden_refs as G
+    p = G.maker.c3_shaped()
+    bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
+    st = random_isometric_state(p.parent, p.local_dim, bonds, seed=31)
+    rec = G.reference("c3_shaped", p, bonds, st)
+    ref = G.observables(rec)
+    g = T.TTN.from_problem(p, precision=prec)
+    g.set_state(st)
+    T.profile_begin()
+    got = []
+    for _ in range(3):
+        g.step(p.dt)
+        got.append(_obs10(g, p))
+    names = {r["name"] for r in T.profile_end()}
+    got = np.array(got)
+    err = np.abs(got - ref).max(axis=0)
+    print(f"precision {prec}: max error per observable (P0..P9, a(t)) {np.array2string(err, precision=1)}")
+    assert err.max() < tol
+    assert ("k_mode_mfma" in names) == (prec == T.TTN_BF16X3)
+    if prec == T.TTN_FP64:
+        terr = G.tensor_sample_error(rec, g.get_state())
+        print(f"node tensors (sampled) within {terr:.2e}")
+        assert terr < 1e-10
+    g.close()
+
+
 def test_exciton10x120_full_size_properties(T):
     """The full exciton workload (10 states, 120 modes, bonds 8/32/48/64,
     1500 SOP terms: nodes of 7.08M elements, the sizes bench.py times), one

@@ -157,3 +157,29 @@ def test_numerically_hermitian_operator_is_accepted():
     m[0, 1] += 1e-3
     p.op_mats[o] = m
     assert T.hermiticity_defect(p) > 1e-7
+
+
+def test_tile_table_round_trip(tmp_path):
+    """The autotuner's table is persisted as JSON: a saved table loads back
+    with the same entries; entries naming tiles this build lacks are skipped."""
+    T.tile_table_clear()
+    src = tmp_path / "tiles.json"
+    src.write_text('{"ttn_tile_table": 1, "entries": [\n'
+                   ' ["f64|nmax=16|nmin=16|N=65536|ents=12|R1=1", 1, 16, 12.5],\n'
+                   ' ["f32|nmax=48|nmin=48|N=7077888|ents=71|R1=1", 3, 16, 300.25],\n'
+                   ' ["f64|nmax=8|nmin=8|N=4096|ents=3|R1=0", 5, 7, 1.0]\n'
+                   ']}\n')
+    assert T.tile_table_load(str(src)) == 2
+    assert T.tile_table_size() == 2
+    out = tmp_path / "saved.json"
+    T.tile_table_save(str(out))
+    import json
+    rec = json.loads(out.read_text())
+    assert sorted(e[0] for e in rec["entries"]) == sorted([
+        "f64|nmax=16|nmin=16|N=65536|ents=12|R1=1", "f32|nmax=48|nmin=48|N=7077888|ents=71|R1=1"])
+    T.tile_table_clear()
+    assert T.tile_table_size() == 0
+    assert T.tile_table_load(str(out)) == 2
+    T.tile_table_clear()
+    with pytest.raises(T.TTNError):
+        T.tile_table_load(str(tmp_path / "missing.json"))

@@ -503,3 +503,21 @@ def test_heom_full_bond_arnoldi_is_exact():
     assert np.abs(o.dense_state() - exact).max() < 1e-11
     tr = _heom_bra(p, p.meta["bra_tr"])
     assert abs(o.bilinear(tr) - 1.0) < 1e-12
+
+
+def test_recorded_jitter_floors_bound_the_parity_tolerances():
+    """The measured jitter floors J (tests/golden/jitter.json, written by
+    tests/golden/measure_jitter.py from the oracle alone: BLAS thread count,
+    1e-15 coefficient perturbations and 1e-16 noise before every QR) sit at
+    least ten times below the FP64 parity tolerances the GPU tests use."""
+    import json
+    import os
+    import test_gpu_parity as gp
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "jitter.json")
+    rec = json.load(open(path))
+    for name, r in rec.items():
+        print(f"J({name}) = {r['J']:.2e}")
+    assert max(1e-10, 10 * rec["sbm4_product_state_40_steps"]["J"]) <= gp.TOL
+    assert max(1e-10, 10 * rec["reduced_vibronic_full_rank_6_steps"]["J"]) <= gp.TOL
+    assert max(1e-10, 10 * rec["vibronic24_full_rank_3_steps"]["J"]) <= gp.TOL
+    assert 10 * rec["reduced_vibronic_product_state_6_steps"]["J"] <= gp.JTOL_VIB
