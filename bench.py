@@ -150,9 +150,12 @@ def error_vs_fp64(T, p, obs, precisions, steps, seed):
         g = T.TTN.from_problem(p, precision=PRECISIONS[name])
         g.set_state(st)
         rows = []
-        for _ in range(steps):
+        for k in range(steps):
+            t0 = time.perf_counter()
             g.step(p.dt)
-            rows.append([g.expect(p.observables[k]) for k in obs] + [g.overlap_t0()])
+            rows.append([g.expect(p.observables[o]) for o in obs] + [g.overlap_t0()])
+            print(f"bench.py: {p.name} {name} from a full-rank state, sweep {k + 1}/{steps}: "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         runs[name] = np.array(rows)
         g.close()
     out = {"start": f"seeded full-rank isometric state (seed {seed})", "steps": steps,
@@ -260,40 +263,77 @@ def heom_line(T, steps: int):
     return out
 
 
-def batch_line(T, n_inst: int, steps: int):
+def batch_line(T, n_inst: int, steps: int, warmup: int):
     """Uneven spin-boson instances (8-64 modes, 6-16 levels, bonds 8-48): one
-    at a time in FP64 against one batch (FP64 and FP32)."""
+    at a time in FP64 against one batch in FP32-mixed on several streams, and
+    in lockstep sweep layers (one grouped launch of the fused solver per layer)
+    with and without step graphs."""
     import torch
     from workloads import batch_sbm_problems
     probs = batch_sbm_problems(seed=5, n_inst=n_inst)
     dts = np.array([p.dt for p in probs])
     res = {}
-    for name in ("fp64", "fp32"):
+    for name, prec, mode, graph in (("sequential_fp64", 0, None, False), ("streams_fp32", 1, "streams", False),
+                                    ("lockstep_fp32", 1, "lockstep", False), ("streams_graph_fp32", 1, "streams", True)):
         gs = []
         for p in probs:
-            g = T.TTN.from_problem(p, precision=PRECISIONS[name])
+            g = T.TTN(p.parent, p.local_dim, p.bond_dim, precision=prec, use_graph=graph)
+            g.set_sop_problem(p)
             g.set_product_state(p.init_vecs)
-            g.step(p.dt)
             gs.append(g)
-        torch.cuda.synchronize()
-        if name == "fp64":
-            t0 = time.perf_counter()
+        b = None
+        if mode is not None:
+            b = T.TTNBatch(gs, lockstep=(mode == "lockstep"))
+            b.step(dts, warmup)
+        else:
             for g, p in zip(gs, probs):
-                g.step(p.dt, steps)
-            torch.cuda.synchronize()
-            res["sequential_fp64"] = n_inst * steps / (time.perf_counter() - t0)
-        b = T.TTNBatch(gs)
+                g.step(p.dt, warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b.step(dts, steps)
+        if b is not None:
+            b.step(dts, steps)
+        else:
+            for g, p in zip(gs, probs):
+                g.step(p.dt, steps)
         torch.cuda.synchronize()
-        res[f"batched_{name}"] = n_inst * steps / (time.perf_counter() - t0)
-        b.close()
+        res[name] = n_inst * steps / (time.perf_counter() - t0)
+        if b is not None:
+            b.close()
         for g in gs:
             g.close()
-    return {"unit": "instance-sweeps/s", **res,
-            "speedup_batched_fp32_vs_sequential_fp64": res["batched_fp32"] / res["sequential_fp64"],
-            "workload": f"{n_inst} of the 256 seeded uneven spin-boson instances (seed 5), {steps} timed sweeps each"}
+    best = max(res["streams_fp32"], res["lockstep_fp32"], res["streams_graph_fp32"])
+    return {"unit": "instance-sweeps/s", **res, "speedup_best_fp32_vs_sequential_fp64": best / res["sequential_fp64"],
+            "note": "streams_graph_fp32: step graphs (use_graph) on several streams",
+            "workload": f"{n_inst} of the 256 seeded uneven spin-boson instances (seed 5), {warmup} warm-up and "
+                        f"{steps} timed sweeps each"}
+
+
+def adaptive_line(T, steps: int):
+    """The exciton workload with subspace expansion (Sec. II D) from bonds of 8
+    (spawning tolerance 1e-6, bonds up to 8/32/48/64 per layer), FP32-mixed:
+    sweeps/s and how the bonds grew."""
+    import torch
+    from workloads import exciton_problem
+    p = exciton_problem()
+    start = np.minimum(np.asarray(p.bond_dim), 8)
+    g = T.TTN(p.parent, p.local_dim, start, precision=PRECISIONS["fp32"], spawn_tol=1e-6, bond_max=p.bond_dim,
+              seed=3)
+    g.set_sop_problem(p)
+    g.set_product_state(p.init_vecs)
+    b0 = int(g.bonds().sum())
+    per = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        g.step(p.dt)
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - t0)
+    b = g.bonds()
+    out = {"unit": "sweeps/s", "value": steps / sum(per), "seconds_per_sweep": per, "bond_sum_start": b0,
+           "bond_sum_end": int(b.sum()), "largest_bond": int(b.max()), "norm_minus_1": g.norm2() - 1.0,
+           "workload": "exciton10x120 from bonds of 8, spawning tolerance 1e-6 (|dt/2| sigma), FP32-mixed, "
+                       f"{steps} sweeps from the product state"}
+    g.close()
+    return out
 
 
 def main():
@@ -306,7 +346,8 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the error runs from a full-rank start")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--only", choices=list(PRECISIONS), help="time one precision only (profiling runs)")
-    ap.add_argument("--batch-instances", type=int, default=8)
+    ap.add_argument("--batch-instances", type=int, default=32)
+    ap.add_argument("--batch-steps", type=int, default=2)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -377,7 +418,8 @@ def main():
         # context lines: a failure there is recorded and the headline still printed
         for key, fn in (("vibronic24", lambda: vibronic_line(T, 30, 3, not args.no_cpu_baseline)),
                         ("heom_sbm", lambda: heom_line(T, 3)),
-                        ("batched_instances", lambda: batch_line(T, args.batch_instances, 1))):
+                        ("exciton10x120_adaptive", lambda: adaptive_line(T, 3)),
+                        ("batched_instances", lambda: batch_line(T, args.batch_instances, args.batch_steps, 2))):
             try:
                 config[key] = fn()
             except (T.TTNError, RuntimeError, MemoryError) as e:

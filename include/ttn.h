@@ -272,11 +272,12 @@ ttn_status ttn_profile_end(ttn_kernel_stat *rows, int32_t max_rows, int32_t *n_r
 ttn_status ttn_batch_create(int32_t n, ttn_t const *insts, int32_t n_streams, ttn_batch_t *out);
 ttn_status ttn_batch_step(ttn_batch_t b, const double *dt, int32_t n_steps);
 /* Lockstep mode (on = 1; 0 returns to the streams): every instance runs on the
- * batch's first stream and a step proceeds in sweep layers, layer j running
- * the j-th operation (QR with its environment update, local exponential,
- * absorption) of every instance's sweep; the layer's local exponentials that
- * fit the fused one-work-group solver go out as ONE grouped launch (one
- * work-group per instance).  Results are those of ttn_step on each instance.
+ * batch's first stream and a step proceeds in sweep layers: in layer j every
+ * instance runs its sweep's operations (QRs with their environment updates,
+ * absorptions, multi-kernel local exponentials) up to its j-th local
+ * exponential that fits the fused one-work-group solver, and those
+ * exponentials of all instances go out as ONE grouped launch (one work-group
+ * per instance).  Results are those of ttn_step on each instance.
  * Not with subspace expansion.  After a device error every instance of the
  * batch is unusable.  Errors: TTN_E_INVALID, TTN_E_DEVICE. */
 ttn_status ttn_batch_set_lockstep(ttn_batch_t b, int32_t on);

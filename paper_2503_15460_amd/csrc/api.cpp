@@ -222,18 +222,27 @@ static void lockstep_step(ttn_batch_t b, const double *dt, int &cur) {
     hipStream_t st = b->streams[0];
     size_t used = 0;
     std::vector<ttn::SmallSolveArgs> grp;
+    std::vector<size_t> pos(n, 0);
+    // layer j: every instance runs its operations up to and including its j-th
+    // fused local exponential, whose launch is deferred; then the layer's
+    // exponentials go out together
     for (size_t j = 0; j < L; ++j) {
         grp.clear();
+        bool any = false;
         for (cur = 0; cur < n; ++cur) {
-            if (j >= sched[cur].size()) continue;
             ttn::Engine &e = *b->insts[cur]->eng;
             e.defer_fused = true;
             e.deferred.clear();
-            sweep_guard([&] { sched[cur][j](); });
+            while (pos[cur] < sched[cur].size() && e.deferred.empty()) {
+                sweep_guard([&] { sched[cur][pos[cur]](); });
+                ++pos[cur];
+                any = true;
+            }
             e.defer_fused = false;
             grp.insert(grp.end(), e.deferred.begin(), e.deferred.end());
         }
         cur = -1;
+        if (!any) break;
         if (grp.empty()) continue;
         std::memcpy(b->h_args + used, grp.data(), sizeof(ttn::SmallSolveArgs) * grp.size());
         if (hipMemcpyAsync(b->d_args + used, b->h_args + used, sizeof(ttn::SmallSolveArgs) * grp.size(),

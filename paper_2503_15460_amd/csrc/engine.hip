@@ -1416,7 +1416,11 @@ void Engine::enqueue_step(double dt) {
     // captured once per such key and replayed; the host-side bookkeeping of a
     // sweep (solve indices, the even number of buffer swaps per node) comes out
     // the same as in the capture
-    std::vector<int64_t> key(m_hint.begin(), m_hint.end());
+    // key: dt and the Krylov dimensions of the multi-kernel solves (they fix the
+    // launch sequence); the fused solver's hint only says when it first checks
+    // convergence, so a replay keeps the hint of its capture
+    std::vector<int64_t> key;
+    for (size_t i = 0; i < m_hint.size(); ++i) key.push_back(solve_small[i] ? -1 : m_hint[i]);
     int64_t dbits;
     std::memcpy(&dbits, &dt, sizeof dbits);
     key.push_back(dbits);

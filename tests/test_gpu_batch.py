@@ -28,8 +28,12 @@ def _make(T, p, precision):
 def test_lockstep_batch_equals_individual_steps(T, precision):
     """Lockstep layers (one grouped launch of the fused solver per layer, all
     instances on one stream) give the results of stepping each instance
-    alone; the grouped work-group can be wider than an instance's own, which
-    changes reduction order only (agreement to rounding)."""
+    alone.  The grouped work-group can be wider than an instance's own, which
+    changes the reduction order only: FP64 agrees to 1e-12; with FP32
+    contractions the rounding-size differences of the FP64 solves change
+    FP32 roundings downstream, and the product-state start amplifies them
+    (agreement to 1e-6)."""
+    tol = 1e-12 if precision == 0 else 1e-6
     probs = batch_sbm_problems(seed=11, n_inst=7, nmin=3, nmax=10, dmin=4, dmax=8, bmin=4, bmax=14)
     batch = [_make(T, p, precision) for p in probs]
     alone = [_make(T, p, precision) for p in probs]
@@ -44,8 +48,8 @@ def test_lockstep_batch_equals_individual_steps(T, precision):
     prof_alone = {r["name"]: r for r in T.profile_end()}
     for gb, ga, p in zip(batch, alone, probs):
         assert gb.counters()["steps"] == 4
-        assert abs(gb.expect(p.observables["sz"]) - ga.expect(p.observables["sz"])) <= 1e-12
-        assert abs(gb.overlap_t0() - ga.overlap_t0()) <= 1e-12
+        assert abs(gb.expect(p.observables["sz"]) - ga.expect(p.observables["sz"])) <= tol
+        assert abs(gb.overlap_t0() - ga.overlap_t0()) <= tol
     # the instances' fused solves went out together: far fewer launches
     print(f"fused-solver launches: {prof['k_small_solve']['calls']} lockstep, "
           f"{prof_alone['k_small_solve']['calls']} one instance at a time")

@@ -88,3 +88,30 @@ def test_launch_profiler_times_every_kernel(T):
         assert r["calls"] > 0 and r["total_ms"] > 0.0, r
     assert sum(r["total_ms"] for r in rows) < wall_ms
     g.close()
+
+
+def test_autotuned_tiles_give_the_same_results(T, tmp_path):
+    """autotune = 1 times the register tiles of every tiled stage on the
+    handle's own programs and fills the tile table; the tile changes no
+    accumulation order, so the sweep is bit for bit the one of the fixed rule.
+    The table survives a JSON round trip."""
+    from workloads import vibronic_problem
+    p = vibronic_problem(n_modes=12, dmin=4, dmax=8, leaf_bond=6, l_bond=12, m_bond=16)
+    T.tile_table_clear()
+    plain = T.TTN.from_problem(p)
+    plain.set_product_state(p.init_vecs)
+    plain.step(p.dt, 2)
+    tuned = T.TTN(p.parent, p.local_dim, p.bond_dim, autotune=True)
+    tuned.set_sop_problem(p)
+    n = T.tile_table_size()
+    print(f"tile table: {n} stage shapes tuned")
+    assert n > 0
+    tuned.set_product_state(p.init_vecs)
+    tuned.step(p.dt, 2)
+    for a, b in zip(plain.get_state(), tuned.get_state()):
+        assert np.array_equal(a, b)
+    path = str(tmp_path / "tiles.json")
+    T.tile_table_save(path)
+    T.tile_table_clear()
+    assert T.tile_table_load(path) == n
+    T.tile_table_clear()

@@ -18,6 +18,7 @@ bond dimensions) with ``numpy.random.default_rng(seed)`` in a fixed order.
 """
 from __future__ import annotations
 
+import functools
 from typing import Dict, List, Tuple
 
 import numpy as np
@@ -78,6 +79,15 @@ def ohmic_J(w, alpha: float, wc: float):
     return 0.5 * np.pi * alpha * w * np.exp(-w / wc)
 
 
+@functools.lru_cache(maxsize=4)
+def _legendre_grid(nquad: int):
+    """Gauss-Legendre nodes and weights on [-1, 1] (computed once per size)."""
+    x, w = np.polynomial.legendre.leggauss(nquad)
+    x.flags.writeable = False
+    w.flags.writeable = False
+    return x, w
+
+
 def gauss_rule(J, wmin: float, wmax: float, n: int, nquad: int = 4000):
     """N-point Gauss rule for the weight J(w) on [wmin, wmax] (Sec. II E 1).
 
@@ -87,7 +97,7 @@ def gauss_rule(J, wmin: float, wmax: float, n: int, nquad: int = 4000):
     eigen-decomposition of the Jacobi matrix (Golub-Welsch).  Returns
     ``(nodes, weights)`` with ``sum weights_i F(nodes_i) ~ int F J``.
     """
-    x, w = np.polynomial.legendre.leggauss(nquad)
+    x, w = _legendre_grid(nquad)
     t = 0.5 * (wmax - wmin) * x + 0.5 * (wmax + wmin)
     wt = 0.5 * (wmax - wmin) * w * J(t)
     mu0 = wt.sum()
