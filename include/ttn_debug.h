@@ -65,9 +65,13 @@ ttn_status ttn_debug_clamp_bonds(int32_t n_nodes, const int32_t *parent, const i
  * m (x) in row-major (rows, cols), rows >= cols, cols <= 64; q_out receives
  * (rows, cols) and r_out (cols, cols), all complex interleaved host buffers.
  * variant 0: one work-group; 1: many work-groups (one launch per column);
- * 2: many work-groups in one cooperative launch (grid-wide barriers).
+ * 2: many work-groups in one cooperative launch (grid-wide barriers);
+ * 3: the Cholesky route (Cholesky QR twice, reflector signs from an LU of the
+ *    leading block), the variant-1 kernels taking over when the matrix is
+ *    outside its range (rank-deficient, near the zero-snap, ill-conditioned);
+ * 4: the Cholesky route alone: TTN_E_NOCONV when the matrix is outside its range.
  * Uses device 0 and the null stream; allocates and frees its own device memory.
- * Errors: TTN_E_INVALID (shape), TTN_E_DEVICE. */
+ * Errors: TTN_E_INVALID (shape), TTN_E_NOCONV (variant 4), TTN_E_DEVICE. */
 ttn_status ttn_debug_qr(int64_t rows, int32_t cols, const double *m, int32_t variant, double *q_out,
                         double *r_out);
 

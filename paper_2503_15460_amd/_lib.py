@@ -252,7 +252,9 @@ def hermiticity_defect(problem) -> float:
 
 
 def gpu_qr(M: np.ndarray, variant: int):
-    """Q, R of the library's Householder QR kernels (variant 0: one work-group, 1: many)."""
+    """Q, R of the library's QR kernels (variant 0: one work-group, 1: many, 2:
+    cooperative, 3: Cholesky route with the variant-1 kernels behind it, 4:
+    Cholesky route alone, TTN_E_NOCONV outside its range)."""
     A = np.ascontiguousarray(M, dtype=np.complex128)
     rows, cols = A.shape
     Q = np.zeros_like(A)

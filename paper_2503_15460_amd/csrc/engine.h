@@ -34,6 +34,13 @@ struct Prog {
     int comb_max_n2 = 0;
     CombJob *d_cjobs = nullptr;
     CombSrc *d_csrcs = nullptr;
+    // pair-operator form (empty: staged application); device buffers are sized
+    // for the capacity at the first plan and reused by later plans
+    std::vector<PairPass> pair;
+    std::vector<double> pair_flops;       // algorithmic flops of each pass
+    std::vector<float2 *> pair_w;         // per child slot (null: not allocated)
+    std::vector<PairTerm *> pair_dterms;  // per child slot
+    std::vector<int> pair_cap_terms;
 };
 
 class Engine {
@@ -75,6 +82,13 @@ private:
     bool have_sop = false, have_state = false;
     bool adaptive = false;  // subspace expansion on (spawn_tol > 0)
     bool graph_mode = false;  // steps replayed from captured hipGraphs (use_graph)
+    // large QRs take the Cholesky route first (TTN_CHOLQR=0 in the environment:
+    // Householder kernels only)
+    bool cholqr = true;
+    // FP32 effective generators of large nodes in the pair-operator form
+    // (TTN_PAIR_OPS=0 in the environment: staged products only)
+    bool pair_ops = true;
+    int64_t pair_min_n = 1 << 18;  // node size from which the pair form is considered (TTN_PAIR_MIN_N)
     hipStream_t own_stream = nullptr;
     struct GraphEntry {
         std::vector<int64_t> key;  // Krylov dimension hints and dt of the captured step
@@ -164,6 +178,10 @@ private:
     void build_spo(int c);
     void build_mf(int z, int k);
     void apply_prog(const Prog &p, const double2 *in, double2 *out);
+    // one application of an effective-generator program after prep (pair
+    // GEMMs or staged products and the group sum)
+    void launch_apply(const Prog &p, const ProgView &v, const double2 *in, double2 *out);
+    void plan_pairs(Prog &h, int z);
     void sync_check(const char *where);
     void save_snapshot();
     void restore_snapshot();

@@ -46,6 +46,9 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
         if (z != t.root && t.cap[z] > 64) throw Error(TTN_E_DIMS, "bond dimensions above 64 are not supported");
     adaptive = opt.spawn_tol > 0.0;
     graph_mode = opt.use_graph != 0;
+    if (const char *e = getenv("TTN_CHOLQR")) cholqr = atoi(e) != 0;
+    if (const char *e = getenv("TTN_PAIR_OPS")) pair_ops = atoi(e) != 0;
+    if (const char *e = getenv("TTN_PAIR_MIN_N")) pair_min_n = std::max<int64_t>(1, atoll(e));
     if (graph_mode && !st) {  // the null stream cannot be captured: a stream of the handle's own
         HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
         st = own_stream;
@@ -233,6 +236,7 @@ void Engine::merge_entries(Prog &p) {
 
 void Engine::prep(const Prog &p) {
     if (!p.cjobs.empty()) launch_combine(p.d_cjobs, p.d_csrcs, (int)p.cjobs.size(), p.comb_max_n2, st);
+    for (const PairPass &pp : p.pair) launch_pair_build(pp, st);
 }
 
 ProgView Engine::view(const Prog &p) const {
@@ -377,6 +381,7 @@ void Engine::build_node_programs(int z) {
         merge_entries(h);
         finish_groups(h, {nullptr});
         upload(h);
+        plan_pairs(h, z);
         if (!root) {
             // SPO rebuild: groups by own-bond channel (>= 1), children factors only
             Prog &s = spoP[z];
@@ -682,6 +687,17 @@ void Engine::set_sop(const SopInput &s) {
     need(&qrw.cpart, sizeof(double) * 2 * QRM_BLOCKS_MAX * QRC_REC);
     need(&qrw.bar, sizeof(unsigned) * 192);
     qrw.bar_base = 0;
+    // Cholesky route of the QR: Gram partials, small matrices, first-pass factor
+    need(&qrw.cq_part, sizeof(double2) * CQR_BLOCKS_MAX * 64 * 64);
+    need(&qrw.cq_G, sizeof(double2) * 64 * 64);
+    need(&qrw.cq_R1, sizeof(double2) * 64 * 64);
+    need(&qrw.cq_R1inv, sizeof(double2) * 64 * 64);
+    need(&qrw.cq_M, sizeof(double2) * 64 * 64);
+    need(&qrw.cq_Y, sizeof(double2) * maxN);
+    qrw.cq_ycap = maxN;
+    need(&qrw.cq_scal, sizeof(double) * 4);
+    need(&qrw.cq_state, sizeof(int) * 4);
+    need(&qrw.cq_counter, sizeof(unsigned) * 4);
     const int n_solves = (2 * n - 1) + 2 * (n - 1);
     need(&d_stats, sizeof(SolveStat) * n_solves);
     size_t total = 0;
@@ -833,8 +849,104 @@ void Engine::rebuild_all_spos() {
 void Engine::apply_prog(const Prog &p, const double2 *in, double2 *out) {
     prep(p);
     ProgView v = view(p);
+    launch_apply(p, v, in, out);
+}
+
+void Engine::launch_apply(const Prog &p, const ProgView &v, const double2 *in, double2 *out) {
+    if (!p.pair.empty()) {
+        for (size_t i = 0; i < p.pair.size(); ++i) launch_pair_gemm(p.pair[i], in, out, i > 0 ? 1 : 0, p.pair_flops[i], st);
+        return;
+    }
     launch_prog_stages(v, in, st);
     launch_prog_sum(v, in, out, st);
+}
+
+// Pair-operator form of node z's effective generator in the FP32 mode: when
+// every product carries at most one child factor besides the parent factor,
+// the products of child slot k make up W_k = sum_e c_e F_e (x) P_e on the
+// index pair (k, parent), applied as one GEMM on the matrix cores; products
+// with the parent factor alone (or none) join the pass with the most products.
+// Taken for large nodes when each dense pair operator costs at most twice the
+// flops of the products it replaces.
+void Engine::plan_pairs(Prog &h, int z) {
+    h.pair.clear();
+    h.pair_flops.clear();
+    if (opt.precision != TTN_FP32 || !pair_ops || z == t.root || t.local_dim[z] > 0) return;
+    const int D = h.g.D, P = D - 1;
+    int64_t ncap = 1;
+    for (int q = 0; q < D; ++q) ncap *= h.capdims[q];
+    if (ncap < pair_min_n || h.n_groups != 1 || h.contract_slot >= 0 || P < 1) return;
+    std::vector<std::vector<PairTerm>> per(P);
+    std::vector<double> work(P, 0.0), wcur(P, 0.0);  // summed factor dims (capacity / current)
+    std::vector<PairTerm> loose;
+    double loose_work = 0.0, loose_cur = 0.0;
+    for (const DevEntry &e : h.ents) {
+        if (e.src != 0) return;
+        int k = -1;
+        const double2 *F = nullptr, *Pm = nullptr;
+        for (int f = 0; f < e.nf; ++f) {
+            if (e.slot[f] == P) {
+                Pm = e.M[f];
+            } else if (k < 0) {
+                k = e.slot[f];
+                F = e.M[f];
+            } else {
+                return;  // two child factors: no pair form
+            }
+        }
+        const double w = (F ? h.capdims[k] : 0) + (Pm ? h.capdims[P] : 0);
+        const double wc = (F ? h.g.dims[k] : 0) + (Pm ? h.g.dims[P] : 0);
+        if (k < 0) {
+            loose.push_back({e.coef, nullptr, Pm});
+            loose_work += w;
+            loose_cur += wc;
+        } else {
+            per[k].push_back({e.coef, F, Pm});
+            work[k] += w;
+            wcur[k] += wc;
+        }
+    }
+    int home = -1;
+    for (int k = 0; k < P; ++k)
+        if (!per[k].empty() && (home < 0 || per[k].size() > per[home].size())) home = k;
+    if (home < 0) {
+        if (loose.empty()) return;
+        home = 0;
+    }
+    for (auto &x : loose) per[home].push_back(x);
+    work[home] += loose_work;
+    wcur[home] += loose_cur;
+    for (int k = 0; k < P; ++k) {
+        if (per[k].empty()) continue;
+        const double qcap = (double)h.capdims[k] * h.capdims[P];
+        if (qcap > 4096 || qcap > 2.0 * work[k]) return;
+    }
+    if ((int)h.pair_w.size() != P) {
+        h.pair_w.assign(P, nullptr);
+        h.pair_dterms.assign(P, nullptr);
+        h.pair_cap_terms.assign(P, 0);
+    }
+    for (int k = 0; k < P; ++k) {
+        if (per[k].empty()) continue;
+        const int64_t qcap = (int64_t)h.capdims[k] * h.capdims[P];
+        if (!h.pair_w[k]) h.pair_w[k] = (float2 *)dalloc(sizeof(float2) * qcap * qcap);
+        if (h.pair_cap_terms[k] < (int)per[k].size()) {
+            if (h.pair_dterms[k]) throw Error(TTN_E_STATE, "internal: pair-operator terms grew");
+            h.pair_dterms[k] = (PairTerm *)dalloc(sizeof(PairTerm) * per[k].size());
+            h.pair_cap_terms[k] = (int)per[k].size();
+        }
+        HIPCHK(hipMemcpy(h.pair_dterms[k], per[k].data(), sizeof(PairTerm) * per[k].size(), hipMemcpyHostToDevice));
+        PairPass pp{};
+        pp.nk = h.g.dims[k];
+        pp.np = h.g.dims[P];
+        pp.L = h.g.L[k];
+        pp.Mid = h.g.R[k] / h.g.dims[P];
+        pp.W = h.pair_w[k];
+        pp.terms = h.pair_dterms[k];
+        pp.n_terms = (int)per[k].size();
+        h.pair.push_back(pp);
+        h.pair_flops.push_back(8.0 * (double)h.g.N * wcur[k]);
+    }
 }
 
 void Engine::build_spo(int c) {
@@ -863,9 +975,13 @@ void Engine::qr_any(double2 *X, const Geom &g, int s, double2 *Rout, int transR)
     // wide factors of mid-size tensors also leave the single work-group kernel:
     // its column loop is sequential on one compute unit
     const bool coop = g.N >= QR_MULTI_MIN || (g.N >= 4096 && g.dims[s] >= 16);
+    // large matrices first take the Cholesky route; the Householder kernels
+    // behind it run only when the matrix is outside its range (device flag)
+    qrw.gate = nullptr;
+    if (coop && cholqr && launch_qr_chol(X, g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st)) qrw.gate = qrw.cq_state;
     if (coop && !graph_mode && launch_qr_coop(X, g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st)) return;
     if (g.N >= QR_MULTI_MIN) launch_qr_multi(X, g.L[s], g.dims[s], g.R[s], Rout, transR, qrw, st);
-    else launch_qr(X, g.L[s], g.dims[s], g.R[s], Rout, transR, st);
+    else launch_qr(X, g.L[s], g.dims[s], g.R[s], Rout, transR, st, qrw.gate);
 }
 
 void Engine::absorb(int z, int s, const double2 *M, int transM) {
@@ -943,8 +1059,7 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
         launch_krylov_start(x, N, bk, st);
         ProgView v = view(p);
         for (int j = 0; j < m; ++j) {
-            launch_prog_stages(v, bk.V + (size_t)j * N, st);
-            launch_prog_sum(v, bk.V + (size_t)j * N, bk.V + (size_t)(j + 1) * N, st);
+            launch_apply(p, v, bk.V + (size_t)j * N, bk.V + (size_t)(j + 1) * N);
             launch_krylov_orth(bk, N, j, mmax, st);
         }
         launch_krylov_finish(bk, N, m, mmax, tau, tol, opt.hermitian, x, stat, st);
@@ -1702,6 +1817,7 @@ void Engine::apply_root_heff(const double *x, double *y) {
 
 void debug_qr(int64_t rows, int cols, const double *m, int variant, double *q_out, double *r_out) {
     if (rows < cols || cols < 1 || cols > 64) throw Error(TTN_E_INVALID, "QR shape out of range");
+    if (variant < 0 || variant > 4) throw Error(TTN_E_INVALID, "QR variant out of range");
     const size_t nm = (size_t)rows * cols;
     std::vector<void *> mem;
     auto alloc = [&](size_t bytes) {
@@ -1733,7 +1849,29 @@ void debug_qr(int64_t rows, int cols, const double *m, int variant, double *q_ou
             q.cpart = (double *)alloc(sizeof(double) * 2 * QRM_BLOCKS_MAX * QRC_REC);
             q.bar = (unsigned *)alloc(sizeof(unsigned) * 192);
             HIPCHK(hipMemset(q.bar, 0, sizeof(unsigned) * 192));
-            if (variant == 1) launch_qr_multi(A, rows, cols, 1, Rd, 0, q, nullptr);
+            if (variant >= 3) {  // Cholesky route (3: Householder kernels behind it, 4: alone)
+                q.cq_part = (double2 *)alloc(sizeof(double2) * CQR_BLOCKS_MAX * 64 * 64);
+                q.cq_G = (double2 *)alloc(sizeof(double2) * 64 * 64);
+                q.cq_R1 = (double2 *)alloc(sizeof(double2) * 64 * 64);
+                q.cq_R1inv = (double2 *)alloc(sizeof(double2) * 64 * 64);
+                q.cq_M = (double2 *)alloc(sizeof(double2) * 64 * 64);
+                q.cq_Y = (double2 *)alloc(sizeof(double2) * nm);
+                q.cq_ycap = (int64_t)nm;
+                q.cq_scal = (double *)alloc(sizeof(double) * 4);
+                q.cq_state = (int *)alloc(sizeof(int) * 4);
+                q.cq_counter = (unsigned *)alloc(sizeof(unsigned) * 4);
+                HIPCHK(hipMemset(q.cq_counter, 0, sizeof(unsigned) * 4));
+                if (!launch_qr_chol(A, rows, cols, 1, Rd, 0, q, nullptr))
+                    throw Error(TTN_E_INVALID, "QR shape outside the Cholesky route");
+                if (variant == 4) {
+                    int state = 1;
+                    HIPCHK(hipMemcpy(&state, q.cq_state, sizeof(int), hipMemcpyDeviceToHost));
+                    if (state != 0) throw Error(TTN_E_NOCONV, "matrix outside the range of the Cholesky route");
+                } else {
+                    q.gate = q.cq_state;
+                    launch_qr_multi(A, rows, cols, 1, Rd, 0, q, nullptr);
+                }
+            } else if (variant == 1) launch_qr_multi(A, rows, cols, 1, Rd, 0, q, nullptr);
             else if (!launch_qr_coop(A, rows, cols, 1, Rd, 0, q, nullptr))
                 throw Error(TTN_E_INVALID, "cooperative QR grid cannot be co-resident");
             if (variant == 2) {

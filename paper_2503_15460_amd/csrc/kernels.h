@@ -86,6 +86,30 @@ struct ProgView {
     int stile[MAXF];               // stage runs on the tiled kernel (dense factors, n <= 64)
 };
 
+// Pair-operator form of an H_eff program of a large node (FP32 mode): when
+// every product acts on at most one child slot k and the parent slot P, the
+// program is sum_k W_k applied on the index pair (k, P), where the dense pair
+// operator W_k = sum_e c_e F_e (x) P_e ((n_k n_P)^2 elements) is rebuilt from
+// the current factors before each use and applied as one complex GEMM on the
+// matrix cores (rows: the other indices of the node tensor).
+struct PairTerm {
+    double2 coef;
+    const double2 *F;  // n_k x n_k on slot k, or null (identity)
+    const double2 *P;  // n_P x n_P on the parent slot, or null (identity)
+};
+struct PairPass {
+    int nk, np;        // dims of slot k and of the parent slot
+    int64_t L, Mid;    // products of the dims before k and between k and P
+    float2 *W;         // Wt[kappa][q], kappa = (a', b') input pair, q = (a, b) output pair
+    const PairTerm *terms;
+    int n_terms;
+};
+constexpr int PAIR_KC = 16;  // complex K per LDS chunk of the pair GEMM
+void launch_pair_build(const PairPass &pp, hipStream_t st);
+// out (FP64) = (accumulate ? out : 0) + W_k applied to in (FP64) on (k, P)
+void launch_pair_gemm(const PairPass &pp, const double2 *in, double2 *out, int accumulate, double flops,
+                      hipStream_t st);
+
 // Statistics written by one Krylov solve.
 struct SolveStat {
     int m;         // Krylov dimension used (last sub-step)
@@ -151,6 +175,20 @@ struct QRWork {
     double *cpart;              // [2][QRM_BLOCKS_MAX][QRC_REC] column partials of the cooperative QR
     unsigned *bar;              // [192] grid barrier of the cooperative QR (starts at 0); bar[128] != 0: failed
     unsigned long long bar_base;  // arrivals counted in bar[0..1] by the launches made so far (host side)
+    // nullable: the Householder kernels return at once while *gate == 0 (the
+    // Cholesky route of the same launch sequence produced the factors)
+    const int *gate;
+    // Cholesky route (launch_qr_chol)
+    double2 *cq_part;     // [CQR_BLOCKS_MAX][64*64] per-work-group Gram partials
+    double2 *cq_G;        // [64*64] reduced Gram matrix
+    double2 *cq_R1;       // [64*64] first Cholesky factor
+    double2 *cq_R1inv;    // [64*64] its inverse
+    double2 *cq_M;        // [64*64] R2^{-1} S
+    double2 *cq_Y;        // [cq_ycap] first-pass factor A R1^{-1}, row-major m x n
+    int64_t cq_ycap;
+    double *cq_scal;      // [4] |A|_F^2
+    int *cq_state;        // [4] 0: the Cholesky route holds, 1: the Householder kernels run
+    unsigned *cq_counter; // [4] last-block ticket (starts at 0)
 };
 constexpr int QRC_REC = 2 + 4 * 64;  // xn2, fro, g_j (complex), row i (complex)
 
@@ -191,9 +229,20 @@ void launch_mode_product(const double2 *X, double2 *Y, const double2 *M, int64_t
 // out[m,n] = sum_{l,r} conj(A[l,m,r]) B[l,n,r] for (L, nA, R) and (L, nB, R)
 void launch_contract(const double2 *A, const double2 *B, double2 *out, int64_t L, int nA, int nB,
                      int64_t R, double2 *part, hipStream_t st);
-void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st);
+void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st,
+               const int *gate = nullptr);
 void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
                      hipStream_t st);
+// The same factors as the Householder kernels (LAPACK convention) for full-rank
+// matrices away from the zero-snap, by Cholesky QR applied twice and the signs
+// of the reflectors read off an LU factorisation of the leading block; sets
+// *q.cq_state to 1 when the matrix is outside that range, so that the
+// Householder kernels launched next with q.gate = q.cq_state do the work.
+// Returns false (nothing launched) when the shape is not covered.
+bool launch_qr_chol(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
+                    hipStream_t st);
+constexpr int CQR_BLOCKS_MAX = 256;
+constexpr int CQR_TILE = 64;  // rows per LDS tile
 // the same reflectors in one cooperative launch (grid-wide barriers between columns);
 // returns false (nothing launched) when the grid cannot be co-resident
 bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, QRWork &q,

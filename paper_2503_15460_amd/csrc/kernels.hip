@@ -465,6 +465,227 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
     }
 }
 
+// ------------------------------------------------------------ pair-operator form
+// W_k[q][kappa] = sum_e c_e F_e[a][a'] P_e[b][b'] for q = (a, b), kappa = (a', b')
+// (a null factor is the identity), summed in FP64 and stored transposed,
+// Wt[kappa][q], in complex FP32.  Work-group tile: 64 pairs alpha = a n_k + a'
+// by 64 pairs beta = b' n_P + b; the terms pass through LDS in chunks.
+constexpr int PB_TC = 16;
+__global__ void __launch_bounds__(256) k_pair_build(PairPass pp) {
+    const int nk = pp.nk, np = pp.np;
+    const int na = nk * nk, nbt = np * np, Q = nk * np;
+    const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
+    __shared__ double2 Fs[64 * PB_TC];  // Fs[i * PB_TC + t] = c_t F_t[a][a'] of alpha = a0 + i
+    __shared__ double2 Ps[PB_TC * 64];  // Ps[t * 64 + j] = P_t[b][b'] of beta = b0 + j
+    const int ta = threadIdx.x >> 4, tb = threadIdx.x & 15;
+    double2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    for (int t0 = 0; t0 < pp.n_terms; t0 += PB_TC) {
+        const int tc = min(PB_TC, pp.n_terms - t0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * PB_TC; e += blockDim.x) {
+            {
+                const int i = e / PB_TC, t = e % PB_TC;
+                const int al = a0 + i;
+                double2 v = make_double2(0.0, 0.0);
+                if (t < tc && al < na) {
+                    const PairTerm T = pp.terms[t0 + t];
+                    const int a = al / nk, ap = al - a * nk;
+                    const double2 f = T.F ? T.F[(size_t)a * nk + ap] : make_double2(a == ap ? 1.0 : 0.0, 0.0);
+                    v = cmul(T.coef, f);
+                }
+                Fs[e] = v;
+            }
+            {
+                const int t = e / 64, j = e % 64;
+                const int be = b0 + j;
+                double2 w = make_double2(0.0, 0.0);
+                if (t < tc && be < nbt) {
+                    const PairTerm T = pp.terms[t0 + t];
+                    const int bp = be / np, b = be - bp * np;
+                    w = T.P ? T.P[(size_t)b * np + bp] : make_double2(b == bp ? 1.0 : 0.0, 0.0);
+                }
+                Ps[e] = w;
+            }
+        }
+        __syncthreads();
+        for (int t = 0; t < tc; ++t) {
+            double2 f[4], w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[i] = Fs[(4 * ta + i) * PB_TC + t];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[j] = Ps[t * 64 + 4 * tb + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cfma(acc[i][j], f[i], w[j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int al = a0 + 4 * ta + i;
+        if (al >= na) continue;
+        const int a = al / nk, ap = al - a * nk;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int be = b0 + 4 * tb + j;
+            if (be >= nbt) continue;
+            const int bp = be / np, b = be - bp * np;
+            pp.W[(size_t)(ap * np + bp) * Q + a * np + b] = make_float2((float)acc[i][j].x, (float)acc[i][j].y);
+        }
+    }
+}
+
+// out[o; q] (+)= sum_kappa W[q][kappa] in[o; kappa] for the node tensor seen as
+// rows o (the indices other than slot k and the parent slot) by the pair index:
+// element (o; a, b) of o = (l, m) at l n_k R_k + a R_k + m n_P + b, R_k = Mid n_P.
+// One real GEMM on the FP32 matrix cores (v_mfma_f32_32x32x2f32) with the
+// complex values realified: row o of the A operand holds (Re, Im) of in[o; kappa]
+// at columns (2 kappa, 2 kappa + 1); rows (2 kappa, 2 kappa + 1) and columns
+// (2q, 2q + 1) of the B operand hold [[Re W, Im W], [-Im W, Re W]].  Work-group
+// tile: 128 rows by 128 realified columns (4 waves of 64 x 64); chunks of 16
+// complex kappa through LDS, the next chunk's loads in flight during the
+// current one's products.  Tiles are dealt so that the work-groups resident on
+// one XCD (work-groups go to the 8 XCDs in turn) share row and column blocks
+// in that XCD's L2.
+constexpr int PG_BM = 128;
+constexpr int PG_BN = 128;
+constexpr int PG_KR = 2 * PAIR_KC;
+constexpr int PG_AP = PG_KR + 1;
+constexpr int PG_GR = 4;  // row tiles per group of the tile order
+__global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const double2 *__restrict__ X, double2 *__restrict__ Y,
+                                                   int accumulate) {
+    const int nk = pp.nk, np = pp.np;
+    const int Q = nk * np;
+    const int64_t Mid = pp.Mid, Rk = Mid * np;
+    const int64_t M = pp.L * Mid;
+    const unsigned nct = (unsigned)((2 * Q + PG_BN - 1) / PG_BN);
+    const unsigned nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
+    const unsigned ntile = nct * nrt;
+    unsigned rt, ct;
+    {
+        const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
+        const unsigned q8 = ntile / 8, r8 = ntile % 8;
+        const unsigned t = x * q8 + min(x, r8) + pos;
+        const unsigned gsz = PG_GR * nct;
+        const unsigned g = t / gsz, w = t - g * gsz;
+        const unsigned rows_g = min((unsigned)PG_GR, nrt - g * PG_GR);
+        rt = g * PG_GR + w % rows_g;
+        ct = w / rows_g;
+    }
+    __shared__ float As[PG_BM * PG_AP];  // As[row * PG_AP + k']
+    __shared__ float Bs[PG_KR * PG_BN];  // Bs[k' * PG_BN + c']
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t o0 = (int64_t)rt * PG_BM;
+    const int q0 = (int)ct * (PG_BN / 2);
+    // A loads: 128 rows x 16 kappa (8 per thread: rows (tid >> 4) + 16 u, kappa offset tid & 15)
+    // B loads: 16 kappa x 64 q (4 per thread: kappa offset (tid >> 6) + 4 u, q offset tid & 63)
+    int64_t rbase[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t o = o0 + (tid >> 4) + 16 * u;
+        if (o < M) {
+            const int64_t l = o / Mid, m = o - l * Mid;
+            rbase[u] = l * nk * Rk + m * np;
+        } else {
+            rbase[u] = -1;
+        }
+    }
+    const int kk_a = tid & 15;
+    const int qq_b = tid & 63;
+    const bool qok = q0 + qq_b < Q;
+    double2 av[8];
+    float2 bv[4];
+    auto load = [&](int kappa0) {
+        const int ka = kappa0 + kk_a;
+        const bool kok = ka < Q;
+        const int ap = ka / np, bp = ka - ap * np;
+        const int64_t off = (int64_t)ap * Rk + bp;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            av[u] = (kok && rbase[u] >= 0) ? X[rbase[u] + off] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kb = kappa0 + (tid >> 6) + 4 * u;
+            bv[u] = (kb < Q && qok) ? pp.W[(size_t)kb * Q + q0 + qq_b] : make_float2(0.0f, 0.0f);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            float *a = As + ((tid >> 4) + 16 * u) * PG_AP + 2 * kk_a;
+            a[0] = (float)av[u].x;
+            a[1] = (float)av[u].y;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = (tid >> 6) + 4 * u;
+            float *b0 = Bs + (2 * kk) * PG_BN + 2 * qq_b;
+            float *b1 = b0 + PG_BN;
+            b0[0] = bv[u].x;
+            b0[1] = bv[u].y;
+            b1[0] = -bv[u].y;
+            b1[1] = bv[u].x;
+        }
+    };
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int kgrp = lane >> 5, l32 = lane & 31;
+    load(0);
+    store();
+    __syncthreads();
+    for (int k0 = 0; k0 < Q; k0 += PAIR_KC) {
+        const bool more = k0 + PAIR_KC < Q;
+        if (more) load(k0 + PAIR_KC);
+#pragma unroll
+        for (int ks = 0; ks < PG_KR; ks += 2) {
+            float a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[(wr + 32 * i + l32) * PG_AP + ks + kgrp];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[(ks + kgrp) * PG_BN + wc + 32 * j + l32];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) {
+            __syncthreads();
+            store();
+            __syncthreads();
+        }
+    }
+    // lane holds rows 8 (v / 4) + 4 (lane / 32) + v % 4 of column lane % 32 of each 32 x 32 tile
+    double *Yd = reinterpret_cast<double *>(Y);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int cr = (int)ct * PG_BN + wc + 32 * j + l32;  // realified column
+        const int q = cr >> 1, part = cr & 1;
+        if (q >= Q) continue;
+        const int a = q / np, b = q - a * np;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t o = o0 + wr + 32 * i + 8 * (v >> 2) + 4 * kgrp + (v & 3);
+                if (o >= M) continue;
+                const int64_t l = o / Mid, m = o - l * Mid;
+                const size_t idx = 2 * (size_t)(l * nk * Rk + (int64_t)a * Rk + m * np + b) + part;
+                const double val = (double)acc[i][j][v];
+                Yd[idx] = accumulate ? Yd[idx] + val : val;
+            }
+    }
+}
+
 // Coefficient-weighted sum of the entries of each group.  Entries without
 // factors read the FP64 input; the others read their last temporary (type T).
 // Output: out_single (FP64, one group) or the group sums p.gsum (type T).
@@ -593,7 +814,8 @@ __device__ __forceinline__ size_t qr_addr(uint32_t rho, int j, int n, uint32_t R
 }
 
 __global__ void __launch_bounds__(1024) k_qr(double2 *A, uint32_t L, int n, uint32_t R, double2 *Rout, int transR,
-                                             double snap) {
+                                             double snap, const int *gate) {
+    if (gate && *gate == 0) return;
     const uint32_t m = L * R;
     const int tid = threadIdx.x, nt = blockDim.x;
     __shared__ double2 tau_s[64];
@@ -774,6 +996,7 @@ __device__ void qrm_apply(double2 *A, uint32_t r0, uint32_t r1, int k, int n, ui
 
 __global__ void __launch_bounds__(QRM_THREADS) k_qrm_step(double2 *A, uint32_t L, int n, uint32_t R, int i,
                                                           uint32_t rows_per, QRWork q, double snap) {
+    if (q.gate && *q.gate == 0) return;
     const uint32_t m = L * R;
     const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
     const int tid = threadIdx.x;
@@ -855,6 +1078,7 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qrm_step(double2 *A, uint32_t L
 // (last block) builds K = T V_top^H
 __global__ void __launch_bounds__(QRM_THREADS) k_qrm_finish(double2 *A, uint32_t L, int n, uint32_t R,
                                                             uint32_t rows_per, QRWork q, double2 *Rout, int transR) {
+    if (q.gate && *q.gate == 0) return;
     const uint32_t m = L * R;
     const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
     const int tid = threadIdx.x;
@@ -946,6 +1170,7 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qrm_finish(double2 *A, uint32_t
 // Q[rho, c] = delta_{rho c} - sum_i V[rho, i] K[i, c], in place, tiles of 16 rows
 __global__ void __launch_bounds__(QRM_THREADS) k_qrm_formq(double2 *A, uint32_t L, int n, uint32_t R,
                                                            uint32_t rows_per, QRWork q) {
+    if (q.gate && *q.gate == 0) return;
     const uint32_t m = L * R;
     const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
     extern __shared__ double2 sf[];
@@ -1021,6 +1246,16 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
     // launch profiler only: earliest work-group start and latest end on the
     // device's constant-rate clock (a cooperative launch takes no dispatch events)
     if (ts && threadIdx.x == 0) atomicMin(ts, (unsigned long long)wall_clock64());
+    if (q.gate && *q.gate == 0) {
+        // not needed: the work-group still makes the n + 2 barrier arrivals the
+        // host has counted for this launch, then leaves
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(q.bar), (unsigned long long)(n + 2),
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (ts) atomicMax(ts + PROF_TS_MAX, (unsigned long long)wall_clock64());
+        }
+        return;
+    }
     const uint32_t m = L * R;
     const uint32_t G = gridDim.x, b = blockIdx.x;
     const uint32_t r0 = b * rows_per, r1 = min(m, r0 + rows_per);
@@ -1269,6 +1504,347 @@ __global__ void __launch_bounds__(QRM_THREADS) k_qr_coop(double2 *A, uint32_t L,
     if (ts) {
         __syncthreads();
         if (threadIdx.x == 0) atomicMax(ts + PROF_TS_MAX, (unsigned long long)wall_clock64());
+    }
+}
+
+// ============================================================ QR (Cholesky route)
+// For a matrix A of full column rank (rows (l, r) of A[l, j, r] as in qr_addr):
+// G1 = A^H A = R1^H R1, Y = A R1^{-1}, G2 = Y^H Y = R2^H R2, Q' = Y R2^{-1} and
+// R' = R2 R1 (Cholesky QR applied twice: Q' orthonormal to rounding while the
+// first pass leaves Y^H Y near the identity; R' has a positive real diagonal).
+// Householder reflections of A and of Q' coincide (their columns differ by
+// positive factors), and for orthonormal Q' the reflectors' alphas are the
+// pivots p_i of the LU factorisation without pivoting of the leading block
+// Q'_1 - S, S = diag(s_i), s_i = -sign(Re p_i) (the Householder reconstruction
+// of Ballard, Demmel, Grigori, Jacobsen, Knight and Nguyen).  The LAPACK
+// factors are then Q = Q' S and R = S R'.  The sub-column a Householder step
+// would test against the zero-snap has norm R'_ii sqrt(1 - |p_i|^2); when one
+// is below CQR_XTOL |A|_F, a Cholesky factorisation breaks down, or Y^H Y is
+// further than CQR_ORTH_TOL from the identity, *cq_state is set to 1 and the
+// Householder kernels launched behind this route (gate = cq_state) run.
+constexpr double CQR_XTOL = 1e-6;
+constexpr double CQR_ORTH_TOL = 0.1;
+constexpr int CQR_THREADS = 256;
+constexpr int CQR_RTHREADS = 512;
+
+// tile of CQR_TILE rows starting at t0 into Xs (row stride ld), zero beyond r1
+__device__ __forceinline__ void cqr_load(double2 *Xs, int ld, const double2 *A, uint32_t t0, uint32_t r1, int n,
+                                         uint32_t R) {
+    if (R == 1) {
+        for (int e = threadIdx.x; e < CQR_TILE * n; e += blockDim.x) {
+            const uint32_t rho = t0 + (uint32_t)(e / n);
+            const int c = e % n;
+            Xs[(e / n) * ld + c] = rho < r1 ? A[(size_t)rho * n + c] : make_double2(0.0, 0.0);
+        }
+    } else {  // consecutive rows are consecutive addresses within one l
+        for (int e = threadIdx.x; e < CQR_TILE * n; e += blockDim.x) {
+            const int rr = e % CQR_TILE, c = e / CQR_TILE;
+            const uint32_t rho = t0 + (uint32_t)rr;
+            Xs[rr * ld + c] = rho < r1 ? A[qr_addr(rho, c, n, R)] : make_double2(0.0, 0.0);
+        }
+    }
+}
+
+// Xs (CQR_TILE x n) <- Xs Ms for upper-triangular Ms (n x n, zeros below the
+// diagonal); thread (rb, db) owns rows 4 rb.. and columns 4 db..
+__device__ __forceinline__ void cqr_tile_times_upper(double2 *Xs, int ld, const double2 *Ms, int n) {
+    const int rb = threadIdx.x >> 4, db = threadIdx.x & 15;
+    double2 y[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) y[i][j] = make_double2(0.0, 0.0);
+    if (4 * db < n) {
+        const int cmax = min(n, 4 * db + 4);
+        for (int c = 0; c < cmax; ++c) {
+            double2 mr[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mr[j] = 4 * db + j < n ? Ms[c * n + 4 * db + j] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double2 x = Xs[(4 * rb + i) * ld + c];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cfma(y[i][j], x, mr[j]);
+            }
+        }
+    }
+    __syncthreads();
+    if (4 * db < n)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * db + j < n) Xs[(4 * rb + i) * ld + 4 * db + j] = y[i][j];
+    __syncthreads();
+}
+
+// Gram partials of the work-group's rows: pass 1 of A itself; pass 2 (APPLY) of
+// Y = A R1^{-1}, which is also written to cq_Y (row-major m x n)
+template <bool APPLY>
+__global__ void __launch_bounds__(CQR_THREADS) k_cqr_gram(const double2 *A, uint32_t L, int n, uint32_t R,
+                                                          uint32_t rows_per, QRWork q) {
+    if (APPLY && *q.cq_state != 0) return;
+    const uint32_t m = L * R;
+    const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
+    extern __shared__ double2 sc[];
+    const int ld = n + 1;
+    double2 *Xs = sc;
+    double2 *Ms = sc + CQR_TILE * ld;
+    if (APPLY)
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) Ms[e] = q.cq_R1inv[e];
+    const int cb = threadIdx.x >> 4, db = threadIdx.x & 15;
+    const bool act = 4 * cb < n && 4 * db < n;
+    double2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    int ci[4], dj[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        ci[i] = min(4 * cb + i, n - 1);
+        dj[i] = min(4 * db + i, n - 1);
+    }
+    for (uint32_t t0 = r0; t0 < r1; t0 += CQR_TILE) {
+        cqr_load(Xs, ld, A, t0, r1, n, R);
+        __syncthreads();
+        if (APPLY) {
+            cqr_tile_times_upper(Xs, ld, Ms, n);
+            for (int e = threadIdx.x; e < CQR_TILE * n; e += blockDim.x) {
+                const uint32_t rho = t0 + (uint32_t)(e / n);
+                if (rho < r1) q.cq_Y[(size_t)rho * n + e % n] = Xs[(e / n) * ld + e % n];
+            }
+        }
+        if (act)
+            for (int t = 0; t < CQR_TILE; ++t) {
+                double2 a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    a[i] = Xs[t * ld + ci[i]];
+                    b[i] = Xs[t * ld + dj[i]];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) cfmac(acc[i][j], a[i], b[j]);
+            }
+        __syncthreads();
+    }
+    if (act) {
+        double2 *part = q.cq_part + (size_t)blockIdx.x * n * n;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * cb + i < n && 4 * db + j < n) part[(4 * cb + i) * n + 4 * db + j] = acc[i][j];
+    }
+}
+
+// in-place upper Cholesky factor of the Hermitian G (n x n in LDS, G = R^H R);
+// returns false when a pivot is not positive and finite
+__device__ bool cqr_cholesky(double2 *G, int n) {
+    __shared__ double s_rkk;
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) s_ok = 1;
+    for (int k = 0; k < n; ++k) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double d = G[k * n + k].x;
+            if (!(d > 0.0) || !isfinite(d)) s_ok = 0;
+            s_rkk = d > 0.0 && isfinite(d) ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double rkk = s_rkk;
+        for (int j = k + threadIdx.x; j < n; j += blockDim.x)
+            G[k * n + j] = j == k ? make_double2(rkk, 0.0) : cscale(G[k * n + j], 1.0 / rkk);
+        __syncthreads();
+        const int w = n - k - 1;
+        for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+            const int i = k + 1 + e / w, j = k + 1 + e % w;
+            if (j >= i) {
+                double2 g = G[i * n + j];
+                const double2 a = G[k * n + i], b = G[k * n + j];
+                g.x -= a.x * b.x + a.y * b.y;  // conj(a) b
+                g.y -= a.x * b.y - a.y * b.x;
+                G[i * n + j] = g;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x)
+        if (e / n > e % n) G[e] = make_double2(0.0, 0.0);
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// X = R^{-1} for upper-triangular R with a real positive diagonal (both n x n
+// in LDS): back substitution row by row, 8 lanes per column
+__device__ void cqr_upper_inverse(const double2 *Rm, double2 *X, int n) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) X[e] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const int j = threadIdx.x >> 3, sub = threadIdx.x & 7;
+    for (int i = n - 1; i >= 0; --i) {
+        double2 acc = make_double2(0.0, 0.0);
+        if (j < n && j >= i)
+            for (int k = i + 1 + sub; k <= j; k += 8) cfma(acc, Rm[i * n + k], X[k * n + j]);
+        acc.x += __shfl_xor(acc.x, 4, 64);
+        acc.y += __shfl_xor(acc.y, 4, 64);
+        acc.x += __shfl_xor(acc.x, 2, 64);
+        acc.y += __shfl_xor(acc.y, 2, 64);
+        acc.x += __shfl_xor(acc.x, 1, 64);
+        acc.y += __shfl_xor(acc.y, 1, 64);
+        if (j < n && j >= i && sub == 0) {
+            const double inv = 1.0 / Rm[i * n + i].x;
+            X[i * n + j] = make_double2(((i == j ? 1.0 : 0.0) - acc.x) * inv, -acc.y * inv);
+        }
+        __syncthreads();
+    }
+}
+
+// Reduces the Gram partials (64 entries per work-group, 8 lanes each, fixed
+// order); the last work-group factorises.  Pass 1: R1, R1^{-1}, |A|_F^2 and the
+// state.  Pass 2: R2, the checks, the signs S, M = R2^{-1} S and R = S R2 R1.
+__global__ void __launch_bounds__(CQR_RTHREADS) k_cqr_reduce(int nb, int n, int pass, QRWork q, double2 *Rout,
+                                                             int transR) {
+    if (pass == 2 && *q.cq_state != 0) return;
+    const int nn = n * n;
+    {
+        const int e = blockIdx.x * (CQR_RTHREADS / 8) + (int)(threadIdx.x >> 3), sub = threadIdx.x & 7;
+        double2 acc = make_double2(0.0, 0.0);
+        if (e < nn)
+            for (int b = sub; b < nb; b += 8) acc = cadd(acc, q.cq_part[(size_t)b * nn + e]);
+        acc.x += __shfl_xor(acc.x, 4, 64);
+        acc.y += __shfl_xor(acc.y, 4, 64);
+        acc.x += __shfl_xor(acc.x, 2, 64);
+        acc.y += __shfl_xor(acc.y, 2, 64);
+        acc.x += __shfl_xor(acc.x, 1, 64);
+        acc.y += __shfl_xor(acc.y, 1, 64);
+        if (e < nn && sub == 0) q.cq_G[e] = acc;
+    }
+    if (!last_block_ticket(q.cq_counter)) return;
+    extern __shared__ double2 sr[];
+    double2 *Gs = sr;       // n*n: G, then its Cholesky factor
+    double2 *Xs = sr + nn;  // n*n: the factor's inverse
+    __shared__ double s_red[CQR_RTHREADS / 64];
+    __shared__ double s_sign[64], s_rdiag[64];
+    __shared__ int s_ok;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) Gs[e] = q.cq_G[e];
+    __syncthreads();
+    if (threadIdx.x == 0) *q.cq_counter = 0;
+    if (pass == 1) {
+        if (threadIdx.x == 0) {
+            double fro2 = 0.0;
+            for (int i = 0; i < n; ++i) fro2 += Gs[i * n + i].x;
+            q.cq_scal[0] = fro2;
+        }
+        const bool ok = cqr_cholesky(Gs, n);
+        if (ok) cqr_upper_inverse(Gs, Xs, n);
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            q.cq_R1[e] = Gs[e];
+            q.cq_R1inv[e] = Xs[e];
+        }
+        if (threadIdx.x == 0) *q.cq_state = ok ? 0 : 1;
+        return;
+    }
+    // pass 2: Y^H Y must be near the identity
+    double dev = 0.0;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+        const double2 g = Gs[e];
+        dev = fmax(dev, sqrt(cabs2(make_double2(g.x - (e / n == e % n ? 1.0 : 0.0), g.y))));
+    }
+    for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = dev;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double d = 0.0;
+        for (int w = 0; w < CQR_RTHREADS / 64; ++w) d = fmax(d, s_red[w]);
+        s_ok = d <= CQR_ORTH_TOL;
+    }
+    __syncthreads();
+    bool ok = s_ok != 0;
+    ok = cqr_cholesky(Gs, n) && ok;
+    if (ok) cqr_upper_inverse(Gs, Xs, n);
+    // R' = R2 R1 (upper triangular) into cq_G, the diagonal kept for the snap test
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int k = i; k <= j; ++k) cfma(acc, Gs[i * n + k], q.cq_R1[k * n + j]);
+        q.cq_G[e] = acc;
+        if (i == j) s_rdiag[i] = acc.x;
+    }
+    __syncthreads();
+    // leading block of Q' = Y R2^{-1} into Gs (R2 is no longer needed)
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int k = 0; k <= j; ++k) cfma(acc, q.cq_Y[i * n + k], Xs[k * n + j]);
+        Gs[e] = acc;
+    }
+    __syncthreads();
+    // LU without pivoting of Q'_1 - S; s_i from the pivot met at step i
+    const double thr = CQR_XTOL * sqrt(q.cq_scal[0]);
+    if (threadIdx.x == 0) s_ok = ok;
+    for (int i = 0; i < n; ++i) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double2 p = Gs[i * n + i];
+            const double s = -copysign(1.0, p.x);
+            const double xn = s_rdiag[i] * sqrt(fmax(0.0, 1.0 - cabs2(p)));
+            if (!(xn > thr)) s_ok = 0;
+            s_sign[i] = s;
+            Gs[i * n + i] = make_double2(p.x - s, p.y);
+        }
+        __syncthreads();
+        const double2 piv = Gs[i * n + i];
+        const int w = n - i - 1;
+        for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+            const int r = i + 1 + e / w, c = i + 1 + e % w;
+            const double2 l = cdiv(Gs[r * n + i], piv);
+            Gs[r * n + c] = csub(Gs[r * n + c], cmul(l, Gs[i * n + c]));
+        }
+    }
+    __syncthreads();
+    ok = s_ok != 0;
+    if (ok) {
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            q.cq_M[e] = cscale(Xs[e], s_sign[j]);
+            const double2 v = cscale(q.cq_G[e], s_sign[i]);
+            if (transR) Rout[j * n + i] = v;
+            else Rout[e] = v;
+        }
+    }
+    if (threadIdx.x == 0) *q.cq_state = ok ? 0 : 1;
+}
+
+// Q = Y M on the work-group's rows, written to A in its own layout
+__global__ void __launch_bounds__(CQR_THREADS) k_cqr_apply(double2 *A, uint32_t L, int n, uint32_t R,
+                                                           uint32_t rows_per, QRWork q) {
+    if (*q.cq_state != 0) return;
+    const uint32_t m = L * R;
+    const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
+    extern __shared__ double2 sc[];
+    const int ld = n + 1;
+    double2 *Xs = sc;
+    double2 *Ms = sc + CQR_TILE * ld;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) Ms[e] = q.cq_M[e];
+    for (uint32_t t0 = r0; t0 < r1; t0 += CQR_TILE) {
+        cqr_load(Xs, ld, q.cq_Y, t0, r1, n, 1);
+        __syncthreads();
+        cqr_tile_times_upper(Xs, ld, Ms, n);
+        if (R == 1) {
+            for (int e = threadIdx.x; e < CQR_TILE * n; e += blockDim.x) {
+                const uint32_t rho = t0 + (uint32_t)(e / n);
+                if (rho < r1) A[(size_t)rho * n + e % n] = Xs[(e / n) * ld + e % n];
+            }
+        } else {
+            for (int e = threadIdx.x; e < CQR_TILE * n; e += blockDim.x) {
+                const int rr = e % CQR_TILE, c = e / CQR_TILE;
+                const uint32_t rho = t0 + (uint32_t)rr;
+                if (rho < r1) A[qr_addr(rho, c, n, R)] = Xs[rr * ld + c];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -2552,11 +3128,12 @@ void launch_contract(const double2 *A, const double2 *B, double2 *out, int64_t L
                (double2 *const *)nullptr, out);
 }
 
-void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st) {
+void launch_qr(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, hipStream_t st,
+               const int *gate) {
     if (n > 64 || L * R < n) throw std::runtime_error("QR shape out of range");
     const double mm = (double)L * R;
     TTN_LAUNCH("k_qr", 16.0 * mm * n * n, 16.0 * mm * n * 4, k_qr, dim3(1), dim3(1024), 0, st, A, (uint32_t)L, n,
-               (uint32_t)R, Rout, transR, QR_SNAP);
+               (uint32_t)R, Rout, transR, QR_SNAP, gate);
 }
 
 void launch_qr_multi(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
@@ -2628,6 +3205,55 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     if (prof::on && slot >= 0)
         prof::recs.push_back({"k_qr_coop", nullptr, nullptr, 16.0 * (double)m * n * n, 32.0 * (double)m * n, slot});
     return true;
+}
+
+bool launch_qr_chol(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
+                    hipStream_t st) {
+    const int64_t m = L * R;
+    if (!q.cq_part || !q.cq_state || n < 1 || n > 64 || m < n || m * n > q.cq_ycap || m > (int64_t)UINT32_MAX)
+        return false;
+    int64_t rows_per = std::max<int64_t>(CQR_TILE, (m + CQR_BLOCKS_MAX - 1) / CQR_BLOCKS_MAX);
+    rows_per = (rows_per + CQR_TILE - 1) / CQR_TILE * CQR_TILE;
+    const unsigned nb = (unsigned)((m + rows_per - 1) / rows_per);
+    if (nb > (unsigned)CQR_BLOCKS_MAX) return false;
+    const size_t lds_tile = sizeof(double2) * (size_t)CQR_TILE * (n + 1);
+    const size_t lds_mat = sizeof(double2) * (size_t)n * n;
+    const unsigned nbr = (unsigned)((n * n + CQR_RTHREADS / 8 - 1) / (CQR_RTHREADS / 8));
+    const double mm = (double)m, nn = (double)n * n;
+    set_lds_limit((const void *)k_cqr_gram<false>, lds_tile);
+    set_lds_limit((const void *)k_cqr_gram<true>, lds_tile + lds_mat);
+    set_lds_limit((const void *)k_cqr_reduce, 2 * lds_mat);
+    set_lds_limit((const void *)k_cqr_apply, lds_tile + lds_mat);
+    const uint32_t Lu = (uint32_t)L, Ru = (uint32_t)R, rp = (uint32_t)rows_per;
+    const double2 *Ac = A;
+    TTN_LAUNCH("k_cqr_gram", 8.0 * mm * nn, 16.0 * (mm * n + nb * nn), k_cqr_gram<false>, dim3(nb),
+               dim3(CQR_THREADS), lds_tile, st, Ac, Lu, n, Ru, rp, q);
+    TTN_LAUNCH("k_cqr_reduce", 2.0 * nb * nn, 16.0 * nb * nn, k_cqr_reduce, dim3(nbr), dim3(CQR_RTHREADS), 2 * lds_mat,
+               st, (int)nb, n, 1, q, Rout, transR);
+    TTN_LAUNCH("k_cqr_gram", 12.0 * mm * nn, 16.0 * (2 * mm * n + nb * nn), k_cqr_gram<true>, dim3(nb),
+               dim3(CQR_THREADS), lds_tile + lds_mat, st, Ac, Lu, n, Ru, rp, q);
+    TTN_LAUNCH("k_cqr_reduce", 2.0 * nb * nn, 16.0 * nb * nn, k_cqr_reduce, dim3(nbr), dim3(CQR_RTHREADS), 2 * lds_mat,
+               st, (int)nb, n, 2, q, Rout, transR);
+    TTN_LAUNCH("k_cqr_apply", 4.0 * mm * nn, 32.0 * mm * n, k_cqr_apply, dim3(nb), dim3(CQR_THREADS),
+               lds_tile + lds_mat, st, A, Lu, n, Ru, rp, q);
+    return true;
+}
+
+void launch_pair_build(const PairPass &pp, hipStream_t st) {
+    const int na = pp.nk * pp.nk, nb = pp.np * pp.np;
+    dim3 grid((unsigned)((na + 63) / 64), (unsigned)((nb + 63) / 64));
+    TTN_LAUNCH("k_pair_build", 8.0 * na * nb * pp.n_terms, 8.0 * na * nb + 16.0 * pp.n_terms * (pp.nk * pp.nk + nb),
+               k_pair_build, grid, dim3(256), 0, st, pp);
+}
+
+void launch_pair_gemm(const PairPass &pp, const double2 *in, double2 *out, int accumulate, double flops,
+                      hipStream_t st) {
+    const int Q = pp.nk * pp.np;
+    const int64_t M = pp.L * pp.Mid;
+    const unsigned nct = (unsigned)((2 * Q + PG_BN - 1) / PG_BN), nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
+    const double N = (double)M * Q;
+    TTN_LAUNCH("k_pair_gemm", flops, 16.0 * N * (accumulate ? 3 : 2) + 8.0 * Q * Q, k_pair_gemm, dim3(nct * nrt),
+               dim3(256), 0, st, pp, in, out, accumulate);
 }
 
 static size_t small_solve_total_lds(const SmallSolveArgs &a) {

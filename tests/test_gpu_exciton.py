@@ -111,6 +111,42 @@ def test_c3_shaped_tree_parity(T, prec, tol):
     g.close()
 
 
+def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch):
+    """FP32 effective generators in the pair-operator form (each child slot's
+    products summed into one dense operator on the pair (child, parent) and
+    applied as a GEMM on the FP32 matrix cores), switched on for every eligible
+    node of the C3-shaped tree by lowering the node-size threshold: three sweeps
+    from the seeded full-rank state against the stored oracle run (1e-4, as the
+    other FP32 contractions) and against the staged FP32 products (1e-6)."""
+    import golden_refs as G
+    p = G.maker.c3_shaped()
+    bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
+    st = random_isometric_state(p.parent, p.local_dim, bonds, seed=31)
+    ref = G.observables(G.reference("c3_shaped", p, bonds, st))
+    runs = {}
+    for form, env in (("pair", {"TTN_PAIR_MIN_N": "1"}), ("staged", {"TTN_PAIR_OPS": "0"})):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        g = T.TTN.from_problem(p, precision=T.TTN_FP32)
+        for k in env:
+            monkeypatch.delenv(k)
+        g.set_state(st)
+        T.profile_begin()
+        got = []
+        for _ in range(3):
+            g.step(p.dt)
+            got.append(_obs10(g, p))
+        names = {r["name"] for r in T.profile_end()}
+        runs[form] = np.array(got)
+        assert ("k_pair_gemm" in names) == (form == "pair")
+        g.close()
+    err = np.abs(runs["pair"] - ref).max()
+    diff = np.abs(runs["pair"] - runs["staged"]).max()
+    print(f"pair form: max error vs oracle {err:.2e}, vs staged FP32 {diff:.2e}")
+    assert err < 1e-4
+    assert diff < 1e-6
+
+
 def test_exciton10x120_full_size_properties(T):
     """The full exciton workload (10 states, 120 modes, bonds 8/32/48/64,
     1500 SOP terms: nodes of 7.08M elements, the sizes bench.py times), one

@@ -35,9 +35,34 @@ def _cases():
     return out
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
-def test_qr_matches_oracle_householder(T, variant):
+def _cholesky_route_cases():
+    """Matrices for the Cholesky route: inside its range (random, graded
+    columns with condition ~1e5) and outside it (rank-deficient, columns
+    already triangular so that the Householder steps have nothing below the
+    diagonal, square)."""
+    rng = np.random.default_rng(13)
+    inside, outside = [], []
+    for (m, n) in [(65, 64), (1000, 48), (4096, 20), (20000, 33)]:
+        inside.append(("random", rng.normal(size=(m, n)) + 1j * rng.normal(size=(m, n))))
+    G = (rng.normal(size=(3000, 24)) + 1j * rng.normal(size=(3000, 24))) * np.logspace(0, -5, 24)
+    inside.append(("graded", G))
+    E = np.zeros((5000, 16), dtype=np.complex128)
+    E[np.arange(16), np.arange(16)] = rng.uniform(0.5, 2.0, 16) * np.exp(1j * rng.uniform(0, 6.28, 16))
+    outside.append(("triangular", E))
+    # square: the last column has no entries below the diagonal
+    outside.append(("square", rng.normal(size=(64, 64)) + 1j * rng.normal(size=(64, 64))))
     for name, M in _cases():
+        if name != "random":
+            outside.append((name, M))
+    return inside, outside
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_qr_matches_oracle_householder(T, variant):
+    cases = _cases()
+    if variant == 3:  # matrices outside the Cholesky route go through the gate to the Householder kernels
+        cases += _cholesky_route_cases()[1]
+    for name, M in cases:
         if variant == 0 and M.size > 200_000:
             continue
         if variant == 2 and M.shape[1] > 48:  # the LDS-resident cooperative QR takes n <= 48
@@ -48,6 +73,32 @@ def test_qr_matches_oracle_householder(T, variant):
         assert np.abs(Q - Qo).max() < 1e-12, (name, M.shape, np.abs(Q - Qo).max())
         assert np.abs(R - Ro).max() < 1e-12 * scale, (name, M.shape)
         assert np.abs(Q.conj().T @ Q - np.eye(M.shape[1])).max() < 1e-12
+
+
+def test_cholesky_route_alone(T):
+    """The Cholesky route by itself gives the oracle's Householder factors (the
+    LAPACK signs) inside its range and declines the matrices a Householder step
+    would snap or that have no full column rank; a 110592 x 64 block (the shape
+    of the largest exciton nodes) is compared by sampled columns."""
+    inside, outside = _cholesky_route_cases()
+    for name, M in inside:
+        Q, R = T.gpu_qr(M, 4)
+        Qo, Ro = householder_qr_lapack(M, snap=SNAP)
+        err = np.abs(Q - Qo).max()
+        print(f"{name} {M.shape}: |Q - Q_householder| {err:.1e}")
+        assert err < 1e-12 * max(1.0, np.linalg.cond(M) / 100), (name, M.shape, err)
+        assert np.abs(R - Ro).max() < 1e-12 * np.abs(M).max() * max(1.0, np.linalg.cond(M) / 100)
+        assert np.abs(Q.conj().T @ Q - np.eye(M.shape[1])).max() < 1e-13
+    for name, M in outside:
+        with pytest.raises(T.TTNError, match="NOCONV"):
+            T.gpu_qr(M, 4)
+    rng = np.random.default_rng(14)
+    M = rng.normal(size=(110592, 64)) + 1j * rng.normal(size=(110592, 64))
+    Q, R = T.gpu_qr(M, 4)
+    Qh, Rh = T.gpu_qr(M, 1)
+    assert np.abs(Q - Qh).max() < 1e-12 and np.abs(R - Rh).max() < 1e-12 * np.abs(M).max()
+    assert np.abs(Q.conj().T @ Q - np.eye(64)).max() < 1e-13
+    assert np.abs(Q @ R - M).max() < 1e-12 * np.abs(M).max()
 
 
 def test_large_node_parity(T):
