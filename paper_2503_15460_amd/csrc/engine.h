@@ -88,7 +88,8 @@ private:
     // FP32 effective generators of large nodes in the pair-operator form
     // (TTN_PAIR_OPS=0 in the environment: staged products only)
     bool pair_ops = true;
-    int64_t pair_min_n = 1 << 18;  // node size from which the pair form is considered (TTN_PAIR_MIN_N)
+    int64_t pair_min_n = 1 << 18;
+    float2 *pair_x32 = nullptr;  // scratch: complex FP32 copy of a pair-form input  // node size from which the pair form is considered (TTN_PAIR_MIN_N)
     hipStream_t own_stream = nullptr;
     struct GraphEntry {
         std::vector<int64_t> key;  // Krylov dimension hints and dt of the captured step

@@ -687,6 +687,13 @@ void Engine::set_sop(const SopInput &s) {
     need(&qrw.cpart, sizeof(double) * 2 * QRM_BLOCKS_MAX * QRC_REC);
     need(&qrw.bar, sizeof(unsigned) * 192);
     qrw.bar_base = 0;
+    // complex FP32 copy of the input of pair-form applications
+    pair_x32 = nullptr;
+    for (int z = 0; z < n; ++z)
+        if (!heffP[z].pair.empty()) {
+            need(&pair_x32, sizeof(float2) * maxN);
+            break;
+        }
     // Cholesky route of the QR: Gram partials, small matrices, first-pass factor
     need(&qrw.cq_part, sizeof(double2) * CQR_BLOCKS_MAX * 64 * 64);
     need(&qrw.cq_G, sizeof(double2) * 64 * 64);
@@ -854,7 +861,10 @@ void Engine::apply_prog(const Prog &p, const double2 *in, double2 *out) {
 
 void Engine::launch_apply(const Prog &p, const ProgView &v, const double2 *in, double2 *out) {
     if (!p.pair.empty()) {
-        for (size_t i = 0; i < p.pair.size(); ++i) launch_pair_gemm(p.pair[i], in, out, i > 0 ? 1 : 0, p.pair_flops[i], st);
+        if (!pair_x32) throw Error(TTN_E_STATE, "internal: pair-form scratch not allocated");
+        launch_to_f32(in, pair_x32, p.g.N, st);
+        for (size_t i = 0; i < p.pair.size(); ++i)
+            launch_pair_gemm(p.pair[i], pair_x32, out, i > 0 ? 1 : 0, p.pair_flops[i], st);
         return;
     }
     launch_prog_stages(v, in, st);

@@ -100,15 +100,17 @@ struct PairTerm {
 struct PairPass {
     int nk, np;        // dims of slot k and of the parent slot
     int64_t L, Mid;    // products of the dims before k and between k and P
-    float2 *W;         // Wt[kappa][q], kappa = (a', b') input pair, q = (a, b) output pair
+    float2 *W;         // W[q][kappa], q = (a, b) output pair, kappa = (a', b') input pair
     const PairTerm *terms;
     int n_terms;
 };
 constexpr int PAIR_KC = 16;  // complex K per LDS chunk of the pair GEMM
 void launch_pair_build(const PairPass &pp, hipStream_t st);
-// out (FP64) = (accumulate ? out : 0) + W_k applied to in (FP64) on (k, P)
-void launch_pair_gemm(const PairPass &pp, const double2 *in, double2 *out, int accumulate, double flops,
+// out (FP64) = (accumulate ? out : 0) + W_k applied to in (complex FP32) on (k, P)
+void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops,
                       hipStream_t st);
+// y = x rounded to complex FP32 (n elements)
+void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st);
 
 // Statistics written by one Krylov solve.
 struct SolveStat {

@@ -467,9 +467,9 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
 
 // ------------------------------------------------------------ pair-operator form
 // W_k[q][kappa] = sum_e c_e F_e[a][a'] P_e[b][b'] for q = (a, b), kappa = (a', b')
-// (a null factor is the identity), summed in FP64 and stored transposed,
-// Wt[kappa][q], in complex FP32.  Work-group tile: 64 pairs alpha = a n_k + a'
-// by 64 pairs beta = b' n_P + b; the terms pass through LDS in chunks.
+// (a null factor is the identity), summed in FP64 and stored row-major,
+// W[q][kappa], in complex FP32.  Work-group tile: 64 pairs alpha = a n_k + a'
+// by 64 pairs beta = b n_P + b'; the terms pass through LDS in chunks.
 constexpr int PB_TC = 16;
 __global__ void __launch_bounds__(256) k_pair_build(PairPass pp) {
     const int nk = pp.nk, np = pp.np;
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(256) k_pair_build(PairPass pp) {
                 double2 w = make_double2(0.0, 0.0);
                 if (t < tc && be < nbt) {
                     const PairTerm T = pp.terms[t0 + t];
-                    const int bp = be / np, b = be - bp * np;
+                    const int b = be / np, bp = be - b * np;
                     w = T.P ? T.P[(size_t)b * np + bp] : make_double2(b == bp ? 1.0 : 0.0, 0.0);
                 }
                 Ps[e] = w;
@@ -533,8 +533,8 @@ __global__ void __launch_bounds__(256) k_pair_build(PairPass pp) {
         for (int j = 0; j < 4; ++j) {
             const int be = b0 + 4 * tb + j;
             if (be >= nbt) continue;
-            const int bp = be / np, b = be - bp * np;
-            pp.W[(size_t)(ap * np + bp) * Q + a * np + b] = make_float2((float)acc[i][j].x, (float)acc[i][j].y);
+            const int b = be / np, bp = be - b * np;
+            pp.W[(size_t)(a * np + b) * Q + ap * np + bp] = make_float2((float)acc[i][j].x, (float)acc[i][j].y);
         }
     }
 }
@@ -543,26 +543,46 @@ __global__ void __launch_bounds__(256) k_pair_build(PairPass pp) {
 // rows o (the indices other than slot k and the parent slot) by the pair index:
 // element (o; a, b) of o = (l, m) at l n_k R_k + a R_k + m n_P + b, R_k = Mid n_P.
 // One real GEMM on the FP32 matrix cores (v_mfma_f32_32x32x2f32) with the
-// complex values realified: row o of the A operand holds (Re, Im) of in[o; kappa]
-// at columns (2 kappa, 2 kappa + 1); rows (2 kappa, 2 kappa + 1) and columns
-// (2q, 2q + 1) of the B operand hold [[Re W, Im W], [-Im W, Re W]].  Work-group
-// tile: 128 rows by 128 realified columns (4 waves of 64 x 64); chunks of 16
-// complex kappa through LDS, the next chunk's loads in flight during the
-// current one's products.  Tiles are dealt so that the work-groups resident on
-// one XCD (work-groups go to the 8 XCDs in turn) share row and column blocks
-// in that XCD's L2.
+// complex values realified: the A operand holds (Re, Im) of in[o; kappa] at
+// realified columns (2 kappa, 2 kappa + 1), the B operand the 2 x 2 blocks
+// [[Re W, Im W], [-Im W, Re W]] of W[q][kappa] at rows (2 kappa, 2 kappa + 1)
+// and columns (2q, 2q + 1).  The input comes as complex FP32 (converted once
+// per application).  Work-group tile: 128 rows by 256 realified columns, four
+// waves of 64 x 128 (2 x 4 matrix-core tiles); chunks of 16 complex kappa pass
+// through LDS with the parts split ([row][part][kappa]) so that one 16-byte
+// LDS read feeds four K steps; the next chunk's global loads are in flight
+// while the current one is multiplied.  Tiles are dealt so that the
+// work-groups resident on one XCD (work-groups go to the 8 XCDs in turn) share
+// row and column blocks in that XCD's L2.
 constexpr int PG_BM = 128;
-constexpr int PG_BN = 128;
-constexpr int PG_KR = 2 * PAIR_KC;
-constexpr int PG_AP = PG_KR + 1;
-constexpr int PG_GR = 4;  // row tiles per group of the tile order
-__global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const double2 *__restrict__ X, double2 *__restrict__ Y,
+constexpr int PG_KS = 16;    // complex kappa per chunk (= K steps of 2 realified)
+// floats per LDS row (two parts of 16, padded): A rows 36 (conflict-free
+// 16-byte reads), B rows 40 (also conflict-free stores of four q per wave)
+constexpr int PG_LDA = 2 * PG_KS + 4;
+constexpr int PG_LDB = 2 * PG_KS + 8;
+constexpr int PG_GR = 4;     // row tiles per group of the tile order
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+__global__ void k_to_f32(const double2 *__restrict__ x, float2 *__restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = make_float2((float)x[i].x, (float)x[i].y);
+}
+
+// WN: matrix-core tiles per wave along the columns (the work-group covers
+// 64 WN realified columns).  LDS (dynamic): two buffers of the A tile
+// (128 rows of PG_LDA floats) and the B tile (64 WN columns of PG_LDB).
+template <int WN>
+__global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__restrict__ X, double2 *__restrict__ Y,
                                                    int accumulate) {
+    constexpr int BN = 64 * WN;       // realified columns per work-group
+    constexpr int QW = BN / 2;        // complex q per work-group
+    constexpr int BU = 16 * QW / 256; // B values per thread and chunk
+    constexpr int BUF = PG_BM * PG_LDA + BN * PG_LDB;  // floats per buffer
     const int nk = pp.nk, np = pp.np;
     const int Q = nk * np;
     const int64_t Mid = pp.Mid, Rk = Mid * np;
     const int64_t M = pp.L * Mid;
-    const unsigned nct = (unsigned)((2 * Q + PG_BN - 1) / PG_BN);
+    const unsigned nct = (unsigned)((2 * Q + BN - 1) / BN);
     const unsigned nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
     const unsigned ntile = nct * nrt;
     unsigned rt, ct;
@@ -576,13 +596,12 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const double2 *_
         rt = g * PG_GR + w % rows_g;
         ct = w / rows_g;
     }
-    __shared__ float As[PG_BM * PG_AP];  // As[row * PG_AP + k']
-    __shared__ float Bs[PG_KR * PG_BN];  // Bs[k' * PG_BN + c']
+    extern __shared__ __attribute__((aligned(16))) float pg_lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t o0 = (int64_t)rt * PG_BM;
-    const int q0 = (int)ct * (PG_BN / 2);
-    // A loads: 128 rows x 16 kappa (8 per thread: rows (tid >> 4) + 16 u, kappa offset tid & 15)
-    // B loads: 16 kappa x 64 q (4 per thread: kappa offset (tid >> 6) + 4 u, q offset tid & 63)
+    const int q0 = (int)ct * QW;
+    // A: 128 rows x 16 kappa, 8 per thread (rows (tid >> 4) + 16 u, kappa offset tid & 15)
+    // B: QW q x 16 kappa from the q-major W, BU per thread (q offset (tid >> 4) + 16 u, kappa offset tid & 15)
     int64_t rbase[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -594,95 +613,127 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const double2 *_
             rbase[u] = -1;
         }
     }
-    const int kk_a = tid & 15;
-    const int qq_b = tid & 63;
-    const bool qok = q0 + qq_b < Q;
-    double2 av[8];
-    float2 bv[4];
+    const int kk = tid & 15;
+    float2 av[8], bv[BU];
     auto load = [&](int kappa0) {
-        const int ka = kappa0 + kk_a;
+        const int ka = kappa0 + kk;
         const bool kok = ka < Q;
         const int ap = ka / np, bp = ka - ap * np;
         const int64_t off = (int64_t)ap * Rk + bp;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            av[u] = (kok && rbase[u] >= 0) ? X[rbase[u] + off] : make_double2(0.0, 0.0);
+            av[u] = (kok && rbase[u] >= 0) ? X[rbase[u] + off] : make_float2(0.0f, 0.0f);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int kb = kappa0 + (tid >> 6) + 4 * u;
-            bv[u] = (kb < Q && qok) ? pp.W[(size_t)kb * Q + q0 + qq_b] : make_float2(0.0f, 0.0f);
+        for (int u = 0; u < BU; ++u) {
+            const int q = q0 + (tid >> 4) + 16 * u;
+            bv[u] = (kok && q < Q) ? pp.W[(size_t)q * Q + ka] : make_float2(0.0f, 0.0f);
         }
     };
-    auto store = [&]() {
+    auto store = [&](float *buf) {
+        float *As = buf, *Bs = buf + PG_BM * PG_LDA;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            float *a = As + ((tid >> 4) + 16 * u) * PG_AP + 2 * kk_a;
-            a[0] = (float)av[u].x;
-            a[1] = (float)av[u].y;
+            float *a = As + ((tid >> 4) + 16 * u) * PG_LDA + kk;
+            a[0] = av[u].x;
+            a[PG_KS] = av[u].y;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int kk = (tid >> 6) + 4 * u;
-            float *b0 = Bs + (2 * kk) * PG_BN + 2 * qq_b;
-            float *b1 = b0 + PG_BN;
+        for (int u = 0; u < BU; ++u) {
+            const int qq = (tid >> 4) + 16 * u;
+            float *b0 = Bs + (2 * qq) * PG_LDB + kk;  // column 2q: (Re W, -Im W) for parts (0, 1)
+            float *b1 = b0 + PG_LDB;                   // column 2q + 1: (Im W, Re W)
             b0[0] = bv[u].x;
-            b0[1] = bv[u].y;
-            b1[0] = -bv[u].y;
-            b1[1] = bv[u].x;
+            b0[PG_KS] = -bv[u].y;
+            b1[0] = bv[u].y;
+            b1[PG_KS] = bv[u].x;
         }
     };
-    f32x16 acc[2][2];
+    f32x16 acc[2][WN];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WN; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    const int kgrp = lane >> 5, l32 = lane & 31;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 32 * WN;
+    const int part = lane >> 5, l32 = lane & 31;
     load(0);
-    store();
+    store(pg_lds);
     __syncthreads();
-    for (int k0 = 0; k0 < Q; k0 += PAIR_KC) {
-        const bool more = k0 + PAIR_KC < Q;
-        if (more) load(k0 + PAIR_KC);
+    int cur = 0;
+    for (int k0 = 0; k0 < Q; k0 += PG_KS) {
+        const bool more = k0 + PG_KS < Q;
+        if (more) load(k0 + PG_KS);
+        const float *As = pg_lds + cur * BUF, *Bs = As + PG_BM * PG_LDA;
 #pragma unroll
-        for (int ks = 0; ks < PG_KR; ks += 2) {
-            float a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[(wr + 32 * i + l32) * PG_AP + ks + kgrp];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Bs[(ks + kgrp) * PG_BN + wc + 32 * j + l32];
+        for (int t4 = 0; t4 < PG_KS; t4 += 4) {
+            f32x4v a[2], b[WN];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const f32x4v *>(As + (wr + 32 * i + l32) * PG_LDA + part * PG_KS + t4);
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < WN; ++j)
+                b[j] = *reinterpret_cast<const f32x4v *>(Bs + (wc + 32 * j + l32) * PG_LDB + part * PG_KS + t4);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
         }
         if (more) {
+            // the other buffer was last read before the previous barrier
+            store(pg_lds + (1 - cur) * BUF);
             __syncthreads();
-            store();
-            __syncthreads();
+            cur = 1 - cur;
         }
     }
     // lane holds rows 8 (v / 4) + 4 (lane / 32) + v % 4 of column lane % 32 of each 32 x 32 tile
     double *Yd = reinterpret_cast<double *>(Y);
+    int64_t obase[2][4];
+    int orun[2][4];  // rows of the group of four that share its l
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int cr = (int)ct * PG_BN + wc + 32 * j + l32;  // realified column
-        const int q = cr >> 1, part = cr & 1;
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            // rows o0 + wr + 32 i + 8 g + 4 part + (0..3): one division per group of four
+            const int64_t o = o0 + wr + 32 * i + 8 * g + 4 * part;
+            const int64_t l = o / Mid, m = o - l * Mid;
+            obase[i][g] = l * nk * Rk + m * np;
+            orun[i][g] = (int)min<int64_t>(4, Mid - m);
+        }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        const int cr = (int)ct * BN + wc + 32 * j + l32;  // realified column
+        const int q = cr >> 1, ri = cr & 1;
         if (q >= Q) continue;
         const int a = q / np, b = q - a * np;
+        const int64_t cofs = (int64_t)a * Rk + b;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i) {
+            size_t idx[16];
+            bool ok[16];
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int64_t o = o0 + wr + 32 * i + 8 * (v >> 2) + 4 * kgrp + (v & 3);
-                if (o >= M) continue;
-                const int64_t l = o / Mid, m = o - l * Mid;
-                const size_t idx = 2 * (size_t)(l * nk * Rk + (int64_t)a * Rk + m * np + b) + part;
-                const double val = (double)acc[i][j][v];
-                Yd[idx] = accumulate ? Yd[idx] + val : val;
+                const int64_t o = o0 + wr + 32 * i + 8 * (v >> 2) + 4 * part + (v & 3);
+                ok[v] = o < M;
+                int64_t base = obase[i][v >> 2];
+                if ((v & 3) < orun[i][v >> 2]) {
+                    base += (int64_t)(v & 3) * np;
+                } else {  // the group of four crosses into the next l
+                    const int64_t l = o / Mid, m = o - l * Mid;
+                    base = l * nk * Rk + m * np;
+                }
+                idx[v] = 2 * (size_t)(base + cofs) + ri;
             }
+            double old[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) old[v] = (accumulate && ok[v]) ? Yd[idx[v]] : 0.0;
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                if (ok[v]) Yd[idx[v]] = old[v] + (double)acc[i][j][v];
+        }
     }
 }
 
@@ -3246,14 +3297,42 @@ void launch_pair_build(const PairPass &pp, hipStream_t st) {
                k_pair_build, grid, dim3(256), 0, st, pp);
 }
 
-void launch_pair_gemm(const PairPass &pp, const double2 *in, double2 *out, int accumulate, double flops,
+// column tiles per wave of the pair GEMM: 2, 4, or 0 for the size rule (TTN_PAIR_WN)
+static int pair_gemm_wn_setting() {
+    static const int v = [] {
+        const char *e = getenv("TTN_PAIR_WN");
+        const int w = e ? atoi(e) : 0;
+        return (w == 2 || w == 4) ? w : 0;
+    }();
+    return v;
+}
+
+void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st) {
+    TTN_LAUNCH("k_to_f32", 0.0, 24.0 * n, k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, st, x, y, n);
+}
+
+void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops,
                       hipStream_t st) {
     const int Q = pp.nk * pp.np;
     const int64_t M = pp.L * pp.Mid;
-    const unsigned nct = (unsigned)((2 * Q + PG_BN - 1) / PG_BN), nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
     const double N = (double)M * Q;
-    TTN_LAUNCH("k_pair_gemm", flops, 16.0 * N * (accumulate ? 3 : 2) + 8.0 * Q * Q, k_pair_gemm, dim3(nct * nrt),
-               dim3(256), 0, st, pp, in, out, accumulate);
+    const double by = 8.0 * N + 16.0 * N * (accumulate ? 2 : 1) + 8.0 * Q * Q;
+    const unsigned nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
+    // wider column tiles halve the re-reads of the input where the column count allows
+    const int wn = pair_gemm_wn_setting();
+    if (wn == 4) {
+        const unsigned nct = (unsigned)((2 * Q + 255) / 256);
+        const size_t lds = sizeof(float) * 2 * (PG_BM * PG_LDA + 256 * PG_LDB);
+        set_lds_limit((const void *)k_pair_gemm<4>, lds);
+        TTN_LAUNCH("k_pair_gemm", flops, by, k_pair_gemm<4>, dim3(nct * nrt), dim3(256), lds, st, pp, in, out,
+                   accumulate);
+    } else {
+        const unsigned nct = (unsigned)((2 * Q + 127) / 128);
+        const size_t lds = sizeof(float) * 2 * (PG_BM * PG_LDA + 128 * PG_LDB);
+        set_lds_limit((const void *)k_pair_gemm<2>, lds);
+        TTN_LAUNCH("k_pair_gemm", flops, by, k_pair_gemm<2>, dim3(nct * nrt), dim3(256), lds, st, pp, in, out,
+                   accumulate);
+    }
 }
 
 static size_t small_solve_total_lds(const SmallSolveArgs &a) {
