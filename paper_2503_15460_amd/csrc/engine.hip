@@ -639,10 +639,12 @@ void Engine::set_sop(const SopInput &s) {
         need(&bk.Hm, sizeof(double2) * (mmax + 1) * mmax);
         need(&bk.h, sizeof(double2) * (mmax + 1));
         need(&bk.y, sizeof(double2) * (mmax + 1));
-        need(&bk.part, sizeof(double) * VEC_BLOCKS * (mmax + 2) * 2);
+        need(&bk.part, sizeof(double) * VEC_BLOCKS * (2 * mmax + 4) * 2);
         need(&bk.scal, sizeof(double) * 4);
         need(&bk.meff, sizeof(int) * 4);
         need(&bk.counter, sizeof(unsigned) * 4);
+        need(&bk.G, sizeof(double2) * (mmax + 1) * (mmax + 1));
+        need(&bk.refine, sizeof(int) * 4);
     }
     {  // copy of the state taken at the start of every step (restored on failure)
         int64_t tot = 0;
@@ -1070,7 +1072,7 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
         ProgView v = view(p);
         for (int j = 0; j < m; ++j) {
             launch_apply(p, v, bk.V + (size_t)j * N, bk.V + (size_t)(j + 1) * N);
-            launch_krylov_orth(bk, N, j, mmax, st);
+            launch_krylov_orth1(bk, N, j, mmax, st);
         }
         launch_krylov_finish(bk, N, m, mmax, tau, tol, opt.hermitian, x, stat, st);
     }

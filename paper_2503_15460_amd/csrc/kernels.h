@@ -159,6 +159,8 @@ struct BigKrylov {
     double *scal;      // [0] beta0 [1] beta
     int *meff;         // breakdown dimension (0: none)
     unsigned *counter; // last-block reduction counter (starts at 0)
+    double2 *G;        // (mmax + 1)^2 Gram matrix of the basis, column j = V^H v_j (one-pass orthogonalisation)
+    int *refine;       // 1: the last update cancelled most of w, one more classical pass follows
 };
 
 // Scratch of the many-work-group Householder QR.
@@ -290,6 +292,10 @@ void launch_transpose(double2 *dst, const double2 *src, int n, hipStream_t st);
 // multi-kernel Krylov pieces
 void launch_krylov_start(const double2 *x, int64_t N, const BigKrylov &k, hipStream_t st);
 void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st);
+// the same orthonormalisation with one pass over the basis for the dots and one
+// for the update (Gram-matrix form of the second Gram-Schmidt pass); needs
+// k.G, k.refine and k.part of VEC_BLOCKS * (2 mmax + 4) * 2 doubles
+void launch_krylov_orth1(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st);
 void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double tau, double tol,
                           int hermitian, double2 *x, SolveStat *stat, hipStream_t st);
 

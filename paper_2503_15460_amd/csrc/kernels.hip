@@ -2465,6 +2465,184 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_finalize(BigKrylov k, uint3
     }
 }
 
+// Gram-Schmidt for w = V[j+1] against V[0..j] with one pass over the basis for
+// the dots and one for the update.  Twice-applied classical Gram-Schmidt
+// forms w - V (h1 + h2) with h1 = V^H w and h2 = V^H (w - V h1); the second
+// dots equal h1 - G h1 with G = V^H V, the Gram matrix of the stored basis,
+// whose column j (v_i^H v_j) comes from the same pass as h1.  So
+//   k_kry_dots1:   h1 = V^H w, G[:, j] = V^H v_j, |w|^2 -> c = 2 h1 - G h1 = Hm[:, j]
+//   k_kry_update1: w -= V c, |w|^2 -> beta
+// When the update cancels most of w (|w - V c|^2 < 1e-4 |w|^2: w nearly inside
+// the span), its rounding is not orthogonal to V; a classical pass on the
+// result then follows (k_kry_refine1, gated: h3 = V^H w, w -= V h3, Hm[:, j] += h3).
+// k_kry_scale1 divides by beta.
+constexpr double KRY_CANCEL = 1e-4;
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_dots1(BigKrylov k, uint32_t N, int j, int mmax) {
+    if (*k.meff) return;
+    __shared__ double2 hb[64], gb[64];
+    __shared__ double red1[16];
+    __shared__ double stage[KRY_STAGE];
+    const int nv = j + 1;
+    const double2 *w = k.V + (size_t)(j + 1) * N;
+    const double2 *vj = k.V + (size_t)j * N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (int i = wave; i < nv; i += nw) {
+        const double2 *vi = k.V + (size_t)i * N;
+        double2 ch = make_double2(0.0, 0.0), cg = make_double2(0.0, 0.0);
+        for (uint32_t base = blockIdx.x * blockDim.x; base < N; base += stride)
+            for (uint32_t t = lane; t < blockDim.x; t += 64) {
+                const uint32_t idx = base + t;
+                if (idx < N) {
+                    const double2 v = vi[idx];
+                    cfmac(ch, v, w[idx]);
+                    cfmac(cg, v, vj[idx]);
+                }
+            }
+        ch.x = wave_sum(ch.x);
+        ch.y = wave_sum(ch.y);
+        cg.x = wave_sum(cg.x);
+        cg.y = wave_sum(cg.y);
+        if (lane == 0) {
+            hb[i] = ch;
+            gb[i] = cg;
+        }
+    }
+    double wn = 0.0;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) wn += cabs2(w[idx]);
+    const double wns = blk_sum1(wn, red1);  // synchronises: hb, gb complete
+    const int K = 2 * nv + 1;  // complex slots per block: h1, g, |w|^2
+    double *part = k.part + (size_t)blockIdx.x * 2 * K;
+    if (threadIdx.x < nv) {
+        part[2 * threadIdx.x] = hb[threadIdx.x].x;
+        part[2 * threadIdx.x + 1] = hb[threadIdx.x].y;
+        part[2 * (nv + threadIdx.x)] = gb[threadIdx.x].x;
+        part[2 * (nv + threadIdx.x) + 1] = gb[threadIdx.x].y;
+    }
+    if (threadIdx.x == 0) {
+        part[2 * (2 * nv)] = wns;
+        part[2 * (2 * nv) + 1] = 0.0;
+    }
+    if (last_block_ticket(k.counter)) {
+        __shared__ double sums[2 * (2 * 65 + 1)];
+        blk_reduce_staged(k.part, gridDim.x, 2 * K, 2 * K, sums, stage);
+        __syncthreads();
+        const int ld = mmax + 1;
+        // G[q][l] = v_q^H v_l: column l (l >= q) of the stored Gram matrix, or
+        // the conjugate of column q; column j is the one just reduced
+        auto gram = [&](int q, int l) -> double2 {
+            if (l >= q)
+                return l == j ? make_double2(sums[2 * (nv + q)], sums[2 * (nv + q) + 1]) : k.G[(size_t)l * ld + q];
+            double2 g = q == j ? make_double2(sums[2 * (nv + l)], sums[2 * (nv + l) + 1]) : k.G[(size_t)q * ld + l];
+            g.y = -g.y;
+            return g;
+        };
+        double2 *hcol = k.Hm + (size_t)j * (mmax + 1);
+        for (int q = threadIdx.x; q < nv; q += blockDim.x) {
+            double2 gh = make_double2(0.0, 0.0);
+            for (int l = 0; l < nv; ++l) cfma(gh, gram(q, l), make_double2(sums[2 * l], sums[2 * l + 1]));
+            const double2 h = make_double2(sums[2 * q], sums[2 * q + 1]);
+            const double2 c = make_double2(2.0 * h.x - gh.x, 2.0 * h.y - gh.y);
+            k.h[q] = c;
+            hcol[q] = c;
+            k.G[(size_t)j * ld + q] = make_double2(sums[2 * (nv + q)], sums[2 * (nv + q) + 1]);
+        }
+        if (threadIdx.x == 0) {
+            k.scal[2] = sums[2 * (2 * nv)];
+            *k.counter = 0;
+        }
+    }
+}
+
+// w -= V c (c = k.h) and |w|^2; last block: beta, Hm[j+1][j], the refinement
+// flag and the breakdown test
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_update1(BigKrylov k, uint32_t N, int j, int mmax, int refine) {
+    if (*k.meff) return;
+    if (refine && !*k.refine) return;
+    __shared__ double2 hb[64];
+    __shared__ double red1[16];
+    __shared__ double stage[KRY_STAGE];
+    const int nv = j + 1;
+    for (int q = threadIdx.x; q < nv; q += blockDim.x) hb[q] = k.h[q];
+    __syncthreads();
+    double2 *w = k.V + (size_t)(j + 1) * N;
+    double wn = 0.0;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x) {
+        double2 wv = w[idx];
+        for (int i = 0; i < nv; ++i) wv = csub(wv, cmul(hb[i], k.V[(size_t)i * N + idx]));
+        w[idx] = wv;
+        wn += cabs2(wv);
+    }
+    const double wns = blk_sum1(wn, red1);
+    if (threadIdx.x == 0) k.part[blockIdx.x] = wns;
+    if (last_block_ticket(k.counter)) {
+        __shared__ double tot[1];
+        blk_reduce_staged(k.part, gridDim.x, 1, 1, tot, stage);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double b2 = tot[0];
+            const double beta = sqrt(b2);
+            // refinement: once, when the update cancelled most of w
+            const int again = (!refine && b2 < KRY_CANCEL * k.scal[2]) ? 1 : 0;
+            *k.refine = again;
+            k.scal[2] = b2;
+            k.scal[1] = beta;
+            k.Hm[(size_t)j * (mmax + 1) + j + 1] = make_double2(beta, 0.0);
+            if (!again && beta <= 1e-14 * k.scal[0]) *k.meff = j + 1;
+            *k.counter = 0;
+        }
+    }
+}
+
+// refinement dots (gated): h3 = V^H w -> k.h, Hm[:, j] += h3
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_refine1(BigKrylov k, uint32_t N, int j, int mmax) {
+    if (*k.meff || !*k.refine) return;
+    __shared__ double2 hb[64];
+    __shared__ double stage[KRY_STAGE];
+    const int nv = j + 1;
+    const double2 *w = k.V + (size_t)(j + 1) * N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (int i = wave; i < nv; i += nw) {
+        const double2 *vi = k.V + (size_t)i * N;
+        double2 c = make_double2(0.0, 0.0);
+        for (uint32_t base = blockIdx.x * blockDim.x; base < N; base += stride)
+            for (uint32_t t = lane; t < blockDim.x; t += 64) {
+                const uint32_t idx = base + t;
+                if (idx < N) cfmac(c, vi[idx], w[idx]);
+            }
+        c.x = wave_sum(c.x);
+        c.y = wave_sum(c.y);
+        if (lane == 0) hb[i] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        k.part[2 * ((size_t)blockIdx.x * nv + threadIdx.x)] = hb[threadIdx.x].x;
+        k.part[2 * ((size_t)blockIdx.x * nv + threadIdx.x) + 1] = hb[threadIdx.x].y;
+    }
+    if (last_block_ticket(k.counter)) {
+        __shared__ double sums[2 * 65];
+        blk_reduce_staged(k.part, gridDim.x, 2 * nv, 2 * nv, sums, stage);
+        __syncthreads();
+        double2 *hcol = k.Hm + (size_t)j * (mmax + 1);
+        for (int q = threadIdx.x; q < nv; q += blockDim.x) {
+            const double2 sv = make_double2(sums[2 * q], sums[2 * q + 1]);
+            k.h[q] = sv;
+            hcol[q] = cadd(hcol[q], sv);
+        }
+        if (threadIdx.x == 0) *k.counter = 0;
+    }
+}
+
+// w /= beta (no-op after a breakdown)
+__global__ void __launch_bounds__(VEC_THREADS) k_kry_scale1(BigKrylov k, uint32_t N, int j) {
+    if (*k.meff) return;
+    const double ib = 1.0 / k.scal[1];
+    double2 *w = k.V + (size_t)(j + 1) * N;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += gridDim.x * blockDim.x)
+        w[idx] = cscale(w[idx], ib);
+}
+
 // exp of the projected matrix (one work-group); y = beta0 exp(-i tau H_m) e_0
 __global__ void __launch_bounds__(1024) k_kry_expm(BigKrylov k, int m, int mmax, double tau, double tol,
                                                    int hermitian, SolveStat *stat) {
@@ -3481,6 +3659,20 @@ void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStrea
                dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, 1);
     TTN_LAUNCH("k_kry_finalize", 8.0 * N * nv + 2.0 * N, 16.0 * N * (nv + 2), k_kry_finalize,
                dim3(grid_for(N, VEC_THREADS)), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j);
+}
+
+void launch_krylov_orth1(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st) {
+    const unsigned nb = vec_blocks(N);
+    const double nv = j + 1;
+    TTN_LAUNCH("k_kry_dots1", 16.0 * N * nv + 4.0 * N, 16.0 * N * (nv + 1), k_kry_dots1, dim3(nb), dim3(VEC_THREADS),
+               0, st, k, (uint32_t)N, j, mmax);
+    TTN_LAUNCH("k_kry_update1", 8.0 * N * nv + 4.0 * N, 16.0 * N * (nv + 2), k_kry_update1, dim3(nb),
+               dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, 0);
+    // refinement after heavy cancellation (both launches return at once otherwise)
+    TTN_LAUNCH("k_kry_refine1", 0.0, 0.0, k_kry_refine1, dim3(nb), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax);
+    TTN_LAUNCH("k_kry_update1", 0.0, 0.0, k_kry_update1, dim3(nb), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax,
+               1);
+    TTN_LAUNCH("k_kry_scale1", 0.0, 32.0 * N, k_kry_scale1, dim3(nb), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j);
 }
 
 void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double tau, double tol, int hermitian,

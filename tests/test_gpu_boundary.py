@@ -59,12 +59,15 @@ def test_caller_workspace(T, make):
     assert g2.counters()["device_bytes"] < before  # the scratch is not allocated by the library
 
 
-def test_reserved_options_refused(T):
+def test_invalid_options_refused(T):
+    """Flags outside 0/1, and step graphs together with subspace expansion
+    (which changes the launch sequence from step to step), are refused."""
     p = sbm_problem(n_modes=2, d=4, bond=2)
-    for field, value in (("use_graph", 1), ("autotune", 2)):
+    for fields in ({"use_graph": 2}, {"autotune": 2}, {"use_graph": 1, "spawn_tol": 1e-6}):
         opt = T._lib.Options()
         T.lib.ttn_default_options(C.byref(opt))
-        setattr(opt, field, value)
+        for field, value in fields.items():
+            setattr(opt, field, value)
         h = C.c_void_p()
         par = np.ascontiguousarray(p.parent, dtype=np.int32)
         ld = np.ascontiguousarray(p.local_dim, dtype=np.int32)
