@@ -264,8 +264,11 @@ def batch_line(T, n_inst: int, steps: int, warmup: int):
     with and without step graphs."""
     import torch
     from workloads import batch_sbm_problems
-    probs = batch_sbm_problems(seed=5, n_inst=n_inst)
+    allp = batch_sbm_problems(seed=5)
+    stride = max(1, len(allp) // n_inst)
+    probs = allp[::stride][:n_inst]  # spread over the seeded sizes
     dts = np.array([p.dt for p in probs])
+    n_inst = len(probs)
     res = {}
     for name, prec, mode, graph in (("sequential_fp64", 0, None, False), ("streams_fp32", 1, "streams", False),
                                     ("lockstep_fp32", 1, "lockstep", False), ("streams_graph_fp32", 1, "streams", True)):
@@ -280,17 +283,26 @@ def batch_line(T, n_inst: int, steps: int, warmup: int):
             b = T.TTNBatch(gs, lockstep=(mode == "lockstep"))
             b.step(dts, warmup)
         else:
-            for g, p in zip(gs, probs):
+            for i, (g, p) in enumerate(zip(gs, probs)):
                 g.step(p.dt, warmup)
+                if (i + 1) % 64 == 0:
+                    print(f"bench.py: batch, {name}: {i + 1} of {n_inst} instances warmed up", file=sys.stderr,
+                          flush=True)
         torch.cuda.synchronize()
+        print(f"bench.py: batch of {n_inst} instances, {name}: warm-up done", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         if b is not None:
             b.step(dts, steps)
         else:
-            for g, p in zip(gs, probs):
+            for i, (g, p) in enumerate(zip(gs, probs)):
                 g.step(p.dt, steps)
+                if (i + 1) % 64 == 0:
+                    print(f"bench.py: batch, {name}: {i + 1} of {n_inst} instances stepped", file=sys.stderr,
+                          flush=True)
         torch.cuda.synchronize()
         res[name] = n_inst * steps / (time.perf_counter() - t0)
+        print(f"bench.py: batch of {n_inst} instances, {name}: {res[name]:.1f} instance-sweeps/s", file=sys.stderr,
+              flush=True)
         if b is not None:
             b.close()
         for g in gs:
@@ -298,8 +310,8 @@ def batch_line(T, n_inst: int, steps: int, warmup: int):
     best = max(res["streams_fp32"], res["lockstep_fp32"], res["streams_graph_fp32"])
     return {"unit": "instance-sweeps/s", **res, "speedup_best_fp32_vs_sequential_fp64": best / res["sequential_fp64"],
             "note": "streams_graph_fp32: step graphs (use_graph) on several streams",
-            "workload": f"{n_inst} of the 256 seeded uneven spin-boson instances (seed 5), {warmup} warm-up and "
-                        f"{steps} timed sweeps each"}
+            "workload": f"{len(probs)} of the 256 seeded uneven spin-boson instances (seed 5, every {stride}th), "
+                        f"{warmup} warm-up and {steps} timed sweeps each"}
 
 
 def adaptive_line(T, steps: int):
@@ -316,11 +328,13 @@ def adaptive_line(T, steps: int):
     g.set_product_state(p.init_vecs)
     b0 = int(g.bonds().sum())
     per = []
-    for _ in range(steps):
+    for k in range(steps):
         t0 = time.perf_counter()
         g.step(p.dt)
         torch.cuda.synchronize()
         per.append(time.perf_counter() - t0)
+        print(f"bench.py: exciton10x120 with subspace expansion, sweep {k + 1}/{steps}: {per[-1]:.1f} s, bond sum "
+              f"{int(g.bonds().sum())}", file=sys.stderr, flush=True)
     b = g.bonds()
     out = {"unit": "sweeps/s", "value": steps / sum(per), "seconds_per_sweep": per, "bond_sum_start": b0,
            "bond_sum_end": int(b.sum()), "largest_bond": int(b.max()), "norm_minus_1": g.norm2() - 1.0,
@@ -340,8 +354,9 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the error runs from a full-rank start")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--only", choices=list(PRECISIONS), help="time one precision only (profiling runs)")
-    ap.add_argument("--batch-instances", type=int, default=32)
+    ap.add_argument("--batch-instances", type=int, default=16)
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--batch-warmup", type=int, default=1)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -365,7 +380,7 @@ def main():
         st = profiled_sweep(T, g, p)
         r["stage"] = stage_rate(st, prec)
         rooflines[name] = roofline(st, 1, "exciton10x120")
-        r["top_kernels"] = [{k: v for k, v in x.items()} for x in sorted(st, key=lambda x: -x["total_ms"])[:6]]
+        r["top_kernels"] = [{k: v for k, v in x.items()} for x in sorted(st, key=lambda x: -x["total_ms"])[:12]]
         if name == "fp64" or a_matvecs is None:
             node, fwd, mv = g.step_solves()
             root = [z for z in range(p.n_nodes) if p.parent[z] < 0][0]
@@ -413,9 +428,11 @@ def main():
         for key, fn in (("vibronic24", lambda: vibronic_line(T, 30, 3)),
                         ("heom_sbm", lambda: heom_line(T, 3)),
                         ("exciton10x120_adaptive", lambda: adaptive_line(T, 3)),
-                        ("batched_instances", lambda: batch_line(T, args.batch_instances, args.batch_steps, 2))):
+                        ("batched_instances", lambda: batch_line(T, args.batch_instances, args.batch_steps, args.batch_warmup))):
             try:
+                t0 = time.perf_counter()
                 config[key] = fn()
+                print(f"bench.py: {key} line done in {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
             except (T.TTNError, RuntimeError, MemoryError) as e:
                 config[key] = {"error": str(e)}
                 print(f"bench.py: {key} failed: {e}", file=sys.stderr, flush=True)

@@ -1624,7 +1624,9 @@ void Engine::finish_step(double dt) {
                     }
                     m_hint[i] = std::min(mmax, m_hint[i] + 6);
                     redo = true;
-                } else if (q.err_lo <= tol) {
+                } else if (q.err_lo <= 1e-3 * tol) {
+                    // lower the prediction only with a wide margin at two dimensions
+                    // less: a failed prediction costs a whole step
                     m_hint[i] = std::max(3, m_hint[i] - 1);
                 }
             }
