@@ -39,6 +39,7 @@ struct Prog {
     std::vector<PairPass> pair;
     std::vector<double> pair_flops;       // algorithmic flops of each pass
     std::vector<float2 *> pair_w;         // per child slot (null: not allocated)
+    std::vector<unsigned short *> pair_wb;  // BF16x3 hi / lo parts per child slot
     std::vector<PairTerm *> pair_dterms;  // per child slot
     std::vector<int> pair_cap_terms;
 };
@@ -88,6 +89,9 @@ private:
     // FP32 effective generators of large nodes in the pair-operator form
     // (TTN_PAIR_OPS=0 in the environment: staged products only)
     bool pair_ops = true;
+    // multi-kernel Krylov: two classical Gram-Schmidt passes per iteration
+    // instead of the Gram-matrix form (TTN_KRYLOV_CGS2=1)
+    bool krylov_cgs2 = false;
     int64_t pair_min_n = 1 << 18;
     float2 *pair_x32 = nullptr;  // scratch: complex FP32 copy of a pair-form input  // node size from which the pair form is considered (TTN_PAIR_MIN_N)
     hipStream_t own_stream = nullptr;

@@ -48,6 +48,7 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
     graph_mode = opt.use_graph != 0;
     if (const char *e = getenv("TTN_CHOLQR")) cholqr = atoi(e) != 0;
     if (const char *e = getenv("TTN_PAIR_OPS")) pair_ops = atoi(e) != 0;
+    if (const char *e = getenv("TTN_KRYLOV_CGS2")) krylov_cgs2 = atoi(e) != 0;
     if (const char *e = getenv("TTN_PAIR_MIN_N")) pair_min_n = std::max<int64_t>(1, atoll(e));
     if (graph_mode && !st) {  // the null stream cannot be captured: a stream of the handle's own
         HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
@@ -236,7 +237,10 @@ void Engine::merge_entries(Prog &p) {
 
 void Engine::prep(const Prog &p) {
     if (!p.cjobs.empty()) launch_combine(p.d_cjobs, p.d_csrcs, (int)p.cjobs.size(), p.comb_max_n2, st);
-    for (const PairPass &pp : p.pair) launch_pair_build(pp, st);
+    for (const PairPass &pp : p.pair) {
+        launch_pair_build(pp, st);
+        if (pp.Wb) launch_pair_split(pp, st);
+    }
 }
 
 ProgView Engine::view(const Prog &p) const {
@@ -864,9 +868,16 @@ void Engine::apply_prog(const Prog &p, const double2 *in, double2 *out) {
 void Engine::launch_apply(const Prog &p, const ProgView &v, const double2 *in, double2 *out) {
     if (!p.pair.empty()) {
         if (!pair_x32) throw Error(TTN_E_STATE, "internal: pair-form scratch not allocated");
-        launch_to_f32(in, pair_x32, p.g.N, st);
-        for (size_t i = 0; i < p.pair.size(); ++i)
-            launch_pair_gemm(p.pair[i], pair_x32, out, i > 0 ? 1 : 0, p.pair_flops[i], st);
+        if (p.pair[0].Wb) {  // BF16x3: hi and lo parts of the input (4 + 4 bytes per element)
+            unsigned *xh = reinterpret_cast<unsigned *>(pair_x32), *xl = xh + p.g.N;
+            launch_to_bf16x2(in, xh, xl, p.g.N, st);
+            for (size_t i = 0; i < p.pair.size(); ++i)
+                launch_pair_gemm_bf(p.pair[i], xh, xl, out, i > 0 ? 1 : 0, p.pair_flops[i], st);
+        } else {
+            launch_to_f32(in, pair_x32, p.g.N, st);
+            for (size_t i = 0; i < p.pair.size(); ++i)
+                launch_pair_gemm(p.pair[i], pair_x32, out, i > 0 ? 1 : 0, p.pair_flops[i], st);
+        }
         return;
     }
     launch_prog_stages(v, in, st);
@@ -883,7 +894,8 @@ void Engine::launch_apply(const Prog &p, const ProgView &v, const double2 *in, d
 void Engine::plan_pairs(Prog &h, int z) {
     h.pair.clear();
     h.pair_flops.clear();
-    if (opt.precision != TTN_FP32 || !pair_ops || z == t.root || t.local_dim[z] > 0) return;
+    if ((opt.precision != TTN_FP32 && opt.precision != TTN_BF16X3) || !pair_ops || z == t.root || t.local_dim[z] > 0)
+        return;
     const int D = h.g.D, P = D - 1;
     int64_t ncap = 1;
     for (int q = 0; q < D; ++q) ncap *= h.capdims[q];
@@ -935,13 +947,18 @@ void Engine::plan_pairs(Prog &h, int z) {
     }
     if ((int)h.pair_w.size() != P) {
         h.pair_w.assign(P, nullptr);
+        h.pair_wb.assign(P, nullptr);
         h.pair_dterms.assign(P, nullptr);
         h.pair_cap_terms.assign(P, 0);
     }
+    // BF16x3 form of the GEMM where the parent dimension keeps 32-kappa chunks
+    // inside one child index (else the FP32 form serves the BF16x3 mode)
+    const bool bf = opt.precision == TTN_BF16X3 && h.capdims[P] % 32 == 0 && h.g.dims[P] % 32 == 0;
     for (int k = 0; k < P; ++k) {
         if (per[k].empty()) continue;
         const int64_t qcap = (int64_t)h.capdims[k] * h.capdims[P];
         if (!h.pair_w[k]) h.pair_w[k] = (float2 *)dalloc(sizeof(float2) * qcap * qcap);
+        if (bf && !h.pair_wb[k]) h.pair_wb[k] = (unsigned short *)dalloc(sizeof(unsigned short) * 8 * qcap * qcap);
         if (h.pair_cap_terms[k] < (int)per[k].size()) {
             if (h.pair_dterms[k]) throw Error(TTN_E_STATE, "internal: pair-operator terms grew");
             h.pair_dterms[k] = (PairTerm *)dalloc(sizeof(PairTerm) * per[k].size());
@@ -956,6 +973,7 @@ void Engine::plan_pairs(Prog &h, int z) {
         pp.W = h.pair_w[k];
         pp.terms = h.pair_dterms[k];
         pp.n_terms = (int)per[k].size();
+        pp.Wb = bf ? h.pair_wb[k] : nullptr;
         h.pair.push_back(pp);
         h.pair_flops.push_back(8.0 * (double)h.g.N * wcur[k]);
     }
@@ -1072,7 +1090,8 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
         ProgView v = view(p);
         for (int j = 0; j < m; ++j) {
             launch_apply(p, v, bk.V + (size_t)j * N, bk.V + (size_t)(j + 1) * N);
-            launch_krylov_orth1(bk, N, j, mmax, st);
+            if (krylov_cgs2) launch_krylov_orth(bk, N, j, mmax, st);
+            else launch_krylov_orth1(bk, N, j, mmax, st);
         }
         launch_krylov_finish(bk, N, m, mmax, tau, tol, opt.hermitian, x, stat, st);
     }

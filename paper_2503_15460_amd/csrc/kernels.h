@@ -103,6 +103,7 @@ struct PairPass {
     float2 *W;         // W[q][kappa], q = (a, b) output pair, kappa = (a', b') input pair
     const PairTerm *terms;
     int n_terms;
+    unsigned short *Wb;  // BF16x3 form: realified bf16 hi then lo parts, [2Q][2Q] each (null otherwise)
 };
 constexpr int PAIR_KC = 16;  // complex K per LDS chunk of the pair GEMM
 void launch_pair_build(const PairPass &pp, hipStream_t st);
@@ -111,6 +112,12 @@ void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int ac
                       hipStream_t st);
 // y = x rounded to complex FP32 (n elements)
 void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st);
+// BF16x3 form: (Re, Im) of x as bf16 hi and lo pairs; the pair operator split
+// into its realified bf16 hi / lo parts; the GEMM on v_mfma_f32_32x32x16_bf16
+void launch_to_bf16x2(const double2 *x, unsigned *xh, unsigned *xl, int64_t n, hipStream_t st);
+void launch_pair_split(const PairPass &pp, hipStream_t st);
+void launch_pair_gemm_bf(const PairPass &pp, const unsigned *xh, const unsigned *xl, double2 *out, int accumulate,
+                         double flops, hipStream_t st);
 
 // Statistics written by one Krylov solve.
 struct SolveStat {

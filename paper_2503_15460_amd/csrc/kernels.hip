@@ -737,6 +737,219 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__
     }
 }
 
+// ---- BF16x3 form of the pair GEMM.  The operands are split into bf16 hi + lo
+// once (the input per application, the pair operator per build) and each
+// product taken as hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16 (FP32
+// accumulation; the dropped lo*lo term is ~2^-16 relative).  Realified
+// interleaved layout: row o of the A operand holds (Re, Im) of in[o; kappa] at
+// k' = (2 kappa, 2 kappa + 1); row c' = 2q + u of the (transposed) B operand
+// holds [Re W, -Im W] (u = 0) or [Im W, Re W] (u = 1) of W[q][kappa] at the same
+// k'.  A lane of the MFMA reads 8 consecutive k' (16 bytes) of its row.
+// Requires n_P % 32 == 0 (a chunk of 32 kappa lies within one a').
+constexpr int PGB_KS = 32;               // complex kappa per chunk (64 k', 4 MFMA K-steps)
+constexpr int PGB_LD = 2 * PGB_KS + 8;   // bf16 per LDS row (padded: 144 B, conflict-free 16-byte reads)
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned pack_bf16x2(unsigned short lo_half, unsigned short hi_half) {
+    return (unsigned)lo_half | ((unsigned)hi_half << 16);
+}
+
+// xh[i], xl[i]: (Re, Im) of x[i] as bf16 hi and lo parts (low half: Re)
+__global__ void k_to_bf16x2(const double2 *__restrict__ x, unsigned *__restrict__ xh, unsigned *__restrict__ xl,
+                            int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        unsigned short rh, rl, ih, il;
+        bf16_split((float)x[i].x, rh, rl);
+        bf16_split((float)x[i].y, ih, il);
+        xh[i] = pack_bf16x2(rh, ih);
+        xl[i] = pack_bf16x2(rl, il);
+    }
+}
+
+// Wb hi / lo ([2Q][2Q] bf16 each, row c' = 2q + u, column k' = 2 kappa + s) from W[q][kappa]
+__global__ void k_pair_split(PairPass pp) {
+    const int Q = pp.nk * pp.np;
+    const int64_t tot = (int64_t)Q * Q;
+    unsigned *wh = reinterpret_cast<unsigned *>(pp.Wb);
+    unsigned *wl = wh + 2 * tot;  // each array holds 4 Q^2 bf16 = 2 Q^2 pairs
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = i / Q, ka = i - q * Q;
+        const float2 w = pp.W[i];
+        unsigned short reh, rel, imh, iml, nih, nil;
+        bf16_split(w.x, reh, rel);
+        bf16_split(w.y, imh, iml);
+        bf16_split(-w.y, nih, nil);
+        // pair index of (row c', k' = 2 kappa): c' * Q + kappa
+        const int64_t r0 = (2 * q) * Q + ka, r1 = (2 * q + 1) * Q + ka;
+        wh[r0] = pack_bf16x2(reh, nih);
+        wl[r0] = pack_bf16x2(rel, nil);
+        wh[r1] = pack_bf16x2(imh, reh);
+        wl[r1] = pack_bf16x2(iml, rel);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pair_gemm_bf(PairPass pp, const unsigned *__restrict__ Xh,
+                                                      const unsigned *__restrict__ Xl, double2 *__restrict__ Y,
+                                                      int accumulate) {
+    constexpr int BN = 128;  // realified columns per work-group (2 waves x 2 tiles of 32)
+    const int nk = pp.nk, np = pp.np;
+    const int Q = nk * np;
+    const int64_t Mid = pp.Mid, Rk = Mid * np;
+    const int64_t M = pp.L * Mid;
+    const unsigned nct = (unsigned)((2 * Q + BN - 1) / BN);
+    const unsigned nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
+    const unsigned ntile = nct * nrt;
+    unsigned rt, ct;
+    {
+        const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
+        const unsigned q8 = ntile / 8, r8 = ntile % 8;
+        const unsigned t = x * q8 + min(x, r8) + pos;
+        const unsigned gsz = PG_GR * nct;
+        const unsigned g = t / gsz, w = t - g * gsz;
+        const unsigned rows_g = min((unsigned)PG_GR, nrt - g * PG_GR);
+        rt = g * PG_GR + w % rows_g;
+        ct = w / rows_g;
+    }
+    extern __shared__ __attribute__((aligned(16))) unsigned short pgb_lds[];
+    unsigned short *Ah = pgb_lds, *Al = Ah + PG_BM * PGB_LD;
+    unsigned short *Bh = Al + PG_BM * PGB_LD, *Bl = Bh + BN * PGB_LD;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t o0 = (int64_t)rt * PG_BM;
+    const int c0 = (int)ct * BN;  // first realified column
+    // loads: thread (row or column tid >> 1, half tid & 1) takes 16 kappa = 32 k' of each part
+    const int lr = tid >> 1, half = tid & 1;
+    int64_t rbase = -1;
+    {
+        const int64_t o = o0 + lr;
+        if (o < M) {
+            const int64_t l = o / Mid, m = o - l * Mid;
+            rbase = l * nk * Rk + m * np;
+        }
+    }
+    const int cb = c0 + lr;  // B row (realified column) of this thread
+    const unsigned *wh = reinterpret_cast<const unsigned *>(pp.Wb);
+    const unsigned *wl = wh + 2 * (int64_t)Q * Q;
+    uint4 ah[4], al[4], bh[4], bl[4];
+    auto load = [&](int kappa0) {
+        const int ap = kappa0 / np, bp = kappa0 - ap * np;  // the chunk lies in one a' (n_P % 32 == 0)
+        const int ka = kappa0 + 16 * half;
+        if (rbase >= 0 && ka < Q) {
+            const uint4 *ph = reinterpret_cast<const uint4 *>(Xh + rbase + (int64_t)ap * Rk + bp + 16 * half);
+            const uint4 *pl = reinterpret_cast<const uint4 *>(Xl + rbase + (int64_t)ap * Rk + bp + 16 * half);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ah[u] = ph[u];
+                al[u] = pl[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ah[u] = make_uint4(0, 0, 0, 0);
+                al[u] = make_uint4(0, 0, 0, 0);
+            }
+        }
+        if (cb < 2 * Q && ka < Q) {
+            const uint4 *ph = reinterpret_cast<const uint4 *>(wh + (int64_t)cb * Q + ka);
+            const uint4 *pl = reinterpret_cast<const uint4 *>(wl + (int64_t)cb * Q + ka);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bh[u] = ph[u];
+                bl[u] = pl[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bh[u] = make_uint4(0, 0, 0, 0);
+                bl[u] = make_uint4(0, 0, 0, 0);
+            }
+        }
+    };
+    auto store = [&]() {
+        uint4 *dah = reinterpret_cast<uint4 *>(Ah + lr * PGB_LD + 32 * half);
+        uint4 *dal = reinterpret_cast<uint4 *>(Al + lr * PGB_LD + 32 * half);
+        uint4 *dbh = reinterpret_cast<uint4 *>(Bh + lr * PGB_LD + 32 * half);
+        uint4 *dbl = reinterpret_cast<uint4 *>(Bl + lr * PGB_LD + 32 * half);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            dah[u] = ah[u];
+            dal[u] = al[u];
+            dbh[u] = bh[u];
+            dbl[u] = bl[u];
+        }
+    };
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int g8 = (lane >> 5) * 8, l32 = lane & 31;
+    load(0);
+    store();
+    __syncthreads();
+    for (int k0 = 0; k0 < Q; k0 += PGB_KS) {
+        const bool more = k0 + PGB_KS < Q;
+        if (more) load(k0 + PGB_KS);
+#pragma unroll
+        for (int t = 0; t < 2 * PGB_KS; t += 16) {
+            bf8v xh[2], xl[2], yh[2], yl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                xh[i] = __builtin_bit_cast(bf8v, *reinterpret_cast<const uint4 *>(Ah + (wr + 32 * i + l32) * PGB_LD + t + g8));
+                xl[i] = __builtin_bit_cast(bf8v, *reinterpret_cast<const uint4 *>(Al + (wr + 32 * i + l32) * PGB_LD + t + g8));
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                yh[j] = __builtin_bit_cast(bf8v, *reinterpret_cast<const uint4 *>(Bh + (wc + 32 * j + l32) * PGB_LD + t + g8));
+                yl[j] = __builtin_bit_cast(bf8v, *reinterpret_cast<const uint4 *>(Bl + (wc + 32 * j + l32) * PGB_LD + t + g8));
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], yh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], yh[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        if (more) {
+            __syncthreads();
+            store();
+            __syncthreads();
+        }
+    }
+    double *Yd = reinterpret_cast<double *>(Y);
+    const int part = lane >> 5;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int cr = c0 + wc + 32 * j + l32;  // realified column
+        const int q = cr >> 1, ri = cr & 1;
+        if (q >= Q) continue;
+        const int a = q / np, b = q - a * np;
+        const int64_t cofs = (int64_t)a * Rk + b;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            size_t idx[16];
+            bool ok[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t o = o0 + wr + 32 * i + 8 * (v >> 2) + 4 * part + (v & 3);
+                ok[v] = o < M;
+                const int64_t l = o / Mid, m = o - l * Mid;
+                idx[v] = 2 * (size_t)(l * nk * Rk + m * np + cofs) + ri;
+            }
+            double old[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) old[v] = (accumulate && ok[v]) ? Yd[idx[v]] : 0.0;
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                if (ok[v]) Yd[idx[v]] = old[v] + (double)acc[i][j][v];
+        }
+    }
+}
+
 // Coefficient-weighted sum of the entries of each group.  Entries without
 // factors read the FP64 input; the others read their last temporary (type T).
 // Output: out_single (FP64, one group) or the group sums p.gsum (type T).
@@ -3483,6 +3696,27 @@ static int pair_gemm_wn_setting() {
         return (w == 2 || w == 4) ? w : 0;
     }();
     return v;
+}
+
+void launch_to_bf16x2(const double2 *x, unsigned *xh, unsigned *xl, int64_t n, hipStream_t st) {
+    TTN_LAUNCH("k_to_bf16x2", 0.0, 24.0 * n, k_to_bf16x2, dim3(grid_for(n, 256)), dim3(256), 0, st, x, xh, xl, n);
+}
+
+void launch_pair_split(const PairPass &pp, hipStream_t st) {
+    const int64_t q2 = (int64_t)pp.nk * pp.np * pp.nk * pp.np;
+    TTN_LAUNCH("k_pair_split", 0.0, 24.0 * q2, k_pair_split, dim3(grid_for(q2, 256)), dim3(256), 0, st, pp);
+}
+
+void launch_pair_gemm_bf(const PairPass &pp, const unsigned *xh, const unsigned *xl, double2 *out, int accumulate,
+                         double flops, hipStream_t st) {
+    const int Q = pp.nk * pp.np;
+    const int64_t M = pp.L * pp.Mid;
+    const double N = (double)M * Q;
+    const unsigned nct = (unsigned)((2 * Q + 127) / 128), nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
+    const size_t lds = sizeof(unsigned short) * (size_t)(2 * PG_BM + 2 * 128) * PGB_LD;
+    set_lds_limit((const void *)k_pair_gemm_bf, lds);
+    TTN_LAUNCH("k_pair_gemm_bf", flops, 8.0 * N + 16.0 * N * (accumulate ? 2 : 1) + 16.0 * Q * Q, k_pair_gemm_bf,
+               dim3(nct * nrt), dim3(256), lds, st, pp, xh, xl, out, accumulate);
 }
 
 void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st) {

@@ -111,13 +111,16 @@ def test_c3_shaped_tree_parity(T, prec, tol):
     g.close()
 
 
-def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch):
-    """FP32 effective generators in the pair-operator form (each child slot's
+@pytest.mark.parametrize("prec,dtol", [(1, 1e-6), (2, 1e-5)])
+def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch, prec, dtol):
+    """Effective generators in the pair-operator form (each child slot's
     products summed into one dense operator on the pair (child, parent) and
-    applied as a GEMM on the FP32 matrix cores), switched on for every eligible
-    node of the C3-shaped tree by lowering the node-size threshold: three sweeps
-    from the seeded full-rank state against the stored oracle run (1e-4, as the
-    other FP32 contractions) and against the staged FP32 products (1e-6)."""
+    applied as a GEMM on the matrix cores: FP32, or BF16x3 where the parent
+    dimension is a multiple of 32), switched on for every eligible node of the
+    C3-shaped tree by lowering the node-size threshold: three sweeps from the
+    seeded full-rank state against the stored oracle run (1e-4, as the other
+    mixed-precision contractions) and against the staged products of the same
+    precision mode (1e-6 FP32, 1e-5 BF16x3)."""
     import golden_refs as G
     p = G.maker.c3_shaped()
     bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
@@ -127,7 +130,7 @@ def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch):
     for form, env in (("pair", {"TTN_PAIR_MIN_N": "1"}), ("staged", {"TTN_PAIR_OPS": "0"})):
         for k, v in env.items():
             monkeypatch.setenv(k, v)
-        g = T.TTN.from_problem(p, precision=T.TTN_FP32)
+        g = T.TTN.from_problem(p, precision=prec)
         for k in env:
             monkeypatch.delenv(k)
         g.set_state(st)
@@ -139,12 +142,14 @@ def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch):
         names = {r["name"] for r in T.profile_end()}
         runs[form] = np.array(got)
         assert ("k_pair_gemm" in names) == (form == "pair")
+        # the A nodes (parent dimension 32) take the BF16x3 GEMM in that mode
+        assert ("k_pair_gemm_bf" in names) == (form == "pair" and prec == T.TTN_BF16X3)
         g.close()
     err = np.abs(runs["pair"] - ref).max()
     diff = np.abs(runs["pair"] - runs["staged"]).max()
-    print(f"pair form: max error vs oracle {err:.2e}, vs staged FP32 {diff:.2e}")
+    print(f"pair form, precision {prec}: max error vs oracle {err:.2e}, vs staged products {diff:.2e}")
     assert err < 1e-4
-    assert diff < 1e-6
+    assert diff < dtol
 
 
 def test_exciton10x120_full_size_properties(T):
