@@ -283,13 +283,22 @@ __global__ void __launch_bounds__(256) k_mode_tile(ProgView p, int stage, const 
 // [[Re, -Im], [Im, Re]] of M[i][j]; Xt row 2j+b holds part b of X[j].  The
 // realified dimension RD = 32 RT covers 2n.  Every FP32 operand is split into
 // bf16 hi + lo and the product taken as hi*hi + hi*lo + lo*hi
-// (v_mfma_f32_32x32x8 bf16, FP32 accumulation; the dropped lo*lo term is
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation; the dropped lo*lo term is
 // ~2^-16 relative).  Mt of every entry is split once per stage launch by
 // k_mfma_prep; a work-group (4 waves x 32 columns) stages chunks of 32
 // realified K of Mt and Xt in LDS; each wave holds all RT row tiles of its
 // columns.
 typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+// eight consecutive bf16 of an MFMA K=16 operand from two groups of four
+__device__ __forceinline__ bf8v join_bf4(bf4 a, bf4 b) {
+    const u32x2v x = __builtin_bit_cast(u32x2v, a), y = __builtin_bit_cast(u32x2v, b);
+    const u32x4v u = {x[0], x[1], y[0], y[1]};
+    return __builtin_bit_cast(bf8v, u);
+}
 
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
     const unsigned u = __float_as_uint(x);
@@ -428,20 +437,22 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
     store_chunk();
     __syncthreads();
     const int col = wave * 32 + (lane & 31);
-    const int kg = lane >> 5;  // this lane's group of 4 within each 8-wide K step
+    const int kg = 2 * (lane >> 5);  // this lane's two groups of 4 within each 16-wide K step
     for (int k0 = 0; k0 < kmax; k0 += MF_KC) {
         const bool more = k0 + MF_KC < kmax;
         if (more) load_chunk(k0 + MF_KC);
 #pragma unroll
-        for (int ks = 0; ks < MF_KC / 4; ks += 2) {
-            const bf4 bh = Bh[col * MF_KP + ks + kg], bl = Bl[col * MF_KP + ks + kg];
+        for (int ks = 0; ks < MF_KC / 4; ks += 4) {
+            const bf8v bh = join_bf4(Bh[col * MF_KP + ks + kg], Bh[col * MF_KP + ks + kg + 1]);
+            const bf8v bl = join_bf4(Bl[col * MF_KP + ks + kg], Bl[col * MF_KP + ks + kg + 1]);
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int row = t * 32 + (lane & 31);
-                const bf4 ah = Ah[row * MF_KP + ks + kg], al = Al[row * MF_KP + ks + kg];
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[t], 0, 0, 0);
+                const bf8v ah = join_bf4(Ah[row * MF_KP + ks + kg], Ah[row * MF_KP + ks + kg + 1]);
+                const bf8v al = join_bf4(Al[row * MF_KP + ks + kg], Al[row * MF_KP + ks + kg + 1]);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[t], 0, 0, 0);
             }
         }
         if (more) {
@@ -748,8 +759,6 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__
 // Requires n_P % 32 == 0 (a chunk of 32 kappa lies within one a').
 constexpr int PGB_KS = 32;               // complex kappa per chunk (64 k', 4 MFMA K-steps)
 constexpr int PGB_LD = 2 * PGB_KS + 8;   // bf16 per LDS row (padded: 144 B, conflict-free 16-byte reads)
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
-
 __device__ __forceinline__ unsigned pack_bf16x2(unsigned short lo_half, unsigned short hi_half) {
     return (unsigned)lo_half | ((unsigned)hi_half << 16);
 }
