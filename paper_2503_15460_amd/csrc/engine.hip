@@ -1424,9 +1424,16 @@ void Engine::sweep_S(int z, double h) {
         if (t.local_dim[c] > 0) emit([=] { forward(c, h); });
         else sweep_S(c, h);
         emit([=] {
-            if (adaptive && spawn(z, k, h, true)) build_mf(z, k);  // centre at c: new functions of c
+            const int nb0 = t.bond[c];
+            const bool grew = adaptive && spawn(z, k, h, true);  // centre at c: new functions of c
+            if (grew) build_mf(z, k);
             const int pcn = (int)t.dims[c].size() - 1;
             qr_slot(c, pcn, Cbuf, 0);  // up: backward bond step
+            // the new functions enter with zero coefficients: the bond matrix's
+            // block on them (the unit block the QR gives the orthonormal new
+            // columns) is exactly zero, so that rounding in the bond generator
+            // cannot carry its norm into the state
+            if (grew) launch_zero_tail(Cbuf, t.bond[c], nb0, st);
             build_spo(c);
         });
         emit([=] { backward(c, Cbuf, h); });
@@ -1441,8 +1448,11 @@ void Engine::sweep_Sstar(int z, double h) {
     for (int k = (int)kids.size() - 1; k >= 0; --k) {
         const int c = kids[k];
         emit([=] {
-            if (adaptive && spawn(z, k, h, false)) build_spo(c);  // centre at z: new hole functions of c
+            const int nb0 = t.bond[c];
+            const bool grew = adaptive && spawn(z, k, h, false);  // centre at z: new hole functions of c
+            if (grew) build_spo(c);
             qr_slot(z, k, Cbuf, 1);  // down: backward bond step on R^T
+            if (grew) launch_zero_tail(Cbuf, t.bond[c], nb0, st);  // zero coefficients of the new functions
             build_mf(z, k);
         });
         emit([=] { backward(c, Cbuf, h); });

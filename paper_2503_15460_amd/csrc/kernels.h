@@ -110,6 +110,8 @@ void launch_pair_build(const PairPass &pp, hipStream_t st);
 // out (FP64) = (accumulate ? out : 0) + W_k applied to in (complex FP32) on (k, P)
 void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops,
                       hipStream_t st);
+// rows and columns >= keep of the n x n matrix C set to zero
+void launch_zero_tail(double2 *C, int n, int keep, hipStream_t st);
 // y = x rounded to complex FP32 (n elements)
 void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st);
 // BF16x3 form: (Re, Im) of x as bf16 hi and lo pairs; the pair operator split

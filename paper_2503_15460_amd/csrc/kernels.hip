@@ -3163,6 +3163,12 @@ __global__ void k_gkl_count(const int *meffP, const int *meffQ, const double *al
     *n = k;
 }
 
+// rows and columns keep.. of an n x n matrix set to zero
+__global__ void k_zero_tail(double2 *C, int n, int keep) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n * n; q += gridDim.x * blockDim.x)
+        if (q / n >= keep || q % n >= keep) C[q] = make_double2(0.0, 0.0);
+}
+
 __global__ void k_copy_scalars(double *dst, const double *src, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
 }
@@ -3616,8 +3622,10 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     const size_t budget = 150 * 1024 / sizeof(double2);  // elements
     if (aux + (size_t)64 * n > budget) return false;
     const int64_t tile_rows = (int64_t)((budget - aux) / n);
-    // about 2048 matrix elements per work-group, within the tile
-    int64_t rows_per = std::max<int64_t>(64, (2048 + n - 1) / n);
+    // at least 2048 matrix elements per work-group, and few enough work-groups
+    // (about 64, within the tile) that the per-column exchange of partial
+    // records stays small: every work-group reads every record of a column
+    int64_t rows_per = std::max<int64_t>({64, (2048 + n - 1) / n, (m + 63) / 64});
     if (rows_per > tile_rows) rows_per = tile_rows;
     if ((m + rows_per - 1) / rows_per > QRM_BLOCKS_MAX) rows_per = (m + QRM_BLOCKS_MAX - 1) / QRM_BLOCKS_MAX;
     if (rows_per > tile_rows || rows_per < n) return false;
@@ -3688,6 +3696,11 @@ bool launch_qr_chol(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     TTN_LAUNCH("k_cqr_apply", 4.0 * mm * nn, 32.0 * mm * n, k_cqr_apply, dim3(nb), dim3(CQR_THREADS),
                lds_tile + lds_mat, st, A, Lu, n, Ru, rp, q);
     return true;
+}
+
+void launch_zero_tail(double2 *C, int n, int keep, hipStream_t st) {
+    TTN_LAUNCH("k_zero_tail", 0.0, 16.0 * n * n, k_zero_tail, dim3(grid_for((int64_t)n * n, 256)), dim3(256), 0, st, C,
+               n, keep);
 }
 
 void launch_pair_build(const PairPass &pp, hipStream_t st) {

@@ -96,3 +96,26 @@ def test_adaptive_respects_bond_max_and_norm(T):
     for x, y in zip(before, h.get_state()):
         assert np.array_equal(x, y)
     h.step(p.dt)  # still usable
+
+
+def test_fp32_expansion_keeps_the_norm(T):
+    """Subspace expansion in the FP32 mode on the exciton workload from bonds
+    of 8 (two sweeps, the bond sum growing from 649 to ~1300): the new functions
+    enter with zero coefficients, so the norm stays 1 to rounding (the bond
+    matrix's unit block on the new functions, left by the QR, once carried
+    ~1e-5 of norm into the state through FP32 rounding of the bond generator)."""
+    import torch
+    from workloads import exciton_problem
+    p = exciton_problem()
+    start = np.minimum(np.asarray(p.bond_dim), 8)
+    g = T.TTN(p.parent, p.local_dim, start, precision=T.TTN_FP32, spawn_tol=1e-6, bond_max=p.bond_dim, seed=3)
+    g.set_sop_problem(p)
+    g.set_product_state(p.init_vecs)
+    b0 = int(g.bonds().sum())
+    for _ in range(2):
+        g.step(p.dt)
+        torch.cuda.synchronize()
+        print(f"bond sum {int(g.bonds().sum())}, norm - 1 = {g.norm2() - 1:.2e}")
+        assert abs(g.norm2() - 1.0) < 1e-10
+    assert int(g.bonds().sum()) > b0
+    g.close()
