@@ -440,8 +440,9 @@ def main():
                 print(f"bench.py: {key} failed: {e}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cb = cpu_oracle_sample(p, a_matvecs[0], a_matvecs[1], 6, threads)
-        one = cpu_oracle_sample(p, a_matvecs[0], a_matvecs[1], 3, 1)
+        # samples of about 10 s of host work each (0.05-0.1 s per product)
+        cb = cpu_oracle_sample(p, a_matvecs[0], a_matvecs[1], 120, threads)
+        one = cpu_oracle_sample(p, a_matvecs[0], a_matvecs[1], 60, 1)
         cb["value_1_thread"] = one["value"]
         cb["sample_1_thread"] = one["sample"]
         out["cpu_baseline"] = cb
