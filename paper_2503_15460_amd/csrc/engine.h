@@ -92,8 +92,11 @@ private:
     // multi-kernel Krylov: two classical Gram-Schmidt passes per iteration
     // instead of the Gram-matrix form (TTN_KRYLOV_CGS2=1)
     bool krylov_cgs2 = false;
-    int64_t pair_min_n = 1 << 18;
-    float2 *pair_x32 = nullptr;  // scratch: complex FP32 copy of a pair-form input  // node size from which the pair form is considered (TTN_PAIR_MIN_N)
+    int64_t pair_min_n = 1 << 18;  // node size from which the pair form is considered (TTN_PAIR_MIN_N)
+    float2 *pair_x32 = nullptr;    // scratch: complex FP32 copy of a pair-form input
+    // FP32 mode: dense stages with factors of 24..64 on the FP32 matrix cores
+    // (TTN_MODE_MFMA32=0 in the environment: the vector-ALU tiled kernel)
+    bool mode_mfma32 = true;
     hipStream_t own_stream = nullptr;
     struct GraphEntry {
         std::vector<int64_t> key;  // Krylov dimension hints and dt of the captured step

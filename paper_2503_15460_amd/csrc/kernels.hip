@@ -293,6 +293,7 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned u32x2v __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
 // eight consecutive bf16 of an MFMA K=16 operand from two groups of four
 __device__ __forceinline__ bf8v join_bf4(bf4 a, bf4 b) {
     const u32x2v x = __builtin_bit_cast(u32x2v, a), y = __builtin_bit_cast(u32x2v, b);
@@ -476,6 +477,143 @@ __global__ void __launch_bounds__(256) k_mode_mfma(ProgView p, int stage, const 
     }
 }
 
+// ------------------------------------------------------------ FP32 MFMA stage
+// The same realified mode product on the FP32 matrix cores
+// (v_mfma_f32_32x32x2f32) for the FP32 mode: row 2i+a, column 2j+b of the A
+// operand hold the 2x2 real block [[Re, -Im], [Im, Re]] of M[i][j] (built in
+// LDS from the FP64 factor), column c of the B operand the (Re, Im) parts of
+// X[j] at rows 2j, 2j+1.  The realified K order is permuted so that one
+// 16-byte LDS read feeds four K steps: in group g of eight, K step s of lane
+// half h takes realified index 8g + 4h + s (A and B alike, so the sum is
+// unchanged).  Work-group: 4 waves x 32 columns, every wave all RT row tiles of
+// its columns; chunks of 16 complex j pass through LDS, the next chunk's
+// global loads in flight during the current chunk's products.
+constexpr int M32_CW = 128;             // columns per work-group
+constexpr int M32_KC = 32;              // realified K per chunk
+constexpr int M32_LD = M32_KC + 4;      // floats per LDS row (16-byte reads conflict-free)
+
+template <typename TS, int RT>
+__global__ void __launch_bounds__(256) k_mode_mfma32(ProgView p, int stage, const TS *__restrict__ in) {
+    constexpr int RD = 32 * RT;
+    __shared__ float As[RD * M32_LD];
+    __shared__ float Bs[M32_CW * M32_LD];
+    const int e = blockIdx.y;
+    const DevEntry *E = p.ent + e;
+    if (E->nf <= stage) return;
+    const int s = E->slot[stage];
+    const int n = p.g.dims[s];
+    const uint32_t R = (uint32_t)p.g.R[s];
+    const uint32_t N = (uint32_t)p.g.N;
+    const uint32_t ncol = N / (uint32_t)n;
+    const uint32_t c0 = blockIdx.x * (uint32_t)M32_CW;
+    if (c0 >= ncol) return;
+    const double2 *__restrict__ M = E->M[stage];
+    float2 *tmp = reinterpret_cast<float2 *>(p.tmp);
+    const TS *__restrict__ src =
+        stage == 0 ? in + (int64_t)E->src * p.in_stride
+                   : reinterpret_cast<const TS *>(tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N);
+    float2 *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nR = (uint32_t)n * R;
+    f32x16 acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[t][v] = 0.0f;
+    const int kmax = min(RD, 2 * n);
+    constexpr int JC = M32_KC / 2;               // complex j per chunk
+    constexpr int MQ = (RD / 2) * JC / 256;      // complex M values per thread (= RT)
+    constexpr int XQ = M32_CW * JC / 256;        // complex X values per thread
+    double2 mv[MQ];
+    TS xv[XQ];
+    auto xmap = [&](int q, int &cc, int &jj) {
+        if (R == 1) {  // columns are rows of a row-major (ncol, n) matrix: j fastest
+            jj = q % JC;
+            cc = q / JC;
+        } else {
+            cc = q % M32_CW;
+            jj = q / M32_CW;
+        }
+    };
+    auto load_chunk = [&](int k0) {
+        const int j0 = k0 / 2;
+#pragma unroll
+        for (int u = 0; u < MQ; ++u) {
+            const int q = tid + 256 * u;
+            const int i = q / JC, jj = q - i * JC;
+            const int j = j0 + jj;
+            mv[u] = (i < n && j < n) ? M[(size_t)i * n + j] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < XQ; ++u) {
+            int cc, jj;
+            xmap(tid + 256 * u, cc, jj);
+            const int j = j0 + jj;
+            const uint32_t c = c0 + cc;
+            TS v{};
+            if (c < ncol && j < n) {
+                const uint32_t l = c / R, r = c - l * R;
+                v = src[(size_t)l * nR + (size_t)j * R + r];
+            }
+            xv[u] = v;
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int u = 0; u < MQ; ++u) {
+            const int q = tid + 256 * u;
+            const int i = q / JC, jj = q - i * JC;
+            const float re = (float)mv[u].x, im = (float)mv[u].y;
+            *reinterpret_cast<float2 *>(As + (2 * i) * M32_LD + 2 * jj) = make_float2(re, -im);
+            *reinterpret_cast<float2 *>(As + (2 * i + 1) * M32_LD + 2 * jj) = make_float2(im, re);
+        }
+#pragma unroll
+        for (int u = 0; u < XQ; ++u) {
+            int cc, jj;
+            xmap(tid + 256 * u, cc, jj);
+            *reinterpret_cast<float2 *>(Bs + cc * M32_LD + 2 * jj) = make_float2((float)xv[u].x, (float)xv[u].y);
+        }
+    };
+    load_chunk(0);
+    store_chunk();
+    __syncthreads();
+    const int l32 = lane & 31, h = lane >> 5;
+    const int col = wave * 32 + l32;
+    for (int k0 = 0; k0 < kmax; k0 += M32_KC) {
+        const bool more = k0 + M32_KC < kmax;
+        if (more) load_chunk(k0 + M32_KC);
+#pragma unroll
+        for (int g = 0; g < M32_KC / 8; ++g) {
+            const f32x4v b = *reinterpret_cast<const f32x4v *>(Bs + col * M32_LD + 8 * g + 4 * h);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const f32x4v a = *reinterpret_cast<const f32x4v *>(As + (t * 32 + l32) * M32_LD + 8 * g + 4 * h);
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st], b[st], acc[t], 0, 0, 0);
+            }
+        }
+        if (more) {
+            __syncthreads();
+            store_chunk();
+            __syncthreads();
+        }
+    }
+    // the lane holds rows t*32 + (v/4)*8 + h*4 + v%4: pairs (2i, 2i+1) in (v, v+1), v even
+    const uint32_t c = c0 + col;
+    if (c < ncol) {
+        const uint32_t l = c / R, r = c - l * R;
+        float2 *yp = dst + (size_t)l * nR + r;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 16; v += 2) {
+                const int i = (t * 32 + (v >> 2) * 8 + h * 4 + (v & 3)) >> 1;
+                if (i < n) yp[(size_t)i * R] = make_float2(acc[t][v], acc[t][v + 1]);
+            }
+    }
+}
+
 // ------------------------------------------------------------ pair-operator form
 // W_k[q][kappa] = sum_e c_e F_e[a][a'] P_e[b][b'] for q = (a, b), kappa = (a', b')
 // (a null factor is the identity), summed in FP64 and stored row-major,
@@ -572,7 +710,6 @@ constexpr int PG_KS = 16;    // complex kappa per chunk (= K steps of 2 realifie
 constexpr int PG_LDA = 2 * PG_KS + 4;
 constexpr int PG_LDB = 2 * PG_KS + 8;
 constexpr int PG_GR = 4;     // row tiles per group of the tile order
-typedef float f32x4v __attribute__((ext_vector_type(4)));
 
 __global__ void k_to_f32(const double2 *__restrict__ x, float2 *__restrict__ y, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -2699,39 +2836,65 @@ __global__ void __launch_bounds__(VEC_THREADS) k_kry_finalize(BigKrylov k, uint3
 // result then follows (k_kry_refine1, gated: h3 = V^H w, w -= V h3, Hm[:, j] += h3).
 // k_kry_scale1 divides by beta.
 constexpr double KRY_CANCEL = 1e-4;
+// The dots stream the basis in chunks of KD_C vectors: each thread reads w and
+// v_j once per chunk into registers and the chunk's vectors with independent
+// loads (KD_C + 2 in flight per element, two elements per iteration), keeping
+// 2 KD_C complex accumulators; the block then reduces them across its waves.
+constexpr int KD_C = 8;
 __global__ void __launch_bounds__(VEC_THREADS) k_kry_dots1(BigKrylov k, uint32_t N, int j, int mmax) {
     if (*k.meff) return;
     __shared__ double2 hb[64], gb[64];
     __shared__ double red1[16];
+    __shared__ double wred[VEC_THREADS / 64][4 * KD_C];
     __shared__ double stage[KRY_STAGE];
     const int nv = j + 1;
-    const double2 *w = k.V + (size_t)(j + 1) * N;
-    const double2 *vj = k.V + (size_t)j * N;
+    const double2 *__restrict__ V = k.V;
+    const double2 *__restrict__ w = V + (size_t)(j + 1) * N;
+    const double2 *__restrict__ vj = V + (size_t)j * N;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (int i = wave; i < nv; i += nw) {
-        const double2 *vi = k.V + (size_t)i * N;
-        double2 ch = make_double2(0.0, 0.0), cg = make_double2(0.0, 0.0);
-        for (uint32_t base = blockIdx.x * blockDim.x; base < N; base += stride)
-            for (uint32_t t = lane; t < blockDim.x; t += 64) {
-                const uint32_t idx = base + t;
-                if (idx < N) {
-                    const double2 v = vi[idx];
-                    cfmac(ch, v, w[idx]);
-                    cfmac(cg, v, vj[idx]);
+    double wn = 0.0;
+    for (int c0 = 0; c0 < nv; c0 += KD_C) {
+        const int cnt = min(KD_C, nv - c0);
+        const double2 *__restrict__ vc = V + (size_t)c0 * N;
+        double2 ch[KD_C], cg[KD_C];
+#pragma unroll
+        for (int c = 0; c < KD_C; ++c) ch[c] = cg[c] = make_double2(0.0, 0.0);
+#pragma unroll 2
+        for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) {
+            const double2 wv = w[idx], jv = vj[idx];
+            if (c0 == 0) wn += cabs2(wv);
+#pragma unroll
+            for (int c = 0; c < KD_C; ++c)
+                if (c < cnt) {
+                    const double2 v = vc[(size_t)c * N + idx];
+                    cfmac(ch[c], v, wv);
+                    cfmac(cg[c], v, jv);
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < KD_C; ++c) {
+            if (c < cnt) {
+                const double a = wave_sum(ch[c].x), b = wave_sum(ch[c].y);
+                const double d = wave_sum(cg[c].x), e = wave_sum(cg[c].y);
+                if (lane == 0) {
+                    wred[wave][4 * c] = a;
+                    wred[wave][4 * c + 1] = b;
+                    wred[wave][4 * c + 2] = d;
+                    wred[wave][4 * c + 3] = e;
                 }
             }
-        ch.x = wave_sum(ch.x);
-        ch.y = wave_sum(ch.y);
-        cg.x = wave_sum(cg.x);
-        cg.y = wave_sum(cg.y);
-        if (lane == 0) {
-            hb[i] = ch;
-            gb[i] = cg;
         }
+        __syncthreads();
+        if (threadIdx.x < 4 * cnt) {
+            double s = 0.0;
+            for (int q = 0; q < nw; ++q) s += wred[q][threadIdx.x];
+            const int c = threadIdx.x >> 2, r = threadIdx.x & 3;
+            double *dst = r < 2 ? reinterpret_cast<double *>(&hb[c0 + c]) : reinterpret_cast<double *>(&gb[c0 + c]);
+            dst[r & 1] = s;
+        }
+        __syncthreads();
     }
-    double wn = 0.0;
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) wn += cabs2(w[idx]);
     const double wns = blk_sum1(wn, red1);  // synchronises: hb, gb complete
     const int K = 2 * nv + 1;  // complex slots per block: h1, g, |w|^2
     double *part = k.part + (size_t)blockIdx.x * 2 * K;
@@ -3415,11 +3578,13 @@ static void tune_stage(const ProgView &p, int s, const TS *in, hipStream_t st) {
     if (best.ti > 0) tile_table()[key] = best;
 }
 
+static int stage_on_mfma(const ProgView &p, int s);
+
 void tune_prog_stages(const ProgView &p, const double2 *in, hipStream_t st) {
     if (p.n_ent == 0) return;
     ProfileSuspend quiet;  // the trial launches are not part of any profile
     for (int s = 0; s < p.max_nf; ++s) {
-        if (!p.stile[s] || (p.bf16x3 && p.mprep && p.snmin[s] >= 24 && p.snmax[s] <= 64)) continue;
+        if (!p.stile[s] || stage_on_mfma(p, s)) continue;
         if (p.f32) {
             if (s == 0) tune_stage<double2, float2>(p, s, in, st);
             else tune_stage<float2, float2>(p, s, (const float2 *)nullptr, st);
@@ -3495,11 +3660,43 @@ static void launch_mode_mfma(const ProgView &p, int s, const double2 *in, hipStr
 #undef TTN_MFMA_CASE
 }
 
+static void launch_mode_mfma32(const ProgView &p, int s, const double2 *in, hipStream_t st) {
+    const uint32_t maxcol = (uint32_t)(p.g.N / p.snmin[s]);
+    dim3 grid((maxcol + M32_CW - 1) / M32_CW, p.n_ent);
+    const int RT = (p.snmax[s] + 15) / 16;
+    const float2 *none = nullptr;
+#define TTN_M32_CASE(RTV)                                                                                          \
+    case RTV:                                                                                                      \
+        if (s == 0)                                                                                                \
+            TTN_LAUNCH("k_mode_mfma32", p.sflops[s], p.sbytes[s], (k_mode_mfma32<double2, RTV>), grid, dim3(256), \
+                       0, st, p, s, in);                                                                           \
+        else                                                                                                       \
+            TTN_LAUNCH("k_mode_mfma32", p.sflops[s], p.sbytes[s], (k_mode_mfma32<float2, RTV>), grid, dim3(256),  \
+                       0, st, p, s, none);                                                                         \
+        break;
+    switch (RT) {
+        TTN_M32_CASE(2)
+        TTN_M32_CASE(3)
+        TTN_M32_CASE(4)
+    default: throw std::runtime_error("MFMA stage shape out of range");
+    }
+#undef TTN_M32_CASE
+}
+
+// dense stages with factors of 24..64 go to the matrix cores: BF16x3 in the
+// BF16x3 mode, FP32 in the FP32 mode (when enabled)
+static int stage_on_mfma(const ProgView &p, int s) {
+    if (!p.stile[s] || p.snmin[s] < 24 || p.snmax[s] > 64) return 0;
+    if (p.bf16x3 && p.mprep) return 1;
+    if (p.f32 && !p.bf16x3 && p.mfma32) return 2;
+    return 0;
+}
+
 static void launch_mode_tile(const ProgView &p, int s, const double2 *in, hipStream_t st) {
-    // BF16x3 mode: dense stages with factors of 24..64 on the matrix cores
-    if (p.bf16x3 && p.mprep && p.snmin[s] >= 24 && p.snmax[s] <= 64) {
-        launch_mode_mfma(p, s, in, st);
-        return;
+    switch (stage_on_mfma(p, s)) {
+    case 1: launch_mode_mfma(p, s, in, st); return;
+    case 2: launch_mode_mfma32(p, s, in, st); return;
+    default: break;
     }
     if (p.f32) {
         if (s == 0) launch_mode_tile_t<double2, float2>(p, s, in, st, "k_mode_tile_f32");

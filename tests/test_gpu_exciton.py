@@ -57,7 +57,8 @@ def test_exciton_tree_fp64_parity(T):
 
 
 def test_exciton_tree_mixed_precisions(T):
-    """Bonds of 24: the two-child nodes' stages qualify for the matrix cores."""
+    """Bonds of 24: the two-child nodes' stages qualify for the matrix cores
+    (BF16x3 stage in that mode, FP32 stage in the FP32 mode)."""
     p = exciton_problem(n_states=3, n_modes=40, dmin=2, dmax=3, leaf_bond=3, c_bond=24, b_bond=24, a_bond=24,
                         n_inter=8)
     st = random_isometric_state(p.parent, p.local_dim, Oracle(p).bond, seed=13)
@@ -70,6 +71,7 @@ def test_exciton_tree_mixed_precisions(T):
         print(f"precision {prec}: max error {err:.2e}")
         assert err < 1e-4
         assert ("k_mode_mfma" in names) == (prec == T.TTN_BF16X3)
+        assert ("k_mode_mfma32" in names) == (prec == T.TTN_FP32)
 
 
 def _obs10(src, p):
@@ -104,6 +106,7 @@ def test_c3_shaped_tree_parity(T, prec, tol):
     print(f"precision {prec}: max error per observable (P0..P9, a(t)) {np.array2string(err, precision=1)}")
     assert err.max() < tol
     assert ("k_mode_mfma" in names) == (prec == T.TTN_BF16X3)
+    assert ("k_mode_mfma32" in names) == (prec == T.TTN_FP32)
     if prec == T.TTN_FP64:
         terr = G.tensor_sample_error(rec, g.get_state())
         print(f"node tensors (sampled) within {terr:.2e}")
@@ -150,6 +153,43 @@ def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch, prec, dtol):
     print(f"pair form, precision {prec}: max error vs oracle {err:.2e}, vs staged products {diff:.2e}")
     assert err < 1e-4
     assert diff < dtol
+
+
+def test_fp32_matrix_core_stages_on_the_c3_shaped_tree(T, monkeypatch):
+    """FP32 mode, staged products: the dense stages with factors of 24..32 on
+    the FP32 matrix cores (k_mode_mfma32) against the same stages on the vector
+    ALUs (k_mode_tile_f32, TTN_MODE_MFMA32=0): three sweeps from the seeded
+    full-rank state agree to 1e-6 (FP32 accumulation in a different order),
+    and both stay within 1e-4 of the stored oracle run."""
+    import golden_refs as G
+    p = G.maker.c3_shaped()
+    bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
+    st = random_isometric_state(p.parent, p.local_dim, bonds, seed=31)
+    ref = G.observables(G.reference("c3_shaped", p, bonds, st))
+    runs = {}
+    for form, flag in (("mfma", "1"), ("valu", "0")):
+        monkeypatch.setenv("TTN_PAIR_OPS", "0")
+        monkeypatch.setenv("TTN_MODE_MFMA32", flag)
+        g = T.TTN.from_problem(p, precision=T.TTN_FP32)
+        monkeypatch.delenv("TTN_PAIR_OPS")
+        monkeypatch.delenv("TTN_MODE_MFMA32")
+        g.set_state(st)
+        T.profile_begin()
+        got = []
+        for _ in range(3):
+            g.step(p.dt)
+            got.append(_obs10(g, p))
+        names = {r["name"] for r in T.profile_end()}
+        runs[form] = np.array(got)
+        assert ("k_mode_mfma32" in names) == (form == "mfma")
+        g.close()
+    for form in runs:
+        err = np.abs(runs[form] - ref).max()
+        print(f"FP32 stages on {form}: max error vs oracle {err:.2e}")
+        assert err < 1e-4
+    diff = np.abs(runs["mfma"] - runs["valu"]).max()
+    print(f"matrix-core vs vector-ALU stages: {diff:.2e}")
+    assert diff < 1e-6
 
 
 def test_exciton10x120_full_size_properties(T):

@@ -127,8 +127,9 @@ def test_fp32_heom_arnoldi(T):
 # ----------------------------------------------------------- BF16x3 on MFMA
 def test_bf16x3_spin_boson_bond32(T):
     """Bond-32 spin-boson (nodes of 32^3 elements): the dense stages run on the
-    BF16x3 MFMA kernel (checked through the launch profiler) and the observables
-    stay within 1e-4 of the FP64 oracle."""
+    matrix cores (the BF16x3 kernel, or the FP32 kernel in the FP32 mode;
+    checked through the launch profiler) and the observables stay within 1e-4
+    of the FP64 oracle."""
     p = sbm_problem(n_modes=8, d=8, bond=32, alpha=0.3, dt=0.05)
     o = Oracle(p)
     st = random_isometric_state(p.parent, p.local_dim, o.bond, seed=6)
@@ -144,6 +145,7 @@ def test_bf16x3_spin_boson_bond32(T):
         g.step(p.dt)
         names = {r["name"] for r in T.profile_end()}
         assert ("k_mode_mfma" in names) == (prec == T.TTN_BF16X3)
+        assert ("k_mode_mfma32" in names) == (prec == T.TTN_FP32)
         got = [g.expect(p.observables["sz"])]
         for _ in range(2):
             g.step(p.dt)
