@@ -50,6 +50,8 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
     if (const char *e = getenv("TTN_PAIR_OPS")) pair_ops = atoi(e) != 0;
     if (const char *e = getenv("TTN_KRYLOV_CGS2")) krylov_cgs2 = atoi(e) != 0;
     if (const char *e = getenv("TTN_MODE_MFMA32")) mode_mfma32 = atoi(e) != 0;
+    if (const char *e = getenv("TTN_PAIR_SPLIT")) pair_split = atoi(e) != 0;
+    if (const char *e = getenv("TTN_PAIR_SLOTS")) pair_slots = std::max(0, atoi(e));
     if (const char *e = getenv("TTN_PAIR_MIN_N")) pair_min_n = std::max<int64_t>(1, atoll(e));
     if (graph_mode && !st) {  // the null stream cannot be captured: a stream of the handle's own
         HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
@@ -697,11 +699,19 @@ void Engine::set_sop(const SopInput &s) {
     qrw.bar_base = 0;
     // complex FP32 copy of the input of pair-form applications
     pair_x32 = nullptr;
+    pair_ws = nullptr;
     for (int z = 0; z < n; ++z)
         if (!heffP[z].pair.empty()) {
             need(&pair_x32, sizeof(float2) * maxN);
             break;
         }
+    // cut tiles of the shared pair-GEMM schedule (FP32 form)
+    if (pair_split)
+        for (int z = 0; z < n; ++z)
+            if (!heffP[z].pair.empty() && !heffP[z].pair[0].Wb) {
+                need(&pair_ws, pair_gemm_ws_bytes(pair_slots));
+                break;
+            }
     // Cholesky route of the QR: Gram partials, small matrices, first-pass factor
     need(&qrw.cq_part, sizeof(double2) * CQR_BLOCKS_MAX * 64 * 64);
     need(&qrw.cq_G, sizeof(double2) * 64 * 64);
@@ -878,7 +888,7 @@ void Engine::launch_apply(const Prog &p, const ProgView &v, const double2 *in, d
         } else {
             launch_to_f32(in, pair_x32, p.g.N, st);
             for (size_t i = 0; i < p.pair.size(); ++i)
-                launch_pair_gemm(p.pair[i], pair_x32, out, i > 0 ? 1 : 0, p.pair_flops[i], st);
+                launch_pair_gemm(p.pair[i], pair_x32, out, i > 0 ? 1 : 0, p.pair_flops[i], pair_ws, pair_slots, st);
         }
         return;
     }

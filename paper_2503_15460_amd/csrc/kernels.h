@@ -108,9 +108,14 @@ struct PairPass {
 };
 constexpr int PAIR_KC = 16;  // complex K per LDS chunk of the pair GEMM
 void launch_pair_build(const PairPass &pp, hipStream_t st);
-// out (FP64) = (accumulate ? out : 0) + W_k applied to in (complex FP32) on (k, P)
-void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops,
-                      hipStream_t st);
+// out (FP64) = (accumulate ? out : 0) + W_k applied to in (complex FP32) on (k, P).
+// ws (pair_gemm_ws_bytes(ws_slots) bytes, or null): the work is shared evenly
+// by ws_slots work-groups (0: the device's resident capacity), tiles cut
+// between two of them summed from ws by a second kernel in a fixed order;
+// null: one work-group per tile.
+void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops, float *ws,
+                      int ws_slots, hipStream_t st);
+size_t pair_gemm_ws_bytes(int ws_slots);  // workspace of the shared schedule on the current device
 // rows and columns >= keep of the n x n matrix C set to zero
 void launch_zero_tail(double2 *C, int n, int keep, hipStream_t st);
 // y = x rounded to complex FP32 (n elements)

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -716,12 +717,53 @@ __global__ void k_to_f32(const double2 *__restrict__ x, float2 *__restrict__ y, 
         y[i] = make_float2((float)x[i].x, (float)x[i].y);
 }
 
+// Tile order: the tiles are dealt to the 8 XCDs in contiguous ranges (work-
+// groups go to the XCDs in turn, XCD = work-group index mod 8); inside a range
+// they run in groups of PG_GR row tiles by all column tiles, so that the
+// work-groups resident on one XCD share row and column blocks in its L2.
+__host__ __device__ inline void pair_xcd_range(unsigned ntile, unsigned x, unsigned &t0, unsigned &cnt) {
+    const unsigned q8 = ntile / 8, r8 = ntile % 8;
+    t0 = x * q8 + (x < r8 ? x : r8);
+    cnt = q8 + (x < r8 ? 1u : 0u);
+}
+__device__ __forceinline__ void pair_tile_rc(unsigned t, unsigned nrt, unsigned nct, unsigned &rt, unsigned &ct) {
+    const unsigned gsz = PG_GR * nct;
+    const unsigned g = t / gsz, w = t - g * gsz;
+    const unsigned rows_g = min((unsigned)PG_GR, nrt - g * PG_GR);
+    rt = g * PG_GR + w % rows_g;
+    ct = w / rows_g;
+}
+
+// Schedule of a launch: `slots` persistent work-groups (a multiple of 8, the
+// resident capacity of the device), S = min(slots / 8, tiles of the range) of
+// them per XCD.  The range's tiles x K chunks are cut into S equal shares of
+// consecutive (tile, chunk) units; since a share is at least one tile long, a
+// tile holds at most one cut.  A cut tile's two parts go to the workspace
+// (part 0 from the earlier share, part 1 from the later) and k_pair_fixup adds
+// them in that order, so the result does not depend on timing.  With S equal
+// to the tile count every work-group takes one whole tile.
+struct PairSched {
+    unsigned ntile, nrt, nct, kc;  // tiles, row / column tiles, K chunks per tile
+};
+__device__ __forceinline__ bool pair_share(const PairSched &sc, int slots, unsigned x, unsigned pos, unsigned &t0,
+                                           uint64_t &ub, uint64_t &ue, unsigned &S) {
+    unsigned cnt;
+    pair_xcd_range(sc.ntile, x, t0, cnt);
+    S = min((unsigned)slots / 8, cnt);
+    if (pos >= S) return false;
+    const uint64_t U = (uint64_t)cnt * sc.kc;
+    ub = pos * U / S;
+    ue = (pos + 1) * U / S;
+    return true;
+}
+
 // WN: matrix-core tiles per wave along the columns (the work-group covers
 // 64 WN realified columns).  LDS (dynamic): two buffers of the A tile
 // (128 rows of PG_LDA floats) and the B tile (64 WN columns of PG_LDB).
+// Products of one tile over the K chunks [kb, ke) into acc.
 template <int WN>
-__global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__restrict__ X, double2 *__restrict__ Y,
-                                                   int accumulate) {
+__device__ __forceinline__ void pair_gemm_tile(const PairPass &pp, const float2 *__restrict__ X, unsigned rt,
+                                               unsigned ct, int kb, int ke, float *pg_lds, f32x16 (&acc)[2][WN]) {
     constexpr int BN = 64 * WN;       // realified columns per work-group
     constexpr int QW = BN / 2;        // complex q per work-group
     constexpr int BU = 16 * QW / 256; // B values per thread and chunk
@@ -730,21 +772,6 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__
     const int Q = nk * np;
     const int64_t Mid = pp.Mid, Rk = Mid * np;
     const int64_t M = pp.L * Mid;
-    const unsigned nct = (unsigned)((2 * Q + BN - 1) / BN);
-    const unsigned nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
-    const unsigned ntile = nct * nrt;
-    unsigned rt, ct;
-    {
-        const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
-        const unsigned q8 = ntile / 8, r8 = ntile % 8;
-        const unsigned t = x * q8 + min(x, r8) + pos;
-        const unsigned gsz = PG_GR * nct;
-        const unsigned g = t / gsz, w = t - g * gsz;
-        const unsigned rows_g = min((unsigned)PG_GR, nrt - g * PG_GR);
-        rt = g * PG_GR + w % rows_g;
-        ct = w / rows_g;
-    }
-    extern __shared__ __attribute__((aligned(16))) float pg_lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t o0 = (int64_t)rt * PG_BM;
     const int q0 = (int)ct * QW;
@@ -796,7 +823,6 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__
             b1[PG_KS] = bv[u].x;
         }
     };
-    f32x16 acc[2][WN];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -805,13 +831,14 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 32 * WN;
     const int part = lane >> 5, l32 = lane & 31;
-    load(0);
+    load(kb * PG_KS);
+    __syncthreads();  // the previous tile's last products have read both buffers
     store(pg_lds);
     __syncthreads();
     int cur = 0;
-    for (int k0 = 0; k0 < Q; k0 += PG_KS) {
-        const bool more = k0 + PG_KS < Q;
-        if (more) load(k0 + PG_KS);
+    for (int kc = kb; kc < ke; ++kc) {
+        const bool more = kc + 1 < ke;
+        if (more) load((kc + 1) * PG_KS);
         const float *As = pg_lds + cur * BUF, *Bs = As + PG_BM * PG_LDA;
 #pragma unroll
         for (int t4 = 0; t4 < PG_KS; t4 += 4) {
@@ -837,6 +864,21 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__
             cur = 1 - cur;
         }
     }
+}
+
+// Y (+)= the tile's products (FP64 output, read back when accumulating)
+template <int WN>
+__device__ __forceinline__ void pair_gemm_store(const PairPass &pp, double2 *__restrict__ Y, int accumulate,
+                                                unsigned rt, unsigned ct, const f32x16 (&acc)[2][WN]) {
+    constexpr int BN = 64 * WN;
+    const int nk = pp.nk, np = pp.np;
+    const int Q = nk * np;
+    const int64_t Mid = pp.Mid, Rk = Mid * np;
+    const int64_t M = pp.L * Mid;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t o0 = (int64_t)rt * PG_BM;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 32 * WN;
+    const int part = lane >> 5, l32 = lane & 31;
     // lane holds rows 8 (v / 4) + 4 (lane / 32) + v % 4 of column lane % 32 of each 32 x 32 tile
     double *Yd = reinterpret_cast<double *>(Y);
     int64_t obase[2][4];
@@ -883,6 +925,78 @@ __global__ void __launch_bounds__(256) k_pair_gemm(PairPass pp, const float2 *__
                 if (ok[v]) Yd[idx[v]] = old[v] + (double)acc[i][j][v];
         }
     }
+}
+
+// workspace of the cut tiles: part p of cut c holds the 32 WN floats of every
+// thread as 8 WN float4, float4 j of thread tid at ((2 c + p) 8 WN + j) 256 + tid
+template <int WN>
+__device__ __forceinline__ f32x4v *pair_ws_part(float *ws, unsigned cut, int p) {
+    return reinterpret_cast<f32x4v *>(ws) + ((size_t)(2 * cut + p) * 8 * WN) * 256;
+}
+
+template <int WN>
+__global__ void __launch_bounds__(256, WN == 2 ? 2 : 1) k_pair_gemm(PairPass pp, const float2 *__restrict__ X, double2 *__restrict__ Y,
+                                                   int accumulate, float *ws, int slots, PairSched sc) {
+    const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
+    unsigned t0, S;
+    uint64_t ub, ue;
+    if (!pair_share(sc, slots, x, pos, t0, ub, ue, S)) return;
+    extern __shared__ __attribute__((aligned(16))) float pg_lds[];
+    f32x16 acc[2][WN];
+    for (uint64_t u = ub; u < ue;) {
+        const unsigned tl = (unsigned)(u / sc.kc);
+        const int kb = (int)(u - (uint64_t)tl * sc.kc);
+        const int ke = (int)min<uint64_t>(sc.kc, kb + (ue - u));
+        unsigned rt, ct;
+        pair_tile_rc(t0 + tl, sc.nrt, sc.nct, rt, ct);
+        pair_gemm_tile<WN>(pp, X, rt, ct, kb, ke, pg_lds, acc);
+        if (kb == 0 && ke == (int)sc.kc) {
+            pair_gemm_store<WN>(pp, Y, accumulate, rt, ct, acc);
+        } else {  // a cut tile: the cut at this share's start (part 1) or at its end (part 0)
+            const unsigned cut = x * ((unsigned)slots / 8) + (kb == 0 ? pos + 1 : pos);
+            f32x4v *w = pair_ws_part<WN>(ws, cut, kb == 0 ? 0 : 1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const f32x4v v = {acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2],
+                                          acc[i][j][4 * g + 3]};
+                        w[(size_t)((i * WN + j) * 4 + g) * 256 + threadIdx.x] = v;
+                    }
+        }
+        u += (uint64_t)(ke - kb);
+    }
+}
+
+// cut tiles: part 0 + part 1, then the output as for a whole tile
+template <int WN>
+__global__ void __launch_bounds__(256) k_pair_fixup(PairPass pp, double2 *__restrict__ Y, int accumulate,
+                                                    const float *ws, int slots, PairSched sc) {
+    const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
+    unsigned t0, S;
+    uint64_t ub, ue;
+    if (pos == 0 || !pair_share(sc, slots, x, pos, t0, ub, ue, S)) return;
+    if (ub % sc.kc == 0) return;  // the share starts on a tile boundary: no cut
+    unsigned rt, ct;
+    pair_tile_rc(t0 + (unsigned)(ub / sc.kc), sc.nrt, sc.nct, rt, ct);
+    const unsigned cut = x * ((unsigned)slots / 8) + pos;
+    const f32x4v *w0 = pair_ws_part<WN>(const_cast<float *>(ws), cut, 0);
+    const f32x4v *w1 = pair_ws_part<WN>(const_cast<float *>(ws), cut, 1);
+    f32x16 acc[2][WN];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const size_t q = (size_t)((i * WN + j) * 4 + g) * 256 + threadIdx.x;
+                const f32x4v a = w0[q], b = w1[q];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[i][j][4 * g + e] = a[e] + b[e];
+            }
+    pair_gemm_store<WN>(pp, Y, accumulate, rt, ct, acc);
 }
 
 // ---- BF16x3 form of the pair GEMM.  The operands are split into bf16 hi + lo
@@ -3942,28 +4056,73 @@ void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st) {
     TTN_LAUNCH("k_to_f32", 0.0, 24.0 * n, k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, st, x, y, n);
 }
 
-void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops,
-                      hipStream_t st) {
+template <int WN> static size_t pair_gemm_lds() { return sizeof(float) * 2 * (PG_BM * PG_LDA + 64 * WN * PG_LDB); }
+
+// resident work-groups of k_pair_gemm<WN> on the current device (a multiple of
+// 8: the schedule deals whole rounds of the 8 XCDs), computed once per device
+template <int WN> static int pair_gemm_slots() {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    set_lds_limit((const void *)k_pair_gemm<WN>, pair_gemm_lds<WN>());
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_pair_gemm<WN>, 256,
+                                                     pair_gemm_lds<WN>()) != hipSuccess)
+        throw std::runtime_error("pair GEMM: device occupancy query failed");
+    const int slots = std::max(8, (cus * std::max(1, per_cu)) / 8 * 8);
+    cache[dev] = slots;
+    return slots;
+}
+
+template <int WN> static int pair_slots_or(int slots) {
+    return slots > 0 ? std::max(8, slots / 8 * 8) : pair_gemm_slots<WN>();
+}
+
+size_t pair_gemm_ws_bytes(int slots) {
+    // part 0 and part 1 of at most one cut per work-group slot, 32 WN floats per thread each
+    return pair_gemm_wn_setting() == 4 ? (size_t)pair_slots_or<4>(slots) * 2 * 256 * 32 * 4 * sizeof(float)
+                                       : (size_t)pair_slots_or<2>(slots) * 2 * 256 * 32 * 2 * sizeof(float);
+}
+
+template <int WN>
+static void pair_gemm_go(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops, double by,
+                         float *ws, int ws_slots, hipStream_t st) {
+    const int Q = pp.nk * pp.np;
+    const int64_t M = pp.L * pp.Mid;
+    PairSched sc;
+    sc.nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
+    sc.nct = (unsigned)((2 * Q + 64 * WN - 1) / (64 * WN));
+    sc.ntile = sc.nrt * sc.nct;
+    sc.kc = (unsigned)((Q + PG_KS - 1) / PG_KS);
+    const size_t lds = pair_gemm_lds<WN>();
+    set_lds_limit((const void *)k_pair_gemm<WN>, lds);
+    const unsigned per_xcd = (sc.ntile + 7) / 8;  // largest tile range of an XCD
+    // without a workspace: one work-group per tile (shares never cut a tile)
+    const int slots = ws ? pair_slots_or<WN>(ws_slots) : (int)(8 * per_xcd);
+    const unsigned grid = 8 * std::min<unsigned>((unsigned)slots / 8, per_xcd);
+    TTN_LAUNCH("k_pair_gemm", flops, by, k_pair_gemm<WN>, dim3(grid), dim3(256), lds, st, pp, in, out, accumulate, ws,
+               slots, sc);
+    if ((unsigned)slots / 8 < per_xcd) {  // some tiles are cut
+        const double fb = (double)slots * 256 * 32 * WN * 4 * 2 + 16.0 * (double)slots * PG_BM * 32 * WN;
+        TTN_LAUNCH("k_pair_fixup", 0.0, fb, k_pair_fixup<WN>, dim3(slots), dim3(256), 0, st, pp, out, accumulate,
+                   (const float *)ws, slots, sc);
+    }
+}
+
+void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops, float *ws,
+                      int ws_slots, hipStream_t st) {
     const int Q = pp.nk * pp.np;
     const int64_t M = pp.L * pp.Mid;
     const double N = (double)M * Q;
     const double by = 8.0 * N + 16.0 * N * (accumulate ? 2 : 1) + 8.0 * Q * Q;
-    const unsigned nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
     // wider column tiles halve the re-reads of the input where the column count allows
-    const int wn = pair_gemm_wn_setting();
-    if (wn == 4) {
-        const unsigned nct = (unsigned)((2 * Q + 255) / 256);
-        const size_t lds = sizeof(float) * 2 * (PG_BM * PG_LDA + 256 * PG_LDB);
-        set_lds_limit((const void *)k_pair_gemm<4>, lds);
-        TTN_LAUNCH("k_pair_gemm", flops, by, k_pair_gemm<4>, dim3(nct * nrt), dim3(256), lds, st, pp, in, out,
-                   accumulate);
-    } else {
-        const unsigned nct = (unsigned)((2 * Q + 127) / 128);
-        const size_t lds = sizeof(float) * 2 * (PG_BM * PG_LDA + 128 * PG_LDB);
-        set_lds_limit((const void *)k_pair_gemm<2>, lds);
-        TTN_LAUNCH("k_pair_gemm", flops, by, k_pair_gemm<2>, dim3(nct * nrt), dim3(256), lds, st, pp, in, out,
-                   accumulate);
-    }
+    if (pair_gemm_wn_setting() == 4) pair_gemm_go<4>(pp, in, out, accumulate, flops, by, ws, ws_slots, st);
+    else pair_gemm_go<2>(pp, in, out, accumulate, flops, by, ws, ws_slots, st);
 }
 
 static size_t small_solve_total_lds(const SmallSolveArgs &a) {

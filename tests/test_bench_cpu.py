@@ -25,6 +25,15 @@ def test_roofline_takes_the_kernel_with_the_largest_total_time():
     assert abs(r["frac"] - r["achieved"] / bench.PEAK_HBM_GBS) < 1e-15
 
 
+def test_roofline_charges_the_pair_gemm_its_fixup_pass():
+    """The cut tiles of the shared pair-GEMM schedule are summed by a second
+    kernel: its time counts towards the GEMM's launch duration."""
+    stats = [_row("k_pair_gemm", 10, 10.0, 1e12, 1e9), _row("k_pair_fixup", 10, 0.5, 0.0, 1e8)]
+    r = bench.roofline(stats, 1, "x")
+    assert r["kernel"] == "k_pair_gemm" and abs(r["avg_launch_us"] - 1050.0) < 1e-9
+    assert abs(r["achieved"] - 1e11 / 1.05e-3 / 1e12) < 1e-9
+
+
 def test_roofline_compute_bound_classes():
     # no modelled bytes: compute bound; plain FP64 vector code reports "alu" at the FP64 peak
     r = bench.roofline([_row("k_small_solve", 10, 1.0, 1e7, 0.0)], 1, "x")

@@ -155,6 +155,43 @@ def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch, prec, dtol):
     assert diff < dtol
 
 
+def test_shared_pair_gemm_schedule_at_full_size(T, monkeypatch):
+    """The exciton workload at full size (the configuration bench.py times),
+    one sweep from a seeded full-rank state: the A nodes' pair GEMMs (864
+    tiles each) shared evenly by the resident work-groups, tiles cut between
+    two of them summed by k_pair_fixup, against one work-group per tile
+    (TTN_PAIR_SPLIT=0): populations and a(t) agree to 1e-6 (FP32 sums of the
+    cut tiles in two parts) and both stay within 1e-4 of the FP64 sweep (whose
+    kernels are pinned to the oracle on the smaller trees)."""
+    p = exciton_problem()
+    bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
+    st = random_isometric_state(p.parent, p.local_dim, bonds, seed=41)
+    runs = {}
+    for form, prec, env in (("fp64", T.TTN_FP64, {}), ("shared", T.TTN_FP32, {}),
+                            ("tiles", T.TTN_FP32, {"TTN_PAIR_SPLIT": "0"})):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        g = T.TTN.from_problem(p, precision=prec)
+        for k in env:
+            monkeypatch.delenv(k)
+        g.set_state(st)
+        T.profile_begin()
+        g.step(p.dt)
+        names = {r["name"] for r in T.profile_end()}
+        runs[form] = _obs10(g, p)
+        if prec == T.TTN_FP32:
+            assert "k_pair_gemm" in names
+            assert ("k_pair_fixup" in names) == (form == "shared")
+        g.close()
+    for form in ("shared", "tiles"):
+        err = np.abs(runs[form] - runs["fp64"]).max()
+        print(f"pair GEMM, {form}: max difference from the FP64 sweep {err:.2e}")
+        assert err < 1e-4
+    diff = np.abs(runs["shared"] - runs["tiles"]).max()
+    print(f"shared schedule vs one work-group per tile: {diff:.2e}")
+    assert diff < 1e-6
+
+
 def test_fp32_matrix_core_stages_on_the_c3_shaped_tree(T, monkeypatch):
     """FP32 mode, staged products: the dense stages with factors of 24..32 on
     the FP32 matrix cores (k_mode_mfma32) against the same stages on the vector
@@ -198,9 +235,10 @@ def test_exciton10x120_full_size_properties(T):
     sweep from the product state. The oracle cannot run this size, so the
     checks are properties that hold at any size: the FP64 sweep keeps the norm
     and the energy (time-independent Hermitian generator), and the BF16x3 mode
-    (FP64 QR and Krylov around bf16 matrix-core stages) keeps the norm and stays
-    within the rounding floor of product-state starts (3e-3) of the FP64
-    populations."""
+    (FP64 QR and Krylov around bf16 matrix-core stages) and the FP32 mode (the
+    timed configuration: pair-operator GEMM shared by the resident work-groups,
+    FP32 matrix-core stages) keep the norm and stay within the rounding floor
+    of product-state starts (3e-3) of the FP64 populations."""
     p = exciton_problem()
     g = T.TTN.from_problem(p, precision=T.TTN_FP64)
     g.set_product_state(p.init_vecs)
@@ -210,12 +248,17 @@ def test_exciton10x120_full_size_properties(T):
     assert abs(g.norm2() - 1.0) < 1e-10
     assert abs(g.energy() - e0) < 1e-9 * abs(e0)
     g.close()
-    g = T.TTN.from_problem(p, precision=T.TTN_BF16X3)
-    g.set_product_state(p.init_vecs)
-    g.step(p.dt)
-    got = _obs(g, p)
-    assert abs(g.norm2() - 1.0) < 1e-9
-    g.close()
-    err = np.abs(got - ref).max()
-    print(f"BF16x3 vs FP64 after one sweep: {err:.2e}")
-    assert err < 3e-3
+    for prec, label in ((T.TTN_FP32, "FP32"), (T.TTN_BF16X3, "BF16x3")):
+        g = T.TTN.from_problem(p, precision=prec)
+        g.set_product_state(p.init_vecs)
+        T.profile_begin()
+        g.step(p.dt)
+        names = {r["name"] for r in T.profile_end()}
+        got = _obs(g, p)
+        assert abs(g.norm2() - 1.0) < 1e-9
+        g.close()
+        err = np.abs(got - ref).max()
+        print(f"{label} vs FP64 after one sweep: {err:.2e}")
+        assert err < 3e-3
+        if prec == T.TTN_FP32:  # the A nodes' 864 GEMM tiles exceed the resident work-groups: cut tiles
+            assert {"k_pair_gemm", "k_pair_fixup", "k_mode_mfma32"} <= names
