@@ -41,10 +41,12 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # its precision (256 CUs x 2.4 GHz x 128 (FP64) or 256 (FP32) flop/clk/CU);
 # the BF16x3 stage and the BF16x3 pair-operator GEMM run on the bf16 matrix
 # cores (their algorithmic flops count one complex product as 8 flops, while
-# the hardware issues three bf16 products for it), the FP32 stage and the FP32
-# pair-operator GEMM on the FP32 matrix cores (whose dense peak equals the FP32
+# the hardware issues three bf16 products for it), the FP32 stage, the FP32
+# environment contraction and the FP32 pair-operator GEMM on the FP32 matrix
+# cores (whose dense peak equals the FP32
 # vector peak).  First match wins.
-KERNEL_PEAK = [("k_mode_mfma32", "mfma", PEAK_FP32_TFLOPS), ("k_mode_mfma", "mfma", PEAK_BF16_TFLOPS),
+KERNEL_PEAK = [("k_mode_mfma32", "mfma", PEAK_FP32_TFLOPS), ("k_contract_mfma", "mfma", PEAK_FP32_TFLOPS),
+               ("k_mode_mfma", "mfma", PEAK_BF16_TFLOPS),
                ("k_pair_gemm_bf", "mfma", PEAK_BF16_TFLOPS), ("k_pair_gemm", "mfma", PEAK_FP32_TFLOPS),
                ("_f32", "alu", PEAK_FP32_TFLOPS)]
 

@@ -18,6 +18,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -1324,6 +1325,111 @@ __global__ void k_contract_reduce(const double2 *__restrict__ part, int nblk, in
     }
 }
 
+// FP32 mode, n up to 64: the same contraction on the FP32 matrix cores.
+// out = A^H B as one real GEMM over the realified rows: the A operand holds
+// (Re, Im) of A[rho][m] at K = (2 rho, 2 rho + 1); column 2n' of the B operand
+// holds (Re, Im) of B[rho][n'] (giving Re sum conj(a) b) and column 2n' + 1
+// holds (Im, -Re) (giving Im).  A chunk of CM_KC rows passes through LDS
+// (A converted to FP32); the four waves take alternate groups of eight K (in
+// the 16-byte order of the FP32 stage kernel) and are summed through LDS at
+// the end.  The work-groups of one row slice (all groups g) go to one XCD
+// (XCD = work-group index mod 8) so that they find the slice of A in its L2.
+constexpr int CM_KC = 32;              // rows per chunk
+constexpr int CM_LD = 2 * CM_KC + 4;   // floats per LDS row
+
+template <int RT, int CT>
+__global__ void __launch_bounds__(256, 2) k_contract_mfma(const double2 *__restrict__ A, const float2 *__restrict__ Bbase,
+                                                       int64_t bstride, uint32_t L, int n, uint32_t R, int nb,
+                                                       int ng, double2 *__restrict__ part) {
+    const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
+    const int g = (int)(pos % (unsigned)ng);
+    const int slice = (int)(pos / (unsigned)ng) * 8 + (int)x;
+    if (slice >= nb) return;
+    __shared__ __attribute__((aligned(16))) float lds[(32 * RT + 32 * CT) * CM_LD];
+    float *As = lds, *Bs = lds + 32 * RT * CM_LD;
+    const float2 *__restrict__ B = Bbase + (size_t)g * bstride;
+    const uint32_t rows = L * R;
+    const uint32_t per = (rows + nb - 1) / nb;
+    const uint32_t r0 = (uint32_t)slice * per, r1 = min(rows, r0 + per);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int q = tid; q < (32 * RT + 32 * CT) * CM_LD; q += 256) lds[q] = 0.0f;  // padding rows stay zero
+    f32x16 acc[RT][CT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    const int l32 = lane & 31, h = lane >> 5;
+    for (uint32_t t0 = r0; t0 < r1; t0 += CM_KC) {
+        const int tr = (int)min((uint32_t)CM_KC, r1 - t0);
+        __syncthreads();
+        for (int q = tid; q < CM_KC * n; q += 256) {
+            int t, m;
+            if (R == 1) {  // rows of a row-major (rows, n) matrix: m fastest
+                m = q % n;
+                t = q / n;
+            } else {
+                t = q % CM_KC;
+                m = q / CM_KC;
+            }
+            double2 a = make_double2(0.0, 0.0);
+            float2 b = make_float2(0.0f, 0.0f);
+            if (t < tr) {
+                const uint32_t rho = t0 + t, l = rho / R, r = rho - l * R;
+                const size_t at = ((size_t)l * n + m) * R + r;
+                a = A[at];
+                b = B[at];
+            }
+            *reinterpret_cast<float2 *>(As + m * CM_LD + 2 * t) = make_float2((float)a.x, (float)a.y);
+            *reinterpret_cast<float2 *>(Bs + (2 * m) * CM_LD + 2 * t) = b;
+            *reinterpret_cast<float2 *>(Bs + (2 * m + 1) * CM_LD + 2 * t) = make_float2(b.y, -b.x);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg) {
+            const int k8 = 8 * (wave + 4 * gg) + 4 * h;
+            f32x4v b[CT];
+#pragma unroll
+            for (int j = 0; j < CT; ++j) b[j] = *reinterpret_cast<const f32x4v *>(Bs + (j * 32 + l32) * CM_LD + k8);
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const f32x4v a = *reinterpret_cast<const f32x4v *>(As + (i * 32 + l32) * CM_LD + k8);
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+#pragma unroll
+                    for (int j = 0; j < CT; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st], b[j][st], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+    // sum of the four waves' accumulators in LDS (one wave after the other), then the FP64 partial
+    float *red = lds;  // RT * CT * 16 * 64 floats, element (i, j, v) of lane at ((i CT + j) 16 + v) 64 + lane
+    for (int w = 0; w < 4; ++w) {
+        __syncthreads();
+        if (wave == w) {
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int j = 0; j < CT; ++j)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        float *r = red + ((i * CT + j) * 16 + v) * 64 + lane;
+                        *r = w == 0 ? acc[i][j][v] : *r + acc[i][j][v];
+                    }
+        }
+    }
+    __syncthreads();
+    double *pd = reinterpret_cast<double *>(part + ((size_t)g * nb + slice) * n * n);
+    for (int e = tid; e < RT * CT * 16 * 64; e += 256) {
+        const int ln = e & 63, v = (e >> 6) & 15, ij = e >> 10;
+        const int i = ij / CT, j = ij - i * CT;
+        const int m = i * 32 + 8 * (v >> 2) + 4 * (ln >> 5) + (v & 3);
+        const int c = j * 32 + (ln & 31);
+        if (m < n && c < 2 * n) pd[2 * ((size_t)m * n + (c >> 1)) + (c & 1)] = (double)red[e];
+    }
+}
+
 static int contract_blocks(uint32_t rows) {
     int b = (int)((rows + 255) / 256);
     return b < 1 ? 1 : (b > 64 ? 64 : b);
@@ -2164,6 +2270,80 @@ __global__ void __launch_bounds__(CQR_THREADS) k_cqr_gram(const double2 *A, uint
     }
 }
 
+// The same Gram partials on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+// G = X^H X as one real GEMM over the realified rows of each LDS tile, the A
+// operand (Re, Im) of X[t][i] at K = (2t, 2t+1), column 2j of the B operand
+// (Re, Im) of X[t][j] (giving Re G[i][j]) and column 2j+1 (Im, -Re) (giving
+// Im G[i][j]).  RT x CT output tiles of 16 x 16 (RT = ceil(n / 16), CT =
+// ceil(2n / 16)); wave w owns the contiguous run of tiles
+// [w TPW, (w + 1) TPW) over the whole K of every tile of rows.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <bool APPLY, int RT, int CT>
+__global__ void __launch_bounds__(CQR_THREADS) k_cqr_gram_mfma(const double2 *A, uint32_t L, int n, uint32_t R,
+                                                               uint32_t rows_per, QRWork q) {
+    constexpr int TPW = (RT * CT + 3) / 4;  // tiles per wave
+    if (APPLY && *q.cq_state != 0) return;
+    const uint32_t m = L * R;
+    const uint32_t r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
+    extern __shared__ double2 sc[];
+    const int ld = n + 1;
+    double2 *Xs = sc;
+    double2 *Ms = sc + CQR_TILE * ld;
+    if (APPLY)
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) Ms[e] = q.cq_R1inv[e];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, kq = lane >> 4;  // operand lane: row / column l16, K index kq
+    f64x4 acc[TPW];
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) acc[k] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (uint32_t t0 = r0; t0 < r1; t0 += CQR_TILE) {
+        cqr_load(Xs, ld, A, t0, r1, n, R);
+        __syncthreads();
+        if (APPLY) {
+            cqr_tile_times_upper(Xs, ld, Ms, n);
+            for (int e = threadIdx.x; e < CQR_TILE * n; e += blockDim.x) {
+                const uint32_t rho = t0 + (uint32_t)(e / n);
+                if (rho < r1) q.cq_Y[(size_t)rho * n + e % n] = Xs[(e / n) * ld + e % n];
+            }
+        }
+        // K step s covers tile rows 2s, 2s + 1 (both parts): lane K index kq is row 2s + kq / 2, part kq % 2
+        for (int s2 = 0; s2 < CQR_TILE / 2; ++s2) {
+            const int t = 2 * s2 + (kq >> 1), part = kq & 1;
+            const double2 *xr = Xs + t * ld;
+#pragma unroll
+            for (int k = 0; k < TPW; ++k) {
+                const int tau = wave * TPW + k;
+                if (tau < RT * CT) {
+                    const int i = (tau / CT) * 16 + l16, jc = (tau % CT) * 16 + l16;
+                    const int j = jc >> 1;
+                    double a = 0.0, b = 0.0;
+                    if (i < n) a = part ? xr[i].y : xr[i].x;
+                    if (j < n) {
+                        const double2 x = xr[j];
+                        b = (jc & 1) ? (part ? -x.x : x.y) : (part ? x.y : x.x);
+                    }
+                    acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // register r of the lane holds row 4 r + lane / 16 of column lane % 16 of each 16 x 16 tile
+    double *part = reinterpret_cast<double *>(q.cq_part + (size_t)blockIdx.x * n * n);
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+        const int tau = wave * TPW + k;
+        if (tau >= RT * CT) continue;
+        const int jc = (tau % CT) * 16 + l16, j = jc >> 1;
+        if (j >= n) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = (tau / CT) * 16 + 4 * r + kq;
+            if (i < n) part[2 * ((size_t)i * n + j) + (jc & 1)] = acc[k][r];
+        }
+    }
+}
+
 // in-place upper Cholesky factor of the Hermitian G (n x n in LDS, G = R^H R);
 // returns false when a pivot is not positive and finite
 __device__ bool cqr_cholesky(double2 *G, int n) {
@@ -2955,11 +3135,12 @@ constexpr double KRY_CANCEL = 1e-4;
 // loads (KD_C + 2 in flight per element, two elements per iteration), keeping
 // 2 KD_C complex accumulators; the block then reduces them across its waves.
 constexpr int KD_C = 8;
-__global__ void __launch_bounds__(VEC_THREADS) k_kry_dots1(BigKrylov k, uint32_t N, int j, int mmax) {
+constexpr int KD_THREADS = 512;  // two waves per SIMD: twice the loads in flight of the 256-thread kernels
+__global__ void __launch_bounds__(KD_THREADS) k_kry_dots1(BigKrylov k, uint32_t N, int j, int mmax) {
     if (*k.meff) return;
     __shared__ double2 hb[64], gb[64];
     __shared__ double red1[16];
-    __shared__ double wred[VEC_THREADS / 64][4 * KD_C];
+    __shared__ double wred[KD_THREADS / 64][4 * KD_C];
     __shared__ double stage[KRY_STAGE];
     const int nv = j + 1;
     const double2 *__restrict__ V = k.V;
@@ -3865,7 +4046,18 @@ void launch_prog_contract(const ProgView &p, const double2 *A, hipStream_t st) {
     const uint32_t L = (uint32_t)p.g.L[s], R = (uint32_t)p.g.R[s];
     const int nb = contract_blocks(L * R);
     const size_t lds = sizeof(double2) * (size_t)CT_ROWS * 2 * n;
-    if (p.f32)
+    if (p.f32 && p.mfma32 && n <= 64) {
+        const unsigned grid = 8 * (unsigned)((nb + 7) / 8) * (unsigned)p.n_groups;
+        const double fl = 8.0 * p.g.N * n * p.n_groups, by = (16.0 + 8.0) * p.g.N * p.n_groups;
+#define TTN_CM(RTV, CTV)                                                                                            \
+    TTN_LAUNCH("k_contract_mfma", fl, by, (k_contract_mfma<RTV, CTV>), dim3(grid), dim3(256), 0, st, A,             \
+               (const float2 *)p.gsum, p.g.N, L, n, R, nb, p.n_groups, p.cpart)
+        if (n <= 16) TTN_CM(1, 1);
+        else if (n <= 32) TTN_CM(1, 2);
+        else if (n <= 48) TTN_CM(2, 3);
+        else TTN_CM(2, 4);
+#undef TTN_CM
+    } else if (p.f32)
         TTN_LAUNCH("k_contract_part_f32", 8.0 * p.g.N * n * p.n_groups, 16.0 * p.g.N + 8.0 * p.g.N * p.n_groups,
                    k_contract_part<float2>, dim3(nb, p.n_groups), dim3(256), lds / 2, st, A,
                    (const float2 *)p.gsum, p.g.N, L, n, n, R, p.cpart);
@@ -3977,6 +4169,16 @@ bool launch_qr_coop(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     return true;
 }
 
+// Gram partials of the Cholesky route on the FP64 matrix cores (TTN_CQR_MFMA=0:
+// the vector-ALU kernel)
+static bool cqr_mfma_setting() {
+    static const bool v = [] {
+        const char *e = getenv("TTN_CQR_MFMA");
+        return e ? atoi(e) != 0 : true;
+    }();
+    return v;
+}
+
 bool launch_qr_chol(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int transR, const QRWork &q,
                     hipStream_t st) {
     const int64_t m = L * R;
@@ -3996,12 +4198,32 @@ bool launch_qr_chol(double2 *A, int64_t L, int n, int64_t R, double2 *Rout, int 
     set_lds_limit((const void *)k_cqr_apply, lds_tile + lds_mat);
     const uint32_t Lu = (uint32_t)L, Ru = (uint32_t)R, rp = (uint32_t)rows_per;
     const double2 *Ac = A;
-    TTN_LAUNCH("k_cqr_gram", 8.0 * mm * nn, 16.0 * (mm * n + nb * nn), k_cqr_gram<false>, dim3(nb),
-               dim3(CQR_THREADS), lds_tile, st, Ac, Lu, n, Ru, rp, q);
+    const bool mf = cqr_mfma_setting();
+    auto gram = [&](auto tag) {
+        constexpr bool AP = decltype(tag)::value;
+        const double fl = AP ? 12.0 * mm * nn : 8.0 * mm * nn;
+        const double by = AP ? 16.0 * (2 * mm * n + nb * nn) : 16.0 * (mm * n + nb * nn);
+        const size_t lds = AP ? lds_tile + lds_mat : lds_tile;
+        if (!mf) {
+            TTN_LAUNCH("k_cqr_gram", fl, by, k_cqr_gram<AP>, dim3(nb), dim3(CQR_THREADS), lds, st, Ac, Lu, n, Ru, rp, q);
+            return;
+        }
+#define TTN_CQG(RTV, CTV)                                                                                          \
+    do {                                                                                                           \
+        set_lds_limit((const void *)k_cqr_gram_mfma<AP, RTV, CTV>, lds);                                           \
+        TTN_LAUNCH("k_cqr_gram_mfma", fl, by, (k_cqr_gram_mfma<AP, RTV, CTV>), dim3(nb), dim3(CQR_THREADS), lds, st, \
+                   Ac, Lu, n, Ru, rp, q);                                                                          \
+    } while (0)
+        if (n <= 16) TTN_CQG(1, 2);
+        else if (n <= 32) TTN_CQG(2, 4);
+        else if (n <= 48) TTN_CQG(3, 6);
+        else TTN_CQG(4, 8);
+#undef TTN_CQG
+    };
+    gram(std::false_type{});
     TTN_LAUNCH("k_cqr_reduce", 2.0 * nb * nn, 16.0 * nb * nn, k_cqr_reduce, dim3(nbr), dim3(CQR_RTHREADS), 2 * lds_mat,
                st, (int)nb, n, 1, q, Rout, transR);
-    TTN_LAUNCH("k_cqr_gram", 12.0 * mm * nn, 16.0 * (2 * mm * n + nb * nn), k_cqr_gram<true>, dim3(nb),
-               dim3(CQR_THREADS), lds_tile + lds_mat, st, Ac, Lu, n, Ru, rp, q);
+    gram(std::true_type{});
     TTN_LAUNCH("k_cqr_reduce", 2.0 * nb * nn, 16.0 * nb * nn, k_cqr_reduce, dim3(nbr), dim3(CQR_RTHREADS), 2 * lds_mat,
                st, (int)nb, n, 2, q, Rout, transR);
     TTN_LAUNCH("k_cqr_apply", 4.0 * mm * nn, 32.0 * mm * n, k_cqr_apply, dim3(nb), dim3(CQR_THREADS),
@@ -4276,7 +4498,7 @@ void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStrea
 void launch_krylov_orth1(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st) {
     const unsigned nb = vec_blocks(N);
     const double nv = j + 1;
-    TTN_LAUNCH("k_kry_dots1", 16.0 * N * nv + 4.0 * N, 16.0 * N * (nv + 1), k_kry_dots1, dim3(nb), dim3(VEC_THREADS),
+    TTN_LAUNCH("k_kry_dots1", 16.0 * N * nv + 4.0 * N, 16.0 * N * (nv + 1), k_kry_dots1, dim3(nb), dim3(KD_THREADS),
                0, st, k, (uint32_t)N, j, mmax);
     TTN_LAUNCH("k_kry_update1", 8.0 * N * nv + 4.0 * N, 16.0 * N * (nv + 2), k_kry_update1, dim3(nb),
                dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax, 0);

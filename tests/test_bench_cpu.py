@@ -46,6 +46,8 @@ def test_roofline_compute_bound_classes():
     # the FP32 matrix-core stage against the FP32 peak (its name extends the bf16 stage's)
     r = bench.roofline([_row("k_mode_mfma32", 10, 1.0, 1e11, 1e7)], 1, "x")
     assert r["bound"] == "mfma" and r["peak"] == bench.PEAK_FP32_TFLOPS
+    r = bench.roofline([_row("k_contract_mfma", 10, 1.0, 1e11, 1e7)], 1, "x")
+    assert r["bound"] == "mfma" and r["peak"] == bench.PEAK_FP32_TFLOPS
     # the pair-operator GEMMs: FP32 matrix cores, and bf16 matrix cores in the BF16x3 form
     r = bench.roofline([_row("k_pair_gemm", 10, 1.0, 1e11, 1e7)], 1, "x")
     assert r["bound"] == "mfma" and r["peak"] == bench.PEAK_FP32_TFLOPS

@@ -193,11 +193,13 @@ def test_shared_pair_gemm_schedule_at_full_size(T, monkeypatch):
 
 
 def test_fp32_matrix_core_stages_on_the_c3_shaped_tree(T, monkeypatch):
-    """FP32 mode, staged products: the dense stages with factors of 24..32 on
-    the FP32 matrix cores (k_mode_mfma32) against the same stages on the vector
-    ALUs (k_mode_tile_f32, TTN_MODE_MFMA32=0): three sweeps from the seeded
-    full-rank state agree to 1e-6 (FP32 accumulation in a different order),
-    and both stay within 1e-4 of the stored oracle run."""
+    """FP32 mode, staged products: the dense stages with factors of 24..32
+    (k_mode_mfma32) and the environment contractions with bonds of 16..64
+    (k_contract_mfma) on the FP32 matrix cores against the same work on the
+    vector ALUs (k_mode_tile_f32, k_contract_part_f32; TTN_MODE_MFMA32=0):
+    three sweeps from the seeded full-rank state agree to 1e-6 (FP32
+    accumulation in a different order), and both stay within 1e-4 of the
+    stored oracle run."""
     import golden_refs as G
     p = G.maker.c3_shaped()
     bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
@@ -219,6 +221,7 @@ def test_fp32_matrix_core_stages_on_the_c3_shaped_tree(T, monkeypatch):
         names = {r["name"] for r in T.profile_end()}
         runs[form] = np.array(got)
         assert ("k_mode_mfma32" in names) == (form == "mfma")
+        assert ("k_contract_mfma" in names) == (form == "mfma")
         g.close()
     for form in runs:
         err = np.abs(runs[form] - ref).max()
