@@ -93,7 +93,7 @@ private:
     // instead of the Gram-matrix form (TTN_KRYLOV_CGS2=1)
     bool krylov_cgs2 = false;
     int64_t pair_min_n = 1 << 18;  // node size from which the pair form is considered (TTN_PAIR_MIN_N)
-    float2 *pair_x32 = nullptr;    // scratch: complex FP32 copy of a pair-form input
+    float2 *pair_x32 = nullptr;    // scratch (FP32 modes): complex FP32 copy of a pair-form or first-stage input
     // FP32 pair GEMM shared evenly by the resident work-groups, cut tiles
     // summed from pair_ws (TTN_PAIR_SPLIT=0: one work-group per tile)
     bool pair_split = true;

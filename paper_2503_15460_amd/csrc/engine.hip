@@ -698,13 +698,11 @@ void Engine::set_sop(const SopInput &s) {
     need(&qrw.bar, sizeof(unsigned) * 192);
     qrw.bar_base = 0;
     // complex FP32 copy of the input of pair-form applications
+    // complex FP32 copy of an input (FP32 modes): pair-form applications and
+    // the shared first-stage input of the staged programs
     pair_x32 = nullptr;
     pair_ws = nullptr;
-    for (int z = 0; z < n; ++z)
-        if (!heffP[z].pair.empty()) {
-            need(&pair_x32, sizeof(float2) * maxN);
-            break;
-        }
+    if (opt.precision == TTN_FP32 || opt.precision == TTN_BF16X3) need(&pair_x32, sizeof(float2) * maxN);
     // cut tiles of the shared pair-GEMM schedule (FP32 form)
     if (pair_split)
         for (int z = 0; z < n; ++z)
@@ -892,7 +890,7 @@ void Engine::launch_apply(const Prog &p, const ProgView &v, const double2 *in, d
         }
         return;
     }
-    launch_prog_stages(v, in, st);
+    launch_prog_stages(v, in, st, pair_x32);
     launch_prog_sum(v, in, out, st);
 }
 
@@ -996,7 +994,7 @@ void Engine::build_spo(int c) {
     if (p.n_groups == 0) return;
     prep(p);
     ProgView v = view(p);
-    launch_prog_stages(v, A[c], st);
+    launch_prog_stages(v, A[c], st, pair_x32);
     launch_prog_sum(v, A[c], nullptr, st);
     launch_prog_contract(v, A[c], st);
 }
@@ -1006,7 +1004,7 @@ void Engine::build_mf(int z, int k) {
     if (p.n_groups == 0) return;
     prep(p);
     ProgView v = view(p);
-    launch_prog_stages(v, A[z], st);
+    launch_prog_stages(v, A[z], st, pair_x32);
     launch_prog_sum(v, A[z], nullptr, st);
     launch_prog_contract(v, A[z], st);
 }

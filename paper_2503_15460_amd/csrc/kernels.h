@@ -231,7 +231,10 @@ struct ProfileSuspend {
 };
 
 // ---- launchers (all asynchronous on `st`) ----
-void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st);
+// x32 (FP32 mode, optional): N complex FP32 of scratch; with several entries
+// the FP64 input is converted into it once and every entry's first stage
+// reads the FP32 copy (the values each stage would have converted itself)
+void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st, float2 *x32 = nullptr);
 // tile autotuner: time every admissible register tile of each tiled stage of p
 // and keep the fastest (process-wide table, keyed by the stage's shape)
 void tune_prog_stages(const ProgView &p, const double2 *in, hipStream_t st);

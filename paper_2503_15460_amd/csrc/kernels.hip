@@ -3928,7 +3928,7 @@ int tile_table_load(const char *path) {
 
 void tile_table_clear() { tile_table().clear(); }
 
-static void launch_mode_mfma(const ProgView &p, int s, const double2 *in, hipStream_t st) {
+static void launch_mode_mfma(const ProgView &p, int s, const double2 *in, const float2 *in32, hipStream_t st) {
     const uint32_t maxcol = (uint32_t)(p.g.N / p.snmin[s]);
     dim3 grid((maxcol + MF_CW - 1) / MF_CW, p.n_ent);
     const int RT = (p.snmax[s] + 15) / 16;
@@ -3936,15 +3936,15 @@ static void launch_mode_mfma(const ProgView &p, int s, const double2 *in, hipStr
     TTN_LAUNCH("k_mfma_prep", 0.0, 4.0 * RD * RD * p.n_ent, k_mfma_prep, dim3(4, p.n_ent), dim3(256), 0, st, p, s,
                RD, p.mprep);
     const unsigned short *mp = p.mprep;
-    const float2 *none = nullptr;
+    const float2 *f = s == 0 ? in32 : nullptr;
 #define TTN_MFMA_CASE(RTV)                                                                                      \
     case RTV:                                                                                                   \
-        if (s == 0)                                                                                             \
+        if (s == 0 && !in32)                                                                                    \
             TTN_LAUNCH("k_mode_mfma", p.sflops[s], p.sbytes[s], (k_mode_mfma<double2, RTV>), grid, dim3(256), 0, \
                        st, p, s, in, mp);                                                                       \
         else                                                                                                    \
             TTN_LAUNCH("k_mode_mfma", p.sflops[s], p.sbytes[s], (k_mode_mfma<float2, RTV>), grid, dim3(256), 0,  \
-                       st, p, s, none, mp);                                                                     \
+                       st, p, s, f, mp);                                                                        \
         break;
     switch (RT) {
         TTN_MFMA_CASE(2)
@@ -3955,19 +3955,19 @@ static void launch_mode_mfma(const ProgView &p, int s, const double2 *in, hipStr
 #undef TTN_MFMA_CASE
 }
 
-static void launch_mode_mfma32(const ProgView &p, int s, const double2 *in, hipStream_t st) {
+static void launch_mode_mfma32(const ProgView &p, int s, const double2 *in, const float2 *in32, hipStream_t st) {
     const uint32_t maxcol = (uint32_t)(p.g.N / p.snmin[s]);
     dim3 grid((maxcol + M32_CW - 1) / M32_CW, p.n_ent);
     const int RT = (p.snmax[s] + 15) / 16;
-    const float2 *none = nullptr;
+    const float2 *f = s == 0 ? in32 : nullptr;
 #define TTN_M32_CASE(RTV)                                                                                          \
     case RTV:                                                                                                      \
-        if (s == 0)                                                                                                \
+        if (s == 0 && !in32)                                                                                       \
             TTN_LAUNCH("k_mode_mfma32", p.sflops[s], p.sbytes[s], (k_mode_mfma32<double2, RTV>), grid, dim3(256), \
                        0, st, p, s, in);                                                                           \
         else                                                                                                       \
             TTN_LAUNCH("k_mode_mfma32", p.sflops[s], p.sbytes[s], (k_mode_mfma32<float2, RTV>), grid, dim3(256),  \
-                       0, st, p, s, none);                                                                         \
+                       0, st, p, s, f);                                                                            \
         break;
     switch (RT) {
         TTN_M32_CASE(2)
@@ -3987,40 +3987,47 @@ static int stage_on_mfma(const ProgView &p, int s) {
     return 0;
 }
 
-static void launch_mode_tile(const ProgView &p, int s, const double2 *in, hipStream_t st) {
+static void launch_mode_tile(const ProgView &p, int s, const double2 *in, const float2 *in32, hipStream_t st) {
     switch (stage_on_mfma(p, s)) {
-    case 1: launch_mode_mfma(p, s, in, st); return;
-    case 2: launch_mode_mfma32(p, s, in, st); return;
+    case 1: launch_mode_mfma(p, s, in, in32, st); return;
+    case 2: launch_mode_mfma32(p, s, in, in32, st); return;
     default: break;
     }
     if (p.f32) {
-        if (s == 0) launch_mode_tile_t<double2, float2>(p, s, in, st, "k_mode_tile_f32");
-        else launch_mode_tile_t<float2, float2>(p, s, (const float2 *)nullptr, st, "k_mode_tile_f32");
+        if (s == 0 && !in32) launch_mode_tile_t<double2, float2>(p, s, in, st, "k_mode_tile_f32");
+        else launch_mode_tile_t<float2, float2>(p, s, s == 0 ? in32 : nullptr, st, "k_mode_tile_f32");
     } else {
         launch_mode_tile_t<double2, double2>(p, s, in, st, "k_mode_tile");
     }
 }
 
-void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st) {
+void launch_prog_stages(const ProgView &p, const double2 *in, hipStream_t st, float2 *x32) {
     if (p.n_ent == 0) return;
     int maxn = 0;
     for (int s = 0; s < p.g.D; ++s) maxn = maxn > p.g.dims[s] ? maxn : p.g.dims[s];
     const int ldn = maxn <= 64 ? maxn : 0;
     const size_t lds = sizeof(double2) * (size_t)ldn * ldn;
+    // one conversion of the shared input instead of one per entry (every entry
+    // reads the same input when in_stride is 0)
+    const float2 *in32 = nullptr;
+    if (p.f32 && x32 && p.in_stride == 0 && p.n_ent >= 4 && p.max_nf > 0) {
+        launch_to_f32(in, x32, p.g.N, st);
+        in32 = x32;
+    }
     for (int s = 0; s < p.max_nf; ++s) {
         if (p.stile[s]) {
-            launch_mode_tile(p, s, in, st);
+            launch_mode_tile(p, s, in, in32, st);
             continue;
         }
         dim3 grid(grid_for(p.g.N, 256), p.n_ent);
         if (p.f32) {
             const size_t l32 = lds / 2;
-            if (s == 0)
+            if (s == 0 && !in32)
                 TTN_LAUNCH("k_mode_stage_f32", p.sflops[s], p.sbytes[s], (k_mode_stage<double2, float2>), grid,
                            dim3(256), l32, st, p, s, in, ldn);
             else
                 TTN_LAUNCH("k_mode_stage_f32", p.sflops[s], p.sbytes[s], (k_mode_stage<float2, float2>), grid,
-                           dim3(256), l32, st, p, s, (const float2 *)nullptr, ldn);
+                           dim3(256), l32, st, p, s, s == 0 ? in32 : (const float2 *)nullptr, ldn);
         } else {
             TTN_LAUNCH("k_mode_stage", p.sflops[s], p.sbytes[s], (k_mode_stage<double2, double2>), grid, dim3(256),
                        lds, st, p, s, in, ldn);
