@@ -43,9 +43,11 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # cores (their algorithmic flops count one complex product as 8 flops, while
 # the hardware issues three bf16 products for it), the FP32 stage, the FP32
 # environment contraction and the FP32 pair-operator GEMM on the FP32 matrix
-# cores (whose dense peak equals the FP32
+# cores (whose dense peak equals the FP32 vector peak), the FP64 stage and the
+# QR's Gram matrix on the FP64 matrix cores (dense peak equal to the FP64
 # vector peak).  First match wins.
-KERNEL_PEAK = [("k_mode_mfma32", "mfma", PEAK_FP32_TFLOPS), ("k_contract_mfma", "mfma", PEAK_FP32_TFLOPS),
+KERNEL_PEAK = [("k_mode_mfma32", "mfma", PEAK_FP32_TFLOPS), ("k_mode_mfma64", "mfma", PEAK_FP64_TFLOPS),
+               ("k_contract_mfma", "mfma", PEAK_FP32_TFLOPS), ("k_cqr_gram_mfma", "mfma", PEAK_FP64_TFLOPS),
                ("k_mode_mfma", "mfma", PEAK_BF16_TFLOPS),
                ("k_pair_gemm_bf", "mfma", PEAK_BF16_TFLOPS), ("k_pair_gemm", "mfma", PEAK_FP32_TFLOPS),
                ("_f32", "alu", PEAK_FP32_TFLOPS)]
@@ -142,11 +144,12 @@ def profiled_sweep(T, g, p, steps=1):
 
 def stage_rate(stats, precision):
     """Rate of the H_eff / environment stage kernels of a profiled sweep."""
-    names = {0: ("k_mode_tile",), 1: ("k_pair_gemm", "k_mode_mfma32", "k_mode_tile"),
+    names = {0: ("k_mode_mfma64", "k_mode_tile"), 1: ("k_pair_gemm", "k_mode_mfma32", "k_mode_tile"),
              2: ("k_pair_gemm_bf", "k_mode_mfma")}[precision]
     name = "+".join(names)
-    # BF16x3: the bf16 stage only (not its FP32 counterpart, whose name shares the prefix)
-    rows = [r for r in stats if r["name"].startswith(names) and not (precision == 2 and "mfma32" in r["name"])]
+    # BF16x3: the bf16 stage only (not the FP32 / FP64 ones, whose names share the prefix)
+    rows = [r for r in stats if r["name"].startswith(names)
+            and not (precision == 2 and ("mfma32" in r["name"] or "mfma64" in r["name"]))]
     ms = sum(r["total_ms"] for r in rows)
     fl = sum(r["flops"] for r in rows)
     if ms <= 0:

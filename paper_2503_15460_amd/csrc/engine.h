@@ -102,6 +102,9 @@ private:
     // FP32 mode: dense stages with factors of 24..64 on the FP32 matrix cores
     // (TTN_MODE_MFMA32=0 in the environment: the vector-ALU tiled kernel)
     bool mode_mfma32 = true;
+    // FP64 mode: dense stages with factors of 16..64 on the FP64 matrix cores
+    // (TTN_MODE_MFMA64=0: the vector-ALU tiled kernel)
+    bool mode_mfma64 = true;
     hipStream_t own_stream = nullptr;
     struct GraphEntry {
         std::vector<int64_t> key;  // Krylov dimension hints and dt of the captured step

@@ -50,6 +50,7 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
     if (const char *e = getenv("TTN_PAIR_OPS")) pair_ops = atoi(e) != 0;
     if (const char *e = getenv("TTN_KRYLOV_CGS2")) krylov_cgs2 = atoi(e) != 0;
     if (const char *e = getenv("TTN_MODE_MFMA32")) mode_mfma32 = atoi(e) != 0;
+    if (const char *e = getenv("TTN_MODE_MFMA64")) mode_mfma64 = atoi(e) != 0;
     if (const char *e = getenv("TTN_PAIR_SPLIT")) pair_split = atoi(e) != 0;
     if (const char *e = getenv("TTN_PAIR_SLOTS")) pair_slots = std::max(0, atoi(e));
     if (const char *e = getenv("TTN_PAIR_MIN_N")) pair_min_n = std::max<int64_t>(1, atoll(e));
@@ -264,6 +265,7 @@ ProgView Engine::view(const Prog &p) const {
     v.bf16x3 = opt.precision == TTN_BF16X3 ? 1 : 0;
     v.mprep = mprep;
     v.mfma32 = mode_mfma32 ? 1 : 0;
+    v.mfma64 = mode_mfma64 ? 1 : 0;
     for (int f = 0; f < MAXF; ++f) {
         v.sflops[f] = p.sflops[f];
         // FP32 temporaries: stage 0 reads FP64 and writes FP32, later stages FP32 both ways

@@ -77,6 +77,7 @@ struct ProgView {
     int bf16x3;               // 1 (with f32): dense stages with factors of 24..64 on BF16x3 MFMA
     unsigned short *mprep;    // bf16 hi/lo realified factors, n_ent * 2 * 128 * 128 (BF16x3 mode)
     int mfma32;               // 1 (FP32 mode): dense stages with factors of 24..64 on the FP32 matrix cores
+    int mfma64;               // 1 (FP64 mode): dense stages with factors of 16..64 on the FP64 matrix cores
     double2 *tmp;             // 2 * n_ent * N (float2 elements in the FP32 mode)
     double2 *gsum;            // n_groups * N (float2 elements in the FP32 mode)
     int64_t in_stride;        // distance of the input slices read by entries with src > 0

@@ -616,6 +616,138 @@ __global__ void __launch_bounds__(256) k_mode_mfma32(ProgView p, int stage, cons
     }
 }
 
+// ------------------------------------------------------------ FP64 MFMA stage
+// The realified mode product of the FP64 mode on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64): A operand rows 2i, 2i+1 hold (Re, -Im), (Im, Re)
+// of M[i][j] at columns 2j, 2j+1; the B operand holds (Re, Im) of X[j] at rows
+// 2j, 2j+1.  In group g of eight realified K, lane K index k takes the pair
+// 8g + 2k, 8g + 2k + 1 on two consecutive K steps, so that one 16-byte LDS
+// read (a complex value) feeds both.  Work-group: 4 waves x 16 columns, every
+// wave all RT row tiles of 16 realified rows; chunks of 16 complex j pass
+// through LDS with the next chunk's global loads in flight.  Register r of a
+// lane holds row 4r + lane / 16 of column lane % 16 of a 16 x 16 tile.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int M64_CW = 64;              // columns per work-group
+constexpr int M64_KC = 32;              // realified K per chunk
+constexpr int M64_LD = M64_KC + 2;      // doubles per LDS row (16-byte aligned rows)
+
+template <int RT>
+__global__ void __launch_bounds__(256) k_mode_mfma64(ProgView p, int stage, const double2 *__restrict__ in) {
+    constexpr int RD = 16 * RT;
+    __shared__ __attribute__((aligned(16))) double As[RD * M64_LD];
+    __shared__ __attribute__((aligned(16))) double Bs[M64_CW * M64_LD];
+    const int e = blockIdx.y;
+    const DevEntry *E = p.ent + e;
+    if (E->nf <= stage) return;
+    const int s = E->slot[stage];
+    const int n = p.g.dims[s];
+    const uint32_t R = (uint32_t)p.g.R[s];
+    const uint32_t N = (uint32_t)p.g.N;
+    const uint32_t ncol = N / (uint32_t)n;
+    const uint32_t c0 = blockIdx.x * (uint32_t)M64_CW;
+    if (c0 >= ncol) return;
+    const double2 *__restrict__ M = E->M[stage];
+    double2 *tmp = p.tmp;
+    const double2 *__restrict__ src =
+        stage == 0 ? in + (int64_t)E->src * p.in_stride : tmp + (2 * (int64_t)e + ((stage - 1) & 1)) * N;
+    double2 *__restrict__ dst = tmp + (2 * (int64_t)e + (stage & 1)) * N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nR = (uint32_t)n * R;
+    f64x4 acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int kmax = min(RD, 2 * n);
+    constexpr int JC = M64_KC / 2;                          // complex j per chunk
+    constexpr int MQ = ((RD / 2) * JC + 255) / 256;         // complex M values per thread
+    constexpr int XQ = M64_CW * JC / 256;                   // complex X values per thread
+    double2 mv[MQ], xv[XQ];
+    auto xmap = [&](int q, int &cc, int &jj) {
+        if (R == 1) {  // columns are rows of a row-major (ncol, n) matrix: j fastest
+            jj = q % JC;
+            cc = q / JC;
+        } else {
+            cc = q % M64_CW;
+            jj = q / M64_CW;
+        }
+    };
+    auto load_chunk = [&](int k0) {
+        const int j0 = k0 / 2;
+#pragma unroll
+        for (int u = 0; u < MQ; ++u) {
+            const int q = tid + 256 * u;
+            const int i = q / JC, jj = q - i * JC;
+            const int j = j0 + jj;
+            mv[u] = (q < (RD / 2) * JC && i < n && j < n) ? M[(size_t)i * n + j] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < XQ; ++u) {
+            int cc, jj;
+            xmap(tid + 256 * u, cc, jj);
+            const int j = j0 + jj;
+            const uint32_t c = c0 + cc;
+            double2 v = make_double2(0.0, 0.0);
+            if (c < ncol && j < n) {
+                const uint32_t l = c / R, r = c - l * R;
+                v = src[(size_t)l * nR + (size_t)j * R + r];
+            }
+            xv[u] = v;
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int u = 0; u < MQ; ++u) {
+            const int q = tid + 256 * u;
+            if (q >= (RD / 2) * JC) continue;
+            const int i = q / JC, jj = q - i * JC;
+            *reinterpret_cast<double2 *>(As + (2 * i) * M64_LD + 2 * jj) = make_double2(mv[u].x, -mv[u].y);
+            *reinterpret_cast<double2 *>(As + (2 * i + 1) * M64_LD + 2 * jj) = make_double2(mv[u].y, mv[u].x);
+        }
+#pragma unroll
+        for (int u = 0; u < XQ; ++u) {
+            int cc, jj;
+            xmap(tid + 256 * u, cc, jj);
+            *reinterpret_cast<double2 *>(Bs + cc * M64_LD + 2 * jj) = xv[u];
+        }
+    };
+    load_chunk(0);
+    store_chunk();
+    __syncthreads();
+    const int l16 = lane & 15, kq = lane >> 4;
+    const int col = wave * 16 + l16;
+    for (int k0 = 0; k0 < kmax; k0 += M64_KC) {
+        const bool more = k0 + M64_KC < kmax;
+        if (more) load_chunk(k0 + M64_KC);
+#pragma unroll
+        for (int g = 0; g < M64_KC / 8; ++g) {
+            const double2 b = *reinterpret_cast<const double2 *>(Bs + col * M64_LD + 8 * g + 2 * kq);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const double2 a = *reinterpret_cast<const double2 *>(As + (t * 16 + l16) * M64_LD + 8 * g + 2 * kq);
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc[t], 0, 0, 0);
+            }
+        }
+        if (more) {
+            __syncthreads();
+            store_chunk();
+            __syncthreads();
+        }
+    }
+    // realified row 4r + kq of tile t: complex row (16 t + 4 r + kq) / 2, part kq % 2
+    const uint32_t c = c0 + col;
+    if (c < ncol) {
+        const uint32_t l = c / R, r = c - l * R;
+        double *yp = reinterpret_cast<double *>(dst + (size_t)l * nR + r);
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int i = (16 * t + 4 * rr + kq) >> 1;
+                if (i < n) yp[2 * (size_t)i * R + (kq & 1)] = acc[t][rr];
+            }
+    }
+}
+
 // ------------------------------------------------------------ pair-operator form
 // W_k[q][kappa] = sum_e c_e F_e[a][a'] P_e[b][b'] for q = (a, b), kappa = (a', b')
 // (a null factor is the identity), summed in FP64 and stored row-major,
@@ -2277,7 +2409,6 @@ __global__ void __launch_bounds__(CQR_THREADS) k_cqr_gram(const double2 *A, uint
 // Im G[i][j]).  RT x CT output tiles of 16 x 16 (RT = ceil(n / 16), CT =
 // ceil(2n / 16)); wave w owns the contiguous run of tiles
 // [w TPW, (w + 1) TPW) over the whole K of every tile of rows.
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <bool APPLY, int RT, int CT>
 __global__ void __launch_bounds__(CQR_THREADS) k_cqr_gram_mfma(const double2 *A, uint32_t L, int n, uint32_t R,
                                                                uint32_t rows_per, QRWork q) {
@@ -3978,12 +4109,29 @@ static void launch_mode_mfma32(const ProgView &p, int s, const double2 *in, cons
 #undef TTN_M32_CASE
 }
 
-// dense stages with factors of 24..64 go to the matrix cores: BF16x3 in the
-// BF16x3 mode, FP32 in the FP32 mode (when enabled)
+static void launch_mode_mfma64(const ProgView &p, int s, const double2 *in, hipStream_t st) {
+    const uint32_t maxcol = (uint32_t)(p.g.N / p.snmin[s]);
+    dim3 grid((maxcol + M64_CW - 1) / M64_CW, p.n_ent);
+    const int need = (2 * p.snmax[s] + 15) / 16;
+    const double2 *x = s == 0 ? in : nullptr;
+#define TTN_M64(RTV) \
+    TTN_LAUNCH("k_mode_mfma64", p.sflops[s], p.sbytes[s], (k_mode_mfma64<RTV>), grid, dim3(256), 0, st, p, s, x)
+    if (need <= 2) TTN_M64(2);
+    else if (need <= 3) TTN_M64(3);
+    else if (need <= 4) TTN_M64(4);
+    else if (need <= 6) TTN_M64(6);
+    else TTN_M64(8);
+#undef TTN_M64
+}
+
+// dense stages go to the matrix cores: factors of 24..64 in BF16x3 in the
+// BF16x3 mode and in FP32 in the FP32 mode, of 16..64 in FP64 in the FP64 mode
+// (when enabled)
 static int stage_on_mfma(const ProgView &p, int s) {
-    if (!p.stile[s] || p.snmin[s] < 24 || p.snmax[s] > 64) return 0;
-    if (p.bf16x3 && p.mprep) return 1;
-    if (p.f32 && !p.bf16x3 && p.mfma32) return 2;
+    if (!p.stile[s] || p.snmax[s] > 64) return 0;
+    if (p.bf16x3 && p.mprep) return p.snmin[s] >= 24 ? 1 : 0;
+    if (p.f32 && !p.bf16x3 && p.mfma32) return p.snmin[s] >= 24 ? 2 : 0;
+    if (!p.f32 && p.mfma64) return p.snmin[s] >= 16 ? 3 : 0;
     return 0;
 }
 
@@ -3991,6 +4139,7 @@ static void launch_mode_tile(const ProgView &p, int s, const double2 *in, const 
     switch (stage_on_mfma(p, s)) {
     case 1: launch_mode_mfma(p, s, in, in32, st); return;
     case 2: launch_mode_mfma32(p, s, in, in32, st); return;
+    case 3: launch_mode_mfma64(p, s, in, st); return;
     default: break;
     }
     if (p.f32) {

@@ -48,6 +48,9 @@ def test_roofline_compute_bound_classes():
     assert r["bound"] == "mfma" and r["peak"] == bench.PEAK_FP32_TFLOPS
     r = bench.roofline([_row("k_contract_mfma", 10, 1.0, 1e11, 1e7)], 1, "x")
     assert r["bound"] == "mfma" and r["peak"] == bench.PEAK_FP32_TFLOPS
+    # the FP64 matrix-core stage against the FP64 peak
+    r = bench.roofline([_row("k_mode_mfma64", 10, 1.0, 1e11, 1e7)], 1, "x")
+    assert r["bound"] == "mfma" and r["peak"] == bench.PEAK_FP64_TFLOPS
     # the pair-operator GEMMs: FP32 matrix cores, and bf16 matrix cores in the BF16x3 form
     r = bench.roofline([_row("k_pair_gemm", 10, 1.0, 1e11, 1e7)], 1, "x")
     assert r["bound"] == "mfma" and r["peak"] == bench.PEAK_FP32_TFLOPS

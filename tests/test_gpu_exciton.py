@@ -232,6 +232,43 @@ def test_fp32_matrix_core_stages_on_the_c3_shaped_tree(T, monkeypatch):
     assert diff < 1e-6
 
 
+def test_fp64_matrix_core_stages_on_the_c3_shaped_tree(T, monkeypatch):
+    """FP64 mode: the dense stages with factors of 16..64 on the FP64 matrix
+    cores (k_mode_mfma64) against the same stages on the vector ALUs
+    (k_mode_tile, TTN_MODE_MFMA64=0): three sweeps from the seeded full-rank
+    state agree to 1e-12 (FP64 accumulation in a different order), both stay
+    within 1e-10 of the stored oracle run, and so do sampled entries of every
+    node tensor."""
+    import golden_refs as G
+    p = G.maker.c3_shaped()
+    bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
+    st = random_isometric_state(p.parent, p.local_dim, bonds, seed=31)
+    rec = G.reference("c3_shaped", p, bonds, st)
+    ref = G.observables(rec)
+    runs = {}
+    for form, flag in (("mfma", "1"), ("valu", "0")):
+        monkeypatch.setenv("TTN_MODE_MFMA64", flag)
+        g = T.TTN.from_problem(p, precision=T.TTN_FP64)
+        monkeypatch.delenv("TTN_MODE_MFMA64")
+        g.set_state(st)
+        T.profile_begin()
+        got = []
+        for _ in range(3):
+            g.step(p.dt)
+            got.append(_obs10(g, p))
+        names = {r["name"] for r in T.profile_end()}
+        runs[form] = np.array(got)
+        assert ("k_mode_mfma64" in names) == (form == "mfma")
+        terr = G.tensor_sample_error(rec, g.get_state())
+        err = np.abs(runs[form] - ref).max()
+        print(f"FP64 stages on {form}: max error vs oracle {err:.2e}, node tensors (sampled) {terr:.2e}")
+        assert err < 1e-10 and terr < 1e-10
+        g.close()
+    diff = np.abs(runs["mfma"] - runs["valu"]).max()
+    print(f"matrix-core vs vector-ALU stages: {diff:.2e}")
+    assert diff < 1e-12
+
+
 def test_exciton10x120_full_size_properties(T):
     """The full exciton workload (10 states, 120 modes, bonds 8/32/48/64,
     1500 SOP terms: nodes of 7.08M elements, the sizes bench.py times), one
