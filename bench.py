@@ -54,7 +54,7 @@ KERNEL_PEAK = [("k_mode_mfma32", "mfma", PEAK_FP32_TFLOPS), ("k_mode_mfma64", "m
 
 
 # second kernels that finish the work of a launch of the first
-COMPANION = {"k_pair_gemm": "k_pair_fixup"}
+COMPANION = {"k_pair_gemm": "k_pair_fixup", "k_pair_gemm_bf": "k_pair_fixup"}
 
 
 def kernel_peak(name: str):

@@ -94,9 +94,11 @@ private:
     bool krylov_cgs2 = false;
     int64_t pair_min_n = 1 << 18;  // node size from which the pair form is considered (TTN_PAIR_MIN_N)
     float2 *pair_x32 = nullptr;    // scratch (FP32 modes): complex FP32 copy of a pair-form or first-stage input
-    // FP32 pair GEMM shared evenly by the resident work-groups, cut tiles
-    // summed from pair_ws (TTN_PAIR_SPLIT=0: one work-group per tile)
-    bool pair_split = true;
+    // pair GEMMs shared evenly by the resident work-groups, cut tiles summed
+    // from pair_ws: 1 (default) the FP32 form, 2 (TTN_PAIR_SPLIT=2) also the
+    // BF16x3 form (which the hardware's own dispatch of one work-group per
+    // tile balances as well: not bound by its matrix cores), 0 neither
+    int pair_split = 1;
     int pair_slots = 0;  // work-groups sharing it (0: the device's capacity; TTN_PAIR_SLOTS, rounded down to 8s)
     float *pair_ws = nullptr;
     // FP32 mode: dense stages with factors of 24..64 on the FP32 matrix cores

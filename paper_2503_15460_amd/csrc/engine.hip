@@ -51,7 +51,7 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
     if (const char *e = getenv("TTN_KRYLOV_CGS2")) krylov_cgs2 = atoi(e) != 0;
     if (const char *e = getenv("TTN_MODE_MFMA32")) mode_mfma32 = atoi(e) != 0;
     if (const char *e = getenv("TTN_MODE_MFMA64")) mode_mfma64 = atoi(e) != 0;
-    if (const char *e = getenv("TTN_PAIR_SPLIT")) pair_split = atoi(e) != 0;
+    if (const char *e = getenv("TTN_PAIR_SPLIT")) pair_split = std::max(0, std::min(2, atoi(e)));
     if (const char *e = getenv("TTN_PAIR_SLOTS")) pair_slots = std::max(0, atoi(e));
     if (const char *e = getenv("TTN_PAIR_MIN_N")) pair_min_n = std::max<int64_t>(1, atoll(e));
     if (graph_mode && !st) {  // the null stream cannot be captured: a stream of the handle's own
@@ -705,13 +705,14 @@ void Engine::set_sop(const SopInput &s) {
     pair_x32 = nullptr;
     pair_ws = nullptr;
     if (opt.precision == TTN_FP32 || opt.precision == TTN_BF16X3) need(&pair_x32, sizeof(float2) * maxN);
-    // cut tiles of the shared pair-GEMM schedule (FP32 form)
-    if (pair_split)
+    // cut tiles of the shared pair-GEMM schedule (FP32 form; BF16x3 form with TTN_PAIR_SPLIT=2)
+    if (pair_split > 0) {
+        size_t ws = 0;
         for (int z = 0; z < n; ++z)
-            if (!heffP[z].pair.empty() && !heffP[z].pair[0].Wb) {
-                need(&pair_ws, pair_gemm_ws_bytes(pair_slots));
-                break;
-            }
+            if (!heffP[z].pair.empty() && (!heffP[z].pair[0].Wb || pair_split > 1))
+                ws = std::max(ws, pair_gemm_ws_bytes(pair_slots, heffP[z].pair[0].Wb ? 1 : 0));
+        if (ws) need(&pair_ws, ws);
+    }
     // Cholesky route of the QR: Gram partials, small matrices, first-pass factor
     need(&qrw.cq_part, sizeof(double2) * CQR_BLOCKS_MAX * 64 * 64);
     need(&qrw.cq_G, sizeof(double2) * 64 * 64);
@@ -884,7 +885,8 @@ void Engine::launch_apply(const Prog &p, const ProgView &v, const double2 *in, d
             unsigned *xh = reinterpret_cast<unsigned *>(pair_x32), *xl = xh + p.g.N;
             launch_to_bf16x2(in, xh, xl, p.g.N, st);
             for (size_t i = 0; i < p.pair.size(); ++i)
-                launch_pair_gemm_bf(p.pair[i], xh, xl, out, i > 0 ? 1 : 0, p.pair_flops[i], st);
+                launch_pair_gemm_bf(p.pair[i], xh, xl, out, i > 0 ? 1 : 0, p.pair_flops[i],
+                                    pair_split > 1 ? pair_ws : nullptr, pair_slots, st);
         } else {
             launch_to_f32(in, pair_x32, p.g.N, st);
             for (size_t i = 0; i < p.pair.size(); ++i)

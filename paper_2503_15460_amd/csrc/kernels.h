@@ -116,7 +116,7 @@ void launch_pair_build(const PairPass &pp, hipStream_t st);
 // null: one work-group per tile.
 void launch_pair_gemm(const PairPass &pp, const float2 *in, double2 *out, int accumulate, double flops, float *ws,
                       int ws_slots, hipStream_t st);
-size_t pair_gemm_ws_bytes(int ws_slots);  // workspace of the shared schedule on the current device
+size_t pair_gemm_ws_bytes(int ws_slots, int bf16x3);  // workspace of the shared schedule on the current device
 // rows and columns >= keep of the n x n matrix C set to zero
 void launch_zero_tail(double2 *C, int n, int keep, hipStream_t st);
 // y = x rounded to complex FP32 (n elements)
@@ -125,8 +125,10 @@ void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st);
 // into its realified bf16 hi / lo parts; the GEMM on v_mfma_f32_32x32x16_bf16
 void launch_to_bf16x2(const double2 *x, unsigned *xh, unsigned *xl, int64_t n, hipStream_t st);
 void launch_pair_split(const PairPass &pp, hipStream_t st);
+// (ws, ws_slots: the shared schedule as for launch_pair_gemm, workspace of
+// pair_gemm_ws_bytes(ws_slots, 1) bytes)
 void launch_pair_gemm_bf(const PairPass &pp, const unsigned *xh, const unsigned *xl, double2 *out, int accumulate,
-                         double flops, hipStream_t st);
+                         double flops, float *ws, int ws_slots, hipStream_t st);
 
 // Statistics written by one Krylov solve.
 struct SolveStat {

@@ -1067,6 +1067,23 @@ __device__ __forceinline__ f32x4v *pair_ws_part(float *ws, unsigned cut, int p) 
     return reinterpret_cast<f32x4v *>(ws) + ((size_t)(2 * cut + p) * 8 * WN) * 256;
 }
 
+// a cut tile's part: the cut at this share's start (part 1) or at its end (part 0)
+template <int WN>
+__device__ __forceinline__ void pair_cut_store(float *ws, int slots, unsigned x, unsigned pos, int kb,
+                                               const f32x16 (&acc)[2][WN]) {
+    const unsigned cut = x * ((unsigned)slots / 8) + (kb == 0 ? pos + 1 : pos);
+    f32x4v *w = pair_ws_part<WN>(ws, cut, kb == 0 ? 0 : 1);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const f32x4v v = {acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]};
+                w[(size_t)((i * WN + j) * 4 + g) * 256 + threadIdx.x] = v;
+            }
+}
+
 template <int WN>
 __global__ void __launch_bounds__(256, WN == 2 ? 2 : 1) k_pair_gemm(PairPass pp, const float2 *__restrict__ X, double2 *__restrict__ Y,
                                                    int accumulate, float *ws, int slots, PairSched sc) {
@@ -1085,19 +1102,8 @@ __global__ void __launch_bounds__(256, WN == 2 ? 2 : 1) k_pair_gemm(PairPass pp,
         pair_gemm_tile<WN>(pp, X, rt, ct, kb, ke, pg_lds, acc);
         if (kb == 0 && ke == (int)sc.kc) {
             pair_gemm_store<WN>(pp, Y, accumulate, rt, ct, acc);
-        } else {  // a cut tile: the cut at this share's start (part 1) or at its end (part 0)
-            const unsigned cut = x * ((unsigned)slots / 8) + (kb == 0 ? pos + 1 : pos);
-            f32x4v *w = pair_ws_part<WN>(ws, cut, kb == 0 ? 0 : 1);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < WN; ++j)
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const f32x4v v = {acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2],
-                                          acc[i][j][4 * g + 3]};
-                        w[(size_t)((i * WN + j) * 4 + g) * 256 + threadIdx.x] = v;
-                    }
+        } else {
+            pair_cut_store<WN>(ws, slots, x, pos, kb, acc);
         }
         u += (uint64_t)(ke - kb);
     }
@@ -1181,29 +1187,15 @@ __global__ void k_pair_split(PairPass pp) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_pair_gemm_bf(PairPass pp, const unsigned *__restrict__ Xh,
-                                                      const unsigned *__restrict__ Xl, double2 *__restrict__ Y,
-                                                      int accumulate) {
+// Products of one tile of the BF16x3 pair GEMM over the K chunks [kb, ke) into acc
+__device__ __forceinline__ void pair_gemm_bf_tile(const PairPass &pp, const unsigned *__restrict__ Xh,
+                                                  const unsigned *__restrict__ Xl, unsigned rt, unsigned ct, int kb,
+                                                  int ke, unsigned short *pgb_lds, f32x16 (&acc)[2][2]) {
     constexpr int BN = 128;  // realified columns per work-group (2 waves x 2 tiles of 32)
     const int nk = pp.nk, np = pp.np;
     const int Q = nk * np;
     const int64_t Mid = pp.Mid, Rk = Mid * np;
     const int64_t M = pp.L * Mid;
-    const unsigned nct = (unsigned)((2 * Q + BN - 1) / BN);
-    const unsigned nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
-    const unsigned ntile = nct * nrt;
-    unsigned rt, ct;
-    {
-        const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
-        const unsigned q8 = ntile / 8, r8 = ntile % 8;
-        const unsigned t = x * q8 + min(x, r8) + pos;
-        const unsigned gsz = PG_GR * nct;
-        const unsigned g = t / gsz, w = t - g * gsz;
-        const unsigned rows_g = min((unsigned)PG_GR, nrt - g * PG_GR);
-        rt = g * PG_GR + w % rows_g;
-        ct = w / rows_g;
-    }
-    extern __shared__ __attribute__((aligned(16))) unsigned short pgb_lds[];
     unsigned short *Ah = pgb_lds, *Al = Ah + PG_BM * PGB_LD;
     unsigned short *Bh = Al + PG_BM * PGB_LD, *Bl = Bh + BN * PGB_LD;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1270,7 +1262,6 @@ __global__ void __launch_bounds__(256) k_pair_gemm_bf(PairPass pp, const unsigne
             dbl[u] = bl[u];
         }
     };
-    f32x16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -1279,12 +1270,13 @@ __global__ void __launch_bounds__(256) k_pair_gemm_bf(PairPass pp, const unsigne
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const int g8 = (lane >> 5) * 8, l32 = lane & 31;
-    load(0);
+    load(kb * PGB_KS);
+    __syncthreads();  // the previous tile's last products have read the buffers
     store();
     __syncthreads();
-    for (int k0 = 0; k0 < Q; k0 += PGB_KS) {
-        const bool more = k0 + PGB_KS < Q;
-        if (more) load(k0 + PGB_KS);
+    for (int kc = kb; kc < ke; ++kc) {
+        const bool more = kc + 1 < ke;
+        if (more) load((kc + 1) * PGB_KS);
 #pragma unroll
         for (int t = 0; t < 2 * PGB_KS; t += 16) {
             bf8v xh[2], xl[2], yh[2], yl[2];
@@ -1313,33 +1305,27 @@ __global__ void __launch_bounds__(256) k_pair_gemm_bf(PairPass pp, const unsigne
             __syncthreads();
         }
     }
-    double *Yd = reinterpret_cast<double *>(Y);
-    const int part = lane >> 5;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int cr = c0 + wc + 32 * j + l32;  // realified column
-        const int q = cr >> 1, ri = cr & 1;
-        if (q >= Q) continue;
-        const int a = q / np, b = q - a * np;
-        const int64_t cofs = (int64_t)a * Rk + b;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            size_t idx[16];
-            bool ok[16];
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int64_t o = o0 + wr + 32 * i + 8 * (v >> 2) + 4 * part + (v & 3);
-                ok[v] = o < M;
-                const int64_t l = o / Mid, m = o - l * Mid;
-                idx[v] = 2 * (size_t)(l * nk * Rk + m * np + cofs) + ri;
-            }
-            double old[16];
-#pragma unroll
-            for (int v = 0; v < 16; ++v) old[v] = (accumulate && ok[v]) ? Yd[idx[v]] : 0.0;
-#pragma unroll
-            for (int v = 0; v < 16; ++v)
-                if (ok[v]) Yd[idx[v]] = old[v] + (double)acc[i][j][v];
-        }
+}
+
+__global__ void __launch_bounds__(256, 2) k_pair_gemm_bf(PairPass pp, const unsigned *__restrict__ Xh,
+                                                         const unsigned *__restrict__ Xl, double2 *__restrict__ Y,
+                                                         int accumulate, float *ws, int slots, PairSched sc) {
+    const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
+    unsigned t0, S;
+    uint64_t ub, ue;
+    if (!pair_share(sc, slots, x, pos, t0, ub, ue, S)) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned short pgb_lds[];
+    f32x16 acc[2][2];
+    for (uint64_t u = ub; u < ue;) {
+        const unsigned tl = (unsigned)(u / sc.kc);
+        const int kb = (int)(u - (uint64_t)tl * sc.kc);
+        const int ke = (int)min<uint64_t>(sc.kc, kb + (ue - u));
+        unsigned rt, ct;
+        pair_tile_rc(t0 + tl, sc.nrt, sc.nct, rt, ct);
+        pair_gemm_bf_tile(pp, Xh, Xl, rt, ct, kb, ke, pgb_lds, acc);
+        if (kb == 0 && ke == (int)sc.kc) pair_gemm_store<2>(pp, Y, accumulate, rt, ct, acc);
+        else pair_cut_store<2>(ws, slots, x, pos, kb, acc);
+        u += (uint64_t)(ke - kb);
     }
 }
 
@@ -4418,16 +4404,33 @@ void launch_pair_split(const PairPass &pp, hipStream_t st) {
     TTN_LAUNCH("k_pair_split", 0.0, 24.0 * q2, k_pair_split, dim3(grid_for(q2, 256)), dim3(256), 0, st, pp);
 }
 
+static int resident_slots(const void *kern, size_t lds);
+static size_t pair_gemm_bf_lds() { return sizeof(unsigned short) * (size_t)(2 * PG_BM + 2 * 128) * PGB_LD; }
+
 void launch_pair_gemm_bf(const PairPass &pp, const unsigned *xh, const unsigned *xl, double2 *out, int accumulate,
-                         double flops, hipStream_t st) {
+                         double flops, float *ws, int ws_slots, hipStream_t st) {
     const int Q = pp.nk * pp.np;
     const int64_t M = pp.L * pp.Mid;
     const double N = (double)M * Q;
-    const unsigned nct = (unsigned)((2 * Q + 127) / 128), nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
-    const size_t lds = sizeof(unsigned short) * (size_t)(2 * PG_BM + 2 * 128) * PGB_LD;
+    PairSched sc;
+    sc.nct = (unsigned)((2 * Q + 127) / 128);
+    sc.nrt = (unsigned)((M + PG_BM - 1) / PG_BM);
+    sc.ntile = sc.nrt * sc.nct;
+    sc.kc = (unsigned)((Q + PGB_KS - 1) / PGB_KS);
+    const size_t lds = pair_gemm_bf_lds();
     set_lds_limit((const void *)k_pair_gemm_bf, lds);
+    const unsigned per_xcd = (sc.ntile + 7) / 8;
+    const int slots = ws ? (ws_slots > 0 ? std::max(8, ws_slots / 8 * 8)
+                                         : resident_slots((const void *)k_pair_gemm_bf, lds))
+                         : (int)(8 * per_xcd);
+    const unsigned grid = 8 * std::min<unsigned>((unsigned)slots / 8, per_xcd);
     TTN_LAUNCH("k_pair_gemm_bf", flops, 8.0 * N + 16.0 * N * (accumulate ? 2 : 1) + 16.0 * Q * Q, k_pair_gemm_bf,
-               dim3(nct * nrt), dim3(256), lds, st, pp, xh, xl, out, accumulate);
+               dim3(grid), dim3(256), lds, st, pp, xh, xl, out, accumulate, ws, slots, sc);
+    if ((unsigned)slots / 8 < per_xcd) {  // some tiles are cut
+        const double fb = (double)slots * 256 * 64 * 4 * 2 + 16.0 * (double)slots * PG_BM * 64;
+        TTN_LAUNCH("k_pair_fixup", 0.0, fb, k_pair_fixup<2>, dim3(slots), dim3(256), 0, st, pp, out, accumulate,
+                   (const float *)ws, slots, sc);
+    }
 }
 
 void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st) {
@@ -4436,33 +4439,41 @@ void launch_to_f32(const double2 *x, float2 *y, int64_t n, hipStream_t st) {
 
 template <int WN> static size_t pair_gemm_lds() { return sizeof(float) * 2 * (PG_BM * PG_LDA + 64 * WN * PG_LDB); }
 
-// resident work-groups of k_pair_gemm<WN> on the current device (a multiple of
-// 8: the schedule deals whole rounds of the 8 XCDs), computed once per device
-template <int WN> static int pair_gemm_slots() {
+// resident work-groups of a kernel (256 threads, `lds` bytes of LDS) on the
+// current device, a multiple of 8 (the schedules deal whole rounds of the 8
+// XCDs), computed once per device and kernel
+static int resident_slots(const void *kern, size_t lds) {
     static std::mutex mu;
-    static std::map<int, int> cache;
+    static std::map<std::pair<int, const void *>, int> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");
     std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find(dev);
+    auto it = cache.find({dev, kern});
     if (it != cache.end()) return it->second;
-    set_lds_limit((const void *)k_pair_gemm<WN>, pair_gemm_lds<WN>());
+    set_lds_limit(kern, lds);
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_pair_gemm<WN>, 256,
-                                                     pair_gemm_lds<WN>()) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess)
         throw std::runtime_error("pair GEMM: device occupancy query failed");
     const int slots = std::max(8, (cus * std::max(1, per_cu)) / 8 * 8);
-    cache[dev] = slots;
+    cache[{dev, kern}] = slots;
     return slots;
+}
+template <int WN> static int pair_gemm_slots() {
+    return resident_slots((const void *)k_pair_gemm<WN>, pair_gemm_lds<WN>());
 }
 
 template <int WN> static int pair_slots_or(int slots) {
     return slots > 0 ? std::max(8, slots / 8 * 8) : pair_gemm_slots<WN>();
 }
 
-size_t pair_gemm_ws_bytes(int slots) {
+size_t pair_gemm_ws_bytes(int slots, int bf16x3) {
     // part 0 and part 1 of at most one cut per work-group slot, 32 WN floats per thread each
+    if (bf16x3) {
+        const int sl = slots > 0 ? std::max(8, slots / 8 * 8) : resident_slots((const void *)k_pair_gemm_bf,
+                                                                                pair_gemm_bf_lds());
+        return (size_t)sl * 2 * 256 * 32 * 2 * sizeof(float);
+    }
     return pair_gemm_wn_setting() == 4 ? (size_t)pair_slots_or<4>(slots) * 2 * 256 * 32 * 4 * sizeof(float)
                                        : (size_t)pair_slots_or<2>(slots) * 2 * 256 * 32 * 2 * sizeof(float);
 }

@@ -158,17 +158,20 @@ def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch, prec, dtol):
 def test_shared_pair_gemm_schedule_at_full_size(T, monkeypatch):
     """The exciton workload at full size (the configuration bench.py times),
     one sweep from a seeded full-rank state: the A nodes' pair GEMMs (864
-    tiles each) shared evenly by the resident work-groups, tiles cut between
-    two of them summed by k_pair_fixup, against one work-group per tile
-    (TTN_PAIR_SPLIT=0): populations and a(t) agree to 1e-6 (FP32 sums of the
-    cut tiles in two parts) and both stay within 1e-4 of the FP64 sweep (whose
-    kernels are pinned to the oracle on the smaller trees)."""
+    tiles each, FP32 and BF16x3 forms) shared evenly by the resident
+    work-groups (the FP32 default; TTN_PAIR_SPLIT=2 for BF16x3), tiles cut
+    between two of them summed by k_pair_fixup, against one work-group per tile
+    (TTN_PAIR_SPLIT=0, the BF16x3 default): populations and a(t) agree to
+    1e-6 (FP32) and 1e-5 (BF16x3) (FP32 sums of the cut tiles in two parts)
+    and all stay within 1e-4 of the FP64 sweep (whose kernels are pinned to
+    the oracle on the smaller trees)."""
     p = exciton_problem()
     bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
     st = random_isometric_state(p.parent, p.local_dim, bonds, seed=41)
     runs = {}
     for form, prec, env in (("fp64", T.TTN_FP64, {}), ("shared", T.TTN_FP32, {}),
-                            ("tiles", T.TTN_FP32, {"TTN_PAIR_SPLIT": "0"})):
+                            ("tiles", T.TTN_FP32, {"TTN_PAIR_SPLIT": "0"}), ("bf_shared", T.TTN_BF16X3, {"TTN_PAIR_SPLIT": "2"}),
+                            ("bf_tiles", T.TTN_BF16X3, {})):
         for k, v in env.items():
             monkeypatch.setenv(k, v)
         g = T.TTN.from_problem(p, precision=prec)
@@ -179,17 +182,18 @@ def test_shared_pair_gemm_schedule_at_full_size(T, monkeypatch):
         g.step(p.dt)
         names = {r["name"] for r in T.profile_end()}
         runs[form] = _obs10(g, p)
-        if prec == T.TTN_FP32:
-            assert "k_pair_gemm" in names
-            assert ("k_pair_fixup" in names) == (form == "shared")
+        if prec != T.TTN_FP64:
+            assert ("k_pair_gemm" if prec == T.TTN_FP32 else "k_pair_gemm_bf") in names
+            assert ("k_pair_fixup" in names) == form.endswith("shared")
         g.close()
-    for form in ("shared", "tiles"):
+    for form in ("shared", "tiles", "bf_shared", "bf_tiles"):
         err = np.abs(runs[form] - runs["fp64"]).max()
         print(f"pair GEMM, {form}: max difference from the FP64 sweep {err:.2e}")
         assert err < 1e-4
-    diff = np.abs(runs["shared"] - runs["tiles"]).max()
-    print(f"shared schedule vs one work-group per tile: {diff:.2e}")
-    assert diff < 1e-6
+    for a, b, tol in (("shared", "tiles", 1e-6), ("bf_shared", "bf_tiles", 1e-5)):
+        diff = np.abs(runs[a] - runs[b]).max()
+        print(f"{a} schedule vs one work-group per tile: {diff:.2e}")
+        assert diff < tol
 
 
 def test_fp32_matrix_core_stages_on_the_c3_shaped_tree(T, monkeypatch):
