@@ -894,7 +894,10 @@ __device__ __forceinline__ bool pair_share(const PairSched &sc, int slots, unsig
 // 64 WN realified columns).  LDS (dynamic): two buffers of the A tile
 // (128 rows of PG_LDA floats) and the B tile (64 WN columns of PG_LDB).
 // Products of one tile over the K chunks [kb, ke) into acc.
-template <int WN>
+// V4 (n_P a multiple of 4): each thread stages 4 consecutive kappa of 2 rows
+// and of QW / 64 operator rows with 16-byte loads and 16-byte LDS stores (one
+// a' per group of 4); otherwise 1 kappa of 8 rows and of QW / 16 operator rows.
+template <int WN, bool V4>
 __device__ __forceinline__ void pair_gemm_tile(const PairPass &pp, const float2 *__restrict__ X, unsigned rt,
                                                unsigned ct, int kb, int ke, float *pg_lds, f32x16 (&acc)[2][WN]) {
     constexpr int BN = 64 * WN;       // realified columns per work-group
@@ -908,12 +911,20 @@ __device__ __forceinline__ void pair_gemm_tile(const PairPass &pp, const float2 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t o0 = (int64_t)rt * PG_BM;
     const int q0 = (int)ct * QW;
-    // A: 128 rows x 16 kappa, 8 per thread (rows (tid >> 4) + 16 u, kappa offset tid & 15)
-    // B: QW q x 16 kappa from the q-major W, BU per thread (q offset (tid >> 4) + 16 u, kappa offset tid & 15)
-    int64_t rbase[8];
+    // scalar staging: A 128 rows x 16 kappa, 8 per thread (rows (tid >> 4) + 16 u,
+    // kappa offset tid & 15); B QW q x 16 kappa from the q-major W, BU per
+    // thread (q offset (tid >> 4) + 16 u, kappa offset tid & 15).  V4: rows
+    // (tid >> 2) + 64 u, kappa offset 4 (tid & 3).
+    constexpr int AR = V4 ? 2 : 8;                 // rows of A per thread
+    constexpr int RS = V4 ? 64 : 16;               // their stride
+    constexpr int BR = V4 ? QW / 64 : BU;          // operator rows per thread
+    constexpr int KV = V4 ? 4 : 1;                 // kappa per row and thread
+    const int rsub = V4 ? (tid >> 2) : (tid >> 4);
+    const int kk = V4 ? 4 * (tid & 3) : (tid & 15);
+    int64_t rbase[AR];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int64_t o = o0 + (tid >> 4) + 16 * u;
+    for (int u = 0; u < AR; ++u) {
+        const int64_t o = o0 + rsub + RS * u;
         if (o < M) {
             const int64_t l = o / Mid, m = o - l * Mid;
             rbase[u] = l * nk * Rk + m * np;
@@ -921,39 +932,79 @@ __device__ __forceinline__ void pair_gemm_tile(const PairPass &pp, const float2 
             rbase[u] = -1;
         }
     }
-    const int kk = tid & 15;
-    float2 av[8], bv[BU];
+    float2 av[AR][KV], bv[BR][KV];
     auto load = [&](int kappa0) {
         const int ka = kappa0 + kk;
-        const bool kok = ka < Q;
+        const bool kok = ka < Q;  // V4: Q and ka are multiples of 4, all 4 or none
         const int ap = ka / np, bp = ka - ap * np;
         const int64_t off = (int64_t)ap * Rk + bp;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            av[u] = (kok && rbase[u] >= 0) ? X[rbase[u] + off] : make_float2(0.0f, 0.0f);
+        for (int u = 0; u < AR; ++u) {
+            if (V4) {
+                float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+                if (kok && rbase[u] >= 0) {
+                    const float4 *src = reinterpret_cast<const float4 *>(X + rbase[u] + off);
+                    lo = src[0];
+                    hi = src[1];
+                }
+                av[u][0] = make_float2(lo.x, lo.y);
+                av[u][1 % KV] = make_float2(lo.z, lo.w);
+                av[u][2 % KV] = make_float2(hi.x, hi.y);
+                av[u][3 % KV] = make_float2(hi.z, hi.w);
+            } else {
+                av[u][0] = (kok && rbase[u] >= 0) ? X[rbase[u] + off] : make_float2(0.0f, 0.0f);
+            }
+        }
 #pragma unroll
-        for (int u = 0; u < BU; ++u) {
-            const int q = q0 + (tid >> 4) + 16 * u;
-            bv[u] = (kok && q < Q) ? pp.W[(size_t)q * Q + ka] : make_float2(0.0f, 0.0f);
+        for (int u = 0; u < BR; ++u) {
+            const int q = q0 + rsub + RS * u;
+            if (V4) {
+                float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+                if (kok && q < Q) {
+                    const float4 *src = reinterpret_cast<const float4 *>(pp.W + (size_t)q * Q + ka);
+                    lo = src[0];
+                    hi = src[1];
+                }
+                bv[u][0] = make_float2(lo.x, lo.y);
+                bv[u][1 % KV] = make_float2(lo.z, lo.w);
+                bv[u][2 % KV] = make_float2(hi.x, hi.y);
+                bv[u][3 % KV] = make_float2(hi.z, hi.w);
+            } else {
+                bv[u][0] = (kok && q < Q) ? pp.W[(size_t)q * Q + ka] : make_float2(0.0f, 0.0f);
+            }
         }
     };
     auto store = [&](float *buf) {
         float *As = buf, *Bs = buf + PG_BM * PG_LDA;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            float *a = As + ((tid >> 4) + 16 * u) * PG_LDA + kk;
-            a[0] = av[u].x;
-            a[PG_KS] = av[u].y;
+        for (int u = 0; u < AR; ++u) {
+            float *a = As + (rsub + RS * u) * PG_LDA + kk;
+            if (V4) {
+                *reinterpret_cast<f32x4v *>(a) = f32x4v{av[u][0].x, av[u][1 % KV].x, av[u][2 % KV].x, av[u][3 % KV].x};
+                *reinterpret_cast<f32x4v *>(a + PG_KS) =
+                    f32x4v{av[u][0].y, av[u][1 % KV].y, av[u][2 % KV].y, av[u][3 % KV].y};
+            } else {
+                a[0] = av[u][0].x;
+                a[PG_KS] = av[u][0].y;
+            }
         }
 #pragma unroll
-        for (int u = 0; u < BU; ++u) {
-            const int qq = (tid >> 4) + 16 * u;
+        for (int u = 0; u < BR; ++u) {
+            const int qq = rsub + RS * u;
             float *b0 = Bs + (2 * qq) * PG_LDB + kk;  // column 2q: (Re W, -Im W) for parts (0, 1)
             float *b1 = b0 + PG_LDB;                   // column 2q + 1: (Im W, Re W)
-            b0[0] = bv[u].x;
-            b0[PG_KS] = -bv[u].y;
-            b1[0] = bv[u].y;
-            b1[PG_KS] = bv[u].x;
+            if (V4) {
+                const float2 w0 = bv[u][0], w1 = bv[u][1 % KV], w2 = bv[u][2 % KV], w3 = bv[u][3 % KV];
+                *reinterpret_cast<f32x4v *>(b0) = f32x4v{w0.x, w1.x, w2.x, w3.x};
+                *reinterpret_cast<f32x4v *>(b0 + PG_KS) = f32x4v{-w0.y, -w1.y, -w2.y, -w3.y};
+                *reinterpret_cast<f32x4v *>(b1) = f32x4v{w0.y, w1.y, w2.y, w3.y};
+                *reinterpret_cast<f32x4v *>(b1 + PG_KS) = f32x4v{w0.x, w1.x, w2.x, w3.x};
+            } else {
+                b0[0] = bv[u][0].x;
+                b0[PG_KS] = -bv[u][0].y;
+                b1[0] = bv[u][0].y;
+                b1[PG_KS] = bv[u][0].x;
+            }
         }
     };
 #pragma unroll
@@ -1084,7 +1135,7 @@ __device__ __forceinline__ void pair_cut_store(float *ws, int slots, unsigned x,
             }
 }
 
-template <int WN>
+template <int WN, bool V4>
 __global__ void __launch_bounds__(256, WN == 2 ? 2 : 1) k_pair_gemm(PairPass pp, const float2 *__restrict__ X, double2 *__restrict__ Y,
                                                    int accumulate, float *ws, int slots, PairSched sc) {
     const unsigned x = blockIdx.x % 8, pos = blockIdx.x / 8;
@@ -1099,7 +1150,7 @@ __global__ void __launch_bounds__(256, WN == 2 ? 2 : 1) k_pair_gemm(PairPass pp,
         const int ke = (int)min<uint64_t>(sc.kc, kb + (ue - u));
         unsigned rt, ct;
         pair_tile_rc(t0 + tl, sc.nrt, sc.nct, rt, ct);
-        pair_gemm_tile<WN>(pp, X, rt, ct, kb, ke, pg_lds, acc);
+        pair_gemm_tile<WN, V4>(pp, X, rt, ct, kb, ke, pg_lds, acc);
         if (kb == 0 && ke == (int)sc.kc) {
             pair_gemm_store<WN>(pp, Y, accumulate, rt, ct, acc);
         } else {
@@ -4386,6 +4437,15 @@ void launch_pair_build(const PairPass &pp, hipStream_t st) {
 }
 
 // column tiles per wave of the pair GEMM: 2, 4, or 0 for the size rule (TTN_PAIR_WN)
+// 16-byte staging of the FP32 pair GEMM where n_P allows (TTN_PAIR_V4=0: scalar staging)
+static bool pair_gemm_v4_setting() {
+    static const bool v = [] {
+        const char *e = getenv("TTN_PAIR_V4");
+        return e ? atoi(e) != 0 : true;
+    }();
+    return v;
+}
+
 static int pair_gemm_wn_setting() {
     static const int v = [] {
         const char *e = getenv("TTN_PAIR_WN");
@@ -4460,7 +4520,7 @@ static int resident_slots(const void *kern, size_t lds) {
     return slots;
 }
 template <int WN> static int pair_gemm_slots() {
-    return resident_slots((const void *)k_pair_gemm<WN>, pair_gemm_lds<WN>());
+    return resident_slots((const void *)k_pair_gemm<WN, true>, pair_gemm_lds<WN>());
 }
 
 template <int WN> static int pair_slots_or(int slots) {
@@ -4489,13 +4549,19 @@ static void pair_gemm_go(const PairPass &pp, const float2 *in, double2 *out, int
     sc.ntile = sc.nrt * sc.nct;
     sc.kc = (unsigned)((Q + PG_KS - 1) / PG_KS);
     const size_t lds = pair_gemm_lds<WN>();
-    set_lds_limit((const void *)k_pair_gemm<WN>, lds);
     const unsigned per_xcd = (sc.ntile + 7) / 8;  // largest tile range of an XCD
     // without a workspace: one work-group per tile (shares never cut a tile)
     const int slots = ws ? pair_slots_or<WN>(ws_slots) : (int)(8 * per_xcd);
     const unsigned grid = 8 * std::min<unsigned>((unsigned)slots / 8, per_xcd);
-    TTN_LAUNCH("k_pair_gemm", flops, by, k_pair_gemm<WN>, dim3(grid), dim3(256), lds, st, pp, in, out, accumulate, ws,
-               slots, sc);
+    if (pp.np % 4 == 0 && pair_gemm_v4_setting()) {  // 16-byte staging
+        set_lds_limit((const void *)k_pair_gemm<WN, true>, lds);
+        TTN_LAUNCH("k_pair_gemm", flops, by, (k_pair_gemm<WN, true>), dim3(grid), dim3(256), lds, st, pp, in, out,
+                   accumulate, ws, slots, sc);
+    } else {
+        set_lds_limit((const void *)k_pair_gemm<WN, false>, lds);
+        TTN_LAUNCH("k_pair_gemm", flops, by, (k_pair_gemm<WN, false>), dim3(grid), dim3(256), lds, st, pp, in, out,
+                   accumulate, ws, slots, sc);
+    }
     if ((unsigned)slots / 8 < per_xcd) {  // some tiles are cut
         const double fb = (double)slots * 256 * 32 * WN * 4 * 2 + 16.0 * (double)slots * PG_BM * 32 * WN;
         TTN_LAUNCH("k_pair_fixup", 0.0, fb, k_pair_fixup<WN>, dim3(slots), dim3(256), 0, st, pp, out, accumulate,
