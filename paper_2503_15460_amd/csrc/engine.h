@@ -100,6 +100,9 @@ private:
     // tile balances as well: not bound by its matrix cores), 0 neither
     int pair_split = 1;
     int pair_slots = 0;  // work-groups sharing it (0: the device's capacity; TTN_PAIR_SLOTS, rounded down to 8s)
+    // FP32 pair GEMM: four kappa per thread and 16-byte staging where the
+    // parent dimension allows (TTN_PAIR_V4=0: one kappa per thread)
+    bool pair_v4 = true;
     float *pair_ws = nullptr;
     // FP32 mode: dense stages with factors of 24..64 on the FP32 matrix cores
     // (TTN_MODE_MFMA32=0 in the environment: the vector-ALU tiled kernel)

@@ -53,6 +53,7 @@ Engine::Engine(const Tree &tr, const ttn_options &o) : t(tr), opt(o) {
     if (const char *e = getenv("TTN_MODE_MFMA64")) mode_mfma64 = atoi(e) != 0;
     if (const char *e = getenv("TTN_PAIR_SPLIT")) pair_split = std::max(0, std::min(2, atoi(e)));
     if (const char *e = getenv("TTN_PAIR_SLOTS")) pair_slots = std::max(0, atoi(e));
+    if (const char *e = getenv("TTN_PAIR_V4")) pair_v4 = atoi(e) != 0;
     if (const char *e = getenv("TTN_PAIR_MIN_N")) pair_min_n = std::max<int64_t>(1, atoll(e));
     if (graph_mode && !st) {  // the null stream cannot be captured: a stream of the handle's own
         HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
@@ -988,6 +989,7 @@ void Engine::plan_pairs(Prog &h, int z) {
         pp.terms = h.pair_dterms[k];
         pp.n_terms = (int)per[k].size();
         pp.Wb = bf ? h.pair_wb[k] : nullptr;
+        pp.v4 = (pair_v4 && pp.np % 4 == 0) ? 1 : 0;
         h.pair.push_back(pp);
         h.pair_flops.push_back(8.0 * (double)h.g.N * wcur[k]);
     }

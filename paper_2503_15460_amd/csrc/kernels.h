@@ -106,6 +106,7 @@ struct PairPass {
     const PairTerm *terms;
     int n_terms;
     unsigned short *Wb;  // BF16x3 form: realified bf16 hi then lo parts, [2Q][2Q] each (null otherwise)
+    int v4;              // FP32 form: stage four kappa at a time (16-byte loads and LDS stores; needs np % 4 == 0)
 };
 constexpr int PAIR_KC = 16;  // complex K per LDS chunk of the pair GEMM
 void launch_pair_build(const PairPass &pp, hipStream_t st);

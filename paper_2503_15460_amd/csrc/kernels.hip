@@ -4437,15 +4437,6 @@ void launch_pair_build(const PairPass &pp, hipStream_t st) {
 }
 
 // column tiles per wave of the pair GEMM: 2, 4, or 0 for the size rule (TTN_PAIR_WN)
-// 16-byte staging of the FP32 pair GEMM where n_P allows (TTN_PAIR_V4=0: scalar staging)
-static bool pair_gemm_v4_setting() {
-    static const bool v = [] {
-        const char *e = getenv("TTN_PAIR_V4");
-        return e ? atoi(e) != 0 : true;
-    }();
-    return v;
-}
-
 static int pair_gemm_wn_setting() {
     static const int v = [] {
         const char *e = getenv("TTN_PAIR_WN");
@@ -4553,7 +4544,7 @@ static void pair_gemm_go(const PairPass &pp, const float2 *in, double2 *out, int
     // without a workspace: one work-group per tile (shares never cut a tile)
     const int slots = ws ? pair_slots_or<WN>(ws_slots) : (int)(8 * per_xcd);
     const unsigned grid = 8 * std::min<unsigned>((unsigned)slots / 8, per_xcd);
-    if (pp.np % 4 == 0 && pair_gemm_v4_setting()) {  // 16-byte staging
+    if (pp.v4 && pp.np % 4 == 0) {  // 16-byte staging
         set_lds_limit((const void *)k_pair_gemm<WN, true>, lds);
         TTN_LAUNCH("k_pair_gemm", flops, by, (k_pair_gemm<WN, true>), dim3(grid), dim3(256), lds, st, pp, in, out,
                    accumulate, ws, slots, sc);

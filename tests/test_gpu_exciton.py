@@ -155,6 +155,33 @@ def test_pair_operator_form_on_the_c3_shaped_tree(T, monkeypatch, prec, dtol):
     assert diff < dtol
 
 
+def test_pair_gemm_staging_forms_agree_bit_for_bit(T, monkeypatch):
+    """The FP32 pair GEMM stages its operands either four kappa at a time with
+    16-byte loads and stores (parent dimension a multiple of 4, the default)
+    or one at a time (TTN_PAIR_V4=0, and any other parent dimension): the same
+    values reach LDS and the matrix cores take them in the same order, so two
+    sweeps of the C3-shaped tree in the pair form give identical node tensors."""
+    import golden_refs as G
+    p = G.maker.c3_shaped()
+    bonds = T.clamp_bonds(p.parent, p.local_dim, p.bond_dim)
+    st = random_isometric_state(p.parent, p.local_dim, bonds, seed=31)
+    states = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("TTN_PAIR_MIN_N", "1")
+        monkeypatch.setenv("TTN_PAIR_V4", flag)
+        g = T.TTN.from_problem(p, precision=T.TTN_FP32)
+        monkeypatch.delenv("TTN_PAIR_MIN_N")
+        monkeypatch.delenv("TTN_PAIR_V4")
+        g.set_state(st)
+        T.profile_begin()
+        g.step(p.dt, 2)
+        assert "k_pair_gemm" in {r["name"] for r in T.profile_end()}
+        states.append(g.get_state())
+        g.close()
+    for a, b in zip(*states):
+        assert np.array_equal(a, b)
+
+
 def test_shared_pair_gemm_schedule_at_full_size(T, monkeypatch):
     """The exciton workload at full size (the configuration bench.py times),
     one sweep from a seeded full-rank state: the A nodes' pair GEMMs (864
