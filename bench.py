@@ -333,6 +333,35 @@ def batch_line(T, n_inst: int, steps: int, warmup: int):
                         f"{warmup} warm-up and {steps} timed sweeps each"}
 
 
+def ground_line(T, sweeps: int):
+    """One-site ground-state sweeps (DMRG on trees, Sec. II C) on the vibronic
+    model from its product state, FP64 and FP32-mixed: sweeps/s and the energy
+    after every sweep (exact-diagonalisation parity is in the tests, on trees
+    small enough for the dense generator)."""
+    import torch
+    from workloads import vibronic_problem
+    p = vibronic_problem()
+    out = {"workload": "vibronic24 ground state: one-site sweeps (S, root, S*) with Lanczos lowest-eigenvector "
+                       f"node solves and no bond steps, {sweeps} sweeps from the product state"}
+    for name in ("fp64", "fp32"):
+        g = T.TTN.from_problem(p, precision=PRECISIONS[name])
+        g.set_product_state(p.init_vecs)
+        es, per = [], []
+        for k in range(sweeps):
+            t0 = time.perf_counter()
+            e = g.ground_sweeps(1)
+            torch.cuda.synchronize()
+            per.append(time.perf_counter() - t0)
+            es.append(e)
+        out[name] = {"unit": "sweeps/s", "value": (sweeps - 1) / sum(per[1:]), "energy_per_sweep_eV": es,
+                     "norm_minus_1": g.norm2() - 1.0}
+        print(f"bench.py: vibronic24 ground state {name}: {1e3 * sum(per[1:]) / (sweeps - 1):.0f} ms/sweep, "
+              f"energy {es[-1]:.10f}", file=sys.stderr, flush=True)
+        g.close()
+    out["fp32_energy_minus_fp64"] = out["fp32"]["energy_per_sweep_eV"][-1] - out["fp64"]["energy_per_sweep_eV"][-1]
+    return out
+
+
 def adaptive_line(T, steps: int):
     """The exciton workload with subspace expansion (Sec. II D) from bonds of 8
     (spawning tolerance 1e-6, bonds up to 8/32/48/64 per layer), FP32-mixed:
@@ -447,6 +476,7 @@ def main():
         for key, fn in (("vibronic24", lambda: vibronic_line(T, 30, 3)),
                         ("heom_sbm", lambda: heom_line(T, 3)),
                         ("exciton10x120_adaptive", lambda: adaptive_line(T, 3)),
+                        ("vibronic24_ground_state", lambda: ground_line(T, 6)),
                         ("batched_instances", lambda: batch_line(T, args.batch_instances, args.batch_steps, args.batch_warmup))):
             try:
                 t0 = time.perf_counter()

@@ -182,6 +182,26 @@ ttn_status ttn_set_product_state(ttn_t h, const double *leaf_vecs);
  * TTN_E_NOCONV (state restored to before the failed step), TTN_E_DEVICE. */
 ttn_status ttn_step(ttn_t h, double dt, int32_t n_steps);
 
+/* Ground-state optimisation (Sec. II C: the single-site machinery also serves
+ * ground states, one-site alternating least squares, DMRG on trees): n_sweeps
+ * sweeps over the nodes in the order of one ttn_step (S, the root, S*), every
+ * node's tensor replaced by the eigenvector of the lowest eigenvalue of its
+ * local effective generator (Lanczos on the state's current tensor, FP64
+ * orthogonalisation; the fused solver restarts from the Ritz vector up to 8
+ * times until the residual |beta y_m| falls below the Krylov tolerance, the
+ * multi-kernel path takes one pass of the largest Krylov dimension) and the R
+ * factor of every QR gauge move absorbed unchanged (no backward bond step).
+ * The state stays normalised; Psi(0) and the propagation time are untouched.
+ * energy (host, 1 double) receives <Psi|G|Psi> / <Psi|Psi> after the last
+ * sweep; unconverged (host, may be NULL) the number of fused local solves
+ * whose residual stayed above the tolerance.  Needs a Hermitian generator
+ * (options.hermitian = 1) and no subspace expansion; precision as set by
+ * options.precision (the H_eff contractions in FP32 in the mixed modes).
+ * Errors: TTN_E_INVALID (n_sweeps < 1, null energy, non-Hermitian generator,
+ * subspace expansion on, handle in a batch), TTN_E_STATE (no SOP or state),
+ * TTN_E_DEVICE. */
+ttn_status ttn_ground_sweeps(ttn_t h, int32_t n_sweeps, double *energy, int32_t *unconverged);
+
 /* Observables; out receives complex values (2 doubles each), caller-owned.
  *   TTN_OBS_EXPECT     n op ids (distinct leaves) -> 1 value
  *   TTN_OBS_NORM       n = 0 -> 1 value

@@ -26,6 +26,7 @@ OBS_EXPECT, OBS_NORM, OBS_ENERGY, OBS_OVERLAP_T0, OBS_BILINEAR = 0, 1, 2, 3, 4
 
 # every symbol declared in include/ttn.h and include/ttn_debug.h
 EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product_state", "ttn_step",
+            "ttn_ground_sweeps",
             "ttn_observe", "ttn_apply_root_heff", "ttn_get_info", "ttn_state_size", "ttn_get_state",
             "ttn_set_state", "ttn_last_error", "ttn_destroy", "ttn_debug_dense_tree_operator",
             "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end",
@@ -109,6 +110,7 @@ def _load():
         "ttn_set_sop": (C.c_int32, [P, C.c_int32, i32p, i64p, dp, C.c_int32, dp, i64p, i32p]),
         "ttn_set_product_state": (C.c_int32, [P, dp]),
         "ttn_step": (C.c_int32, [P, C.c_double, C.c_int32]),
+        "ttn_ground_sweeps": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
         "ttn_observe": (C.c_int32, [P, C.c_int32, C.c_int32, i32p, dp, dp]),
         "ttn_apply_root_heff": (C.c_int32, [P, dp, dp]),
         "ttn_get_info": (C.c_int32, [P, i32p, i64p]),
@@ -370,6 +372,15 @@ class TTN:
 
     def step(self, dt: float, n_steps: int = 1):
         self._c(lib.ttn_step(self.h, float(dt), int(n_steps)))
+
+    def ground_sweeps(self, n_sweeps: int = 1, unconverged: bool = False):
+        """n one-site ground-state sweeps (DMRG on trees); returns the energy
+        <Psi|G|Psi> / <Psi|Psi> after them (and the number of fused local
+        solves left above the tolerance when unconverged=True)."""
+        e = C.c_double()
+        bad = C.c_int32()
+        self._c(lib.ttn_ground_sweeps(self.h, int(n_sweeps), C.byref(e), C.byref(bad)))
+        return (e.value, bad.value) if unconverged else e.value
 
     def _obs(self, kind, ids=(), vecs=None) -> complex:
         arr = np.ascontiguousarray(ids, dtype=np.int32) if len(ids) else np.zeros(1, dtype=np.int32)

@@ -145,6 +145,19 @@ ttn_status ttn_step(ttn_t h, double dt, int32_t n_steps) {
     });
 }
 
+ttn_status ttn_ground_sweeps(ttn_t h, int32_t n_sweeps, double *energy, int32_t *unconverged) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] {
+        if (!energy) throw ttn::Error(TTN_E_INVALID, "null output");
+        if (h->batch) throw ttn::Error(TTN_E_INVALID, "the handle belongs to a batch");
+        int bad = 0;
+        double e = 0.0;
+        sweep_guard([&] { e = h->eng->ground_sweeps(n_sweeps, &bad); });
+        *energy = e;
+        if (unconverged) *unconverged = bad;
+    });
+}
+
 ttn_status ttn_batch_create(int32_t n, ttn_t const *insts, int32_t n_streams, ttn_batch_t *out) {
     if (!out) {
         g_err = "null output handle";

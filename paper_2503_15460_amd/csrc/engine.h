@@ -69,6 +69,8 @@ public:
     void check_ready(double dt) const;
     hipStream_t stream() const { return st; }
     std::vector<double> observe(int kind, int n, const int32_t *op_ids, const double *vecs);
+    // n one-site ground-state sweeps (DMRG on trees); returns <Psi|G|Psi> / <Psi|Psi>
+    double ground_sweeps(int n, int *unconverged);
     void apply_root_heff(const double *x, double *y);
     void info(int32_t *bonds, int64_t *counters);
     size_t workspace_need() const { return ws_need; }
@@ -83,6 +85,7 @@ private:
     bool have_sop = false, have_state = false;
     bool adaptive = false;  // subspace expansion on (spawn_tol > 0)
     bool graph_mode = false;  // steps replayed from captured hipGraphs (use_graph)
+    bool ground = false;      // inside ground_sweeps: node solves are lowest-eigenvector solves, no bond steps
     // large QRs take the Cholesky route first (TTN_CHOLQR=0 in the environment:
     // Householder kernels only)
     bool cholqr = true;

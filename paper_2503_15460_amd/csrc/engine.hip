@@ -1066,6 +1066,7 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
         a.hermitian = opt.hermitian;
         a.m_hint = m_hint[si] > 0 ? m_hint[si] : 8;
         a.stat = stat;
+        a.ground = ground ? 1 : 0;
         // two-slot problems use the batched matvec when its temporaries fit in LDS
         int nA = 0;
         for (auto &e : p.ents)
@@ -1097,6 +1098,19 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
         else launch_small_solve(a, st);
     } else {
         if (!bk.V) throw Error(TTN_E_STATE, "internal: Krylov scratch not allocated");
+        if (ground) {  // one Lanczos pass of the largest dimension, then the lowest Ritz pair
+            const int64_t N = p.g.N;
+            const int m = (int)std::min<int64_t>(mmax, N);
+            launch_krylov_start(x, N, bk, st);
+            ProgView v = view(p);
+            for (int j = 0; j < m; ++j) {
+                launch_apply(p, v, bk.V + (size_t)j * N, bk.V + (size_t)(j + 1) * N);
+                if (krylov_cgs2) launch_krylov_orth(bk, N, j, mmax, st);
+                else launch_krylov_orth1(bk, N, j, mmax, st);
+            }
+            launch_krylov_ground(bk, N, m, mmax, x, stat, st);
+            return;
+        }
         int m = m_hint[si] > 0 ? m_hint[si] : 20;
         m = std::max(3, std::min(m, mmax));
         m = (int)std::min<int64_t>(m, p.g.N);
@@ -1115,7 +1129,10 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
 
 void Engine::forward(int z, double tau) { expm_prog(heffP[z], A[z], tau, z, true); }
 
-void Engine::backward(int c, double2 *C, double tau) { expm_prog(bondP[c], C, -tau, c, false); }
+void Engine::backward(int c, double2 *C, double tau) {
+    if (ground) return;  // ground-state sweeps: the bond factor is absorbed unchanged
+    expm_prog(bondP[c], C, -tau, c, false);
+}
 
 // ------------------------------------------------------ subspace expansion
 // Paper Sec. II D: when the sweep crosses the bond between node z and its
@@ -1706,6 +1723,46 @@ void Engine::step(double dt, int n_steps) {
         enqueue_step(dt);
         finish_step(dt);
     }
+}
+
+// ------------------------------------------------------ ground state
+// One-site ground-state sweeps (Sec. II C: the single-site machinery also
+// serves ground-state optimisation, DMRG on trees): the traversal of the
+// time-evolution sweep, S, the root, S*, with every node's local step replaced
+// by the lowest eigenvector of the same local effective generator and the
+// R factor of every gauge move absorbed unchanged (no backward bond step).
+double Engine::ground_sweeps(int n, int *unconverged) {
+    if (!have_sop || !have_state) throw Error(TTN_E_STATE, "the ground-state sweep needs ttn_set_sop and a state");
+    if (n < 1) throw Error(TTN_E_INVALID, "n_sweeps must be at least 1");
+    if (!opt.hermitian) throw Error(TTN_E_INVALID, "the ground-state sweep needs a Hermitian generator");
+    if (adaptive) throw Error(TTN_E_INVALID, "the ground-state sweep does not take subspace expansion");
+    int bad = 0;
+    ground = true;
+    try {
+        for (int s = 0; s < n; ++s) {
+            solve_idx = 0;
+            sweep_S(t.root, 0.0);
+            forward(t.root, 0.0);
+            sweep_Sstar(t.root, 0.0);
+            HIPCHK(hipMemcpyAsync(h_stats, d_stats, sizeof(SolveStat) * solve_idx, hipMemcpyDeviceToHost, st));
+            sync_check("ground-state sweep");
+            for (int i = 0; i < solve_idx; ++i) {  // matvec and H_eff flop counters as for a time step
+                bad += h_stats[i].fail;
+                const Prog &p = heffP[solve_node[i]];
+                ++counters[1];
+                counters[3] += h_stats[i].matvecs;
+                counters[4] += (int64_t)h_stats[i].matvecs * p.flops;
+            }
+        }
+    } catch (...) {
+        ground = false;
+        throw;
+    }
+    ground = false;
+    if (unconverged) *unconverged = bad;
+    const std::vector<double> e = observe(TTN_OBS_ENERGY, 0, nullptr, nullptr);
+    const std::vector<double> nn = observe(TTN_OBS_NORM, 0, nullptr, nullptr);
+    return e[0] / nn[0];
 }
 
 // ------------------------------------------------------------ observables

@@ -139,6 +139,7 @@ struct SolveStat {
     int matvecs;   // matrix-vector products
     double err;    // final error estimate (relative)
     double err_lo; // error estimate at a smaller dimension (big path)
+    double eval;   // ground-state mode: the lowest Ritz value of the local generator
 };
 
 struct SmallSolveArgs {
@@ -158,6 +159,7 @@ struct SmallSolveArgs {
     int mlds_elems;    // their total size in complex elements
     int nA;            // entries with a slot-1 factor (batched)
     SolveStat *stat;
+    int ground;        // 1: x <- the lowest eigenvector of G instead of exp(-i tau G) x (Hermitian G)
 };
 constexpr int SMALL_MAXENT = 128;  // entries of the batched two-slot matvec
 constexpr int SMALL_UB = 2048;     // slot-0 operator size limit of the batched two-slot matvec
@@ -320,5 +322,10 @@ void launch_krylov_orth(const BigKrylov &k, int64_t N, int j, int mmax, hipStrea
 void launch_krylov_orth1(const BigKrylov &k, int64_t N, int j, int mmax, hipStream_t st);
 void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double tau, double tol,
                           int hermitian, double2 *x, SolveStat *stat, hipStream_t st);
+// Ground-state form of the finish: x <- the Ritz vector of the lowest Ritz
+// value of the m-dimensional Lanczos matrix (unit norm), stat->eval the value,
+// stat->err the residual estimate |beta_m y_m| relative to max(1, |value|)
+void launch_krylov_ground(const BigKrylov &k, int64_t N, int m, int mmax, double2 *x, SolveStat *stat,
+                          hipStream_t st);
 
 }  // namespace ttn

@@ -2953,9 +2953,75 @@ __device__ void blk_sub_basis(const double2 *V, uint32_t N, int nv, const double
     }
 }
 
+// Lowest eigenpair of the real symmetric tridiagonal T (diagonal a[0..m),
+// off-diagonal b[0..m-1)), one thread: the eigenvalue by bisection on the
+// Sturm count of the LDL^T pivots of T - s I inside the Gershgorin interval;
+// the eigenvector by inverse iteration with the shift sigma just below it, so
+// that T - sigma I is positive definite and its LDL^T solve needs no pivoting;
+// returns the Rayleigh quotient, y receives the unit eigenvector (y[0] >= 0).
+__device__ double tridiag_ground(const double *a, const double *b, int m, double *y, double *work) {
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+    }
+    auto below = [&](double sft) {  // eigenvalues of T below sft
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < m; ++i) {
+            d = a[i] - sft - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    const double scale = fmax(1.0, fmax(fabs(lo), fabs(hi)));
+    for (int it = 0; it < 200 && hi - lo > 4e-16 * scale; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) >= 1) hi = mid;
+        else lo = mid;
+    }
+    const double sigma = lo - 1e-12 * scale;  // below the lowest eigenvalue: T - sigma I positive definite
+    double *dd = work, *ll = work + m;
+    dd[0] = a[0] - sigma;
+    for (int i = 0; i + 1 < m; ++i) {
+        ll[i] = b[i] / dd[i];
+        dd[i + 1] = a[i + 1] - sigma - ll[i] * b[i];
+    }
+    for (int i = 0; i < m; ++i) y[i] = 1.0;
+    for (int rep = 0; rep < 3; ++rep) {
+        for (int i = 1; i < m; ++i) y[i] -= ll[i - 1] * y[i - 1];  // L z = y
+        for (int i = 0; i < m; ++i) y[i] /= dd[i];                 // D w = z
+        for (int i = m - 2; i >= 0; --i) y[i] -= ll[i] * y[i + 1]; // L^T v = w
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += y[i] * y[i];
+        nrm = sqrt(nrm);
+        for (int i = 0; i < m; ++i) y[i] /= nrm;
+    }
+    int imax = 0;
+    for (int i = 1; i < m; ++i)
+        if (fabs(y[i]) > fabs(y[imax])) imax = i;
+    if (y[imax] < 0.0)
+        for (int i = 0; i < m; ++i) y[i] = -y[i];
+    double rq = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double ty = a[i] * y[i];
+        if (i > 0) ty += b[i - 1] * y[i - 1];
+        if (i + 1 < m) ty += b[i] * y[i + 1];
+        rq += y[i] * ty;
+    }
+    return rq;
+}
+
 // One Krylov exponential x <- exp(-i tau G) x; returns true when converged.
+// Ground-state mode (a.ground): at the same checkpoints the lowest Ritz pair of
+// the Lanczos matrix instead of the exponential; converged when the residual
+// |beta y_last| is below tol max(1, |value|); x then receives the Ritz vector
+// (unit norm).  At the last allowed dimension x receives the Ritz vector even
+// when it has not converged (a restart then begins from it).
 __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x, const SmallLds &L, int &m_used,
-                                int &matvecs, double &err_out) {
+                                int &matvecs, double &err_out, double *lambda = nullptr) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const uint32_t N = (uint32_t)a.g.N;
     const int mmax = a.mmax;
@@ -2995,7 +3061,34 @@ __device__ bool blk_krylov_once(const SmallSolveArgs &a, double tau, double2 *x,
         if (tid == 0) L.Hm[(j + 1) * mmax + j] = make_double2(beta, 0.0);
         __syncthreads();
         const bool breakdown = beta <= 1e-14 * beta0;
-        if (breakdown || j + 1 >= a.m_hint - 1 || j == mmax - 1) {
+        if (a.ground && (breakdown || j + 1 >= a.m_hint - 1 || j == mmax - 1)) {
+            const int m = j + 1;
+            double *ta = reinterpret_cast<double *>(L.r1), *tb = ta + m, *ty = tb + m, *tw = ty + m;
+            __shared__ double s_lam;
+            if (tid == 0) {
+                for (int i = 0; i < m; ++i) {
+                    ta[i] = L.Hm[i * mmax + i].x;
+                    if (i + 1 < m) tb[i] = L.Hm[(i + 1) * mmax + i].x;
+                }
+                s_lam = tridiag_ground(ta, tb, m, ty, tw);
+                for (int i = 0; i < m; ++i) L.ybuf[i] = make_double2(ty[i], 0.0);
+            }
+            __syncthreads();
+            const double lam = s_lam;
+            const double err = breakdown ? 0.0 : beta * fabs(L.ybuf[j].x) / fmax(1.0, fabs(lam));
+            const bool conv = breakdown || err <= a.tol;
+            if (conv || j == mmax - 1) {
+                for (uint32_t idx = tid; idx < N; idx += nt) x[idx] = make_double2(0.0, 0.0);
+                blk_sub_basis(V, N, m, L.ybuf, x);  // x = -sum_i y_i V_i
+                for (uint32_t idx = tid; idx < N; idx += nt) x[idx] = cscale(x[idx], -1.0);
+                m_used = m;
+                err_out = err;
+                if (lambda) *lambda = lam;
+                __syncthreads();
+                return conv;
+            }
+            err_out = err;
+        } else if (breakdown || j + 1 >= a.m_hint - 1 || j == mmax - 1) {
             // projected matrix of dimension j+1 (tridiagonal for Hermitian G)
             double2 *Hs = L.r1;
             const int m = j + 1;
@@ -3144,6 +3237,20 @@ __device__ void small_solve(const SmallSolveArgs &a) {
     int m_used = 0, matvecs = 0, level = 0;
     double err = 0.0;
     bool ok = false;
+    if (a.ground) {  // Lanczos restarted from the last Ritz vector until the residual converges
+        double lam = 0.0;
+        for (level = 0; level < 8 && !ok; ++level) ok = blk_krylov_once(a, 0.0, x, L, m_used, matvecs, err, &lam);
+        if (threadIdx.x == 0 && a.stat) {
+            a.stat->m = m_used;
+            a.stat->level = level - 1;
+            a.stat->fail = ok ? 0 : 1;
+            a.stat->matvecs = matvecs;
+            a.stat->err = err;
+            a.stat->err_lo = 0.0;
+            a.stat->eval = lam;
+        }
+        return;
+    }
     for (level = 0; level <= 8; ++level) {
         if (level > 0) {
             for (uint32_t idx = threadIdx.x; idx < N; idx += blockDim.x) x[idx] = xorig[idx];
@@ -3537,6 +3644,31 @@ __global__ void __launch_bounds__(1024) k_kry_expm(BigKrylov k, int m, int mmax,
         stat->matvecs = mm;
         stat->err = errs[0];
         stat->err_lo = (mm - 2 >= 1) ? errs[1] : 1.0;
+    }
+}
+
+// ground-state finish of the multi-kernel Lanczos (one work-group): k.y <- the
+// unit Ritz vector of the lowest Ritz value, stat: value and residual estimate
+__global__ void __launch_bounds__(64) k_kry_ground(BigKrylov k, int m, int mmax, SolveStat *stat) {
+    __shared__ double ta[64], tb[64], ty[64], tw[128];
+    const int meff = *k.meff;
+    const int mm = meff ? meff : m;
+    if (threadIdx.x == 0) {
+        const int ld = mmax + 1;
+        for (int i = 0; i < mm; ++i) {
+            ta[i] = k.Hm[(size_t)i * ld + i].x;
+            if (i + 1 < mm) tb[i] = k.Hm[(size_t)i * ld + i + 1].x;
+        }
+        const double lam = tridiag_ground(ta, tb, mm, ty, tw);
+        const double beta = meff ? 0.0 : k.Hm[(size_t)(mm - 1) * ld + mm].x;
+        for (int i = 0; i < mm; ++i) k.y[i] = make_double2(ty[i], 0.0);
+        stat->m = mm;
+        stat->level = 0;
+        stat->matvecs = m;
+        stat->err = beta * fabs(ty[mm - 1]) / fmax(1.0, fabs(lam));
+        stat->err_lo = 0.0;
+        stat->fail = 0;
+        stat->eval = lam;
     }
 }
 
@@ -4731,6 +4863,14 @@ void launch_krylov_orth1(const BigKrylov &k, int64_t N, int j, int mmax, hipStre
     TTN_LAUNCH("k_kry_update1", 0.0, 0.0, k_kry_update1, dim3(nb), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j, mmax,
                1);
     TTN_LAUNCH("k_kry_scale1", 0.0, 32.0 * N, k_kry_scale1, dim3(nb), dim3(VEC_THREADS), 0, st, k, (uint32_t)N, j);
+}
+
+void launch_krylov_ground(const BigKrylov &k, int64_t N, int m, int mmax, double2 *x, SolveStat *stat,
+                          hipStream_t st) {
+    if (m > 63) throw std::runtime_error("ground-state Lanczos dimension above 63");
+    TTN_LAUNCH("k_kry_ground", 0.0, 0.0, k_kry_ground, dim3(1), dim3(64), 0, st, k, m, mmax, stat);
+    TTN_LAUNCH("k_kry_combine", 8.0 * N * m, 16.0 * N * (m + 1), k_kry_combine, dim3(grid_for(N, VEC_THREADS)),
+               dim3(VEC_THREADS), 0, st, k, (uint32_t)N, m, x);
 }
 
 void launch_krylov_finish(const BigKrylov &k, int64_t N, int m, int mmax, double tau, double tol, int hermitian,
