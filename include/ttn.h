@@ -10,6 +10,9 @@
  *                    (Sec. II B 1, SOP equation);
  *   ttn_step       - the projector-splitting solution of the local equation of
  *                    motion dA/dt = -i sum_r c_r h_r A H_r (Sec. II C) over dt;
+ *   ttn_ground_sweeps - ground-state optimisation by the same single-site
+ *                    sweep with lowest-eigenvector node updates (Sec. II C,
+ *                    DMRG on trees);
  *   ttn_observe    - autocorrelation a(t) (Sec. IV A), populations and spin
  *                    expectation values (Secs. IV, V A), and the HEOM reduced
  *                    density matrix by vacuum projection (SI, FP-HEOM section).
