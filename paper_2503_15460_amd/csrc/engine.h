@@ -69,6 +69,7 @@ public:
     void check_ready(double dt) const;
     hipStream_t stream() const { return st; }
     std::vector<double> observe(int kind, int n, const int32_t *op_ids, const double *vecs);
+    double krylov_tolerance() const;  // local exponential error target (option or precision default)
     // n one-site ground-state sweeps (DMRG on trees); returns <Psi|G|Psi> / <Psi|Psi>
     double ground_sweeps(int n, int *unconverged);
     void apply_root_heff(const double *x, double *y);

@@ -1043,6 +1043,14 @@ bool Engine::use_fused(const Prog &p) const {
     return p.g.N <= SMALL_MAX && (p.g.D == 2 || (int64_t)p.ents.size() * p.g.N <= SMALL_SEQ_WORK);
 }
 
+// Relative error target of the local exponentials: the option, else 1e-13 in
+// FP64 and 1e-8 in the FP32 modes (below the ~1e-7 relative rounding their
+// complex FP32 contractions leave in every matrix-vector product)
+double Engine::krylov_tolerance() const {
+    if (opt.krylov_tol > 0) return opt.krylov_tol;
+    return opt.precision == TTN_FP64 ? 1e-13 : 1e-8;
+}
+
 void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd) {
     const int si = solve_idx++;
     if (si >= n_stats) throw Error(TTN_E_STATE, "internal: solve index overflow");
@@ -1051,7 +1059,7 @@ void Engine::expm_prog(const Prog &p, double2 *x, double tau, int node, bool fwd
     const bool fused = use_fused(p);
     solve_small[si] = fused ? 1 : 0;
     SolveStat *stat = d_stats + si;
-    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP64 ? 1e-13 : 1e-10);
+    const double tol = krylov_tolerance();
     prep(p);
     if (fused) {
         SmallSolveArgs a{};
@@ -1654,7 +1662,7 @@ void Engine::drop_graphs() {
 // multi-kernel solve missed its tolerance, restore the snapshot and run the
 // sweep again (synchronously) with larger dimensions.
 void Engine::finish_step(double dt) {
-    const double tol = opt.krylov_tol > 0 ? opt.krylov_tol : (opt.precision == TTN_FP64 ? 1e-13 : 1e-10);
+    const double tol = krylov_tolerance();
     while (true) {
         hipError_t e = hipEventSynchronize(step_done);
         if (e == hipSuccess) e = hipGetLastError();
