@@ -7,9 +7,9 @@ both consume the very same inputs without sharing any of the method's code.
 """
 from .problem import Problem, TreeBuilder
 from .models import (sbm_problem, vibronic_problem, exciton_problem,
-                     heom_sbm_problem, batch_sbm_problems, random_isometric_state,
+                     heom_sbm_problem, pseudomode_sbm_problem, batch_sbm_problems, random_isometric_state,
                      CONFIGS, config_problem)
 
 __all__ = ["Problem", "TreeBuilder", "sbm_problem", "vibronic_problem",
-           "exciton_problem", "heom_sbm_problem", "batch_sbm_problems",
+           "exciton_problem", "heom_sbm_problem", "pseudomode_sbm_problem", "batch_sbm_problems",
            "random_isometric_state", "CONFIGS", "config_problem"]

@@ -406,6 +406,85 @@ def heom_sbm_problem(K: int = 16, levels: int = 10, eps: float = 0.5, delta: flo
     return p
 
 
+def pseudomode_sbm_problem(K: int = 4, levels: int = 5, eps: float = 0.5, delta: float = 1.0,
+                           lam: float = 0.2, gam: float = 1.0, T: float = 1.0, bonds=(16, 24, 32),
+                           dt: float = 0.0075, n_steps: int = 400, rho0=None, coupling_scale: float = 1.0,
+                           name: str = "pseudomode_sbm") -> Problem:
+    """Quasi-Lindblad pseudomode form of the spin-boson model (SI, section on
+    the equivalence of free-pole HEOM and the generalised pseudomode method).
+
+    The bath correlation function C(t) = sum_k alpha_k exp(-nu_k t) of the
+    Debye bath (the same expansion as ``heom_sbm_problem``) is written as
+    sum_k (V_k - i M_k) exp(-(gamma_k + i E_k) t) (V_k + i M_k)^* with real
+    V_k - i M_k = sqrt(alpha_k), gamma_k + i E_k = nu_k.  In the Liouville
+    representation (ket index n and bra index m~ of every pseudomode, tilde
+    operators acting from the right: a~ |n><m| = |n><m| a^dag) the generator
+    G with d/dt |rho) = -i G |rho) is
+    ``L_s + sum_k [2i gamma_k a_k a~_k - i (nu_k n_k + nu_k^* n~_k)]
+          + sum_k 2i (M_k^* S^L a~_k + M_k S^R a_k)
+          + sum_k [(V_k^* - i M_k^*) S^L a_k^dag - (V_k + i M_k) S^R a~_k^dag]
+          + sum_k [(V_k - i M_k) S^L a_k - (V_k^* + i M_k^*) S^R a~_k]``
+    with L_s = H_s^L - H_s^R and, for the row-major vec of the system's 2 x 2
+    density matrix, X^L = X (x) 1 and X^R = 1 (x) X^T.  Each pseudomode and
+    its tilde partner form one leaf of dimension levels^2 (index n levels + m),
+    so that the boson trace vec(1) is a product over leaves; the K leaves form
+    a balanced binary subtree beside the 4-dim system leaf.  ``coupling_scale``
+    multiplies V_k and M_k (0: the spin decouples from the pseudomodes).
+    """
+    beta = 1.0 / T
+    alphas, nus = debye_matsubara(lam, gam, beta, K)
+    root_a = np.sqrt(alphas.astype(np.complex128))
+    V = root_a.real * coupling_scale
+    M = -root_a.imag * coupling_scale
+    L = levels
+    leaves = [("leaf", bonds[0], L * L, f"q{k}") for k in range(K)]
+
+    def bond_of(level):
+        return bonds[min(level + 1, len(bonds) - 1)]
+    bath = balanced_spec(leaves, bond_of, arity=2)
+    spec = ("node", 1, [("leaf", 4, 4, "S"), bath])
+    p = empty_problem(name, spec, dt=dt, n_steps=n_steps, hermitian=False)
+    op = _OpCache(p)
+    S = p.leaf_names["S"]
+    I2 = np.eye(2, dtype=np.complex128)
+    hs = 0.5 * eps * SIGMA["z"] + 0.5 * delta * SIGMA["x"]
+    sop = SIGMA["z"]
+    SL = np.kron(sop, I2)
+    SR = np.kron(I2, sop.T)
+    add_term(p, 1.0, [op(S, "Ls", np.kron(hs, I2) - np.kron(I2, hs.T))])
+    bo = boson_ops(L)
+    IL = np.eye(L, dtype=np.complex128)
+    a_, ad_, n_ = bo["a"], bo["adag"], bo["n"]
+    pm = {"a": np.kron(a_, IL), "adag": np.kron(ad_, IL), "n": np.kron(n_, IL),
+          "at": np.kron(IL, a_), "atdag": np.kron(IL, ad_), "nt": np.kron(IL, n_), "a_at": np.kron(a_, a_)}
+    for k in range(K):
+        q = p.leaf_names[f"q{k}"]
+        g_k, nu = nus[k].real, nus[k]
+        v, m = V[k], M[k]
+        add_term(p, 2j * g_k, [op(q, "a_at", pm["a_at"])])
+        add_term(p, -1j * nu, [op(q, "n", pm["n"])])
+        add_term(p, -1j * np.conj(nu), [op(q, "nt", pm["nt"])])
+        if v != 0.0 or m != 0.0:
+            add_term(p, 2j * np.conj(m), [op(S, "SL", SL), op(q, "at", pm["at"])])
+            add_term(p, 2j * m, [op(S, "SR", SR), op(q, "a", pm["a"])])
+            add_term(p, np.conj(v) - 1j * np.conj(m), [op(S, "SL", SL), op(q, "adag", pm["adag"])])
+            add_term(p, -(v + 1j * m), [op(S, "SR", SR), op(q, "atdag", pm["atdag"])])
+            add_term(p, v - 1j * m, [op(S, "SL", SL), op(q, "a", pm["a"])])
+            add_term(p, -(np.conj(v) + 1j * np.conj(m)), [op(S, "SR", SR), op(q, "at", pm["at"])])
+    if rho0 is None:
+        rho0 = np.array([[1, 0], [0, 0]], dtype=np.complex128)
+    p.init_vecs[S] = np.asarray(rho0, dtype=np.complex128).reshape(-1)
+    vac = np.zeros(L * L, dtype=np.complex128)
+    vac[0] = 1.0  # |0><0|
+    for k in range(K):
+        p.init_vecs[p.leaf_names[f"q{k}"]] = vac.copy()
+    # bilinear observables: (b| rho) with b = vec(O^T) on S and the boson trace vec(1) on every leaf
+    p.meta.update(dict(alphas=alphas, nus=nus, V=V, M=M, eps=eps, delta=delta, lam=lam, gam=gam, beta=beta,
+                       K=K, levels=L, bra_sz=SIGMA["z"].T.reshape(-1).copy(), bra_tr=I2.reshape(-1).copy(),
+                       bra_bath=IL.reshape(-1).copy()))
+    return p
+
+
 def batch_sbm_problems(seed: int = 5, n_inst: int = 256, nmin: int = 8, nmax: int = 64,
                        dmin: int = 6, dmax: int = 16, bmin: int = 8, bmax: int = 48,
                        dt: float = 0.05, n_steps: int = 100) -> List[Problem]:
