@@ -276,6 +276,35 @@ def heom_line(T, steps: int):
     return out
 
 
+def pseudomode_line(T, steps: int):
+    """Quasi-Lindblad pseudomode spin-boson (the same Debye bath as the HEOM
+    line with 8 poles, each pseudomode and its tilde partner one leaf of 5 x 5
+    levels, bonds 16-32, Arnoldi): FP64 and FP32 sweeps/s, <sigma_z> and
+    Tr rho_S (the boson trace) after the sweeps."""
+    from workloads import pseudomode_sbm_problem
+    p = pseudomode_sbm_problem(K=8, levels=5, bonds=(16, 24, 32))
+    S = p.leaf_names["S"]
+
+    def obs(g):
+        out = []
+        for key in ("bra_sz", "bra_tr"):
+            bra = {z: p.meta["bra_bath"] for z in p.leaves()}
+            bra[S] = p.meta[key]
+            out.append(g.bilinear(bra))
+        return np.array(out)
+    out, vals = {}, {}
+    for name in ("fp64", "fp32"):
+        out[name], g = timed_run(T, p, PRECISIONS[name], steps, 1, keep=True)
+        vals[name] = obs(g)
+        g.close()
+    out["sigma_z_trace_fp64"] = [float(vals["fp64"][0].real), float(vals["fp64"][1].real)]
+    out["fp32_max_abs_diff_vs_fp64"] = float(np.abs(vals["fp64"] - vals["fp32"]).max())
+    out["workload"] = ("pseudomode_sbm: eps 0.5, Delta 1, Debye lambda 0.2 gamma 1 T 1, 8 poles as quasi-Lindblad "
+                       "pseudomodes (leaf = mode and tilde partner, 5 x 5 levels), binary tree, bonds 16-32, "
+                       f"non-Hermitian (Arnoldi), dt 0.0075, {1 + steps} sweeps")
+    return out
+
+
 def batch_line(T, n_inst: int, steps: int, warmup: int):
     """Uneven spin-boson instances (8-64 modes, 6-16 levels, bonds 8-48): one
     at a time in FP64 against one batch in FP32-mixed on several streams, and
@@ -475,6 +504,7 @@ def main():
         # context lines: a failure there is recorded and the headline still printed
         for key, fn in (("vibronic24", lambda: vibronic_line(T, 30, 3)),
                         ("heom_sbm", lambda: heom_line(T, 3)),
+                        ("pseudomode_sbm", lambda: pseudomode_line(T, 3)),
                         ("exciton10x120_adaptive", lambda: adaptive_line(T, 3)),
                         ("vibronic24_ground_state", lambda: ground_line(T, 6)),
                         ("batched_instances", lambda: batch_line(T, args.batch_instances, args.batch_steps, args.batch_warmup))):
