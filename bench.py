@@ -305,6 +305,44 @@ def pseudomode_line(T, steps: int):
     return out
 
 
+def ipchain_line(T, steps: int):
+    """Interaction-picture chain spin-boson (Ohmic, alpha 0.5, w_c 5, 64 chain
+    modes of 8 levels, bonds 8-24): time-dependent couplings G_l(t) set at
+    every step's midpoint through ttn_set_coefficients.  FP64 and FP32 sweeps/s
+    with the coefficient updates inside the timed region (FP32 also with step
+    graphs), the share of the time spent in the updates, and <sigma_z>."""
+    import torch
+    from workloads import ipchain_coefficients, ipchain_sbm_problem
+    p = ipchain_sbm_problem(n_modes=64, d=8, bonds=(8, 16, 24), eps=0.0, delta=1.0, alpha=0.5, wc=5.0, dt=0.02)
+    coef = lambda t: ipchain_coefficients(p, t)  # noqa: E731
+    out = {}
+    for name, prec, graph in (("fp64", T.TTN_FP64, False), ("fp32", T.TTN_FP32, False),
+                              ("fp32_graph", T.TTN_FP32, True)):
+        g = T.TTN(p.parent, p.local_dim, p.bond_dim, precision=prec, hermitian=True, use_graph=graph)
+        g.set_sop_problem(p)
+        g.set_product_state(p.init_vecs)
+        t = g.step_td(p.dt, coef, 0.0, 2)  # step graphs: the second step settles the capture key
+        torch.cuda.synchronize()
+        upd = 0.0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            u0 = time.perf_counter()
+            g.set_coefficients(coef(t + 0.5 * p.dt))
+            upd += time.perf_counter() - u0
+            g.step(p.dt)
+            t += p.dt
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"value": steps / el, "unit": "sweeps/s", "ms_per_step": 1e3 * el / steps,
+                     "coefficient_update_ms": 1e3 * upd / steps,
+                     "sigma_z": float(g.expect(p.observables["sz"]).real)}
+        g.close()
+    out["workload"] = ("ipchain_sbm: eps 0, Delta 1, Ohmic alpha 0.5 w_c 5 (Gauss rule to 10 w_c), 64 chain modes "
+                       "of 8 levels in a balanced binary tree beside the spin, bonds 8-24, dt 0.02, couplings "
+                       f"G_l(t) at every step's midpoint, {2 + steps} steps")
+    return out
+
+
 def batch_line(T, n_inst: int, steps: int, warmup: int):
     """Uneven spin-boson instances (8-64 modes, 6-16 levels, bonds 8-48): one
     at a time in FP64 against one batch in FP32-mixed on several streams, and
@@ -505,6 +543,7 @@ def main():
         for key, fn in (("vibronic24", lambda: vibronic_line(T, 30, 3)),
                         ("heom_sbm", lambda: heom_line(T, 3)),
                         ("pseudomode_sbm", lambda: pseudomode_line(T, 3)),
+                        ("ipchain_sbm", lambda: ipchain_line(T, 5)),
                         ("exciton10x120_adaptive", lambda: adaptive_line(T, 3)),
                         ("vibronic24_ground_state", lambda: ground_line(T, 6)),
                         ("batched_instances", lambda: batch_line(T, args.batch_instances, args.batch_steps, args.batch_warmup))):

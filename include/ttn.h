@@ -8,6 +8,8 @@
  *                    functions n on every bond, primitive dimensions at leaves);
  *   ttn_set_sop    - the sum-of-product generator H = sum_r c_r prod h_{a,r}
  *                    (Sec. II B 1, SOP equation);
+ *   ttn_set_coefficients - new coefficients c_r for the same terms between
+ *                    steps (time-dependent coefficients, Sec. II B);
  *   ttn_step       - the projector-splitting solution of the local equation of
  *                    motion dA/dt = -i sum_r c_r h_r A H_r (Sec. II C) over dt;
  *   ttn_ground_sweeps - ground-state optimisation by the same single-site
@@ -164,6 +166,32 @@ ttn_status ttn_create(int32_t n_nodes, const int32_t *parent, const int32_t *loc
 ttn_status ttn_set_sop(ttn_t h, int32_t n_ops, const int32_t *op_leaf, const int64_t *op_offset,
                        const double *op_data, int32_t n_terms, const double *coeff,
                        const int64_t *term_ptr, const int32_t *term_ops);
+
+/* Time-dependent coefficients (Sec. II B: the operator front-end allows
+ * coefficients that depend on time; Sec. II E 2: the interaction-picture chain
+ * form of the spin-boson model has time-dependent couplings g_k(t)).  Replaces the coefficients c_r of the
+ * terms given to ttn_set_sop (same operators, same terms, same order) for the
+ * following steps.  coeff (host): n_terms complex values, 2 doubles each.  A
+ * step then propagates with the coefficients frozen: a caller integrating
+ * H(t) sets c_r(t + dt/2) before every step of dt (the midpoint rule, second
+ * order like the symmetric sweep).
+ * The operator is compiled again on the host.  When its structure is the same
+ * (the same channels on every bond and the same entries at every node, which
+ * holds while no coefficient or sum of coefficients becomes or stops being
+ * exactly zero), the leaf channel operators and the coefficient tables on the
+ * device are overwritten in place, with no device allocation; otherwise the
+ * operator is rebuilt as by ttn_set_sop.  Either way the state is kept and its
+ * environments are rebuilt.  Step graphs (use_graph) stay valid when only
+ * values changed and the band of every leaf channel operator is the same (the
+ * graphs read the rewritten tables); otherwise they are recorded again at the
+ * next step.
+ * rebuilt (host, may be NULL) receives 1 if the operator was rebuilt, else 0.
+ * Errors: TTN_E_STATE (no SOP yet), TTN_E_INVALID (n_terms differs from the
+ * operator's, null coeff, a coefficient not finite, or hermitian = 1 and the
+ * generator with these coefficients fails the Hermiticity check of
+ * ttn_set_sop; the operator in place is then unchanged), TTN_E_OOM (rebuild
+ * only; the handle then has no operator), TTN_E_DEVICE. */
+ttn_status ttn_set_coefficients(ttn_t h, int32_t n_terms, const double *coeff, int32_t *rebuilt);
 
 /* Product initial state (the Hartree product the paper starts its
  * propagations from, Secs. III and IV A, where the unoccupied single-particle

@@ -30,6 +30,9 @@ What it follows (paper: pyTTN, arXiv 2503.15460):
 * Local exponentials: dense ``expm`` for local problems up to ``dense_max``
   unknowns, otherwise Lanczos (Hermitian) or Arnoldi (non-Hermitian) with full
   re-orthogonalisation and an a-posteriori error estimate.
+* Time-dependent coefficients (Sec. II B; the interaction-picture chain form
+  of Sec. II E 2): the paper does not state how a step treats them; read here
+  as coefficients frozen at the midpoint of each step (``step_td``).
 
 Readings of points the paper leaves open are listed in the repository's design
 notes; in short: unoccupied SPFs of a product state are completed with unit
@@ -612,6 +615,26 @@ class Oracle:
         self.forward(self.root, dt)
         self._Sstar(self.root, h)
         self.time += dt
+
+    def set_coefficients(self, coef) -> None:
+        """New coefficients c_r for the same terms (Sec. II B: coefficients may
+        depend on time).  The SPO matrices hold the inside aggregates, which
+        carry coefficients, so they are rebuilt from the state; the mean fields
+        are rebuilt by the sweep before every use."""
+        coef = np.asarray(coef, dtype=np.complex128)
+        if coef.shape != self.coef.shape:
+            raise ValueError(f"expected {self.coef.shape[0]} coefficients, got {coef.shape}")
+        self.coef = coef.copy()
+        if self.A[self.root] is not None:
+            self.build_all_spos()
+
+    def step_td(self, dt: float, coef_at: Callable[[float], np.ndarray]) -> None:
+        """One step of a generator with time-dependent coefficients: the
+        coefficients are frozen at the midpoint of the step, c_r(t + dt/2),
+        and the sweep of ``step`` propagates over dt (second order in dt, like
+        the symmetric sweep itself)."""
+        self.set_coefficients(coef_at(self.time + 0.5 * dt))
+        self.step(dt)
 
     # ------------------------------------------------------ observables
     def _contract(self, bra, ket, leaf_ops: Dict[int, np.ndarray]) -> complex:

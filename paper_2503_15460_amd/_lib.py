@@ -26,7 +26,7 @@ OBS_EXPECT, OBS_NORM, OBS_ENERGY, OBS_OVERLAP_T0, OBS_BILINEAR = 0, 1, 2, 3, 4
 
 # every symbol declared in include/ttn.h and include/ttn_debug.h
 EXPORTED = ["ttn_default_options", "ttn_create", "ttn_set_sop", "ttn_set_product_state", "ttn_step",
-            "ttn_ground_sweeps",
+            "ttn_ground_sweeps", "ttn_set_coefficients",
             "ttn_observe", "ttn_apply_root_heff", "ttn_get_info", "ttn_state_size", "ttn_get_state",
             "ttn_set_state", "ttn_last_error", "ttn_destroy", "ttn_debug_dense_tree_operator",
             "ttn_debug_clamp_bonds", "ttn_debug_qr", "ttn_profile_begin", "ttn_profile_end",
@@ -111,6 +111,7 @@ def _load():
         "ttn_set_product_state": (C.c_int32, [P, dp]),
         "ttn_step": (C.c_int32, [P, C.c_double, C.c_int32]),
         "ttn_ground_sweeps": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+        "ttn_set_coefficients": (C.c_int32, [P, C.c_int32, dp, C.POINTER(C.c_int32)]),
         "ttn_observe": (C.c_int32, [P, C.c_int32, C.c_int32, i32p, dp, dp]),
         "ttn_apply_root_heff": (C.c_int32, [P, dp, dp]),
         "ttn_get_info": (C.c_int32, [P, i32p, i64p]),
@@ -364,6 +365,24 @@ class TTN:
         self._c(lib.ttn_set_sop(self.h, len(op_leaf), _ptr(op_leaf, C.c_int32), _ptr(off, C.c_int64),
                                 _ptr(data, C.c_double), len(p.term_ops), _ptr(coeff, C.c_double),
                                 _ptr(tptr, C.c_int64), _ptr(tops, C.c_int32)))
+
+    def set_coefficients(self, coeff) -> bool:
+        """New coefficients for the terms in place (one complex value per
+        term, in term order); returns True if the operator was rebuilt."""
+        c = np.ascontiguousarray(coeff, dtype=np.complex128)
+        rebuilt = C.c_int32()
+        self._c(lib.ttn_set_coefficients(self.h, len(c), _ptr(c.view(np.float64), C.c_double), C.byref(rebuilt)))
+        return bool(rebuilt.value)
+
+    def step_td(self, dt: float, coef_at, t: float, n_steps: int = 1) -> float:
+        """n_steps steps of dt from time t of a generator whose coefficients
+        depend on time: before every step the coefficients coef_at(t + dt/2)
+        (the midpoint of that step) are set.  Returns the time reached."""
+        for _ in range(int(n_steps)):
+            self.set_coefficients(coef_at(t + 0.5 * dt))
+            self.step(dt)
+            t += dt
+        return t
 
     def set_product_state(self, vecs: Dict[int, np.ndarray]):
         leaves = [z for z in range(self.n) if self.local_dim[z] > 0]

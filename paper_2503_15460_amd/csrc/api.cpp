@@ -132,6 +132,14 @@ ttn_status ttn_set_sop(ttn_t h, int32_t n_ops, const int32_t *op_leaf, const int
     });
 }
 
+ttn_status ttn_set_coefficients(ttn_t h, int32_t n_terms, const double *coeff, int32_t *rebuilt) {
+    if (!h) return TTN_E_INVALID;
+    return guard(h, [&] {
+        const bool r = h->eng->set_coefficients(coeff, n_terms);
+        if (rebuilt) *rebuilt = r ? 1 : 0;
+    });
+}
+
 ttn_status ttn_set_product_state(ttn_t h, const double *leaf_vecs) {
     if (!h) return TTN_E_INVALID;
     return guard(h, [&] { h->eng->set_product_state(leaf_vecs); });

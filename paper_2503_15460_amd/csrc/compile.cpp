@@ -510,6 +510,23 @@ TreeOp compile_tree_operator(const Tree &t, const SopInput &s) {
     return op;
 }
 
+bool same_tree_operator_structure(const TreeOp &a, const TreeOp &b) {
+    if (a.n_ch != b.n_ch || a.inside_used != b.inside_used || a.outside_used != b.outside_used) return false;
+    if (a.entries.size() != b.entries.size() || a.leafU.size() != b.leafU.size()) return false;
+    for (size_t z = 0; z < a.entries.size(); ++z) {
+        const auto &ea = a.entries[z], &eb = b.entries[z];
+        if (ea.size() != eb.size()) return false;
+        for (size_t e = 0; e < ea.size(); ++e)
+            if (ea[e].slot != eb[e].slot || ea[e].bp != eb[e].bp) return false;
+    }
+    for (size_t l = 0; l < a.leafU.size(); ++l) {
+        if (a.leafU[l].size() != b.leafU[l].size()) return false;
+        for (size_t ch = 0; ch < a.leafU[l].size(); ++ch)
+            if (a.leafU[l][ch].empty() != b.leafU[l][ch].empty()) return false;
+    }
+    return true;
+}
+
 // Greedy: every (item, position) gives a candidate key (group, number of
 // factors, position, slots, ids of the other factors); the largest candidate
 // sets are taken first and every item joins at most one set.

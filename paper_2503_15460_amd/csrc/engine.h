@@ -50,6 +50,10 @@ public:
     ~Engine();
 
     void set_sop(const SopInput &s);
+    // New coefficients for the terms of the operator in place (same operators
+    // and terms); returns true if the compiled structure changed and the
+    // operator was rebuilt, false if only values were replaced.
+    bool set_coefficients(const double *coeff, int n_terms);
     void set_product_state(const double *leaf_vecs);
     void set_state(const double *buf, size_t bytes);
     void get_state(double *buf, size_t bytes);
@@ -172,6 +176,7 @@ private:
 
     void *dalloc(size_t bytes);
     void free_sop();
+    void put_leaf_ops(int c);  // leaf channel operators of leaf c and their bands into U[c]
     Geom geom_of(const std::vector<int> &dims) const;
     void upload(Prog &p);
     void merge_entries(Prog &p);

@@ -512,6 +512,35 @@ void Engine::build_node_programs(int z) {
     }
 }
 
+// Leaf channel operators of leaf c (channel 0, the identity, left empty) and
+// the band of each; U[c] is allocated on the first call and overwritten after.
+void Engine::put_leaf_ops(int c) {
+    const int d = t.local_dim[c];
+    const int li = t.leaf_index[c];
+    std::vector<double2> hu((size_t)op.n_ch[c] * d * d, make_double2(0.0, 0.0));
+    for (int ch = 1; ch < op.n_ch[c]; ++ch)
+        if (ch < (int)op.leafU[li].size())
+            for (size_t q = 0; q < op.leafU[li][ch].size(); ++q) hu[(size_t)ch * d * d + q] = to_d2(op.leafU[li][ch][q]);
+    // band of every channel operator (exact zeros outside i - lo <= j <= i + hi)
+    ulo[c].assign(op.n_ch[c], d - 1);
+    uhi[c].assign(op.n_ch[c], d - 1);
+    for (int ch = 1; ch < op.n_ch[c]; ++ch) {
+        int lo = 0, hi = 0;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                const double2 v = hu[(size_t)ch * d * d + (size_t)i * d + j];
+                if (v.x != 0.0 || v.y != 0.0) {
+                    lo = std::max(lo, i - j);
+                    hi = std::max(hi, j - i);
+                }
+            }
+        ulo[c][ch] = lo;
+        uhi[c][ch] = hi;
+    }
+    if (!U[c]) U[c] = (double2 *)dalloc(sizeof(double2) * hu.size());
+    HIPCHK(hipMemcpy(U[c], hu.data(), sizeof(double2) * hu.size(), hipMemcpyHostToDevice));
+}
+
 void Engine::set_sop(const SopInput &s) {
     if (opt.hermitian && !sop_is_hermitian(s))
         throw Error(TTN_E_INVALID, "hermitian=1 but the SOP generator is not Hermitian");
@@ -534,33 +563,7 @@ void Engine::set_sop(const SopInput &s) {
         mf[c] = (double2 *)dalloc(bytes);
         HIPCHK(hipMemset(spo[c], 0, bytes));
         HIPCHK(hipMemset(mf[c], 0, bytes));
-        if (t.local_dim[c] > 0) {
-            const int d = t.local_dim[c];
-            const int li = t.leaf_index[c];
-            std::vector<double2> hu((size_t)op.n_ch[c] * d * d, make_double2(0.0, 0.0));
-            for (int ch = 1; ch < op.n_ch[c]; ++ch)
-                if (ch < (int)op.leafU[li].size())
-                    for (size_t q = 0; q < op.leafU[li][ch].size(); ++q)
-                        hu[(size_t)ch * d * d + q] = to_d2(op.leafU[li][ch][q]);
-            // band of every channel operator (exact zeros outside i - lo <= j <= i + hi)
-            ulo[c].assign(op.n_ch[c], d - 1);
-            uhi[c].assign(op.n_ch[c], d - 1);
-            for (int ch = 1; ch < op.n_ch[c]; ++ch) {
-                int lo = 0, hi = 0;
-                for (int i = 0; i < d; ++i)
-                    for (int j = 0; j < d; ++j) {
-                        const double2 v = hu[(size_t)ch * d * d + (size_t)i * d + j];
-                        if (v.x != 0.0 || v.y != 0.0) {
-                            lo = std::max(lo, i - j);
-                            hi = std::max(hi, j - i);
-                        }
-                    }
-                ulo[c][ch] = lo;
-                uhi[c][ch] = hi;
-            }
-            U[c] = (double2 *)dalloc(sizeof(double2) * hu.size());
-            HIPCHK(hipMemcpy(U[c], hu.data(), sizeof(double2) * hu.size(), hipMemcpyHostToDevice));
-        }
+        if (t.local_dim[c] > 0) put_leaf_ops(c);
     }
     build_programs();
     // scratch sizes
@@ -774,6 +777,48 @@ void Engine::set_sop(const SopInput &s) {
     }
     if (have_state) rebuild_all_spos();
     HIPCHK(hipStreamSynchronize(st));
+}
+
+// Time-dependent coefficients (Sec. II B): the same terms with new c_r.  The
+// operator is compiled again on the host; when its structure is unchanged,
+// the leaf channel operators and the program tables (entry coefficients,
+// combination weights, pair-operator terms) are rewritten in place, with no
+// device allocation, and the environments are rebuilt from the state.
+bool Engine::set_coefficients(const double *coeff, int n_terms) {
+    if (!have_sop) throw Error(TTN_E_STATE, "no SOP generator set");
+    if (!coeff || n_terms != sop.n_terms)
+        throw Error(TTN_E_INVALID, "set_coefficients needs the " + std::to_string(sop.n_terms) +
+                                       " coefficients of the terms in place");
+    SopInput s = sop;
+    for (int r = 0; r < n_terms; ++r) {
+        const cplx c(coeff[2 * r], coeff[2 * r + 1]);
+        if (!std::isfinite(c.real()) || !std::isfinite(c.imag()))
+            throw Error(TTN_E_INVALID, "non-finite coefficient in term " + std::to_string(r));
+        s.coeff[r] = c;
+    }
+    if (opt.hermitian && !sop_is_hermitian(s))
+        throw Error(TTN_E_INVALID, "hermitian=1 but the SOP generator with these coefficients is not Hermitian");
+    TreeOp newop = compile_tree_operator(t, s);
+    if (!same_tree_operator_structure(op, newop)) {
+        set_sop(s);
+        return true;
+    }
+    HIPCHK(hipStreamSynchronize(st));  // kernels in flight read the tables rewritten below
+    sop = std::move(s);
+    op = std::move(newop);
+    const size_t n_alloc = sop_allocs.size();
+    const auto lo0 = ulo, hi0 = uhi;
+    for (int c = 0; c < t.n; ++c)
+        if (c != t.root && t.local_dim[c] > 0) put_leaf_ops(c);
+    // step graphs read the rewritten tables through their device pointers; the
+    // launch sequence itself depends on the values only through the bands of
+    // the leaf channel operators (banded or dense stage kernels)
+    if (ulo != lo0 || uhi != hi0) drop_graphs();
+    for (int z = 0; z < t.n; ++z) build_node_programs(z);
+    if (sop_allocs.size() != n_alloc) throw Error(TTN_E_STATE, "internal: coefficient update allocated");
+    if (have_state) rebuild_all_spos();
+    HIPCHK(hipStreamSynchronize(st));
+    return false;
 }
 
 // ------------------------------------------------------------------ state

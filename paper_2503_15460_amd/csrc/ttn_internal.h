@@ -92,6 +92,11 @@ double sop_hermiticity_defect(const SopInput &s, double cluster);
 bool sop_is_hermitian(const SopInput &s, double rtol = 1e-7);
 
 TreeOp compile_tree_operator(const Tree &t, const SopInput &s);
+// True if two compiled operators differ at most in values: the same channels
+// on every bond, the same entries (slots and parent channel) at every node and
+// the same non-empty leaf channel operators.  Programs, environments and
+// scratch built for one then fit the other.
+bool same_tree_operator_structure(const TreeOp &a, const TreeOp &b);
 
 // Node form of the operator (Sec. II B 2, terms (B) and (C)): products that
 // share every factor but one are summed into one product whose remaining

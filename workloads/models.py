@@ -485,6 +485,102 @@ def pseudomode_sbm_problem(K: int = 4, levels: int = 5, eps: float = 0.5, delta:
     return p
 
 
+def chain_transform(w, g):
+    """Star-to-chain transformation of a harmonic bath (Sec. II E 2, chain form
+    of the system-bath Hamiltonian): Lanczos tridiagonalisation of diag(w)
+    started from g / |g|, with full re-orthogonalisation.
+
+    Returns ``(V, eps, t, kappa0)`` with V real orthogonal (star mode
+    a_k = sum_l V[k, l] b_l in terms of the chain modes b_l), V[:, 0] = g / kappa0,
+    kappa0 = |g| and V^T diag(w) V tridiagonal with on-site energies eps and
+    hoppings t.
+    """
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    n = len(w)
+    kappa0 = float(np.linalg.norm(g))
+    V = np.zeros((n, n))
+    V[:, 0] = g / kappa0
+    eps = np.zeros(n)
+    t = np.zeros(max(n - 1, 0))
+    for j in range(n):
+        v = w * V[:, j]
+        eps[j] = V[:, j] @ v
+        for _ in range(2):  # projection on every earlier vector, twice
+            v -= V[:, : j + 1] @ (V[:, : j + 1].T @ v)
+        if j + 1 < n:
+            t[j] = np.linalg.norm(v)
+            V[:, j + 1] = v / t[j]
+    return V, eps, t, kappa0
+
+
+def ipchain_sbm_problem(n_modes: int = 8, d: int = 6, bonds=(8, 8, 8), eps: float = 0.0, delta: float = 1.0,
+                        alpha: float = 0.5, wc: float = 5.0, dt: float = 0.02, n_steps: int = 200,
+                        chain: bool = True, name: str = "ipchain_sbm") -> Problem:
+    """Interaction-picture chain form of the spin-boson model (Sec. II E 2,
+    equation for H_SB^ic(t)), a generator with time-dependent coefficients.
+
+    The star model of ``sbm_problem`` (Ohmic bath, J(w) = pi sum g_k^2
+    delta(w - w_k) from the Gauss rule of Sec. II E 1) is taken to the chain
+    modes b_l = sum_k V[k, l] a_k of ``chain_transform`` and to the interaction
+    picture of the bath Hamiltonian H_B = sum_k w_k n_k (in the chain basis the
+    on-site and hopping terms), where H_B drops out and
+    ``G(t) = eps/2 sz + delta/2 sx + sz sum_l [G_l(t) b_l^dag + G_l(t)^* b_l]``
+    with ``G_l(t) = sum_k V[k, l] g_k exp(i w_k t)``; at t = 0 only the first
+    chain mode couples, with kappa0 = |g|.  ``chain=False`` keeps the star
+    modes (V = 1, G_k(t) = g_k exp(i w_k t)): on the truncated Fock spaces this
+    is exactly the interaction picture of the truncated star model.
+
+    Terms, in order: eps/2 sz, delta/2 sx, then per mode l the pair
+    sz b_l^dag and sz b_l; ``ipchain_coefficients(p, t)`` gives all of their
+    coefficients at time t (``p.coeff`` holds those at t = 0).  Tree: the spin
+    leaf beside a balanced binary tree over the modes in chain order, bonds
+    ``bonds[0]`` at the leaves and ``bonds[min(level + 1, -1)]`` above.
+    """
+    w, g = ohmic_discretisation(n_modes, alpha, wc)
+    V, ceps, hop, kappa0 = chain_transform(w, g) if chain else (np.eye(n_modes), w, np.zeros(n_modes - 1),
+                                                               float(np.linalg.norm(g)))
+
+    def bond_of(level):
+        return bonds[min(level + 1, len(bonds) - 1)]
+    leaves = [("leaf", bonds[0], d, f"b{k}") for k in range(n_modes)]
+    bath = balanced_spec(leaves, bond_of, arity=2)
+    spec = ("node", 1, [("leaf", bonds[0], 2, "S"), bath])
+    p = empty_problem(name, spec, dt=dt, n_steps=n_steps, hermitian=True)
+    op = _OpCache(p)
+    S = p.leaf_names["S"]
+    bo = boson_ops(d)
+    add_term(p, eps / 2, [op(S, "sz", SIGMA["z"])])
+    add_term(p, delta / 2, [op(S, "sx", SIGMA["x"])])
+    for k in range(n_modes):
+        b = p.leaf_names[f"b{k}"]
+        add_term(p, 1.0, [op(S, "sz", SIGMA["z"]), op(b, "adag", bo["adag"])])
+        add_term(p, 1.0, [op(S, "sz", SIGMA["z"]), op(b, "a", bo["a"])])
+    p.init_vecs[S] = np.array([1, 0], dtype=np.complex128)
+    for k in range(n_modes):
+        v = np.zeros(d, dtype=np.complex128)
+        v[0] = 1.0
+        p.init_vecs[p.leaf_names[f"b{k}"]] = v
+    p.observables["sz"] = [op(S, "sz", SIGMA["z"])]
+    p.observables["sx"] = [op(S, "sx", SIGMA["x"])]
+    p.meta.update(dict(omega=w, g=g, V=V, chain_eps=ceps, chain_hop=hop, kappa0=kappa0, eps=eps, delta=delta,
+                       alpha=alpha, wc=wc, d=d, chain=chain))
+    p.coeff = ipchain_coefficients(p, 0.0)
+    return p
+
+
+def ipchain_coefficients(p: Problem, t: float) -> np.ndarray:
+    """Coefficients of every term of ``ipchain_sbm_problem`` at time t."""
+    m = p.meta
+    G = m["V"].T @ (m["g"] * np.exp(1j * m["omega"] * t))
+    c = np.empty(2 + 2 * len(G), dtype=np.complex128)
+    c[0] = m["eps"] / 2
+    c[1] = m["delta"] / 2
+    c[2::2] = G
+    c[3::2] = np.conj(G)
+    return c
+
+
 def batch_sbm_problems(seed: int = 5, n_inst: int = 256, nmin: int = 8, nmax: int = 64,
                        dmin: int = 6, dmax: int = 16, bmin: int = 8, bmax: int = 48,
                        dt: float = 0.05, n_steps: int = 100) -> List[Problem]:
