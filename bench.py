@@ -336,6 +336,8 @@ def ipchain_line(T, steps: int):
         out[name] = {"value": steps / el, "unit": "sweeps/s", "ms_per_step": 1e3 * el / steps,
                      "coefficient_update_ms": 1e3 * upd / steps,
                      "sigma_z": float(g.expect(p.observables["sz"]).real)}
+        if graph:
+            out[name]["graph_captures"] = g.graph_captures()
         g.close()
     out["workload"] = ("ipchain_sbm: eps 0, Delta 1, Ohmic alpha 0.5 w_c 5 (Gauss rule to 10 w_c), 64 chain modes "
                        "of 8 levels in a balanced binary tree beside the spin, bonds 8-24, dt 0.02, couplings "

@@ -5,6 +5,7 @@
 
 #include <functional>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.h"
@@ -137,6 +138,16 @@ private:
     std::vector<Prog> heffP, spoP, bondP;
     std::vector<std::vector<Prog>> mfP;
     std::vector<void *> sop_allocs;
+    // bytes last written to every host-written device table (program tables,
+    // leaf operators, pair terms); in staged mode (coefficient updates)
+    // unchanged tables are skipped and the rest copied asynchronously from
+    // pinned staging chunks, which the next update reuses after its first sync
+    std::unordered_map<const void *, std::string> shadow;
+    bool staged = false;
+    std::vector<std::pair<char *, size_t>> stage_chunks;
+    size_t stage_cur = 0, stage_off = 0;
+    void h2d(void *dst, const void *src, size_t bytes);
+    char *stage_alloc(size_t bytes);
     double2 *tmp = nullptr, *gsum = nullptr, *cpart = nullptr;
     unsigned short *mprep = nullptr;  // BF16x3 split factors
     double2 *Rbuf = nullptr, *Cbuf = nullptr, *smallV = nullptr, *obs = nullptr, *snapshot = nullptr;

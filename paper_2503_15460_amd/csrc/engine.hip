@@ -86,6 +86,40 @@ Engine::~Engine() {
     if (h_flags) (void)hipHostFree(h_flags);
     if (step_done) (void)hipEventDestroy(step_done);
     if (state_mem) (void)hipFree(state_mem);
+    for (auto &c : stage_chunks) (void)hipHostFree(c.first);
+}
+
+// Copy of a host-written device table (see `shadow`).
+void Engine::h2d(void *dst, const void *src, size_t bytes) {
+    std::string &sh = shadow[dst];
+    if (staged && sh.size() == bytes && std::memcmp(sh.data(), src, bytes) == 0) return;
+    sh.assign((const char *)src, bytes);
+    if (!staged) {
+        HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+        return;
+    }
+    char *p = stage_alloc(bytes);
+    std::memcpy(p, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, st));
+}
+
+// Pinned staging space for one asynchronous copy (1 MiB chunks, kept).
+char *Engine::stage_alloc(size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    while (stage_cur < stage_chunks.size() && stage_off + bytes > stage_chunks[stage_cur].second) {
+        ++stage_cur;
+        stage_off = 0;
+    }
+    if (stage_cur == stage_chunks.size()) {
+        const size_t cap = std::max<size_t>(bytes, (size_t)1 << 20);
+        void *p = nullptr;
+        HIPCHK(hipHostMalloc(&p, cap, hipHostMallocDefault));
+        stage_chunks.push_back({(char *)p, cap});
+        stage_off = 0;
+    }
+    char *p = stage_chunks[stage_cur].first + stage_off;
+    stage_off += bytes;
+    return p;
 }
 
 void Engine::set_stream(hipStream_t s) {
@@ -114,6 +148,7 @@ void Engine::free_sop() {
     have_sop = false;
     for (void *p : sop_allocs) (void)hipFree(p);
     sop_allocs.clear();
+    shadow.clear();  // freed addresses may come back for other tables
     heffP.clear();
     spoP.clear();
     bondP.clear();
@@ -161,7 +196,7 @@ void Engine::upload(Prog &p) {
     auto put = [&](auto *&dptr, const auto &vec) {
         using T = std::remove_reference_t<decltype(vec[0])>;
         if (!dptr) dptr = (std::remove_const_t<T> *)dalloc(sizeof(T) * std::max<size_t>(1, vec.size()));
-        if (!vec.empty()) HIPCHK(hipMemcpy((void *)dptr, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice));
+        if (!vec.empty()) h2d((void *)dptr, vec.data(), sizeof(T) * vec.size());
     };
     put(p.d_ent, p.ents);
     put(p.d_gptr, p.gptr);
@@ -538,7 +573,7 @@ void Engine::put_leaf_ops(int c) {
         uhi[c][ch] = hi;
     }
     if (!U[c]) U[c] = (double2 *)dalloc(sizeof(double2) * hu.size());
-    HIPCHK(hipMemcpy(U[c], hu.data(), sizeof(double2) * hu.size(), hipMemcpyHostToDevice));
+    h2d(U[c], hu.data(), sizeof(double2) * hu.size());
 }
 
 void Engine::set_sop(const SopInput &s) {
@@ -803,11 +838,19 @@ bool Engine::set_coefficients(const double *coeff, int n_terms) {
         set_sop(s);
         return true;
     }
-    HIPCHK(hipStreamSynchronize(st));  // kernels in flight read the tables rewritten below
+    // kernels in flight read the tables rewritten below, and earlier staged
+    // copies read the staging chunks reused below
+    HIPCHK(hipStreamSynchronize(st));
     sop = std::move(s);
     op = std::move(newop);
     const size_t n_alloc = sop_allocs.size();
     const auto lo0 = ulo, hi0 = uhi;
+    stage_cur = stage_off = 0;
+    struct Staged {
+        bool &f;
+        ~Staged() { f = false; }
+    } staged_guard{staged};
+    staged = true;  // tables whose bytes did not change are skipped, the rest copied on the stream
     for (int c = 0; c < t.n; ++c)
         if (c != t.root && t.local_dim[c] > 0) put_leaf_ops(c);
     // step graphs read the rewritten tables through their device pointers; the
@@ -1024,7 +1067,7 @@ void Engine::plan_pairs(Prog &h, int z) {
             h.pair_dterms[k] = (PairTerm *)dalloc(sizeof(PairTerm) * per[k].size());
             h.pair_cap_terms[k] = (int)per[k].size();
         }
-        HIPCHK(hipMemcpy(h.pair_dterms[k], per[k].data(), sizeof(PairTerm) * per[k].size(), hipMemcpyHostToDevice));
+        h2d(h.pair_dterms[k], per[k].data(), sizeof(PairTerm) * per[k].size());
         PairPass pp{};
         pp.nk = h.g.dims[k];
         pp.np = h.g.dims[P];
