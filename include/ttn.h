@@ -89,7 +89,7 @@ typedef struct ttn_batch_ctx *ttn_batch_t;
 
 typedef struct {
     int32_t precision;      /* TTN_FP64, TTN_FP32 or TTN_BF16X3 */
-    double krylov_tol;      /* local exponential error target, relative (0 -> 1e-13, FP32/BF16X3: 1e-8) */
+    double krylov_tol;      /* local exponential error target, relative (0 -> 1e-13, FP32/BF16X3: 1e-10) */
     int32_t krylov_mmax;    /* max Krylov dimension per solve (0 -> 40) */
     int32_t hermitian;      /* 1: Lanczos (G must be Hermitian), 0: Arnoldi */
     void *hip_stream;       /* hipStream_t for all work of the handle, NULL = null stream */
