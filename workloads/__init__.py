@@ -8,9 +8,10 @@ both consume the very same inputs without sharing any of the method's code.
 from .problem import Problem, TreeBuilder
 from .models import (sbm_problem, vibronic_problem, exciton_problem,
                      heom_sbm_problem, pseudomode_sbm_problem, batch_sbm_problems, random_isometric_state,
-                     chain_transform, ipchain_sbm_problem, ipchain_coefficients, CONFIGS, config_problem)
+                     chain_transform, ipchain_sbm_problem, ipchain_coefficients, multiset_vibronic_problem,
+                     CONFIGS, config_problem)
 
 __all__ = ["Problem", "TreeBuilder", "sbm_problem", "vibronic_problem",
            "exciton_problem", "heom_sbm_problem", "pseudomode_sbm_problem", "batch_sbm_problems",
            "random_isometric_state", "chain_transform", "ipchain_sbm_problem", "ipchain_coefficients",
-           "CONFIGS", "config_problem"]
+           "multiset_vibronic_problem", "CONFIGS", "config_problem"]

@@ -581,6 +581,67 @@ def ipchain_coefficients(p: Problem, t: float) -> np.ndarray:
     return c
 
 
+def multiset_vibronic_problem(n_sets: int = 3, n_modes: int = 4, d: int = 4, bonds=(4, 6), seed: int = 0,
+                              coupled: bool = True, dt: float = 0.1, n_steps: int = 50,
+                              name: str = "multiset_vibronic") -> Problem:
+    """Seeded vibronic model for the multi-set ansatz of Sec. II A
+    (|Psi> = sum_alpha |alpha> |Psi^alpha>, one tree tensor network of the
+    same shape per electronic state alpha).
+
+    ``G = sum_{alpha beta} |alpha><beta| (x) G_{alpha beta}`` on the modes with
+    ``G_{alpha alpha} = E_alpha + sum_k w_k n_k + sum_k kappa_{alpha k} x_k``
+    and, for alpha != beta, ``G_{alpha beta} = D_{alpha beta} + sum_k
+    lambda_{alpha beta k} x_k`` (real symmetric couplings, so G is Hermitian);
+    ``coupled=False`` drops the off-diagonal blocks.  The tree holds the modes
+    only: a balanced binary tree with bonds ``bonds[0]`` at the leaves and
+    ``bonds[1]`` above.  Every term lists its block in
+    ``meta["set_pair"][r] = (alpha, beta)``; a term without operators is a
+    constant of its block.  Start: alpha = 0 with every mode in its ground
+    state (``meta["set_weights"]``: 1 for alpha = 0, else 0).
+    """
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.5, 1.5, n_modes)
+    E = np.sort(rng.uniform(-0.5, 0.5, n_sets))
+    kappa = rng.normal(0.0, 0.3, (n_sets, n_modes))
+    D = rng.normal(0.0, 0.2, (n_sets, n_sets))
+    lam = rng.normal(0.0, 0.1, (n_sets, n_sets, n_modes))
+    leaves = [("leaf", bonds[0], d, f"q{k}") for k in range(n_modes)]
+    top = balanced_spec(leaves, lambda lev: bonds[min(1, len(bonds) - 1)], arity=2)
+    spec = ("node", 1, top[2]) if top[0] == "node" else ("node", 1, [top])
+    p = empty_problem(name, spec, dt=dt, n_steps=n_steps, hermitian=True)
+    op = _OpCache(p)
+    bo = boson_ops(d)
+    pairs = []
+
+    def term(a, b, coef, ops):
+        add_term(p, coef, ops)
+        pairs.append((a, b))
+    for a in range(n_sets):
+        term(a, a, E[a], [])
+        for k in range(n_modes):
+            q = p.leaf_names[f"q{k}"]
+            term(a, a, w[k], [op(q, "n", bo["n"])])
+            term(a, a, kappa[a, k], [op(q, "x", bo["x"])])
+    if coupled:
+        for a in range(n_sets):
+            for b in range(n_sets):
+                if a == b:
+                    continue
+                lo, hi = min(a, b), max(a, b)
+                term(a, b, D[lo, hi], [])
+                for k in range(n_modes):
+                    q = p.leaf_names[f"q{k}"]
+                    term(a, b, lam[lo, hi, k], [op(q, "x", bo["x"])])
+    vac = np.zeros(d, dtype=np.complex128)
+    vac[0] = 1.0
+    for k in range(n_modes):
+        p.init_vecs[p.leaf_names[f"q{k}"]] = vac.copy()
+    weights = np.zeros(n_sets, dtype=np.complex128)
+    weights[0] = 1.0
+    p.meta.update(dict(n_sets=n_sets, set_pair=pairs, set_weights=weights, omega=w, E=E, kappa=kappa))
+    return p
+
+
 def batch_sbm_problems(seed: int = 5, n_inst: int = 256, nmin: int = 8, nmax: int = 64,
                        dmin: int = 6, dmax: int = 16, bmin: int = 8, bmax: int = 48,
                        dt: float = 0.05, n_steps: int = 100) -> List[Problem]:
