@@ -11,6 +11,12 @@ from workloads import ipchain_coefficients, ipchain_sbm_problem, random_isometri
 
 pytestmark = pytest.mark.gpu
 
+# FP64 bars: from a seeded full-rank state, and from the product state, whose
+# rank-deficient factors pick their completion from rounding (the oracle's own
+# floors, tests/golden/jitter.json: 2.4e-15 and 4.0e-8 over these 20 steps)
+TOL_FULL_RANK = 1e-10
+TOL_PRODUCT = 5e-7
+
 
 @pytest.fixture(scope="module")
 def T():
@@ -37,15 +43,17 @@ def _start(p, o, g, start):
         g.set_state(st)
 
 
-@pytest.mark.parametrize("prec,start,tol", [(0, "random", 1e-10), (0, "product", 1e-7), (1, "random", 1e-5)])
+@pytest.mark.parametrize("prec,start,tol", [(0, "random", TOL_FULL_RANK), (0, "product", TOL_PRODUCT),
+                                             (1, "random", 1e-5)])
 def test_timedep_parity(T, prec, start, tol):
     """20 midpoint steps: <sigma_z> after every step against the oracle, every
     coefficient change taken in place (no rebuild).  FP64 from a seeded
-    full-rank state to 1e-10 (the oracle's own floor there, 1e-16 noise
-    before every QR: 4e-15) and the full state vector at the end (1e-10
-    relative); FP64 from the product state to 1e-7 (the same noise moves
-    <sigma_z> by 1.3e-8 after 20 steps, as the rank-deficient factors of a
-    product state pick their completion); FP32 contractions to 1e-5."""
+    full-rank state to 1e-10 and the full state vector at the end (1e-10
+    relative); FP64 from the product state to 5e-7, ten times the oracle's
+    own floor there (1e-16 noise before every QR moves <sigma_z> and a(t) by
+    4e-8 over the 20 steps, as the rank-deficient factors of a product state
+    pick their completion; measured on the GPU: 3e-10); FP32 contractions to
+    1e-5."""
     p = _problem()
     o = Oracle(p)
     g = T.TTN.from_problem(p, precision=prec)

@@ -521,3 +521,8 @@ def test_recorded_jitter_floors_bound_the_parity_tolerances():
     assert max(1e-10, 10 * rec["reduced_vibronic_full_rank_6_steps"]["J"]) <= gp.TOL
     assert max(1e-10, 10 * rec["vibronic24_full_rank_3_steps"]["J"]) <= gp.TOL
     assert 10 * rec["reduced_vibronic_product_state_6_steps"]["J"] <= gp.JTOL_VIB
+    import test_gpu_pseudomode as gpm
+    import test_gpu_timedep as gtd
+    assert max(1e-10, 10 * rec["ipchain_full_rank_20_steps"]["J"]) <= gtd.TOL_FULL_RANK
+    assert 10 * rec["ipchain_product_state_20_steps"]["J"] <= gtd.TOL_PRODUCT
+    assert max(1e-10, 10 * rec["pseudomode_product_state_6_steps"]["J"]) <= gpm.TOL_FP64
