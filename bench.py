@@ -233,6 +233,41 @@ def cpu_oracle_sample(p, a_matvecs_per_step: float, a_node: int, n_terms_sample:
             "seconds_per_step_estimate": t_step}
 
 
+def oracle_step(p, coef_at=None, threads: int = 16):
+    """The oracle on the host: one whole step of p from its product state
+    (coefficients at the step's midpoint when they depend on time), timed at
+    `threads` BLAS threads (at most the host's)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Oracle
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    o = Oracle(p)
+    o.set_product_state(p.init_vecs)
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        if coef_at is None:
+            o.step(p.dt)
+        else:
+            o.step_td(p.dt, coef_at)
+        el = time.perf_counter() - t0
+    return {"value": 1.0 / el, "unit": "sweeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"one whole step from the product state, {el:.1f} s"}
+
+
+def launch_summary(stats, steps: int, wall_ms_per_step: float):
+    """Launch-level view of a profiled sweep: launches and summed kernel time
+    per step, the fraction of the (unprofiled) wall time the kernels fill, and
+    the three kernels with the largest total time."""
+    launches = sum(r["calls"] for r in stats) / steps
+    busy = sum(r["total_ms"] for r in stats) / steps
+    top = sorted(stats, key=lambda r: -r["total_ms"])[:3]
+    return {"launches_per_step": launches, "kernel_ms_per_step": busy,
+            "kernel_busy_frac": busy / wall_ms_per_step if wall_ms_per_step > 0 else None,
+            "avg_launch_us": 1e3 * busy / launches if launches else None,
+            "top": [{"kernel": r["name"], "ms_per_step": r["total_ms"] / steps, "calls_per_step": r["calls"] / steps}
+                    for r in top]}
+
+
 def vibronic_line(T, steps, warmup):
     """Secondary line: the 2-state / 24-mode vibronic model (bonds 8/16/20) in
     FP64 and FP32-mixed."""
@@ -296,7 +331,18 @@ def pseudomode_line(T, steps: int):
     for name in ("fp64", "fp32"):
         out[name], g = timed_run(T, p, PRECISIONS[name], steps, 1, keep=True)
         vals[name] = obs(g)
+        if name == "fp64":
+            try:
+                st = profiled_sweep(T, g, p, 1)
+                out[name]["launches"] = launch_summary(st, 1, out[name]["ms_per_step"])
+                out[name]["roofline"] = roofline(st, 1, "pseudomode_sbm")
+            except Exception as e:  # context only: the line keeps its timings
+                out[name]["launches"] = {"error": str(e)}
         g.close()
+    try:
+        out["cpu_baseline"] = oracle_step(p)
+    except Exception as e:
+        out["cpu_baseline"] = {"error": str(e)}
     out["sigma_z_trace_fp64"] = [float(vals["fp64"][0].real), float(vals["fp64"][1].real)]
     out["fp32_max_abs_diff_vs_fp64"] = float(np.abs(vals["fp64"] - vals["fp32"]).max())
     out["workload"] = ("pseudomode_sbm: eps 0.5, Delta 1, Debye lambda 0.2 gamma 1 T 1, 8 poles as quasi-Lindblad "
@@ -338,7 +384,19 @@ def ipchain_line(T, steps: int):
                      "sigma_z": float(g.expect(p.observables["sz"]).real)}
         if graph:
             out[name]["graph_captures"] = g.graph_captures()
+        if name == "fp64":
+            try:
+                g.set_coefficients(coef(t + 0.5 * p.dt))
+                st = profiled_sweep(T, g, p, 1)
+                out[name]["launches"] = launch_summary(st, 1, out[name]["ms_per_step"] - out[name]["coefficient_update_ms"])
+                out[name]["roofline"] = roofline(st, 1, "ipchain_sbm")
+            except Exception as e:  # context only: the line keeps its timings
+                out[name]["launches"] = {"error": str(e)}
         g.close()
+    try:
+        out["cpu_baseline"] = oracle_step(p, coef)
+    except Exception as e:
+        out["cpu_baseline"] = {"error": str(e)}
     out["workload"] = ("ipchain_sbm: eps 0, Delta 1, Ohmic alpha 0.5 w_c 5 (Gauss rule to 10 w_c), 64 chain modes "
                        "of 8 levels in a balanced binary tree beside the spin, bonds 8-24, dt 0.02, couplings "
                        f"G_l(t) at every step's midpoint, {2 + steps} steps")

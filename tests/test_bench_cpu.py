@@ -88,3 +88,24 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_launch_summary():
+    stats = [_row("k_small_solve", 40, 20.0, 0.0, 0.0), _row("k_mode_tile", 200, 10.0, 0.0, 0.0),
+             _row("k_qr", 100, 5.0, 0.0, 0.0), _row("k_copy", 10, 1.0, 0.0, 0.0)]
+    s = bench.launch_summary(stats, 2, 50.0)
+    assert s["launches_per_step"] == 175 and abs(s["kernel_ms_per_step"] - 18.0) < 1e-12
+    assert abs(s["kernel_busy_frac"] - 18.0 / 50.0) < 1e-12
+    assert abs(s["avg_launch_us"] - 1e3 * 18.0 / 175) < 1e-9
+    assert [t["kernel"] for t in s["top"]] == ["k_small_solve", "k_mode_tile", "k_qr"]
+
+
+def test_oracle_step_baseline():
+    """The oracle leg of the context lines: one whole step, also with
+    time-dependent coefficients, reported as a rate with its thread count."""
+    from workloads import ipchain_coefficients, ipchain_sbm_problem, sbm_problem
+    r = bench.oracle_step(sbm_problem(n_modes=2, d=3, bond=2), threads=1)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["value"] > 0 and r["unit"] == "sweeps/s"
+    p = ipchain_sbm_problem(n_modes=2, d=3, bonds=(2, 2, 2))
+    r = bench.oracle_step(p, lambda t: ipchain_coefficients(p, t), threads=2)
+    assert r["value"] > 0 and r["cores"] == min(2, os.cpu_count())
